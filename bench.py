@@ -1,0 +1,253 @@
+"""Throughput of the denoiser on one MI355X.
+
+Workload: the 1920x1080 moving-camera sequence (camera translating 2 px
+and yawing 0.1 deg per frame, three spheres moving 5 px per frame), binary32
+storage, with the paper's final filter: Reinhard tone map in, temporal
+accumulation with variance colour clamping (gamma 1), variance estimate,
+five edge-avoiding a-trous levels, inverse tone map.  One step = one frame
+of the whole chain; inputs for all frames are resident in HBM before the
+timed region.  The separable-blur chain is timed the same way and reported
+as a variant.
+
+Prints one JSON line.  See --help.
+"""
+
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import json
+import multiprocessing as mp
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from paper_2312_06827_amd.scene import CONFIGS, render_frame  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = CONFIGS["hd_motion"]
+
+# Algorithmic bytes per pixel (each input plane read once, each output
+# written once), binary32 storage, ids on.
+BYTES_PER_PX = {
+    # cur rgb, z, normal, mv, prev z, prev normal, ids x2, history rgb,
+    # m1, m2, n -> rgb, m1, m2, n
+    "temporal": 12 + 4 + 12 + 8 + 4 + 12 + 2 + 12 + 8 + 1 + 12 + 8 + 1,
+    # m1, m2, n, z -> var
+    "variance": 4 + 4 + 1 + 4 + 4,
+    # rgb, var, z, dzdx, dzdy, normal -> rgb, var
+    "atrous": 12 + 4 + 4 + 4 + 4 + 12 + 12 + 4,
+    "atrous_last": 12 + 4 + 4 + 4 + 4 + 12 + 12,
+    # horizontal: rgb, var, z, dzdx, normal -> scratch rgb; vertical:
+    # scratch rgb, var, z, dzdy, normal -> rgb, var
+    "atrous_sep": (12 + 4 + 4 + 4 + 12 + 12) + (12 + 4 + 4 + 4 + 12 + 12 + 4),
+    "atrous_sep_last": (12 + 4 + 4 + 4 + 12 + 12) + (12 + 4 + 4 + 4 + 12 + 12),
+}
+
+
+def frame_bytes_per_px(levels: int, sep: bool) -> int:
+    a, al = ("atrous_sep", "atrous_sep_last") if sep else ("atrous", "atrous_last")
+    return (BYTES_PER_PX["temporal"] + BYTES_PER_PX["variance"]
+            + (levels - 1) * BYTES_PER_PX[a] + BYTES_PER_PX[al])
+
+
+def _render(args):
+    cfg, f = args
+    return render_frame(cfg, f)
+
+
+def generate(cfg, n_frames, workers):
+    cfg = type(cfg)(**{**cfg.__dict__, "frames": n_frames})
+    ctx = mp.get_context("fork")
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=ctx) as ex:
+        return list(ex.map(_render, [(cfg, f) for f in range(n_frames)]))
+
+
+class KernelTimer:
+    """HIP events around each library call, on the stream it runs on."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.pending = []
+
+    def __call__(self, name):
+        torch = self.torch
+        timer = self
+
+        class _Ctx:
+            def __enter__(self_):
+                self_.a = torch.cuda.Event(enable_timing=True)
+                self_.b = torch.cuda.Event(enable_timing=True)
+                self_.a.record()
+
+            def __exit__(self_, *exc):
+                self_.b.record()
+                timer.pending.append((name, self_.a, self_.b))
+        return _Ctx()
+
+    def summary(self):
+        out = {}
+        for name, a, b in self.pending:
+            out.setdefault(name, []).append(a.elapsed_time(b))
+        return {k: (float(np.mean(v)), len(v)) for k, v in out.items()}
+
+
+def run_chain(torch, frames_dev, cfg, H, W, warmup, steps, with_timer):
+    from paper_2312_06827_amd.pipeline import Denoiser
+
+    den = Denoiser(H, W, cfg)
+    for f in range(warmup):
+        den.frame(frames_dev[f])
+    torch.cuda.synchronize()
+    timer = KernelTimer(torch) if with_timer else None
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record()
+    for f in range(warmup, warmup + steps):
+        den.frame(frames_dev[f], timer=timer)
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = start.elapsed_time(stop)
+    return gpu_ms, wall, (timer.summary() if timer else None)
+
+
+def copy_probe(torch, nbytes=1 << 30, reps=10):
+    from paper_2312_06827_amd import lib
+
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    lib.sv_probe_copy(dst, src)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        lib.sv_probe_copy(dst, src)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    return 2 * nbytes / (ms * 1e-3) / 1e9  # read + write
+
+
+def cpu_baseline(frames_np, warm, timed):
+    """The oracle as it stands, on the host cores, on a bounded sample."""
+    import oracle as O
+
+    p = O.OracleParams(clamp=True, tonemap=True, use_id=True)
+    H, W = frames_np[0]["z"].shape
+    st = O.new_state(H, W)
+    for f in range(warm):
+        _, st, _ = O.run_frame(frames_np[f], st, p)
+    t0 = time.perf_counter()
+    for f in range(warm, warm + timed):
+        _, st, _ = O.run_frame(frames_np[f], st, p)
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": W * H * timed / dt / 1e6, "unit": "Mpix/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{W}x{H} frames {warm}..{warm + timed - 1} of the same sequence after "
+                      f"{warm} untimed frames, FP64 C oracle with OpenMP ({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    H, W = WORKLOAD.height, WORKLOAD.width
+    n_frames = args.warmup + args.steps
+    t0 = time.perf_counter()
+    frames_np = generate(WORKLOAD, n_frames, args.workers)  # before any GPU call (fork)
+    gen_s = time.perf_counter() - t0
+    print(f"# generated {n_frames} frames in {gen_s:.1f} s", file=sys.stderr, flush=True)
+
+    import torch
+
+    from paper_2312_06827_amd.pipeline import MOTION, MOTION_SEP, FrameInputs
+
+    frames_dev = [FrameInputs.from_numpy(fr) for fr in frames_np]
+    torch.cuda.synchronize()
+
+    gpu_ms, wall, ktimes = run_chain(torch, frames_dev, MOTION, H, W, args.warmup, args.steps,
+                                     with_timer=True)
+    ms_per_step = gpu_ms / args.steps
+    mpix = W * H * args.steps / (gpu_ms * 1e-3) / 1e6
+    print(f"# 2d chain: {ms_per_step * 1e3:.1f} us/frame (host wall {wall / args.steps * 1e6:.1f}"
+          f" us/frame)", file=sys.stderr, flush=True)
+
+    # roofline of the dominant kernel: the a-trous levels
+    npx = W * H
+    lv = [k for k in ktimes if k.startswith("atrous")]
+    tot_bytes = sum(ktimes[k][1] * npx * BYTES_PER_PX["atrous_last" if k.endswith("4") else "atrous"]
+                    for k in lv)
+    tot_ms = sum(ktimes[k][0] * ktimes[k][1] for k in lv)
+    achieved = tot_bytes / (tot_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "atrous (5x5 level, mean over the five levels)"}
+    per_kernel = {k: {"us": round(v[0] * 1e3, 2), "launches": v[1]} for k, v in sorted(ktimes.items())}
+
+    variants = {}
+    if not args.no_variants:
+        g2, w2, kt2 = run_chain(torch, frames_dev, MOTION_SEP, H, W, args.warmup, args.steps,
+                                with_timer=True)
+        variants["separable"] = {
+            "value": round(W * H * args.steps / (g2 * 1e-3) / 1e6, 1), "unit": "Mpix/s",
+            "ms_per_step": round(g2 / args.steps, 4),
+            "frame_hbm_frac": round(W * H * args.steps * frame_bytes_per_px(5, True)
+                                    / (g2 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "per_kernel_us": {k: round(v[0] * 1e3, 2) for k, v in sorted(kt2.items())}}
+    copy_gbs = copy_probe(torch)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(frames_np, warm=4, timed=6)
+
+    fb = frame_bytes_per_px(5, False)
+    line = {
+        "metric": "1080p denoise Mpix/s + HBM roofline frac; learned vs plain at equal RelMSE",
+        "value": round(mpix, 1),
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded procedural scene, 1 spp Exp(1) noise with 0.5% x50 fireflies)",
+        "config": {"workload": "svgf denoise, 1920x1080, moving camera + 3 moving spheres, "
+                               "clamp gamma 1, Reinhard tone map, 5 a-trous levels (2D)",
+                   "width": W, "height": H, "frames_timed": args.steps, "levels": 5,
+                   "alpha": 0.2, "sigma_z": 1, "sigma_n": 128, "sigma_l": 4},
+        "roofline": roofline,
+        "frame_hbm_frac": round(mpix * 1e6 * fb / 1e9 / HBM_PEAK_GBS, 4),
+        "frame_bytes_per_px": fb,
+        "copy_probe_gbs": round(copy_gbs, 1),
+        "per_kernel_us": per_kernel,
+        "variants": variants,
+        "cpu_baseline": cpu,
+        "host": {"cpu": platform.processor() or platform.machine(), "gen_s": round(gen_s, 1)},
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,263 @@
+/*
+ * sv.h - C ABI of the MI355X (gfx950) SVGF-style denoiser.
+ *
+ * The calls follow the denoiser of "Hybrid-Rendering Techniques in GPU"
+ * (Granja & Pereira, 2021): Reinhard tone map before denoising and its
+ * inverse after (Section 3.4); a temporal filter with backward reprojection,
+ * variance colour clamping of the history and accumulation of colour and
+ * luminance moments (Sections 2, 3 step 4, 3.1); a variance estimate
+ * (Section 2); and the edge-avoiding a-trous wavelet filter guided by that
+ * variance, in 5x5 form (Section 2, Fig. 1) and in separable form
+ * (Section 3.3).  The paper names these operations without formulas; the
+ * formulas implemented are those of spatiotemporal variance-guided
+ * filtering, which Section 2 cites, with the readings stated per call.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Images are planes (structure of arrays), row-major.  Every plane of a
+ *    call has the same width w, height h and row pitch (in ELEMENTS of the
+ *    plane's own type, pitch >= w).  Pixel (x, y) of plane P is P[y*pitch+x].
+ *  - Colour planes and G-buffer planes have the call's storage type
+ *    (SV_F32: float, SV_F16: IEEE binary16).  Moments (m1, m2), variance,
+ *    kappa and alpha maps are always float; history lengths and object ids
+ *    are always uint8_t.  All arithmetic is binary32.
+ *  - Every pointer is a DEVICE pointer to memory the caller owns and keeps
+ *    alive until the work on the stream has finished.  The library never
+ *    allocates, frees or retains them and keeps no state between calls.
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = the default
+ *    stream) and the call returns without synchronising.
+ *  - Arguments are checked on the host before any HIP call; on failure
+ *    nothing is enqueued and a status below is returned.  w == 0 or h == 0
+ *    is a valid empty call that enqueues nothing.  Limits: w, h <= 32768,
+ *    pitch * h < 2^31.
+ *  - A pixel is EMPTY (no surface) when its depth z is not > 0 or not
+ *    finite.  Empty pixels pass their colour through, get zero moments,
+ *    variance and history length, and are never used as neighbours.
+ *  - Stencil calls (clamp, temporal, variance, a-trous) read neighbours:
+ *    their outputs must not overlap any input plane (SV_EALIAS).
+ *  - Results are deterministic: no atomics, a fixed summation order per
+ *    pixel.
+ *  - Luminance is L(c) = 0.2126 r + 0.7152 g + 0.0722 b (Rec. 709).
+ */
+#ifndef SV_H
+#define SV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ----------------------------------------------------- */
+enum {
+    SV_OK = 0,
+    SV_EINVAL = 1,      /* null required pointer, bad size, pitch, step, param */
+    SV_EALIAS = 2,      /* an output overlaps an input of a stencil call */
+    SV_EDTYPE = 3,      /* unknown storage type */
+    SV_EHIP = 4,        /* the HIP runtime reported an error on launch */
+    SV_EUNSUPPORTED = 5 /* valid but not implemented combination */
+};
+
+typedef void *sv_stream; /* a hipStream_t */
+
+typedef struct {
+    int32_t w, h;  /* image size in pixels */
+    int32_t pitch; /* row pitch in elements, >= w */
+} sv_dims;
+
+typedef enum { SV_F32 = 0, SV_F16 = 1 } sv_dtype;
+
+/* Three colour planes.  Inputs are only read through these pointers. */
+typedef struct {
+    void *r, *g, *b;
+} sv_rgb;
+
+/* G-buffer of one frame (Section 3 step 2): view depth z (> 0 for a
+ * surface), its screen gradients dz/dx and dz/dy in depth units per pixel,
+ * unit normal (nx, ny, nz), and an optional object id (may be NULL). */
+typedef struct {
+    const void *z, *dzdx, *dzdy, *nx, *ny, *nz;
+    const uint8_t *id;
+} sv_gbuf;
+
+/* ---- Reinhard tone map (Section 3.4) ----------------------------------- */
+typedef enum {
+    SV_TM_LUMA = 0,    /* forward c/(1 + k L(c)); inverse c/(1 - k L(c)) */
+    SV_TM_CHANNEL = 1, /* forward c/(1 + k c) per channel; inverse c/(1 - k c) */
+    SV_TM_PAPER = 2    /* inverse only: the listing's c (1 + L(c)) weight */
+} sv_tm_mode;
+
+typedef struct {
+    float k;      /* luminance multiplier (lumaMultiplier), default 1 */
+    float weight; /* reinhardToneMappingWeight, SV_TM_PAPER only */
+    int32_t mode; /* sv_tm_mode */
+} sv_tm_params;
+
+/* Pointwise tone map (inverse = 0) or its inverse (inverse = 1) of `in`
+ * into `out`; in place (out == in) is allowed.  The forward map divides the
+ * radiance by 1 + k L(c) as the paper's listing does.  Its exact inverse
+ * c' / (1 - k L(c')) is the default "remove" step (the denominator is
+ * floored at 2^-20); the listing's own c' (1 + L(c')) w, which is not an
+ * inverse, is available as SV_TM_PAPER.  Returns SV_EINVAL for null planes
+ * or p == NULL, SV_EUNSUPPORTED for SV_TM_PAPER forward. */
+int sv_tonemap(const sv_rgb *in, const sv_rgb *out, sv_dims d, sv_dtype t,
+               int inverse, const sv_tm_params *p, sv_stream stream);
+
+/* ---- variance colour clamp (Sections 2, 3.1) -------------------------- */
+
+/* History rectification by variance colour clamping.  For each pixel the
+ * mean mu and the population standard deviation sigma (two-pass) of `cur`
+ * over its 3x3 neighbourhood (pixels inside the image and, if z != NULL,
+ * not empty) are computed per channel, and `hist` is clamped to
+ * [mu - gamma sigma, mu + gamma sigma] into `out`.  gamma <= 0 copies.
+ * `z` (storage type, may be NULL) marks empty pixels.  `out` may equal
+ * `hist` but must not overlap `cur`. */
+int sv_clamp(const sv_rgb *hist, const sv_rgb *cur, const sv_rgb *out,
+             const void *z, sv_dims d, sv_dtype t, float gamma,
+             sv_stream stream);
+
+/* ---- temporal filter (Section 2; Section 3 step 4; Section 3.1) -------- */
+enum {
+    SV_T_CLAMP = 1,     /* clamp the reprojected history (gamma > 0) */
+    SV_T_USE_ID = 2,    /* object ids of the taps must match */
+    SV_T_TONEMAP_IN = 4 /* forward tone map (LUMA, tm_k) the current colour */
+};
+
+typedef struct {
+    sv_rgb cur;              /* current 1-spp colour */
+    sv_gbuf g;               /* current G-buffer (dz/dx, dz/dy unused) */
+    const void *mvx, *mvy;   /* backward motion in pixels: p was at p + mv */
+    sv_gbuf prev;            /* previous frame's z, normal, id */
+    sv_rgb hist;             /* colour history (previous output) */
+    const float *hist_m1;    /* luminance moment history E[L] */
+    const float *hist_m2;    /* luminance moment history E[L^2] */
+    const uint8_t *hist_n;   /* history length, 0 = none */
+    sv_rgb out;              /* accumulated colour */
+    float *out_m1, *out_m2;  /* accumulated moments */
+    uint8_t *out_n;          /* new history length */
+    const float *alpha_map;  /* optional per-pixel colour alpha (NULL) */
+} sv_temporal_io;
+
+typedef struct {
+    float alpha;     /* colour blend weight, default 0.2 */
+    float alpha_m;   /* moment blend weight, default 0.2 */
+    float gamma;     /* clamp box half-width in sigmas, default 1 */
+    float tau_z;     /* relative depth tolerance, default 0.1 */
+    float tau_n;     /* normal cosine threshold, default 0.9 */
+    float tm_k;      /* tone-map multiplier for SV_T_TONEMAP_IN, default 1 */
+    int32_t max_hist;/* history length cap, 1..255, default 255 */
+    int32_t flags;   /* SV_T_* */
+} sv_temporal_params;
+
+/* One temporal step, fused: (1) the current colour c, tone mapped if
+ * SV_T_TONEMAP_IN; (2) backward reprojection: with x0 = x + floor(mvx),
+ * fx = mvx - floor(mvx) (likewise y) the four history pixels around
+ * p + mv are bilinear taps; a tap is usable if it is inside the image, its
+ * history length is >= 1, |prev.z - z| <= tau_z z, prev.n . n >= tau_n
+ * (and ids match under SV_T_USE_ID) - these tests are evaluated in binary32
+ * as written, the cosine as fma(nz,nz', fma(ny,ny', nx*nx')); the usable
+ * taps' bilinear weights are renormalised and the history length is the
+ * largest among usable taps of positive weight; no usable tap (or |mv| not
+ * finite or >= 2^20) discards the history; (3) with SV_T_CLAMP the
+ * reprojected colour is clamped to the 3x3 mean +- gamma sigma of c;
+ * (4) with n = min(n_hist + 1, max_hist), a = max(alpha, 1/n),
+ * am = max(alpha_m, 1/n): out = (1-a) hist + a c, m1 = (1-am) m1_hist +
+ * am L(c), m2 = (1-am) m2_hist + am L(c)^2; a discarded history gives
+ * out = c, m1 = L, m2 = L^2, n = 1.  alpha_map, if given, replaces alpha
+ * per pixel.  Outputs must not overlap any input (SV_EALIAS).  Required:
+ * cur, g.z, g.n*, mvx, mvy, prev.z, prev.n*, hist, hist_m1, hist_m2,
+ * hist_n, out, out_m1, out_m2, out_n; ids when SV_T_USE_ID. */
+int sv_temporal(const sv_temporal_io *io, sv_dims d, sv_dtype t,
+                const sv_temporal_params *p, sv_stream stream);
+
+/* ---- variance estimate (Section 2) ------------------------------------ */
+typedef struct {
+    float sigma_z;    /* depth weight scale, default 1 */
+    float sigma_n;    /* normal weight exponent, default 128 */
+    float eps_z;      /* depth weight epsilon, default 1e-10 */
+    int32_t min_hist; /* history length for the temporal estimate, default 4 */
+    int32_t radius;   /* spatial window radius, 0..7, default 3 */
+} sv_variance_params;
+
+/* var = max(0, m2 - m1^2) where n >= min_hist.  Where 1 <= n < min_hist
+ * the moments are averaged over the (2 radius + 1)^2 window (inside the
+ * image, not empty) with weight 1 at the centre and
+ * exp(-|z(p)-z(q)| / (sigma_z |dzdx(p) dx + dzdy(p) dy| + eps_z))
+ * * max(0, n(p).n(q))^sigma_n elsewhere, and var = weighted mean of
+ * (m2 - m1^2) + weighted spread of m1 about its weighted mean (floored at
+ * 0).  n == 0 or an empty pixel gives 0.  `var` must not overlap the
+ * inputs. */
+int sv_variance(const float *m1, const float *m2, const uint8_t *n,
+                const sv_gbuf *g, float *var, sv_dims d, sv_dtype t,
+                const sv_variance_params *p, sv_stream stream);
+
+/* ---- edge-avoiding a-trous level (Section 2, Fig. 1; Section 3.3) ------ */
+enum {
+    SV_A_UNIT_WEIGHTS = 1, /* every edge-stopping weight 1 (plain B3) */
+    SV_A_INV_TONEMAP = 2   /* exact inverse LUMA tone map (tm_k) on output */
+};
+
+typedef struct {
+    float sigma_z; /* default 1 */
+    float sigma_n; /* default 128 */
+    float sigma_l; /* default 4 */
+    float eps_z;   /* default 1e-10 */
+    float eps_l;   /* default 1e-10 */
+    float tm_k;    /* tone-map multiplier for SV_A_INV_TONEMAP, default 1 */
+    int32_t flags; /* SV_A_* */
+} sv_atrous_params;
+
+/* One level with hole spacing `step` (>= 1; 1, 2, 4, 8, 16 for the five
+ * levels).  g(p) is the 3x3 Gaussian (1/4, 1/2, 1/4)^2 of var_in over
+ * in-image, non-empty pixels, renormalised.  Over taps q = p + step (a, b),
+ * a, b in -2..2, inside the image and not empty, with the B3-spline weights
+ * H = h(a) h(b), h = (1, 4, 6, 4, 1)/16, and edge weights (1 at q = p)
+ *   w = exp(-|z(p)-z(q)| / (sigma_z |dzdx(p) step a + dzdy(p) step b| + eps_z))
+ *     * max(0, n(p).n(q))^sigma_n
+ *     * exp(-|L(c(p)) - L(c(q))| / (sigma_l kappa(p) sqrt(g(p)) + eps_l)),
+ * the output is c' = sum H w c(q) / sum H w and
+ * var' = sum (H w)^2 var_in(q) / (sum H w)^2.  kappa may be NULL (1);
+ * var_out may be NULL (not written, e.g. on the last level).  Outputs must
+ * not overlap inputs. */
+int sv_atrous(const sv_rgb *c_in, const float *var_in, const sv_gbuf *g,
+              const float *kappa, const sv_rgb *c_out, float *var_out,
+              int32_t step, sv_dims d, sv_dtype t, const sv_atrous_params *p,
+              sv_stream stream);
+
+/* Separable level (Section 3.3): the 5x5 kernel split into a horizontal
+ * pass of 5 taps (a, 0) and a vertical pass of 5 taps (0, b), 10 neighbour
+ * visits instead of 25.  Both passes use g from var_in.  The horizontal
+ * pass filters colour only into `scratch` (caller-owned planes of the
+ * storage type, same dims); the vertical pass filters `scratch` (luminance
+ * taken from it) and alone updates the variance:
+ * var' = sum (h(b) w)^2 var_in(q) / (sum h(b) w)^2.  Weights as sv_atrous
+ * with the offset (step a, 0) or (0, step b).  scratch must not overlap
+ * inputs or outputs. */
+int sv_atrous_sep(const sv_rgb *c_in, const float *var_in, const sv_gbuf *g,
+                  const float *kappa, const sv_rgb *scratch,
+                  const sv_rgb *c_out, float *var_out, int32_t step,
+                  sv_dims d, sv_dtype t, const sv_atrous_params *p,
+                  sv_stream stream);
+
+/* ---- misc --------------------------------------------------------------- */
+
+/* Static string for a status code (never NULL). */
+const char *sv_status_str(int status);
+
+/* ABI version: increases when a signature or a struct changes. */
+int sv_version(void);
+
+/* The hipError_t of the last SV_EHIP returned on this thread (0 if none). */
+int sv_last_hip_error(void);
+
+/* Device-to-device copy of `bytes` (a multiple of 16, pointers 16-byte
+ * aligned) by a plain streaming kernel: the bandwidth probe that the
+ * roofline figures are compared with. */
+int sv_probe_copy(void *dst, const void *src, size_t bytes, sv_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SV_H */

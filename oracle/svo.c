@@ -190,6 +190,9 @@ void svo_reproject(int W, int H, const double *z, const double *nx,
             ovalid[p] = 0;
             if (empty_px(z[p]))
                 continue;
+            /* motion that is not finite or beyond 2^20 pixels: no history */
+            if (!(fabs(mvx[p]) < 1048576.0) || !(fabs(mvy[p]) < 1048576.0))
+                continue;
             double fx0 = floor(mvx[p]), fy0 = floor(mvy[p]);
             double fx = mvx[p] - fx0, fy = mvy[p] - fy0;
             long x0 = x + (long)fx0, y0 = y + (long)fy0;

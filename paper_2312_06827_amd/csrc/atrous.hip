@@ -1,0 +1,496 @@
+// Edge-avoiding a-trous wavelet levels guided by the variance (Section 2,
+// Fig. 1) in 5x5 form, and the separable form of Section 3.3.
+//
+// Every tap's weight H(a,b) * w_z * w_n * w_l is evaluated as one
+// exponential: log2 H - |dz| kz(a,b) - |dL| kl + sigma_n log2 max(0, n.n'),
+// with kz(a,b) = log2(e) / (sigma_z |grad z . step (a,b)| + eps_z) (12
+// distinct values per pixel, the offsets pairing up as +-(a,b)) and
+// kl = log2(e) / (sigma_l kappa sqrt(g) + eps_l).  A tap outside the image
+// or on an empty pixel is staged with luminance +inf and zero colour,
+// variance, depth and normal, which drives its exponent to -inf (weight 0)
+// without a branch.
+#include "sv_internal.h"
+
+namespace sv {
+
+struct AtrousArgs {
+    const void *cr, *cg, *cb;
+    const float *var;
+    const void *z, *dzdx, *dzdy, *nx, *ny, *nz;
+    const float *kappa;
+    void *or_, *og, *ob;
+    float *var_out;
+    int w, h, pitch, step;
+    float sigma_z, sigma_n, sigma_l, eps_z, eps_l, tm_k;
+    float dmin;  // 1 when sigma_n == 0 (normal weight off), else 0
+    int inv_tm;
+};
+
+// log2 of the B3-spline taps (1, 4, 6, 4, 1) / 16
+__device__ constexpr float kLog2H1[5] = {-4.0f, -2.0f, -1.4150374992788438f, -2.0f, -4.0f};
+__device__ constexpr float kH1[5] = {0.0625f, 0.25f, 0.375f, 0.25f, 0.0625f};
+constexpr float kG3[3] = {0.25f, 0.5f, 0.25f};
+
+// Index of the distinct depth denominator of offset (a, b): offsets +-(a,b)
+// share one; the canonical one has b > 0, or b == 0 and a > 0.
+__host__ __device__ constexpr int kz_index(int a, int b) {
+    return (b < 0 || (b == 0 && a < 0)) ? kz_index(-a, -b)
+                                        : (b == 0 ? a - 1 : 2 + (b - 1) * 5 + (a + 2));
+}
+
+// 3x3 Gaussian of the variance around (x, y) over in-image, non-empty
+// pixels, renormalised.
+template <typename T>
+__device__ __forceinline__ float prefilter_global(const AtrousArgs &a, int x, int y) {
+    float s = 0.f, sw = 0.f;
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+        const int qy = y + dy;
+        if (qy < 0 || qy >= a.h) continue;
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int qx = x + dx;
+            if (qx < 0 || qx >= a.w) continue;
+            const size_t q = (size_t)qy * a.pitch + qx;
+            if (empty_px(ld((const T *)a.z + q))) continue;
+            const float k = kG3[dx + 1] * kG3[dy + 1];
+            s = fmaf(k, a.var[q], s);
+            sw += k;
+        }
+    }
+    return s / sw;
+}
+
+__device__ __forceinline__ float luma_scale(const AtrousArgs &a, float g, size_t o) {
+    const float kap = a.kappa ? a.kappa[o] : 1.0f;
+    return kLog2e / fmaf(a.sigma_l * kap, sqrtf(g), a.eps_l);
+}
+
+struct Acc {
+    float sw, sr, sg, sb, sv;
+};
+
+// One weighted tap (not the centre).  qc = (r, g, b, L), qg = (z, nx, ny, nz).
+template <bool UNIT, bool WANT_VAR>
+__device__ __forceinline__ void tap(Acc &acc, float4 qc, float4 qg, float qv, float log2h,
+                                    float hconst, float kz, float zp, float lp, float nxp,
+                                    float nyp, float nzp, float kl, float sn, float dmin) {
+    float hw;
+    if (UNIT) {
+        hw = qg.x > 0.f ? hconst : 0.f;
+    } else {
+        float t = fmaf(-fabsf(zp - qg.x), kz, log2h);
+        t = fmaf(-fabsf(lp - qc.w), kl, t);
+        const float d = fmaf(nzp, qg.w, fmaf(nyp, qg.z, nxp * qg.y));
+        t = fmaf(sn, fast_log2(fmaxf(d, dmin)), t);
+        hw = fast_exp2(t);
+    }
+    acc.sw += hw;
+    acc.sr = fmaf(hw, qc.x, acc.sr);
+    acc.sg = fmaf(hw, qc.y, acc.sg);
+    acc.sb = fmaf(hw, qc.z, acc.sb);
+    if (WANT_VAR) acc.sv = fmaf(hw * hw, qv, acc.sv);
+}
+
+template <typename T>
+__device__ __forceinline__ void write_out(const AtrousArgs &a, size_t o, float r, float g,
+                                          float b) {
+    if (a.inv_tm) inv_tonemap(r, g, b, a.tm_k);
+    st((T *)a.or_ + o, r);
+    st((T *)a.og + o, g);
+    st((T *)a.ob + o, b);
+}
+
+template <typename T>
+__device__ __forceinline__ void pass_through(const AtrousArgs &a, size_t o, const void *r,
+                                             const void *g, const void *b) {
+    write_out<T>(a, o, ld((const T *)r + o), ld((const T *)g + o), ld((const T *)b + o));
+    if (a.var_out) a.var_out[o] = 0.f;
+}
+
+// ---- 5x5 level, LDS tile ---------------------------------------------------
+//
+// A workgroup of 256 threads owns TX = 64 columns and TY = 4 * PY rows taken
+// on the step lattice: rows ybase + j * STEP, j = 0..TY-1, with ybase = band
+// * STEP * TY + phase.  All 25 taps of those pixels then lie in the tile's
+// own lattice rows j - 2 .. j + TY + 1 and columns -2 STEP .. TX + 2 STEP,
+// so the LDS footprint is (TY + 4) x (TX + 4 STEP) pixels whatever the step.
+template <typename T, int STEP, int PY, bool UNIT, bool WANT_VAR>
+__global__ __launch_bounds__(256) void atrous_tile_k(AtrousArgs a) {
+    constexpr int TX = 64, TY = 4 * PY, ROWS = TY + 4, COLS = TX + 4 * STEP;
+    constexpr bool NEED_V = WANT_VAR || STEP == 1;
+    __shared__ float4 s_cl[ROWS * COLS];  // r, g, b, L (L = +inf: no tap)
+    __shared__ float4 s_gn[ROWS * COLS];  // z, nx, ny, nz (z = 0: no tap)
+    __shared__ float s_v[NEED_V ? ROWS * COLS : 1];
+    const int tid = threadIdx.x;
+    const int x0 = blockIdx.x * TX;
+    const int band = blockIdx.y / STEP, phase = blockIdx.y - band * STEP;
+    const int ybase = band * STEP * TY + phase;
+
+    for (int i = tid; i < ROWS * COLS; i += 256) {
+        const int r = i / COLS, c = i - r * COLS;
+        const int gx = x0 - 2 * STEP + c, gy = ybase + (r - 2) * STEP;
+        float4 cl = make_float4(0.f, 0.f, 0.f, INFINITY);
+        float4 gn = make_float4(0.f, 0.f, 0.f, 0.f);
+        float v = 0.f;
+        if (gx >= 0 && gx < a.w && gy >= 0 && gy < a.h) {
+            const size_t o = (size_t)gy * a.pitch + gx;
+            const float zz = ld((const T *)a.z + o);
+            if (!empty_px(zz)) {
+                const float R = ld((const T *)a.cr + o), G = ld((const T *)a.cg + o),
+                            B = ld((const T *)a.cb + o);
+                cl = make_float4(R, G, B, luma(R, G, B));
+                gn = make_float4(zz, ld((const T *)a.nx + o), ld((const T *)a.ny + o),
+                                 ld((const T *)a.nz + o));
+                if (NEED_V) v = a.var[o];
+            }
+        }
+        s_cl[i] = cl;
+        s_gn[i] = gn;
+        if (NEED_V) s_v[i] = v;
+    }
+    __syncthreads();
+
+    const int lx = tid & 63, ly = tid >> 6;
+    const int x = x0 + lx;
+    if (x >= a.w) return;
+    const float sn = a.sigma_n, dmin = a.dmin;
+#pragma unroll 1
+    for (int k = 0; k < PY; ++k) {
+        const int j = ly + 4 * k;
+        const int y = ybase + j * STEP;
+        if (y >= a.h) break;
+        const size_t o = (size_t)y * a.pitch + x;
+        const int ci = (j + 2) * COLS + lx + 2 * STEP;
+        const float4 pc = s_cl[ci];
+        const float4 pg = s_gn[ci];
+        if (pg.x == 0.f) {  // empty pixel
+            pass_through<T>(a, o, a.cr, a.cg, a.cb);
+            continue;
+        }
+        // prefiltered variance
+        float g;
+        if (STEP == 1) {
+            float s = 0.f, sw = 0.f;
+#pragma unroll
+            for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int qi = ci + dy * COLS + dx;
+                    const float kk = s_gn[qi].x > 0.f ? kG3[dx + 1] * kG3[dy + 1] : 0.f;
+                    s = fmaf(kk, s_v[qi], s);
+                    sw += kk;
+                }
+            g = s / sw;
+        } else {
+            g = prefilter_global<T>(a, x, y);
+        }
+        float kz[12];
+        float kl = 0.f;
+        if (!UNIT) {
+            kl = luma_scale(a, g, o);
+            const float gx = ld((const T *)a.dzdx + o) * (float)STEP;
+            const float gy = ld((const T *)a.dzdy + o) * (float)STEP;
+#pragma unroll
+            for (int b = 0; b <= 2; ++b)
+#pragma unroll
+                for (int aa = -2; aa <= 2; ++aa) {
+                    if (b == 0 && aa <= 0) continue;
+                    const float den =
+                        fmaf(a.sigma_z, fabsf(fmaf(gx, (float)aa, gy * (float)b)), a.eps_z);
+                    kz[kz_index(aa, b)] = kLog2e * fast_rcp(den);
+                }
+        }
+        constexpr float h00 = 0.375f * 0.375f;
+        Acc acc;
+        acc.sw = h00;
+        acc.sr = h00 * pc.x;
+        acc.sg = h00 * pc.y;
+        acc.sb = h00 * pc.z;
+        acc.sv = WANT_VAR ? h00 * h00 * s_v[ci] : 0.f;
+#pragma unroll
+        for (int b = -2; b <= 2; ++b)
+#pragma unroll
+            for (int aa = -2; aa <= 2; ++aa) {
+                if (aa == 0 && b == 0) continue;
+                const int qi = ci + b * COLS + aa * STEP;
+                const float qv = WANT_VAR ? s_v[qi] : 0.f;
+                tap<UNIT, WANT_VAR>(acc, s_cl[qi], s_gn[qi], qv, kLog2H1[aa + 2] + kLog2H1[b + 2],
+                                    kH1[aa + 2] * kH1[b + 2], UNIT ? 0.f : kz[kz_index(aa, b)],
+                                    pg.x, pc.w, pg.y, pg.z, pg.w, kl, sn, dmin);
+            }
+        const float inv = 1.0f / acc.sw;
+        write_out<T>(a, o, acc.sr * inv, acc.sg * inv, acc.sb * inv);
+        if (WANT_VAR) a.var_out[o] = acc.sv * inv * inv;
+    }
+}
+
+// ---- 5x5 level, direct loads (any step) -------------------------------------
+
+template <typename T>
+__device__ __forceinline__ void load_tap(const AtrousArgs &a, int qx, int qy, float4 &qc,
+                                         float4 &qg, float &qv) {
+    qc = make_float4(0.f, 0.f, 0.f, INFINITY);
+    qg = make_float4(0.f, 0.f, 0.f, 0.f);
+    qv = 0.f;
+    if (qx < 0 || qx >= a.w || qy < 0 || qy >= a.h) return;
+    const size_t q = (size_t)qy * a.pitch + qx;
+    const float zz = ld((const T *)a.z + q);
+    if (empty_px(zz)) return;
+    const float R = ld((const T *)a.cr + q), G = ld((const T *)a.cg + q), B = ld((const T *)a.cb + q);
+    qc = make_float4(R, G, B, luma(R, G, B));
+    qg = make_float4(zz, ld((const T *)a.nx + q), ld((const T *)a.ny + q), ld((const T *)a.nz + q));
+    qv = a.var[q];
+}
+
+template <typename T, bool UNIT, bool WANT_VAR>
+__global__ __launch_bounds__(256) void atrous_direct_k(AtrousArgs a) {
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (x >= a.w || y >= a.h) return;
+    const size_t o = (size_t)y * a.pitch + x;
+    float4 pc, pg;
+    float pv;
+    load_tap<T>(a, x, y, pc, pg, pv);
+    if (pg.x == 0.f) {
+        pass_through<T>(a, o, a.cr, a.cg, a.cb);
+        return;
+    }
+    const float g = prefilter_global<T>(a, x, y);
+    const float s = (float)a.step;
+    float kz[12];
+    float kl = 0.f;
+    if (!UNIT) {
+        kl = luma_scale(a, g, o);
+        const float gx = ld((const T *)a.dzdx + o) * s, gy = ld((const T *)a.dzdy + o) * s;
+#pragma unroll
+        for (int b = 0; b <= 2; ++b)
+#pragma unroll
+            for (int aa = -2; aa <= 2; ++aa) {
+                if (b == 0 && aa <= 0) continue;
+                const float den = fmaf(a.sigma_z, fabsf(fmaf(gx, (float)aa, gy * (float)b)), a.eps_z);
+                kz[kz_index(aa, b)] = kLog2e * fast_rcp(den);
+            }
+    }
+    constexpr float h00 = 0.375f * 0.375f;
+    Acc acc{h00, h00 * pc.x, h00 * pc.y, h00 * pc.z, WANT_VAR ? h00 * h00 * pv : 0.f};
+#pragma unroll
+    for (int b = -2; b <= 2; ++b)
+#pragma unroll
+        for (int aa = -2; aa <= 2; ++aa) {
+            if (aa == 0 && b == 0) continue;
+            float4 qc, qg;
+            float qv;
+            load_tap<T>(a, x + aa * a.step, y + b * a.step, qc, qg, qv);
+            tap<UNIT, WANT_VAR>(acc, qc, qg, qv, kLog2H1[aa + 2] + kLog2H1[b + 2],
+                                kH1[aa + 2] * kH1[b + 2], UNIT ? 0.f : kz[kz_index(aa, b)], pg.x,
+                                pc.w, pg.y, pg.z, pg.w, kl, a.sigma_n, a.dmin);
+        }
+    const float inv = 1.0f / acc.sw;
+    write_out<T>(a, o, acc.sr * inv, acc.sg * inv, acc.sb * inv);
+    if (WANT_VAR) a.var_out[o] = acc.sv * inv * inv;
+}
+
+// ---- separable level (Section 3.3), direct loads -------------------------------
+//
+// Horizontal pass: colour only, into the scratch planes (the args' output
+// planes).  Vertical pass: reads the scratch planes as colour (cr/cg/cb) and
+// var_in for the propagation; g comes from var_in in both.
+
+template <typename T, bool UNIT, bool VERTICAL, bool WANT_VAR>
+__global__ __launch_bounds__(256) void atrous_sep_k(AtrousArgs a) {
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (x >= a.w || y >= a.h) return;
+    const size_t o = (size_t)y * a.pitch + x;
+    float4 pc, pg;
+    float pv;
+    load_tap<T>(a, x, y, pc, pg, pv);
+    if (pg.x == 0.f) {
+        if (VERTICAL) {
+            pass_through<T>(a, o, a.cr, a.cg, a.cb);
+        } else {
+            st((T *)a.or_ + o, ld((const T *)a.cr + o));
+            st((T *)a.og + o, ld((const T *)a.cg + o));
+            st((T *)a.ob + o, ld((const T *)a.cb + o));
+        }
+        return;
+    }
+    const float g = prefilter_global<T>(a, x, y);
+    const float s = (float)a.step;
+    float kz[2] = {0.f, 0.f};
+    float kl = 0.f;
+    if (!UNIT) {
+        kl = luma_scale(a, g, o);
+        const float grad = ld((const T *)(VERTICAL ? a.dzdy : a.dzdx) + o) * s;
+#pragma unroll
+        for (int i = 1; i <= 2; ++i) {
+            const float den = fmaf(a.sigma_z, fabsf(grad * (float)i), a.eps_z);
+            kz[i - 1] = kLog2e * fast_rcp(den);
+        }
+    }
+    constexpr float h0 = 0.375f;
+    Acc acc{h0, h0 * pc.x, h0 * pc.y, h0 * pc.z, WANT_VAR ? h0 * h0 * pv : 0.f};
+#pragma unroll
+    for (int t = -2; t <= 2; ++t) {
+        if (t == 0) continue;
+        float4 qc, qg;
+        float qv;
+        const int qx = VERTICAL ? x : x + t * a.step, qy = VERTICAL ? y + t * a.step : y;
+        load_tap<T>(a, qx, qy, qc, qg, qv);
+        tap<UNIT, WANT_VAR>(acc, qc, qg, qv, kLog2H1[t + 2], kH1[t + 2],
+                            UNIT ? 0.f : kz[(t < 0 ? -t : t) - 1], pg.x, pc.w, pg.y, pg.z, pg.w,
+                            kl, a.sigma_n, a.dmin);
+    }
+    const float inv = 1.0f / acc.sw;
+    if (VERTICAL) {
+        write_out<T>(a, o, acc.sr * inv, acc.sg * inv, acc.sb * inv);
+        if (WANT_VAR) a.var_out[o] = acc.sv * inv * inv;
+    } else {
+        st((T *)a.or_ + o, acc.sr * inv);
+        st((T *)a.og + o, acc.sg * inv);
+        st((T *)a.ob + o, acc.sb * inv);
+    }
+}
+
+// ---- launch ---------------------------------------------------------------------
+
+template <typename T, int STEP, bool UNIT, bool WANT_VAR>
+static void launch_tile(const AtrousArgs &a, hipStream_t s) {
+    constexpr int PY = 2, TY = 4 * PY;
+    const int bands = (a.h + STEP * TY - 1) / (STEP * TY);
+    dim3 grid((a.w + 63) / 64, bands * STEP);
+    hipLaunchKernelGGL((atrous_tile_k<T, STEP, PY, UNIT, WANT_VAR>), grid, dim3(256), 0, s, a);
+}
+
+template <typename T, bool UNIT, bool WANT_VAR>
+static void launch_2d(const AtrousArgs &a, hipStream_t s) {
+    switch (a.step) {
+    case 1: launch_tile<T, 1, UNIT, WANT_VAR>(a, s); return;
+    case 2: launch_tile<T, 2, UNIT, WANT_VAR>(a, s); return;
+    case 4: launch_tile<T, 4, UNIT, WANT_VAR>(a, s); return;
+    case 8: launch_tile<T, 8, UNIT, WANT_VAR>(a, s); return;
+    case 16: launch_tile<T, 16, UNIT, WANT_VAR>(a, s); return;
+    default: {
+        dim3 grid((a.w + 63) / 64, (a.h + 3) / 4);
+        hipLaunchKernelGGL((atrous_direct_k<T, UNIT, WANT_VAR>), grid, dim3(256), 0, s, a);
+    }
+    }
+}
+
+template <typename T>
+static void dispatch_2d(const AtrousArgs &a, bool unit, hipStream_t s) {
+    const bool wv = a.var_out != nullptr;
+    if (unit) {
+        if (wv) launch_2d<T, true, true>(a, s);
+        else launch_2d<T, true, false>(a, s);
+    } else {
+        if (wv) launch_2d<T, false, true>(a, s);
+        else launch_2d<T, false, false>(a, s);
+    }
+}
+
+template <typename T, bool VERTICAL>
+static void dispatch_sep(const AtrousArgs &a, bool unit, hipStream_t s) {
+    dim3 grid((a.w + 63) / 64, (a.h + 3) / 4);
+    const bool wv = VERTICAL && a.var_out != nullptr;
+    if (unit) {
+        if (wv) hipLaunchKernelGGL((atrous_sep_k<T, true, VERTICAL, true>), grid, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((atrous_sep_k<T, true, VERTICAL, false>), grid, dim3(256), 0, s, a);
+    } else {
+        if (wv) hipLaunchKernelGGL((atrous_sep_k<T, false, VERTICAL, true>), grid, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((atrous_sep_k<T, false, VERTICAL, false>), grid, dim3(256), 0, s, a);
+    }
+}
+
+static int check_atrous(const sv_rgb *c_in, const float *var_in, const sv_gbuf *g,
+                        const float *kappa, const sv_rgb *scratch, const sv_rgb *c_out,
+                        float *var_out, int32_t step, sv_dims d, sv_dtype t,
+                        const sv_atrous_params *p, int *empty) {
+    if (!valid_dtype(t)) return SV_EDTYPE;
+    int dc = check_dims(d);
+    if (dc < 0 || !c_in || !g || !c_out || !p || step < 1) return SV_EINVAL;
+    if (!(p->sigma_n >= 0.f)) return SV_EINVAL;
+    *empty = dc == 1;
+    if (dc == 1) return SV_OK;
+    if (!c_in->r || !c_in->g || !c_in->b || !var_in || !g->z || !g->dzdx || !g->dzdy || !g->nx ||
+        !g->ny || !g->nz || !c_out->r || !c_out->g || !c_out->b)
+        return SV_EINVAL;
+    const size_t es = elem_size(t);
+    const span ins[] = {plane_span(c_in->r, d, es), plane_span(c_in->g, d, es),
+                        plane_span(c_in->b, d, es), plane_span(var_in, d, 4),
+                        plane_span(g->z, d, es),    plane_span(g->dzdx, d, es),
+                        plane_span(g->dzdy, d, es), plane_span(g->nx, d, es),
+                        plane_span(g->ny, d, es),   plane_span(g->nz, d, es),
+                        kappa ? plane_span(kappa, d, 4) : span{0, 0}};
+    span outs[7];
+    int no = 0;
+    outs[no++] = plane_span(c_out->r, d, es);
+    outs[no++] = plane_span(c_out->g, d, es);
+    outs[no++] = plane_span(c_out->b, d, es);
+    if (var_out) outs[no++] = plane_span(var_out, d, 4);
+    if (scratch) {
+        outs[no++] = plane_span(scratch->r, d, es);
+        outs[no++] = plane_span(scratch->g, d, es);
+        outs[no++] = plane_span(scratch->b, d, es);
+    }
+    for (int i = 0; i < no; ++i) {
+        for (const span &si : ins)
+            if (overlaps(outs[i], si)) return SV_EALIAS;
+        for (int j = i + 1; j < no; ++j)
+            if (overlaps(outs[i], outs[j])) return SV_EALIAS;
+    }
+    return SV_OK;
+}
+
+static AtrousArgs make_args(const sv_rgb *c_in, const float *var_in, const sv_gbuf *g,
+                            const float *kappa, const sv_rgb *c_out, float *var_out,
+                            int32_t step, sv_dims d, const sv_atrous_params *p) {
+    return AtrousArgs{c_in->r, c_in->g, c_in->b, var_in, g->z, g->dzdx, g->dzdy, g->nx, g->ny,
+                      g->nz, kappa, c_out->r, c_out->g, c_out->b, var_out, d.w, d.h, d.pitch,
+                      step, p->sigma_z, p->sigma_n, p->sigma_l, p->eps_z, p->eps_l, p->tm_k,
+                      p->sigma_n == 0.f ? 1.f : 0.f, (p->flags & SV_A_INV_TONEMAP) ? 1 : 0};
+}
+
+}  // namespace sv
+
+extern "C" int sv_atrous(const sv_rgb *c_in, const float *var_in, const sv_gbuf *g,
+                         const float *kappa, const sv_rgb *c_out, float *var_out, int32_t step,
+                         sv_dims d, sv_dtype t, const sv_atrous_params *p, sv_stream stream) {
+    using namespace sv;
+    int empty = 0;
+    int rc = check_atrous(c_in, var_in, g, kappa, nullptr, c_out, var_out, step, d, t, p, &empty);
+    if (rc != SV_OK || empty) return rc;
+    AtrousArgs a = make_args(c_in, var_in, g, kappa, c_out, var_out, step, d, p);
+    const bool unit = (p->flags & SV_A_UNIT_WEIGHTS) != 0;
+    if (t == SV_F32) dispatch_2d<float>(a, unit, as_stream(stream));
+    else dispatch_2d<half_t>(a, unit, as_stream(stream));
+    return hip_status(hipGetLastError());
+}
+
+extern "C" int sv_atrous_sep(const sv_rgb *c_in, const float *var_in, const sv_gbuf *g,
+                             const float *kappa, const sv_rgb *scratch, const sv_rgb *c_out,
+                             float *var_out, int32_t step, sv_dims d, sv_dtype t,
+                             const sv_atrous_params *p, sv_stream stream) {
+    using namespace sv;
+    if (!scratch) return SV_EINVAL;
+    int empty = 0;
+    int rc = check_atrous(c_in, var_in, g, kappa, scratch, c_out, var_out, step, d, t, p, &empty);
+    if (rc != SV_OK || empty) return rc;
+    if (!scratch->r || !scratch->g || !scratch->b) return SV_EINVAL;
+    const bool unit = (p->flags & SV_A_UNIT_WEIGHTS) != 0;
+    hipStream_t s = as_stream(stream);
+    // horizontal: c_in -> scratch (no variance, no inverse tone map)
+    AtrousArgs h = make_args(c_in, var_in, g, kappa, scratch, nullptr, step, d, p);
+    h.inv_tm = 0;
+    // vertical: scratch -> c_out, variance from var_in
+    AtrousArgs v = make_args(scratch, var_in, g, kappa, c_out, var_out, step, d, p);
+    if (t == SV_F32) {
+        dispatch_sep<float, false>(h, unit, s);
+        dispatch_sep<float, true>(v, unit, s);
+    } else {
+        dispatch_sep<half_t, false>(h, unit, s);
+        dispatch_sep<half_t, true>(v, unit, s);
+    }
+    return hip_status(hipGetLastError());
+}

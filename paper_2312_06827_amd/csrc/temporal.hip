@@ -1,0 +1,333 @@
+// Temporal filter: backward reprojection of the history, variance colour
+// clamp of the reprojected colour, and accumulation of colour and luminance
+// moments (Section 2; Section 3 step 4; Section 3.1).  One fused pass:
+// every pixel reads its current colour (tone mapped on the fly), its 3x3
+// neighbourhood through an LDS tile, and four bilinear history taps.
+#include "sv_internal.h"
+
+namespace sv {
+
+constexpr int kTX = 64, kTY = 4;  // pixels per workgroup (one wave per row)
+
+struct TemporalArgs {
+    const void *cr, *cg, *cb;
+    const void *z, *nx, *ny, *nz;
+    const uint8_t *id;
+    const void *mvx, *mvy;
+    const void *pz, *pnx, *pny, *pnz;
+    const uint8_t *pid;
+    const void *hr, *hg, *hb;
+    const float *hm1, *hm2;
+    const uint8_t *hn;
+    void *or_, *og, *ob;
+    float *om1, *om2;
+    uint8_t *on;
+    const float *alpha_map;
+    int w, h, pitch;
+    float alpha, alpha_m, gamma, tau_z, tau_n, tm_k;
+    int max_hist;
+};
+
+// binary32 decisions, operation order fixed and never contracted.
+__device__ __forceinline__ bool depth_consistent(float z_prev, float z_cur, float tau) {
+    float d = fabsf(__fsub_rn(z_prev, z_cur));
+    float lim = __fmul_rn(tau, z_cur);
+    return d <= lim;
+}
+
+__device__ __forceinline__ bool normal_consistent(float ax, float ay, float az, float bx, float by,
+                                                  float bz, float tau) {
+    float d = __fmul_rn(ax, bx);
+    d = fmaf(ay, by, d);
+    d = fmaf(az, bz, d);
+    return d >= tau;
+}
+
+// 3x3 box of the tile around (lx+1, ly+1): mean and population sigma per
+// channel (two-pass) over valid entries (w component 1).
+__device__ __forceinline__ void box_stats(const float4 *tile, int lx, int ly, float3 &mu,
+                                          float3 &sd) {
+    float sr = 0.f, sg = 0.f, sb = 0.f, cnt = 0.f;
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) {
+            float4 q = tile[(ly + dy) * (kTX + 2) + lx + dx];
+            sr += q.w * q.x;
+            sg += q.w * q.y;
+            sb += q.w * q.z;
+            cnt += q.w;
+        }
+    float inv = 1.0f / cnt;
+    mu = make_float3(sr * inv, sg * inv, sb * inv);
+    float vr = 0.f, vg = 0.f, vb = 0.f;
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) {
+            float4 q = tile[(ly + dy) * (kTX + 2) + lx + dx];
+            float er = q.x - mu.x, eg = q.y - mu.y, eb = q.z - mu.z;
+            vr = fmaf(q.w * er, er, vr);
+            vg = fmaf(q.w * eg, eg, vg);
+            vb = fmaf(q.w * eb, eb, vb);
+        }
+    sd = make_float3(sqrtf(vr * inv), sqrtf(vg * inv), sqrtf(vb * inv));
+}
+
+// Stage the current colour (tone mapped if TM) of the tile and a one-pixel
+// apron; w = 1 for pixels inside the image that are not empty, else 0.
+template <typename T, bool TM>
+__device__ __forceinline__ void stage_current(float4 *tile, const void *cr, const void *cg,
+                                              const void *cb, const void *zp, int w, int h,
+                                              int pitch, float tm_k) {
+    const int x0 = blockIdx.x * kTX - 1, y0 = blockIdx.y * kTY - 1;
+    for (int i = threadIdx.x; i < (kTX + 2) * (kTY + 2); i += 256) {
+        int r = i / (kTX + 2), c = i - r * (kTX + 2);
+        int gx = x0 + c, gy = y0 + r;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (gx >= 0 && gx < w && gy >= 0 && gy < h) {
+            size_t o = (size_t)gy * pitch + gx;
+            float R = ld((const T *)cr + o), G = ld((const T *)cg + o), B = ld((const T *)cb + o);
+            if (TM) {
+                float den = 1.0f + tm_k * luma(R, G, B);
+                R = R / den;
+                G = G / den;
+                B = B / den;
+            }
+            float valid = (zp == nullptr || !empty_px(ld((const T *)zp + o))) ? 1.f : 0.f;
+            v = make_float4(R, G, B, valid);
+        }
+        tile[i] = v;
+    }
+}
+
+template <typename T, bool TM, bool CLAMP, bool USE_ID>
+__global__ __launch_bounds__(256) void temporal_k(TemporalArgs a) {
+    __shared__ float4 tile[(kTX + 2) * (kTY + 2)];
+    stage_current<T, TM>(tile, a.cr, a.cg, a.cb, a.z, a.w, a.h, a.pitch, a.tm_k);
+    __syncthreads();
+    const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
+    const int x = blockIdx.x * kTX + lx, y = blockIdx.y * kTY + ly;
+    if (x >= a.w || y >= a.h) return;
+    const size_t o = (size_t)y * a.pitch + x;
+    const float4 c = tile[(ly + 1) * (kTX + 2) + lx + 1];
+    const float L = luma(c.x, c.y, c.z);
+    const float zc = ld((const T *)a.z + o);
+    if (empty_px(zc)) {
+        st((T *)a.or_ + o, c.x);
+        st((T *)a.og + o, c.y);
+        st((T *)a.ob + o, c.z);
+        a.om1[o] = 0.f;
+        a.om2[o] = 0.f;
+        a.on[o] = 0;
+        return;
+    }
+    const float nxc = ld((const T *)a.nx + o), nyc = ld((const T *)a.ny + o),
+                nzc = ld((const T *)a.nz + o);
+    const float mvx = ld((const T *)a.mvx + o), mvy = ld((const T *)a.mvy + o);
+    const uint8_t idc = USE_ID ? a.id[o] : 0;
+
+    // ---- backward reprojection: bilinear taps around p + mv ----
+    float sw = 0.f, ar = 0.f, ag = 0.f, ab = 0.f, a1 = 0.f, a2 = 0.f;
+    int nmax = 0;
+    bool any = false;
+    if (fabsf(mvx) < 1048576.0f && fabsf(mvy) < 1048576.0f) {
+        const float fx0 = floorf(mvx), fy0 = floorf(mvy);
+        const float fx = mvx - fx0, fy = mvy - fy0;  // exact in binary32
+        const int x0 = x + (int)fx0, y0 = y + (int)fy0;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int tx = x0 + (t & 1), ty = y0 + (t >> 1);
+            const float bw = ((t & 1) ? fx : 1.0f - fx) * ((t >> 1) ? fy : 1.0f - fy);
+            if (!(bw > 0.f) || tx < 0 || tx >= a.w || ty < 0 || ty >= a.h) continue;
+            const size_t q = (size_t)ty * a.pitch + tx;
+            const int hn = a.hn[q];
+            if (hn < 1) continue;
+            if (!depth_consistent(ld((const T *)a.pz + q), zc, a.tau_z)) continue;
+            if (!normal_consistent(ld((const T *)a.pnx + q), ld((const T *)a.pny + q),
+                                   ld((const T *)a.pnz + q), nxc, nyc, nzc, a.tau_n))
+                continue;
+            if (USE_ID && a.pid[q] != idc) continue;
+            any = true;
+            sw += bw;
+            ar = fmaf(bw, ld((const T *)a.hr + q), ar);
+            ag = fmaf(bw, ld((const T *)a.hg + q), ag);
+            ab = fmaf(bw, ld((const T *)a.hb + q), ab);
+            a1 = fmaf(bw, a.hm1[q], a1);
+            a2 = fmaf(bw, a.hm2[q], a2);
+            nmax = max(nmax, hn);
+        }
+    }
+    float outr, outg, outb, m1, m2;
+    int n;
+    if (!any) {
+        outr = c.x;
+        outg = c.y;
+        outb = c.z;
+        m1 = L;
+        m2 = L * L;
+        n = 1;
+    } else {
+        float hr = ar / sw, hg = ag / sw, hb = ab / sw;
+        const float hm1 = a1 / sw, hm2 = a2 / sw;
+        // ---- history rectification: variance colour clamp ----
+        if (CLAMP) {
+            float3 mu, sd;
+            box_stats(tile, lx, ly, mu, sd);
+            hr = fminf(fmaxf(hr, mu.x - a.gamma * sd.x), mu.x + a.gamma * sd.x);
+            hg = fminf(fmaxf(hg, mu.y - a.gamma * sd.y), mu.y + a.gamma * sd.y);
+            hb = fminf(fmaxf(hb, mu.z - a.gamma * sd.z), mu.z + a.gamma * sd.z);
+        }
+        // ---- accumulation ----
+        n = min(nmax + 1, a.max_hist);
+        const float inv_n = 1.0f / (float)n;
+        const float ac = fmaxf(a.alpha_map ? a.alpha_map[o] : a.alpha, inv_n);
+        const float am = fmaxf(a.alpha_m, inv_n);
+        outr = fmaf(ac, c.x - hr, hr);
+        outg = fmaf(ac, c.y - hg, hg);
+        outb = fmaf(ac, c.z - hb, hb);
+        m1 = fmaf(am, L - hm1, hm1);
+        m2 = fmaf(am, fmaf(L, L, -hm2), hm2);
+    }
+    st((T *)a.or_ + o, outr);
+    st((T *)a.og + o, outg);
+    st((T *)a.ob + o, outb);
+    a.om1[o] = m1;
+    a.om2[o] = m2;
+    a.on[o] = (uint8_t)n;
+}
+
+struct ClampArgs {
+    const void *hr, *hg, *hb, *cr, *cg, *cb, *z;
+    void *or_, *og, *ob;
+    int w, h, pitch;
+    float gamma;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void clamp_k(ClampArgs a) {
+    __shared__ float4 tile[(kTX + 2) * (kTY + 2)];
+    stage_current<T, false>(tile, a.cr, a.cg, a.cb, a.z, a.w, a.h, a.pitch, 0.f);
+    __syncthreads();
+    const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
+    const int x = blockIdx.x * kTX + lx, y = blockIdx.y * kTY + ly;
+    if (x >= a.w || y >= a.h) return;
+    const size_t o = (size_t)y * a.pitch + x;
+    float r = ld((const T *)a.hr + o), g = ld((const T *)a.hg + o), b = ld((const T *)a.hb + o);
+    const bool active = a.gamma > 0.f && tile[(ly + 1) * (kTX + 2) + lx + 1].w > 0.f;
+    if (active) {
+        float3 mu, sd;
+        box_stats(tile, lx, ly, mu, sd);
+        r = fminf(fmaxf(r, mu.x - a.gamma * sd.x), mu.x + a.gamma * sd.x);
+        g = fminf(fmaxf(g, mu.y - a.gamma * sd.y), mu.y + a.gamma * sd.y);
+        b = fminf(fmaxf(b, mu.z - a.gamma * sd.z), mu.z + a.gamma * sd.z);
+    }
+    st((T *)a.or_ + o, r);
+    st((T *)a.og + o, g);
+    st((T *)a.ob + o, b);
+}
+
+template <typename T, bool TM, bool CLAMP>
+static void launch_temporal_id(const TemporalArgs &a, bool use_id, dim3 grid, hipStream_t s) {
+    if (use_id)
+        hipLaunchKernelGGL((temporal_k<T, TM, CLAMP, true>), grid, dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((temporal_k<T, TM, CLAMP, false>), grid, dim3(256), 0, s, a);
+}
+
+template <typename T>
+static void launch_temporal(const TemporalArgs &a, bool tm, bool clamp, bool use_id, dim3 grid,
+                            hipStream_t s) {
+    if (tm) {
+        if (clamp) launch_temporal_id<T, true, true>(a, use_id, grid, s);
+        else launch_temporal_id<T, true, false>(a, use_id, grid, s);
+    } else {
+        if (clamp) launch_temporal_id<T, false, true>(a, use_id, grid, s);
+        else launch_temporal_id<T, false, false>(a, use_id, grid, s);
+    }
+}
+
+}  // namespace sv
+
+extern "C" int sv_temporal(const sv_temporal_io *io, sv_dims d, sv_dtype t,
+                           const sv_temporal_params *p, sv_stream stream) {
+    using namespace sv;
+    if (!valid_dtype(t)) return SV_EDTYPE;
+    int dc = check_dims(d);
+    if (dc < 0 || !io || !p) return SV_EINVAL;
+    if (p->max_hist < 1 || p->max_hist > 255) return SV_EINVAL;
+    if (dc == 1) return SV_OK;
+    const bool use_id = (p->flags & SV_T_USE_ID) != 0;
+    const bool clamp = (p->flags & SV_T_CLAMP) != 0 && p->gamma > 0.f;
+    const bool tm = (p->flags & SV_T_TONEMAP_IN) != 0;
+    const void *req[] = {io->cur.r, io->cur.g, io->cur.b, io->g.z, io->g.nx, io->g.ny, io->g.nz,
+                         io->mvx, io->mvy, io->prev.z, io->prev.nx, io->prev.ny, io->prev.nz,
+                         io->hist.r, io->hist.g, io->hist.b, io->hist_m1, io->hist_m2,
+                         io->hist_n, io->out.r, io->out.g, io->out.b, io->out_m1,
+                         io->out_m2, io->out_n};
+    for (const void *q : req)
+        if (!q) return SV_EINVAL;
+    if (use_id && (!io->g.id || !io->prev.id)) return SV_EINVAL;
+    const size_t es = elem_size(t);
+    const span ins[] = {
+        plane_span(io->cur.r, d, es), plane_span(io->cur.g, d, es), plane_span(io->cur.b, d, es),
+        plane_span(io->g.z, d, es), plane_span(io->g.nx, d, es), plane_span(io->g.ny, d, es),
+        plane_span(io->g.nz, d, es), plane_span(io->mvx, d, es), plane_span(io->mvy, d, es),
+        plane_span(io->prev.z, d, es), plane_span(io->prev.nx, d, es),
+        plane_span(io->prev.ny, d, es), plane_span(io->prev.nz, d, es),
+        plane_span(io->hist.r, d, es), plane_span(io->hist.g, d, es),
+        plane_span(io->hist.b, d, es), plane_span(io->hist_m1, d, 4),
+        plane_span(io->hist_m2, d, 4), plane_span(io->hist_n, d, 1),
+        use_id ? plane_span(io->g.id, d, 1) : span{0, 0},
+        use_id ? plane_span(io->prev.id, d, 1) : span{0, 0},
+        io->alpha_map ? plane_span(io->alpha_map, d, 4) : span{0, 0}};
+    const span outs[] = {plane_span(io->out.r, d, es), plane_span(io->out.g, d, es),
+                         plane_span(io->out.b, d, es), plane_span(io->out_m1, d, 4),
+                         plane_span(io->out_m2, d, 4), plane_span(io->out_n, d, 1)};
+    for (const span &so : outs) {
+        for (const span &si : ins)
+            if (overlaps(so, si)) return SV_EALIAS;
+    }
+    for (int i = 0; i < 6; ++i)
+        for (int j = i + 1; j < 6; ++j)
+            if (overlaps(outs[i], outs[j])) return SV_EALIAS;
+    TemporalArgs a{io->cur.r, io->cur.g, io->cur.b, io->g.z, io->g.nx, io->g.ny, io->g.nz,
+                   io->g.id, io->mvx, io->mvy, io->prev.z, io->prev.nx, io->prev.ny,
+                   io->prev.nz, io->prev.id, io->hist.r, io->hist.g, io->hist.b, io->hist_m1,
+                   io->hist_m2, io->hist_n, io->out.r, io->out.g, io->out.b, io->out_m1,
+                   io->out_m2, io->out_n, io->alpha_map, d.w, d.h, d.pitch, p->alpha,
+                   p->alpha_m, p->gamma, p->tau_z, p->tau_n, p->tm_k, p->max_hist};
+    dim3 grid((d.w + kTX - 1) / kTX, (d.h + kTY - 1) / kTY);
+    hipStream_t s = as_stream(stream);
+    if (t == SV_F32) launch_temporal<float>(a, tm, clamp, use_id, grid, s);
+    else launch_temporal<half_t>(a, tm, clamp, use_id, grid, s);
+    return hip_status(hipGetLastError());
+}
+
+extern "C" int sv_clamp(const sv_rgb *hist, const sv_rgb *cur, const sv_rgb *out, const void *z,
+                        sv_dims d, sv_dtype t, float gamma, sv_stream stream) {
+    using namespace sv;
+    if (!valid_dtype(t)) return SV_EDTYPE;
+    int dc = check_dims(d);
+    if (dc < 0 || !hist || !cur || !out) return SV_EINVAL;
+    if (dc == 1) return SV_OK;
+    if (!hist->r || !hist->g || !hist->b || !cur->r || !cur->g || !cur->b || !out->r ||
+        !out->g || !out->b)
+        return SV_EINVAL;
+    const size_t es = elem_size(t);
+    const span ins[] = {plane_span(cur->r, d, es), plane_span(cur->g, d, es),
+                        plane_span(cur->b, d, es), z ? plane_span(z, d, es) : span{0, 0}};
+    const span outs[] = {plane_span(out->r, d, es), plane_span(out->g, d, es),
+                         plane_span(out->b, d, es)};
+    for (const span &so : outs)
+        for (const span &si : ins)
+            if (overlaps(so, si)) return SV_EALIAS;
+    ClampArgs a{hist->r, hist->g, hist->b, cur->r, cur->g, cur->b, z,
+                out->r, out->g, out->b, d.w, d.h, d.pitch, gamma};
+    dim3 grid((d.w + kTX - 1) / kTX, (d.h + kTY - 1) / kTY);
+    if (t == SV_F32)
+        hipLaunchKernelGGL(clamp_k<float>, grid, dim3(256), 0, as_stream(stream), a);
+    else
+        hipLaunchKernelGGL(clamp_k<half_t>, grid, dim3(256), 0, as_stream(stream), a);
+    return hip_status(hipGetLastError());
+}

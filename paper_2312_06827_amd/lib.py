@@ -1,0 +1,326 @@
+"""ctypes binding of ``libsv.so`` (C ABI in ``include/sv.h``).
+
+Argument marshalling only: every step runs in the library's HIP kernels.
+Planes are torch tensors on the GPU: a 2-D ``(H, W)`` view (row pitch =
+``stride(0)``, unit column stride) or, for colour and normals, a ``(3, H, W)``
+tensor whose three planes share that layout.  ``float32`` planes select
+``SV_F32`` storage, ``float16`` planes ``SV_F16``.  Calls are enqueued on
+torch's current stream unless ``stream`` (a ``torch.cuda.Stream``) is given.
+
+There is no CPU fallback: loading fails loudly when the library is missing,
+and CPU tensors are rejected.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence, Union
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsv.so")
+
+SV_OK, SV_EINVAL, SV_EALIAS, SV_EDTYPE, SV_EHIP, SV_EUNSUPPORTED = range(6)
+SV_F32, SV_F16 = 0, 1
+SV_TM_LUMA, SV_TM_CHANNEL, SV_TM_PAPER = 0, 1, 2
+SV_T_CLAMP, SV_T_USE_ID, SV_T_TONEMAP_IN = 1, 2, 4
+SV_A_UNIT_WEIGHTS, SV_A_INV_TONEMAP = 1, 2
+
+_vp = ctypes.c_void_p
+
+
+class sv_dims(ctypes.Structure):
+    _fields_ = [("w", ctypes.c_int32), ("h", ctypes.c_int32), ("pitch", ctypes.c_int32)]
+
+
+class sv_rgb(ctypes.Structure):
+    _fields_ = [("r", _vp), ("g", _vp), ("b", _vp)]
+
+
+class sv_gbuf(ctypes.Structure):
+    _fields_ = [("z", _vp), ("dzdx", _vp), ("dzdy", _vp), ("nx", _vp), ("ny", _vp),
+                ("nz", _vp), ("id", _vp)]
+
+
+class sv_tm_params(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_float), ("weight", ctypes.c_float), ("mode", ctypes.c_int32)]
+
+
+class sv_temporal_io(ctypes.Structure):
+    _fields_ = [("cur", sv_rgb), ("g", sv_gbuf), ("mvx", _vp), ("mvy", _vp),
+                ("prev", sv_gbuf), ("hist", sv_rgb), ("hist_m1", _vp), ("hist_m2", _vp),
+                ("hist_n", _vp), ("out", sv_rgb), ("out_m1", _vp), ("out_m2", _vp),
+                ("out_n", _vp), ("alpha_map", _vp)]
+
+
+class sv_temporal_params(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_float), ("alpha_m", ctypes.c_float),
+                ("gamma", ctypes.c_float), ("tau_z", ctypes.c_float),
+                ("tau_n", ctypes.c_float), ("tm_k", ctypes.c_float),
+                ("max_hist", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+class sv_variance_params(ctypes.Structure):
+    _fields_ = [("sigma_z", ctypes.c_float), ("sigma_n", ctypes.c_float),
+                ("eps_z", ctypes.c_float), ("min_hist", ctypes.c_int32),
+                ("radius", ctypes.c_int32)]
+
+
+class sv_atrous_params(ctypes.Structure):
+    _fields_ = [("sigma_z", ctypes.c_float), ("sigma_n", ctypes.c_float),
+                ("sigma_l", ctypes.c_float), ("eps_z", ctypes.c_float),
+                ("eps_l", ctypes.c_float), ("tm_k", ctypes.c_float),
+                ("flags", ctypes.c_int32)]
+
+
+_P = ctypes.POINTER
+EXPORTS = {
+    "sv_tonemap": ([_P(sv_rgb), _P(sv_rgb), sv_dims, ctypes.c_int, ctypes.c_int,
+                    _P(sv_tm_params), _vp], ctypes.c_int),
+    "sv_clamp": ([_P(sv_rgb), _P(sv_rgb), _P(sv_rgb), _vp, sv_dims, ctypes.c_int,
+                  ctypes.c_float, _vp], ctypes.c_int),
+    "sv_temporal": ([_P(sv_temporal_io), sv_dims, ctypes.c_int, _P(sv_temporal_params), _vp],
+                    ctypes.c_int),
+    "sv_variance": ([_vp, _vp, _vp, _P(sv_gbuf), _vp, sv_dims, ctypes.c_int,
+                     _P(sv_variance_params), _vp], ctypes.c_int),
+    "sv_atrous": ([_P(sv_rgb), _vp, _P(sv_gbuf), _vp, _P(sv_rgb), _vp, ctypes.c_int32,
+                   sv_dims, ctypes.c_int, _P(sv_atrous_params), _vp], ctypes.c_int),
+    "sv_atrous_sep": ([_P(sv_rgb), _vp, _P(sv_gbuf), _vp, _P(sv_rgb), _P(sv_rgb), _vp,
+                       ctypes.c_int32, sv_dims, ctypes.c_int, _P(sv_atrous_params), _vp],
+                      ctypes.c_int),
+    "sv_status_str": ([ctypes.c_int], ctypes.c_char_p),
+    "sv_version": ([], ctypes.c_int),
+    "sv_last_hip_error": ([], ctypes.c_int),
+    "sv_probe_copy": ([_vp, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libsv.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"{path} is missing: build it with `python -m paper_2312_06827_amd._build` "
+            "(there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    for name, (args, res) in EXPORTS.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+class SVError(RuntimeError):
+    def __init__(self, fn: str, status: int):
+        lib = load()
+        msg = lib.sv_status_str(status).decode()
+        if status == SV_EHIP:
+            msg += f" (hipError {lib.sv_last_hip_error()})"
+        super().__init__(f"{fn}: {msg}")
+        self.status = status
+
+
+def _check(fn: str, status: int):
+    if status != SV_OK:
+        raise SVError(fn, status)
+
+
+# ---- marshalling helpers ----------------------------------------------------
+
+Planes = Union[torch.Tensor, Sequence[torch.Tensor]]
+
+
+def _plane_ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected (the library takes device pointers)")
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError("a plane must be a 2-D (H, W) view with unit column stride")
+    return t.data_ptr()
+
+
+def _planes3(x: Planes):
+    if isinstance(x, torch.Tensor):
+        if x.dim() != 3 or x.shape[0] != 3:
+            raise ValueError("colour must be a (3, H, W) tensor or three planes")
+        return x[0], x[1], x[2]
+    r, g, b = x
+    return r, g, b
+
+
+def _rgb(x: Planes) -> sv_rgb:
+    r, g, b = _planes3(x)
+    return sv_rgb(_plane_ptr(r), _plane_ptr(g), _plane_ptr(b))
+
+
+def dims_of(t: torch.Tensor) -> sv_dims:
+    p = t if t.dim() == 2 else t[0]
+    return sv_dims(p.shape[1], p.shape[0], p.stride(0))
+
+
+def dtype_of(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return SV_F32
+    if t.dtype == torch.float16:
+        return SV_F16
+    raise ValueError(f"unsupported storage type {t.dtype}")
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+@dataclass
+class GBuf:
+    """G-buffer planes: depth, its screen gradients, normals (3, H, W), ids."""
+    z: torch.Tensor
+    dzdx: Optional[torch.Tensor]
+    dzdy: Optional[torch.Tensor]
+    n: torch.Tensor
+    id: Optional[torch.Tensor] = None
+
+    def c(self) -> sv_gbuf:
+        nx, ny, nz = _planes3(self.n)
+        return sv_gbuf(_plane_ptr(self.z), _plane_ptr(self.dzdx), _plane_ptr(self.dzdy),
+                       _plane_ptr(nx), _plane_ptr(ny), _plane_ptr(nz), _plane_ptr(self.id))
+
+
+@dataclass
+class TemporalParams:
+    alpha: float = 0.2
+    alpha_m: float = 0.2
+    gamma: float = 1.0
+    tau_z: float = 0.1
+    tau_n: float = 0.9
+    tm_k: float = 1.0
+    max_hist: int = 255
+    clamp: bool = False
+    use_id: bool = False
+    tonemap: bool = False
+
+    def c(self) -> sv_temporal_params:
+        flags = ((SV_T_CLAMP if self.clamp else 0) | (SV_T_USE_ID if self.use_id else 0)
+                 | (SV_T_TONEMAP_IN if self.tonemap else 0))
+        return sv_temporal_params(self.alpha, self.alpha_m, self.gamma, self.tau_z, self.tau_n,
+                                  self.tm_k, self.max_hist, flags)
+
+
+@dataclass
+class VarianceParams:
+    sigma_z: float = 1.0
+    sigma_n: float = 128.0
+    eps_z: float = 1e-10
+    min_hist: int = 4
+    radius: int = 3
+
+    def c(self) -> sv_variance_params:
+        return sv_variance_params(self.sigma_z, self.sigma_n, self.eps_z, self.min_hist,
+                                  self.radius)
+
+
+@dataclass
+class AtrousParams:
+    sigma_z: float = 1.0
+    sigma_n: float = 128.0
+    sigma_l: float = 4.0
+    eps_z: float = 1e-10
+    eps_l: float = 1e-10
+    tm_k: float = 1.0
+    unit_weights: bool = False
+    inv_tonemap: bool = False
+
+    def c(self) -> sv_atrous_params:
+        flags = ((SV_A_UNIT_WEIGHTS if self.unit_weights else 0)
+                 | (SV_A_INV_TONEMAP if self.inv_tonemap else 0))
+        return sv_atrous_params(self.sigma_z, self.sigma_n, self.sigma_l, self.eps_z,
+                                self.eps_l, self.tm_k, flags)
+
+
+# ---- the calls ------------------------------------------------------------------
+
+def sv_tonemap(inp: Planes, out: Planes, inverse: bool = False, k: float = 1.0,
+               weight: float = 1.0, mode: int = SV_TM_LUMA, stream=None):
+    r = _planes3(inp)[0]
+    p = sv_tm_params(k, weight, mode)
+    _check("sv_tonemap", load().sv_tonemap(
+        ctypes.byref(_rgb(inp)), ctypes.byref(_rgb(out)), dims_of(r), dtype_of(r),
+        int(bool(inverse)), ctypes.byref(p), _stream(stream)))
+
+
+def sv_clamp(hist: Planes, cur: Planes, out: Planes, gamma: float,
+             z: Optional[torch.Tensor] = None, stream=None):
+    r = _planes3(cur)[0]
+    _check("sv_clamp", load().sv_clamp(
+        ctypes.byref(_rgb(hist)), ctypes.byref(_rgb(cur)), ctypes.byref(_rgb(out)),
+        _plane_ptr(z), dims_of(r), dtype_of(r), float(gamma), _stream(stream)))
+
+
+def sv_temporal(cur: Planes, g: GBuf, mv: Planes, prev: GBuf, hist: Planes,
+                hist_m1: torch.Tensor, hist_m2: torch.Tensor, hist_n: torch.Tensor,
+                out: Planes, out_m1: torch.Tensor, out_m2: torch.Tensor, out_n: torch.Tensor,
+                params: TemporalParams, alpha_map: Optional[torch.Tensor] = None, stream=None):
+    mvx, mvy = mv[0], mv[1]
+    io = sv_temporal_io(_rgb(cur), g.c(), _plane_ptr(mvx), _plane_ptr(mvy), prev.c(),
+                        _rgb(hist), _plane_ptr(hist_m1), _plane_ptr(hist_m2),
+                        _plane_ptr(hist_n), _rgb(out), _plane_ptr(out_m1), _plane_ptr(out_m2),
+                        _plane_ptr(out_n), _plane_ptr(alpha_map))
+    r = _planes3(cur)[0]
+    pc = params.c()
+    _check("sv_temporal", load().sv_temporal(ctypes.byref(io), dims_of(r), dtype_of(r),
+                                             ctypes.byref(pc), _stream(stream)))
+
+
+def sv_variance(m1: torch.Tensor, m2: torch.Tensor, n: torch.Tensor, g: GBuf,
+                var: torch.Tensor, params: VarianceParams, stream=None):
+    gc = g.c()
+    pc = params.c()
+    _check("sv_variance", load().sv_variance(
+        _plane_ptr(m1), _plane_ptr(m2), _plane_ptr(n), ctypes.byref(gc), _plane_ptr(var),
+        dims_of(m1), dtype_of(g.z), ctypes.byref(pc), _stream(stream)))
+
+
+def sv_atrous(c_in: Planes, var_in: torch.Tensor, g: GBuf, c_out: Planes,
+              var_out: Optional[torch.Tensor], step: int, params: AtrousParams,
+              kappa: Optional[torch.Tensor] = None, stream=None):
+    r = _planes3(c_in)[0]
+    gc = g.c()
+    pc = params.c()
+    _check("sv_atrous", load().sv_atrous(
+        ctypes.byref(_rgb(c_in)), _plane_ptr(var_in), ctypes.byref(gc), _plane_ptr(kappa),
+        ctypes.byref(_rgb(c_out)), _plane_ptr(var_out), int(step), dims_of(r), dtype_of(r),
+        ctypes.byref(pc), _stream(stream)))
+
+
+def sv_atrous_sep(c_in: Planes, var_in: torch.Tensor, g: GBuf, scratch: Planes, c_out: Planes,
+                  var_out: Optional[torch.Tensor], step: int, params: AtrousParams,
+                  kappa: Optional[torch.Tensor] = None, stream=None):
+    r = _planes3(c_in)[0]
+    gc = g.c()
+    pc = params.c()
+    _check("sv_atrous_sep", load().sv_atrous_sep(
+        ctypes.byref(_rgb(c_in)), _plane_ptr(var_in), ctypes.byref(gc), _plane_ptr(kappa),
+        ctypes.byref(_rgb(scratch)), ctypes.byref(_rgb(c_out)), _plane_ptr(var_out), int(step),
+        dims_of(r), dtype_of(r), ctypes.byref(pc), _stream(stream)))
+
+
+def sv_probe_copy(dst: torch.Tensor, src: torch.Tensor, stream=None):
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() < nbytes:
+        raise ValueError("dst is smaller than src")
+    _check("sv_probe_copy", load().sv_probe_copy(dst.data_ptr(), src.data_ptr(), nbytes,
+                                                 _stream(stream)))
+
+
+def sv_version() -> int:
+    return load().sv_version()

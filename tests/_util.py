@@ -1,0 +1,47 @@
+"""Shared test helpers: the parity metric and seeded synthetic call inputs."""
+
+import sys
+
+import numpy as np
+
+
+def say(msg):
+    """Progress line, flushed, so a GPU run names its case before it runs."""
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel_err(gpu, ora, floor=1e-3):
+    """Largest relative error |g - o| / max(|o|, floor * RMS(o)), taken per
+    plane (leading axes are planes) and maximised."""
+    g = np.asarray(gpu, dtype=np.float64)
+    o = np.asarray(ora, dtype=np.float64)
+    assert g.shape == o.shape, (g.shape, o.shape)
+    if o.ndim == 2:
+        g, o = g[None], o[None]
+    g = g.reshape(-1, *o.shape[-2:])
+    o = o.reshape(-1, *o.shape[-2:])
+    worst = 0.0
+    for gp, op in zip(g, o):
+        rms = np.sqrt(np.mean(op * op))
+        den = np.maximum(np.abs(op), floor * rms)
+        den = np.where(den > 0, den, 1.0)
+        e = np.abs(gp - op) / den
+        if not np.all(np.isfinite(e)):
+            return float("inf")
+        worst = max(worst, float(e.max()))
+    return worst
+
+
+def random_gbuf(r, H, W, z_range=(4.0, 6.0)):
+    """A smooth random surface with its analytic gradients and normals."""
+    ys, xs = np.mgrid[0:H, 0:W].astype(np.float64)
+    kx, ky, ph = r.uniform(0.02, 0.1), r.uniform(0.02, 0.1), r.uniform(0, 6.28)
+    z = z_range[0] + (z_range[1] - z_range[0]) * 0.5 * (1 + np.sin(kx * xs + ph) * np.cos(ky * ys))
+    amp = 0.5 * (z_range[1] - z_range[0])
+    dzdx = amp * kx * np.cos(kx * xs + ph) * np.cos(ky * ys)
+    dzdy = -amp * ky * np.sin(kx * xs + ph) * np.sin(ky * ys)
+    n = np.stack([-dzdx, np.ones_like(z), -dzdy])
+    n /= np.linalg.norm(n, axis=0)
+    f = lambda a: a.astype(np.float32)
+    return f(z), f(dzdx), f(dzdy), f(n)

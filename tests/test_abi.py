@@ -1,0 +1,153 @@
+"""The C-ABI library loads, exports every symbol its header declares, and
+rejects bad arguments on the host before any HIP call (so these run
+without a GPU: no call here reaches a kernel launch)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2312_06827_amd import lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sv.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sv_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def so():
+    if not os.path.exists(L.LIB_PATH):
+        pytest.fail("libsv.so is not built (run __graft_entry__.build())")
+    return L.load()
+
+
+def test_every_declared_symbol_is_exported(so):
+    names = declared_functions()
+    assert {"sv_tonemap", "sv_clamp", "sv_temporal", "sv_variance", "sv_atrous",
+            "sv_atrous_sep"} <= set(names)
+    for n in names:
+        assert hasattr(so, n), n
+    assert set(names) <= set(L.EXPORTS)
+
+
+def test_status_strings_and_version(so):
+    assert so.sv_version() == 1
+    for code in range(6):
+        assert so.sv_status_str(code)
+    assert so.sv_status_str(99) == b"unknown status"
+    assert so.sv_last_hip_error() == 0
+
+
+# Fake device addresses: never dereferenced, every case below fails
+# validation before a launch.
+A = 0x10000000
+STRIDE = 0x01000000
+
+
+def rgb(base):
+    return L.sv_rgb(base, base + STRIDE, base + 2 * STRIDE)
+
+
+def gbuf(base):
+    return L.sv_gbuf(*[base + i * STRIDE for i in range(6)], None)
+
+
+D = L.sv_dims(64, 32, 64)
+TM = L.sv_tm_params(1.0, 1.0, L.SV_TM_LUMA)
+AP = L.sv_atrous_params(1.0, 128.0, 4.0, 1e-10, 1e-10, 1.0, 0)
+
+
+def test_tonemap_validation(so):
+    r = ctypes.byref
+    assert so.sv_tonemap(None, r(rgb(A)), D, L.SV_F32, 0, r(TM), None) == L.SV_EINVAL
+    assert so.sv_tonemap(r(rgb(A)), r(rgb(A)), D, 7, 0, r(TM), None) == L.SV_EDTYPE
+    assert so.sv_tonemap(r(rgb(A)), r(rgb(A)), L.sv_dims(64, 32, 10), L.SV_F32, 0, r(TM),
+                         None) == L.SV_EINVAL
+    assert so.sv_tonemap(r(rgb(A)), r(rgb(A)), L.sv_dims(-1, 32, 64), L.SV_F32, 0, r(TM),
+                         None) == L.SV_EINVAL
+    paper_fwd = L.sv_tm_params(1.0, 1.0, L.SV_TM_PAPER)
+    assert so.sv_tonemap(r(rgb(A)), r(rgb(A)), D, L.SV_F32, 0, r(paper_fwd),
+                         None) == L.SV_EUNSUPPORTED
+    # empty image: valid, nothing enqueued
+    assert so.sv_tonemap(r(rgb(A)), r(rgb(A)), L.sv_dims(0, 32, 64), L.SV_F32, 0, r(TM),
+                         None) == L.SV_OK
+    big = L.sv_dims(32768, 32768, 65536)
+    assert so.sv_tonemap(r(rgb(A)), r(rgb(A)), big, L.SV_F32, 0, r(TM), None) == L.SV_EINVAL
+
+
+def test_atrous_validation_and_aliasing(so):
+    r = ctypes.byref
+    B = A + 0x20000000
+    g = gbuf(A + 0x40000000)
+    var = A + 0x60000000
+    # step must be >= 1
+    assert so.sv_atrous(r(rgb(A)), var, r(g), None, r(rgb(B)), None, 0, D, L.SV_F32, r(AP),
+                        None) == L.SV_EINVAL
+    # output overlapping the input colour
+    assert so.sv_atrous(r(rgb(A)), var, r(g), None, r(rgb(A + 64)), None, 1, D, L.SV_F32,
+                        r(AP), None) == L.SV_EALIAS
+    # output variance overlapping the G-buffer
+    assert so.sv_atrous(r(rgb(A)), var, r(g), None, r(rgb(B)), A + 0x40000000 + 128, 1, D,
+                        L.SV_F32, r(AP), None) == L.SV_EALIAS
+    # two outputs on top of each other
+    assert so.sv_atrous(r(rgb(A)), var, r(g), None, L.sv_rgb(B, B, B + STRIDE), None, 1, D,
+                        L.SV_F32, r(AP), None) == L.SV_EALIAS
+    # missing G-buffer plane
+    g2 = gbuf(A + 0x40000000)
+    g2.nz = None
+    assert so.sv_atrous(r(rgb(A)), var, r(g2), None, r(rgb(B)), None, 1, D, L.SV_F32, r(AP),
+                        None) == L.SV_EINVAL
+    # separable needs scratch, which must not alias the output
+    assert so.sv_atrous_sep(r(rgb(A)), var, r(g), None, None, r(rgb(B)), None, 1, D, L.SV_F32,
+                            r(AP), None) == L.SV_EINVAL
+    assert so.sv_atrous_sep(r(rgb(A)), var, r(g), None, r(rgb(B)), r(rgb(B)), None, 1, D,
+                            L.SV_F32, r(AP), None) == L.SV_EALIAS
+    bad = L.sv_atrous_params(1.0, -1.0, 4.0, 1e-10, 1e-10, 1.0, 0)
+    assert so.sv_atrous(r(rgb(A)), var, r(g), None, r(rgb(B)), None, 1, D, L.SV_F32, r(bad),
+                        None) == L.SV_EINVAL
+
+
+def test_temporal_and_variance_validation(so):
+    r = ctypes.byref
+    io = L.sv_temporal_io()
+    p = L.sv_temporal_params(0.2, 0.2, 1.0, 0.1, 0.9, 1.0, 255, 0)
+    assert so.sv_temporal(r(io), D, L.SV_F32, r(p), None) == L.SV_EINVAL
+    base = [A + i * 0x01000000 for i in range(40)]
+    io = L.sv_temporal_io(rgb(base[0]), gbuf(base[3]), base[9], base[10], gbuf(base[11]),
+                          rgb(base[17]), base[20], base[21], base[22], rgb(base[23]),
+                          base[26], base[27], base[28], None)
+    # output moments on top of the history moments
+    io.out_m1 = base[20]
+    assert so.sv_temporal(r(io), D, L.SV_F32, r(p), None) == L.SV_EALIAS
+    io.out_m1 = base[26]
+    p_bad = L.sv_temporal_params(0.2, 0.2, 1.0, 0.1, 0.9, 1.0, 0, 0)
+    assert so.sv_temporal(r(io), D, L.SV_F32, r(p_bad), None) == L.SV_EINVAL
+    p_id = L.sv_temporal_params(0.2, 0.2, 1.0, 0.1, 0.9, 1.0, 255, L.SV_T_USE_ID)
+    assert so.sv_temporal(r(io), D, L.SV_F32, r(p_id), None) == L.SV_EINVAL
+    vp = L.sv_variance_params(1.0, 128.0, 1e-10, 4, 8)
+    g = gbuf(base[3])
+    assert so.sv_variance(base[30], base[31], base[32], r(g), base[33], D, L.SV_F32, r(vp),
+                          None) == L.SV_EINVAL
+    vp = L.sv_variance_params(1.0, 128.0, 1e-10, 4, 3)
+    assert so.sv_variance(base[30], base[31], base[32], r(g), base[30], D, L.SV_F32, r(vp),
+                          None) == L.SV_EALIAS
+
+
+def test_probe_copy_validation(so):
+    assert so.sv_probe_copy(None, A, 64, None) == L.SV_EINVAL
+    assert so.sv_probe_copy(A, A + 0x100000, 60, None) == L.SV_EINVAL
+    assert so.sv_probe_copy(A, A + 32, 64, None) == L.SV_EALIAS
+    assert so.sv_probe_copy(A, A + 0x100000, 0, None) == L.SV_OK
+
+
+def test_binding_rejects_host_tensors():
+    import torch
+    t = torch.zeros((3, 4, 4))
+    with pytest.raises(ValueError):
+        L.sv_tonemap(t, t)

@@ -1,0 +1,264 @@
+"""Parity of every library call, through the C ABI, with the FP64 oracle on
+identical seeded inputs (binary32 storage): element by element, maximum
+relative error 1e-5 (per plane, denominators floored at 1e-3 of the
+plane's RMS).  History lengths are compared exactly.  Sizes span several
+64x8 tiles with ragged tails, down to 1x1, and planes with a row pitch
+larger than the width."""
+
+from dataclasses import replace
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2312_06827_amd import lib as L
+from paper_2312_06827_amd.scene import CONFIGS, render_frame, with_size
+from tests._util import rel_err, random_gbuf, say
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+SIZES = [(1, 1), (3, 5), (37, 70), (67, 131)]  # (H, W)
+
+
+def dev(a, pitch=None, dtype=torch.float32):
+    """numpy (.., H, W) -> device tensor view with row pitch `pitch`."""
+    a = np.ascontiguousarray(a)
+    t = torch.from_numpy(a).to(dtype)
+    if pitch is None or pitch == a.shape[-1]:
+        return t.cuda()
+    full = torch.zeros(a.shape[:-1] + (pitch,), dtype=dtype)
+    full[..., : a.shape[-1]] = t
+    return full.cuda()[..., : a.shape[-1]]
+
+
+def empty_like_dev(shape, pitch=None, dtype=torch.float32):
+    W = shape[-1]
+    p = W if pitch is None else pitch
+    t = torch.full(shape[:-1] + (p,), float("nan") if dtype.is_floating_point else 0,
+                   dtype=dtype, device="cuda")
+    return t[..., :W]
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().to(torch.float64).cpu().numpy() if t.dtype.is_floating_point \
+        else t.detach().cpu().numpy()
+
+
+def gbuf_dev(z, dzdx, dzdy, n, pitch=None, ids=None):
+    return L.GBuf(dev(z, pitch), dev(dzdx, pitch), dev(dzdy, pitch), dev(n, pitch),
+                  None if ids is None else dev(ids, pitch, torch.uint8))
+
+
+def scene_frame(H, W, frame=3, seed=2):
+    cfg = replace(with_size(CONFIGS["hd_motion"], W, H, frame + 1), seed=seed)
+    return render_frame(cfg, frame)
+
+
+# ---- tone map -----------------------------------------------------------------
+
+@pytest.mark.parametrize("H,W", SIZES)
+def test_tonemap(H, W):
+    r = np.random.default_rng(100 + H)
+    c = r.exponential(1.0, (3, H, W)).astype(np.float32) * 3
+    for mode, name in [(L.SV_TM_LUMA, "luma"), (L.SV_TM_CHANNEL, "channel")]:
+        for inverse in (False, True):
+            src = c if not inverse else O.tonemap(c, mode=name).astype(np.float32)
+            say(f"tonemap {H}x{W} mode={name} inverse={inverse}")
+            out = empty_like_dev((3, H, W), pitch=W + 3)
+            L.sv_tonemap(dev(src, W + 3), out, inverse=inverse, mode=mode, k=1.0)
+            ref = O.tonemap(src, inverse=inverse, mode=name)
+            assert rel_err(host(out), ref) <= TOL32
+    src = O.tonemap(c).astype(np.float32)
+    out = empty_like_dev((3, H, W))
+    L.sv_tonemap(dev(src), out, inverse=True, mode=L.SV_TM_PAPER, weight=0.7)
+    assert rel_err(host(out), O.tonemap(src, inverse=True, mode="paper", weight=0.7)) <= TOL32
+
+
+def test_tonemap_in_place():
+    c = np.random.default_rng(1).exponential(1.0, (3, 40, 50)).astype(np.float32)
+    t = dev(c)
+    L.sv_tonemap(t, t)
+    assert rel_err(host(t), O.tonemap(c)) <= TOL32
+
+
+# ---- clamp --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("H,W", SIZES)
+@pytest.mark.parametrize("gamma", [0.0, 1.0, 2.5])
+def test_clamp(H, W, gamma):
+    r = np.random.default_rng(200 + H + int(gamma * 10))
+    cur = r.uniform(0, 1, (3, H, W)).astype(np.float32)
+    hist = r.uniform(-0.5, 1.5, (3, H, W)).astype(np.float32)
+    z = r.uniform(1, 2, (H, W)).astype(np.float32)
+    z[r.random((H, W)) < 0.1] = 0.0  # empty pixels
+    say(f"clamp {H}x{W} gamma={gamma}")
+    out = empty_like_dev((3, H, W), pitch=W + 1)
+    L.sv_clamp(dev(hist, W + 1), dev(cur, W + 1), out, gamma, z=dev(z, W + 1))
+    ref = O.clamp(hist, cur, gamma, z=z)
+    assert rel_err(host(out), ref) <= TOL32
+
+
+# ---- temporal ---------------------------------------------------------------------
+
+def _temporal_case(H, W, seed):
+    fr = scene_frame(H, W, frame=3, seed=seed)
+    r = np.random.default_rng(seed)
+    # a synthetic history: shifted clean image plus noise, random moments,
+    # lengths 0..12 (some taps have no history)
+    hist = (np.roll(fr["clean"], 1, axis=-1) * r.uniform(0.7, 1.3, (3, H, W))).astype(np.float32)
+    L0 = hist.mean(0)
+    m1 = (L0 * r.uniform(0.9, 1.1, (H, W))).astype(np.float32)
+    m2 = (m1 * m1 * r.uniform(1.0, 2.0, (H, W))).astype(np.float32)
+    hn = r.integers(0, 13, (H, W)).astype(np.uint8)
+    state = {"rgb": hist, "m1": m1, "m2": m2, "n": hn}
+    return fr, state
+
+
+@pytest.mark.parametrize("H,W", [(3, 5), (37, 70), (67, 131)])
+@pytest.mark.parametrize("clamp,tonemap,use_id", [
+    (False, False, False), (True, False, False), (False, True, False), (True, True, True)])
+def test_temporal(H, W, clamp, tonemap, use_id):
+    fr, st = _temporal_case(H, W, 7 + H)
+    if H > 10:  # a few empty pixels
+        fr = dict(fr)
+        fr["z"] = fr["z"].copy()
+        fr["z"][5, 7] = 0.0
+        fr["z"][-1, -1] = np.inf
+    p = O.OracleParams(clamp=clamp, tonemap=tonemap, use_id=use_id, gamma=1.0)
+    ref = O.temporal(fr, st, p)
+    P = W + 5
+    say(f"temporal {H}x{W} clamp={clamp} tm={tonemap} id={use_id}")
+    g = gbuf_dev(fr["z"], fr["dzdx"], fr["dzdy"], fr["n"], P, fr["id"])
+    prev = L.GBuf(dev(fr["prev_z"], P), None, None, dev(fr["prev_n"], P),
+                  dev(fr["prev_id"], P, torch.uint8))
+    out = empty_like_dev((3, H, W), P)
+    om1, om2 = empty_like_dev((H, W), P), empty_like_dev((H, W), P)
+    on = empty_like_dev((H, W), P, torch.uint8)
+    tp = L.TemporalParams(clamp=clamp, tonemap=tonemap, use_id=use_id, gamma=1.0)
+    L.sv_temporal(dev(fr["rgb"], P), g, dev(fr["mv"], P), prev, dev(st["rgb"], P),
+                  dev(st["m1"], P), dev(st["m2"], P), dev(st["n"], P, torch.uint8),
+                  out, om1, om2, on, tp)
+    np.testing.assert_array_equal(host(on), ref["n"])
+    assert rel_err(host(out), ref["rgb"]) <= TOL32
+    assert rel_err(host(om1), ref["m1"]) <= TOL32
+    assert rel_err(host(om2), ref["m2"]) <= TOL32
+
+
+def test_temporal_alpha_map_and_discarded_motion():
+    H, W = 40, 72
+    fr, st = _temporal_case(H, W, 31)
+    fr = dict(fr)
+    fr["mv"] = fr["mv"].copy()
+    fr["mv"][0, 3, 3] = np.nan
+    fr["mv"][1, 4, 4] = 2.0e6
+    am = np.random.default_rng(3).uniform(0.05, 1.0, (H, W)).astype(np.float32)
+    p = O.OracleParams(clamp=True, tonemap=True)
+    ref = O.temporal(fr, st, p, alpha_map=am)
+    say("temporal alpha_map")
+    g = gbuf_dev(fr["z"], fr["dzdx"], fr["dzdy"], fr["n"])
+    prev = L.GBuf(dev(fr["prev_z"]), None, None, dev(fr["prev_n"]))
+    out, om1, om2 = empty_like_dev((3, H, W)), empty_like_dev((H, W)), empty_like_dev((H, W))
+    on = empty_like_dev((H, W), dtype=torch.uint8)
+    L.sv_temporal(dev(fr["rgb"]), g, dev(fr["mv"]), prev, dev(st["rgb"]), dev(st["m1"]),
+                  dev(st["m2"]), dev(st["n"], dtype=torch.uint8), out, om1, om2, on,
+                  L.TemporalParams(clamp=True, tonemap=True), alpha_map=dev(am))
+    np.testing.assert_array_equal(host(on), ref["n"])
+    assert host(on)[3, 3] == 1 and host(on)[4, 4] == 1
+    assert rel_err(host(out), ref["rgb"]) <= TOL32
+
+
+# ---- variance ------------------------------------------------------------------------
+
+@pytest.mark.parametrize("H,W", SIZES)
+def test_variance(H, W):
+    r = np.random.default_rng(300 + H)
+    z, dzdx, dzdy, n = random_gbuf(r, H, W)
+    if H > 10:
+        z[r.random((H, W)) < 0.05] = 0.0
+    m1 = r.uniform(0.1, 1.0, (H, W)).astype(np.float32)
+    m2 = (m1 * m1 * r.uniform(0.9, 2.0, (H, W))).astype(np.float32)
+    hn = r.integers(0, 7, (H, W)).astype(np.uint8)
+    for sigma_n in (128.0, 0.0):
+        say(f"variance {H}x{W} sigma_n={sigma_n}")
+        out = empty_like_dev((H, W), W + 2)
+        L.sv_variance(dev(m1, W + 2), dev(m2, W + 2), dev(hn, W + 2, torch.uint8),
+                      gbuf_dev(z, dzdx, dzdy, n, W + 2), out, L.VarianceParams(sigma_n=sigma_n))
+        ref = O.variance(m1, m2, hn, z, dzdx, dzdy, n, sigma_n=sigma_n)
+        assert rel_err(host(out), ref) <= TOL32
+
+
+# ---- a-trous ----------------------------------------------------------------------------
+
+def _atrous_inputs(H, W, seed, holes=False, scene=True):
+    r = np.random.default_rng(seed)
+    if scene and H >= 8 and W >= 8:
+        fr = scene_frame(H, W, frame=2, seed=seed)
+        z, dzdx, dzdy, n = fr["z"], fr["dzdx"], fr["dzdy"], fr["n"]
+        c = O.tonemap(fr["rgb"]).astype(np.float32)
+    else:
+        z, dzdx, dzdy, n = random_gbuf(r, H, W)
+        c = r.exponential(0.5, (3, H, W)).astype(np.float32)
+    z = z.copy()
+    if holes:
+        z[r.random((H, W)) < 0.03] = 0.0
+    var = (r.uniform(0.001, 0.05, (H, W))).astype(np.float32)
+    return c, var, z, dzdx, dzdy, n
+
+
+@pytest.mark.parametrize("H,W", SIZES + [(130, 200)])
+@pytest.mark.parametrize("step", [1, 2, 3, 4, 8, 16, 32])
+def test_atrous(H, W, step):
+    c, var, z, dzdx, dzdy, n = _atrous_inputs(H, W, 400 + step + H, holes=(step == 2))
+    P = W + 7
+    g = gbuf_dev(z, dzdx, dzdy, n, P)
+    for unit, want_var, inv in [(False, True, False), (False, False, True), (True, True, False)]:
+        say(f"atrous {H}x{W} step={step} unit={unit} var={want_var} inv={inv}")
+        out = empty_like_dev((3, H, W), P)
+        vo = empty_like_dev((H, W), P) if want_var else None
+        L.sv_atrous(dev(c, P), dev(var, P), g, out, vo, step,
+                    L.AtrousParams(unit_weights=unit, inv_tonemap=inv))
+        rc, rv = O.atrous(c, var, z, dzdx, dzdy, n, step, unit_weights=unit, inv_tonemap=inv,
+                          want_var=want_var)
+        assert rel_err(host(out), rc) <= TOL32
+        if want_var:
+            assert rel_err(host(vo), rv) <= TOL32
+
+
+@pytest.mark.parametrize("step", [1, 4, 16])
+def test_atrous_kappa_and_params(step):
+    H, W = 90, 150
+    c, var, z, dzdx, dzdy, n = _atrous_inputs(H, W, 500 + step)
+    kappa = np.random.default_rng(5).uniform(0.25, 4.0, (H, W)).astype(np.float32)
+    g = gbuf_dev(z, dzdx, dzdy, n)
+    for sz, sn, sl in [(1.0, 128.0, 4.0), (2.0, 0.0, 1.0), (0.5, 32.0, 8.0)]:
+        say(f"atrous params step={step} sz={sz} sn={sn} sl={sl}")
+        out, vo = empty_like_dev((3, H, W)), empty_like_dev((H, W))
+        L.sv_atrous(dev(c), dev(var), g, out, vo, step,
+                    L.AtrousParams(sigma_z=sz, sigma_n=sn, sigma_l=sl), kappa=dev(kappa))
+        rc, rv = O.atrous(c, var, z, dzdx, dzdy, n, step, kappa=kappa, sigma_z=sz, sigma_n=sn,
+                          sigma_l=sl)
+        assert rel_err(host(out), rc) <= TOL32
+        assert rel_err(host(vo), rv) <= TOL32
+
+
+@pytest.mark.parametrize("H,W", SIZES + [(130, 200)])
+@pytest.mark.parametrize("step", [1, 2, 4, 8, 16, 5])
+def test_atrous_sep(H, W, step):
+    c, var, z, dzdx, dzdy, n = _atrous_inputs(H, W, 600 + step + H, holes=(step == 4))
+    P = W + 2
+    g = gbuf_dev(z, dzdx, dzdy, n, P)
+    for unit, want_var, inv in [(False, True, False), (False, False, True), (True, True, False)]:
+        say(f"atrous_sep {H}x{W} step={step} unit={unit} var={want_var} inv={inv}")
+        out, sh = empty_like_dev((3, H, W), P), empty_like_dev((3, H, W), P)
+        vo = empty_like_dev((H, W), P) if want_var else None
+        L.sv_atrous_sep(dev(c, P), dev(var, P), g, sh, out, vo, step,
+                        L.AtrousParams(unit_weights=unit, inv_tonemap=inv))
+        rc, rv, rsh = O.atrous_sep(c, var, z, dzdx, dzdy, n, step, unit_weights=unit,
+                                   inv_tonemap=inv, want_var=want_var)
+        assert rel_err(host(sh), rsh) <= TOL32
+        assert rel_err(host(out), rc) <= TOL32
+        if want_var:
+            assert rel_err(host(vo), rv) <= TOL32

@@ -1,0 +1,72 @@
+"""Whole-chain parity: the device pipeline (temporal, variance, five a-trous
+levels, tone map around them) against the oracle run frame by frame on the
+same generated sequence.  Every frame's output and the temporal
+intermediates must stay within 1e-5 (binary32 storage); history lengths
+must agree exactly (no decision flips)."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2312_06827_amd.pipeline import MOTION, MOTION_SEP, PLAIN, Denoiser, FrameInputs
+from paper_2312_06827_amd.scene import CONFIGS, sequence, with_size
+from tests._util import rel_err, say
+
+pytestmark = pytest.mark.gpu
+TOL32 = 1e-5
+
+ORACLE_PLAIN = O.OracleParams()
+ORACLE_MOTION = O.OracleParams(clamp=True, tonemap=True, use_id=True)
+ORACLE_MOTION_SEP = O.OracleParams(clamp=True, tonemap=True, use_id=True, separable=True)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().to(torch.float64).cpu().numpy() if t.dtype.is_floating_point \
+        else t.detach().cpu().numpy()
+
+
+def run_pair(cfg, filt, ofilt, frames=None, check_every=1):
+    den = Denoiser(cfg.height, cfg.width, filt)
+    st = O.new_state(cfg.height, cfg.width)
+    worst = 0.0
+    for f, fr in enumerate(sequence(cfg, 0, frames)):
+        out = den.frame(FrameInputs.from_numpy(fr))
+        ref, st, ex = O.run_frame(fr, st, ofilt)
+        if f % check_every and f != (frames or cfg.frames) - 1:
+            continue
+        inter = den.intermediates()
+        np.testing.assert_array_equal(host(inter["n"]), ex["temporal"]["n"])
+        errs = {
+            "out": rel_err(host(out), ref),
+            "temporal": rel_err(host(inter["t_rgb"]), ex["temporal"]["rgb"]),
+            "m1": rel_err(host(inter["m1"]), ex["temporal"]["m1"]),
+            "m2": rel_err(host(inter["m2"]), ex["temporal"]["m2"]),
+            "var": rel_err(host(inter["var"]), ex["var"]),
+        }
+        say(f"  frame {f}: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+        worst = max(worst, max(errs.values()))
+        for k, v in errs.items():
+            assert v <= TOL32, (f, k, v)
+    return worst
+
+
+def test_small_static_plain():
+    say("sequence 256x256 static, plain filter, 8 frames")
+    run_pair(CONFIGS["small_static"], PLAIN, ORACLE_PLAIN)
+
+
+@pytest.mark.parametrize("sep", [False, True])
+def test_motion_reduced(sep):
+    cfg = with_size(CONFIGS["hd_motion"], 480, 270, 12)
+    say(f"sequence 480x270 motion, clamp+tonemap, separable={sep}, 12 frames")
+    run_pair(cfg, MOTION_SEP if sep else MOTION, ORACLE_MOTION_SEP if sep else ORACLE_MOTION)
+
+
+@pytest.mark.parametrize("sep", [False, True])
+def test_motion_full_hd_first_frames(sep):
+    cfg = CONFIGS["hd_motion"]
+    say(f"sequence 1920x1080 motion, separable={sep}, 3 frames")
+    run_pair(cfg, MOTION_SEP if sep else MOTION, ORACLE_MOTION_SEP if sep else ORACLE_MOTION,
+             frames=3)
