@@ -71,42 +71,47 @@ def generate(cfg, n_frames, workers):
 
 
 class KernelTimer:
-    """HIP events around each library call, on the stream it runs on."""
+    """HIP events around each library call, recorded on torch's current
+    stream (the stream the calls launch on).  Events are created up front so
+    that no event creation happens inside the timed loop."""
 
-    def __init__(self, torch):
-        self.torch = torch
-        self.pending = []
+    def __init__(self, torch, n):
+        self.pool = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                     for _ in range(n)]
+        self.used = []
 
     def __call__(self, name):
-        torch = self.torch
-        timer = self
+        a, b = self.pool[len(self.used)]
+        self.used.append((name, a, b))
 
         class _Ctx:
             def __enter__(self_):
-                self_.a = torch.cuda.Event(enable_timing=True)
-                self_.b = torch.cuda.Event(enable_timing=True)
-                self_.a.record()
+                a.record()
 
             def __exit__(self_, *exc):
-                self_.b.record()
-                timer.pending.append((name, self_.a, self_.b))
+                b.record()
         return _Ctx()
 
     def summary(self):
         out = {}
-        for name, a, b in self.pending:
+        for name, a, b in self.used:
             out.setdefault(name, []).append(a.elapsed_time(b))
         return {k: (float(np.mean(v)), len(v)) for k, v in out.items()}
 
 
-def run_chain(torch, frames_dev, cfg, H, W, warmup, steps, with_timer):
+def run_chain(torch, frames_dev, cfg, H, W, warmup, steps, per_kernel):
+    """Warm up, then time `steps` frames.  Headline mode enqueues each frame
+    with one native call and nothing else; per-kernel mode brackets every
+    library call with events (which adds a few microseconds per call)."""
     from paper_2312_06827_amd.pipeline import Denoiser
 
     den = Denoiser(H, W, cfg)
+    timer = KernelTimer(torch, 16 * (warmup + steps)) if per_kernel else None
     for f in range(warmup):
-        den.frame(frames_dev[f])
+        den.frame(frames_dev[f], timer=timer)
     torch.cuda.synchronize()
-    timer = KernelTimer(torch) if with_timer else None
+    if timer is not None:
+        timer.used.clear()
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -184,12 +189,17 @@ def main():
     frames_dev = [FrameInputs.from_numpy(fr) for fr in frames_np]
     torch.cuda.synchronize()
 
-    gpu_ms, wall, ktimes = run_chain(torch, frames_dev, MOTION, H, W, args.warmup, args.steps,
-                                     with_timer=True)
+    # a throwaway pass warms clocks, code objects and allocator
+    run_chain(torch, frames_dev, MOTION, H, W, 2, min(8, args.steps), per_kernel=False)
+    gpu_ms, wall, _ = run_chain(torch, frames_dev, MOTION, H, W, args.warmup, args.steps,
+                                per_kernel=False)
     ms_per_step = gpu_ms / args.steps
     mpix = W * H * args.steps / (gpu_ms * 1e-3) / 1e6
     print(f"# 2d chain: {ms_per_step * 1e3:.1f} us/frame (host wall {wall / args.steps * 1e6:.1f}"
           f" us/frame)", file=sys.stderr, flush=True)
+    # per-kernel durations: the same frames again, every call between events
+    _, _, ktimes = run_chain(torch, frames_dev, MOTION, H, W, args.warmup, args.steps,
+                             per_kernel=True)
 
     # roofline of the dominant kernel: the a-trous levels
     npx = W * H
@@ -205,8 +215,10 @@ def main():
 
     variants = {}
     if not args.no_variants:
-        g2, w2, kt2 = run_chain(torch, frames_dev, MOTION_SEP, H, W, args.warmup, args.steps,
-                                with_timer=True)
+        g2, w2, _ = run_chain(torch, frames_dev, MOTION_SEP, H, W, args.warmup, args.steps,
+                              per_kernel=False)
+        _, _, kt2 = run_chain(torch, frames_dev, MOTION_SEP, H, W, args.warmup, args.steps,
+                              per_kernel=True)
         variants["separable"] = {
             "value": round(W * H * args.steps / (g2 * 1e-3) / 1e6, 1), "unit": "Mpix/s",
             "ms_per_step": round(g2 / args.steps, 4),

@@ -131,10 +131,10 @@ typedef struct {
     sv_gbuf prev;            /* previous frame's z, normal, id */
     sv_rgb hist;             /* colour history (previous output) */
     const float *hist_m1;    /* luminance moment history E[L] */
-    const float *hist_m2;    /* luminance moment history E[L^2] */
+    const float *hist_m2c;   /* central moment history E[L^2] - E[L]^2 */
     const uint8_t *hist_n;   /* history length, 0 = none */
     sv_rgb out;              /* accumulated colour */
-    float *out_m1, *out_m2;  /* accumulated moments */
+    float *out_m1, *out_m2c; /* accumulated moments (m2c central) */
     uint8_t *out_n;          /* new history length */
     const float *alpha_map;  /* optional per-pixel colour alpha (NULL) */
 } sv_temporal_io;
@@ -150,7 +150,11 @@ typedef struct {
     int32_t flags;   /* SV_T_* */
 } sv_temporal_params;
 
-/* One temporal step, fused: (1) the current colour c, tone mapped if
+/* One temporal step, fused.  The luminance moments are the exponential
+ * moving averages of L and L^2 that the method accumulates; the second one
+ * is kept as the central moment m2c = E[L^2] - E[L]^2 (the same
+ * information, free of the cancellation E[L^2] - E[L]^2 suffers in
+ * binary32).  Steps: (1) the current colour c, tone mapped if
  * SV_T_TONEMAP_IN; (2) backward reprojection: with x0 = x + floor(mvx),
  * fx = mvx - floor(mvx) (likewise y) the four history pixels around
  * p + mv are bilinear taps; a tap is usable if it is inside the image, its
@@ -163,11 +167,13 @@ typedef struct {
  * reprojected colour is clamped to the 3x3 mean +- gamma sigma of c;
  * (4) with n = min(n_hist + 1, max_hist), a = max(alpha, 1/n),
  * am = max(alpha_m, 1/n): out = (1-a) hist + a c, m1 = (1-am) m1_hist +
- * am L(c), m2 = (1-am) m2_hist + am L(c)^2; a discarded history gives
- * out = c, m1 = L, m2 = L^2, n = 1.  alpha_map, if given, replaces alpha
+ * am L(c), m2c = (1-am) (m2c_hist + am (L(c) - m1_hist)^2), which is the
+ * central form of the EMA (1-am) E[L^2] + am L^2; the reprojected m2c is
+ * the bilinear mixture's central moment (taps' m2c plus the spread of
+ * their m1).  A discarded history gives out = c, m1 = L, m2c = 0, n = 1.  alpha_map, if given, replaces alpha
  * per pixel.  Outputs must not overlap any input (SV_EALIAS).  Required:
- * cur, g.z, g.n*, mvx, mvy, prev.z, prev.n*, hist, hist_m1, hist_m2,
- * hist_n, out, out_m1, out_m2, out_n; ids when SV_T_USE_ID. */
+ * cur, g.z, g.n*, mvx, mvy, prev.z, prev.n*, hist, hist_m1, hist_m2c,
+ * hist_n, out, out_m1, out_m2c, out_n; ids when SV_T_USE_ID. */
 int sv_temporal(const sv_temporal_io *io, sv_dims d, sv_dtype t,
                 const sv_temporal_params *p, sv_stream stream);
 
@@ -180,15 +186,17 @@ typedef struct {
     int32_t radius;   /* spatial window radius, 0..7, default 3 */
 } sv_variance_params;
 
-/* var = max(0, m2 - m1^2) where n >= min_hist.  Where 1 <= n < min_hist
- * the moments are averaged over the (2 radius + 1)^2 window (inside the
- * image, not empty) with weight 1 at the centre and
+/* var = max(0, m2c) where n >= min_hist (m2c = E[L^2] - E[L]^2 as
+ * sv_temporal writes it).  Where 1 <= n < min_hist the moments are averaged
+ * over the (2 radius + 1)^2 window (inside the image, not empty) with
+ * weight 1 at the centre and
  * exp(-|z(p)-z(q)| / (sigma_z |dzdx(p) dx + dzdy(p) dy| + eps_z))
- * * max(0, n(p).n(q))^sigma_n elsewhere, and var = weighted mean of
- * (m2 - m1^2) + weighted spread of m1 about its weighted mean (floored at
- * 0).  n == 0 or an empty pixel gives 0.  `var` must not overlap the
+ * * max(0, cos(n(p), n(q)))^sigma_n elsewhere (cosine of unit normals taken
+ * as 1 - |n(p) - n(q)|^2 / 2), and var = weighted mean of m2c + weighted
+ * spread of m1 about its weighted mean (floored at 0), the variance of the
+ * mixture.  n == 0 or an empty pixel gives 0.  `var` must not overlap the
  * inputs. */
-int sv_variance(const float *m1, const float *m2, const uint8_t *n,
+int sv_variance(const float *m1, const float *m2c, const uint8_t *n,
                 const sv_gbuf *g, float *var, sv_dims d, sv_dtype t,
                 const sv_variance_params *p, sv_stream stream);
 
@@ -214,7 +222,7 @@ typedef struct {
  * a, b in -2..2, inside the image and not empty, with the B3-spline weights
  * H = h(a) h(b), h = (1, 4, 6, 4, 1)/16, and edge weights (1 at q = p)
  *   w = exp(-|z(p)-z(q)| / (sigma_z |dzdx(p) step a + dzdy(p) step b| + eps_z))
- *     * max(0, n(p).n(q))^sigma_n
+ *     * max(0, 1 - |n(p) - n(q)|^2 / 2)^sigma_n
  *     * exp(-|L(c(p)) - L(c(q))| / (sigma_l kappa(p) sqrt(g(p)) + eps_l)),
  * the output is c' = sum H w c(q) / sum H w and
  * var' = sum (H w)^2 var_in(q) / (sum H w)^2.  kappa may be NULL (1);
@@ -239,6 +247,54 @@ int sv_atrous_sep(const sv_rgb *c_in, const float *var_in, const sv_gbuf *g,
                   const sv_rgb *c_out, float *var_out, int32_t step,
                   sv_dims d, sv_dtype t, const sv_atrous_params *p,
                   sv_stream stream);
+
+/* ---- one frame of the whole filter (Section 3, steps 4 and 5) --------- */
+
+/* Caller-owned buffers of one denoiser instance; every plane has the
+ * call's dims, colour planes the storage type.  The library keeps nothing:
+ * the history lives here between calls. */
+typedef struct {
+    sv_rgb hist[2];          /* colour history, double-buffered */
+    float *m1[2], *m2c[2];   /* moment history (m2c central), double-buffered */
+    uint8_t *n[2];           /* history length, double-buffered (0 = none) */
+    sv_rgb temporal;         /* temporal output (scratch) */
+    float *var;              /* variance estimate (scratch) */
+    sv_rgb level[2];         /* a-trous colour ping-pong (scratch) */
+    float *level_var[2];     /* a-trous variance ping-pong (scratch) */
+    sv_rgb scratch;          /* separable horizontal result (separable only) */
+    sv_rgb out;              /* final output of the frame */
+    int32_t cur;             /* 0 or 1: which history buffers are current;
+                                each call flips it */
+} sv_denoiser;
+
+typedef struct {
+    sv_rgb cur;              /* current 1-spp colour */
+    sv_gbuf g;               /* current G-buffer (all planes) */
+    const void *mvx, *mvy;   /* backward motion in pixels */
+    sv_gbuf prev;            /* previous frame's z, normal, id */
+    const float *alpha_map;  /* optional per-pixel colour alpha (NULL) */
+    const float *kappa;      /* optional per-pixel sigma_l scale (NULL) */
+} sv_frame_in;
+
+typedef struct {
+    sv_temporal_params temporal; /* SV_T_TONEMAP_IN also inverts at the end */
+    sv_variance_params variance;
+    sv_atrous_params atrous;     /* SV_A_INV_TONEMAP is set by the driver */
+    int32_t levels;              /* a-trous levels, steps 1, 2, 4, ...; 0..10 */
+    int32_t separable;           /* 1: sv_atrous_sep levels */
+    int32_t feedback;            /* colour history: 0 level-0 output,
+                                    1 temporal output */
+} sv_frame_params;
+
+/* Enqueues one frame: sv_temporal (history -> temporal), sv_variance,
+ * `levels` a-trous levels with steps 2^i (the inverse LUMA tone map fused
+ * into the last one when the temporal step tone maps), the colour history
+ * of the next frame being the level-0 output (feedback 0) or the temporal
+ * output (feedback 1); then flips st->cur.  The result is in st->out.
+ * Exactly the kernels of the individual calls, in the same order, so the
+ * output is bitwise that of calling them one by one. */
+int sv_denoise_frame(const sv_frame_in *in, sv_denoiser *st, sv_dims d,
+                     sv_dtype t, const sv_frame_params *p, sv_stream stream);
 
 /* ---- misc --------------------------------------------------------------- */
 

@@ -226,7 +226,9 @@ def temporal(frame: Dict[str, np.ndarray], state: Dict[str, np.ndarray],
         _ptr(o[0]), _ptr(o[1]), _ptr(o[2]), _ptr(o[3]), _ptr(o[4]), _ptr(on, _ip))
     if rc != 0:
         raise MemoryError("oracle temporal: allocation failed")
-    return {"rgb": o[:3], "m1": o[3], "m2": o[4], "n": on}
+    # m2c: the second central moment E[L^2] - E[L]^2 of the accumulated
+    # luminance (the form in which the device path stores it)
+    return {"rgb": o[:3], "m1": o[3], "m2": o[4], "m2c": o[4] - o[3] * o[3], "n": on}
 
 
 def variance(m1, m2, hist_n, z, dzdx, dzdy, n, sigma_z=1.0, sigma_n=128.0,

@@ -412,11 +412,15 @@ static double w_depth(double zp, double zq, double gx, double gy, double dx,
     return exp(-fabs(zp - zq) / (sigma_z * fabs(gx * dx + gy * dy) + eps_z));
 }
 
-/* Normal: a power of the clamped cosine between the two normals. */
+/* Normal: a power of the clamped cosine between the two unit normals,
+ * the cosine taken as 1 - |n(p) - n(q)|^2 / 2 (the same value for unit
+ * vectors; for G-buffer normals rounded to binary32 or binary16 it stays a
+ * function of the angle alone). */
 static double w_normal(double ax, double ay, double az, double bx, double by,
                        double bz, double sigma_n)
 {
-    double d = ax * bx + ay * by + az * bz;
+    double dx = ax - bx, dy = ay - by, dz = az - bz;
+    double d = 1.0 - 0.5 * (dx * dx + dy * dy + dz * dz);
     return pow(d > 0.0 ? d : 0.0, sigma_n);
 }
 

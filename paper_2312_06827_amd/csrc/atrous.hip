@@ -2,7 +2,8 @@
 // Fig. 1) in 5x5 form, and the separable form of Section 3.3.
 //
 // Every tap's weight H(a,b) * w_z * w_n * w_l is evaluated as one
-// exponential: log2 H - |dz| kz(a,b) - |dL| kl + sigma_n log2 max(0, n.n'),
+// exponential: log2 H - |dz| kz(a,b) - |dL| kl + sigma_n log2 max(0, cos)
+// (the normal term as in sv_internal.h),
 // with kz(a,b) = log2(e) / (sigma_z |grad z . step (a,b)| + eps_z) (12
 // distinct values per pixel, the offsets pairing up as +-(a,b)) and
 // kl = log2(e) / (sigma_l kappa sqrt(g) + eps_l).  A tap outside the image
@@ -21,10 +22,14 @@ struct AtrousArgs {
     void *or_, *og, *ob;
     float *var_out;
     int w, h, pitch, step;
-    float sigma_z, sigma_n, sigma_l, eps_z, eps_l, tm_k;
-    float dmin;  // 1 when sigma_n == 0 (normal weight off), else 0
+    float sigma_z, sigma_l, eps_z, eps_l, tm_k;
+    NormalCoef nc;
     int inv_tm;
 };
+
+// Weight modes: every edge weight 1 (plain B3), or the full weight with the
+// normal term off / as its series / through the logarithm.
+enum { kUnit = 3 };
 
 // log2 of the B3-spline taps (1, 4, 6, 4, 1) / 16
 __device__ constexpr float kLog2H1[5] = {-4.0f, -2.0f, -1.4150374992788438f, -2.0f, -4.0f};
@@ -33,30 +38,35 @@ constexpr float kG3[3] = {0.25f, 0.5f, 0.25f};
 
 // Index of the distinct depth denominator of offset (a, b): offsets +-(a,b)
 // share one; the canonical one has b > 0, or b == 0 and a > 0.
-__host__ __device__ constexpr int kz_index(int a, int b) {
-    return (b < 0 || (b == 0 && a < 0)) ? kz_index(-a, -b)
-                                        : (b == 0 ? a - 1 : 2 + (b - 1) * 5 + (a + 2));
+// (Not recursive, so that it folds to a constant once the tap loops unroll.)
+__host__ __device__ __forceinline__ constexpr int kz_index(int a, int b) {
+    const bool flip = b < 0 || (b == 0 && a < 0);
+    const int ca = flip ? -a : a, cb = flip ? -b : b;
+    return cb == 0 ? ca - 1 : 2 + (cb - 1) * 5 + (ca + 2);
 }
+static_assert(kz_index(1, 0) == 0 && kz_index(-2, 0) == 1 && kz_index(-2, 1) == 2 &&
+                  kz_index(2, -2) == 7 && kz_index(2, 2) == 11,
+              "depth denominator indexing");
 
 // 3x3 Gaussian of the variance around (x, y) over in-image, non-empty
-// pixels, renormalised.
+// pixels, renormalised.  All nine loads are issued before any test.
 template <typename T>
 __device__ __forceinline__ float prefilter_global(const AtrousArgs &a, int x, int y) {
+    float zq[9], vq[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const int qx = x + i % 3 - 1, qy = y + i / 3 - 1;
+        const bool in = qx >= 0 && qx < a.w && qy >= 0 && qy < a.h;
+        const size_t q = in ? (size_t)qy * a.pitch + qx : (size_t)y * a.pitch + x;
+        zq[i] = in ? ld((const T *)a.z + q) : 0.f;
+        vq[i] = a.var[q];
+    }
     float s = 0.f, sw = 0.f;
 #pragma unroll
-    for (int dy = -1; dy <= 1; ++dy) {
-        const int qy = y + dy;
-        if (qy < 0 || qy >= a.h) continue;
-#pragma unroll
-        for (int dx = -1; dx <= 1; ++dx) {
-            const int qx = x + dx;
-            if (qx < 0 || qx >= a.w) continue;
-            const size_t q = (size_t)qy * a.pitch + qx;
-            if (empty_px(ld((const T *)a.z + q))) continue;
-            const float k = kG3[dx + 1] * kG3[dy + 1];
-            s = fmaf(k, a.var[q], s);
-            sw += k;
-        }
+    for (int i = 0; i < 9; ++i) {
+        const float k = empty_px(zq[i]) ? 0.f : kG3[i % 3] * kG3[i / 3];
+        s = fmaf(k, vq[i], s);
+        sw += k;
     }
     return s / sw;
 }
@@ -71,18 +81,18 @@ struct Acc {
 };
 
 // One weighted tap (not the centre).  qc = (r, g, b, L), qg = (z, nx, ny, nz).
-template <bool UNIT, bool WANT_VAR>
+template <int MODE, bool WANT_VAR>
 __device__ __forceinline__ void tap(Acc &acc, float4 qc, float4 qg, float qv, float log2h,
                                     float hconst, float kz, float zp, float lp, float nxp,
-                                    float nyp, float nzp, float kl, float sn, float dmin) {
+                                    float nyp, float nzp, float kl, const NormalCoef &nc) {
     float hw;
-    if (UNIT) {
+    if (MODE == kUnit) {
         hw = qg.x > 0.f ? hconst : 0.f;
     } else {
         float t = fmaf(-fabsf(zp - qg.x), kz, log2h);
         t = fmaf(-fabsf(lp - qc.w), kl, t);
-        const float d = fmaf(nzp, qg.w, fmaf(nyp, qg.z, nxp * qg.y));
-        t = fmaf(sn, fast_log2(fmaxf(d, dmin)), t);
+        if (MODE != kNormalOff)
+            t = add_normal_term<MODE>(t, chord2(nxp, nyp, nzp, qg.y, qg.z, qg.w), nc);
         hw = fast_exp2(t);
     }
     acc.sw += hw;
@@ -115,13 +125,18 @@ __device__ __forceinline__ void pass_through(const AtrousArgs &a, size_t o, cons
 // * STEP * TY + phase.  All 25 taps of those pixels then lie in the tile's
 // own lattice rows j - 2 .. j + TY + 1 and columns -2 STEP .. TX + 2 STEP,
 // so the LDS footprint is (TY + 4) x (TX + 4 STEP) pixels whatever the step.
-template <typename T, int STEP, int PY, bool UNIT, bool WANT_VAR>
+template <typename T, int STEP, int PY, int MODE, bool WANT_VAR>
 __global__ __launch_bounds__(256) void atrous_tile_k(AtrousArgs a) {
     constexpr int TX = 64, TY = 4 * PY, ROWS = TY + 4, COLS = TX + 4 * STEP;
-    constexpr bool NEED_V = WANT_VAR || STEP == 1;
+    // The 3x3 variance prefilter needs image rows y-1, y, y+1: inside the
+    // tile for STEP 1, three extra staged rows per lattice row otherwise.
+    constexpr bool PF_TILE = STEP == 1;
+    constexpr bool NEED_V = WANT_VAR || PF_TILE;
+    constexpr int PFC = TX + 2;
     __shared__ float4 s_cl[ROWS * COLS];  // r, g, b, L (L = +inf: no tap)
     __shared__ float4 s_gn[ROWS * COLS];  // z, nx, ny, nz (z = 0: no tap)
     __shared__ float s_v[NEED_V ? ROWS * COLS : 1];
+    __shared__ float2 s_pf[PF_TILE ? 1 : TY * 3 * PFC];  // (var, 1) or (0, 0)
     const int tid = threadIdx.x;
     const int x0 = blockIdx.x * TX;
     const int band = blockIdx.y / STEP, phase = blockIdx.y - band * STEP;
@@ -149,12 +164,24 @@ __global__ __launch_bounds__(256) void atrous_tile_k(AtrousArgs a) {
         s_gn[i] = gn;
         if (NEED_V) s_v[i] = v;
     }
+    if (!PF_TILE) {
+        for (int i = tid; i < TY * 3 * PFC; i += 256) {
+            const int j = i / (3 * PFC), rem = i - j * (3 * PFC);
+            const int r3 = rem / PFC, c = rem - r3 * PFC;
+            const int gx = x0 - 1 + c, gy = ybase + j * STEP + r3 - 1;
+            float2 e = make_float2(0.f, 0.f);
+            if (gx >= 0 && gx < a.w && gy >= 0 && gy < a.h) {
+                const size_t o = (size_t)gy * a.pitch + gx;
+                if (!empty_px(ld((const T *)a.z + o))) e = make_float2(a.var[o], 1.f);
+            }
+            s_pf[i] = e;
+        }
+    }
     __syncthreads();
 
     const int lx = tid & 63, ly = tid >> 6;
     const int x = x0 + lx;
     if (x >= a.w) return;
-    const float sn = a.sigma_n, dmin = a.dmin;
 #pragma unroll 1
     for (int k = 0; k < PY; ++k) {
         const int j = ly + 4 * k;
@@ -183,11 +210,21 @@ __global__ __launch_bounds__(256) void atrous_tile_k(AtrousArgs a) {
                 }
             g = s / sw;
         } else {
-            g = prefilter_global<T>(a, x, y);
+            float s = 0.f, sw = 0.f;
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx) {
+                    const float2 e = s_pf[(j * 3 + dy) * PFC + lx + dx];
+                    const float kk = e.y * (kG3[dx] * kG3[dy]);
+                    s = fmaf(kk, e.x, s);
+                    sw += kk;
+                }
+            g = s / sw;
         }
         float kz[12];
         float kl = 0.f;
-        if (!UNIT) {
+        if (MODE != kUnit) {
             kl = luma_scale(a, g, o);
             const float gx = ld((const T *)a.dzdx + o) * (float)STEP;
             const float gy = ld((const T *)a.dzdy + o) * (float)STEP;
@@ -215,9 +252,9 @@ __global__ __launch_bounds__(256) void atrous_tile_k(AtrousArgs a) {
                 if (aa == 0 && b == 0) continue;
                 const int qi = ci + b * COLS + aa * STEP;
                 const float qv = WANT_VAR ? s_v[qi] : 0.f;
-                tap<UNIT, WANT_VAR>(acc, s_cl[qi], s_gn[qi], qv, kLog2H1[aa + 2] + kLog2H1[b + 2],
-                                    kH1[aa + 2] * kH1[b + 2], UNIT ? 0.f : kz[kz_index(aa, b)],
-                                    pg.x, pc.w, pg.y, pg.z, pg.w, kl, sn, dmin);
+                tap<MODE, WANT_VAR>(acc, s_cl[qi], s_gn[qi], qv, kLog2H1[aa + 2] + kLog2H1[b + 2],
+                                    kH1[aa + 2] * kH1[b + 2], MODE == kUnit ? 0.f : kz[kz_index(aa, b)],
+                                    pg.x, pc.w, pg.y, pg.z, pg.w, kl, a.nc);
             }
         const float inv = 1.0f / acc.sw;
         write_out<T>(a, o, acc.sr * inv, acc.sg * inv, acc.sb * inv);
@@ -243,7 +280,7 @@ __device__ __forceinline__ void load_tap(const AtrousArgs &a, int qx, int qy, fl
     qv = a.var[q];
 }
 
-template <typename T, bool UNIT, bool WANT_VAR>
+template <typename T, int MODE, bool WANT_VAR>
 __global__ __launch_bounds__(256) void atrous_direct_k(AtrousArgs a) {
     const int x = blockIdx.x * 64 + (threadIdx.x & 63);
     const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
@@ -260,7 +297,7 @@ __global__ __launch_bounds__(256) void atrous_direct_k(AtrousArgs a) {
     const float s = (float)a.step;
     float kz[12];
     float kl = 0.f;
-    if (!UNIT) {
+    if (MODE != kUnit) {
         kl = luma_scale(a, g, o);
         const float gx = ld((const T *)a.dzdx + o) * s, gy = ld((const T *)a.dzdy + o) * s;
 #pragma unroll
@@ -282,9 +319,9 @@ __global__ __launch_bounds__(256) void atrous_direct_k(AtrousArgs a) {
             float4 qc, qg;
             float qv;
             load_tap<T>(a, x + aa * a.step, y + b * a.step, qc, qg, qv);
-            tap<UNIT, WANT_VAR>(acc, qc, qg, qv, kLog2H1[aa + 2] + kLog2H1[b + 2],
-                                kH1[aa + 2] * kH1[b + 2], UNIT ? 0.f : kz[kz_index(aa, b)], pg.x,
-                                pc.w, pg.y, pg.z, pg.w, kl, a.sigma_n, a.dmin);
+            tap<MODE, WANT_VAR>(acc, qc, qg, qv, kLog2H1[aa + 2] + kLog2H1[b + 2],
+                                kH1[aa + 2] * kH1[b + 2], MODE == kUnit ? 0.f : kz[kz_index(aa, b)], pg.x,
+                                pc.w, pg.y, pg.z, pg.w, kl, a.nc);
         }
     const float inv = 1.0f / acc.sw;
     write_out<T>(a, o, acc.sr * inv, acc.sg * inv, acc.sb * inv);
@@ -297,7 +334,7 @@ __global__ __launch_bounds__(256) void atrous_direct_k(AtrousArgs a) {
 // planes).  Vertical pass: reads the scratch planes as colour (cr/cg/cb) and
 // var_in for the propagation; g comes from var_in in both.
 
-template <typename T, bool UNIT, bool VERTICAL, bool WANT_VAR>
+template <typename T, int MODE, bool VERTICAL, bool WANT_VAR>
 __global__ __launch_bounds__(256) void atrous_sep_k(AtrousArgs a) {
     const int x = blockIdx.x * 64 + (threadIdx.x & 63);
     const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
@@ -320,7 +357,7 @@ __global__ __launch_bounds__(256) void atrous_sep_k(AtrousArgs a) {
     const float s = (float)a.step;
     float kz[2] = {0.f, 0.f};
     float kl = 0.f;
-    if (!UNIT) {
+    if (MODE != kUnit) {
         kl = luma_scale(a, g, o);
         const float grad = ld((const T *)(VERTICAL ? a.dzdy : a.dzdx) + o) * s;
 #pragma unroll
@@ -338,9 +375,9 @@ __global__ __launch_bounds__(256) void atrous_sep_k(AtrousArgs a) {
         float qv;
         const int qx = VERTICAL ? x : x + t * a.step, qy = VERTICAL ? y + t * a.step : y;
         load_tap<T>(a, qx, qy, qc, qg, qv);
-        tap<UNIT, WANT_VAR>(acc, qc, qg, qv, kLog2H1[t + 2], kH1[t + 2],
-                            UNIT ? 0.f : kz[(t < 0 ? -t : t) - 1], pg.x, pc.w, pg.y, pg.z, pg.w,
-                            kl, a.sigma_n, a.dmin);
+        tap<MODE, WANT_VAR>(acc, qc, qg, qv, kLog2H1[t + 2], kH1[t + 2],
+                            MODE == kUnit ? 0.f : kz[(t < 0 ? -t : t) - 1], pg.x, pc.w, pg.y, pg.z, pg.w,
+                            kl, a.nc);
     }
     const float inv = 1.0f / acc.sw;
     if (VERTICAL) {
@@ -355,52 +392,66 @@ __global__ __launch_bounds__(256) void atrous_sep_k(AtrousArgs a) {
 
 // ---- launch ---------------------------------------------------------------------
 
-template <typename T, int STEP, bool UNIT, bool WANT_VAR>
+template <typename T, int STEP, int MODE, bool WANT_VAR>
 static void launch_tile(const AtrousArgs &a, hipStream_t s) {
     constexpr int PY = 2, TY = 4 * PY;
     const int bands = (a.h + STEP * TY - 1) / (STEP * TY);
     dim3 grid((a.w + 63) / 64, bands * STEP);
-    hipLaunchKernelGGL((atrous_tile_k<T, STEP, PY, UNIT, WANT_VAR>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((atrous_tile_k<T, STEP, PY, MODE, WANT_VAR>), grid, dim3(256), 0, s, a);
 }
 
-template <typename T, bool UNIT, bool WANT_VAR>
+template <typename T, int MODE, bool WANT_VAR>
 static void launch_2d(const AtrousArgs &a, hipStream_t s) {
     switch (a.step) {
-    case 1: launch_tile<T, 1, UNIT, WANT_VAR>(a, s); return;
-    case 2: launch_tile<T, 2, UNIT, WANT_VAR>(a, s); return;
-    case 4: launch_tile<T, 4, UNIT, WANT_VAR>(a, s); return;
-    case 8: launch_tile<T, 8, UNIT, WANT_VAR>(a, s); return;
-    case 16: launch_tile<T, 16, UNIT, WANT_VAR>(a, s); return;
+    case 1: launch_tile<T, 1, MODE, WANT_VAR>(a, s); return;
+    case 2: launch_tile<T, 2, MODE, WANT_VAR>(a, s); return;
+    case 4: launch_tile<T, 4, MODE, WANT_VAR>(a, s); return;
+    case 8: launch_tile<T, 8, MODE, WANT_VAR>(a, s); return;
+    case 16: launch_tile<T, 16, MODE, WANT_VAR>(a, s); return;
     default: {
         dim3 grid((a.w + 63) / 64, (a.h + 3) / 4);
-        hipLaunchKernelGGL((atrous_direct_k<T, UNIT, WANT_VAR>), grid, dim3(256), 0, s, a);
+        hipLaunchKernelGGL((atrous_direct_k<T, MODE, WANT_VAR>), grid, dim3(256), 0, s, a);
     }
     }
+}
+
+template <typename T, int MODE>
+static void launch_2d_var(const AtrousArgs &a, hipStream_t s) {
+    if (a.var_out) launch_2d<T, MODE, true>(a, s);
+    else launch_2d<T, MODE, false>(a, s);
 }
 
 template <typename T>
-static void dispatch_2d(const AtrousArgs &a, bool unit, hipStream_t s) {
-    const bool wv = a.var_out != nullptr;
-    if (unit) {
-        if (wv) launch_2d<T, true, true>(a, s);
-        else launch_2d<T, true, false>(a, s);
-    } else {
-        if (wv) launch_2d<T, false, true>(a, s);
-        else launch_2d<T, false, false>(a, s);
+static void dispatch_2d(const AtrousArgs &a, int mode, hipStream_t s) {
+    switch (mode) {
+    case kUnit: launch_2d_var<T, kUnit>(a, s); return;
+    case kNormalOff: launch_2d_var<T, kNormalOff>(a, s); return;
+    case kNormalPoly: launch_2d_var<T, kNormalPoly>(a, s); return;
+    default: launch_2d_var<T, kNormalLog>(a, s); return;
     }
 }
 
-template <typename T, bool VERTICAL>
-static void dispatch_sep(const AtrousArgs &a, bool unit, hipStream_t s) {
+template <typename T, int MODE, bool VERTICAL>
+static void launch_sep(const AtrousArgs &a, hipStream_t s) {
     dim3 grid((a.w + 63) / 64, (a.h + 3) / 4);
-    const bool wv = VERTICAL && a.var_out != nullptr;
-    if (unit) {
-        if (wv) hipLaunchKernelGGL((atrous_sep_k<T, true, VERTICAL, true>), grid, dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((atrous_sep_k<T, true, VERTICAL, false>), grid, dim3(256), 0, s, a);
-    } else {
-        if (wv) hipLaunchKernelGGL((atrous_sep_k<T, false, VERTICAL, true>), grid, dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((atrous_sep_k<T, false, VERTICAL, false>), grid, dim3(256), 0, s, a);
+    if (VERTICAL && a.var_out)
+        hipLaunchKernelGGL((atrous_sep_k<T, MODE, VERTICAL, true>), grid, dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((atrous_sep_k<T, MODE, VERTICAL, false>), grid, dim3(256), 0, s, a);
+}
+
+template <typename T, bool VERTICAL>
+static void dispatch_sep(const AtrousArgs &a, int mode, hipStream_t s) {
+    switch (mode) {
+    case kUnit: launch_sep<T, kUnit, VERTICAL>(a, s); return;
+    case kNormalOff: launch_sep<T, kNormalOff, VERTICAL>(a, s); return;
+    case kNormalPoly: launch_sep<T, kNormalPoly, VERTICAL>(a, s); return;
+    default: launch_sep<T, kNormalLog, VERTICAL>(a, s); return;
     }
+}
+
+static int weight_mode(const sv_atrous_params *p) {
+    return (p->flags & SV_A_UNIT_WEIGHTS) ? kUnit : normal_mode(p->sigma_n);
 }
 
 static int check_atrous(const sv_rgb *c_in, const float *var_in, const sv_gbuf *g,
@@ -448,8 +499,8 @@ static AtrousArgs make_args(const sv_rgb *c_in, const float *var_in, const sv_gb
                             int32_t step, sv_dims d, const sv_atrous_params *p) {
     return AtrousArgs{c_in->r, c_in->g, c_in->b, var_in, g->z, g->dzdx, g->dzdy, g->nx, g->ny,
                       g->nz, kappa, c_out->r, c_out->g, c_out->b, var_out, d.w, d.h, d.pitch,
-                      step, p->sigma_z, p->sigma_n, p->sigma_l, p->eps_z, p->eps_l, p->tm_k,
-                      p->sigma_n == 0.f ? 1.f : 0.f, (p->flags & SV_A_INV_TONEMAP) ? 1 : 0};
+                      step, p->sigma_z, p->sigma_l, p->eps_z, p->eps_l, p->tm_k,
+                      make_normal_coef(p->sigma_n), (p->flags & SV_A_INV_TONEMAP) ? 1 : 0};
 }
 
 }  // namespace sv
@@ -462,9 +513,9 @@ extern "C" int sv_atrous(const sv_rgb *c_in, const float *var_in, const sv_gbuf 
     int rc = check_atrous(c_in, var_in, g, kappa, nullptr, c_out, var_out, step, d, t, p, &empty);
     if (rc != SV_OK || empty) return rc;
     AtrousArgs a = make_args(c_in, var_in, g, kappa, c_out, var_out, step, d, p);
-    const bool unit = (p->flags & SV_A_UNIT_WEIGHTS) != 0;
-    if (t == SV_F32) dispatch_2d<float>(a, unit, as_stream(stream));
-    else dispatch_2d<half_t>(a, unit, as_stream(stream));
+    const int mode = weight_mode(p);
+    if (t == SV_F32) dispatch_2d<float>(a, mode, as_stream(stream));
+    else dispatch_2d<half_t>(a, mode, as_stream(stream));
     return hip_status(hipGetLastError());
 }
 
@@ -478,7 +529,7 @@ extern "C" int sv_atrous_sep(const sv_rgb *c_in, const float *var_in, const sv_g
     int rc = check_atrous(c_in, var_in, g, kappa, scratch, c_out, var_out, step, d, t, p, &empty);
     if (rc != SV_OK || empty) return rc;
     if (!scratch->r || !scratch->g || !scratch->b) return SV_EINVAL;
-    const bool unit = (p->flags & SV_A_UNIT_WEIGHTS) != 0;
+    const int mode = weight_mode(p);
     hipStream_t s = as_stream(stream);
     // horizontal: c_in -> scratch (no variance, no inverse tone map)
     AtrousArgs h = make_args(c_in, var_in, g, kappa, scratch, nullptr, step, d, p);
@@ -486,11 +537,11 @@ extern "C" int sv_atrous_sep(const sv_rgb *c_in, const float *var_in, const sv_g
     // vertical: scratch -> c_out, variance from var_in
     AtrousArgs v = make_args(scratch, var_in, g, kappa, c_out, var_out, step, d, p);
     if (t == SV_F32) {
-        dispatch_sep<float, false>(h, unit, s);
-        dispatch_sep<float, true>(v, unit, s);
+        dispatch_sep<float, false>(h, mode, s);
+        dispatch_sep<float, true>(v, mode, s);
     } else {
-        dispatch_sep<half_t, false>(h, unit, s);
-        dispatch_sep<half_t, true>(v, unit, s);
+        dispatch_sep<half_t, false>(h, mode, s);
+        dispatch_sep<half_t, true>(v, mode, s);
     }
     return hip_status(hipGetLastError());
 }

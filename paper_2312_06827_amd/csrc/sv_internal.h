@@ -40,6 +40,58 @@ __device__ __forceinline__ float fast_log2(float x) { return __builtin_amdgcn_lo
 
 constexpr float kLog2e = 1.4426950408889634f;
 
+// ---- normal edge weight ----------------------------------------------------
+//
+// The weight is max(0, cos)^sigma_n with the cosine of two unit normals
+// taken as 1 - s2/2, s2 = |n(p) - n(q)|^2.  Its base-2 logarithm
+// sigma_n log2(1 - s2/2) is added to a tap's exponent.  For sigma_n >= 64
+// the logarithm is its series -(t + t^2/2 + t^3/3 + t^4/4), t = s2/2: the
+// weights that matter have t small, where the first omitted term
+// sigma_n t^5/5 times the weight exp(-sigma_n t) stays below
+// e^-5 5^4 / sigma_n^4 (2.5e-7 at sigma_n = 64, 1.6e-8 at 128), and it
+// avoids rounding 1 - s2/2 near 1, which sigma_n would amplify.  Below 64 the
+// logarithm of the rounded u = 1 - s2/2 is corrected by the rounding error
+// of u.
+enum { kNormalOff = 0, kNormalPoly = 1, kNormalLog = 2 };
+
+struct NormalCoef {
+    float c1, c2, c3, c4;  // sigma_n log2(e) times the series coefficients in s2
+    float sn;              // sigma_n
+    float snl;             // sigma_n log2(e)
+};
+
+inline NormalCoef make_normal_coef(float sigma_n) {
+    const float k = sigma_n * 1.4426950408889634f;
+    // -(t + t^2/2 + t^3/3 + t^4/4) with t = s2/2
+    return NormalCoef{-k / 2.0f, -k / 8.0f, -k / 24.0f, -k / 64.0f, sigma_n, k};
+}
+
+inline int normal_mode(float sigma_n) {
+    return sigma_n == 0.0f ? kNormalOff : (sigma_n >= 64.0f ? kNormalPoly : kNormalLog);
+}
+
+template <int NM>
+__device__ __forceinline__ float add_normal_term(float e, float s2, const NormalCoef &k) {
+    if (NM == kNormalPoly) {
+        float p = fmaf(s2, k.c4, k.c3);
+        p = fmaf(s2, p, k.c2);
+        p = fmaf(s2, p, k.c1);
+        return fmaf(s2, p, e);
+    } else if (NM == kNormalLog) {
+        const float u = fmaf(-0.5f, s2, 1.0f);
+        const float r = fmaf(-0.5f, s2, 1.0f - u);  // (1 - s2/2) - u, exact
+        e = fmaf(k.sn, __builtin_amdgcn_logf(fmaxf(u, 0.0f)), e);
+        return fmaf(k.snl, r, e);
+    }
+    return e;
+}
+
+__device__ __forceinline__ float chord2(float ax, float ay, float az, float bx, float by,
+                                        float bz) {
+    const float dx = ax - bx, dy = ay - by, dz = az - bz;
+    return fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+}
+
 // Exact inverse of the LUMA tone map, denominator floored at 2^-20.
 __device__ __forceinline__ void inv_tonemap(float &r, float &g, float &b, float k) {
     float L = luma(r, g, b);

@@ -17,10 +17,10 @@ struct TemporalArgs {
     const void *pz, *pnx, *pny, *pnz;
     const uint8_t *pid;
     const void *hr, *hg, *hb;
-    const float *hm1, *hm2;
+    const float *hm1, *hm2c;  // E[L], E[L^2] - E[L]^2
     const uint8_t *hn;
     void *or_, *og, *ob;
-    float *om1, *om2;
+    float *om1, *om2c;
     uint8_t *on;
     const float *alpha_map;
     int w, h, pitch;
@@ -43,35 +43,42 @@ __device__ __forceinline__ bool normal_consistent(float ax, float ay, float az, 
     return d >= tau;
 }
 
-// 3x3 box of the tile around (lx+1, ly+1): mean and population sigma per
-// channel (two-pass) over valid entries (w component 1).
-__device__ __forceinline__ void box_stats(const float4 *tile, int lx, int ly, float3 &mu,
-                                          float3 &sd) {
-    float sr = 0.f, sg = 0.f, sb = 0.f, cnt = 0.f;
+// 3x3 box of the tile around (lx+1, ly+1): clamp bounds mu -+ gamma sigma
+// per channel from the mean and population sigma (two-pass) over valid
+// entries (w component 1).  Binary64: the bounds are differences of
+// quantities of the colour's size and may be close to zero.
+__device__ __forceinline__ void box_bounds(const float4 *tile, int lx, int ly, float gamma,
+                                           float3 &lo, float3 &hi) {
+    double sr = 0.0, sg = 0.0, sb = 0.0, cnt = 0.0;
 #pragma unroll
     for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
         for (int dx = 0; dx < 3; ++dx) {
-            float4 q = tile[(ly + dy) * (kTX + 2) + lx + dx];
-            sr += q.w * q.x;
-            sg += q.w * q.y;
-            sb += q.w * q.z;
-            cnt += q.w;
+            const float4 q = tile[(ly + dy) * (kTX + 2) + lx + dx];
+            const double w = q.w;
+            sr = fma(w, (double)q.x, sr);
+            sg = fma(w, (double)q.y, sg);
+            sb = fma(w, (double)q.z, sb);
+            cnt += w;
         }
-    float inv = 1.0f / cnt;
-    mu = make_float3(sr * inv, sg * inv, sb * inv);
-    float vr = 0.f, vg = 0.f, vb = 0.f;
+    const double inv = 1.0 / cnt;
+    const double mr = sr * inv, mg = sg * inv, mb = sb * inv;
+    double vr = 0.0, vg = 0.0, vb = 0.0;
 #pragma unroll
     for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
         for (int dx = 0; dx < 3; ++dx) {
-            float4 q = tile[(ly + dy) * (kTX + 2) + lx + dx];
-            float er = q.x - mu.x, eg = q.y - mu.y, eb = q.z - mu.z;
-            vr = fmaf(q.w * er, er, vr);
-            vg = fmaf(q.w * eg, eg, vg);
-            vb = fmaf(q.w * eb, eb, vb);
+            const float4 q = tile[(ly + dy) * (kTX + 2) + lx + dx];
+            const double w = q.w;
+            const double er = q.x - mr, eg = q.y - mg, eb = q.z - mb;
+            vr = fma(w * er, er, vr);
+            vg = fma(w * eg, eg, vg);
+            vb = fma(w * eb, eb, vb);
         }
-    sd = make_float3(sqrtf(vr * inv), sqrtf(vg * inv), sqrtf(vb * inv));
+    const double gr = gamma * sqrt(vr * inv), gg = gamma * sqrt(vg * inv),
+                 gb = gamma * sqrt(vb * inv);
+    lo = make_float3((float)(mr - gr), (float)(mg - gg), (float)(mb - gb));
+    hi = make_float3((float)(mr + gr), (float)(mg + gg), (float)(mb + gb));
 }
 
 // Stage the current colour (tone mapped if TM) of the tile and a one-pixel
@@ -118,7 +125,7 @@ __global__ __launch_bounds__(256) void temporal_k(TemporalArgs a) {
         st((T *)a.og + o, c.y);
         st((T *)a.ob + o, c.z);
         a.om1[o] = 0.f;
-        a.om2[o] = 0.f;
+        a.om2c[o] = 0.f;
         a.on[o] = 0;
         return;
     }
@@ -128,55 +135,80 @@ __global__ __launch_bounds__(256) void temporal_k(TemporalArgs a) {
     const uint8_t idc = USE_ID ? a.id[o] : 0;
 
     // ---- backward reprojection: bilinear taps around p + mv ----
-    float sw = 0.f, ar = 0.f, ag = 0.f, ab = 0.f, a1 = 0.f, a2 = 0.f;
-    int nmax = 0;
-    bool any = false;
-    if (fabsf(mvx) < 1048576.0f && fabsf(mvy) < 1048576.0f) {
-        const float fx0 = floorf(mvx), fy0 = floorf(mvy);
-        const float fx = mvx - fx0, fy = mvy - fy0;  // exact in binary32
-        const int x0 = x + (int)fx0, y0 = y + (int)fy0;
+    // Every load of the four taps is issued before any test, so the taps'
+    // memory latencies overlap instead of chaining through the tests.
+    float bw[4], tz[4], tnx[4], tny[4], tnz[4], tr[4], tg[4], tb[4], t1[4], t2[4];
+    int thn[4], tid_[4];
+    bool inb[4];
+    const bool mv_ok = fabsf(mvx) < 1048576.0f && fabsf(mvy) < 1048576.0f;
+    const float fx0 = mv_ok ? floorf(mvx) : 0.f, fy0 = mv_ok ? floorf(mvy) : 0.f;
+    const float fx = mvx - fx0, fy = mvy - fy0;  // exact in binary32
+    const int x0 = x + (int)fx0, y0 = y + (int)fy0;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int tx = x0 + (t & 1), ty = y0 + (t >> 1);
-            const float bw = ((t & 1) ? fx : 1.0f - fx) * ((t >> 1) ? fy : 1.0f - fy);
-            if (!(bw > 0.f) || tx < 0 || tx >= a.w || ty < 0 || ty >= a.h) continue;
-            const size_t q = (size_t)ty * a.pitch + tx;
-            const int hn = a.hn[q];
-            if (hn < 1) continue;
-            if (!depth_consistent(ld((const T *)a.pz + q), zc, a.tau_z)) continue;
-            if (!normal_consistent(ld((const T *)a.pnx + q), ld((const T *)a.pny + q),
-                                   ld((const T *)a.pnz + q), nxc, nyc, nzc, a.tau_n))
-                continue;
-            if (USE_ID && a.pid[q] != idc) continue;
-            any = true;
-            sw += bw;
-            ar = fmaf(bw, ld((const T *)a.hr + q), ar);
-            ag = fmaf(bw, ld((const T *)a.hg + q), ag);
-            ab = fmaf(bw, ld((const T *)a.hb + q), ab);
-            a1 = fmaf(bw, a.hm1[q], a1);
-            a2 = fmaf(bw, a.hm2[q], a2);
-            nmax = max(nmax, hn);
-        }
+    for (int t = 0; t < 4; ++t) {
+        const int tx = x0 + (t & 1), ty = y0 + (t >> 1);
+        bw[t] = ((t & 1) ? fx : 1.0f - fx) * ((t >> 1) ? fy : 1.0f - fy);
+        inb[t] = mv_ok && bw[t] > 0.f && tx >= 0 && tx < a.w && ty >= 0 && ty < a.h;
+        const size_t q = inb[t] ? (size_t)ty * a.pitch + tx : o;
+        thn[t] = a.hn[q];
+        tz[t] = ld((const T *)a.pz + q);
+        tnx[t] = ld((const T *)a.pnx + q);
+        tny[t] = ld((const T *)a.pny + q);
+        tnz[t] = ld((const T *)a.pnz + q);
+        tid_[t] = USE_ID ? a.pid[q] : 0;
+        tr[t] = ld((const T *)a.hr + q);
+        tg[t] = ld((const T *)a.hg + q);
+        tb[t] = ld((const T *)a.hb + q);
+        t1[t] = a.hm1[q];
+        t2[t] = a.hm2c[q];
     }
-    float outr, outg, outb, m1, m2;
+    float sw = 0.f, ar = 0.f, ag = 0.f, ab = 0.f, a1 = 0.f;
+    int nmax = 0;
+    bool ok[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        ok[t] = inb[t] && thn[t] >= 1 && depth_consistent(tz[t], zc, a.tau_z) &&
+                normal_consistent(tnx[t], tny[t], tnz[t], nxc, nyc, nzc, a.tau_n) &&
+                (!USE_ID || tid_[t] == idc);
+        // selects, not zero weights: an unusable tap's history may hold
+        // anything (even NaN) and must not reach the sums
+        sw = ok[t] ? sw + bw[t] : sw;
+        ar = ok[t] ? fmaf(bw[t], tr[t], ar) : ar;
+        ag = ok[t] ? fmaf(bw[t], tg[t], ag) : ag;
+        ab = ok[t] ? fmaf(bw[t], tb[t], ab) : ab;
+        a1 = ok[t] ? fmaf(bw[t], t1[t], a1) : a1;
+        nmax = ok[t] ? max(nmax, thn[t]) : nmax;
+    }
+    const bool any = ok[0] || ok[1] || ok[2] || ok[3];
+    float outr, outg, outb, m1, m2c;
     int n;
     if (!any) {
         outr = c.x;
         outg = c.y;
         outb = c.z;
         m1 = L;
-        m2 = L * L;
+        m2c = 0.f;
         n = 1;
     } else {
-        float hr = ar / sw, hg = ag / sw, hb = ab / sw;
-        const float hm1 = a1 / sw, hm2 = a2 / sw;
+        const float inv = 1.0f / sw;
+        float hr = ar * inv, hg = ag * inv, hb = ab * inv;
+        const float hm1 = a1 * inv;
+        // second central moment of the bilinear mixture: mean of the taps'
+        // central moments plus the spread of their means (no cancellation)
+        float s2 = 0.f;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const float d = t1[t] - hm1;
+            s2 = ok[t] ? fmaf(bw[t], fmaf(d, d, t2[t]), s2) : s2;
+        }
+        const float hm2c = s2 * inv;
         // ---- history rectification: variance colour clamp ----
         if (CLAMP) {
-            float3 mu, sd;
-            box_stats(tile, lx, ly, mu, sd);
-            hr = fminf(fmaxf(hr, mu.x - a.gamma * sd.x), mu.x + a.gamma * sd.x);
-            hg = fminf(fmaxf(hg, mu.y - a.gamma * sd.y), mu.y + a.gamma * sd.y);
-            hb = fminf(fmaxf(hb, mu.z - a.gamma * sd.z), mu.z + a.gamma * sd.z);
+            float3 lo, hi;
+            box_bounds(tile, lx, ly, a.gamma, lo, hi);
+            hr = fminf(fmaxf(hr, lo.x), hi.x);
+            hg = fminf(fmaxf(hg, lo.y), hi.y);
+            hb = fminf(fmaxf(hb, lo.z), hi.z);
         }
         // ---- accumulation ----
         n = min(nmax + 1, a.max_hist);
@@ -186,14 +218,17 @@ __global__ __launch_bounds__(256) void temporal_k(TemporalArgs a) {
         outr = fmaf(ac, c.x - hr, hr);
         outg = fmaf(ac, c.y - hg, hg);
         outb = fmaf(ac, c.z - hb, hb);
-        m1 = fmaf(am, L - hm1, hm1);
-        m2 = fmaf(am, fmaf(L, L, -hm2), hm2);
+        const float dl = L - hm1;
+        m1 = fmaf(am, dl, hm1);
+        // EMA of the raw moments written for the central one:
+        // (1 - am) (m2c + am (L - m1)^2)
+        m2c = (1.0f - am) * fmaf(am * dl, dl, hm2c);
     }
     st((T *)a.or_ + o, outr);
     st((T *)a.og + o, outg);
     st((T *)a.ob + o, outb);
     a.om1[o] = m1;
-    a.om2[o] = m2;
+    a.om2c[o] = m2c;
     a.on[o] = (uint8_t)n;
 }
 
@@ -216,11 +251,11 @@ __global__ __launch_bounds__(256) void clamp_k(ClampArgs a) {
     float r = ld((const T *)a.hr + o), g = ld((const T *)a.hg + o), b = ld((const T *)a.hb + o);
     const bool active = a.gamma > 0.f && tile[(ly + 1) * (kTX + 2) + lx + 1].w > 0.f;
     if (active) {
-        float3 mu, sd;
-        box_stats(tile, lx, ly, mu, sd);
-        r = fminf(fmaxf(r, mu.x - a.gamma * sd.x), mu.x + a.gamma * sd.x);
-        g = fminf(fmaxf(g, mu.y - a.gamma * sd.y), mu.y + a.gamma * sd.y);
-        b = fminf(fmaxf(b, mu.z - a.gamma * sd.z), mu.z + a.gamma * sd.z);
+        float3 lo, hi;
+        box_bounds(tile, lx, ly, a.gamma, lo, hi);
+        r = fminf(fmaxf(r, lo.x), hi.x);
+        g = fminf(fmaxf(g, lo.y), hi.y);
+        b = fminf(fmaxf(b, lo.z), hi.z);
     }
     st((T *)a.or_ + o, r);
     st((T *)a.og + o, g);
@@ -262,9 +297,9 @@ extern "C" int sv_temporal(const sv_temporal_io *io, sv_dims d, sv_dtype t,
     const bool tm = (p->flags & SV_T_TONEMAP_IN) != 0;
     const void *req[] = {io->cur.r, io->cur.g, io->cur.b, io->g.z, io->g.nx, io->g.ny, io->g.nz,
                          io->mvx, io->mvy, io->prev.z, io->prev.nx, io->prev.ny, io->prev.nz,
-                         io->hist.r, io->hist.g, io->hist.b, io->hist_m1, io->hist_m2,
+                         io->hist.r, io->hist.g, io->hist.b, io->hist_m1, io->hist_m2c,
                          io->hist_n, io->out.r, io->out.g, io->out.b, io->out_m1,
-                         io->out_m2, io->out_n};
+                         io->out_m2c, io->out_n};
     for (const void *q : req)
         if (!q) return SV_EINVAL;
     if (use_id && (!io->g.id || !io->prev.id)) return SV_EINVAL;
@@ -277,13 +312,13 @@ extern "C" int sv_temporal(const sv_temporal_io *io, sv_dims d, sv_dtype t,
         plane_span(io->prev.ny, d, es), plane_span(io->prev.nz, d, es),
         plane_span(io->hist.r, d, es), plane_span(io->hist.g, d, es),
         plane_span(io->hist.b, d, es), plane_span(io->hist_m1, d, 4),
-        plane_span(io->hist_m2, d, 4), plane_span(io->hist_n, d, 1),
+        plane_span(io->hist_m2c, d, 4), plane_span(io->hist_n, d, 1),
         use_id ? plane_span(io->g.id, d, 1) : span{0, 0},
         use_id ? plane_span(io->prev.id, d, 1) : span{0, 0},
         io->alpha_map ? plane_span(io->alpha_map, d, 4) : span{0, 0}};
     const span outs[] = {plane_span(io->out.r, d, es), plane_span(io->out.g, d, es),
                          plane_span(io->out.b, d, es), plane_span(io->out_m1, d, 4),
-                         plane_span(io->out_m2, d, 4), plane_span(io->out_n, d, 1)};
+                         plane_span(io->out_m2c, d, 4), plane_span(io->out_n, d, 1)};
     for (const span &so : outs) {
         for (const span &si : ins)
             if (overlaps(so, si)) return SV_EALIAS;
@@ -294,8 +329,8 @@ extern "C" int sv_temporal(const sv_temporal_io *io, sv_dims d, sv_dtype t,
     TemporalArgs a{io->cur.r, io->cur.g, io->cur.b, io->g.z, io->g.nx, io->g.ny, io->g.nz,
                    io->g.id, io->mvx, io->mvy, io->prev.z, io->prev.nx, io->prev.ny,
                    io->prev.nz, io->prev.id, io->hist.r, io->hist.g, io->hist.b, io->hist_m1,
-                   io->hist_m2, io->hist_n, io->out.r, io->out.g, io->out.b, io->out_m1,
-                   io->out_m2, io->out_n, io->alpha_map, d.w, d.h, d.pitch, p->alpha,
+                   io->hist_m2c, io->hist_n, io->out.r, io->out.g, io->out.b, io->out_m1,
+                   io->out_m2c, io->out_n, io->alpha_map, d.w, d.h, d.pitch, p->alpha,
                    p->alpha_m, p->gamma, p->tau_z, p->tau_n, p->tm_k, p->max_hist};
     dim3 grid((d.w + kTX - 1) / kTX, (d.h + kTY - 1) / kTY);
     hipStream_t s = as_stream(stream);

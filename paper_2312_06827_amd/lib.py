@@ -51,8 +51,8 @@ class sv_tm_params(ctypes.Structure):
 
 class sv_temporal_io(ctypes.Structure):
     _fields_ = [("cur", sv_rgb), ("g", sv_gbuf), ("mvx", _vp), ("mvy", _vp),
-                ("prev", sv_gbuf), ("hist", sv_rgb), ("hist_m1", _vp), ("hist_m2", _vp),
-                ("hist_n", _vp), ("out", sv_rgb), ("out_m1", _vp), ("out_m2", _vp),
+                ("prev", sv_gbuf), ("hist", sv_rgb), ("hist_m1", _vp), ("hist_m2c", _vp),
+                ("hist_n", _vp), ("out", sv_rgb), ("out_m1", _vp), ("out_m2c", _vp),
                 ("out_n", _vp), ("alpha_map", _vp)]
 
 
@@ -76,6 +76,24 @@ class sv_atrous_params(ctypes.Structure):
                 ("flags", ctypes.c_int32)]
 
 
+class sv_denoiser(ctypes.Structure):
+    _fields_ = [("hist", sv_rgb * 2), ("m1", _vp * 2), ("m2c", _vp * 2), ("n", _vp * 2),
+                ("temporal", sv_rgb), ("var", _vp), ("level", sv_rgb * 2),
+                ("level_var", _vp * 2), ("scratch", sv_rgb), ("out", sv_rgb),
+                ("cur", ctypes.c_int32)]
+
+
+class sv_frame_in(ctypes.Structure):
+    _fields_ = [("cur", sv_rgb), ("g", sv_gbuf), ("mvx", _vp), ("mvy", _vp),
+                ("prev", sv_gbuf), ("alpha_map", _vp), ("kappa", _vp)]
+
+
+class sv_frame_params(ctypes.Structure):
+    _fields_ = [("temporal", sv_temporal_params), ("variance", sv_variance_params),
+                ("atrous", sv_atrous_params), ("levels", ctypes.c_int32),
+                ("separable", ctypes.c_int32), ("feedback", ctypes.c_int32)]
+
+
 _P = ctypes.POINTER
 EXPORTS = {
     "sv_tonemap": ([_P(sv_rgb), _P(sv_rgb), sv_dims, ctypes.c_int, ctypes.c_int,
@@ -91,6 +109,8 @@ EXPORTS = {
     "sv_atrous_sep": ([_P(sv_rgb), _vp, _P(sv_gbuf), _vp, _P(sv_rgb), _P(sv_rgb), _vp,
                        ctypes.c_int32, sv_dims, ctypes.c_int, _P(sv_atrous_params), _vp],
                       ctypes.c_int),
+    "sv_denoise_frame": ([_P(sv_frame_in), _P(sv_denoiser), sv_dims, ctypes.c_int,
+                          _P(sv_frame_params), _vp], ctypes.c_int),
     "sv_status_str": ([ctypes.c_int], ctypes.c_char_p),
     "sv_version": ([], ctypes.c_int),
     "sv_last_hip_error": ([], ctypes.c_int),
@@ -267,13 +287,14 @@ def sv_clamp(hist: Planes, cur: Planes, out: Planes, gamma: float,
 
 
 def sv_temporal(cur: Planes, g: GBuf, mv: Planes, prev: GBuf, hist: Planes,
-                hist_m1: torch.Tensor, hist_m2: torch.Tensor, hist_n: torch.Tensor,
-                out: Planes, out_m1: torch.Tensor, out_m2: torch.Tensor, out_n: torch.Tensor,
+                hist_m1: torch.Tensor, hist_m2c: torch.Tensor, hist_n: torch.Tensor,
+                out: Planes, out_m1: torch.Tensor, out_m2c: torch.Tensor, out_n: torch.Tensor,
                 params: TemporalParams, alpha_map: Optional[torch.Tensor] = None, stream=None):
+    """m2c planes hold the central moment E[L^2] - E[L]^2."""
     mvx, mvy = mv[0], mv[1]
     io = sv_temporal_io(_rgb(cur), g.c(), _plane_ptr(mvx), _plane_ptr(mvy), prev.c(),
-                        _rgb(hist), _plane_ptr(hist_m1), _plane_ptr(hist_m2),
-                        _plane_ptr(hist_n), _rgb(out), _plane_ptr(out_m1), _plane_ptr(out_m2),
+                        _rgb(hist), _plane_ptr(hist_m1), _plane_ptr(hist_m2c),
+                        _plane_ptr(hist_n), _rgb(out), _plane_ptr(out_m1), _plane_ptr(out_m2c),
                         _plane_ptr(out_n), _plane_ptr(alpha_map))
     r = _planes3(cur)[0]
     pc = params.c()
@@ -281,12 +302,12 @@ def sv_temporal(cur: Planes, g: GBuf, mv: Planes, prev: GBuf, hist: Planes,
                                              ctypes.byref(pc), _stream(stream)))
 
 
-def sv_variance(m1: torch.Tensor, m2: torch.Tensor, n: torch.Tensor, g: GBuf,
+def sv_variance(m1: torch.Tensor, m2c: torch.Tensor, n: torch.Tensor, g: GBuf,
                 var: torch.Tensor, params: VarianceParams, stream=None):
     gc = g.c()
     pc = params.c()
     _check("sv_variance", load().sv_variance(
-        _plane_ptr(m1), _plane_ptr(m2), _plane_ptr(n), ctypes.byref(gc), _plane_ptr(var),
+        _plane_ptr(m1), _plane_ptr(m2c), _plane_ptr(n), ctypes.byref(gc), _plane_ptr(var),
         dims_of(m1), dtype_of(g.z), ctypes.byref(pc), _stream(stream)))
 
 
@@ -320,6 +341,15 @@ def sv_probe_copy(dst: torch.Tensor, src: torch.Tensor, stream=None):
         raise ValueError("dst is smaller than src")
     _check("sv_probe_copy", load().sv_probe_copy(dst.data_ptr(), src.data_ptr(), nbytes,
                                                  _stream(stream)))
+
+
+def sv_denoise_frame(fin: sv_frame_in, st: sv_denoiser, dims: sv_dims, dtype: int,
+                     params: sv_frame_params, stream=None):
+    """One frame through the native driver (structures prepared by the
+    caller; see pipeline.Denoiser)."""
+    _check("sv_denoise_frame", load().sv_denoise_frame(
+        ctypes.byref(fin), ctypes.byref(st), dims, dtype, ctypes.byref(params),
+        _stream(stream)))
 
 
 def sv_version() -> int:

@@ -59,6 +59,13 @@ class FilterConfig:
         return AtrousParams(self.sigma_z, self.sigma_n, self.sigma_l, self.eps_z, self.eps_l,
                             self.tm_k, False, inv_tonemap)
 
+    def frame_params(self) -> lib.sv_frame_params:
+        if self.feedback not in ("atrous0", "temporal"):
+            raise ValueError(f"unknown feedback {self.feedback!r}")
+        return lib.sv_frame_params(self.temporal().c(), self.variance().c(), self.atrous().c(),
+                                   self.levels, int(self.separable),
+                                   1 if self.feedback == "temporal" else 0)
+
 
 # The filter settings of the workloads: plain (static camera) and the
 # paper's final configuration (clamp + tone map, with 2D or separable blur).
@@ -74,6 +81,18 @@ class FrameInputs:
     g: GBuf                    # current G-buffer
     mv: torch.Tensor           # (2, H, W) backward motion
     prev: GBuf                 # previous frame's z, n, id
+
+    def c(self, alpha_map: Optional[torch.Tensor] = None,
+          kappa: Optional[torch.Tensor] = None) -> lib.sv_frame_in:
+        key = (None if alpha_map is None else alpha_map.data_ptr(),
+               None if kappa is None else kappa.data_ptr())
+        cached = self.__dict__.get("_c")
+        if cached is None or cached[0] != key:
+            fin = lib.sv_frame_in(lib._rgb(self.rgb), self.g.c(), lib._plane_ptr(self.mv[0]),
+                                  lib._plane_ptr(self.mv[1]), self.prev.c(),
+                                  lib._plane_ptr(alpha_map), lib._plane_ptr(kappa))
+            self.__dict__["_c"] = cached = (key, fin)
+        return cached[1]
 
     @staticmethod
     def from_numpy(fr: Dict[str, np.ndarray], device="cuda") -> "FrameInputs":
@@ -98,19 +117,42 @@ class Denoiser:
         u8 = lambda: torch.zeros((height, width), dtype=torch.uint8, device=dev)
         self.c_hist = [rgb(), rgb()]
         self.m1 = [f32(), f32()]
-        self.m2 = [f32(), f32()]
+        self.m2c = [f32(), f32()]  # central second moment
         self.n = [u8(), u8()]
-        self.t_rgb = [rgb(), rgb()]  # temporal output (double-buffered for "temporal" feedback)
+        self.t_rgb = [rgb()]  # temporal output (the history itself under "temporal" feedback)
         self.var = f32()
         self.lvl = [rgb(), rgb()]
         self.lvl_var = [f32(), f32()]
         self.scratch = rgb() if cfg.separable else None
         self.out = rgb()
-        self.k = 0  # index of the current history buffers
         self.frames = 0
+        # the same buffers, as the native driver's structure
+        R = lib._rgb
+        scratch = R(self.scratch) if self.scratch is not None else lib.sv_rgb()
+        self._st = lib.sv_denoiser(
+            (lib.sv_rgb * 2)(R(self.c_hist[0]), R(self.c_hist[1])),
+            (lib._vp * 2)(*[t.data_ptr() for t in self.m1]),
+            (lib._vp * 2)(*[t.data_ptr() for t in self.m2c]),
+            (lib._vp * 2)(*[t.data_ptr() for t in self.n]),
+            R(self.t_rgb[0]), self.var.data_ptr(),
+            (lib.sv_rgb * 2)(R(self.lvl[0]), R(self.lvl[1])),
+            (lib._vp * 2)(*[t.data_ptr() for t in self.lvl_var]),
+            scratch, R(self.out), 0)
+        self._dims = lib.dims_of(self.out)
+        self._dtype = lib.dtype_of(self.out)
+        self._params = cfg.frame_params()
+
+    @property
+    def k(self) -> int:
+        """Index of the buffers that hold the current history."""
+        return self._st.cur
+
+    @k.setter
+    def k(self, v: int):
+        self._st.cur = v
 
     def reset(self):
-        for t in self.c_hist + self.m1 + self.m2 + self.n + self.t_rgb:
+        for t in self.c_hist + self.m1 + self.m2c + self.n:
             t.zero_()
         self.k = 0
         self.frames = 0
@@ -118,8 +160,7 @@ class Denoiser:
     def state(self) -> Dict[str, torch.Tensor]:
         """The history the next frame will read."""
         k = self.k
-        c = self.t_rgb[k] if self.cfg.feedback == "temporal" else self.c_hist[k]
-        return {"rgb": c, "m1": self.m1[k], "m2": self.m2[k], "n": self.n[k]}
+        return {"rgb": self.c_hist[k], "m1": self.m1[k], "m2c": self.m2c[k], "n": self.n[k]}
 
     def frame(self, inp: FrameInputs, alpha_map: Optional[torch.Tensor] = None,
               kappa: Optional[torch.Tensor] = None, stream=None,
@@ -128,23 +169,30 @@ class Denoiser:
         """Enqueue one frame; returns the output tensor (valid once the
         stream reaches it; overwritten by the next frame).  `timer(name)`,
         if given, wraps each library call (for per-kernel events)."""
+        if timer is None:
+            lib.sv_denoise_frame(inp.c(alpha_map, kappa), self._st, self._dims, self._dtype,
+                                 self._params, stream=stream)
+            self.frames += 1
+            return self.out
+        # the same sequence call by call, for per-kernel timing
         cfg, k, k1 = self.cfg, self.k, 1 - self.k
-        tm = timer if timer is not None else (lambda name: contextlib.nullcontext())
-        hist = self.t_rgb[k] if cfg.feedback == "temporal" else self.c_hist[k]
-        t_out = self.t_rgb[k1]
+        tm = timer
+        fb_t = cfg.feedback == "temporal" or cfg.levels == 0
+        hist = self.c_hist[k]
+        t_out = self.c_hist[k1] if fb_t else self.t_rgb[0]
         with tm("temporal"):
-            lib.sv_temporal(inp.rgb, inp.g, inp.mv, inp.prev, hist, self.m1[k], self.m2[k],
-                            self.n[k], t_out, self.m1[k1], self.m2[k1], self.n[k1],
+            lib.sv_temporal(inp.rgb, inp.g, inp.mv, inp.prev, hist, self.m1[k], self.m2c[k],
+                            self.n[k], t_out, self.m1[k1], self.m2c[k1], self.n[k1],
                             cfg.temporal(), alpha_map=alpha_map, stream=stream)
         with tm("variance"):
-            lib.sv_variance(self.m1[k1], self.m2[k1], self.n[k1], inp.g, self.var,
+            lib.sv_variance(self.m1[k1], self.m2c[k1], self.n[k1], inp.g, self.var,
                             cfg.variance(), stream=stream)
         c, v = t_out, self.var
         L = cfg.levels
         for i in range(L):
             last = i == L - 1
-            fuse_inv = cfg.tonemap and last and not (i == 0 and cfg.feedback == "atrous0")
-            if i == 0 and cfg.feedback == "atrous0":
+            fuse_inv = cfg.tonemap and last and not (i == 0 and not fb_t)
+            if i == 0 and not fb_t:
                 dst = self.c_hist[k1]
             elif last:
                 dst = self.out
@@ -161,11 +209,11 @@ class Denoiser:
                     lib.sv_atrous(c, v, inp.g, dst, dst_var, 1 << i, p, kappa=kappa,
                                   stream=stream)
             c, v = dst, dst_var
-        if cfg.tonemap and (L == 0 or (L == 1 and cfg.feedback == "atrous0")):
-            lib.sv_tonemap(c, self.out, inverse=True, k=cfg.tm_k, stream=stream)
-            c = self.out
-        elif c is not self.out:
-            self.out.copy_(c)
+        if L == 0 or (L == 1 and not fb_t):
+            if cfg.tonemap:
+                lib.sv_tonemap(c, self.out, inverse=True, k=cfg.tm_k, stream=stream)
+            else:
+                self.out.copy_(c)
         self.k = k1
         self.frames += 1
         return self.out
@@ -173,5 +221,7 @@ class Denoiser:
     def intermediates(self) -> Dict[str, torch.Tensor]:
         """Views of the last frame's temporal output, moments and variance."""
         k = self.k
-        return {"t_rgb": self.t_rgb[k], "m1": self.m1[k], "m2": self.m2[k], "n": self.n[k],
+        fb_t = self.cfg.feedback == "temporal" or self.cfg.levels == 0
+        t_rgb = self.c_hist[k] if fb_t else self.t_rgb[0]
+        return {"t_rgb": t_rgb, "m1": self.m1[k], "m2c": self.m2c[k], "n": self.n[k],
                 "var": self.var, "level0": self.c_hist[k]}

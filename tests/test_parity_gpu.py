@@ -111,9 +111,11 @@ def _temporal_case(H, W, seed):
     hist = (np.roll(fr["clean"], 1, axis=-1) * r.uniform(0.7, 1.3, (3, H, W))).astype(np.float32)
     L0 = hist.mean(0)
     m1 = (L0 * r.uniform(0.9, 1.1, (H, W))).astype(np.float32)
-    m2 = (m1 * m1 * r.uniform(1.0, 2.0, (H, W))).astype(np.float32)
+    m2c = (m1 * m1 * r.uniform(0.0, 1.0, (H, W))).astype(np.float32)
     hn = r.integers(0, 13, (H, W)).astype(np.uint8)
-    state = {"rgb": hist, "m1": m1, "m2": m2, "n": hn}
+    # the oracle keeps the raw second moment E[L^2] = m2c + m1^2
+    state = {"rgb": hist, "m1": m1, "m2c": m2c,
+             "m2": m2c.astype(np.float64) + m1.astype(np.float64) ** 2, "n": hn}
     return fr, state
 
 
@@ -139,12 +141,12 @@ def test_temporal(H, W, clamp, tonemap, use_id):
     on = empty_like_dev((H, W), P, torch.uint8)
     tp = L.TemporalParams(clamp=clamp, tonemap=tonemap, use_id=use_id, gamma=1.0)
     L.sv_temporal(dev(fr["rgb"], P), g, dev(fr["mv"], P), prev, dev(st["rgb"], P),
-                  dev(st["m1"], P), dev(st["m2"], P), dev(st["n"], P, torch.uint8),
+                  dev(st["m1"], P), dev(st["m2c"], P), dev(st["n"], P, torch.uint8),
                   out, om1, om2, on, tp)
     np.testing.assert_array_equal(host(on), ref["n"])
     assert rel_err(host(out), ref["rgb"]) <= TOL32
     assert rel_err(host(om1), ref["m1"]) <= TOL32
-    assert rel_err(host(om2), ref["m2"]) <= TOL32
+    assert rel_err(host(om2), ref["m2c"]) <= TOL32
 
 
 def test_temporal_alpha_map_and_discarded_motion():
@@ -163,7 +165,7 @@ def test_temporal_alpha_map_and_discarded_motion():
     out, om1, om2 = empty_like_dev((3, H, W)), empty_like_dev((H, W)), empty_like_dev((H, W))
     on = empty_like_dev((H, W), dtype=torch.uint8)
     L.sv_temporal(dev(fr["rgb"]), g, dev(fr["mv"]), prev, dev(st["rgb"]), dev(st["m1"]),
-                  dev(st["m2"]), dev(st["n"], dtype=torch.uint8), out, om1, om2, on,
+                  dev(st["m2c"]), dev(st["n"], dtype=torch.uint8), out, om1, om2, on,
                   L.TemporalParams(clamp=True, tonemap=True), alpha_map=dev(am))
     np.testing.assert_array_equal(host(on), ref["n"])
     assert host(on)[3, 3] == 1 and host(on)[4, 4] == 1
@@ -179,12 +181,13 @@ def test_variance(H, W):
     if H > 10:
         z[r.random((H, W)) < 0.05] = 0.0
     m1 = r.uniform(0.1, 1.0, (H, W)).astype(np.float32)
-    m2 = (m1 * m1 * r.uniform(0.9, 2.0, (H, W))).astype(np.float32)
+    m2c = (m1 * m1 * r.uniform(0.0, 1.0, (H, W))).astype(np.float32)
+    m2 = m2c.astype(np.float64) + m1.astype(np.float64) ** 2  # raw moment for the oracle
     hn = r.integers(0, 7, (H, W)).astype(np.uint8)
-    for sigma_n in (128.0, 0.0):
+    for sigma_n in (128.0, 16.0, 0.0):
         say(f"variance {H}x{W} sigma_n={sigma_n}")
         out = empty_like_dev((H, W), W + 2)
-        L.sv_variance(dev(m1, W + 2), dev(m2, W + 2), dev(hn, W + 2, torch.uint8),
+        L.sv_variance(dev(m1, W + 2), dev(m2c, W + 2), dev(hn, W + 2, torch.uint8),
                       gbuf_dev(z, dzdx, dzdy, n, W + 2), out, L.VarianceParams(sigma_n=sigma_n))
         ref = O.variance(m1, m2, hn, z, dzdx, dzdy, n, sigma_n=sigma_n)
         assert rel_err(host(out), ref) <= TOL32
@@ -233,7 +236,8 @@ def test_atrous_kappa_and_params(step):
     c, var, z, dzdx, dzdy, n = _atrous_inputs(H, W, 500 + step)
     kappa = np.random.default_rng(5).uniform(0.25, 4.0, (H, W)).astype(np.float32)
     g = gbuf_dev(z, dzdx, dzdy, n)
-    for sz, sn, sl in [(1.0, 128.0, 4.0), (2.0, 0.0, 1.0), (0.5, 32.0, 8.0)]:
+    for sz, sn, sl in [(1.0, 128.0, 4.0), (2.0, 0.0, 1.0), (0.5, 32.0, 8.0), (1.0, 64.0, 4.0),
+                       (1.0, 1.0, 4.0)]:
         say(f"atrous params step={step} sz={sz} sn={sn} sl={sl}")
         out, vo = empty_like_dev((3, H, W)), empty_like_dev((H, W))
         L.sv_atrous(dev(c), dev(var), g, out, vo, step,

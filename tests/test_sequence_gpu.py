@@ -42,7 +42,10 @@ def run_pair(cfg, filt, ofilt, frames=None, check_every=1):
             "out": rel_err(host(out), ref),
             "temporal": rel_err(host(inter["t_rgb"]), ex["temporal"]["rgb"]),
             "m1": rel_err(host(inter["m1"]), ex["temporal"]["m1"]),
-            "m2": rel_err(host(inter["m2"]), ex["temporal"]["m2"]),
+            # the method's second moment E[L^2]; the device keeps it central
+            # (m2c = E[L^2] - E[L]^2), whose relative accuracy for a sample of
+            # two is set by (L - m1)^2, not by the kernel
+            "m2": rel_err(host(inter["m2c"]) + host(inter["m1"]) ** 2, ex["temporal"]["m2"]),
             "var": rel_err(host(inter["var"]), ex["var"]),
         }
         say(f"  frame {f}: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
@@ -70,3 +73,33 @@ def test_motion_full_hd_first_frames(sep):
     say(f"sequence 1920x1080 motion, separable={sep}, 3 frames")
     run_pair(cfg, MOTION_SEP if sep else MOTION, ORACLE_MOTION_SEP if sep else ORACLE_MOTION,
              frames=3)
+
+
+class _NullTimer:
+    def __call__(self, name):
+        import contextlib
+        return contextlib.nullcontext()
+
+
+@pytest.mark.parametrize("levels,sep,feedback", [(5, False, "atrous0"), (5, True, "atrous0"),
+                                                 (1, False, "atrous0"), (0, False, "atrous0"),
+                                                 (3, True, "temporal")])
+def test_native_driver_equals_call_by_call(levels, sep, feedback):
+    """sv_denoise_frame enqueues exactly the individual calls: bitwise equal."""
+    from dataclasses import replace
+    cfg = with_size(CONFIGS["hd_motion"], 200, 120, 6)
+    filt = replace(MOTION_SEP if sep else MOTION, levels=levels, feedback=feedback)
+    say(f"native driver vs calls: levels={levels} sep={sep} feedback={feedback}")
+    a = Denoiser(cfg.height, cfg.width, filt)
+    b = Denoiser(cfg.height, cfg.width, filt)
+    ofilt = O.OracleParams(clamp=True, tonemap=True, use_id=True, separable=sep,
+                           levels=levels, feedback=feedback)
+    st = O.new_state(cfg.height, cfg.width)
+    for fr in sequence(cfg):
+        inp = FrameInputs.from_numpy(fr)
+        oa = a.frame(inp).clone()
+        ob = b.frame(inp, timer=_NullTimer()).clone()
+        assert torch.equal(oa, ob)
+        ref, st, _ = O.run_frame(fr, st, ofilt)
+        assert rel_err(host(oa), ref) <= TOL32
+    assert a.k == b.k
