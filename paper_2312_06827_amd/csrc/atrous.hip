@@ -28,7 +28,7 @@ struct AtrousArgs {
 };
 
 // Weight modes: every edge weight 1 (plain B3), or the full weight with the
-// normal term off / as its series / through the logarithm.
+// normal term off or on.
 enum { kUnit = 3 };
 
 // log2 of the B3-spline taps (1, 4, 6, 4, 1) / 16
@@ -57,9 +57,9 @@ __device__ __forceinline__ float prefilter_global(const AtrousArgs &a, int x, in
     for (int i = 0; i < 9; ++i) {
         const int qx = x + i % 3 - 1, qy = y + i / 3 - 1;
         const bool in = qx >= 0 && qx < a.w && qy >= 0 && qy < a.h;
-        const size_t q = in ? (size_t)qy * a.pitch + qx : (size_t)y * a.pitch + x;
-        zq[i] = in ? ld((const T *)a.z + q) : 0.f;
-        vq[i] = a.var[q];
+        const uint32_t q = in ? (uint32_t)qy * (uint32_t)a.pitch + (uint32_t)qx : (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x;
+        zq[i] = in ? ldo<T>(a.z, q) : 0.f;
+        vq[i] = ldf(a.var, q);
     }
     float s = 0.f, sw = 0.f;
 #pragma unroll
@@ -71,8 +71,8 @@ __device__ __forceinline__ float prefilter_global(const AtrousArgs &a, int x, in
     return s / sw;
 }
 
-__device__ __forceinline__ float luma_scale(const AtrousArgs &a, float g, size_t o) {
-    const float kap = a.kappa ? a.kappa[o] : 1.0f;
+__device__ __forceinline__ float luma_scale(const AtrousArgs &a, float g, uint32_t o) {
+    const float kap = a.kappa ? ldf(a.kappa, o) : 1.0f;
     return kLog2e / fmaf(a.sigma_l * kap, sqrtf(g), a.eps_l);
 }
 
@@ -103,19 +103,19 @@ __device__ __forceinline__ void tap(Acc &acc, float4 qc, float4 qg, float qv, fl
 }
 
 template <typename T>
-__device__ __forceinline__ void write_out(const AtrousArgs &a, size_t o, float r, float g,
+__device__ __forceinline__ void write_out(const AtrousArgs &a, uint32_t o, float r, float g,
                                           float b) {
     if (a.inv_tm) inv_tonemap(r, g, b, a.tm_k);
-    st((T *)a.or_ + o, r);
-    st((T *)a.og + o, g);
-    st((T *)a.ob + o, b);
+    sto<T>(a.or_, o, r);
+    sto<T>(a.og, o, g);
+    sto<T>(a.ob, o, b);
 }
 
 template <typename T>
-__device__ __forceinline__ void pass_through(const AtrousArgs &a, size_t o, const void *r,
+__device__ __forceinline__ void pass_through(const AtrousArgs &a, uint32_t o, const void *r,
                                              const void *g, const void *b) {
-    write_out<T>(a, o, ld((const T *)r + o), ld((const T *)g + o), ld((const T *)b + o));
-    if (a.var_out) a.var_out[o] = 0.f;
+    write_out<T>(a, o, ldo<T>(r, o), ldo<T>(g, o), ldo<T>(b, o));
+    if (a.var_out) stf(a.var_out, o, 0.f);
 }
 
 // ---- 5x5 level, LDS tile ---------------------------------------------------
@@ -149,15 +149,15 @@ __global__ __launch_bounds__(256) void atrous_tile_k(AtrousArgs a) {
         float4 gn = make_float4(0.f, 0.f, 0.f, 0.f);
         float v = 0.f;
         if (gx >= 0 && gx < a.w && gy >= 0 && gy < a.h) {
-            const size_t o = (size_t)gy * a.pitch + gx;
-            const float zz = ld((const T *)a.z + o);
+            const uint32_t o = (uint32_t)gy * (uint32_t)a.pitch + (uint32_t)gx;
+            const float zz = ldo<T>(a.z, o);
             if (!empty_px(zz)) {
-                const float R = ld((const T *)a.cr + o), G = ld((const T *)a.cg + o),
-                            B = ld((const T *)a.cb + o);
+                const float R = ldo<T>(a.cr, o), G = ldo<T>(a.cg, o),
+                            B = ldo<T>(a.cb, o);
                 cl = make_float4(R, G, B, luma(R, G, B));
-                gn = make_float4(zz, ld((const T *)a.nx + o), ld((const T *)a.ny + o),
-                                 ld((const T *)a.nz + o));
-                if (NEED_V) v = a.var[o];
+                gn = make_float4(zz, ldo<T>(a.nx, o), ldo<T>(a.ny, o),
+                                 ldo<T>(a.nz, o));
+                if (NEED_V) v = ldf(a.var, o);
             }
         }
         s_cl[i] = cl;
@@ -171,8 +171,8 @@ __global__ __launch_bounds__(256) void atrous_tile_k(AtrousArgs a) {
             const int gx = x0 - 1 + c, gy = ybase + j * STEP + r3 - 1;
             float2 e = make_float2(0.f, 0.f);
             if (gx >= 0 && gx < a.w && gy >= 0 && gy < a.h) {
-                const size_t o = (size_t)gy * a.pitch + gx;
-                if (!empty_px(ld((const T *)a.z + o))) e = make_float2(a.var[o], 1.f);
+                const uint32_t o = (uint32_t)gy * (uint32_t)a.pitch + (uint32_t)gx;
+                if (!empty_px(ldo<T>(a.z, o))) e = make_float2(ldf(a.var, o), 1.f);
             }
             s_pf[i] = e;
         }
@@ -187,7 +187,7 @@ __global__ __launch_bounds__(256) void atrous_tile_k(AtrousArgs a) {
         const int j = ly + 4 * k;
         const int y = ybase + j * STEP;
         if (y >= a.h) break;
-        const size_t o = (size_t)y * a.pitch + x;
+        const uint32_t o = (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x;
         const int ci = (j + 2) * COLS + lx + 2 * STEP;
         const float4 pc = s_cl[ci];
         const float4 pg = s_gn[ci];
@@ -226,8 +226,8 @@ __global__ __launch_bounds__(256) void atrous_tile_k(AtrousArgs a) {
         float kl = 0.f;
         if (MODE != kUnit) {
             kl = luma_scale(a, g, o);
-            const float gx = ld((const T *)a.dzdx + o) * (float)STEP;
-            const float gy = ld((const T *)a.dzdy + o) * (float)STEP;
+            const float gx = ldo<T>(a.dzdx, o) * (float)STEP;
+            const float gy = ldo<T>(a.dzdy, o) * (float)STEP;
 #pragma unroll
             for (int b = 0; b <= 2; ++b)
 #pragma unroll
@@ -258,7 +258,7 @@ __global__ __launch_bounds__(256) void atrous_tile_k(AtrousArgs a) {
             }
         const float inv = 1.0f / acc.sw;
         write_out<T>(a, o, acc.sr * inv, acc.sg * inv, acc.sb * inv);
-        if (WANT_VAR) a.var_out[o] = acc.sv * inv * inv;
+        if (WANT_VAR) stf(a.var_out, o, acc.sv * inv * inv);
     }
 }
 
@@ -271,13 +271,13 @@ __device__ __forceinline__ void load_tap(const AtrousArgs &a, int qx, int qy, fl
     qg = make_float4(0.f, 0.f, 0.f, 0.f);
     qv = 0.f;
     if (qx < 0 || qx >= a.w || qy < 0 || qy >= a.h) return;
-    const size_t q = (size_t)qy * a.pitch + qx;
-    const float zz = ld((const T *)a.z + q);
+    const uint32_t q = (uint32_t)qy * (uint32_t)a.pitch + (uint32_t)qx;
+    const float zz = ldo<T>(a.z, q);
     if (empty_px(zz)) return;
-    const float R = ld((const T *)a.cr + q), G = ld((const T *)a.cg + q), B = ld((const T *)a.cb + q);
+    const float R = ldo<T>(a.cr, q), G = ldo<T>(a.cg, q), B = ldo<T>(a.cb, q);
     qc = make_float4(R, G, B, luma(R, G, B));
-    qg = make_float4(zz, ld((const T *)a.nx + q), ld((const T *)a.ny + q), ld((const T *)a.nz + q));
-    qv = a.var[q];
+    qg = make_float4(zz, ldo<T>(a.nx, q), ldo<T>(a.ny, q), ldo<T>(a.nz, q));
+    qv = ldf(a.var, q);
 }
 
 template <typename T, int MODE, bool WANT_VAR>
@@ -285,7 +285,7 @@ __global__ __launch_bounds__(256) void atrous_direct_k(AtrousArgs a) {
     const int x = blockIdx.x * 64 + (threadIdx.x & 63);
     const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
     if (x >= a.w || y >= a.h) return;
-    const size_t o = (size_t)y * a.pitch + x;
+    const uint32_t o = (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x;
     float4 pc, pg;
     float pv;
     load_tap<T>(a, x, y, pc, pg, pv);
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(256) void atrous_direct_k(AtrousArgs a) {
     float kl = 0.f;
     if (MODE != kUnit) {
         kl = luma_scale(a, g, o);
-        const float gx = ld((const T *)a.dzdx + o) * s, gy = ld((const T *)a.dzdy + o) * s;
+        const float gx = ldo<T>(a.dzdx, o) * s, gy = ldo<T>(a.dzdy, o) * s;
 #pragma unroll
         for (int b = 0; b <= 2; ++b)
 #pragma unroll
@@ -325,7 +325,7 @@ __global__ __launch_bounds__(256) void atrous_direct_k(AtrousArgs a) {
         }
     const float inv = 1.0f / acc.sw;
     write_out<T>(a, o, acc.sr * inv, acc.sg * inv, acc.sb * inv);
-    if (WANT_VAR) a.var_out[o] = acc.sv * inv * inv;
+    if (WANT_VAR) stf(a.var_out, o, acc.sv * inv * inv);
 }
 
 // ---- separable level (Section 3.3), direct loads -------------------------------
@@ -339,7 +339,7 @@ __global__ __launch_bounds__(256) void atrous_sep_k(AtrousArgs a) {
     const int x = blockIdx.x * 64 + (threadIdx.x & 63);
     const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
     if (x >= a.w || y >= a.h) return;
-    const size_t o = (size_t)y * a.pitch + x;
+    const uint32_t o = (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x;
     float4 pc, pg;
     float pv;
     load_tap<T>(a, x, y, pc, pg, pv);
@@ -347,9 +347,9 @@ __global__ __launch_bounds__(256) void atrous_sep_k(AtrousArgs a) {
         if (VERTICAL) {
             pass_through<T>(a, o, a.cr, a.cg, a.cb);
         } else {
-            st((T *)a.or_ + o, ld((const T *)a.cr + o));
-            st((T *)a.og + o, ld((const T *)a.cg + o));
-            st((T *)a.ob + o, ld((const T *)a.cb + o));
+            sto<T>(a.or_, o, ldo<T>(a.cr, o));
+            sto<T>(a.og, o, ldo<T>(a.cg, o));
+            sto<T>(a.ob, o, ldo<T>(a.cb, o));
         }
         return;
     }
@@ -382,11 +382,11 @@ __global__ __launch_bounds__(256) void atrous_sep_k(AtrousArgs a) {
     const float inv = 1.0f / acc.sw;
     if (VERTICAL) {
         write_out<T>(a, o, acc.sr * inv, acc.sg * inv, acc.sb * inv);
-        if (WANT_VAR) a.var_out[o] = acc.sv * inv * inv;
+        if (WANT_VAR) stf(a.var_out, o, acc.sv * inv * inv);
     } else {
-        st((T *)a.or_ + o, acc.sr * inv);
-        st((T *)a.og + o, acc.sg * inv);
-        st((T *)a.ob + o, acc.sb * inv);
+        sto<T>(a.or_, o, acc.sr * inv);
+        sto<T>(a.og, o, acc.sg * inv);
+        sto<T>(a.ob, o, acc.sb * inv);
     }
 }
 
@@ -426,7 +426,6 @@ static void dispatch_2d(const AtrousArgs &a, int mode, hipStream_t s) {
     switch (mode) {
     case kUnit: launch_2d_var<T, kUnit>(a, s); return;
     case kNormalOff: launch_2d_var<T, kNormalOff>(a, s); return;
-    case kNormalPoly: launch_2d_var<T, kNormalPoly>(a, s); return;
     default: launch_2d_var<T, kNormalLog>(a, s); return;
     }
 }
@@ -445,7 +444,6 @@ static void dispatch_sep(const AtrousArgs &a, int mode, hipStream_t s) {
     switch (mode) {
     case kUnit: launch_sep<T, kUnit, VERTICAL>(a, s); return;
     case kNormalOff: launch_sep<T, kNormalOff, VERTICAL>(a, s); return;
-    case kNormalPoly: launch_sep<T, kNormalPoly, VERTICAL>(a, s); return;
     default: launch_sep<T, kNormalLog, VERTICAL>(a, s); return;
     }
 }

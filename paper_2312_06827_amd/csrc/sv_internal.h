@@ -24,6 +24,25 @@ template <typename T> __device__ __forceinline__ void st(T *p, float v);
 template <> __device__ __forceinline__ void st<float>(float *p, float v) { *p = v; }
 template <> __device__ __forceinline__ void st<half_t>(half_t *p, float v) { *p = (half_t)v; }
 
+// Plane element `idx` addressed by a 32-bit byte offset from the plane's
+// base (an SGPR pair): loads and stores then need no 64-bit address
+// arithmetic.  The host limits pitch * h to 2^29 elements, so every byte
+// offset fits in 32 bits.
+template <typename T>
+__device__ __forceinline__ float ldo(const void *base, uint32_t idx) {
+    return ld((const T *)((const char *)base + idx * (uint32_t)sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ void sto(void *base, uint32_t idx, float v) {
+    st((T *)((char *)base + idx * (uint32_t)sizeof(T)), v);
+}
+__device__ __forceinline__ float ldf(const float *base, uint32_t idx) {
+    return *(const float *)((const char *)base + idx * 4u);
+}
+__device__ __forceinline__ void stf(float *base, uint32_t idx, float v) {
+    *(float *)((char *)base + idx * 4u) = v;
+}
+
 // ---- shared arithmetic ----------------------------------------------------
 
 // Rec. 709 luminance, fixed evaluation order.
@@ -43,43 +62,30 @@ constexpr float kLog2e = 1.4426950408889634f;
 // ---- normal edge weight ----------------------------------------------------
 //
 // The weight is max(0, cos)^sigma_n with the cosine of two unit normals
-// taken as 1 - s2/2, s2 = |n(p) - n(q)|^2.  Its base-2 logarithm
-// sigma_n log2(1 - s2/2) is added to a tap's exponent.  For sigma_n >= 64
-// the logarithm is its series -(t + t^2/2 + t^3/3 + t^4/4), t = s2/2: the
-// weights that matter have t small, where the first omitted term
-// sigma_n t^5/5 times the weight exp(-sigma_n t) stays below
-// e^-5 5^4 / sigma_n^4 (2.5e-7 at sigma_n = 64, 1.6e-8 at 128), and it
-// avoids rounding 1 - s2/2 near 1, which sigma_n would amplify.  Below 64 the
-// logarithm of the rounded u = 1 - s2/2 is corrected by the rounding error
-// of u.
-enum { kNormalOff = 0, kNormalPoly = 1, kNormalLog = 2 };
+// taken as u = 1 - s2/2, s2 = |n(p) - n(q)|^2 (accurate where the normals
+// are close, unlike 1 - rounded dot products).  Its base-2 logarithm
+// sigma_n log2(u) is added to a tap's exponent.  u is rounded once; sigma_n
+// (128) would amplify that rounding into the weight, so the exact residual
+// r = (1 - s2/2) - u is added as sigma_n log2(e) r (the first-order term of
+// log(u + r) - log(u) near u = 1, where every weight that matters lies).
+enum { kNormalOff = 0, kNormalLog = 2 };
 
 struct NormalCoef {
-    float c1, c2, c3, c4;  // sigma_n log2(e) times the series coefficients in s2
-    float sn;              // sigma_n
-    float snl;             // sigma_n log2(e)
+    float sn;   // sigma_n
+    float snl;  // sigma_n log2(e)
 };
 
 inline NormalCoef make_normal_coef(float sigma_n) {
-    const float k = sigma_n * 1.4426950408889634f;
-    // -(t + t^2/2 + t^3/3 + t^4/4) with t = s2/2
-    return NormalCoef{-k / 2.0f, -k / 8.0f, -k / 24.0f, -k / 64.0f, sigma_n, k};
+    return NormalCoef{sigma_n, sigma_n * 1.4426950408889634f};
 }
 
-inline int normal_mode(float sigma_n) {
-    return sigma_n == 0.0f ? kNormalOff : (sigma_n >= 64.0f ? kNormalPoly : kNormalLog);
-}
+inline int normal_mode(float sigma_n) { return sigma_n == 0.0f ? kNormalOff : kNormalLog; }
 
 template <int NM>
 __device__ __forceinline__ float add_normal_term(float e, float s2, const NormalCoef &k) {
-    if (NM == kNormalPoly) {
-        float p = fmaf(s2, k.c4, k.c3);
-        p = fmaf(s2, p, k.c2);
-        p = fmaf(s2, p, k.c1);
-        return fmaf(s2, p, e);
-    } else if (NM == kNormalLog) {
+    if (NM == kNormalLog) {
         const float u = fmaf(-0.5f, s2, 1.0f);
-        const float r = fmaf(-0.5f, s2, 1.0f - u);  // (1 - s2/2) - u, exact
+        const float r = fmaf(-0.5f, s2, 1.0f - u);  // (1 - s2/2) - u, exact for u >= 1/2
         e = fmaf(k.sn, __builtin_amdgcn_logf(fmaxf(u, 0.0f)), e);
         return fmaf(k.snl, r, e);
     }
@@ -114,7 +120,7 @@ inline int check_dims(sv_dims d) {
     if (d.w < 0 || d.h < 0 || d.w > kMaxDim || d.h > kMaxDim) return -1;
     if (d.w == 0 || d.h == 0) return 1;
     if (d.pitch < d.w) return -1;
-    if ((int64_t)d.pitch * d.h >= ((int64_t)1 << 31)) return -1;
+    if ((int64_t)d.pitch * d.h > ((int64_t)1 << 29)) return -1;
     return 0;
 }
 

@@ -44,39 +44,36 @@ __device__ __forceinline__ bool normal_consistent(float ax, float ay, float az, 
 }
 
 // 3x3 box of the tile around (lx+1, ly+1): clamp bounds mu -+ gamma sigma
-// per channel from the mean and population sigma (two-pass) over valid
-// entries (w component 1).  Binary64: the bounds are differences of
-// quantities of the colour's size and may be close to zero.
+// per channel from the mean and population variance over valid entries
+// (w component 1, else 0; their colour is masked out here).  Binary64: the
+// bounds are differences of quantities of the colour's size and may be
+// close to zero.  One pass of sums of x and x^2 suffices there: products of
+// binary32 values are exact in binary64, and the cancellation in
+// E[x^2] - E[x]^2 costs at most log2(mu^2 / sigma^2) of its 53 bits.
 __device__ __forceinline__ void box_bounds(const float4 *tile, int lx, int ly, float gamma,
                                            float3 &lo, float3 &hi) {
-    double sr = 0.0, sg = 0.0, sb = 0.0, cnt = 0.0;
+    double s1r = 0.0, s1g = 0.0, s1b = 0.0, s2r = 0.0, s2g = 0.0, s2b = 0.0;
+    float cnt = 0.f;
 #pragma unroll
     for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
         for (int dx = 0; dx < 3; ++dx) {
             const float4 q = tile[(ly + dy) * (kTX + 2) + lx + dx];
-            const double w = q.w;
-            sr = fma(w, (double)q.x, sr);
-            sg = fma(w, (double)q.y, sg);
-            sb = fma(w, (double)q.z, sb);
-            cnt += w;
+            const double r = q.w * q.x, g = q.w * q.y, b = q.w * q.z;  // exact: w is 0 or 1
+            s1r += r;
+            s1g += g;
+            s1b += b;
+            s2r = fma(r, r, s2r);
+            s2g = fma(g, g, s2g);
+            s2b = fma(b, b, s2b);
+            cnt += q.w;
         }
-    const double inv = 1.0 / cnt;
-    const double mr = sr * inv, mg = sg * inv, mb = sb * inv;
-    double vr = 0.0, vg = 0.0, vb = 0.0;
-#pragma unroll
-    for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-        for (int dx = 0; dx < 3; ++dx) {
-            const float4 q = tile[(ly + dy) * (kTX + 2) + lx + dx];
-            const double w = q.w;
-            const double er = q.x - mr, eg = q.y - mg, eb = q.z - mb;
-            vr = fma(w * er, er, vr);
-            vg = fma(w * eg, eg, vg);
-            vb = fma(w * eb, eb, vb);
-        }
-    const double gr = gamma * sqrt(vr * inv), gg = gamma * sqrt(vg * inv),
-                 gb = gamma * sqrt(vb * inv);
+    const double inv = 1.0 / (double)cnt;
+    const double mr = s1r * inv, mg = s1g * inv, mb = s1b * inv;
+    const double vr = fmax(0.0, fma(-mr, mr, s2r * inv));
+    const double vg = fmax(0.0, fma(-mg, mg, s2g * inv));
+    const double vb = fmax(0.0, fma(-mb, mb, s2b * inv));
+    const double gr = gamma * sqrt(vr), gg = gamma * sqrt(vg), gb = gamma * sqrt(vb);
     lo = make_float3((float)(mr - gr), (float)(mg - gg), (float)(mb - gb));
     hi = make_float3((float)(mr + gr), (float)(mg + gg), (float)(mb + gb));
 }
@@ -93,15 +90,15 @@ __device__ __forceinline__ void stage_current(float4 *tile, const void *cr, cons
         int gx = x0 + c, gy = y0 + r;
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
         if (gx >= 0 && gx < w && gy >= 0 && gy < h) {
-            size_t o = (size_t)gy * pitch + gx;
-            float R = ld((const T *)cr + o), G = ld((const T *)cg + o), B = ld((const T *)cb + o);
+            uint32_t o = (uint32_t)gy * (uint32_t)pitch + (uint32_t)gx;
+            float R = ldo<T>(cr, o), G = ldo<T>(cg, o), B = ldo<T>(cb, o);
             if (TM) {
-                float den = 1.0f + tm_k * luma(R, G, B);
-                R = R / den;
-                G = G / den;
-                B = B / den;
+                const float sc = 1.0f / (1.0f + tm_k * luma(R, G, B));
+                R *= sc;
+                G *= sc;
+                B *= sc;
             }
-            float valid = (zp == nullptr || !empty_px(ld((const T *)zp + o))) ? 1.f : 0.f;
+            float valid = (zp == nullptr || !empty_px(ldo<T>(zp, o))) ? 1.f : 0.f;
             v = make_float4(R, G, B, valid);
         }
         tile[i] = v;
@@ -116,22 +113,22 @@ __global__ __launch_bounds__(256) void temporal_k(TemporalArgs a) {
     const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
     const int x = blockIdx.x * kTX + lx, y = blockIdx.y * kTY + ly;
     if (x >= a.w || y >= a.h) return;
-    const size_t o = (size_t)y * a.pitch + x;
+    const uint32_t o = (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x;
     const float4 c = tile[(ly + 1) * (kTX + 2) + lx + 1];
     const float L = luma(c.x, c.y, c.z);
-    const float zc = ld((const T *)a.z + o);
+    const float zc = ldo<T>(a.z, o);
     if (empty_px(zc)) {
-        st((T *)a.or_ + o, c.x);
-        st((T *)a.og + o, c.y);
-        st((T *)a.ob + o, c.z);
-        a.om1[o] = 0.f;
-        a.om2c[o] = 0.f;
+        sto<T>(a.or_, o, c.x);
+        sto<T>(a.og, o, c.y);
+        sto<T>(a.ob, o, c.z);
+        stf(a.om1, o, 0.f);
+        stf(a.om2c, o, 0.f);
         a.on[o] = 0;
         return;
     }
-    const float nxc = ld((const T *)a.nx + o), nyc = ld((const T *)a.ny + o),
-                nzc = ld((const T *)a.nz + o);
-    const float mvx = ld((const T *)a.mvx + o), mvy = ld((const T *)a.mvy + o);
+    const float nxc = ldo<T>(a.nx, o), nyc = ldo<T>(a.ny, o),
+                nzc = ldo<T>(a.nz, o);
+    const float mvx = ldo<T>(a.mvx, o), mvy = ldo<T>(a.mvy, o);
     const uint8_t idc = USE_ID ? a.id[o] : 0;
 
     // ---- backward reprojection: bilinear taps around p + mv ----
@@ -149,18 +146,18 @@ __global__ __launch_bounds__(256) void temporal_k(TemporalArgs a) {
         const int tx = x0 + (t & 1), ty = y0 + (t >> 1);
         bw[t] = ((t & 1) ? fx : 1.0f - fx) * ((t >> 1) ? fy : 1.0f - fy);
         inb[t] = mv_ok && bw[t] > 0.f && tx >= 0 && tx < a.w && ty >= 0 && ty < a.h;
-        const size_t q = inb[t] ? (size_t)ty * a.pitch + tx : o;
+        const uint32_t q = inb[t] ? (uint32_t)ty * (uint32_t)a.pitch + (uint32_t)tx : o;
         thn[t] = a.hn[q];
-        tz[t] = ld((const T *)a.pz + q);
-        tnx[t] = ld((const T *)a.pnx + q);
-        tny[t] = ld((const T *)a.pny + q);
-        tnz[t] = ld((const T *)a.pnz + q);
+        tz[t] = ldo<T>(a.pz, q);
+        tnx[t] = ldo<T>(a.pnx, q);
+        tny[t] = ldo<T>(a.pny, q);
+        tnz[t] = ldo<T>(a.pnz, q);
         tid_[t] = USE_ID ? a.pid[q] : 0;
-        tr[t] = ld((const T *)a.hr + q);
-        tg[t] = ld((const T *)a.hg + q);
-        tb[t] = ld((const T *)a.hb + q);
-        t1[t] = a.hm1[q];
-        t2[t] = a.hm2c[q];
+        tr[t] = ldo<T>(a.hr, q);
+        tg[t] = ldo<T>(a.hg, q);
+        tb[t] = ldo<T>(a.hb, q);
+        t1[t] = ldf(a.hm1, q);
+        t2[t] = ldf(a.hm2c, q);
     }
     float sw = 0.f, ar = 0.f, ag = 0.f, ab = 0.f, a1 = 0.f;
     int nmax = 0;
@@ -213,7 +210,7 @@ __global__ __launch_bounds__(256) void temporal_k(TemporalArgs a) {
         // ---- accumulation ----
         n = min(nmax + 1, a.max_hist);
         const float inv_n = 1.0f / (float)n;
-        const float ac = fmaxf(a.alpha_map ? a.alpha_map[o] : a.alpha, inv_n);
+        const float ac = fmaxf(a.alpha_map ? ldf(a.alpha_map, o) : a.alpha, inv_n);
         const float am = fmaxf(a.alpha_m, inv_n);
         outr = fmaf(ac, c.x - hr, hr);
         outg = fmaf(ac, c.y - hg, hg);
@@ -224,11 +221,11 @@ __global__ __launch_bounds__(256) void temporal_k(TemporalArgs a) {
         // (1 - am) (m2c + am (L - m1)^2)
         m2c = (1.0f - am) * fmaf(am * dl, dl, hm2c);
     }
-    st((T *)a.or_ + o, outr);
-    st((T *)a.og + o, outg);
-    st((T *)a.ob + o, outb);
-    a.om1[o] = m1;
-    a.om2c[o] = m2c;
+    sto<T>(a.or_, o, outr);
+    sto<T>(a.og, o, outg);
+    sto<T>(a.ob, o, outb);
+    stf(a.om1, o, m1);
+    stf(a.om2c, o, m2c);
     a.on[o] = (uint8_t)n;
 }
 
@@ -247,8 +244,8 @@ __global__ __launch_bounds__(256) void clamp_k(ClampArgs a) {
     const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
     const int x = blockIdx.x * kTX + lx, y = blockIdx.y * kTY + ly;
     if (x >= a.w || y >= a.h) return;
-    const size_t o = (size_t)y * a.pitch + x;
-    float r = ld((const T *)a.hr + o), g = ld((const T *)a.hg + o), b = ld((const T *)a.hb + o);
+    const uint32_t o = (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x;
+    float r = ldo<T>(a.hr, o), g = ldo<T>(a.hg, o), b = ldo<T>(a.hb, o);
     const bool active = a.gamma > 0.f && tile[(ly + 1) * (kTX + 2) + lx + 1].w > 0.f;
     if (active) {
         float3 lo, hi;
@@ -257,9 +254,9 @@ __global__ __launch_bounds__(256) void clamp_k(ClampArgs a) {
         g = fminf(fmaxf(g, lo.y), hi.y);
         b = fminf(fmaxf(b, lo.z), hi.z);
     }
-    st((T *)a.or_ + o, r);
-    st((T *)a.og + o, g);
-    st((T *)a.ob + o, b);
+    sto<T>(a.or_, o, r);
+    sto<T>(a.og, o, g);
+    sto<T>(a.ob, o, b);
 }
 
 template <typename T, bool TM, bool CLAMP>

@@ -16,8 +16,8 @@ __global__ __launch_bounds__(256) void tonemap_k(TonemapArgs a) {
     int x = blockIdx.x * 64 + (threadIdx.x & 63);
     int y = blockIdx.y * 4 + (threadIdx.x >> 6);
     if (x >= a.w || y >= a.h) return;
-    size_t o = (size_t)y * a.pitch + x;
-    float r = ld((const T *)a.r + o), g = ld((const T *)a.g + o), b = ld((const T *)a.b + o);
+    uint32_t o = (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x;
+    float r = ldo<T>(a.r, o), g = ldo<T>(a.g, o), b = ldo<T>(a.b, o);
     if (a.mode == SV_TM_CHANNEL) {
         if (!a.inverse) {
             r = r / (1.0f + a.k * r);
@@ -41,9 +41,9 @@ __global__ __launch_bounds__(256) void tonemap_k(TonemapArgs a) {
     } else {
         inv_tonemap(r, g, b, a.k);
     }
-    st((T *)a.ro + o, r);
-    st((T *)a.go + o, g);
-    st((T *)a.bo + o, b);
+    sto<T>(a.ro, o, r);
+    sto<T>(a.go, o, g);
+    sto<T>(a.bo, o, b);
 }
 
 }  // namespace sv

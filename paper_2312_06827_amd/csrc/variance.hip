@@ -44,17 +44,17 @@ __global__ __launch_bounds__(256) void variance_k(VarianceArgs a) {
     const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
     const int x = blockIdx.x * kVX + lx, y = blockIdx.y * kVY + ly;
     const bool inside = x < a.w && y < a.h;
-    const size_t o = inside ? (size_t)y * a.pitch + x : 0;
+    const uint32_t o = inside ? (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x : 0;
     int n = 0;
     float zp = 0.f;
     if (inside) {
         n = a.n[o];
-        zp = ld((const T *)a.z + o);
+        zp = ldo<T>(a.z, o);
     }
     const bool live = inside && n >= 1 && !empty_px(zp);
     const bool spatial = live && n < a.min_hist;
     float v = 0.f;
-    if (live && !spatial) v = fmaxf(0.f, a.m2c[o]);
+    if (live && !spatial) v = fmaxf(0.f, ldf(a.m2c, o));
     if (threadIdx.x == 0) s_count = 0;
     __syncthreads();
     if (spatial) s_list[atomicAdd(&s_count, 1)] = threadIdx.x;
@@ -71,14 +71,14 @@ __global__ __launch_bounds__(256) void variance_k(VarianceArgs a) {
             const int gx = gx0 + c, gy = gy0 + r;
             float m1 = 0.f, m2 = 0.f, zz = 0.f, nx = 0.f, ny = 0.f, nz = 0.f;
             if (gx >= 0 && gx < a.w && gy >= 0 && gy < a.h) {
-                const size_t q = (size_t)gy * a.pitch + gx;
-                zz = ld((const T *)a.z + q);
+                const uint32_t q = (uint32_t)gy * (uint32_t)a.pitch + (uint32_t)gx;
+                zz = ldo<T>(a.z, q);
                 if (empty_px(zz)) zz = 0.f;
-                m1 = a.m1[q];
-                m2 = a.m2c[q];
-                nx = ld((const T *)a.nx + q);
-                ny = ld((const T *)a.ny + q);
-                nz = ld((const T *)a.nz + q);
+                m1 = ldf(a.m1, q);
+                m2 = ldf(a.m2c, q);
+                nx = ldo<T>(a.nx, q);
+                ny = ldo<T>(a.ny, q);
+                nz = ldo<T>(a.nz, q);
             }
             s_m1[i] = m1;
             s_m2[i] = m2;
@@ -92,8 +92,8 @@ __global__ __launch_bounds__(256) void variance_k(VarianceArgs a) {
         for (int e = wave; e < cnt; e += 4) {
             const int pt = s_list[e];
             const int px = pt & 63, py = pt >> 6;
-            const size_t po = (size_t)(blockIdx.y * kVY + py) * a.pitch + blockIdx.x * kVX + px;
-            const float gx = ld((const T *)a.dzdx + po), gy = ld((const T *)a.dzdy + po);
+            const uint32_t po = (uint32_t)(blockIdx.y * kVY + py) * (uint32_t)a.pitch + (uint32_t)(blockIdx.x * kVX + px);
+            const float gx = ldo<T>(a.dzdx, po), gy = ldo<T>(a.dzdy, po);
             const int ci = (py + R) * WX + px + R;
             const float zc = s_z[ci], nxp = s_nx[ci], nyp = s_ny[ci], nzp = s_nz[ci];
             // pass 1: per-lane taps (lane, lane + 64, ...) then wavefront sums
@@ -141,7 +141,7 @@ __global__ __launch_bounds__(256) void variance_k(VarianceArgs a) {
         __syncthreads();
         if (spatial) v = s_res[threadIdx.x];
     }
-    if (inside) a.var[o] = v;
+    if (inside) stf(a.var, o, v);
 }
 
 template <typename T>
@@ -150,9 +150,6 @@ static void launch_variance(const VarianceArgs &a, int nm, dim3 grid, size_t lds
     switch (nm) {
     case kNormalOff:
         hipLaunchKernelGGL((variance_k<T, kNormalOff>), grid, dim3(256), lds, s, a);
-        break;
-    case kNormalPoly:
-        hipLaunchKernelGGL((variance_k<T, kNormalPoly>), grid, dim3(256), lds, s, a);
         break;
     default:
         hipLaunchKernelGGL((variance_k<T, kNormalLog>), grid, dim3(256), lds, s, a);

@@ -45,3 +45,21 @@ def random_gbuf(r, H, W, z_range=(4.0, 6.0)):
     n /= np.linalg.norm(n, axis=0)
     f = lambda a: a.astype(np.float32)
     return f(z), f(dzdx), f(dzdy), f(n)
+
+
+def worst(gpu, ora, floor=1e-3):
+    """Where the relative error of rel_err() peaks: (plane, y, x, gpu, oracle)."""
+    g = np.asarray(gpu, dtype=np.float64)
+    o = np.asarray(ora, dtype=np.float64)
+    if o.ndim == 2:
+        g, o = g[None], o[None]
+    best = (0.0, None)
+    for k, (gp, op) in enumerate(zip(g, o)):
+        rms = np.sqrt(np.mean(op * op))
+        den = np.maximum(np.abs(op), floor * rms)
+        den = np.where(den > 0, den, 1.0)
+        e = np.abs(gp - op) / den
+        i = np.unravel_index(int(np.argmax(e)), e.shape)
+        if e[i] > best[0]:
+            best = (float(e[i]), (k,) + tuple(int(v) for v in i) + (float(gp[i]), float(op[i])))
+    return best[1]
