@@ -99,13 +99,13 @@ class KernelTimer:
         return {k: (float(np.mean(v)), len(v)) for k, v in out.items()}
 
 
-def run_chain(torch, frames_dev, cfg, H, W, warmup, steps, per_kernel):
+def run_chain(torch, frames_dev, cfg, H, W, warmup, steps, per_kernel, tiles=None):
     """Warm up, then time `steps` frames.  Headline mode enqueues each frame
     with one native call and nothing else; per-kernel mode brackets every
     library call with events (which adds a few microseconds per call)."""
     from paper_2312_06827_amd.pipeline import Denoiser
 
-    den = Denoiser(H, W, cfg)
+    den = Denoiser(H, W, cfg, tiles=tiles)
     timer = KernelTimer(torch, 16 * (warmup + steps)) if per_kernel else None
     for f in range(warmup):
         den.frame(frames_dev[f], timer=timer)
@@ -189,17 +189,23 @@ def main():
     frames_dev = [FrameInputs.from_numpy(fr) for fr in frames_np]
     torch.cuda.synchronize()
 
+    # launch shapes of the a-trous levels, measured on this device and size
+    from paper_2312_06827_amd.autotune import tiles_for
+    tiles_2d = tiles_for(H, W, separable=False, cache=None)
+    tiles_sep = tiles_for(H, W, separable=True, cache=None)
+    print(f"# tuned launch shapes 2d {tiles_2d} sep {tiles_sep}", file=sys.stderr, flush=True)
     # a throwaway pass warms clocks, code objects and allocator
-    run_chain(torch, frames_dev, MOTION, H, W, 2, min(8, args.steps), per_kernel=False)
+    run_chain(torch, frames_dev, MOTION, H, W, 2, min(8, args.steps), per_kernel=False,
+              tiles=tiles_2d)
     gpu_ms, wall, _ = run_chain(torch, frames_dev, MOTION, H, W, args.warmup, args.steps,
-                                per_kernel=False)
+                                per_kernel=False, tiles=tiles_2d)
     ms_per_step = gpu_ms / args.steps
     mpix = W * H * args.steps / (gpu_ms * 1e-3) / 1e6
     print(f"# 2d chain: {ms_per_step * 1e3:.1f} us/frame (host wall {wall / args.steps * 1e6:.1f}"
           f" us/frame)", file=sys.stderr, flush=True)
     # per-kernel durations: the same frames again, every call between events
     _, _, ktimes = run_chain(torch, frames_dev, MOTION, H, W, args.warmup, args.steps,
-                             per_kernel=True)
+                             per_kernel=True, tiles=tiles_2d)
 
     # roofline of the dominant kernel: the a-trous levels
     npx = W * H
@@ -216,9 +222,9 @@ def main():
     variants = {}
     if not args.no_variants:
         g2, w2, _ = run_chain(torch, frames_dev, MOTION_SEP, H, W, args.warmup, args.steps,
-                              per_kernel=False)
+                              per_kernel=False, tiles=tiles_sep)
         _, _, kt2 = run_chain(torch, frames_dev, MOTION_SEP, H, W, args.warmup, args.steps,
-                              per_kernel=True)
+                              per_kernel=True, tiles=tiles_sep)
         variants["separable"] = {
             "value": round(W * H * args.steps / (g2 * 1e-3) / 1e6, 1), "unit": "Mpix/s",
             "ms_per_step": round(g2 / args.steps, 4),

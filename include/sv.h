@@ -186,7 +186,11 @@ typedef struct {
     int32_t radius;   /* spatial window radius, 0..7, default 3 */
 } sv_variance_params;
 
-/* var = max(0, m2c) where n >= min_hist (m2c = E[L^2] - E[L]^2 as
+/* Two passes: every pixel with n >= min_hist gets the temporal estimate and
+ * the others are listed in `work`; a second pass spreads the listed pixels
+ * over the whole GPU for the spatial estimate (they are few, about 1% in
+ * steady motion, but clustered at disocclusions).
+ * var = max(0, m2c) where n >= min_hist (m2c = E[L^2] - E[L]^2 as
  * sv_temporal writes it).  Where 1 <= n < min_hist the moments are averaged
  * over the (2 radius + 1)^2 window (inside the image, not empty) with
  * weight 1 at the centre and
@@ -197,8 +201,16 @@ typedef struct {
  * mixture.  n == 0 or an empty pixel gives 0.  `var` must not overlap the
  * inputs. */
 int sv_variance(const float *m1, const float *m2c, const uint8_t *n,
-                const sv_gbuf *g, float *var, sv_dims d, sv_dtype t,
+                const sv_gbuf *g, float *var, void *work, sv_dims d, sv_dtype t,
                 const sv_variance_params *p, sv_stream stream);
+
+/* Size in bytes of the `work` buffer sv_variance needs for dims d (0 for
+ * invalid dims): eight counters and a list of the short-history pixels.
+ * The caller allocates it on the device and ZEROES it before its first
+ * use; every call returns the counters to zero, so one buffer serves any
+ * number of calls in order on one stream (calls that may run concurrently
+ * need one buffer each).  It must not overlap any input or `var`. */
+size_t sv_variance_work_bytes(sv_dims d);
 
 /* ---- edge-avoiding a-trous level (Section 2, Fig. 1; Section 3.3) ------ */
 enum {
@@ -214,6 +226,12 @@ typedef struct {
     float eps_l;   /* default 1e-10 */
     float tm_k;    /* tone-map multiplier for SV_A_INV_TONEMAP, default 1 */
     int32_t flags; /* SV_A_* */
+    /* Launch shape of the LDS-tiled kernels (results do not depend on it):
+     * persistent: -1 library default, 0 one tile per workgroup, 1 each
+     * workgroup loops over tiles and prefetches the next one;
+     * blocks_per_cu: workgroups per CU of a persistent launch (0 default). */
+    int32_t persistent;
+    int32_t blocks_per_cu;
 } sv_atrous_params;
 
 /* One level with hole spacing `step` (>= 1; 1, 2, 4, 8, 16 for the five
@@ -259,6 +277,7 @@ typedef struct {
     uint8_t *n[2];           /* history length, double-buffered (0 = none) */
     sv_rgb temporal;         /* temporal output (scratch) */
     float *var;              /* variance estimate (scratch) */
+    void *var_work;          /* sv_variance workspace (zeroed once) */
     sv_rgb level[2];         /* a-trous colour ping-pong (scratch) */
     float *level_var[2];     /* a-trous variance ping-pong (scratch) */
     sv_rgb scratch;          /* separable horizontal result (separable only) */
@@ -284,6 +303,10 @@ typedef struct {
     int32_t separable;           /* 1: sv_atrous_sep levels */
     int32_t feedback;            /* colour history: 0 level-0 output,
                                     1 temporal output */
+    /* per-level launch shape overriding atrous.persistent / blocks_per_cu
+     * when >= 0 / > 0 (set by an autotuner; results do not depend on it) */
+    int32_t level_persistent[10];
+    int32_t level_blocks_per_cu[10];
 } sv_frame_params;
 
 /* Enqueues one frame: sv_temporal (history -> temporal), sv_variance,

@@ -15,7 +15,7 @@ int hip_status(hipError_t e) {
 __global__ __launch_bounds__(256) void probe_copy_k(uint4 *__restrict__ dst,
                                                     const uint4 *__restrict__ src, size_t n) {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    size_t stride = (size_t)gridDim.x * blockDim.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (; i < n; i += stride) dst[i] = src[i];
 }
 
@@ -48,7 +48,7 @@ int sv_probe_copy(void *dst, const void *src, size_t bytes, sv_stream stream) {
     if (a < b + bytes && b < a + bytes) return SV_EALIAS;
     size_t n = bytes / 16;
     size_t blocks = (n + 255) / 256;
-    if (blocks > 256 * 64) blocks = 256 * 64;  // grid-stride beyond 64 blocks per CU
+    if (blocks > 256 * 64) blocks = 256 * 64;  // 64 workgroups per CU, grid-stride beyond
     hipLaunchKernelGGL(sv::probe_copy_k, dim3((unsigned)blocks), dim3(256), 0,
                        sv::as_stream(stream), (uint4 *)dst, (const uint4 *)src, n);
     return sv::hip_status(hipGetLastError());

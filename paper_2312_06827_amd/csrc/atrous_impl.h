@@ -1,0 +1,569 @@
+// Edge-avoiding a-trous wavelet levels guided by the variance (Section 2,
+// Fig. 1) in 5x5 form, and the separable form of Section 3.3.
+//
+// Every tap's weight H(a,b) * w_z * w_n * w_l is evaluated as one
+// exponential: log2 H - |dz| kz(a,b) - |dL| kl + sigma_n log2 max(0, cos)
+// (the normal term as in sv_internal.h),
+// with kz(a,b) = log2(e) / (sigma_z |grad z . step (a,b)| + eps_z) (12
+// distinct values per pixel, the offsets pairing up as +-(a,b)) and
+// kl = log2(e) / (sigma_l kappa sqrt(g) + eps_l).  A tap outside the image
+// or on an empty pixel is staged with luminance +inf and zero colour,
+// variance, depth and normal, which drives its exponent to -inf (weight 0)
+// without a branch.
+#pragma once
+#include "sv_internal.h"
+
+namespace sv {
+
+struct AtrousArgs {
+    const void *cr, *cg, *cb;
+    const float *var;
+    const void *z, *dzdx, *dzdy, *nx, *ny, *nz;
+    const float *kappa;
+    void *or_, *og, *ob;
+    float *var_out;
+    int w, h, pitch, step;
+    float sigma_z, sigma_l, eps_z, eps_l, tm_k;
+    NormalCoef nc;
+    int inv_tm;
+};
+
+// Weight modes: every edge weight 1 (plain B3), or the full edge weights.
+enum { kUnit = 0, kWeighted = 1 };
+
+// log2 of the B3-spline taps (1, 4, 6, 4, 1) / 16
+__device__ constexpr float kLog2H1[5] = {-4.0f, -2.0f, -1.4150374992788438f, -2.0f, -4.0f};
+__device__ constexpr float kH1[5] = {0.0625f, 0.25f, 0.375f, 0.25f, 0.0625f};
+constexpr float kG3[3] = {0.25f, 0.5f, 0.25f};
+
+// Index of the distinct depth denominator of offset (a, b): offsets +-(a,b)
+// share one; the canonical one has b > 0, or b == 0 and a > 0.
+// (Not recursive, so that it folds to a constant once the tap loops unroll.)
+__host__ __device__ __forceinline__ constexpr int kz_index(int a, int b) {
+    const bool flip = b < 0 || (b == 0 && a < 0);
+    const int ca = flip ? -a : a, cb = flip ? -b : b;
+    return cb == 0 ? ca - 1 : 2 + (cb - 1) * 5 + (ca + 2);
+}
+static_assert(kz_index(1, 0) == 0 && kz_index(-2, 0) == 1 && kz_index(-2, 1) == 2 &&
+                  kz_index(2, -2) == 7 && kz_index(2, 2) == 11,
+              "depth denominator indexing");
+
+// 3x3 Gaussian of the variance around (x, y) over in-image, non-empty
+// pixels, renormalised.  All nine loads are issued before any test.
+template <typename T>
+__device__ __forceinline__ float prefilter_global(const AtrousArgs &a, int x, int y) {
+    float zq[9], vq[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const int qx = x + i % 3 - 1, qy = y + i / 3 - 1;
+        const bool in = qx >= 0 && qx < a.w && qy >= 0 && qy < a.h;
+        const uint32_t q = in ? (uint32_t)qy * (uint32_t)a.pitch + (uint32_t)qx : (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x;
+        zq[i] = in ? ldo<T>(a.z, q) : 0.f;
+        vq[i] = ldf(a.var, q);
+    }
+    float s = 0.f, sw = 0.f;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const float k = empty_px(zq[i]) ? 0.f : kG3[i % 3] * kG3[i / 3];
+        s = fmaf(k, vq[i], s);
+        sw += k;
+    }
+    return s / sw;
+}
+
+__device__ __forceinline__ float luma_scale(const AtrousArgs &a, float g, uint32_t o) {
+    const float kap = a.kappa ? ldf(a.kappa, o) : 1.0f;
+    return kLog2e / fmaf(a.sigma_l * kap, sqrtf(g), a.eps_l);
+}
+
+struct Acc {
+    float sw, sr, sg, sb, sv;
+};
+
+// One weighted tap (not the centre).  qc = (r, g, b, L), qg = (z, nx, ny, nz).
+template <int MODE, bool WANT_VAR>
+__device__ __forceinline__ void tap(Acc &acc, float4 qc, float4 qg, float qv, float log2h,
+                                    float hconst, float kz, float zp, float lp, float nxp,
+                                    float nyp, float nzp, float kl, const NormalCoef &nc) {
+    float hw;
+    if (MODE == kUnit) {
+        hw = qg.x > 0.f ? hconst : 0.f;
+    } else {
+        float t = fmaf(-fabsf(zp - qg.x), kz, log2h);
+        t = fmaf(-fabsf(lp - qc.w), kl, t);
+        t = add_normal_term(t, chord2(nxp, nyp, nzp, qg.y, qg.z, qg.w), nc);
+        hw = fast_exp2(t);
+    }
+    acc.sw += hw;
+    acc.sr = fmaf(hw, qc.x, acc.sr);
+    acc.sg = fmaf(hw, qc.y, acc.sg);
+    acc.sb = fmaf(hw, qc.z, acc.sb);
+    if (WANT_VAR) acc.sv = fmaf(hw * hw, qv, acc.sv);
+}
+
+template <typename T>
+__device__ __forceinline__ void write_out(const AtrousArgs &a, uint32_t o, float r, float g,
+                                          float b) {
+    if (a.inv_tm) inv_tonemap(r, g, b, a.tm_k);
+    sto<T>(a.or_, o, r);
+    sto<T>(a.og, o, g);
+    sto<T>(a.ob, o, b);
+}
+
+template <typename T>
+__device__ __forceinline__ void pass_through(const AtrousArgs &a, uint32_t o, const void *r,
+                                             const void *g, const void *b) {
+    write_out<T>(a, o, ldo<T>(r, o), ldo<T>(g, o), ldo<T>(b, o));
+    if (a.var_out) stf(a.var_out, o, 0.f);
+}
+
+// ---- a-trous level, LDS tile -------------------------------------------------
+//
+// One kernel for the 5x5 level (DIR 0) and the two passes of the separable
+// level (DIR 1 horizontal, DIR 2 vertical).  A tile is TX = 64 columns by
+// TY = 4 * PY rows taken on the step lattice: rows ybase + j * STEP,
+// j = 0..TY-1, with ybase = band * STEP * TY + phase.  The taps of those
+// pixels lie in the tile's own lattice rows (HY = 2 above and below, none
+// for the horizontal pass) and columns (HX = 2 STEP left and right, none for
+// the vertical pass), so the LDS footprint is (TY + 2 HY) x (TX + 2 HX)
+// pixels whatever the step, plus three image rows per lattice row for the
+// 3x3 variance prefilter unless they are already in the tile.
+//
+// The kernel is persistent: each workgroup walks a strided run of tiles of
+// its XCD's contiguous range, and issues the global loads of its next tile
+// into registers before computing the current one from LDS, so the memory
+// latency of a tile hides behind the arithmetic of the previous one.
+enum { kDir2D = 0, kDirH = 1, kDirV = 2 };
+
+template <int STEP, int PY, int DIR, bool WANT_VAR>
+struct TileShape {
+    static constexpr int TX = 64, TY = 4 * PY;
+    static constexpr int HY = DIR == kDirH ? 0 : 2, HX = DIR == kDirV ? 0 : 2 * STEP;
+    static constexpr int ROWS = TY + 2 * HY, COLS = TX + 2 * HX;
+    static constexpr int AMAX = DIR == kDirV ? 0 : 2, BMAX = DIR == kDirH ? 0 : 2;
+    static constexpr bool PF_TILE = STEP == 1 && DIR == kDir2D;
+    static constexpr bool NEED_V = WANT_VAR || PF_TILE;
+    static constexpr int PFC = TX + 2;
+    static constexpr int NS = ROWS * COLS, IT = (NS + 255) / 256;
+    static constexpr int NP = PF_TILE ? 0 : TY * 3 * PFC, ITP = (NP + 255) / 256;
+};
+
+// Raw values of one tile held in registers between issue and LDS store.
+template <int IT, int ITP>
+struct TileRegs {
+    float z[IT], r[IT], g[IT], b[IT], nx[IT], ny[IT], nz[IT], v[IT];
+    bool in[IT];
+    float pz[ITP > 0 ? ITP : 1], pv[ITP > 0 ? ITP : 1];
+    bool pin[ITP > 0 ? ITP : 1];
+};
+
+struct TileOrigin {
+    int x0, ybase;
+};
+
+template <int STEP, int TY, int TX>
+__device__ __forceinline__ TileOrigin tile_origin(int tile, int gxt) {
+    const int tyt = tile / gxt;  // band * STEP + phase
+    const int band = tyt / STEP, phase = tyt - band * STEP;
+    return TileOrigin{(tile - tyt * gxt) * TX, band * STEP * TY + phase};
+}
+
+// Issue every global load of a tile (addresses clamped into the image; a
+// pixel outside reads pixel (0, 0) and is masked when stored).
+template <typename T, class S, class R>
+__device__ __forceinline__ void tile_issue(const AtrousArgs &a, TileOrigin t, R &g) {
+    constexpr int STEP = S::HX == 0 ? 1 : S::HX / 2;  // only used for HX
+#pragma unroll
+    for (int it = 0; it < S::IT; ++it) {
+        const int i = threadIdx.x + it * 256;
+        const int r = i / S::COLS, c = i - r * S::COLS;
+        const int gx = t.x0 - S::HX + c;
+        const int gy = t.ybase + (r - S::HY) * a.step;
+        const bool in = i < S::NS && gx >= 0 && gx < a.w && gy >= 0 && gy < a.h;
+        const uint32_t o = in ? (uint32_t)gy * (uint32_t)a.pitch + (uint32_t)gx : 0u;
+        g.in[it] = in;
+        g.z[it] = ldo<T>(a.z, o);
+        g.r[it] = ldo<T>(a.cr, o);
+        g.g[it] = ldo<T>(a.cg, o);
+        g.b[it] = ldo<T>(a.cb, o);
+        g.nx[it] = ldo<T>(a.nx, o);
+        g.ny[it] = ldo<T>(a.ny, o);
+        g.nz[it] = ldo<T>(a.nz, o);
+        g.v[it] = S::NEED_V ? ldf(a.var, o) : 0.f;
+    }
+    (void)STEP;
+#pragma unroll
+    for (int it = 0; it < S::ITP; ++it) {
+        const int i = threadIdx.x + it * 256;
+        const int j = i / (3 * S::PFC), rem = i - j * (3 * S::PFC);
+        const int r3 = rem / S::PFC, c = rem - r3 * S::PFC;
+        const int gx = t.x0 - 1 + c, gy = t.ybase + j * a.step + r3 - 1;
+        const bool in = i < S::NP && gx >= 0 && gx < a.w && gy >= 0 && gy < a.h;
+        const uint32_t o = in ? (uint32_t)gy * (uint32_t)a.pitch + (uint32_t)gx : 0u;
+        g.pin[it] = in;
+        g.pz[it] = ldo<T>(a.z, o);
+        g.pv[it] = ldf(a.var, o);
+    }
+}
+
+template <class S, class R>
+__device__ __forceinline__ void tile_store(const R &g, float4 *s_cl, float4 *s_gn, float *s_v,
+                                           float2 *s_pf) {
+#pragma unroll
+    for (int it = 0; it < S::IT; ++it) {
+        const int i = threadIdx.x + it * 256;
+        if (i < S::NS) {
+            const bool ok = g.in[it] && !empty_px(g.z[it]);
+            s_cl[i] = ok ? make_float4(g.r[it], g.g[it], g.b[it], luma(g.r[it], g.g[it], g.b[it]))
+                         : make_float4(0.f, 0.f, 0.f, INFINITY);
+            s_gn[i] = ok ? make_float4(g.z[it], g.nx[it], g.ny[it], g.nz[it])
+                         : make_float4(0.f, 0.f, 0.f, 0.f);
+            if (S::NEED_V) s_v[i] = ok ? g.v[it] : 0.f;
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < S::ITP; ++it) {
+        const int i = threadIdx.x + it * 256;
+        if (i < S::NP)
+            s_pf[i] = (g.pin[it] && !empty_px(g.pz[it])) ? make_float2(g.pv[it], 1.f)
+                                                        : make_float2(0.f, 0.f);
+    }
+}
+
+template <typename T, int STEP, int PY, int MODE, bool WANT_VAR, int DIR>
+__device__ __forceinline__ void tile_compute(const AtrousArgs &a, TileOrigin t,
+                                             const float4 *s_cl, const float4 *s_gn,
+                                             const float *s_v, const float2 *s_pf) {
+    using S = TileShape<STEP, PY, DIR, WANT_VAR>;
+    constexpr int COLS = S::COLS, HY = S::HY, HX = S::HX, PFC = S::PFC;
+    const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
+    const int x = t.x0 + lx;
+    if (x >= a.w) return;
+#pragma unroll 1
+    for (int k = 0; k < PY; ++k) {
+        const int j = ly + 4 * k;
+        const int y = t.ybase + j * STEP;
+        if (y >= a.h) break;
+        const uint32_t o = (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x;
+        const int ci = (j + HY) * COLS + lx + HX;
+        const float4 pc = s_cl[ci];
+        const float4 pg = s_gn[ci];
+        if (pg.x == 0.f) {  // empty pixel
+            if (DIR == kDirH) {
+                sto<T>(a.or_, o, ldo<T>(a.cr, o));
+                sto<T>(a.og, o, ldo<T>(a.cg, o));
+                sto<T>(a.ob, o, ldo<T>(a.cb, o));
+            } else {
+                pass_through<T>(a, o, a.cr, a.cg, a.cb);
+            }
+            continue;
+        }
+        // prefiltered variance
+        float g;
+        {
+            float s = 0.f, sw = 0.f;
+            if (S::PF_TILE) {
+#pragma unroll
+                for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        const int qi = ci + dy * COLS + dx;
+                        const float kk = s_gn[qi].x > 0.f ? kG3[dx + 1] * kG3[dy + 1] : 0.f;
+                        s = fmaf(kk, s_v[qi], s);
+                        sw += kk;
+                    }
+            } else {
+#pragma unroll
+                for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                    for (int dx = 0; dx < 3; ++dx) {
+                        const float2 e = s_pf[(j * 3 + dy) * PFC + lx + dx];
+                        const float kk = e.y * (kG3[dx] * kG3[dy]);
+                        s = fmaf(kk, e.x, s);
+                        sw += kk;
+                    }
+            }
+            g = s / sw;
+        }
+        float kz[12];
+        float kl = 0.f;
+        if (MODE != kUnit) {
+            kl = luma_scale(a, g, o);
+            const float gx = DIR == kDirV ? 0.f : ldo<T>(a.dzdx, o) * (float)STEP;
+            const float gy = DIR == kDirH ? 0.f : ldo<T>(a.dzdy, o) * (float)STEP;
+#pragma unroll
+            for (int b = 0; b <= 2; ++b)
+#pragma unroll
+                for (int aa = -2; aa <= 2; ++aa) {
+                    if (b == 0 && aa <= 0) continue;
+                    const float den =
+                        fmaf(a.sigma_z, fabsf(fmaf(gx, (float)aa, gy * (float)b)), a.eps_z);
+                    kz[kz_index(aa, b)] = kLog2e * fast_rcp(den);
+                }
+        }
+        constexpr float h0 = DIR == kDir2D ? 0.375f * 0.375f : 0.375f;
+        Acc acc;
+        acc.sw = h0;
+        acc.sr = h0 * pc.x;
+        acc.sg = h0 * pc.y;
+        acc.sb = h0 * pc.z;
+        acc.sv = WANT_VAR ? h0 * h0 * s_v[ci] : 0.f;
+#pragma unroll
+        for (int b = -S::BMAX; b <= S::BMAX; ++b)
+#pragma unroll
+            for (int aa = -S::AMAX; aa <= S::AMAX; ++aa) {
+                if (aa == 0 && b == 0) continue;
+                const int qi = ci + b * COLS + aa * STEP;
+                const float qv = WANT_VAR ? s_v[qi] : 0.f;
+                const float log2h = DIR == kDir2D ? kLog2H1[aa + 2] + kLog2H1[b + 2]
+                                    : kLog2H1[(DIR == kDirH ? aa : b) + 2];
+                const float hc = DIR == kDir2D ? kH1[aa + 2] * kH1[b + 2]
+                                 : kH1[(DIR == kDirH ? aa : b) + 2];
+                tap<MODE, WANT_VAR>(acc, s_cl[qi], s_gn[qi], qv, log2h, hc,
+                                    MODE == kUnit ? 0.f : kz[kz_index(aa, b)], pg.x, pc.w, pg.y,
+                                    pg.z, pg.w, kl, a.nc);
+            }
+        const float inv = 1.0f / acc.sw;
+        if (DIR == kDirH) {
+            sto<T>(a.or_, o, acc.sr * inv);
+            sto<T>(a.og, o, acc.sg * inv);
+            sto<T>(a.ob, o, acc.sb * inv);
+        } else {
+            write_out<T>(a, o, acc.sr * inv, acc.sg * inv, acc.sb * inv);
+            if (WANT_VAR) stf(a.var_out, o, acc.sv * inv * inv);
+        }
+    }
+}
+
+template <typename T, int STEP, int PY, int MODE, bool WANT_VAR, int DIR, bool PERSIST>
+__global__ __launch_bounds__(256) void atrous_tile_k(AtrousArgs a, int tiles, int per_xcd) {
+    using S = TileShape<STEP, PY, DIR, WANT_VAR>;
+    __shared__ float4 s_cl[S::NS];  // r, g, b, L (L = +inf: no tap)
+    __shared__ float4 s_gn[S::NS];  // z, nx, ny, nz (z = 0: no tap)
+    __shared__ float s_v[S::NEED_V ? S::NS : 1];
+    __shared__ float2 s_pf[S::NP > 0 ? S::NP : 1];  // (var, 1) or (0, 0)
+    const int gxt = (a.w + S::TX - 1) / S::TX;
+    // this workgroup's run of tiles: its XCD's range, strided by the number
+    // of workgroups on that XCD
+    const int xcd = (int)blockIdx.x % kXCD, slot = (int)blockIdx.x / kXCD;
+    const int nslot = (int)gridDim.x / kXCD;
+    const int first = xcd * per_xcd, last = min(tiles, first + per_xcd);
+    int t = first + slot;
+    if (t >= last) return;
+    TileRegs<S::IT, S::ITP> regs;
+    tile_issue<T, S>(a, tile_origin<STEP, S::TY, S::TX>(t, gxt), regs);
+    tile_store<S>(regs, s_cl, s_gn, s_v, s_pf);
+    __syncthreads();
+    if (!PERSIST) {  // one tile per workgroup: no prefetch registers live
+        tile_compute<T, STEP, PY, MODE, WANT_VAR, DIR>(a, tile_origin<STEP, S::TY, S::TX>(t, gxt),
+                                                       s_cl, s_gn, s_v, s_pf);
+        return;
+    }
+    for (;;) {
+        const int tn = t + nslot;
+        if (tn < last) tile_issue<T, S>(a, tile_origin<STEP, S::TY, S::TX>(tn, gxt), regs);
+        tile_compute<T, STEP, PY, MODE, WANT_VAR, DIR>(a, tile_origin<STEP, S::TY, S::TX>(t, gxt),
+                                                       s_cl, s_gn, s_v, s_pf);
+        if (tn >= last) break;
+        __syncthreads();
+        tile_store<S>(regs, s_cl, s_gn, s_v, s_pf);
+        __syncthreads();
+        t = tn;
+    }
+}
+
+// ---- 5x5 level, direct loads (any step) -------------------------------------
+
+template <typename T>
+__device__ __forceinline__ void load_tap(const AtrousArgs &a, int qx, int qy, float4 &qc,
+                                         float4 &qg, float &qv) {
+    qc = make_float4(0.f, 0.f, 0.f, INFINITY);
+    qg = make_float4(0.f, 0.f, 0.f, 0.f);
+    qv = 0.f;
+    if (qx < 0 || qx >= a.w || qy < 0 || qy >= a.h) return;
+    const uint32_t q = (uint32_t)qy * (uint32_t)a.pitch + (uint32_t)qx;
+    const float zz = ldo<T>(a.z, q);
+    if (empty_px(zz)) return;
+    const float R = ldo<T>(a.cr, q), G = ldo<T>(a.cg, q), B = ldo<T>(a.cb, q);
+    qc = make_float4(R, G, B, luma(R, G, B));
+    qg = make_float4(zz, ldo<T>(a.nx, q), ldo<T>(a.ny, q), ldo<T>(a.nz, q));
+    qv = ldf(a.var, q);
+}
+
+template <typename T, int MODE, bool WANT_VAR>
+__global__ __launch_bounds__(256) void atrous_direct_k(AtrousArgs a) {
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (x >= a.w || y >= a.h) return;
+    const uint32_t o = (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x;
+    float4 pc, pg;
+    float pv;
+    load_tap<T>(a, x, y, pc, pg, pv);
+    if (pg.x == 0.f) {
+        pass_through<T>(a, o, a.cr, a.cg, a.cb);
+        return;
+    }
+    const float g = prefilter_global<T>(a, x, y);
+    const float s = (float)a.step;
+    float kz[12];
+    float kl = 0.f;
+    if (MODE != kUnit) {
+        kl = luma_scale(a, g, o);
+        const float gx = ldo<T>(a.dzdx, o) * s, gy = ldo<T>(a.dzdy, o) * s;
+#pragma unroll
+        for (int b = 0; b <= 2; ++b)
+#pragma unroll
+            for (int aa = -2; aa <= 2; ++aa) {
+                if (b == 0 && aa <= 0) continue;
+                const float den = fmaf(a.sigma_z, fabsf(fmaf(gx, (float)aa, gy * (float)b)), a.eps_z);
+                kz[kz_index(aa, b)] = kLog2e * fast_rcp(den);
+            }
+    }
+    constexpr float h00 = 0.375f * 0.375f;
+    Acc acc{h00, h00 * pc.x, h00 * pc.y, h00 * pc.z, WANT_VAR ? h00 * h00 * pv : 0.f};
+#pragma unroll
+    for (int b = -2; b <= 2; ++b)
+#pragma unroll
+        for (int aa = -2; aa <= 2; ++aa) {
+            if (aa == 0 && b == 0) continue;
+            float4 qc, qg;
+            float qv;
+            load_tap<T>(a, x + aa * a.step, y + b * a.step, qc, qg, qv);
+            tap<MODE, WANT_VAR>(acc, qc, qg, qv, kLog2H1[aa + 2] + kLog2H1[b + 2],
+                                kH1[aa + 2] * kH1[b + 2], MODE == kUnit ? 0.f : kz[kz_index(aa, b)], pg.x,
+                                pc.w, pg.y, pg.z, pg.w, kl, a.nc);
+        }
+    const float inv = 1.0f / acc.sw;
+    write_out<T>(a, o, acc.sr * inv, acc.sg * inv, acc.sb * inv);
+    if (WANT_VAR) stf(a.var_out, o, acc.sv * inv * inv);
+}
+
+// ---- separable level (Section 3.3), direct loads -------------------------------
+//
+// Horizontal pass: colour only, into the scratch planes (the args' output
+// planes).  Vertical pass: reads the scratch planes as colour (cr/cg/cb) and
+// var_in for the propagation; g comes from var_in in both.
+
+template <typename T, int MODE, bool VERTICAL, bool WANT_VAR>
+__global__ __launch_bounds__(256) void atrous_sep_k(AtrousArgs a) {
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (x >= a.w || y >= a.h) return;
+    const uint32_t o = (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x;
+    float4 pc, pg;
+    float pv;
+    load_tap<T>(a, x, y, pc, pg, pv);
+    if (pg.x == 0.f) {
+        if (VERTICAL) {
+            pass_through<T>(a, o, a.cr, a.cg, a.cb);
+        } else {
+            sto<T>(a.or_, o, ldo<T>(a.cr, o));
+            sto<T>(a.og, o, ldo<T>(a.cg, o));
+            sto<T>(a.ob, o, ldo<T>(a.cb, o));
+        }
+        return;
+    }
+    const float g = prefilter_global<T>(a, x, y);
+    const float s = (float)a.step;
+    float kz[2] = {0.f, 0.f};
+    float kl = 0.f;
+    if (MODE != kUnit) {
+        kl = luma_scale(a, g, o);
+        const float grad = ld((const T *)(VERTICAL ? a.dzdy : a.dzdx) + o) * s;
+#pragma unroll
+        for (int i = 1; i <= 2; ++i) {
+            const float den = fmaf(a.sigma_z, fabsf(grad * (float)i), a.eps_z);
+            kz[i - 1] = kLog2e * fast_rcp(den);
+        }
+    }
+    constexpr float h0 = 0.375f;
+    Acc acc{h0, h0 * pc.x, h0 * pc.y, h0 * pc.z, WANT_VAR ? h0 * h0 * pv : 0.f};
+#pragma unroll
+    for (int t = -2; t <= 2; ++t) {
+        if (t == 0) continue;
+        float4 qc, qg;
+        float qv;
+        const int qx = VERTICAL ? x : x + t * a.step, qy = VERTICAL ? y + t * a.step : y;
+        load_tap<T>(a, qx, qy, qc, qg, qv);
+        tap<MODE, WANT_VAR>(acc, qc, qg, qv, kLog2H1[t + 2], kH1[t + 2],
+                            MODE == kUnit ? 0.f : kz[(t < 0 ? -t : t) - 1], pg.x, pc.w, pg.y, pg.z, pg.w,
+                            kl, a.nc);
+    }
+    const float inv = 1.0f / acc.sw;
+    if (VERTICAL) {
+        write_out<T>(a, o, acc.sr * inv, acc.sg * inv, acc.sb * inv);
+        if (WANT_VAR) stf(a.var_out, o, acc.sv * inv * inv);
+    } else {
+        sto<T>(a.or_, o, acc.sr * inv);
+        sto<T>(a.og, o, acc.sg * inv);
+        sto<T>(a.ob, o, acc.sb * inv);
+    }
+}
+
+// ---- launch ---------------------------------------------------------------------
+
+constexpr int kCUs = 256;
+
+// Launch-time tile configuration (autotuned by the caller, or the defaults).
+struct TileCfg {
+    bool persistent;
+    int blocks_per_cu;
+};
+
+template <typename T, int STEP, int MODE, bool WANT_VAR, int DIR>
+void launch_tile(const AtrousArgs &a, TileCfg cfg, hipStream_t s) {
+    constexpr int PY = 2, TY = 4 * PY;
+    const int bands = (a.h + STEP * TY - 1) / (STEP * TY);
+    const int tiles = ((a.w + 63) / 64) * bands * STEP;
+    const int per_xcd = (tiles + kXCD - 1) / kXCD;
+    if (cfg.persistent) {
+        const int slots = min(per_xcd, kCUs / kXCD * max(1, cfg.blocks_per_cu));
+        hipLaunchKernelGGL((atrous_tile_k<T, STEP, PY, MODE, WANT_VAR, DIR, true>),
+                           dim3(slots * kXCD), dim3(256), 0, s, a, tiles, per_xcd);
+    } else {
+        hipLaunchKernelGGL((atrous_tile_k<T, STEP, PY, MODE, WANT_VAR, DIR, false>),
+                           dim3(per_xcd * kXCD), dim3(256), 0, s, a, tiles, per_xcd);
+    }
+}
+
+template <typename T, int MODE, bool WANT_VAR, int DIR>
+void launch_steps(const AtrousArgs &a, TileCfg cfg, hipStream_t s) {
+    switch (a.step) {
+    case 1: launch_tile<T, 1, MODE, WANT_VAR, DIR>(a, cfg, s); return;
+    case 2: launch_tile<T, 2, MODE, WANT_VAR, DIR>(a, cfg, s); return;
+    case 4: launch_tile<T, 4, MODE, WANT_VAR, DIR>(a, cfg, s); return;
+    case 8: launch_tile<T, 8, MODE, WANT_VAR, DIR>(a, cfg, s); return;
+    case 16: launch_tile<T, 16, MODE, WANT_VAR, DIR>(a, cfg, s); return;
+    default: {  // other steps: direct loads
+        dim3 grid((a.w + 63) / 64, (a.h + 3) / 4);
+        if (DIR == kDir2D)
+            hipLaunchKernelGGL((atrous_direct_k<T, MODE, WANT_VAR>), grid, dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((atrous_sep_k<T, MODE, DIR == kDirV, WANT_VAR>), grid, dim3(256), 0,
+                               s, a);
+    }
+    }
+}
+
+// One pass (5x5 level, or one half of a separable level) for storage type T.
+template <typename T, int DIR>
+void launch_pass(const AtrousArgs &a, bool unit, TileCfg cfg, hipStream_t s) {
+    const bool wv = a.var_out != nullptr && DIR != kDirH;
+    if (unit) {
+        if (wv) launch_steps<T, kUnit, true, DIR>(a, cfg, s);
+        else launch_steps<T, kUnit, false, DIR>(a, cfg, s);
+    } else {
+        if (wv) launch_steps<T, kWeighted, true, DIR>(a, cfg, s);
+        else launch_steps<T, kWeighted, false, DIR>(a, cfg, s);
+    }
+}
+
+// Entry points of the per-(type, direction) compilation units.
+void launch_pass_f32_2d(const AtrousArgs &a, bool unit, TileCfg cfg, hipStream_t s);
+void launch_pass_f32_h(const AtrousArgs &a, bool unit, TileCfg cfg, hipStream_t s);
+void launch_pass_f32_v(const AtrousArgs &a, bool unit, TileCfg cfg, hipStream_t s);
+void launch_pass_f16_2d(const AtrousArgs &a, bool unit, TileCfg cfg, hipStream_t s);
+void launch_pass_f16_h(const AtrousArgs &a, bool unit, TileCfg cfg, hipStream_t s);
+void launch_pass_f16_v(const AtrousArgs &a, bool unit, TileCfg cfg, hipStream_t s);
+
+}  // namespace sv

@@ -31,8 +31,8 @@ extern "C" int sv_denoise_frame(const sv_frame_in *in, sv_denoiser *st, sv_dims 
     io.alpha_map = in->alpha_map;
     int rc = sv_temporal(&io, d, t, &p->temporal, stream);
     if (rc != SV_OK) return rc;
-    rc = sv_variance(st->m1[k1], st->m2c[k1], st->n[k1], &in->g, st->var, d, t, &p->variance,
-                     stream);
+    rc = sv_variance(st->m1[k1], st->m2c[k1], st->n[k1], &in->g, st->var, st->var_work, d, t,
+                     &p->variance, stream);
     if (rc != SV_OK) return rc;
 
     sv_rgb c = io.out;
@@ -43,6 +43,8 @@ extern "C" int sv_denoise_frame(const sv_frame_in *in, sv_denoiser *st, sv_dims 
         const bool level0_is_hist = i == 0 && !fb_temporal;
         sv_atrous_params ap = p->atrous;
         ap.flags &= ~SV_A_INV_TONEMAP;
+        if (p->level_persistent[i] >= 0) ap.persistent = p->level_persistent[i];
+        if (p->level_blocks_per_cu[i] > 0) ap.blocks_per_cu = p->level_blocks_per_cu[i];
         if (tm && last && !level0_is_hist) ap.flags |= SV_A_INV_TONEMAP;
         const sv_rgb dst = level0_is_hist ? st->hist[k1] : (last ? st->out : st->level[i & 1]);
         float *dst_var = last ? nullptr : st->level_var[i & 1];

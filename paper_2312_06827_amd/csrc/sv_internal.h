@@ -68,28 +68,23 @@ constexpr float kLog2e = 1.4426950408889634f;
 // (128) would amplify that rounding into the weight, so the exact residual
 // r = (1 - s2/2) - u is added as sigma_n log2(e) r (the first-order term of
 // log(u + r) - log(u) near u = 1, where every weight that matters lies).
-enum { kNormalOff = 0, kNormalLog = 2 };
-
+// sigma_n == 0 (normal weight off) uses the same code with u floored at 1:
+// both terms are then exactly 0.
 struct NormalCoef {
-    float sn;   // sigma_n
-    float snl;  // sigma_n log2(e)
+    float sn;    // sigma_n
+    float snl;   // sigma_n log2(e)
+    float umin;  // 0, or 1 when sigma_n == 0
 };
 
 inline NormalCoef make_normal_coef(float sigma_n) {
-    return NormalCoef{sigma_n, sigma_n * 1.4426950408889634f};
+    return NormalCoef{sigma_n, sigma_n * 1.4426950408889634f, sigma_n == 0.0f ? 1.0f : 0.0f};
 }
 
-inline int normal_mode(float sigma_n) { return sigma_n == 0.0f ? kNormalOff : kNormalLog; }
-
-template <int NM>
 __device__ __forceinline__ float add_normal_term(float e, float s2, const NormalCoef &k) {
-    if (NM == kNormalLog) {
-        const float u = fmaf(-0.5f, s2, 1.0f);
-        const float r = fmaf(-0.5f, s2, 1.0f - u);  // (1 - s2/2) - u, exact for u >= 1/2
-        e = fmaf(k.sn, __builtin_amdgcn_logf(fmaxf(u, 0.0f)), e);
-        return fmaf(k.snl, r, e);
-    }
-    return e;
+    const float u = fmaf(-0.5f, s2, 1.0f);
+    const float r = fmaf(-0.5f, s2, 1.0f - u);  // (1 - s2/2) - u, exact for u >= 1/2
+    e = fmaf(k.sn, __builtin_amdgcn_logf(fmaxf(u, k.umin)), e);
+    return fmaf(k.snl, r, e);
 }
 
 __device__ __forceinline__ float chord2(float ax, float ay, float az, float bx, float by,
@@ -106,6 +101,26 @@ __device__ __forceinline__ void inv_tonemap(float &r, float &g, float &b, float 
     g = g / den;
     b = b / den;
 }
+
+// ---- XCD-aware tile order ----------------------------------------------------
+//
+// The 256 CUs sit in 8 XCDs, each with its own L2, and workgroups are handed
+// to the XCDs round-robin by workgroup index.  Tile kernels launch a 1-D
+// grid of 8 * ceil(tiles / 8) workgroups and map workgroup b to tile
+// (b % 8) * ceil(tiles / 8) + b / 8: every XCD then sweeps one contiguous
+// range of tiles in order, so the halos that neighbouring tiles share are
+// re-read from its own L2.  Returns -1 for the padding workgroups (which
+// must return before any barrier).
+constexpr int kXCD = 8;
+
+__device__ __forceinline__ int xcd_tile(int tiles) {
+    const int per = (tiles + kXCD - 1) / kXCD;
+    const int b = (int)blockIdx.x;
+    const int t = (b % kXCD) * per + b / kXCD;
+    return t < tiles ? t : -1;
+}
+
+inline unsigned xcd_grid(int tiles) { return (unsigned)(((tiles + kXCD - 1) / kXCD) * kXCD); }
 
 // ---- host-side checks -----------------------------------------------------
 

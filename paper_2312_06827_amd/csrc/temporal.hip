@@ -83,35 +83,42 @@ __device__ __forceinline__ void box_bounds(const float4 *tile, int lx, int ly, f
 template <typename T, bool TM>
 __device__ __forceinline__ void stage_current(float4 *tile, const void *cr, const void *cg,
                                               const void *cb, const void *zp, int w, int h,
-                                              int pitch, float tm_k) {
-    const int x0 = blockIdx.x * kTX - 1, y0 = blockIdx.y * kTY - 1;
-    for (int i = threadIdx.x; i < (kTX + 2) * (kTY + 2); i += 256) {
-        int r = i / (kTX + 2), c = i - r * (kTX + 2);
-        int gx = x0 + c, gy = y0 + r;
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (gx >= 0 && gx < w && gy >= 0 && gy < h) {
-            uint32_t o = (uint32_t)gy * (uint32_t)pitch + (uint32_t)gx;
-            float R = ldo<T>(cr, o), G = ldo<T>(cg, o), B = ldo<T>(cb, o);
-            if (TM) {
-                const float sc = 1.0f / (1.0f + tm_k * luma(R, G, B));
-                R *= sc;
-                G *= sc;
-                B *= sc;
-            }
-            float valid = (zp == nullptr || !empty_px(ldo<T>(zp, o))) ? 1.f : 0.f;
-            v = make_float4(R, G, B, valid);
+                                              int pitch, float tm_k, int bx, int by) {
+    // unrolled, every load issued from an in-image address (masked after)
+    const int x0 = (int)bx * kTX - 1, y0 = (int)by * kTY - 1;
+    constexpr int NS = (kTX + 2) * (kTY + 2), IT = (NS + 255) / 256;
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int i = threadIdx.x + it * 256;
+        const int r = i / (kTX + 2), c = i - r * (kTX + 2);
+        const int gx = x0 + c, gy = y0 + r;
+        const bool in = i < NS && gx >= 0 && gx < w && gy >= 0 && gy < h;
+        const uint32_t o = in ? (uint32_t)gy * (uint32_t)pitch + (uint32_t)gx : 0u;
+        float R = ldo<T>(cr, o), G = ldo<T>(cg, o), B = ldo<T>(cb, o);
+        const float zz = zp ? ldo<T>(zp, o) : 1.f;
+        if (TM) {
+            const float sc = 1.0f / (1.0f + tm_k * luma(R, G, B));
+            R *= sc;
+            G *= sc;
+            B *= sc;
         }
-        tile[i] = v;
+        if (i < NS)
+            tile[i] = in ? make_float4(R, G, B, empty_px(zz) ? 0.f : 1.f)
+                         : make_float4(0.f, 0.f, 0.f, 0.f);
     }
 }
 
 template <typename T, bool TM, bool CLAMP, bool USE_ID>
 __global__ __launch_bounds__(256) void temporal_k(TemporalArgs a) {
     __shared__ float4 tile[(kTX + 2) * (kTY + 2)];
-    stage_current<T, TM>(tile, a.cr, a.cg, a.cb, a.z, a.w, a.h, a.pitch, a.tm_k);
+    const int gxt = (a.w + kTX - 1) / kTX;
+    const int t = xcd_tile(gxt * ((a.h + kTY - 1) / kTY));
+    if (t < 0) return;
+    const int by = t / gxt, bx = t - by * gxt;
+    stage_current<T, TM>(tile, a.cr, a.cg, a.cb, a.z, a.w, a.h, a.pitch, a.tm_k, bx, by);
     __syncthreads();
     const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
-    const int x = blockIdx.x * kTX + lx, y = blockIdx.y * kTY + ly;
+    const int x = bx * kTX + lx, y = by * kTY + ly;
     if (x >= a.w || y >= a.h) return;
     const uint32_t o = (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x;
     const float4 c = tile[(ly + 1) * (kTX + 2) + lx + 1];
@@ -239,10 +246,14 @@ struct ClampArgs {
 template <typename T>
 __global__ __launch_bounds__(256) void clamp_k(ClampArgs a) {
     __shared__ float4 tile[(kTX + 2) * (kTY + 2)];
-    stage_current<T, false>(tile, a.cr, a.cg, a.cb, a.z, a.w, a.h, a.pitch, 0.f);
+    const int gxt = (a.w + kTX - 1) / kTX;
+    const int t = xcd_tile(gxt * ((a.h + kTY - 1) / kTY));
+    if (t < 0) return;
+    const int by = t / gxt, bx = t - by * gxt;
+    stage_current<T, false>(tile, a.cr, a.cg, a.cb, a.z, a.w, a.h, a.pitch, 0.f, bx, by);
     __syncthreads();
     const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
-    const int x = blockIdx.x * kTX + lx, y = blockIdx.y * kTY + ly;
+    const int x = bx * kTX + lx, y = by * kTY + ly;
     if (x >= a.w || y >= a.h) return;
     const uint32_t o = (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x;
     float r = ldo<T>(a.hr, o), g = ldo<T>(a.hg, o), b = ldo<T>(a.hb, o);
@@ -329,7 +340,7 @@ extern "C" int sv_temporal(const sv_temporal_io *io, sv_dims d, sv_dtype t,
                    io->hist_m2c, io->hist_n, io->out.r, io->out.g, io->out.b, io->out_m1,
                    io->out_m2c, io->out_n, io->alpha_map, d.w, d.h, d.pitch, p->alpha,
                    p->alpha_m, p->gamma, p->tau_z, p->tau_n, p->tm_k, p->max_hist};
-    dim3 grid((d.w + kTX - 1) / kTX, (d.h + kTY - 1) / kTY);
+    dim3 grid(xcd_grid(((d.w + kTX - 1) / kTX) * ((d.h + kTY - 1) / kTY)));
     hipStream_t s = as_stream(stream);
     if (t == SV_F32) launch_temporal<float>(a, tm, clamp, use_id, grid, s);
     else launch_temporal<half_t>(a, tm, clamp, use_id, grid, s);
@@ -356,7 +367,7 @@ extern "C" int sv_clamp(const sv_rgb *hist, const sv_rgb *cur, const sv_rgb *out
             if (overlaps(so, si)) return SV_EALIAS;
     ClampArgs a{hist->r, hist->g, hist->b, cur->r, cur->g, cur->b, z,
                 out->r, out->g, out->b, d.w, d.h, d.pitch, gamma};
-    dim3 grid((d.w + kTX - 1) / kTX, (d.h + kTY - 1) / kTY);
+    dim3 grid(xcd_grid(((d.w + kTX - 1) / kTX) * ((d.h + kTY - 1) / kTY)));
     if (t == SV_F32)
         hipLaunchKernelGGL(clamp_k<float>, grid, dim3(256), 0, as_stream(stream), a);
     else

@@ -2,165 +2,203 @@
 // moments where the history is long enough, a depth- and normal-weighted
 // spatial estimate where it is not.  The second moment arrives as the
 // central moment m2c = E[L^2] - E[L]^2, so neither branch cancels.
+//
+// Pass 1 (pointwise) writes the temporal estimate and lists the pixels
+// whose history is short; pass 2 computes the spatial estimate of the
+// listed pixels, eight lanes per pixel, spread over every CU.
 #include "sv_internal.h"
 
 namespace sv {
 
 constexpr int kVX = 64, kVY = 4;
+constexpr int kSpatialBlocks = 1024;  // pass-2 grid (grid-stride over the list)
+constexpr int kLines = 32;             // counters sit 128 bytes apart
+
+// Workspace: one counter per XCD (workgroup b runs on XCD b % 8 and appends
+// to sublist b % 8), then the eight sublists, each sized for every pixel
+// of the workgroups that feed it.
+struct VarWork {
+    uint32_t count[kXCD * kLines];  // count[k * kLines]: entries in sublist k
+    uint32_t list[1];               // sublist k at list + k * cap: (y << 15) | x
+};
+
+inline uint32_t point_grid(sv_dims d) {
+    return xcd_grid(((d.w + kVX - 1) / kVX) * ((d.h + kVY - 1) / kVY));
+}
 
 struct VarianceArgs {
     const float *m1, *m2c;
     const uint8_t *n;
     const void *z, *dzdx, *dzdy, *nx, *ny, *nz;
     float *var;
+    VarWork *work;
+    uint32_t cap;  // entries per sublist
     int w, h, pitch;
     float sigma_z, eps_z;
     NormalCoef nc;
-    int min_hist, radius;
+    int min_hist;
 };
 
-// Sum over the 64 lanes of a wavefront (butterfly: a fixed order, so the
-// result is the same on every run).
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+template <typename T>
+__global__ __launch_bounds__(256) void variance_point_k(VarianceArgs a) {
+    __shared__ uint32_t wave_n[4], base_sh;
+    const int gxt = (a.w + kVX - 1) / kVX;
+    const int tile = xcd_tile(gxt * ((a.h + kVY - 1) / kVY));
+    const int byt = tile / gxt, bxt = tile - byt * gxt;
+    const int x = bxt * kVX + (threadIdx.x & 63), y = byt * kVY + (threadIdx.x >> 6);
+    const bool inside = tile >= 0 && x < a.w && y < a.h;
+    const uint32_t o = inside ? (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x : 0u;
+    // all three loads issued together (the address is in the image)
+    const int nn = a.n[o];
+    const float zp = ldo<T>(a.z, o), m2 = ldf(a.m2c, o);
+    const int n = inside ? nn : 0;
+    const bool live = inside && n >= 1 && !empty_px(zp);
+    const bool spatial = live && n < a.min_hist;
+    if (inside && !spatial) stf(a.var, o, live ? fmaxf(0.f, m2) : 0.f);
+    // list the short-history pixels: one atomic per workgroup, on this XCD's counter
+    const uint64_t mask = __ballot(spatial);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) wave_n[wave] = (uint32_t)__popcll(mask);
+    __syncthreads();
+    const uint32_t n0 = wave_n[0], n1 = wave_n[1], n2 = wave_n[2], n3 = wave_n[3];
+    const uint32_t total = n0 + n1 + n2 + n3;
+    if (total == 0) return;  // uniform over the workgroup
+    const uint32_t k = blockIdx.x % kXCD;
+    if (threadIdx.x == 0) base_sh = atomicAdd(&a.work->count[k * kLines], total);
+    __syncthreads();
+    const uint32_t before = (wave > 0 ? n0 : 0u) + (wave > 1 ? n1 : 0u) + (wave > 2 ? n2 : 0u);
+    const uint32_t slot =
+        base_sh + before + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+    // a sublist holds every pixel of its workgroups; a workspace that was
+    // not zeroed cannot push a store past its end
+    if (spatial && slot < a.cap) a.work->list[k * a.cap + slot] = ((uint32_t)y << 15) | (uint32_t)x;
+}
+
+__global__ __launch_bounds__(64) void variance_reset_k(VarWork *w) {
+    if (threadIdx.x < kXCD) w->count[threadIdx.x * kLines] = 0;
+}
+
+// Sum over the 8 lanes of an aligned lane group (butterfly: a fixed order,
+// so the result is the same on every run).
+__device__ __forceinline__ float group8_sum(float v) {
+    v += __shfl_xor(v, 4, 64);
+    v += __shfl_xor(v, 2, 64);
+    v += __shfl_xor(v, 1, 64);
     return v;
 }
 
-// One workgroup covers 64x4 pixels.  The temporal estimate is pointwise.
-// Pixels with a short history (1 <= n < min_hist) are rare (disocclusions)
-// and scattered; instead of letting each of them hold its whole wavefront
-// through a (2R+1)^2 loop, the workgroup lists them and each wavefront takes
-// one listed pixel at a time with one window tap per lane, combining the
-// lanes by wavefront sums.  The window (tile plus an R apron) is staged in
-// LDS only when the list is not empty: m1, m2c, z, nx, ny, nz per pixel,
-// z = 0 outside the image or empty.
-template <typename T, int NM>
-__global__ __launch_bounds__(256) void variance_k(VarianceArgs a) {
-    extern __shared__ float s_win[];
-    __shared__ int s_count;
-    __shared__ int s_list[256];
-    __shared__ float s_res[256];
-    const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
-    const int x = blockIdx.x * kVX + lx, y = blockIdx.y * kVY + ly;
-    const bool inside = x < a.w && y < a.h;
-    const uint32_t o = inside ? (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x : 0;
-    int n = 0;
-    float zp = 0.f;
-    if (inside) {
-        n = a.n[o];
-        zp = ldo<T>(a.z, o);
-    }
-    const bool live = inside && n >= 1 && !empty_px(zp);
-    const bool spatial = live && n < a.min_hist;
-    float v = 0.f;
-    if (live && !spatial) v = fmaxf(0.f, ldf(a.m2c, o));
-    if (threadIdx.x == 0) s_count = 0;
-    __syncthreads();
-    if (spatial) s_list[atomicAdd(&s_count, 1)] = threadIdx.x;
-    __syncthreads();
-    const int cnt = s_count;
-    if (cnt > 0) {
-        const int R = a.radius, D = 2 * R + 1, NT = D * D;
-        const int WX = kVX + 2 * R, WY = kVY + 2 * R, NW = WX * WY;
-        float *s_m1 = s_win, *s_m2 = s_win + NW, *s_z = s_win + 2 * NW;
-        float *s_nx = s_win + 3 * NW, *s_ny = s_win + 4 * NW, *s_nz = s_win + 5 * NW;
-        const int gx0 = blockIdx.x * kVX - R, gy0 = blockIdx.y * kVY - R;
-        for (int i = threadIdx.x; i < NW; i += 256) {
-            const int r = i / WX, c = i - r * WX;
-            const int gx = gx0 + c, gy = gy0 + r;
-            float m1 = 0.f, m2 = 0.f, zz = 0.f, nx = 0.f, ny = 0.f, nz = 0.f;
-            if (gx >= 0 && gx < a.w && gy >= 0 && gy < a.h) {
-                const uint32_t q = (uint32_t)gy * (uint32_t)a.pitch + (uint32_t)gx;
-                zz = ldo<T>(a.z, q);
-                if (empty_px(zz)) zz = 0.f;
-                m1 = ldf(a.m1, q);
-                m2 = ldf(a.m2c, q);
-                nx = ldo<T>(a.nx, q);
-                ny = ldo<T>(a.ny, q);
-                nz = ldo<T>(a.nz, q);
-            }
-            s_m1[i] = m1;
-            s_m2[i] = m2;
-            s_z[i] = zz;
-            s_nx[i] = nx;
-            s_ny[i] = ny;
-            s_nz[i] = nz;
-        }
-        __syncthreads();
-        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-        for (int e = wave; e < cnt; e += 4) {
-            const int pt = s_list[e];
-            const int px = pt & 63, py = pt >> 6;
-            const uint32_t po = (uint32_t)(blockIdx.y * kVY + py) * (uint32_t)a.pitch + (uint32_t)(blockIdx.x * kVX + px);
-            const float gx = ldo<T>(a.dzdx, po), gy = ldo<T>(a.dzdy, po);
-            const int ci = (py + R) * WX + px + R;
-            const float zc = s_z[ci], nxp = s_nx[ci], nyp = s_ny[ci], nzp = s_nz[ci];
-            // pass 1: per-lane taps (lane, lane + 64, ...) then wavefront sums
-            float w[4], m1v[4];
-            float sw = 0.f, s1 = 0.f, sm = 0.f;
+// Window of radius R, eight lanes per listed pixel: lane `sub` takes taps
+// sub, sub + 8, ...  Every tap's loads are issued before any weight is
+// formed, and the weights and m1 stay in registers for the second pass.
+template <typename T, int R>
+__global__ __launch_bounds__(256) void variance_spatial_k(VarianceArgs a) {
+    constexpr int D = 2 * R + 1, NT = D * D, PER = (NT + 7) / 8, CTR = R * D + R;
+    uint32_t pre[kXCD + 1];
+    pre[0] = 0;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int t = lane + 64 * k;
-                w[k] = 0.f;
-                m1v[k] = 0.f;
-                if (t < NT) {
-                    const int dx = t % D - R, dy = t / D - R;
-                    const int qi = ci + dy * WX + dx;
-                    const float zq = s_z[qi];
-                    if (dx == 0 && dy == 0) {
-                        w[k] = 1.f;
-                    } else if (zq > 0.f) {
-                        const float den = fmaf(a.sigma_z, fabsf(fmaf(gx, (float)dx, gy * (float)dy)),
-                                               a.eps_z);
-                        float ex = -fabsf(zc - zq) * (kLog2e / den);
-                        ex = add_normal_term<NM>(
-                            ex, chord2(nxp, nyp, nzp, s_nx[qi], s_ny[qi], s_nz[qi]), a.nc);
-                        w[k] = __builtin_amdgcn_exp2f(ex);
-                    }
-                    m1v[k] = s_m1[qi];
-                    sw += w[k];
-                    s1 = fmaf(w[k], m1v[k], s1);
-                    sm = fmaf(w[k], s_m2[qi], sm);
-                }
-            }
-            sw = wave_sum(sw);
-            s1 = wave_sum(s1);
-            sm = wave_sum(sm);
-            const float mean1 = s1 / sw;
-            // pass 2: spread of m1 about its weighted mean
-            float spread = 0.f;
+    for (int k = 0; k < kXCD; ++k) pre[k + 1] = pre[k] + min(a.work->count[k * kLines], a.cap);
+    const uint32_t count = pre[kXCD];
+    const int sub = threadIdx.x & 7;
+    const uint32_t groups = gridDim.x * (blockDim.x / 8);
+    for (uint32_t e = blockIdx.x * (blockDim.x / 8) + (threadIdx.x >> 3); e < count; e += groups) {
+        int k = 0;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const float d = m1v[k] - mean1;
-                spread = fmaf(w[k] * d, d, spread);
-            }
-            spread = wave_sum(spread);
-            if (lane == 0) s_res[pt] = fmaxf(0.f, (sm + spread) / sw);
+        for (int j = 1; j < kXCD; ++j) k += e >= pre[j] ? 1 : 0;
+        const uint32_t packed = a.work->list[k * a.cap + (e - pre[k])];
+        const int x = (int)(packed & 32767u), y = (int)(packed >> 15);
+        if (x >= a.w || y >= a.h) continue;  // only a stale entry can be outside
+        const uint32_t po = (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x;
+        const float zc = ldo<T>(a.z, po), gx = ldo<T>(a.dzdx, po), gy = ldo<T>(a.dzdy, po);
+        const float nxp = ldo<T>(a.nx, po), nyp = ldo<T>(a.ny, po), nzp = ldo<T>(a.nz, po);
+        float zq[PER], qx_[PER], qy_[PER], qz_[PER], m1q[PER], m2q[PER];
+        bool ok[PER];
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int t = sub + 8 * j;
+            const int dx = t % D - R, dy = t / D - R;
+            const int qx = x + dx, qy = y + dy;
+            ok[j] = t < NT && qx >= 0 && qx < a.w && qy >= 0 && qy < a.h;
+            const uint32_t q = ok[j] ? (uint32_t)qy * (uint32_t)a.pitch + (uint32_t)qx : po;
+            zq[j] = ldo<T>(a.z, q);
+            qx_[j] = ldo<T>(a.nx, q);
+            qy_[j] = ldo<T>(a.ny, q);
+            qz_[j] = ldo<T>(a.nz, q);
+            m1q[j] = ldf(a.m1, q);
+            m2q[j] = ldf(a.m2c, q);
         }
-        __syncthreads();
-        if (spatial) v = s_res[threadIdx.x];
+        // pass 1: weights and weighted sums of m1 and m2c
+        float wt[PER];
+        float sw = 0.f, s1 = 0.f, sm = 0.f;
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int t = sub + 8 * j;
+            const int dx = t % D - R, dy = t / D - R;
+            float w;
+            if (t == CTR) {
+                w = 1.f;
+            } else {
+                const float s2 = chord2(nxp, nyp, nzp, qx_[j], qy_[j], qz_[j]);
+                const float den =
+                    fmaf(a.sigma_z, fabsf(fmaf(gx, (float)dx, gy * (float)dy)), a.eps_z);
+                float ex = -fabsf(zc - zq[j]) * (kLog2e / den);
+                ex = add_normal_term(ex, s2, a.nc);
+                w = empty_px(zq[j]) ? 0.f : __builtin_amdgcn_exp2f(ex);
+            }
+            w = ok[j] ? w : 0.f;
+            wt[j] = w;
+            if (ok[j]) {
+                sw += w;
+                s1 = fmaf(w, m1q[j], s1);
+                sm = fmaf(w, m2q[j], sm);
+            }
+        }
+        sw = group8_sum(sw);
+        s1 = group8_sum(s1);
+        sm = group8_sum(sm);
+        const float mean1 = s1 / sw;
+        // pass 2: spread of m1 about its weighted mean
+        float spread = 0.f;
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const float d = m1q[j] - mean1;
+            if (ok[j]) spread = fmaf(wt[j] * d, d, spread);
+        }
+        spread = group8_sum(spread);
+        if (sub == 0) stf(a.var, po, fmaxf(0.f, (sm + spread) / sw));
     }
-    if (inside) stf(a.var, o, v);
+}
+
+template <typename T, int R>
+void launch_spatial(const VarianceArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL((variance_spatial_k<T, R>), dim3(kSpatialBlocks), dim3(256), 0, s, a);
 }
 
 template <typename T>
-static void launch_variance(const VarianceArgs &a, int nm, dim3 grid, size_t lds,
-                            hipStream_t s) {
-    switch (nm) {
-    case kNormalOff:
-        hipLaunchKernelGGL((variance_k<T, kNormalOff>), grid, dim3(256), lds, s, a);
-        break;
-    default:
-        hipLaunchKernelGGL((variance_k<T, kNormalLog>), grid, dim3(256), lds, s, a);
+void launch_variance(const VarianceArgs &a, unsigned grid, int radius, hipStream_t s) {
+    hipLaunchKernelGGL(variance_point_k<T>, dim3(grid), dim3(256), 0, s, a);
+    switch (radius) {
+    case 0: launch_spatial<T, 0>(a, s); break;
+    case 1: launch_spatial<T, 1>(a, s); break;
+    case 2: launch_spatial<T, 2>(a, s); break;
+    case 3: launch_spatial<T, 3>(a, s); break;
+    case 4: launch_spatial<T, 4>(a, s); break;
+    case 5: launch_spatial<T, 5>(a, s); break;
+    case 6: launch_spatial<T, 6>(a, s); break;
+    default: launch_spatial<T, 7>(a, s); break;
     }
+    hipLaunchKernelGGL(variance_reset_k, dim3(1), dim3(64), 0, s, a.work);
 }
 
 }  // namespace sv
 
+extern "C" size_t sv_variance_work_bytes(sv_dims d) {
+    if (sv::check_dims(d) < 0) return 0;
+    return offsetof(sv::VarWork, list) + sizeof(uint32_t) * 256 * (size_t)sv::point_grid(d);
+}
+
 extern "C" int sv_variance(const float *m1, const float *m2c, const uint8_t *n, const sv_gbuf *g,
-                           float *var, sv_dims d, sv_dtype t, const sv_variance_params *p,
-                           sv_stream stream) {
+                           float *var, void *work, sv_dims d, sv_dtype t,
+                           const sv_variance_params *p, sv_stream stream) {
     using namespace sv;
     if (!valid_dtype(t)) return SV_EDTYPE;
     int dc = check_dims(d);
@@ -168,7 +206,8 @@ extern "C" int sv_variance(const float *m1, const float *m2c, const uint8_t *n, 
     if (p->radius < 0 || p->radius > 7 || p->min_hist < 0) return SV_EINVAL;
     if (!(p->sigma_n >= 0.f)) return SV_EINVAL;
     if (dc == 1) return SV_OK;
-    if (!m1 || !m2c || !n || !var || !g->z || !g->dzdx || !g->dzdy || !g->nx || !g->ny || !g->nz)
+    if (!m1 || !m2c || !n || !var || !work || !g->z || !g->dzdx || !g->dzdy || !g->nx || !g->ny ||
+        !g->nz)
         return SV_EINVAL;
     const size_t es = elem_size(t);
     const span ins[] = {plane_span(m1, d, 4), plane_span(m2c, d, 4), plane_span(n, d, 1),
@@ -176,15 +215,18 @@ extern "C" int sv_variance(const float *m1, const float *m2c, const uint8_t *n, 
                         plane_span(g->dzdy, d, es), plane_span(g->nx, d, es),
                         plane_span(g->ny, d, es), plane_span(g->nz, d, es)};
     const span so = plane_span(var, d, 4);
+    const span sw{(uintptr_t)work, (uintptr_t)work + sv_variance_work_bytes(d)};
     for (const span &si : ins)
-        if (overlaps(so, si)) return SV_EALIAS;
+        if (overlaps(so, si) || overlaps(sw, si)) return SV_EALIAS;
+    if (overlaps(so, sw)) return SV_EALIAS;
+    const unsigned grid = point_grid(d);
     VarianceArgs a{m1, m2c, n, g->z, g->dzdx, g->dzdy, g->nx, g->ny, g->nz, var,
-                   d.w, d.h, d.pitch, p->sigma_z, p->eps_z, make_normal_coef(p->sigma_n),
-                   p->min_hist, p->radius};
-    const size_t lds = sizeof(float) * 6 * (kVX + 2 * p->radius) * (kVY + 2 * p->radius);
-    dim3 grid((d.w + kVX - 1) / kVX, (d.h + kVY - 1) / kVY);
-    const int nm = normal_mode(p->sigma_n);
-    if (t == SV_F32) launch_variance<float>(a, nm, grid, lds, as_stream(stream));
-    else launch_variance<half_t>(a, nm, grid, lds, as_stream(stream));
+                   (VarWork *)work, (grid / kXCD) * 256u, d.w, d.h, d.pitch, p->sigma_z,
+                   p->eps_z, make_normal_coef(p->sigma_n), p->min_hist};
+    hipStream_t s = as_stream(stream);
+    if (t == SV_F32)
+        launch_variance<float>(a, grid, p->radius, s);
+    else
+        launch_variance<half_t>(a, grid, p->radius, s);
     return hip_status(hipGetLastError());
 }

@@ -73,12 +73,13 @@ class sv_atrous_params(ctypes.Structure):
     _fields_ = [("sigma_z", ctypes.c_float), ("sigma_n", ctypes.c_float),
                 ("sigma_l", ctypes.c_float), ("eps_z", ctypes.c_float),
                 ("eps_l", ctypes.c_float), ("tm_k", ctypes.c_float),
-                ("flags", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("persistent", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32)]
 
 
 class sv_denoiser(ctypes.Structure):
     _fields_ = [("hist", sv_rgb * 2), ("m1", _vp * 2), ("m2c", _vp * 2), ("n", _vp * 2),
-                ("temporal", sv_rgb), ("var", _vp), ("level", sv_rgb * 2),
+                ("temporal", sv_rgb), ("var", _vp), ("var_work", _vp), ("level", sv_rgb * 2),
                 ("level_var", _vp * 2), ("scratch", sv_rgb), ("out", sv_rgb),
                 ("cur", ctypes.c_int32)]
 
@@ -91,7 +92,9 @@ class sv_frame_in(ctypes.Structure):
 class sv_frame_params(ctypes.Structure):
     _fields_ = [("temporal", sv_temporal_params), ("variance", sv_variance_params),
                 ("atrous", sv_atrous_params), ("levels", ctypes.c_int32),
-                ("separable", ctypes.c_int32), ("feedback", ctypes.c_int32)]
+                ("separable", ctypes.c_int32), ("feedback", ctypes.c_int32),
+                ("level_persistent", ctypes.c_int32 * 10),
+                ("level_blocks_per_cu", ctypes.c_int32 * 10)]
 
 
 _P = ctypes.POINTER
@@ -102,8 +105,9 @@ EXPORTS = {
                   ctypes.c_float, _vp], ctypes.c_int),
     "sv_temporal": ([_P(sv_temporal_io), sv_dims, ctypes.c_int, _P(sv_temporal_params), _vp],
                     ctypes.c_int),
-    "sv_variance": ([_vp, _vp, _vp, _P(sv_gbuf), _vp, sv_dims, ctypes.c_int,
+    "sv_variance": ([_vp, _vp, _vp, _P(sv_gbuf), _vp, _vp, sv_dims, ctypes.c_int,
                      _P(sv_variance_params), _vp], ctypes.c_int),
+    "sv_variance_work_bytes": ([sv_dims], ctypes.c_size_t),
     "sv_atrous": ([_P(sv_rgb), _vp, _P(sv_gbuf), _vp, _P(sv_rgb), _vp, ctypes.c_int32,
                    sv_dims, ctypes.c_int, _P(sv_atrous_params), _vp], ctypes.c_int),
     "sv_atrous_sep": ([_P(sv_rgb), _vp, _P(sv_gbuf), _vp, _P(sv_rgb), _P(sv_rgb), _vp,
@@ -259,12 +263,15 @@ class AtrousParams:
     tm_k: float = 1.0
     unit_weights: bool = False
     inv_tonemap: bool = False
+    persistent: int = -1      # launch shape: -1 default, 0 / 1
+    blocks_per_cu: int = 0    # persistent workgroups per CU, 0 default
 
     def c(self) -> sv_atrous_params:
         flags = ((SV_A_UNIT_WEIGHTS if self.unit_weights else 0)
                  | (SV_A_INV_TONEMAP if self.inv_tonemap else 0))
         return sv_atrous_params(self.sigma_z, self.sigma_n, self.sigma_l, self.eps_z,
-                                self.eps_l, self.tm_k, flags)
+                                self.eps_l, self.tm_k, flags, self.persistent,
+                                self.blocks_per_cu)
 
 
 # ---- the calls ------------------------------------------------------------------
@@ -302,13 +309,24 @@ def sv_temporal(cur: Planes, g: GBuf, mv: Planes, prev: GBuf, hist: Planes,
                                              ctypes.byref(pc), _stream(stream)))
 
 
+def variance_workspace(like: torch.Tensor) -> torch.Tensor:
+    """A zeroed device workspace for sv_variance on planes shaped like `like`."""
+    nbytes = load().sv_variance_work_bytes(dims_of(like))
+    if nbytes == 0:
+        raise ValueError("invalid dimensions")
+    return torch.zeros((nbytes + 3) // 4, dtype=torch.int32, device=like.device)
+
+
 def sv_variance(m1: torch.Tensor, m2c: torch.Tensor, n: torch.Tensor, g: GBuf,
-                var: torch.Tensor, params: VarianceParams, stream=None):
+                var: torch.Tensor, params: VarianceParams, work: torch.Tensor, stream=None):
+    """`work`: a workspace from variance_workspace() (zeroed; stays zeroed)."""
     gc = g.c()
     pc = params.c()
+    if work.numel() * work.element_size() < load().sv_variance_work_bytes(dims_of(m1)):
+        raise ValueError("variance workspace too small")
     _check("sv_variance", load().sv_variance(
         _plane_ptr(m1), _plane_ptr(m2c), _plane_ptr(n), ctypes.byref(gc), _plane_ptr(var),
-        dims_of(m1), dtype_of(g.z), ctypes.byref(pc), _stream(stream)))
+        work.data_ptr(), dims_of(m1), dtype_of(g.z), ctypes.byref(pc), _stream(stream)))
 
 
 def sv_atrous(c_in: Planes, var_in: torch.Tensor, g: GBuf, c_out: Planes,

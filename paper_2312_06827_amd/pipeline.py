@@ -14,6 +14,7 @@ frame never writes what it reads.
 from __future__ import annotations
 
 import contextlib
+import ctypes
 from dataclasses import dataclass
 from typing import Callable, Dict, Optional
 
@@ -59,12 +60,17 @@ class FilterConfig:
         return AtrousParams(self.sigma_z, self.sigma_n, self.sigma_l, self.eps_z, self.eps_l,
                             self.tm_k, False, inv_tonemap)
 
-    def frame_params(self) -> lib.sv_frame_params:
+    def frame_params(self, tiles=None) -> lib.sv_frame_params:
+        """`tiles`: optional per-level (persistent, blocks_per_cu) launch shapes."""
         if self.feedback not in ("atrous0", "temporal"):
             raise ValueError(f"unknown feedback {self.feedback!r}")
+        lp = (ctypes.c_int32 * 10)(*([-1] * 10))
+        lb = (ctypes.c_int32 * 10)(*([0] * 10))
+        for i, (per, bpc) in enumerate((tiles or [])[:10]):
+            lp[i], lb[i] = per, bpc
         return lib.sv_frame_params(self.temporal().c(), self.variance().c(), self.atrous().c(),
                                    self.levels, int(self.separable),
-                                   1 if self.feedback == "temporal" else 0)
+                                   1 if self.feedback == "temporal" else 0, lp, lb)
 
 
 # The filter settings of the workloads: plain (static camera) and the
@@ -108,7 +114,7 @@ class FrameInputs:
 
 class Denoiser:
     def __init__(self, height: int, width: int, cfg: FilterConfig = PLAIN,
-                 dtype: torch.dtype = torch.float32, device: str = "cuda"):
+                 dtype: torch.dtype = torch.float32, device: str = "cuda", tiles=None):
         lib.load()
         self.H, self.W, self.cfg, self.dtype = height, width, cfg, dtype
         dev = torch.device(device)
@@ -121,6 +127,7 @@ class Denoiser:
         self.n = [u8(), u8()]
         self.t_rgb = [rgb()]  # temporal output (the history itself under "temporal" feedback)
         self.var = f32()
+        self.var_work = lib.variance_workspace(self.var)
         self.lvl = [rgb(), rgb()]
         self.lvl_var = [f32(), f32()]
         self.scratch = rgb() if cfg.separable else None
@@ -134,13 +141,14 @@ class Denoiser:
             (lib._vp * 2)(*[t.data_ptr() for t in self.m1]),
             (lib._vp * 2)(*[t.data_ptr() for t in self.m2c]),
             (lib._vp * 2)(*[t.data_ptr() for t in self.n]),
-            R(self.t_rgb[0]), self.var.data_ptr(),
+            R(self.t_rgb[0]), self.var.data_ptr(), self.var_work.data_ptr(),
             (lib.sv_rgb * 2)(R(self.lvl[0]), R(self.lvl[1])),
             (lib._vp * 2)(*[t.data_ptr() for t in self.lvl_var]),
             scratch, R(self.out), 0)
         self._dims = lib.dims_of(self.out)
         self._dtype = lib.dtype_of(self.out)
-        self._params = cfg.frame_params()
+        self.tiles = tiles
+        self._params = cfg.frame_params(tiles)
 
     @property
     def k(self) -> int:
@@ -186,7 +194,7 @@ class Denoiser:
                             cfg.temporal(), alpha_map=alpha_map, stream=stream)
         with tm("variance"):
             lib.sv_variance(self.m1[k1], self.m2c[k1], self.n[k1], inp.g, self.var,
-                            cfg.variance(), stream=stream)
+                            cfg.variance(), self.var_work, stream=stream)
         c, v = t_out, self.var
         L = cfg.levels
         for i in range(L):
@@ -200,6 +208,8 @@ class Denoiser:
                 dst = self.lvl[i % 2]
             dst_var = None if last else self.lvl_var[i % 2]
             p = cfg.atrous(inv_tonemap=fuse_inv)
+            if self.tiles and i < len(self.tiles):
+                p.persistent, p.blocks_per_cu = self.tiles[i]
             if cfg.separable:
                 with tm(f"atrous_sep{i}"):
                     lib.sv_atrous_sep(c, v, inp.g, self.scratch, dst, dst_var, 1 << i, p,

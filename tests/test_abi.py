@@ -60,7 +60,7 @@ def gbuf(base):
 
 D = L.sv_dims(64, 32, 64)
 TM = L.sv_tm_params(1.0, 1.0, L.SV_TM_LUMA)
-AP = L.sv_atrous_params(1.0, 128.0, 4.0, 1e-10, 1e-10, 1.0, 0)
+AP = L.sv_atrous_params(1.0, 128.0, 4.0, 1e-10, 1e-10, 1.0, 0, -1, 0)
 
 
 def test_tonemap_validation(so):
@@ -108,7 +108,7 @@ def test_atrous_validation_and_aliasing(so):
                             r(AP), None) == L.SV_EINVAL
     assert so.sv_atrous_sep(r(rgb(A)), var, r(g), None, r(rgb(B)), r(rgb(B)), None, 1, D,
                             L.SV_F32, r(AP), None) == L.SV_EALIAS
-    bad = L.sv_atrous_params(1.0, -1.0, 4.0, 1e-10, 1e-10, 1.0, 0)
+    bad = L.sv_atrous_params(1.0, -1.0, 4.0, 1e-10, 1e-10, 1.0, 0, -1, 0)
     assert so.sv_atrous(r(rgb(A)), var, r(g), None, r(rgb(B)), None, 1, D, L.SV_F32, r(bad),
                         None) == L.SV_EINVAL
 
@@ -132,11 +132,18 @@ def test_temporal_and_variance_validation(so):
     assert so.sv_temporal(r(io), D, L.SV_F32, r(p_id), None) == L.SV_EINVAL
     vp = L.sv_variance_params(1.0, 128.0, 1e-10, 4, 8)
     g = gbuf(base[3])
-    assert so.sv_variance(base[30], base[31], base[32], r(g), base[33], D, L.SV_F32, r(vp),
-                          None) == L.SV_EINVAL
+    assert so.sv_variance(base[30], base[31], base[32], r(g), base[33], base[34], D, L.SV_F32,
+                          r(vp), None) == L.SV_EINVAL
     vp = L.sv_variance_params(1.0, 128.0, 1e-10, 4, 3)
-    assert so.sv_variance(base[30], base[31], base[32], r(g), base[30], D, L.SV_F32, r(vp),
-                          None) == L.SV_EALIAS
+    assert so.sv_variance(base[30], base[31], base[32], r(g), base[30], base[34], D, L.SV_F32,
+                          r(vp), None) == L.SV_EALIAS
+    # the workspace must not overlap an input
+    assert so.sv_variance(base[30], base[31], base[32], r(g), base[33], base[31], D, L.SV_F32,
+                          r(vp), None) == L.SV_EALIAS
+    assert so.sv_variance(base[30], base[31], base[32], r(g), base[33], None, D, L.SV_F32,
+                          r(vp), None) == L.SV_EINVAL
+    assert so.sv_variance_work_bytes(D) == 1024 + 4 * 256 * 8  # 64x32: 8 tiles of 64x4
+    assert so.sv_variance_work_bytes(L.sv_dims(-1, 2, 2)) == 0
 
 
 def test_probe_copy_validation(so):

@@ -187,8 +187,14 @@ def test_variance(H, W):
     for sigma_n in (128.0, 16.0, 0.0):
         say(f"variance {H}x{W} sigma_n={sigma_n}")
         out = empty_like_dev((H, W), W + 2)
+        work = L.variance_workspace(out)
         L.sv_variance(dev(m1, W + 2), dev(m2c, W + 2), dev(hn, W + 2, torch.uint8),
-                      gbuf_dev(z, dzdx, dzdy, n, W + 2), out, L.VarianceParams(sigma_n=sigma_n))
+                      gbuf_dev(z, dzdx, dzdy, n, W + 2), out, L.VarianceParams(sigma_n=sigma_n),
+                      work)
+        L.sv_variance(dev(m1, W + 2), dev(m2c, W + 2), dev(hn, W + 2, torch.uint8),
+                      gbuf_dev(z, dzdx, dzdy, n, W + 2), out, L.VarianceParams(sigma_n=sigma_n),
+                      work)  # a second call: the workspace is back to zero
+        assert int(work[:256].abs().sum().item()) == 0  # the eight counters
         ref = O.variance(m1, m2, hn, z, dzdx, dzdy, n, sigma_n=sigma_n)
         assert rel_err(host(out), ref) <= TOL32
 
@@ -271,3 +277,31 @@ def test_atrous_sep(H, W, step):
         assert rel_err(host(out), rc) <= TOL32
         if want_var:
             assert rel_err(host(vo), rv) <= TOL32
+
+
+@pytest.mark.parametrize("sep", [False, True])
+def test_atrous_launch_shape_does_not_change_results(sep):
+    """Persistent or not, any workgroups per CU: bitwise identical output."""
+    from paper_2312_06827_amd.autotune import CANDIDATES
+    H, W = 300, 450
+    c, var, z, dzdx, dzdy, n = _atrous_inputs(H, W, 700)
+    g = gbuf_dev(z, dzdx, dzdy, n)
+    cd, vd = dev(c), dev(var)
+    for step in (1, 2, 16):
+        ref = None
+        for per, bpc in CANDIDATES:
+            say(f"launch shape sep={sep} step={step} persistent={per} bpc={bpc}")
+            out, vo, sh = empty_like_dev((3, H, W)), empty_like_dev((H, W)), empty_like_dev((3, H, W))
+            p = L.AtrousParams(persistent=per, blocks_per_cu=bpc)
+            if sep:
+                L.sv_atrous_sep(cd, vd, g, sh, out, vo, step, p)
+            else:
+                L.sv_atrous(cd, vd, g, out, vo, step, p)
+            got = (host(out), host(vo))
+            if ref is None:
+                ref = got
+                rc, rv = (O.atrous_sep if sep else O.atrous)(c, var, z, dzdx, dzdy, n, step)[:2]
+                assert rel_err(got[0], rc) <= TOL32 and rel_err(got[1], rv) <= TOL32
+            else:
+                np.testing.assert_array_equal(got[0], ref[0])
+                np.testing.assert_array_equal(got[1], ref[1])
