@@ -32,7 +32,13 @@ if ROOT not in sys.path:
 from paper_2312_06827_amd.scene import CONFIGS, render_frame  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+# VALU issue rate with packed FP32 off: 256 CUs x 4 SIMDs x 16 lanes x
+# 2.4 GHz = 39.3 T lane-operations per second (a transcendental takes four
+# issue slots).  The published 157.3 TFLOP/s counts an FMA as two flops and
+# packed (two-wide) FP32 issue, which this library does not generate.
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 WORKLOAD = CONFIGS["hd_motion"]
+PROFILES = os.path.join(ROOT, "profiles")
 
 # Algorithmic bytes per pixel (each input plane read once, each output
 # written once), binary32 storage, ids on.
@@ -52,6 +58,53 @@ BYTES_PER_PX = {
 }
 
 
+# Algorithmic VALU slots per output pixel of one a-trous level (FP32 ops
+# of the level's definition, one slot each, a transcendental four).  Per
+# non-centre tap: depth term 2, luminance term 2, normal term 12 (chord 6,
+# max + log2 + scale 6), exp2 4, accumulation 6 (Σw, three colour FMAs,
+# w² var).  Per pixel: 3x3 variance prefilter 23, luminance scale 11, the
+# 12 distinct depth scales 84, own luminance 3, centre tap 5, normalisation
+# 9.  The separable level: 4 horizontal taps without the variance term
+# (24 each) plus 62 per pixel, and 4 vertical taps (26 each) plus 65.
+ALU_OPS_PER_PX = {"atrous": 24 * 26 + 135, "atrous_sep": 4 * 24 + 62 + 4 * 26 + 65}
+
+# Source files that make up the 2D a-trous kernel; PMC traffic measured on
+# them is reported only while they are unchanged.
+ATROUS_SOURCES = ("paper_2312_06827_amd/csrc/atrous_impl.h",
+                  "paper_2312_06827_amd/csrc/atrous_f32_2d.hip",
+                  "paper_2312_06827_amd/csrc/atrous.hip",
+                  "paper_2312_06827_amd/csrc/sv_internal.h")
+TRAFFIC_FILE = os.path.join(PROFILES, "atrous2d_f32_1920x1080_pmc_traffic.txt")
+
+
+def source_digest(paths) -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for rel in paths:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(rel.encode() + b"\0" + f.read() + b"\0")
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per a-trous launch (mean over the five levels) from the
+    committed PMC summary, or None if it is missing or the kernel sources
+    changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            kv = dict(l.split(":", 1) for l in f.read().splitlines() if ":" in l and not
+                      l.startswith(("#", " ")))
+    except OSError:
+        return None
+    if kv.get("kernel_source_sha256", "").strip() != source_digest(ATROUS_SOURCES):
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch_mean"])
+    except (KeyError, ValueError):
+        return None
+
+
 def frame_bytes_per_px(levels: int, sep: bool) -> int:
     a, al = ("atrous_sep", "atrous_sep_last") if sep else ("atrous", "atrous_last")
     return (BYTES_PER_PX["temporal"] + BYTES_PER_PX["variance"]
@@ -65,6 +118,8 @@ def _render(args):
 
 def generate(cfg, n_frames, workers):
     cfg = type(cfg)(**{**cfg.__dict__, "frames": n_frames})
+    if workers <= 1:
+        return [render_frame(cfg, f) for f in range(n_frames)]
     ctx = mp.get_context("fork")
     with cf.ProcessPoolExecutor(max_workers=workers, mp_context=ctx) as ex:
         return list(ex.map(_render, [(cfg, f) for f in range(n_frames)]))
@@ -169,6 +224,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--tune", action="store_true",
+                    help="a-trous launch shapes from the autotuner (timed before the run)"
+                         " instead of the library defaults")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     args = ap.parse_args()
     if args.gpus != 1:
@@ -191,8 +249,11 @@ def main():
 
     # launch shapes of the a-trous levels, measured on this device and size
     from paper_2312_06827_amd.autotune import tiles_for
-    tiles_2d = tiles_for(H, W, separable=False, cache=None)
-    tiles_sep = tiles_for(H, W, separable=True, cache=None)
+    if not args.tune:
+        tiles_2d = tiles_sep = None
+    else:
+        tiles_2d = tiles_for(H, W, separable=False, cache=None)
+        tiles_sep = tiles_for(H, W, separable=True, cache=None)
     print(f"# tuned launch shapes 2d {tiles_2d} sep {tiles_sep}", file=sys.stderr, flush=True)
     # a throwaway pass warms clocks, code objects and allocator
     run_chain(torch, frames_dev, MOTION, H, W, 2, min(8, args.steps), per_kernel=False,
@@ -207,16 +268,26 @@ def main():
     _, _, ktimes = run_chain(torch, frames_dev, MOTION, H, W, args.warmup, args.steps,
                              per_kernel=True, tiles=tiles_2d)
 
-    # roofline of the dominant kernel: the a-trous levels
+    # roofline of the dominant kernel: the 5x5 a-trous level (VALU-bound;
+    # its HBM figures are reported beside)
     npx = W * H
     lv = [k for k in ktimes if k.startswith("atrous")]
+    launches = sum(ktimes[k][1] for k in lv)
+    tot_ms = sum(ktimes[k][0] * ktimes[k][1] for k in lv)
+    mean_us = tot_ms / launches * 1e3
     tot_bytes = sum(ktimes[k][1] * npx * BYTES_PER_PX["atrous_last" if k.endswith("4") else "atrous"]
                     for k in lv)
-    tot_ms = sum(ktimes[k][0] * ktimes[k][1] for k in lv)
-    achieved = tot_bytes / (tot_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "atrous (5x5 level, mean over the five levels)"}
+    achieved = npx * ALU_OPS_PER_PX["atrous"] / (mean_us * 1e-6) / 1e12
+    hbm_gbs = tot_bytes / (tot_ms * 1e-3) / 1e9
+    roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": round(VALU_PEAK_TOPS, 2),
+                "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
+                "traffic": measured_traffic(),
+                "kernel": "atrous 5x5 level (mean over the five levels)",
+                "ops_per_px": ALU_OPS_PER_PX["atrous"], "px_per_launch": npx,
+                "launch_us": round(mean_us, 2),
+                "algorithmic_bytes_per_launch": round(tot_bytes / launches),
+                "hbm_achieved_gbs": round(hbm_gbs, 1),
+                "hbm_frac": round(hbm_gbs / HBM_PEAK_GBS, 4)}
     per_kernel = {k: {"us": round(v[0] * 1e3, 2), "launches": v[1]} for k, v in sorted(ktimes.items())}
 
     variants = {}

@@ -227,7 +227,8 @@ typedef struct {
     float tm_k;    /* tone-map multiplier for SV_A_INV_TONEMAP, default 1 */
     int32_t flags; /* SV_A_* */
     /* Launch shape of the LDS-tiled kernels (results do not depend on it):
-     * persistent: -1 library default, 0 one tile per workgroup, 1 each
+     * persistent: -1 library default (one tile per workgroup), 0 one tile
+     * per workgroup, 1 each
      * workgroup loops over tiles and prefetches the next one;
      * blocks_per_cu: workgroups per CU of a persistent launch (0 default). */
     int32_t persistent;
@@ -265,6 +266,104 @@ int sv_atrous_sep(const sv_rgb *c_in, const float *var_in, const sv_gbuf *g,
                   const sv_rgb *c_out, float *var_out, int32_t step,
                   sv_dims d, sv_dtype t, const sv_atrous_params *p,
                   sv_stream stream);
+
+/* ---- learned blend factor and edge scale ------------------------------
+ *
+ * Not in the paper, which blends with one fixed alpha and filters with one
+ * fixed sigma_l (Section 2).  A per-pixel network predicts both:
+ *
+ *   x (14 features) -> 32 -> ReLU -> 32 -> ReLU -> (o1, o2)
+ *   alpha = 0.05 + 0.95 sigmoid(o1)      (colour blend factor, sv_temporal
+ *                                          alpha_map; the 1/n floor still
+ *                                          applies)
+ *   kappa = 2^(2 tanh(o2))               (sigma_l scale, sv_atrous kappa)
+ *
+ * Features, from the temporal step's own intermediates: luminance of the
+ * current (tone-mapped) colour; luminance of the reprojected, clamped
+ * history (0 without history); its reprojected central second moment (0
+ * without history); the population variance of the current luminance over
+ * the in-image, non-empty 3x3 neighbourhood; new history length / 255;
+ * dz/dx; dz/dy; the normal (3); motion length (0 where the motion is
+ * discarded); albedo (3).  Empty pixels have all-zero raw features.  Each
+ * is standardised as (x - mu) * inv_s in binary32 and stored as bfloat16
+ * (round to nearest even): one row of 16 values per pixel (the last two
+ * zero), row index y * w + x, no pitch.
+ *
+ * Parameters, flat binary32 vector of SV_MLP_PARAMS in this order: W1
+ * (32 x 14, row-major [out][in]), b1 (32), W2 (32 x 32), b2 (32), W3 (2 x 32),
+ * b3 (2).  Matrix products take their operands as bfloat16 (weights from
+ * the bfloat16 mirror `wq` of the flat vector, activations and, in the
+ * backward pass, the incoming gradients rounded to nearest even) and
+ * accumulate in binary32; biases are binary32. */
+#define SV_MLP_IN 14
+#define SV_MLP_HIDDEN 32
+#define SV_MLP_PARAMS 1602
+
+typedef struct {
+    const float *params;    /* SV_MLP_PARAMS binary32 (biases read here) */
+    const uint16_t *wq;     /* SV_MLP_PARAMS bfloat16 mirror (matrices read here) */
+    const float *mu;        /* 14 feature means */
+    const float *inv_s;     /* 14 inverse feature scales */
+} sv_mlp;
+
+/* Feature rows for sv_mlp_forward / sv_mlp_backward.  `io` supplies the
+ * current frame, G-buffer (dzdx, dzdy required), motion, previous G-buffer
+ * and history exactly as for sv_temporal with the same `p`; its outputs
+ * and alpha_map are ignored.  `feat` receives w*h rows of 16 bfloat16
+ * (32 bytes each, 16-byte aligned).  `hist_out` (optional, binary32 planes
+ * with the call's pitch) receives the clamped reprojected history colour,
+ * 0 where there is no history: the blend's other operand, needed by
+ * sv_mlp_alpha_grad. */
+int sv_mlp_features(const sv_temporal_io *io, const sv_rgb *albedo, const sv_mlp *w,
+                    void *feat, const sv_rgb *hist_out, sv_dims d, sv_dtype t,
+                    const sv_temporal_params *p, sv_stream stream);
+
+/* Network forward over the w*h feature rows: alpha and kappa as binary32
+ * planes with the pitch of d (either may be NULL). */
+int sv_mlp_forward(const sv_mlp *w, const void *feat, float *alpha, float *kappa,
+                   sv_dims d, sv_stream stream);
+
+/* Gradient of L = sum over pixels of (d_alpha * alpha + d_kappa * kappa)
+ * (binary32 planes with the pitch of d: dL/dalpha and dL/dkappa per pixel)
+ * with respect to every parameter, times `scale`, written to `grad`
+ * (SV_MLP_PARAMS binary32, flat order).  The forward pass is recomputed.
+ * `work`: device buffer of sv_mlp_backward_work_bytes(d) bytes (per-wave
+ * partial sums, reduced in a fixed order, so the result is deterministic). */
+int sv_mlp_backward(const sv_mlp *w, const void *feat, const float *d_alpha,
+                    const float *d_kappa, float scale, float *grad, void *work,
+                    sv_dims d, sv_stream stream);
+size_t sv_mlp_backward_work_bytes(sv_dims d);
+
+typedef struct {
+    float lr, beta1, beta2, eps; /* defaults 1e-3, 0.9, 0.999, 1e-8 */
+} sv_adam_params;
+
+/* One Adam step over n binary32 parameters (t counts from 1): m, v and the
+ * master `params` are updated in place, and `wq` (optional) receives the
+ * bfloat16 mirror of the new parameters. */
+int sv_adam(float *params, uint16_t *wq, float *m, float *v, const float *grad, int32_t n,
+            int32_t t, const sv_adam_params *p, sv_stream stream);
+
+/* dL/dalpha per pixel for L = sum over pixels of the per-pixel RelMSE term
+ * (1/3) sum_c (c_t - y)^2 / (y^2 + 0.01) of the temporal output against the
+ * target, with the history held fixed: c_t = (1 - a) hist + a cur, a =
+ * max(alpha, 1/n).  Zero where 1/n wins or the pixel is empty.  c_t: the
+ * temporal output (storage type); cur: the current colour, tone mapped
+ * here if tm_k > 0; hist: sv_mlp_features' hist_out; y: target colour
+ * (binary32, in the space of c_t); n: the new history length. */
+int sv_mlp_alpha_grad(const sv_rgb *c_t, const sv_rgb *cur, const sv_rgb *hist,
+                      const sv_rgb *y, const float *alpha, const uint8_t *n, const void *z,
+                      float tm_k, float *d_alpha, sv_dims d, sv_dtype t, sv_stream stream);
+
+/* Adds to d_kappa the derivative of the same per-pixel RelMSE term of one
+ * 5x5 a-trous level's colour output c' against y with respect to kappa(p),
+ * the level input held fixed:
+ * dc'/dkappa = sum H (dw/dkappa) (c(q) - c') / sum H w, where only the
+ * luminance weight depends on kappa.  Arguments as sv_atrous (no outputs;
+ * p's flags other than the sigmas and epsilons are ignored). */
+int sv_atrous_kappa_grad(const sv_rgb *c_in, const float *var_in, const sv_gbuf *g,
+                         const float *kappa, const sv_rgb *y, float *d_kappa, int32_t step,
+                         sv_dims d, sv_dtype t, const sv_atrous_params *p, sv_stream stream);
 
 /* ---- one frame of the whole filter (Section 3, steps 4 and 5) --------- */
 

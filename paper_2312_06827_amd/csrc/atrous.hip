@@ -45,11 +45,11 @@ static int check_atrous(const sv_rgb *c_in, const float *var_in, const sv_gbuf *
 }
 
 static TileCfg tile_cfg(const sv_atrous_params *p, int dir) {
-    // default: persistent workgroups everywhere but the 5x5 level at step 1,
-    // which is arithmetic-bound and runs best at full occupancy
-    TileCfg c{true, 4};
-    if (p->persistent == 0) c.persistent = false;
-    else if (p->persistent < 0) c.persistent = true;
+    // default: one tile per workgroup, which measured fastest (or within
+    // noise of the persistent forms) for every level at 1080p; callers pick
+    // the persistent form through the params (the autotuner does)
+    TileCfg c{false, 4};
+    if (p->persistent > 0) c.persistent = true;
     if (p->blocks_per_cu > 0) c.blocks_per_cu = p->blocks_per_cu;
     (void)dir;
     return c;
@@ -89,7 +89,6 @@ extern "C" int sv_atrous(const sv_rgb *c_in, const float *var_in, const sv_gbuf 
     AtrousArgs a = make_args(c_in, var_in, g, kappa, c_out, var_out, step, d, p);
     const bool unit = (p->flags & SV_A_UNIT_WEIGHTS) != 0;
     TileCfg cfg = tile_cfg(p, kDir2D);
-    if (p->persistent < 0 && step == 1) cfg.persistent = false;
     run_pass(a, t, kDir2D, unit, cfg, as_stream(stream));
     return hip_status(hipGetLastError());
 }

@@ -1,0 +1,619 @@
+// Learned blend factor and edge scale: a 14 -> 32 -> 32 -> 2 per-pixel
+// network on the matrix cores (bfloat16 operands, binary32 accumulation),
+// its backward pass, Adam, and the two truncated loss gradients that train
+// it (through the temporal blend and through each a-trous level).
+//
+// Matrix layout.  Each layer is computed transposed, Y^T = W X^T, with
+// v_mfma_f32_32x32x8_bf16: A = the weights (32 output units x 8 inputs per
+// instruction), B = 32 pixels x 8 inputs.  Lane l supplies A[l % 32][4 (l/32)
+// + 0..3] and B[4 (l/32) + 0..3][l % 32] of each 8-wide K block and receives
+// D[8 (r/4) + 4 (l/32) + r % 4][l % 32] in accumulator r = 0..15.  So after a
+// layer, accumulators 4 kb .. 4 kb + 3 of a lane are exactly that lane's B
+// operand for K block kb of the next layer: activations never leave
+// registers in the forward pass.
+#include "sv_internal.h"
+
+namespace sv {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kOffW1 = 0, kOffB1 = 448, kOffW2 = 480, kOffB2 = 1504, kOffW3 = 1536,
+              kOffB3 = 1600;
+static_assert(kOffB3 + 2 == SV_MLP_PARAMS, "parameter layout");
+constexpr float kAlphaMin = 0.05f;
+
+__device__ __forceinline__ uint16_t to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float from_bf16(uint16_t h) {
+    return __uint_as_float((uint32_t)h << 16);
+}
+
+__device__ __forceinline__ f32x16 mfma(bf16x4 a, bf16x4 b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// Output unit (row of D) held in accumulator r by a lane of half `hf`.
+__device__ __forceinline__ int drow(int r, int hf) { return 8 * (r >> 2) + 4 * hf + (r & 3); }
+
+struct MlpArgs {
+    const float *params;
+    const uint16_t *wq;
+    const uint4 *feat;  // 2 x 16 bytes per pixel
+    float *alpha, *kappa;
+    const float *d_alpha, *d_kappa;
+    float *part;  // backward: per-wave partial gradients
+    int w, h, pitch;
+    int npix, nblk;  // pixels, 32-pixel blocks
+};
+
+// Weights one lane holds for the forward pass.
+struct FwdW {
+    bf16x4 w1[2], w2[4];
+    float w3a[16], w3b[16];  // W3 rows 0 and 1 at this lane's units (bf16 values)
+    float b3a, b3b;
+};
+
+__device__ __forceinline__ void load_fwd(const MlpArgs &a, int col, int hf, FwdW &f) {
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int k = 8 * kb + 4 * hf + i;
+            f.w1[kb][i] = (short)(k < SV_MLP_IN ? a.wq[kOffW1 + col * SV_MLP_IN + k] : 0);
+        }
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            f.w2[kb][i] = (short)a.wq[kOffW2 + col * SV_MLP_HIDDEN + 8 * kb + 4 * hf + i];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        f.w3a[r] = from_bf16(a.wq[kOffW3 + drow(r, hf)]);
+        f.w3b[r] = from_bf16(a.wq[kOffW3 + SV_MLP_HIDDEN + drow(r, hf)]);
+    }
+    f.b3a = a.params[kOffB3];
+    f.b3b = a.params[kOffB3 + 1];
+}
+
+// Forward pass of one 32-pixel block.  x: this lane's B operands of layer
+// 1; returns the layer-1 and layer-2 pre-activations (with biases), the
+// bfloat16 layer-2 activations as floats, and the two outputs (the same in
+// both halves of the wave).
+struct FwdOut {
+    f32x16 a1, a2;
+    bf16x4 h1[4];
+    float h2[16];
+    float o0, o1;
+};
+
+__device__ __forceinline__ void forward_block(const MlpArgs &a, const FwdW &f, const bf16x4 (&x)[2],
+                                              int hf, FwdOut &r) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) r.a1[i] = a.params[kOffB1 + drow(i, hf)];
+    r.a1 = mfma(f.w1[0], x[0], r.a1);
+    r.a1 = mfma(f.w1[1], x[1], r.a1);
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) r.h1[kb][i] = (short)to_bf16(fmaxf(r.a1[4 * kb + i], 0.f));
+#pragma unroll
+    for (int i = 0; i < 16; ++i) r.a2[i] = a.params[kOffB2 + drow(i, hf)];
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) r.a2 = mfma(f.w2[kb], r.h1[kb], r.a2);
+    float o0 = 0.f, o1 = 0.f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        r.h2[i] = from_bf16(to_bf16(fmaxf(r.a2[i], 0.f)));
+        o0 = fmaf(f.w3a[i], r.h2[i], o0);
+        o1 = fmaf(f.w3b[i], r.h2[i], o1);
+    }
+    o0 += __shfl_xor(o0, 32, 64);
+    o1 += __shfl_xor(o1, 32, 64);
+    r.o0 = o0 + f.b3a;
+    r.o1 = o1 + f.b3b;
+}
+
+__device__ __forceinline__ void load_x(const MlpArgs &a, int p, int hf, bf16x4 (&x)[2]) {
+    // features 8 kb + 4 hf .. + 3 of pixel p: 8 bytes inside its 32-byte row
+    const uint2 *row = (const uint2 *)(a.feat + 2 * (size_t)p);
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb) {
+        const uint2 v = row[2 * kb + hf];
+        x[kb][0] = (short)(v.x & 0xFFFFu);
+        x[kb][1] = (short)(v.x >> 16);
+        x[kb][2] = (short)(v.y & 0xFFFFu);
+        x[kb][3] = (short)(v.y >> 16);
+    }
+}
+
+__device__ __forceinline__ uint32_t plane_off(const MlpArgs &a, int p) {
+    const int y = p / a.w, x = p - y * a.w;
+    return (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x;
+}
+
+__global__ __launch_bounds__(256) void mlp_forward_k(MlpArgs a) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 31, hf = lane >> 5;
+    FwdW f;
+    load_fwd(a, col, hf, f);
+    for (int blk = blockIdx.x * 4 + wave; blk < a.nblk; blk += gridDim.x * 4) {
+        const int p = blk * 32 + col;
+        const bool valid = p < a.npix;
+        bf16x4 x[2];
+        load_x(a, valid ? p : a.npix - 1, hf, x);
+        FwdOut r;
+        forward_block(a, f, x, hf, r);
+        if (valid && hf == 0) {
+            const uint32_t o = plane_off(a, p);
+            if (a.alpha) a.alpha[o] = kAlphaMin + (1.0f - kAlphaMin) / (1.0f + expf(-r.o0));
+            if (a.kappa) a.kappa[o] = exp2f(2.0f * tanhf(r.o1));
+        }
+    }
+}
+
+// ---- backward ------------------------------------------------------------
+
+constexpr int kTP = 36;  // LDS tile row pitch in bfloat16 (32 + 4: fewer bank conflicts)
+
+// Sum over the 32 lanes of one half-wave (butterfly, fixed order).
+__device__ __forceinline__ float half_sum(float v) {
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    v += __shfl_xor(v, 4, 64);
+    v += __shfl_xor(v, 8, 64);
+    v += __shfl_xor(v, 16, 64);
+    return v;
+}
+
+__device__ __forceinline__ bf16x4 tile_read(const uint16_t *t, int row, int k0) {
+    const uint2 v = *(const uint2 *)(t + row * kTP + k0);
+    bf16x4 r;
+    r[0] = (short)(v.x & 0xFFFFu);
+    r[1] = (short)(v.x >> 16);
+    r[2] = (short)(v.y & 0xFFFFu);
+    r[3] = (short)(v.y >> 16);
+    return r;
+}
+
+// Every wave of a workgroup runs the same number of iterations (a wave
+// whose block is past the end works on an empty block), so the workgroup
+// barriers around the LDS transposes are uniform.
+__global__ __launch_bounds__(256) void mlp_backward_k(MlpArgs a) {
+    // per wave: tiles [unit or feature][pixel] of g_h2, h1, g_h1, x
+    __shared__ __align__(16) uint16_t lds[4][4][32 * kTP];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 31, hf = lane >> 5;
+    uint16_t *t_gh2 = lds[wave][0], *t_h1 = lds[wave][1], *t_gh1 = lds[wave][2],
+             *t_x = lds[wave][3];
+    // rows 16..31 of the x tile stay zero: the feature dimension is padded
+    for (int i = lane; i < 32 * kTP; i += 64) t_x[i] = 0;
+    FwdW f;
+    load_fwd(a, col, hf, f);
+    bf16x4 w2t[4];  // A operand of W2^T: [h1 unit = col][h2 unit]
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            w2t[kb][i] = (short)a.wq[kOffW2 + (8 * kb + 4 * hf + i) * SV_MLP_HIDDEN + col];
+    f32x16 dw1, dw2;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        dw1[i] = 0.f;
+        dw2[i] = 0.f;
+    }
+    float dw3a[16], dw3b[16], db1[16], db2[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) dw3a[i] = dw3b[i] = db1[i] = db2[i] = 0.f;
+    float db3a = 0.f, db3b = 0.f;
+    const int stride = gridDim.x * 4;
+    for (int base = blockIdx.x * 4; base < a.nblk; base += stride) {
+        const int blk = base + wave;
+        const int p = blk * 32 + col;
+        const bool valid = blk < a.nblk && p < a.npix;
+        bf16x4 x[2];
+        load_x(a, valid ? p : 0, hf, x);
+        FwdOut r;
+        forward_block(a, f, x, hf, r);
+        // gradients of the outputs
+        float da = 0.f, dk = 0.f;
+        if (valid) {
+            const uint32_t o = plane_off(a, p);
+            da = a.d_alpha ? a.d_alpha[o] : 0.f;
+            dk = a.d_kappa ? a.d_kappa[o] : 0.f;
+        }
+        const float sg = 1.0f / (1.0f + expf(-r.o0));
+        const float th = tanhf(r.o1);
+        const float kap = exp2f(2.0f * th);
+        const float g0 = da * (1.0f - kAlphaMin) * sg * (1.0f - sg);
+        const float g1 = dk * kap * 0.69314718055994531f * 2.0f * (1.0f - th * th);
+        const float g0q = from_bf16(to_bf16(g0)), g1q = from_bf16(to_bf16(g1));
+        if (hf == 0) {
+            db3a += g0;
+            db3b += g1;
+        }
+        // layer 3 and the gradient reaching layer 2
+        float gh2[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            dw3a[i] = fmaf(g0q, r.h2[i], dw3a[i]);
+            dw3b[i] = fmaf(g1q, r.h2[i], dw3b[i]);
+            gh2[i] = r.a2[i] > 0.f ? fmaf(f.w3a[i], g0q, f.w3b[i] * g1q) : 0.f;
+            db2[i] += gh2[i];
+        }
+        bf16x4 gb[4];
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) gb[kb][i] = (short)to_bf16(gh2[4 * kb + i]);
+        // gradient reaching layer 1: W2^T g_h2, masked by a1 > 0
+        f32x16 g1acc;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) g1acc[i] = 0.f;
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) g1acc = mfma(w2t[kb], gb[kb], g1acc);
+        float gh1[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            gh1[i] = r.a1[i] > 0.f ? g1acc[i] : 0.f;
+            db1[i] += gh1[i];
+        }
+        // transposes for the weight gradients (contractions over pixels)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int u = drow(i, hf);
+            t_gh2[u * kTP + col] = (uint16_t)gb[i >> 2][i & 3];
+            t_h1[u * kTP + col] = (uint16_t)r.h1[i >> 2][i & 3];
+            t_gh1[u * kTP + col] = to_bf16(gh1[i]);
+        }
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) t_x[(8 * kb + 4 * hf + i) * kTP + col] = (uint16_t)x[kb][i];
+        __syncthreads();
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) {
+            const int k0 = 8 * kb + 4 * hf;
+            dw2 = mfma(tile_read(t_gh2, col, k0), tile_read(t_h1, col, k0), dw2);
+            dw1 = mfma(tile_read(t_gh1, col, k0), tile_read(t_x, col, k0), dw1);
+        }
+        __syncthreads();
+    }
+    // this wave's partial gradient, flat order
+    float *out = a.part + (size_t)(blockIdx.x * 4 + wave) * SV_MLP_PARAMS;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int u = drow(i, hf);
+        out[kOffW2 + u * SV_MLP_HIDDEN + col] = dw2[i];
+        if (col < SV_MLP_IN) out[kOffW1 + u * SV_MLP_IN + col] = dw1[i];
+        const float s3a = half_sum(dw3a[i]), s3b = half_sum(dw3b[i]);
+        const float s1 = half_sum(db1[i]), s2 = half_sum(db2[i]);
+        if (col == 0) {
+            out[kOffW3 + u] = s3a;
+            out[kOffW3 + SV_MLP_HIDDEN + u] = s3b;
+            out[kOffB1 + u] = s1;
+            out[kOffB2 + u] = s2;
+        }
+    }
+    db3a = half_sum(db3a);
+    db3b = half_sum(db3b);
+    db3a += __shfl_xor(db3a, 32, 64);
+    db3b += __shfl_xor(db3b, 32, 64);
+    if (lane == 0) {
+        out[kOffB3] = db3a;
+        out[kOffB3 + 1] = db3b;
+    }
+}
+
+__global__ __launch_bounds__(256) void mlp_reduce_k(const float *part, int nw, float scale,
+                                                    float *grad) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= SV_MLP_PARAMS) return;
+    float s = 0.f;
+    for (int w = 0; w < nw; ++w) s += part[(size_t)w * SV_MLP_PARAMS + j];
+    grad[j] = s * scale;
+}
+
+__global__ __launch_bounds__(256) void adam_k(float *params, uint16_t *wq, float *m, float *v,
+                                              const float *g, int n, float lr, float b1, float b2,
+                                              float eps, float c1, float c2) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const float gj = g[j];
+    const float mj = fmaf(b1, m[j], (1.0f - b1) * gj);
+    const float vj = fmaf(b2, v[j], (1.0f - b2) * gj * gj);
+    m[j] = mj;
+    v[j] = vj;
+    const float pj = params[j] - lr * (mj / c1) / (sqrtf(vj / c2) + eps);
+    params[j] = pj;
+    if (wq) wq[j] = to_bf16(pj);
+}
+
+// ---- truncated loss gradients ---------------------------------------------
+
+struct AlphaGradArgs {
+    const void *ctr, *ctg, *ctb, *cr, *cg, *cb;
+    const float *hr, *hg, *hb, *yr, *yg, *yb, *alpha;
+    const uint8_t *n;
+    const void *z;
+    float *d_alpha;
+    int w, h, pitch;
+    float tm_k;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void alpha_grad_k(AlphaGradArgs a) {
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63), y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (x >= a.w || y >= a.h) return;
+    const uint32_t o = (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x;
+    const int n = a.n[o];
+    float g = 0.f;
+    if (!empty_px(ldo<T>(a.z, o)) && n >= 1 && a.alpha[o] >= 1.0f / (float)n) {
+        float c[3] = {ldo<T>(a.cr, o), ldo<T>(a.cg, o), ldo<T>(a.cb, o)};
+        if (a.tm_k > 0.f) {
+            const float sc = 1.0f / (1.0f + a.tm_k * luma(c[0], c[1], c[2]));
+            c[0] *= sc;
+            c[1] *= sc;
+            c[2] *= sc;
+        }
+        const float ct[3] = {ldo<T>(a.ctr, o), ldo<T>(a.ctg, o), ldo<T>(a.ctb, o)};
+        const float hh[3] = {ldf(a.hr, o), ldf(a.hg, o), ldf(a.hb, o)};
+        const float yy[3] = {ldf(a.yr, o), ldf(a.yg, o), ldf(a.yb, o)};
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            g = fmaf((ct[k] - yy[k]) / fmaf(yy[k], yy[k], 0.01f), c[k] - hh[k], g);
+        g *= 2.0f / 3.0f;
+    }
+    a.d_alpha[o] = g;
+}
+
+struct KappaGradArgs {
+    const void *cr, *cg, *cb;
+    const float *var;
+    const void *z, *dzdx, *dzdy, *nx, *ny, *nz;
+    const float *kappa;
+    const float *yr, *yg, *yb;
+    float *d_kappa;
+    int w, h, pitch, step;
+    float sigma_z, sigma_n, sigma_l, eps_z, eps_l;
+};
+
+// One pixel per thread, taps read directly (the training pass, not the
+// measured path).
+template <typename T>
+__global__ __launch_bounds__(256) void kappa_grad_k(KappaGradArgs a) {
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63), y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (x >= a.w || y >= a.h) return;
+    const uint32_t o = (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x;
+    const float zp = ldo<T>(a.z, o);
+    if (empty_px(zp)) return;
+    // 3x3 Gaussian of the variance, in-image taps renormalised
+    float gs = 0.f, gw = 0.f;
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int qx = x + dx, qy = y + dy;
+            if (qx < 0 || qx >= a.w || qy < 0 || qy >= a.h) continue;
+            const float k = (dx == 0 ? 0.5f : 0.25f) * (dy == 0 ? 0.5f : 0.25f);
+            gs = fmaf(k, ldf(a.var, (uint32_t)qy * (uint32_t)a.pitch + (uint32_t)qx), gs);
+            gw += k;
+        }
+    const float sg = sqrtf(gs / gw);
+    const float dl = fmaf(a.sigma_l * ldf(a.kappa, o), sg, a.eps_l);
+    const float cp[3] = {ldo<T>(a.cr, o), ldo<T>(a.cg, o), ldo<T>(a.cb, o)};
+    const float lp = luma(cp[0], cp[1], cp[2]);
+    const float gx = ldo<T>(a.dzdx, o), gy = ldo<T>(a.dzdy, o);
+    const float nxp = ldo<T>(a.nx, o), nyp = ldo<T>(a.ny, o), nzp = ldo<T>(a.nz, o);
+    const float h1[5] = {1.f / 16, 4.f / 16, 6.f / 16, 4.f / 16, 1.f / 16};
+    float sw = 0.f, sd = 0.f, sc[3] = {0.f, 0.f, 0.f}, sdc[3] = {0.f, 0.f, 0.f};
+    for (int b = -2; b <= 2; ++b)
+        for (int aa = -2; aa <= 2; ++aa) {
+            const int qx = x + aa * a.step, qy = y + b * a.step;
+            if (qx < 0 || qx >= a.w || qy < 0 || qy >= a.h) continue;
+            const uint32_t q = (uint32_t)qy * (uint32_t)a.pitch + (uint32_t)qx;
+            const float hh = h1[aa + 2] * h1[b + 2];
+            const float cq[3] = {ldo<T>(a.cr, q), ldo<T>(a.cg, q), ldo<T>(a.cb, q)};
+            float w = 1.f, d = 0.f;
+            if (aa != 0 || b != 0) {
+                const float zq = ldo<T>(a.z, q);
+                if (empty_px(zq)) continue;
+                const float den = fmaf(a.sigma_z,
+                                       fabsf(fmaf(gx, (float)(a.step * aa), gy * (float)(a.step * b))),
+                                       a.eps_z);
+                const float wz = expf(-fabsf(zp - zq) / den);
+                const float ch = chord2(nxp, nyp, nzp, ldo<T>(a.nx, q), ldo<T>(a.ny, q),
+                                        ldo<T>(a.nz, q));
+                const float wn = a.sigma_n == 0.f ? 1.f : powf(fmaxf(0.f, fmaf(-0.5f, ch, 1.f)), a.sigma_n);
+                const float adl = fabsf(lp - luma(cq[0], cq[1], cq[2]));
+                w = wz * wn * expf(-adl / dl);
+                d = w * adl * a.sigma_l * sg / (dl * dl);
+            }
+            sw = fmaf(hh, w, sw);
+            sd = fmaf(hh, d, sd);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                sc[k] = fmaf(hh * w, cq[k], sc[k]);
+                sdc[k] = fmaf(hh * d, cq[k], sdc[k]);
+            }
+        }
+    const float yy[3] = {ldf(a.yr, o), ldf(a.yg, o), ldf(a.yb, o)};
+    float g = 0.f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const float out = sc[k] / sw;
+        const float der = (sdc[k] - out * sd) / sw;
+        g = fmaf((out - yy[k]) / fmaf(yy[k], yy[k], 0.01f), der, g);
+    }
+    a.d_kappa[o] += g * (2.0f / 3.0f);
+}
+
+inline unsigned mlp_grid(int nblk) {
+    const int wgs = (nblk + 3) / 4;
+    return (unsigned)std::max(1, std::min(wgs, 256 * 8));
+}
+
+inline bool valid_mlp(const sv_mlp *w) { return w && w->params && w->wq; }
+
+}  // namespace sv
+
+extern "C" int sv_mlp_forward(const sv_mlp *w, const void *feat, float *alpha, float *kappa,
+                              sv_dims d, sv_stream stream) {
+    using namespace sv;
+    const int dc = check_dims(d);
+    if (dc < 0 || !valid_mlp(w)) return SV_EINVAL;
+    if (dc == 1) return SV_OK;
+    if (!feat || ((uintptr_t)feat & 15u)) return SV_EINVAL;
+    const span fs{(uintptr_t)feat, (uintptr_t)feat + (size_t)d.w * (size_t)d.h * 32u};
+    if ((alpha && overlaps(plane_span(alpha, d, 4), fs)) ||
+        (kappa && overlaps(plane_span(kappa, d, 4), fs)) ||
+        (alpha && kappa && overlaps(plane_span(alpha, d, 4), plane_span(kappa, d, 4))))
+        return SV_EALIAS;
+    MlpArgs a{};
+    a.params = w->params;
+    a.wq = w->wq;
+    a.feat = (const uint4 *)feat;
+    a.alpha = alpha;
+    a.kappa = kappa;
+    a.w = d.w;
+    a.h = d.h;
+    a.pitch = d.pitch;
+    a.npix = d.w * d.h;
+    a.nblk = (a.npix + 31) / 32;
+    hipLaunchKernelGGL(mlp_forward_k, dim3(mlp_grid(a.nblk)), dim3(256), 0, as_stream(stream), a);
+    return hip_status(hipGetLastError());
+}
+
+extern "C" size_t sv_mlp_backward_work_bytes(sv_dims d) {
+    using namespace sv;
+    if (check_dims(d) < 0) return 0;
+    const int nblk = (d.w * d.h + 31) / 32;
+    return (size_t)mlp_grid(nblk) * 4u * SV_MLP_PARAMS * sizeof(float);
+}
+
+extern "C" int sv_mlp_backward(const sv_mlp *w, const void *feat, const float *d_alpha,
+                               const float *d_kappa, float scale, float *grad, void *work,
+                               sv_dims d, sv_stream stream) {
+    using namespace sv;
+    const int dc = check_dims(d);
+    if (dc < 0 || !valid_mlp(w) || !grad) return SV_EINVAL;
+    if (dc == 1) {  // no pixels: a zero gradient (a fill kernel, not a memset node)
+        hipLaunchKernelGGL(mlp_reduce_k, dim3((SV_MLP_PARAMS + 255) / 256), dim3(256), 0,
+                           as_stream(stream), (const float *)nullptr, 0, 0.f, grad);
+        return hip_status(hipGetLastError());
+    }
+    if (!feat || ((uintptr_t)feat & 15u) || !work) return SV_EINVAL;
+    MlpArgs a{};
+    a.params = w->params;
+    a.wq = w->wq;
+    a.feat = (const uint4 *)feat;
+    a.d_alpha = d_alpha;
+    a.d_kappa = d_kappa;
+    a.part = (float *)work;
+    a.w = d.w;
+    a.h = d.h;
+    a.pitch = d.pitch;
+    a.npix = d.w * d.h;
+    a.nblk = (a.npix + 31) / 32;
+    const span ws{(uintptr_t)work, (uintptr_t)work + sv_mlp_backward_work_bytes(d)};
+    const span gs{(uintptr_t)grad, (uintptr_t)grad + SV_MLP_PARAMS * sizeof(float)};
+    const span fs{(uintptr_t)feat, (uintptr_t)feat + (size_t)d.w * (size_t)d.h * 32u};
+    if (overlaps(ws, gs) || overlaps(ws, fs) || overlaps(gs, fs) ||
+        (d_alpha && (overlaps(ws, plane_span(d_alpha, d, 4)) || overlaps(gs, plane_span(d_alpha, d, 4)))) ||
+        (d_kappa && (overlaps(ws, plane_span(d_kappa, d, 4)) || overlaps(gs, plane_span(d_kappa, d, 4)))))
+        return SV_EALIAS;
+    const unsigned grid = mlp_grid(a.nblk);
+    hipStream_t s = as_stream(stream);
+    hipLaunchKernelGGL(mlp_backward_k, dim3(grid), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(mlp_reduce_k, dim3((SV_MLP_PARAMS + 255) / 256), dim3(256), 0, s,
+                       (const float *)work, (int)grid * 4, scale, grad);
+    return hip_status(hipGetLastError());
+}
+
+extern "C" int sv_adam(float *params, uint16_t *wq, float *m, float *v, const float *grad,
+                       int32_t n, int32_t t, const sv_adam_params *p, sv_stream stream) {
+    using namespace sv;
+    if (!params || !m || !v || !grad || !p || n < 0 || t < 1) return SV_EINVAL;
+    if (n == 0) return SV_OK;
+    const float c1 = 1.0f - powf(p->beta1, (float)t), c2 = 1.0f - powf(p->beta2, (float)t);
+    hipLaunchKernelGGL(adam_k, dim3((n + 255) / 256), dim3(256), 0, as_stream(stream), params, wq,
+                       m, v, grad, n, p->lr, p->beta1, p->beta2, p->eps, c1, c2);
+    return hip_status(hipGetLastError());
+}
+
+extern "C" int sv_mlp_alpha_grad(const sv_rgb *c_t, const sv_rgb *cur, const sv_rgb *hist,
+                                 const sv_rgb *y, const float *alpha, const uint8_t *n,
+                                 const void *z, float tm_k, float *d_alpha, sv_dims d, sv_dtype t,
+                                 sv_stream stream) {
+    using namespace sv;
+    if (!valid_dtype(t)) return SV_EDTYPE;
+    const int dc = check_dims(d);
+    if (dc < 0 || !c_t || !cur || !hist || !y) return SV_EINVAL;
+    if (dc == 1) return SV_OK;
+    const void *req[] = {c_t->r, c_t->g, c_t->b, cur->r, cur->g, cur->b, hist->r, hist->g,
+                         hist->b, y->r, y->g, y->b, alpha, n, z, d_alpha};
+    for (const void *q : req)
+        if (!q) return SV_EINVAL;
+    const size_t es = elem_size(t);
+    const span so = plane_span(d_alpha, d, 4);
+    const span ins[] = {plane_span(c_t->r, d, es), plane_span(c_t->g, d, es),
+                        plane_span(c_t->b, d, es), plane_span(cur->r, d, es),
+                        plane_span(cur->g, d, es), plane_span(cur->b, d, es),
+                        plane_span(hist->r, d, 4), plane_span(hist->g, d, 4),
+                        plane_span(hist->b, d, 4), plane_span(y->r, d, 4),
+                        plane_span(y->g, d, 4), plane_span(y->b, d, 4),
+                        plane_span(alpha, d, 4), plane_span(n, d, 1), plane_span(z, d, es)};
+    for (const span &si : ins)
+        if (overlaps(so, si)) return SV_EALIAS;
+    AlphaGradArgs a{c_t->r, c_t->g, c_t->b, cur->r, cur->g, cur->b,
+                    (const float *)hist->r, (const float *)hist->g, (const float *)hist->b,
+                    (const float *)y->r, (const float *)y->g, (const float *)y->b, alpha, n, z,
+                    d_alpha, d.w, d.h, d.pitch, tm_k};
+    dim3 grid((d.w + 63) / 64, (d.h + 3) / 4);
+    if (t == SV_F32)
+        hipLaunchKernelGGL(alpha_grad_k<float>, grid, dim3(256), 0, as_stream(stream), a);
+    else
+        hipLaunchKernelGGL(alpha_grad_k<half_t>, grid, dim3(256), 0, as_stream(stream), a);
+    return hip_status(hipGetLastError());
+}
+
+extern "C" int sv_atrous_kappa_grad(const sv_rgb *c_in, const float *var_in, const sv_gbuf *g,
+                                    const float *kappa, const sv_rgb *y, float *d_kappa,
+                                    int32_t step, sv_dims d, sv_dtype t,
+                                    const sv_atrous_params *p, sv_stream stream) {
+    using namespace sv;
+    if (!valid_dtype(t)) return SV_EDTYPE;
+    const int dc = check_dims(d);
+    if (dc < 0 || !c_in || !g || !y || !p || step < 1 || step > kMaxDim) return SV_EINVAL;
+    if (dc == 1) return SV_OK;
+    const void *req[] = {c_in->r, c_in->g, c_in->b, var_in, g->z, g->dzdx, g->dzdy, g->nx,
+                         g->ny, g->nz, kappa, y->r, y->g, y->b, d_kappa};
+    for (const void *q : req)
+        if (!q) return SV_EINVAL;
+    if (!(p->sigma_n >= 0.f)) return SV_EINVAL;
+    const size_t es = elem_size(t);
+    const span so = plane_span(d_kappa, d, 4);
+    const span ins[] = {plane_span(c_in->r, d, es), plane_span(c_in->g, d, es),
+                        plane_span(c_in->b, d, es), plane_span(var_in, d, 4),
+                        plane_span(g->z, d, es), plane_span(g->dzdx, d, es),
+                        plane_span(g->dzdy, d, es), plane_span(g->nx, d, es),
+                        plane_span(g->ny, d, es), plane_span(g->nz, d, es),
+                        plane_span(kappa, d, 4), plane_span(y->r, d, 4),
+                        plane_span(y->g, d, 4), plane_span(y->b, d, 4)};
+    for (const span &si : ins)
+        if (overlaps(so, si)) return SV_EALIAS;
+    KappaGradArgs a{c_in->r, c_in->g, c_in->b, var_in, g->z, g->dzdx, g->dzdy, g->nx, g->ny,
+                    g->nz, kappa, (const float *)y->r, (const float *)y->g, (const float *)y->b,
+                    d_kappa, d.w, d.h, d.pitch, step, p->sigma_z, p->sigma_n, p->sigma_l,
+                    p->eps_z, p->eps_l};
+    dim3 grid((d.w + 63) / 64, (d.h + 3) / 4);
+    if (t == SV_F32)
+        hipLaunchKernelGGL(kappa_grad_k<float>, grid, dim3(256), 0, as_stream(stream), a);
+    else
+        hipLaunchKernelGGL(kappa_grad_k<half_t>, grid, dim3(256), 0, as_stream(stream), a);
+    return hip_status(hipGetLastError());
+}

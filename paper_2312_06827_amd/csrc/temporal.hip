@@ -26,6 +26,11 @@ struct TemporalArgs {
     int w, h, pitch;
     float alpha, alpha_m, gamma, tau_z, tau_n, tm_k;
     int max_hist;
+    // feature mode only
+    const void *dzdx, *dzdy, *alr, *alg, *alb;
+    uint4 *feat;              // two 16-byte halves per pixel, row y * w + x
+    float *fhr, *fhg, *fhb;   // clamped reprojected history (optional)
+    const float *mu, *inv_s;  // standardisation
 };
 
 // binary32 decisions, operation order fixed and never contracted.
@@ -108,7 +113,53 @@ __device__ __forceinline__ void stage_current(float4 *tile, const void *cr, cons
     }
 }
 
-template <typename T, bool TM, bool CLAMP, bool USE_ID>
+// Population variance of the luminance over the valid entries of the 3x3
+// box around (lx+1, ly+1) (two passes, binary32).
+__device__ __forceinline__ float box_luma_var(const float4 *tile, int lx, int ly) {
+    float s = 0.f, cnt = 0.f, L[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const float4 q = tile[(ly + i / 3) * (kTX + 2) + lx + i % 3];
+        L[i] = luma(q.x, q.y, q.z);
+        s = q.w > 0.f ? s + L[i] : s;
+        cnt += q.w;
+    }
+    const float m = s / cnt;
+    float v = 0.f;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const float4 q = tile[(ly + i / 3) * (kTX + 2) + lx + i % 3];
+        const float d = L[i] - m;
+        v = q.w > 0.f ? fmaf(d, d, v) : v;
+    }
+    return v / cnt;
+}
+
+__device__ __forceinline__ uint32_t bf16_bits(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+    return u >> 16;
+}
+
+// Standardise the 14 raw features, round to bfloat16 and store the pixel's
+// 32-byte row (two zero pads at the end).
+__device__ __forceinline__ void store_features(const TemporalArgs &a, int x, int y,
+                                               const float (&f)[SV_MLP_IN]) {
+    uint32_t pk[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int k0 = 2 * i, k1 = 2 * i + 1;
+        // features 14 and 15 are the zero pads
+        const uint32_t lo = k0 < SV_MLP_IN ? bf16_bits((f[k0] - a.mu[k0]) * a.inv_s[k0]) : 0u;
+        const uint32_t hi = k1 < SV_MLP_IN ? bf16_bits((f[k1] - a.mu[k1]) * a.inv_s[k1]) : 0u;
+        pk[i] = lo | (hi << 16);
+    }
+    uint4 *row = a.feat + 2 * ((size_t)y * (size_t)a.w + (size_t)x);
+    row[0] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
+    row[1] = make_uint4(pk[4], pk[5], pk[6], pk[7]);
+}
+
+template <typename T, bool TM, bool CLAMP, bool USE_ID, bool FEAT>
 __global__ __launch_bounds__(256) void temporal_k(TemporalArgs a) {
     __shared__ float4 tile[(kTX + 2) * (kTY + 2)];
     const int gxt = (a.w + kTX - 1) / kTX;
@@ -124,6 +175,18 @@ __global__ __launch_bounds__(256) void temporal_k(TemporalArgs a) {
     const float4 c = tile[(ly + 1) * (kTX + 2) + lx + 1];
     const float L = luma(c.x, c.y, c.z);
     const float zc = ldo<T>(a.z, o);
+    if (FEAT && empty_px(zc)) {
+        float f[SV_MLP_IN];
+#pragma unroll
+        for (int i = 0; i < SV_MLP_IN; ++i) f[i] = 0.f;
+        store_features(a, x, y, f);
+        if (a.fhr) {
+            stf(a.fhr, o, 0.f);
+            stf(a.fhg, o, 0.f);
+            stf(a.fhb, o, 0.f);
+        }
+        return;
+    }
     if (empty_px(zc)) {
         sto<T>(a.or_, o, c.x);
         sto<T>(a.og, o, c.y);
@@ -186,6 +249,19 @@ __global__ __launch_bounds__(256) void temporal_k(TemporalArgs a) {
     const bool any = ok[0] || ok[1] || ok[2] || ok[3];
     float outr, outg, outb, m1, m2c;
     int n;
+    if (FEAT && !any) {
+        float f[SV_MLP_IN] = {L, 0.f, 0.f, box_luma_var(tile, lx, ly), 1.0f / 255.0f,
+                              ldo<T>(a.dzdx, o), ldo<T>(a.dzdy, o), nxc, nyc, nzc,
+                              mv_ok ? sqrtf(fmaf(mvy, mvy, mvx * mvx)) : 0.f,
+                              ldo<T>(a.alr, o), ldo<T>(a.alg, o), ldo<T>(a.alb, o)};
+        store_features(a, x, y, f);
+        if (a.fhr) {
+            stf(a.fhr, o, 0.f);
+            stf(a.fhg, o, 0.f);
+            stf(a.fhb, o, 0.f);
+        }
+        return;
+    }
     if (!any) {
         outr = c.x;
         outg = c.y;
@@ -213,6 +289,20 @@ __global__ __launch_bounds__(256) void temporal_k(TemporalArgs a) {
             hr = fminf(fmaxf(hr, lo.x), hi.x);
             hg = fminf(fmaxf(hg, lo.y), hi.y);
             hb = fminf(fmaxf(hb, lo.z), hi.z);
+        }
+        if (FEAT) {
+            float f[SV_MLP_IN] = {L, luma(hr, hg, hb), fmaxf(hm2c, 0.f), box_luma_var(tile, lx, ly),
+                                  (float)min(nmax + 1, a.max_hist) / 255.0f,
+                                  ldo<T>(a.dzdx, o), ldo<T>(a.dzdy, o), nxc, nyc, nzc,
+                                  mv_ok ? sqrtf(fmaf(mvy, mvy, mvx * mvx)) : 0.f,
+                                  ldo<T>(a.alr, o), ldo<T>(a.alg, o), ldo<T>(a.alb, o)};
+            store_features(a, x, y, f);
+            if (a.fhr) {
+                stf(a.fhr, o, hr);
+                stf(a.fhg, o, hg);
+                stf(a.fhb, o, hb);
+            }
+            return;
         }
         // ---- accumulation ----
         n = min(nmax + 1, a.max_hist);
@@ -270,23 +360,23 @@ __global__ __launch_bounds__(256) void clamp_k(ClampArgs a) {
     sto<T>(a.ob, o, b);
 }
 
-template <typename T, bool TM, bool CLAMP>
+template <typename T, bool TM, bool CLAMP, bool FEAT>
 static void launch_temporal_id(const TemporalArgs &a, bool use_id, dim3 grid, hipStream_t s) {
     if (use_id)
-        hipLaunchKernelGGL((temporal_k<T, TM, CLAMP, true>), grid, dim3(256), 0, s, a);
+        hipLaunchKernelGGL((temporal_k<T, TM, CLAMP, true, FEAT>), grid, dim3(256), 0, s, a);
     else
-        hipLaunchKernelGGL((temporal_k<T, TM, CLAMP, false>), grid, dim3(256), 0, s, a);
+        hipLaunchKernelGGL((temporal_k<T, TM, CLAMP, false, FEAT>), grid, dim3(256), 0, s, a);
 }
 
-template <typename T>
+template <typename T, bool FEAT>
 static void launch_temporal(const TemporalArgs &a, bool tm, bool clamp, bool use_id, dim3 grid,
                             hipStream_t s) {
     if (tm) {
-        if (clamp) launch_temporal_id<T, true, true>(a, use_id, grid, s);
-        else launch_temporal_id<T, true, false>(a, use_id, grid, s);
+        if (clamp) launch_temporal_id<T, true, true, FEAT>(a, use_id, grid, s);
+        else launch_temporal_id<T, true, false, FEAT>(a, use_id, grid, s);
     } else {
-        if (clamp) launch_temporal_id<T, false, true>(a, use_id, grid, s);
-        else launch_temporal_id<T, false, false>(a, use_id, grid, s);
+        if (clamp) launch_temporal_id<T, false, true, FEAT>(a, use_id, grid, s);
+        else launch_temporal_id<T, false, false, FEAT>(a, use_id, grid, s);
     }
 }
 
@@ -342,8 +432,75 @@ extern "C" int sv_temporal(const sv_temporal_io *io, sv_dims d, sv_dtype t,
                    p->alpha_m, p->gamma, p->tau_z, p->tau_n, p->tm_k, p->max_hist};
     dim3 grid(xcd_grid(((d.w + kTX - 1) / kTX) * ((d.h + kTY - 1) / kTY)));
     hipStream_t s = as_stream(stream);
-    if (t == SV_F32) launch_temporal<float>(a, tm, clamp, use_id, grid, s);
-    else launch_temporal<half_t>(a, tm, clamp, use_id, grid, s);
+    if (t == SV_F32) launch_temporal<float, false>(a, tm, clamp, use_id, grid, s);
+    else launch_temporal<half_t, false>(a, tm, clamp, use_id, grid, s);
+    return hip_status(hipGetLastError());
+}
+
+extern "C" int sv_mlp_features(const sv_temporal_io *io, const sv_rgb *albedo, const sv_mlp *w,
+                               void *feat, const sv_rgb *hist_out, sv_dims d, sv_dtype t,
+                               const sv_temporal_params *p, sv_stream stream) {
+    using namespace sv;
+    if (!valid_dtype(t)) return SV_EDTYPE;
+    int dc = check_dims(d);
+    if (dc < 0 || !io || !p || !albedo || !w) return SV_EINVAL;
+    if (p->max_hist < 1 || p->max_hist > 255) return SV_EINVAL;
+    if (dc == 1) return SV_OK;
+    const bool use_id = (p->flags & SV_T_USE_ID) != 0;
+    const bool clamp = (p->flags & SV_T_CLAMP) != 0 && p->gamma > 0.f;
+    const bool tm = (p->flags & SV_T_TONEMAP_IN) != 0;
+    const void *req[] = {io->cur.r, io->cur.g, io->cur.b, io->g.z, io->g.dzdx, io->g.dzdy,
+                         io->g.nx, io->g.ny, io->g.nz, io->mvx, io->mvy, io->prev.z,
+                         io->prev.nx, io->prev.ny, io->prev.nz, io->hist.r, io->hist.g,
+                         io->hist.b, io->hist_m1, io->hist_m2c, io->hist_n, albedo->r,
+                         albedo->g, albedo->b, feat, w->mu, w->inv_s};
+    for (const void *q : req)
+        if (!q) return SV_EINVAL;
+    if (((uintptr_t)feat & 15u) != 0) return SV_EINVAL;
+    if (use_id && (!io->g.id || !io->prev.id)) return SV_EINVAL;
+    if (hist_out && (!hist_out->r || !hist_out->g || !hist_out->b)) return SV_EINVAL;
+    const size_t es = elem_size(t);
+    const span fs{(uintptr_t)feat, (uintptr_t)feat + (size_t)d.w * (size_t)d.h * 32u};
+    const span ins[] = {
+        plane_span(io->cur.r, d, es), plane_span(io->cur.g, d, es), plane_span(io->cur.b, d, es),
+        plane_span(io->g.z, d, es), plane_span(io->g.dzdx, d, es), plane_span(io->g.dzdy, d, es),
+        plane_span(io->g.nx, d, es), plane_span(io->g.ny, d, es), plane_span(io->g.nz, d, es),
+        plane_span(io->mvx, d, es), plane_span(io->mvy, d, es), plane_span(io->prev.z, d, es),
+        plane_span(io->prev.nx, d, es), plane_span(io->prev.ny, d, es),
+        plane_span(io->prev.nz, d, es), plane_span(io->hist.r, d, es),
+        plane_span(io->hist.g, d, es), plane_span(io->hist.b, d, es),
+        plane_span(io->hist_m1, d, 4), plane_span(io->hist_m2c, d, 4),
+        plane_span(io->hist_n, d, 1), plane_span(albedo->r, d, es), plane_span(albedo->g, d, es),
+        plane_span(albedo->b, d, es),
+        use_id ? plane_span(io->g.id, d, 1) : span{0, 0},
+        use_id ? plane_span(io->prev.id, d, 1) : span{0, 0}};
+    span outs[4] = {fs, span{0, 0}, span{0, 0}, span{0, 0}};
+    if (hist_out) {
+        outs[1] = plane_span(hist_out->r, d, 4);
+        outs[2] = plane_span(hist_out->g, d, 4);
+        outs[3] = plane_span(hist_out->b, d, 4);
+    }
+    for (const span &so : outs) {
+        for (const span &si : ins)
+            if (overlaps(so, si)) return SV_EALIAS;
+    }
+    for (int i = 0; i < 4; ++i)
+        for (int j = i + 1; j < 4; ++j)
+            if (overlaps(outs[i], outs[j])) return SV_EALIAS;
+    TemporalArgs a{io->cur.r, io->cur.g, io->cur.b, io->g.z, io->g.nx, io->g.ny, io->g.nz,
+                   io->g.id, io->mvx, io->mvy, io->prev.z, io->prev.nx, io->prev.ny,
+                   io->prev.nz, io->prev.id, io->hist.r, io->hist.g, io->hist.b, io->hist_m1,
+                   io->hist_m2c, io->hist_n, nullptr, nullptr, nullptr, nullptr,
+                   nullptr, nullptr, nullptr, d.w, d.h, d.pitch, p->alpha,
+                   p->alpha_m, p->gamma, p->tau_z, p->tau_n, p->tm_k, p->max_hist,
+                   io->g.dzdx, io->g.dzdy, albedo->r, albedo->g, albedo->b, (uint4 *)feat,
+                   hist_out ? (float *)hist_out->r : nullptr,
+                   hist_out ? (float *)hist_out->g : nullptr,
+                   hist_out ? (float *)hist_out->b : nullptr, w->mu, w->inv_s};
+    dim3 grid(xcd_grid(((d.w + kTX - 1) / kTX) * ((d.h + kTY - 1) / kTY)));
+    hipStream_t s = as_stream(stream);
+    if (t == SV_F32) launch_temporal<float, true>(a, tm, clamp, use_id, grid, s);
+    else launch_temporal<half_t, true>(a, tm, clamp, use_id, grid, s);
     return hip_status(hipGetLastError());
 }
 

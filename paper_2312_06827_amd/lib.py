@@ -98,6 +98,17 @@ class sv_frame_params(ctypes.Structure):
 
 
 _P = ctypes.POINTER
+class sv_mlp(ctypes.Structure):
+    _fields_ = [("params", _vp), ("wq", _vp), ("mu", _vp), ("inv_s", _vp)]
+
+
+class sv_adam_params(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float)]
+
+
+SV_MLP_IN, SV_MLP_HIDDEN, SV_MLP_PARAMS = 14, 32, 1602
+
 EXPORTS = {
     "sv_tonemap": ([_P(sv_rgb), _P(sv_rgb), sv_dims, ctypes.c_int, ctypes.c_int,
                     _P(sv_tm_params), _vp], ctypes.c_int),
@@ -115,6 +126,18 @@ EXPORTS = {
                       ctypes.c_int),
     "sv_denoise_frame": ([_P(sv_frame_in), _P(sv_denoiser), sv_dims, ctypes.c_int,
                           _P(sv_frame_params), _vp], ctypes.c_int),
+    "sv_mlp_features": ([_P(sv_temporal_io), _P(sv_rgb), _P(sv_mlp), _vp, _P(sv_rgb), sv_dims,
+                         ctypes.c_int, _P(sv_temporal_params), _vp], ctypes.c_int),
+    "sv_mlp_forward": ([_P(sv_mlp), _vp, _vp, _vp, sv_dims, _vp], ctypes.c_int),
+    "sv_mlp_backward": ([_P(sv_mlp), _vp, _vp, _vp, ctypes.c_float, _vp, _vp, sv_dims, _vp],
+                        ctypes.c_int),
+    "sv_mlp_backward_work_bytes": ([sv_dims], ctypes.c_size_t),
+    "sv_adam": ([_vp, _vp, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _P(sv_adam_params),
+                 _vp], ctypes.c_int),
+    "sv_mlp_alpha_grad": ([_P(sv_rgb), _P(sv_rgb), _P(sv_rgb), _P(sv_rgb), _vp, _vp, _vp,
+                           ctypes.c_float, _vp, sv_dims, ctypes.c_int, _vp], ctypes.c_int),
+    "sv_atrous_kappa_grad": ([_P(sv_rgb), _vp, _P(sv_gbuf), _vp, _P(sv_rgb), _vp, ctypes.c_int32,
+                              sv_dims, ctypes.c_int, _P(sv_atrous_params), _vp], ctypes.c_int),
     "sv_status_str": ([ctypes.c_int], ctypes.c_char_p),
     "sv_version": ([], ctypes.c_int),
     "sv_last_hip_error": ([], ctypes.c_int),
@@ -351,6 +374,117 @@ def sv_atrous_sep(c_in: Planes, var_in: torch.Tensor, g: GBuf, scratch: Planes, 
         ctypes.byref(_rgb(c_in)), _plane_ptr(var_in), ctypes.byref(gc), _plane_ptr(kappa),
         ctypes.byref(_rgb(scratch)), ctypes.byref(_rgb(c_out)), _plane_ptr(var_out), int(step),
         dims_of(r), dtype_of(r), ctypes.byref(pc), _stream(stream)))
+
+
+# ---- learned blend factor and edge scale -------------------------------------
+
+class MLP:
+    """Device parameters of the per-pixel network: binary32 flat vector
+    (SV_MLP_PARAMS, order W1 b1 W2 b2 W3 b3, matrices [out][in]), its
+    bfloat16 mirror, the feature standardisation, and Adam's moments."""
+
+    def __init__(self, params, mu, inv_s, device="cuda"):
+        f = lambda a: torch.as_tensor(a, dtype=torch.float32).to(device).contiguous()
+        self.params = f(params)
+        if self.params.numel() != SV_MLP_PARAMS:
+            raise ValueError(f"expected {SV_MLP_PARAMS} parameters")
+        self.mu, self.inv_s = f(mu), f(inv_s)
+        if self.mu.numel() != SV_MLP_IN or self.inv_s.numel() != SV_MLP_IN:
+            raise ValueError("standardisation needs 14 means and 14 inverse scales")
+        self.wq = torch.empty(SV_MLP_PARAMS, dtype=torch.int16, device=device)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.t = 0
+        self.sync_mirror()
+
+    def sync_mirror(self):
+        """Refresh the bfloat16 mirror from the binary32 parameters (round to
+        nearest even, torch's conversion)."""
+        self.wq.copy_(self.params.to(torch.bfloat16).view(torch.int16))
+
+    def c(self) -> sv_mlp:
+        return sv_mlp(self.params.data_ptr(), self.wq.data_ptr(), self.mu.data_ptr(),
+                      self.inv_s.data_ptr())
+
+
+def feature_rows(H: int, W: int, device="cuda") -> torch.Tensor:
+    """Buffer for sv_mlp_features: H*W rows of 16 bfloat16 (as int16)."""
+    return torch.empty((H * W, 16), dtype=torch.int16, device=device)
+
+
+def sv_mlp_features(cur: Planes, g: GBuf, mv: Planes, prev: GBuf, hist: Planes,
+                    hist_m1: torch.Tensor, hist_m2c: torch.Tensor, hist_n: torch.Tensor,
+                    albedo: Planes, mlp: MLP, feat: torch.Tensor, params: TemporalParams,
+                    hist_out: Optional[Planes] = None, stream=None):
+    r = _planes3(cur)[0]
+    d = dims_of(r)
+    if feat.numel() * feat.element_size() < d.w * d.h * 32 or not feat.is_contiguous():
+        raise ValueError("feature buffer too small or not contiguous")
+    mvx, mvy = mv[0], mv[1]
+    io = sv_temporal_io(_rgb(cur), g.c(), _plane_ptr(mvx), _plane_ptr(mvy), prev.c(),
+                        _rgb(hist), _plane_ptr(hist_m1), _plane_ptr(hist_m2c),
+                        _plane_ptr(hist_n), sv_rgb(), None, None, None, None)
+    pc, mc = params.c(), mlp.c()
+    ho = None if hist_out is None else ctypes.byref(_rgb(hist_out))
+    _check("sv_mlp_features", load().sv_mlp_features(
+        ctypes.byref(io), ctypes.byref(_rgb(albedo)), ctypes.byref(mc), feat.data_ptr(), ho,
+        d, dtype_of(r), ctypes.byref(pc), _stream(stream)))
+
+
+def sv_mlp_forward(mlp: MLP, feat: torch.Tensor, alpha: Optional[torch.Tensor],
+                   kappa: Optional[torch.Tensor], like: torch.Tensor, stream=None):
+    """alpha / kappa: binary32 planes shaped like `like` (either may be None)."""
+    mc = mlp.c()
+    _check("sv_mlp_forward", load().sv_mlp_forward(
+        ctypes.byref(mc), feat.data_ptr(), _plane_ptr(alpha), _plane_ptr(kappa), dims_of(like),
+        _stream(stream)))
+
+
+def mlp_workspace(like: torch.Tensor) -> torch.Tensor:
+    nbytes = load().sv_mlp_backward_work_bytes(dims_of(like))
+    return torch.empty(max(1, nbytes // 4), dtype=torch.float32, device=like.device)
+
+
+def sv_mlp_backward(mlp: MLP, feat: torch.Tensor, d_alpha: Optional[torch.Tensor],
+                    d_kappa: Optional[torch.Tensor], grad: torch.Tensor, work: torch.Tensor,
+                    like: torch.Tensor, scale: float = 1.0, stream=None):
+    d = dims_of(like)
+    if work.numel() * work.element_size() < load().sv_mlp_backward_work_bytes(d):
+        raise ValueError("backward workspace too small")
+    mc = mlp.c()
+    _check("sv_mlp_backward", load().sv_mlp_backward(
+        ctypes.byref(mc), feat.data_ptr(), _plane_ptr(d_alpha), _plane_ptr(d_kappa),
+        float(scale), grad.data_ptr(), work.data_ptr(), d, _stream(stream)))
+
+
+def sv_adam(mlp: MLP, grad: torch.Tensor, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+            stream=None):
+    mlp.t += 1
+    p = sv_adam_params(lr, beta1, beta2, eps)
+    _check("sv_adam", load().sv_adam(
+        mlp.params.data_ptr(), mlp.wq.data_ptr(), mlp.m.data_ptr(), mlp.v.data_ptr(),
+        grad.data_ptr(), SV_MLP_PARAMS, mlp.t, ctypes.byref(p), _stream(stream)))
+
+
+def sv_mlp_alpha_grad(c_t: Planes, cur: Planes, hist: Planes, y: Planes, alpha: torch.Tensor,
+                      n: torch.Tensor, z: torch.Tensor, d_alpha: torch.Tensor, tm_k: float = 1.0,
+                      stream=None):
+    r = _planes3(c_t)[0]
+    _check("sv_mlp_alpha_grad", load().sv_mlp_alpha_grad(
+        ctypes.byref(_rgb(c_t)), ctypes.byref(_rgb(cur)), ctypes.byref(_rgb(hist)),
+        ctypes.byref(_rgb(y)), _plane_ptr(alpha), _plane_ptr(n), _plane_ptr(z), float(tm_k),
+        _plane_ptr(d_alpha), dims_of(r), dtype_of(r), _stream(stream)))
+
+
+def sv_atrous_kappa_grad(c_in: Planes, var_in: torch.Tensor, g: GBuf, kappa: torch.Tensor,
+                         y: Planes, d_kappa: torch.Tensor, step: int, params: AtrousParams,
+                         stream=None):
+    r = _planes3(c_in)[0]
+    gc, pc = g.c(), params.c()
+    _check("sv_atrous_kappa_grad", load().sv_atrous_kappa_grad(
+        ctypes.byref(_rgb(c_in)), _plane_ptr(var_in), ctypes.byref(gc), _plane_ptr(kappa),
+        ctypes.byref(_rgb(y)), _plane_ptr(d_kappa), int(step), dims_of(r), dtype_of(r),
+        ctypes.byref(pc), _stream(stream)))
 
 
 def sv_probe_copy(dst: torch.Tensor, src: torch.Tensor, stream=None):

@@ -158,3 +158,52 @@ def test_binding_rejects_host_tensors():
     t = torch.zeros((3, 4, 4))
     with pytest.raises(ValueError):
         L.sv_tonemap(t, t)
+
+
+def test_mlp_validation(so):
+    r = ctypes.byref
+    base = [A + i * 0x01000000 for i in range(48)]
+    w = L.sv_mlp(base[40], base[41], base[42], base[43])
+    feat = base[44]
+    # missing parameters, misaligned or missing feature rows
+    assert so.sv_mlp_forward(r(L.sv_mlp(None, base[41], None, None)), feat, base[30], None, D,
+                             None) == L.SV_EINVAL
+    assert so.sv_mlp_forward(r(w), feat + 8, base[30], None, D, None) == L.SV_EINVAL
+    assert so.sv_mlp_forward(r(w), None, base[30], None, D, None) == L.SV_EINVAL
+    # outputs on top of the rows or of each other
+    assert so.sv_mlp_forward(r(w), feat, feat + 64, None, D, None) == L.SV_EALIAS
+    assert so.sv_mlp_forward(r(w), feat, base[30], base[30] + 4, D, None) == L.SV_EALIAS
+    # backward: workspace, gradient and inputs must be distinct
+    wb = so.sv_mlp_backward_work_bytes(D)
+    # 2048 pixels = 64 blocks of 32, four per workgroup: 16 workgroups x 4 waves
+    assert wb == 16 * 4 * L.SV_MLP_PARAMS * 4
+    assert so.sv_mlp_backward(r(w), feat, base[30], base[31], 1.0, base[32], None, D,
+                              None) == L.SV_EINVAL
+    assert so.sv_mlp_backward(r(w), feat, base[30], base[31], 1.0, base[32], base[32] + 16, D,
+                              None) == L.SV_EALIAS
+    assert so.sv_mlp_backward(r(w), feat, base[30], base[31], 1.0, base[30], base[33], D,
+                              None) == L.SV_EALIAS
+    ap = L.sv_adam_params(1e-3, 0.9, 0.999, 1e-8)
+    assert so.sv_adam(base[40], base[41], base[42], base[43], base[44], 10, 0, r(ap),
+                      None) == L.SV_EINVAL
+    assert so.sv_adam(None, None, base[42], base[43], base[44], 10, 1, r(ap), None) == L.SV_EINVAL
+    # features: the history colour output must not overlap an input
+    io = L.sv_temporal_io(rgb(base[0]), gbuf(base[3]), base[9], base[10], gbuf(base[11]),
+                          rgb(base[17]), base[20], base[21], base[22], L.sv_rgb(), None, None,
+                          None, None)
+    p = L.sv_temporal_params(0.2, 0.2, 1.0, 0.1, 0.9, 1.0, 255, 0)
+    assert so.sv_mlp_features(r(io), r(rgb(base[25])), r(w), feat, r(rgb(base[0])), D,
+                              L.SV_F32, r(p), None) == L.SV_EALIAS
+    assert so.sv_mlp_features(r(io), None, r(w), feat, None, D, L.SV_F32, r(p),
+                              None) == L.SV_EINVAL
+    assert so.sv_mlp_features(r(io), r(rgb(base[25])), r(w), feat + 4, None, D, L.SV_F32, r(p),
+                              None) == L.SV_EINVAL
+    # loss gradients
+    assert so.sv_mlp_alpha_grad(r(rgb(base[0])), r(rgb(base[3])), r(rgb(base[6])),
+                                r(rgb(base[9])), base[12], base[13], base[14], 1.0, base[12],
+                                D, L.SV_F32, None) == L.SV_EALIAS
+    g = gbuf(base[20])
+    assert so.sv_atrous_kappa_grad(r(rgb(base[0])), base[3], r(g), base[4], r(rgb(base[5])),
+                                   base[4], 1, D, L.SV_F32, r(AP), None) == L.SV_EALIAS
+    assert so.sv_atrous_kappa_grad(r(rgb(base[0])), base[3], r(g), base[4], r(rgb(base[5])),
+                                   base[8], 0, D, L.SV_F32, r(AP), None) == L.SV_EINVAL

@@ -1,0 +1,230 @@
+"""Parity of the learned component's kernels with its FP64 oracle
+(oracle/mlp.py), and the gain of a network trained by them.
+
+Tolerances.  The device rounds matrix operands to bfloat16 exactly as the
+oracle's precision model does, but its binary32 sums run in another order;
+a pre-activation within a few binary32 ulps of a bfloat16 rounding
+boundary can therefore round the other way (one bfloat16 ulp, 2^-8
+relative, of one activation).  Such flips are rare; the tests bound the
+median error tightly and the maximum by the effect of a few flips.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from oracle import mlp as M
+from paper_2312_06827_amd import lib as L
+from paper_2312_06827_amd.scene import CONFIGS, render_frame, sequence, with_size
+from tests._util import rel_err, say
+
+pytestmark = pytest.mark.gpu
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().to(torch.float64).cpu().numpy() if t.dtype.is_floating_point \
+        else t.detach().cpu().numpy()
+
+
+def dev(a, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).cuda()
+
+
+def _weights(seed):
+    r = np.random.default_rng(seed)
+    w = M.init_weights(seed)
+    w.w3 = r.normal(0, 0.6, w.w3.shape)
+    w.b1 = r.normal(0, 0.2, w.b1.shape)
+    w.b2 = r.normal(0, 0.2, w.b2.shape)
+    w.b3 = r.normal(0, 0.3, w.b3.shape)
+    w.mu = r.normal(0, 0.5, M.N_IN)
+    w.inv_s = r.uniform(0.5, 2.0, M.N_IN)
+    # binary32 master values
+    for k in ("w1", "b1", "w2", "b2", "w3", "b3", "mu", "inv_s"):
+        setattr(w, k, M.f32(getattr(w, k)))
+    return w
+
+
+def _device_mlp(w):
+    return L.MLP(w.flat(), w.mu, w.inv_s)
+
+
+def _rows(xs):
+    """(14, N) bf16-representable values -> device feature rows (N, 16)."""
+    N = xs.shape[1]
+    rows = np.zeros((N, 16), np.float32)
+    rows[:, :14] = xs.T
+    t = torch.from_numpy(rows).to(torch.bfloat16)
+    assert np.array_equal(t.to(torch.float64).numpy()[:, :14], xs.T)
+    return t.view(torch.int16).cuda()
+
+
+@pytest.mark.parametrize("H,W", [(1, 1), (5, 7), (33, 61), (64, 64)])
+def test_forward_parity(H, W):
+    w = _weights(10 + H)
+    xs = M.bf16(np.random.default_rng(H).normal(0, 1.2, (14, H * W)))
+    mlp = _device_mlp(w)
+    P = W + 3
+    a = torch.full((H, P), float("nan"), device="cuda")[:, :W]
+    k = torch.full((H, P), float("nan"), device="cuda")[:, :W]
+    say(f"mlp forward {H}x{W}")
+    L.sv_mlp_forward(mlp, _rows(xs), a, k, a)
+    fw = M.forward(w, xs, bf16_ops=True)
+    ea = np.abs(host(a).ravel() - fw["alpha"])
+    ek = np.abs(host(k).ravel() - fw["kappa"]) / fw["kappa"]
+    say(f"  alpha err median {np.median(ea):.1e} max {ea.max():.1e}; "
+        f"kappa rel err median {np.median(ek):.1e} max {ek.max():.1e}")
+    assert np.median(ea) <= 1e-6 and np.median(ek) <= 1e-6
+    assert ea.max() <= 2e-3 and ek.max() <= 4e-3
+
+
+@pytest.mark.parametrize("N", [40, 1000, 4096 + 17])
+def test_backward_parity(N):
+    w = _weights(20 + N)
+    r = np.random.default_rng(N)
+    xs = M.bf16(r.normal(0, 1.2, (14, N)))
+    da = r.normal(0, 1.0, N)
+    dk = r.normal(0, 1.0, N)
+    H, W = 1, N
+    mlp = _device_mlp(w)
+    grad = torch.empty(L.SV_MLP_PARAMS, device="cuda")
+    like = torch.empty((H, W), device="cuda")
+    work = L.mlp_workspace(like)
+    say(f"mlp backward N={N}")
+    L.sv_mlp_backward(mlp, _rows(xs), dev(da[None]), dev(dk[None]), grad, work, like, scale=0.5)
+    fw = M.forward(w, xs, bf16_ops=True)
+    g_o = M.head_grads(fw, M.f32(da), M.f32(dk))
+    ref = 0.5 * M.backward(w, fw, g_o, bf16_ops=True)
+    got = host(grad)
+    off = 0
+    for name, n in [("W1", 448), ("b1", 32), ("W2", 1024), ("b2", 32), ("W3", 64), ("b3", 2)]:
+        g, o = got[off:off + n], ref[off:off + n]
+        e = np.abs(g - o).max() / max(np.abs(o).max(), 1e-30)
+        say(f"  {name}: max err / max |grad| = {e:.1e}")
+        assert e <= 5e-3, name
+        off += n
+    # a second call with the same inputs is bitwise identical (fixed order)
+    g2 = torch.empty_like(grad)
+    L.sv_mlp_backward(mlp, _rows(xs), dev(da[None]), dev(dk[None]), g2, work, like, scale=0.5)
+    assert torch.equal(grad, g2)
+
+
+def test_adam_parity():
+    r = np.random.default_rng(3)
+    p0 = M.f32(r.normal(0, 1, L.SV_MLP_PARAMS))
+    mlp = L.MLP(p0, np.zeros(14), np.ones(14))
+    p, m, v = p0.copy(), np.zeros_like(p0), np.zeros_like(p0)
+    for t in range(1, 4):
+        g = M.f32(r.normal(0, 1, L.SV_MLP_PARAMS))
+        L.sv_adam(mlp, dev(g), lr=1e-2)
+        p, m, v = M.adam(p, m, v, g, t, M.AdamParams(lr=1e-2))
+    assert rel_err(host(mlp.params)[None], p[None]) <= 1e-5
+    mirror = mlp.wq.view(torch.bfloat16).to(torch.float64).cpu().numpy()
+    np.testing.assert_array_equal(mirror, M.bf16(host(mlp.params)))
+
+
+def _history_state(H, W, seed, frames=4):
+    """Oracle state after a few frames of a motion sequence, and the next frame."""
+    cfg = with_size(CONFIGS["hd_motion"], W, H, frames + 1)
+    from dataclasses import replace
+    cfg = replace(cfg, seed=seed)
+    p = O.OracleParams(clamp=True, tonemap=True, use_id=True)
+    st = O.new_state(H, W)
+    frs = list(sequence(cfg))
+    for fr in frs[:frames]:
+        _, st, _ = O.run_frame(fr, st, p)
+    return frs[frames], st, p
+
+
+@pytest.mark.parametrize("H,W", [(37, 70), (90, 160)])
+def test_features_parity(H, W):
+    fr, st, p = _history_state(H, W, 77 + H)
+    fr = dict(fr)
+    fr["z"] = fr["z"].copy()
+    fr["z"][3, 4] = 0.0  # an empty pixel
+    w = _weights(5)
+    mlp = _device_mlp(w)
+    feat = L.feature_rows(H, W)
+    hist_out = torch.empty((3, H, W), device="cuda")
+    g = L.GBuf(dev(fr["z"]), dev(fr["dzdx"]), dev(fr["dzdy"]), dev(fr["n"]),
+               dev(fr["id"], torch.uint8))
+    prev = L.GBuf(dev(fr["prev_z"]), None, None, dev(fr["prev_n"]), dev(fr["prev_id"], torch.uint8))
+    m2c = (st["m2"] - st["m1"] ** 2).astype(np.float32)
+    say(f"mlp features {H}x{W}")
+    L.sv_mlp_features(dev(fr["rgb"]), g, dev(fr["mv"]), prev, dev(st["rgb"]), dev(st["m1"]),
+                      dev(m2c), dev(st["n"], torch.uint8), dev(fr["albedo"]), mlp, feat,
+                      L.TemporalParams(clamp=True, tonemap=True, use_id=True),
+                      hist_out=hist_out)
+    # the oracle gets the same (binary32) history the device read
+    st32 = dict(st)
+    st32["m1"] = st["m1"].astype(np.float32).astype(np.float64)
+    st32["m2"] = m2c.astype(np.float64) + st32["m1"] ** 2
+    st32["rgb"] = st["rgb"].astype(np.float32).astype(np.float64)
+    ft = M.features(fr, st32, p)
+    ref = M.standardise(ft["x"], w).T.reshape(H * W, 14)
+    got = feat.view(torch.bfloat16).to(torch.float64).cpu().numpy()
+    assert np.all(got[:, 14:] == 0)
+    got = got[:, :14]
+    ulp = np.maximum(np.abs(ref), 1e-30) * 2.0 ** -7  # one bf16 ulp (upper bound)
+    bad = np.abs(got - ref) > ulp
+    say(f"  features differing by more than one bf16 ulp: {int(bad.sum())} of {bad.size}; "
+        f"differing at all: {int((got != ref).sum())}")
+    assert not bad.any(), np.argwhere(bad)[:5]
+    assert (got != ref).mean() <= 2e-3
+    assert rel_err(host(hist_out), ft["hist"]) <= 1e-5
+
+
+def test_alpha_grad_parity():
+    H, W = 40, 72
+    fr, st, p = _history_state(H, W, 91)
+    r = np.random.default_rng(4)
+    alpha = r.uniform(0.05, 1.0, (H, W)).astype(np.float32)
+    ft = M.features(fr, st, p)
+    t = O.temporal(fr, st, p, alpha_map=alpha)
+    y = O.tonemap(fr["clean"])
+    ref = M.alpha_grad(t["rgb"], ft["cur"], ft["hist"], y, alpha, t["n"])
+    out = torch.empty((H, W), device="cuda")
+    say("mlp alpha grad")
+    L.sv_mlp_alpha_grad(dev(t["rgb"]), dev(fr["rgb"]), dev(ft["hist"]), dev(y), dev(alpha),
+                        dev(t["n"], torch.uint8), dev(fr["z"]), out, tm_k=1.0)
+    assert rel_err(host(out), ref) <= 1e-4
+
+
+@pytest.mark.parametrize("step", [1, 4])
+def test_kappa_grad_parity(step):
+    H, W = 48, 80
+    fr = render_frame(with_size(CONFIGS["hd_motion"], W, H, 3), 2)
+    r = np.random.default_rng(step)
+    c = O.tonemap(fr["rgb"]).astype(np.float32)
+    var = r.uniform(0.001, 0.05, (H, W)).astype(np.float32)
+    kappa = r.uniform(0.5, 2.0, (H, W)).astype(np.float32)
+    y = O.tonemap(fr["clean"]).astype(np.float32)
+    deriv = M.atrous_kappa_derivative(c, var, fr["z"], fr["dzdx"], fr["dzdy"], fr["n"], kappa, step)
+    outc = O.atrous(c, var, fr["z"], fr["dzdx"], fr["dzdy"], fr["n"], step, kappa=kappa)[0]
+    ref = 0.25 + M.kappa_grad_level(outc, y, deriv)  # accumulates onto 0.25
+    dk = torch.full((H, W), 0.25, device="cuda")
+    g = L.GBuf(dev(fr["z"]), dev(fr["dzdx"]), dev(fr["dzdy"]), dev(fr["n"]))
+    say(f"kappa grad step={step}")
+    L.sv_atrous_kappa_grad(dev(c), dev(var), g, dev(kappa), dev(y), dk, step, L.AtrousParams())
+    e = np.abs(host(dk) - ref) / np.maximum(np.abs(ref - 0.25), 1e-3 * np.sqrt(np.mean((ref - 0.25) ** 2)))
+    say(f"  rel err max {e.max():.1e}")
+    assert e.max() <= 1e-3
+
+
+def test_training_beats_plain_filter():
+    """A network trained from scratch by the library's kernels lowers the
+    RelMSE-to-clean of the filter on held-out sequences."""
+    from paper_2312_06827_amd import learn
+    # sequences long enough for the history length to pass 1/alpha: below
+    # that the blend factor is max(alpha, 1/n) and alpha gets no gradient
+    cfg = learn.TrainConfig(width=256, height=144, frames=24, sequences=16, warm=2,
+                            lr=3e-3, stat_frames=24)
+    say("training 16 sequences of 24 frames at 256x144")
+    net = learn.train(cfg, log=say)
+    plain = learn.evaluate([5900, 5901], 256, 144, 30, None, first=10)
+    learned = learn.evaluate([5900, 5901], 256, 144, 30, net, first=10)
+    say(f"held-out RelMSE: plain {plain:.5f}, learned {learned:.5f}")
+    assert np.isfinite(learned)
+    assert learned < plain
