@@ -105,6 +105,11 @@ def measured_traffic():
         return None
 
 
+# Binary16 storage, 2D levels: the survey's per-pass figures at FP16
+# (temporal 56, variance 13, level 32, last level 28) plus the id planes.
+FP16_FRAME_BYTES = 56 + 2 + 13 + 4 * 32 + 28
+
+
 def frame_bytes_per_px(levels: int, sep: bool) -> int:
     a, al = ("atrous_sep", "atrous_sep_last") if sep else ("atrous", "atrous_last")
     return (BYTES_PER_PX["temporal"] + BYTES_PER_PX["variance"]
@@ -197,6 +202,118 @@ def copy_probe(torch, nbytes=1 << 30, reps=10):
     return 2 * nbytes / (ms * 1e-3) / 1e9  # read + write
 
 
+def _timed_frames(torch, fn, frames, warmup):
+    """Run fn(frame) over frames; time the ones after `warmup` with events."""
+    for f in frames[:warmup]:
+        fn(f)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for f in frames[warmup:]:
+        fn(f)
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / max(1, len(frames) - warmup)
+
+
+UHD_WARMUP, UHD_STEPS = 4, 10
+BATCH_WARMUP, BATCH_STEPS = 3, 5
+
+
+def generate_variant_frames(workers):
+    """Host frames of the 4K and sixteen-stream variants (generated before
+    the GPU is touched, like the headline frames)."""
+    from paper_2312_06827_amd.scene import batched_configs
+    uhd = CONFIGS["uhd_half"]
+    uhd = type(uhd)(**{**uhd.__dict__, "frames": UHD_WARMUP + UHD_STEPS})
+    n = BATCH_WARMUP + BATCH_STEPS
+    scfg = batched_configs(16, n, half=True)
+    jobs = [(uhd, f) for f in range(uhd.frames)] + [(c, f) for f in range(n) for c in scfg]
+    if workers <= 1:
+        out = [_render(j) for j in jobs]
+    else:
+        with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork")) as ex:
+            out = list(ex.map(_render, jobs))
+    k = uhd.frames
+    return {"uhd": out[:k], "batch_cfg": scfg,
+            "batch": [out[k + f * 16:k + (f + 1) * 16] for f in range(n)]}
+
+
+def variant_uhd_half(torch, frames_np, warmup=UHD_WARMUP, steps=UHD_STEPS):
+    """Binary16 storage at 3840x2160 (2D levels)."""
+    from paper_2312_06827_amd.pipeline import MOTION, Denoiser, FrameInputs
+    cfg = CONFIGS["uhd_half"]
+    frames = [FrameInputs.from_numpy(fr) for fr in frames_np]
+    den = Denoiser(cfg.height, cfg.width, MOTION, dtype=torch.float16)
+    ms = _timed_frames(torch, den.frame, frames, warmup)
+    px = cfg.width * cfg.height
+    return {"value": round(px / (ms * 1e-3) / 1e6, 1), "unit": "Mpix/s", "ms_per_step": round(ms, 4),
+            "dtype": "f16 storage / f32 math", "frame_bytes_per_px": FP16_FRAME_BYTES,
+            "frame_hbm_frac": round(px * FP16_FRAME_BYTES / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "config": f"{cfg.width}x{cfg.height}, {steps} frames timed after {warmup}"}
+
+
+def variant_batched(torch, scfg, frames_np, warmup=BATCH_WARMUP, steps=BATCH_STEPS):
+    """Sixteen streams of uneven size, binary16: one launch per pass under a
+    HIP graph, against the same streams run one by one."""
+    from paper_2312_06827_amd.pipeline import MOTION, BatchDenoiser, Denoiser, FrameInputs
+    frames = [[FrameInputs.from_numpy(fr) for fr in per] for per in frames_np]
+    sizes = [(c.height, c.width) for c in scfg]
+    px = sum(h * w for h, w in sizes)
+    batch = BatchDenoiser(sizes, MOTION, torch.float16)
+    ms_b = _timed_frames(torch, batch.frame, frames, warmup)
+    passes = batch.passes()
+    batch.close()
+    singles = [Denoiser(h, w, MOTION, torch.float16) for h, w in sizes]
+    ms_s = _timed_frames(torch, lambda fr: [d.frame(x) for d, x in zip(singles, fr)], frames, warmup)
+    return {"value": round(px / (ms_b * 1e-3) / 1e6, 1), "unit": "Mpix/s",
+            "ms_per_step": round(ms_b, 4), "launches_per_frame": passes,
+            "one_by_one": {"value": round(px / (ms_s * 1e-3) / 1e6, 1), "ms_per_step": round(ms_s, 4),
+                           "launches_per_frame": 16 * passes},
+            "config": f"16 streams {min(sizes)}..{max(sizes)} (HxW), {px / 1e6:.1f} Mpix per frame, "
+                      f"{steps} frames timed after {warmup}"}
+
+
+def variant_learned(torch, frames_np, warmup, steps):
+    """The learned blend/edge network on the headline workload: throughput
+    of the learned chain (5 and 4 levels) and RelMSE-to-clean of both
+    filters over the timed frames."""
+    from dataclasses import replace as dc_replace
+
+    from paper_2312_06827_amd import learn
+    from paper_2312_06827_amd.pipeline import MOTION, Denoiser, FrameInputs
+    if not os.path.exists(learn.DEFAULT_WEIGHTS):
+        return None
+    net = learn.load_weights(learn.DEFAULT_WEIGHTS)
+    H, W = WORKLOAD.height, WORKLOAD.width
+    frames = [FrameInputs.from_numpy(fr) for fr in frames_np[:warmup + steps]]
+    albedo = [torch.from_numpy(fr["albedo"]).cuda() for fr in frames_np[:warmup + steps]]
+    clean = [torch.from_numpy(fr["clean"]).cuda() for fr in frames_np[:warmup + steps]]
+    out = {}
+    for levels in (5, 4):
+        cfg = dc_replace(MOTION, levels=levels)
+        den = learn.LearnedDenoiser(H, W, net, cfg)
+        errs = []
+        idx = iter(range(len(frames)))
+
+        def step(fr, den=den, errs=errs):
+            i = next(idx)
+            o = den.frame(fr, albedo[i])
+            if i >= warmup:
+                errs.append(o)
+        ms = _timed_frames(torch, step, frames, warmup)
+        # quality over the same frames (recomputed untimed)
+        den = learn.LearnedDenoiser(H, W, net, cfg)
+        rel = [learn.relmse(den.frame(fr, albedo[i]), clean[i]) for i, fr in enumerate(frames)]
+        out[f"learned_{levels}"] = {"value": round(H * W / (ms * 1e-3) / 1e6, 1),
+                                    "ms_per_step": round(ms, 4),
+                                    "relmse": round(float(np.mean(rel[warmup:])), 6)}
+    plain = Denoiser(H, W, MOTION)
+    rel = [learn.relmse(plain.frame(fr), clean[i]) for i, fr in enumerate(frames)]
+    out["plain_5_relmse"] = round(float(np.mean(rel[warmup:])), 6)
+    return out
+
+
 def cpu_baseline(frames_np, warm, timed):
     """The oracle as it stands, on the host cores, on a bounded sample."""
     import oracle as O
@@ -237,6 +354,7 @@ def main():
     n_frames = args.warmup + args.steps
     t0 = time.perf_counter()
     frames_np = generate(WORKLOAD, n_frames, args.workers)  # before any GPU call (fork)
+    vframes = None if args.no_variants else generate_variant_frames(args.workers)
     gen_s = time.perf_counter() - t0
     print(f"# generated {n_frames} frames in {gen_s:.1f} s", file=sys.stderr, flush=True)
 
@@ -302,6 +420,17 @@ def main():
             "frame_hbm_frac": round(W * H * args.steps * frame_bytes_per_px(5, True)
                                     / (g2 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "per_kernel_us": {k: round(v[0] * 1e3, 2) for k, v in sorted(kt2.items())}}
+        print(f"# separable chain: {variants['separable']['ms_per_step'] * 1e3:.1f} us/frame",
+              file=sys.stderr, flush=True)
+        variants["uhd_half"] = variant_uhd_half(torch, vframes["uhd"])
+        print(f"# 4K binary16: {variants['uhd_half']['ms_per_step'] * 1e3:.1f} us/frame",
+              file=sys.stderr, flush=True)
+        variants["batched"] = variant_batched(torch, vframes["batch_cfg"], vframes["batch"])
+        print(f"# 16 streams batched: {variants['batched']['ms_per_step'] * 1e3:.1f} us/frame",
+              file=sys.stderr, flush=True)
+        learned = variant_learned(torch, frames_np, args.warmup, args.steps)
+        if learned is not None:
+            variants["learned"] = learned
     copy_gbs = copy_probe(torch)
 
     cpu = None

@@ -255,12 +255,17 @@ int sv_atrous(const sv_rgb *c_in, const float *var_in, const sv_gbuf *g,
 /* Separable level (Section 3.3): the 5x5 kernel split into a horizontal
  * pass of 5 taps (a, 0) and a vertical pass of 5 taps (0, b), 10 neighbour
  * visits instead of 25.  Both passes use g from var_in.  The horizontal
- * pass filters colour only into `scratch` (caller-owned planes of the
- * storage type, same dims); the vertical pass filters `scratch` (luminance
- * taken from it) and alone updates the variance:
+ * pass filters colour only; the vertical pass filters its result
+ * (luminance taken from it, the result rounded to the storage type) and
+ * alone updates the variance:
  * var' = sum (h(b) w)^2 var_in(q) / (sum h(b) w)^2.  Weights as sv_atrous
- * with the offset (step a, 0) or (0, step b).  scratch must not overlap
- * inputs or outputs. */
+ * with the offset (step a, 0) or (0, step b).
+ * With `scratch` (caller-owned planes of the storage type, same dims; must
+ * not overlap inputs or outputs) the horizontal result is written there
+ * and read back by a second kernel.  With scratch NULL both passes run in
+ * one kernel and the horizontal result never leaves the chip (steps 1, 2,
+ * 4, 8, 16; other steps return SV_EUNSUPPORTED); the outputs are bitwise
+ * those of the two-kernel form. */
 int sv_atrous_sep(const sv_rgb *c_in, const float *var_in, const sv_gbuf *g,
                   const float *kappa, const sv_rgb *scratch,
                   const sv_rgb *c_out, float *var_out, int32_t step,
@@ -344,26 +349,33 @@ typedef struct {
 int sv_adam(float *params, uint16_t *wq, float *m, float *v, const float *grad, int32_t n,
             int32_t t, const sv_adam_params *p, sv_stream stream);
 
-/* dL/dalpha per pixel for L = sum over pixels of the per-pixel RelMSE term
- * (1/3) sum_c (c_t - y)^2 / (y^2 + 0.01) of the temporal output against the
- * target, with the history held fixed: c_t = (1 - a) hist + a cur, a =
- * max(alpha, 1/n).  Zero where 1/n wins or the pixel is empty.  c_t: the
- * temporal output (storage type); cur: the current colour, tone mapped
- * here if tm_k > 0; hist: sv_mlp_features' hist_out; y: target colour
- * (binary32, in the space of c_t); n: the new history length. */
+/* Per pixel, (2/3) sum_c (c_t - y) / (y^2 + 0.01) (cur - hist): with c_t
+ * the temporal output, dL/dalpha of the per-pixel RelMSE term
+ * (1/3) sum_c (c_t - y)^2 / (y^2 + 0.01) with the history held fixed
+ * (c_t = (1 - a) hist + a cur, a = max(alpha, 1/n)); with c_t a later
+ * colour (the chain's final output) the same local derivative weighted by
+ * that colour's residual.  Zero where 1/n wins or the pixel is empty.
+ * c_t: storage type; cur: the current colour, tone mapped here if
+ * tm_k > 0; hist: sv_mlp_features' hist_out; y: target colour (binary32,
+ * in the space of c_t); n: the new history length. */
 int sv_mlp_alpha_grad(const sv_rgb *c_t, const sv_rgb *cur, const sv_rgb *hist,
                       const sv_rgb *y, const float *alpha, const uint8_t *n, const void *z,
                       float tm_k, float *d_alpha, sv_dims d, sv_dtype t, sv_stream stream);
 
-/* Adds to d_kappa the derivative of the same per-pixel RelMSE term of one
- * 5x5 a-trous level's colour output c' against y with respect to kappa(p),
- * the level input held fixed:
- * dc'/dkappa = sum H (dw/dkappa) (c(q) - c') / sum H w, where only the
- * luminance weight depends on kappa.  Arguments as sv_atrous (no outputs;
- * p's flags other than the sigmas and epsilons are ignored). */
+/* Adds to d_kappa, per pixel, (2/3) sum_c r_c / (y_c^2 + 0.01) dc'_c/dkappa:
+ * the local derivative of one 5x5 a-trous level's colour output c' with
+ * respect to kappa(p), the level input held fixed,
+ * dc'/dkappa = sum H (dw/dkappa) (c(q) - c') / sum H w (only the luminance
+ * weight depends on kappa), times the residual r = c' - y of the level's
+ * own output, or r = ref - y when `ref` (binary32 planes, optional) is
+ * given - e.g. the chain's final output, so that every level's local
+ * derivative is weighted by the error that reaches the end.  Arguments as
+ * sv_atrous (no outputs; p's flags other than the sigmas and epsilons are
+ * ignored); y is binary32. */
 int sv_atrous_kappa_grad(const sv_rgb *c_in, const float *var_in, const sv_gbuf *g,
-                         const float *kappa, const sv_rgb *y, float *d_kappa, int32_t step,
-                         sv_dims d, sv_dtype t, const sv_atrous_params *p, sv_stream stream);
+                         const float *kappa, const sv_rgb *y, const sv_rgb *ref,
+                         float *d_kappa, int32_t step, sv_dims d, sv_dtype t,
+                         const sv_atrous_params *p, sv_stream stream);
 
 /* ---- one frame of the whole filter (Section 3, steps 4 and 5) --------- */
 
@@ -379,7 +391,8 @@ typedef struct {
     void *var_work;          /* sv_variance workspace (zeroed once) */
     sv_rgb level[2];         /* a-trous colour ping-pong (scratch) */
     float *level_var[2];     /* a-trous variance ping-pong (scratch) */
-    sv_rgb scratch;          /* separable horizontal result (separable only) */
+    sv_rgb scratch;          /* separable horizontal result (separable levels at
+                                steps above 16 only; may be empty otherwise) */
     sv_rgb out;              /* final output of the frame */
     int32_t cur;             /* 0 or 1: which history buffers are current;
                                 each call flips it */
@@ -417,6 +430,37 @@ typedef struct {
  * output is bitwise that of calling them one by one. */
 int sv_denoise_frame(const sv_frame_in *in, sv_denoiser *st, sv_dims d,
                      sv_dtype t, const sv_frame_params *p, sv_stream stream);
+
+/* ---- batched streams: many independent denoisers, one launch per pass ---
+ *
+ * Not in the paper.  A plan over n streams (1..64) of any sizes, each with
+ * its own caller-owned sv_denoiser buffers, all with the same storage type
+ * and sv_frame_params (1..5 levels; one level only with feedback = 1).
+ * Each sv_batch_frame does for every stream exactly what sv_denoise_frame
+ * does (the same kernels' tile code, so each stream's results are bitwise
+ * those of sv_denoise_frame), but every pass runs once for all streams: one
+ * persistent launch over the tiles of all of them, the passes of a frame
+ * captured on the first call as a HIP graph and replayed afterwards.
+ *
+ * The plan is the one object of the library that allocates (a device
+ * buffer of the streams' per-pass arguments, pinned staging for it, two
+ * events, a capture stream and the graph); sv_batch_destroy frees them.
+ * The plan keeps the `states` pointers: those structures must outlive it.
+ * Frames of one plan must be issued in order on one stream. */
+typedef struct sv_batch sv_batch;
+
+int sv_batch_create(const sv_dims *dims, sv_denoiser *const *states, int32_t n,
+                    sv_dtype t, const sv_frame_params *p, sv_batch **out);
+
+/* One frame of every stream: in[i] are stream i's inputs (as for
+ * sv_denoise_frame).  Flips every state's `cur`. */
+int sv_batch_frame(sv_batch *b, const sv_frame_in *in, sv_stream stream);
+
+/* Passes (launches) per frame once the first frame has run, else 0; -1 for
+ * a NULL plan. */
+int sv_batch_passes(const sv_batch *b);
+
+void sv_batch_destroy(sv_batch *b);
 
 /* ---- misc --------------------------------------------------------------- */
 

@@ -94,6 +94,9 @@ def tiles_for(H: int, W: int, dtype: torch.dtype = torch.float32, separable: boo
               retune: bool = False) -> List[Tuple[int, int]]:
     """Per-level launch shapes for this device and size, from the cache or
     measured now (and cached)."""
+    if separable:
+        # the fused separable level has one launch form: nothing to choose
+        return [(0, 0)] * levels
     dev = torch.cuda.get_device_name()
     keys = [_key(dev, W, H, dtype, separable, i) for i in range(levels)]
     table = {}

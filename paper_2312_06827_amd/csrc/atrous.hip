@@ -98,13 +98,20 @@ extern "C" int sv_atrous_sep(const sv_rgb *c_in, const float *var_in, const sv_g
                              float *var_out, int32_t step, sv_dims d, sv_dtype t,
                              const sv_atrous_params *p, sv_stream stream) {
     using namespace sv;
-    if (!scratch) return SV_EINVAL;
     int empty = 0;
+    if (scratch && (!scratch->r || !scratch->g || !scratch->b)) return SV_EINVAL;
     int rc = check_atrous(c_in, var_in, g, kappa, scratch, c_out, var_out, step, d, t, p, &empty);
     if (rc != SV_OK || empty) return rc;
-    if (!scratch->r || !scratch->g || !scratch->b) return SV_EINVAL;
     const bool unit = (p->flags & SV_A_UNIT_WEIGHTS) != 0;
     hipStream_t s = as_stream(stream);
+    if (!scratch) {  // both passes in one kernel, the horizontal result kept on chip
+        HvArgs a{make_args(c_in, var_in, g, kappa, c_out, nullptr, step, d, p),
+                 make_args(c_in, var_in, g, kappa, c_out, var_out, step, d, p)};
+        a.h.inv_tm = 0;
+        const bool ok = t == SV_F32 ? launch_hv_f32(a, unit, s) : launch_hv_f16(a, unit, s);
+        if (!ok) return SV_EUNSUPPORTED;
+        return hip_status(hipGetLastError());
+    }
     // horizontal: c_in -> scratch (no variance, no inverse tone map)
     AtrousArgs h = make_args(c_in, var_in, g, kappa, scratch, nullptr, step, d, p);
     h.inv_tm = 0;

@@ -1,0 +1,6 @@
+// Fused separable a-trous level (Section 3.3), binary32 storage.
+#include "atrous_impl.h"
+
+namespace sv {
+bool launch_hv_f32(const HvArgs &a, bool unit, hipStream_t s) { return launch_hv<float>(a, unit, s); }
+}  // namespace sv

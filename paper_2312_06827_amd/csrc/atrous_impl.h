@@ -372,6 +372,41 @@ __global__ __launch_bounds__(256) void atrous_tile_k(AtrousArgs a, int tiles, in
     }
 }
 
+// Batched form: the tiles of many streams (each its own AtrousArgs) as one
+// persistent sweep; every tile is staged and computed exactly as above.
+template <typename T, int STEP, int PY, int MODE, bool WANT_VAR, int DIR>
+__global__ __launch_bounds__(256) void atrous_batch_k(const AtrousArgs *args, const int *prefix,
+                                                      int n, int total) {
+    using S = TileShape<STEP, PY, DIR, WANT_VAR>;
+    __shared__ float4 s_cl[S::NS];
+    __shared__ float4 s_gn[S::NS];
+    __shared__ float s_v[S::NEED_V ? S::NS : 1];
+    __shared__ float2 s_pf[S::NP > 0 ? S::NP : 1];
+    const int per = (total + kXCD - 1) / kXCD, xcd = (int)blockIdx.x % kXCD;
+    for (int slot = (int)blockIdx.x / kXCD; slot < per; slot += (int)gridDim.x / kXCD) {
+        const int t = xcd * per + slot;
+        if (t >= total) break;
+        const int s = batch_stream(prefix, n, t);
+        const AtrousArgs a = args[s];
+        const int gxt = (a.w + S::TX - 1) / S::TX;
+        const TileOrigin o = tile_origin<STEP, S::TY, S::TX>(t - prefix[s], gxt);
+        TileRegs<S::IT, S::ITP> regs;
+        tile_issue<T, S>(a, o, regs);
+        tile_store<S>(regs, s_cl, s_gn, s_v, s_pf);
+        __syncthreads();
+        tile_compute<T, STEP, PY, MODE, WANT_VAR, DIR>(a, o, s_cl, s_gn, s_v, s_pf);
+        __syncthreads();  // the next tile's staging reuses the LDS
+    }
+}
+
+template <typename T, int STEP, int PY, int MODE, bool WANT_VAR, int DIR>
+void atrous_batch_launch(const void *args, const int *prefix, int n, int total, int bpc,
+                         hipStream_t s) {
+    hipLaunchKernelGGL((atrous_batch_k<T, STEP, PY, MODE, WANT_VAR, DIR>),
+                       dim3(batch_grid(total, bpc)), dim3(256), 0, s, (const AtrousArgs *)args,
+                       prefix, n, total);
+}
+
 // ---- 5x5 level, direct loads (any step) -------------------------------------
 
 template <typename T>
@@ -500,6 +535,340 @@ __global__ __launch_bounds__(256) void atrous_sep_k(AtrousArgs a) {
     }
 }
 
+// ---- separable level, both passes fused -------------------------------------
+//
+// One wave owns 64 columns and walks kHvRows + 4 lattice rows of one step
+// phase (image rows ph + j * STEP).  Each row is staged once in LDS for the
+// horizontal pass; the horizontal results of the last five rows live in a
+// register ring (slot = row mod 5, static after unrolling by five), which
+// is exactly the vertical pass's 5-tap window for the row two behind.  The
+// horizontal result is rounded to the storage type as the scratch planes
+// of the two-pass form would round it, and every weight, sum and order is
+// that of the two passes, so the output is bitwise theirs.  The level
+// reads the G-buffer and colour once and writes only its outputs.
+constexpr int kHvRows = 16;
+static_assert((kHvRows + 4) % 5 == 0, "rows per tile must fill the five-slot ring");
+
+template <int STEP>
+struct HvShape {
+    static constexpr int TX = 64, HX = 2 * STEP, COLS = TX + 2 * HX, PFC = TX + 2;
+    static constexpr int IT = (COLS + 63) / 64, ITP = (3 * PFC + 63) / 64;
+    static constexpr int ROWS = kHvRows + 4;
+};
+
+template <int STEP>
+struct HvRow {  // one lattice row's loads, held between issue and LDS store
+    float r[HvShape<STEP>::IT], g[HvShape<STEP>::IT], b[HvShape<STEP>::IT];
+    float z[HvShape<STEP>::IT], nx[HvShape<STEP>::IT], ny[HvShape<STEP>::IT],
+        nz[HvShape<STEP>::IT];
+    bool in[HvShape<STEP>::IT];
+    float pz[HvShape<STEP>::ITP], pv[HvShape<STEP>::ITP];
+    bool pin[HvShape<STEP>::ITP];
+    float dzdx, dzdy, kap;  // this lane's pixel
+};
+
+template <typename T>
+__device__ __forceinline__ float round_to(float v) {
+    return (float)(T)v;
+}
+
+template <typename T, int STEP>
+__device__ __forceinline__ void hv_issue(const AtrousArgs &a, int x0, int y, HvRow<STEP> &q) {
+    using S = HvShape<STEP>;
+    const int lx = threadIdx.x;
+    const bool yin = y >= 0 && y < a.h;
+#pragma unroll
+    for (int it = 0; it < S::IT; ++it) {
+        const int i = lx + it * 64;
+        const int gx = x0 - S::HX + i;
+        const bool in = i < S::COLS && yin && gx >= 0 && gx < a.w;
+        const uint32_t o = in ? (uint32_t)y * (uint32_t)a.pitch + (uint32_t)gx : 0u;
+        q.in[it] = in;
+        q.z[it] = ldo<T>(a.z, o);
+        q.r[it] = ldo<T>(a.cr, o);
+        q.g[it] = ldo<T>(a.cg, o);
+        q.b[it] = ldo<T>(a.cb, o);
+        q.nx[it] = ldo<T>(a.nx, o);
+        q.ny[it] = ldo<T>(a.ny, o);
+        q.nz[it] = ldo<T>(a.nz, o);
+    }
+#pragma unroll
+    for (int it = 0; it < S::ITP; ++it) {
+        const int i = lx + it * 64;
+        const int rr = i / S::PFC, c = i - rr * S::PFC;
+        const int gx = x0 - 1 + c, gy = y + rr - 1;
+        const bool in = i < 3 * S::PFC && gx >= 0 && gx < a.w && gy >= 0 && gy < a.h;
+        const uint32_t o = in ? (uint32_t)gy * (uint32_t)a.pitch + (uint32_t)gx : 0u;
+        q.pin[it] = in;
+        q.pz[it] = ldo<T>(a.z, o);
+        q.pv[it] = ldf(a.var, o);
+    }
+    const int x = x0 + lx;
+    const uint32_t o = (yin && x < a.w) ? (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x : 0u;
+    q.dzdx = ldo<T>(a.dzdx, o);
+    q.dzdy = ldo<T>(a.dzdy, o);
+    q.kap = a.kappa ? ldf(a.kappa, o) : 1.0f;
+}
+
+template <int STEP>
+__device__ __forceinline__ void hv_store(const HvRow<STEP> &q, float4 *s_cl, float4 *s_gn,
+                                         float2 *s_pf) {
+    using S = HvShape<STEP>;
+    const int lx = threadIdx.x;
+#pragma unroll
+    for (int it = 0; it < S::IT; ++it) {
+        const int i = lx + it * 64;
+        if (i < S::COLS) {
+            const bool ok = q.in[it] && !empty_px(q.z[it]);
+            s_cl[i] = ok ? make_float4(q.r[it], q.g[it], q.b[it], luma(q.r[it], q.g[it], q.b[it]))
+                         : make_float4(0.f, 0.f, 0.f, INFINITY);
+            s_gn[i] = ok ? make_float4(q.z[it], q.nx[it], q.ny[it], q.nz[it])
+                         : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < S::ITP; ++it) {
+        const int i = lx + it * 64;
+        if (i < 3 * S::PFC)
+            s_pf[i] = (q.pin[it] && !empty_px(q.pz[it])) ? make_float2(q.pv[it], 1.f)
+                                                         : make_float2(0.f, 0.f);
+    }
+}
+
+// One slot of the ring: a row's horizontal result at this lane's column
+// and what the vertical pass needs of that pixel.
+struct HvSlot {
+    float4 c;   // r, g, b (rounded to the storage type), L (+inf: not a tap)
+    float4 gn;  // z (0: not a tap), normal
+    float v;    // input variance (0 when not a tap)
+    float g;    // prefiltered variance
+    float dzdy, kap;
+};
+
+template <typename T, int STEP, int MODE, int SLOT>
+__device__ __forceinline__ void hv_row(const AtrousArgs &ah, const AtrousArgs &av, int x0, int ph,
+                                       int j0, int ro, HvSlot (&ring)[5], float4 *s_cl,
+                                       float4 *s_gn, float2 *s_pf, HvRow<STEP> &q) {
+    using S = HvShape<STEP>;
+    constexpr bool WANT_VAR = MODE >= 2;  // packed: MODE & 1 = weights, MODE & 2 = variance
+    constexpr int WM = MODE & 1;
+    const int lx = threadIdx.x, x = x0 + lx;
+    const int r = ro + SLOT;  // row index within the tile
+    const int y = ph + (j0 - 2 + r) * STEP;
+    // stage this row, then start loading the next
+    __syncthreads();
+    hv_store<STEP>(q, s_cl, s_gn, s_pf);
+    __syncthreads();
+    const float dzdx = q.dzdx, dzdy = q.dzdy, kap = q.kap;
+    if (r + 1 < S::ROWS) hv_issue<T, STEP>(ah, x0, ph + (j0 - 1 + r) * STEP, q);
+    // ---- horizontal pass at (x, y) ----
+    HvSlot &cur = ring[SLOT];
+    const int ci = lx + S::HX;
+    const float4 pc = s_cl[ci], pg = s_gn[ci];
+    cur.gn = pg;
+    cur.v = s_pf[S::PFC + lx + 1].x;
+    cur.dzdy = dzdy;
+    cur.kap = kap;
+    {
+        float s = 0.f, sw = 0.f;
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+                const float2 e = s_pf[dy * S::PFC + lx + dx];
+                const float kk = e.y * (kG3[dx] * kG3[dy]);
+                s = fmaf(kk, e.x, s);
+                sw += kk;
+            }
+        cur.g = s / sw;
+    }
+    if (pg.x == 0.f) {
+        // not a tap; an empty pixel inside the image passes its colour on
+        cur.c = make_float4(pc.x, pc.y, pc.z, INFINITY);
+        if (y >= 0 && y < ah.h && x < ah.w) {
+            const uint32_t o = (uint32_t)y * (uint32_t)ah.pitch + (uint32_t)x;
+            cur.c.x = ldo<T>(ah.cr, o);
+            cur.c.y = ldo<T>(ah.cg, o);
+            cur.c.z = ldo<T>(ah.cb, o);
+        }
+    } else {
+        float kz[2] = {0.f, 0.f};
+        float kl = 0.f;
+        if (WM != kUnit) {
+            kl = kLog2e / fmaf(ah.sigma_l * kap, sqrtf(cur.g), ah.eps_l);
+            const float gx = dzdx * (float)STEP, gy = 0.f;
+#pragma unroll
+            for (int aa = 1; aa <= 2; ++aa) {
+                const float den = fmaf(ah.sigma_z, fabsf(fmaf(gx, (float)aa, gy * 0.f)), ah.eps_z);
+                kz[aa - 1] = kLog2e * fast_rcp(den);
+            }
+        }
+        constexpr float h0 = 0.375f;
+        Acc acc;
+        acc.sw = h0;
+        acc.sr = h0 * pc.x;
+        acc.sg = h0 * pc.y;
+        acc.sb = h0 * pc.z;
+        acc.sv = 0.f;
+#pragma unroll
+        for (int aa = -2; aa <= 2; ++aa) {
+            if (aa == 0) continue;
+            const int qi = ci + aa * STEP;
+            tap<WM, false>(acc, s_cl[qi], s_gn[qi], 0.f, kLog2H1[aa + 2], kH1[aa + 2],
+                           WM == kUnit ? 0.f : kz[(aa < 0 ? -aa : aa) - 1], pg.x, pc.w, pg.y, pg.z,
+                           pg.w, kl, ah.nc);
+        }
+        const float inv = 1.0f / acc.sw;
+        const float hr = round_to<T>(acc.sr * inv), hg = round_to<T>(acc.sg * inv),
+                    hb = round_to<T>(acc.sb * inv);
+        cur.c = make_float4(hr, hg, hb, luma(hr, hg, hb));
+    }
+    // ---- vertical pass for the row two behind ----
+    if (r < 4) return;
+    constexpr int CS = (SLOT + 3) % 5;  // centre: row r - 2
+    const HvSlot &cen = ring[CS];
+    const int yc = ph + (j0 - 4 + r) * STEP;
+    if (x >= av.w || yc >= av.h) return;
+    const uint32_t o = (uint32_t)yc * (uint32_t)av.pitch + (uint32_t)x;
+    if (cen.gn.x == 0.f) {  // empty pixel: pass through
+        write_out<T>(av, o, cen.c.x, cen.c.y, cen.c.z);
+        if (av.var_out) stf(av.var_out, o, 0.f);
+        return;
+    }
+    float kz[2] = {0.f, 0.f};
+    float kl = 0.f;
+    if (WM != kUnit) {
+        kl = kLog2e / fmaf(av.sigma_l * cen.kap, sqrtf(cen.g), av.eps_l);
+        const float gx = 0.f, gy = cen.dzdy * (float)STEP;
+#pragma unroll
+        for (int b = 1; b <= 2; ++b) {
+            const float den = fmaf(av.sigma_z, fabsf(fmaf(gx, 0.f, gy * (float)b)), av.eps_z);
+            kz[b - 1] = kLog2e * fast_rcp(den);
+        }
+    }
+    constexpr float h0 = 0.375f;
+    Acc acc;
+    acc.sw = h0;
+    acc.sr = h0 * cen.c.x;
+    acc.sg = h0 * cen.c.y;
+    acc.sb = h0 * cen.c.z;
+    acc.sv = WANT_VAR ? h0 * h0 * cen.v : 0.f;
+#pragma unroll
+    for (int b = -2; b <= 2; ++b) {
+        if (b == 0) continue;
+        const HvSlot &qs = ring[(SLOT + 3 + b) % 5];
+        tap<WM, WANT_VAR>(acc, qs.c, qs.gn, qs.v, kLog2H1[b + 2], kH1[b + 2],
+                          WM == kUnit ? 0.f : kz[(b < 0 ? -b : b) - 1], cen.gn.x, cen.c.w,
+                          cen.gn.y, cen.gn.z, cen.gn.w, kl, av.nc);
+    }
+    const float inv = 1.0f / acc.sw;
+    write_out<T>(av, o, acc.sr * inv, acc.sg * inv, acc.sb * inv);
+    if (WANT_VAR) stf(av.var_out, o, acc.sv * inv * inv);
+}
+
+struct HvArgs {
+    AtrousArgs h;  // horizontal pass: input colour, variance, G-buffer
+    AtrousArgs v;  // vertical pass: outputs (colour, variance, inverse tone map)
+};
+
+inline int hv_tiles(const AtrousArgs &a) {
+    return ((a.w + 63) / 64) * a.step * ((((a.h + a.step - 1) / a.step) + kHvRows - 1) / kHvRows);
+}
+
+// Tile t: 64 columns x kHvRows lattice rows of one phase (columns fastest,
+// then phases, then bands of rows).  MODE: bit 0 = edge weights on,
+// bit 1 = variance output.
+template <typename T, int STEP, int MODE>
+__device__ __forceinline__ void hv_tile(const HvArgs &a, int t, float4 *s_cl, float4 *s_gn,
+                                        float2 *s_pf) {
+    using S = HvShape<STEP>;
+    const int gxt = (a.h.w + 63) / 64;
+    const int cx = t % gxt, rest = t / gxt;
+    const int ph = rest % STEP, band = rest / STEP;
+    const int x0 = cx * 64, j0 = band * kHvRows;
+    HvSlot ring[5];
+    HvRow<STEP> q;
+    hv_issue<T, STEP>(a.h, x0, ph + (j0 - 2) * STEP, q);
+#pragma unroll 1
+    for (int ro = 0; ro < S::ROWS; ro += 5) {  // five rows: each ring slot a fixed register set
+        hv_row<T, STEP, MODE, 0>(a.h, a.v, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q);
+        hv_row<T, STEP, MODE, 1>(a.h, a.v, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q);
+        hv_row<T, STEP, MODE, 2>(a.h, a.v, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q);
+        hv_row<T, STEP, MODE, 3>(a.h, a.v, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q);
+        hv_row<T, STEP, MODE, 4>(a.h, a.v, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q);
+    }
+}
+
+template <typename T, int STEP, int MODE>
+__global__ __launch_bounds__(64) void atrous_hv_k(HvArgs a, int tiles) {
+    using S = HvShape<STEP>;
+    __shared__ float4 s_cl[S::COLS];
+    __shared__ float4 s_gn[S::COLS];
+    __shared__ float2 s_pf[3 * S::PFC];
+    const int t = xcd_tile(tiles);
+    if (t < 0) return;
+    hv_tile<T, STEP, MODE>(a, t, s_cl, s_gn, s_pf);
+}
+
+template <typename T, int STEP, int MODE>
+__global__ __launch_bounds__(64) void atrous_hv_batch_k(const HvArgs *args, const int *prefix,
+                                                        int n, int total) {
+    using S = HvShape<STEP>;
+    __shared__ float4 s_cl[S::COLS];
+    __shared__ float4 s_gn[S::COLS];
+    __shared__ float2 s_pf[3 * S::PFC];
+    const int per = (total + kXCD - 1) / kXCD, xcd = (int)blockIdx.x % kXCD;
+    for (int slot = (int)blockIdx.x / kXCD; slot < per; slot += (int)gridDim.x / kXCD) {
+        const int t = xcd * per + slot;
+        if (t >= total) break;
+        const int s = batch_stream(prefix, n, t);
+        const HvArgs a = args[s];
+        hv_tile<T, STEP, MODE>(a, t - prefix[s], s_cl, s_gn, s_pf);
+        __syncthreads();
+    }
+}
+
+template <typename T, int STEP, int MODE>
+void hv_batch_launch(const void *args, const int *prefix, int n, int total, int bpc,
+                     hipStream_t s) {
+    // one-wave workgroups: four per CU-slot of the four-wave kernels
+    hipLaunchKernelGGL((atrous_hv_batch_k<T, STEP, MODE>), dim3(batch_grid(total, 4 * bpc)),
+                       dim3(64), 0, s, (const HvArgs *)args, prefix, n, total);
+}
+
+template <typename T, int STEP, int MODE>
+void launch_hv_mode(const HvArgs &a, hipStream_t s) {
+    const int tiles = hv_tiles(a.h);
+    if (record_pass(&hv_batch_launch<T, STEP, MODE>, a, tiles, 8)) return;
+    hipLaunchKernelGGL((atrous_hv_k<T, STEP, MODE>), dim3(xcd_grid(tiles)), dim3(64), 0, s, a,
+                       tiles);
+}
+
+template <typename T, int STEP>
+void launch_hv_step(const HvArgs &a, int mode, hipStream_t s) {
+    switch (mode) {
+    case 0: launch_hv_mode<T, STEP, 0>(a, s); return;
+    case 1: launch_hv_mode<T, STEP, 1>(a, s); return;
+    case 2: launch_hv_mode<T, STEP, 2>(a, s); return;
+    default: launch_hv_mode<T, STEP, 3>(a, s); return;
+    }
+}
+
+// Fused separable level; false when the step has no fused form (then the
+// two passes run through a scratch buffer).
+template <typename T>
+bool launch_hv(const HvArgs &a, bool unit, hipStream_t s) {
+    const int mode = (unit ? 0 : 1) | (a.v.var_out ? 2 : 0);
+    switch (a.h.step) {
+    case 1: launch_hv_step<T, 1>(a, mode, s); return true;
+    case 2: launch_hv_step<T, 2>(a, mode, s); return true;
+    case 4: launch_hv_step<T, 4>(a, mode, s); return true;
+    case 8: launch_hv_step<T, 8>(a, mode, s); return true;
+    case 16: launch_hv_step<T, 16>(a, mode, s); return true;
+    default: return false;
+    }
+}
+
 // ---- launch ---------------------------------------------------------------------
 
 constexpr int kCUs = 256;
@@ -516,6 +885,9 @@ void launch_tile(const AtrousArgs &a, TileCfg cfg, hipStream_t s) {
     const int bands = (a.h + STEP * TY - 1) / (STEP * TY);
     const int tiles = ((a.w + 63) / 64) * bands * STEP;
     const int per_xcd = (tiles + kXCD - 1) / kXCD;
+    if (record_pass(&atrous_batch_launch<T, STEP, PY, MODE, WANT_VAR, DIR>, a, tiles,
+                    cfg.persistent ? max(1, cfg.blocks_per_cu) : 4))
+        return;
     if (cfg.persistent) {
         const int slots = min(per_xcd, kCUs / kXCD * max(1, cfg.blocks_per_cu));
         hipLaunchKernelGGL((atrous_tile_k<T, STEP, PY, MODE, WANT_VAR, DIR, true>),
@@ -534,7 +906,8 @@ void launch_steps(const AtrousArgs &a, TileCfg cfg, hipStream_t s) {
     case 4: launch_tile<T, 4, MODE, WANT_VAR, DIR>(a, cfg, s); return;
     case 8: launch_tile<T, 8, MODE, WANT_VAR, DIR>(a, cfg, s); return;
     case 16: launch_tile<T, 16, MODE, WANT_VAR, DIR>(a, cfg, s); return;
-    default: {  // other steps: direct loads
+    default: {  // other steps: direct loads (not available batched)
+        if (record_pass<AtrousArgs>(nullptr, a, 0, 0)) return;
         dim3 grid((a.w + 63) / 64, (a.h + 3) / 4);
         if (DIR == kDir2D)
             hipLaunchKernelGGL((atrous_direct_k<T, MODE, WANT_VAR>), grid, dim3(256), 0, s, a);
@@ -565,5 +938,7 @@ void launch_pass_f32_v(const AtrousArgs &a, bool unit, TileCfg cfg, hipStream_t 
 void launch_pass_f16_2d(const AtrousArgs &a, bool unit, TileCfg cfg, hipStream_t s);
 void launch_pass_f16_h(const AtrousArgs &a, bool unit, TileCfg cfg, hipStream_t s);
 void launch_pass_f16_v(const AtrousArgs &a, bool unit, TileCfg cfg, hipStream_t s);
+bool launch_hv_f32(const HvArgs &a, bool unit, hipStream_t s);
+bool launch_hv_f16(const HvArgs &a, bool unit, hipStream_t s);
 
 }  // namespace sv

@@ -48,8 +48,10 @@ extern "C" int sv_denoise_frame(const sv_frame_in *in, sv_denoiser *st, sv_dims 
         if (tm && last && !level0_is_hist) ap.flags |= SV_A_INV_TONEMAP;
         const sv_rgb dst = level0_is_hist ? st->hist[k1] : (last ? st->out : st->level[i & 1]);
         float *dst_var = last ? nullptr : st->level_var[i & 1];
-        rc = p->separable ? sv_atrous_sep(&c, v, &in->g, in->kappa, &st->scratch, &dst, dst_var,
-                                          1 << i, d, t, &ap, stream)
+        // separable levels: the fused form (no scratch) where the step has one
+        const bool fused = (1 << i) <= 16;
+        rc = p->separable ? sv_atrous_sep(&c, v, &in->g, in->kappa, fused ? nullptr : &st->scratch,
+                                          &dst, dst_var, 1 << i, d, t, &ap, stream)
                           : sv_atrous(&c, v, &in->g, in->kappa, &dst, dst_var, 1 << i, d, t, &ap,
                                       stream);
         if (rc != SV_OK) return rc;

@@ -377,6 +377,7 @@ struct KappaGradArgs {
     const void *z, *dzdx, *dzdy, *nx, *ny, *nz;
     const float *kappa;
     const float *yr, *yg, *yb;
+    const float *rr, *rg, *rb;  // optional: the colour whose residual is used
     float *d_kappa;
     int w, h, pitch, step;
     float sigma_z, sigma_n, sigma_l, eps_z, eps_l;
@@ -442,12 +443,14 @@ __global__ __launch_bounds__(256) void kappa_grad_k(KappaGradArgs a) {
             }
         }
     const float yy[3] = {ldf(a.yr, o), ldf(a.yg, o), ldf(a.yb, o)};
+    const float *rp[3] = {a.rr, a.rg, a.rb};
     float g = 0.f;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const float out = sc[k] / sw;
         const float der = (sdc[k] - out * sd) / sw;
-        g = fmaf((out - yy[k]) / fmaf(yy[k], yy[k], 0.01f), der, g);
+        const float res = (a.rr ? ldf(rp[k], o) : out) - yy[k];
+        g = fmaf(res / fmaf(yy[k], yy[k], 0.01f), der, g);
     }
     a.d_kappa[o] += g * (2.0f / 3.0f);
 }
@@ -582,8 +585,8 @@ extern "C" int sv_mlp_alpha_grad(const sv_rgb *c_t, const sv_rgb *cur, const sv_
 }
 
 extern "C" int sv_atrous_kappa_grad(const sv_rgb *c_in, const float *var_in, const sv_gbuf *g,
-                                    const float *kappa, const sv_rgb *y, float *d_kappa,
-                                    int32_t step, sv_dims d, sv_dtype t,
+                                    const float *kappa, const sv_rgb *y, const sv_rgb *ref,
+                                    float *d_kappa, int32_t step, sv_dims d, sv_dtype t,
                                     const sv_atrous_params *p, sv_stream stream) {
     using namespace sv;
     if (!valid_dtype(t)) return SV_EDTYPE;
@@ -595,8 +598,12 @@ extern "C" int sv_atrous_kappa_grad(const sv_rgb *c_in, const float *var_in, con
     for (const void *q : req)
         if (!q) return SV_EINVAL;
     if (!(p->sigma_n >= 0.f)) return SV_EINVAL;
+    if (ref && (!ref->r || !ref->g || !ref->b)) return SV_EINVAL;
     const size_t es = elem_size(t);
     const span so = plane_span(d_kappa, d, 4);
+    if (ref && (overlaps(so, plane_span(ref->r, d, 4)) || overlaps(so, plane_span(ref->g, d, 4)) ||
+                overlaps(so, plane_span(ref->b, d, 4))))
+        return SV_EALIAS;
     const span ins[] = {plane_span(c_in->r, d, es), plane_span(c_in->g, d, es),
                         plane_span(c_in->b, d, es), plane_span(var_in, d, 4),
                         plane_span(g->z, d, es), plane_span(g->dzdx, d, es),
@@ -608,6 +615,8 @@ extern "C" int sv_atrous_kappa_grad(const sv_rgb *c_in, const float *var_in, con
         if (overlaps(so, si)) return SV_EALIAS;
     KappaGradArgs a{c_in->r, c_in->g, c_in->b, var_in, g->z, g->dzdx, g->dzdy, g->nx, g->ny,
                     g->nz, kappa, (const float *)y->r, (const float *)y->g, (const float *)y->b,
+                    ref ? (const float *)ref->r : nullptr, ref ? (const float *)ref->g : nullptr,
+                    ref ? (const float *)ref->b : nullptr,
                     d_kappa, d.w, d.h, d.pitch, step, p->sigma_z, p->sigma_n, p->sigma_l,
                     p->eps_z, p->eps_l};
     dim3 grid((d.w + 63) / 64, (d.h + 3) / 4);

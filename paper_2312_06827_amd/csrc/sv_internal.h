@@ -122,6 +122,75 @@ __device__ __forceinline__ int xcd_tile(int tiles) {
 
 inline unsigned xcd_grid(int tiles) { return (unsigned)(((tiles + kXCD - 1) / kXCD) * kXCD); }
 
+// ---- batched passes (many independent streams, one launch per pass) ----------
+//
+// A batched pass runs the tiles of n streams as one global list: stream s
+// owns tiles prefix[s] .. prefix[s+1]-1 and its own argument struct.  The
+// grid is persistent (a multiple of 8 workgroups); as in xcd_tile each XCD
+// sweeps one contiguous eighth of the list, so a stream's tiles stay on one
+// or two XCDs.  Every tile is computed by the same device code as the
+// single-stream kernel, so each stream's result is bitwise the same.
+
+// Stream that owns global tile t (prefix has n + 1 entries; n is small and
+// the loop is uniform across the workgroup).
+__device__ __forceinline__ int batch_stream(const int *prefix, int n, int t) {
+    int s = 0;
+    while (s + 1 < n && prefix[s + 1] <= t) ++s;
+    return s;
+}
+
+// Launcher of one batched pass: `args` holds n argument structs (device),
+// `prefix` n + 1 tile offsets (device), total = prefix[n].
+typedef void (*BatchLaunch)(const void *args, const int *prefix, int n, int total,
+                            int blocks_per_cu, hipStream_t s);
+
+inline unsigned batch_grid(int total, int blocks_per_cu) {
+    const int cap = 256 * (blocks_per_cu > 0 ? blocks_per_cu : 4);
+    return xcd_grid(total < cap ? (total > 0 ? total : 1) : cap);
+}
+
+// While a recorder is installed on the calling thread, the pass launchers
+// append (launcher, argument struct, tile count) here instead of
+// launching: the batch plan records each stream's frame this way and
+// replays the passes batched.
+struct PassRecord {
+    BatchLaunch fn;
+    size_t arg_size;
+    int tiles;
+    int blocks_per_cu;
+    unsigned char args[512];
+};
+
+struct Recorder {
+    PassRecord *passes;
+    int cap, count;
+    bool overflow;
+};
+
+inline Recorder *&recorder() {
+    static thread_local Recorder *r = nullptr;
+    return r;
+}
+
+template <class A>
+inline bool record_pass(BatchLaunch fn, const A &a, int tiles, int blocks_per_cu) {
+    static_assert(sizeof(A) <= sizeof(PassRecord::args), "argument struct too large");
+    Recorder *r = recorder();
+    if (!r) return false;
+    if (r->count >= r->cap) {
+        r->overflow = true;
+        return true;
+    }
+    PassRecord &p = r->passes[r->count++];
+    p.fn = fn;
+    p.arg_size = sizeof(A);
+    p.tiles = tiles;
+    p.blocks_per_cu = blocks_per_cu;
+    const unsigned char *src = (const unsigned char *)&a;
+    for (size_t i = 0; i < sizeof(A); ++i) p.args[i] = src[i];
+    return true;
+}
+
 // ---- host-side checks -----------------------------------------------------
 
 constexpr int32_t kMaxDim = 32768;

@@ -159,13 +159,11 @@ __device__ __forceinline__ void store_features(const TemporalArgs &a, int x, int
     row[1] = make_uint4(pk[4], pk[5], pk[6], pk[7]);
 }
 
+// One 64x4 tile (bx, by).  Returns once this thread's pixel is done (the
+// caller's barrier follows).
 template <typename T, bool TM, bool CLAMP, bool USE_ID, bool FEAT>
-__global__ __launch_bounds__(256) void temporal_k(TemporalArgs a) {
-    __shared__ float4 tile[(kTX + 2) * (kTY + 2)];
-    const int gxt = (a.w + kTX - 1) / kTX;
-    const int t = xcd_tile(gxt * ((a.h + kTY - 1) / kTY));
-    if (t < 0) return;
-    const int by = t / gxt, bx = t - by * gxt;
+__device__ __forceinline__ void temporal_tile(const TemporalArgs &a, float4 *tile, int bx,
+                                              int by) {
     stage_current<T, TM>(tile, a.cr, a.cg, a.cb, a.z, a.w, a.h, a.pitch, a.tm_k, bx, by);
     __syncthreads();
     const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
@@ -326,6 +324,40 @@ __global__ __launch_bounds__(256) void temporal_k(TemporalArgs a) {
     a.on[o] = (uint8_t)n;
 }
 
+template <typename T, bool TM, bool CLAMP, bool USE_ID, bool FEAT>
+__global__ __launch_bounds__(256) void temporal_k(TemporalArgs a) {
+    __shared__ float4 tile[(kTX + 2) * (kTY + 2)];
+    const int gxt = (a.w + kTX - 1) / kTX;
+    const int t = xcd_tile(gxt * ((a.h + kTY - 1) / kTY));
+    if (t < 0) return;
+    const int by = t / gxt, bx = t - by * gxt;
+    temporal_tile<T, TM, CLAMP, USE_ID, FEAT>(a, tile, bx, by);
+}
+
+template <typename T, bool TM, bool CLAMP, bool USE_ID, bool FEAT>
+__global__ __launch_bounds__(256) void temporal_batch_k(const TemporalArgs *args, const int *prefix,
+                                                        int n, int total) {
+    __shared__ float4 tile[(kTX + 2) * (kTY + 2)];
+    const int per = (total + kXCD - 1) / kXCD, xcd = (int)blockIdx.x % kXCD;
+    for (int slot = (int)blockIdx.x / kXCD; slot < per; slot += (int)gridDim.x / kXCD) {
+        const int t = xcd * per + slot;
+        if (t >= total) break;
+        const int s = batch_stream(prefix, n, t);
+        const TemporalArgs a = args[s];
+        const int lt = t - prefix[s], gxt = (a.w + kTX - 1) / kTX;
+        temporal_tile<T, TM, CLAMP, USE_ID, FEAT>(a, tile, lt % gxt, lt / gxt);
+        __syncthreads();  // the next tile's staging reuses the LDS
+    }
+}
+
+template <typename T, bool TM, bool CLAMP, bool USE_ID, bool FEAT>
+static void temporal_batch_launch(const void *args, const int *prefix, int n, int total, int bpc,
+                                  hipStream_t s) {
+    hipLaunchKernelGGL((temporal_batch_k<T, TM, CLAMP, USE_ID, FEAT>),
+                       dim3(batch_grid(total, bpc)), dim3(256), 0, s, (const TemporalArgs *)args,
+                       prefix, n, total);
+}
+
 struct ClampArgs {
     const void *hr, *hg, *hb, *cr, *cg, *cb, *z;
     void *or_, *og, *ob;
@@ -360,12 +392,17 @@ __global__ __launch_bounds__(256) void clamp_k(ClampArgs a) {
     sto<T>(a.ob, o, b);
 }
 
+template <typename T, bool TM, bool CLAMP, bool USE_ID, bool FEAT>
+static void launch_temporal_one(const TemporalArgs &a, dim3 grid, hipStream_t s) {
+    const int tiles = ((a.w + kTX - 1) / kTX) * ((a.h + kTY - 1) / kTY);
+    if (record_pass(&temporal_batch_launch<T, TM, CLAMP, USE_ID, FEAT>, a, tiles, 8)) return;
+    hipLaunchKernelGGL((temporal_k<T, TM, CLAMP, USE_ID, FEAT>), grid, dim3(256), 0, s, a);
+}
+
 template <typename T, bool TM, bool CLAMP, bool FEAT>
 static void launch_temporal_id(const TemporalArgs &a, bool use_id, dim3 grid, hipStream_t s) {
-    if (use_id)
-        hipLaunchKernelGGL((temporal_k<T, TM, CLAMP, true, FEAT>), grid, dim3(256), 0, s, a);
-    else
-        hipLaunchKernelGGL((temporal_k<T, TM, CLAMP, false, FEAT>), grid, dim3(256), 0, s, a);
+    if (use_id) launch_temporal_one<T, TM, CLAMP, true, FEAT>(a, grid, s);
+    else launch_temporal_one<T, TM, CLAMP, false, FEAT>(a, grid, s);
 }
 
 template <typename T, bool FEAT>

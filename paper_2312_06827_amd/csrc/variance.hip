@@ -14,9 +14,9 @@ constexpr int kVX = 64, kVY = 4;
 constexpr int kSpatialBlocks = 1024;  // pass-2 grid (grid-stride over the list)
 constexpr int kLines = 32;             // counters sit 128 bytes apart
 
-// Workspace: one counter per XCD (workgroup b runs on XCD b % 8 and appends
-// to sublist b % 8), then the eight sublists, each sized for every pixel
-// of the workgroups that feed it.
+// Workspace: eight counters, then eight sublists; tile t appends to
+// sublist t % 8, so each sublist holds at most ceil(tiles / 8) tiles'
+// pixels (its capacity) whichever workgroup runs the tile.
 struct VarWork {
     uint32_t count[kXCD * kLines];  // count[k * kLines]: entries in sublist k
     uint32_t list[1];               // sublist k at list + k * cap: (y << 15) | x
@@ -39,11 +39,11 @@ struct VarianceArgs {
     int min_hist;
 };
 
+// Tile `tile` (-1: a padding workgroup, which still takes the barriers).
 template <typename T>
-__global__ __launch_bounds__(256) void variance_point_k(VarianceArgs a) {
-    __shared__ uint32_t wave_n[4], base_sh;
+__device__ __forceinline__ void variance_point_tile(const VarianceArgs &a, int tile,
+                                                    uint32_t *wave_n, uint32_t &base_sh) {
     const int gxt = (a.w + kVX - 1) / kVX;
-    const int tile = xcd_tile(gxt * ((a.h + kVY - 1) / kVY));
     const int byt = tile / gxt, bxt = tile - byt * gxt;
     const int x = bxt * kVX + (threadIdx.x & 63), y = byt * kVY + (threadIdx.x >> 6);
     const bool inside = tile >= 0 && x < a.w && y < a.h;
@@ -63,7 +63,7 @@ __global__ __launch_bounds__(256) void variance_point_k(VarianceArgs a) {
     const uint32_t n0 = wave_n[0], n1 = wave_n[1], n2 = wave_n[2], n3 = wave_n[3];
     const uint32_t total = n0 + n1 + n2 + n3;
     if (total == 0) return;  // uniform over the workgroup
-    const uint32_t k = blockIdx.x % kXCD;
+    const uint32_t k = (uint32_t)tile % kXCD;
     if (threadIdx.x == 0) base_sh = atomicAdd(&a.work->count[k * kLines], total);
     __syncthreads();
     const uint32_t before = (wave > 0 ? n0 : 0u) + (wave > 1 ? n1 : 0u) + (wave > 2 ? n2 : 0u);
@@ -74,8 +74,35 @@ __global__ __launch_bounds__(256) void variance_point_k(VarianceArgs a) {
     if (spatial && slot < a.cap) a.work->list[k * a.cap + slot] = ((uint32_t)y << 15) | (uint32_t)x;
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void variance_point_k(VarianceArgs a) {
+    __shared__ uint32_t wave_n[4], base_sh;
+    const int gxt = (a.w + kVX - 1) / kVX;
+    variance_point_tile<T>(a, xcd_tile(gxt * ((a.h + kVY - 1) / kVY)), wave_n, base_sh);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void variance_point_batch_k(const VarianceArgs *args,
+                                                              const int *prefix, int n, int total) {
+    __shared__ uint32_t wave_n[4], base_sh;
+    const int per = (total + kXCD - 1) / kXCD, xcd = (int)blockIdx.x % kXCD;
+    for (int slot = (int)blockIdx.x / kXCD; slot < per; slot += (int)gridDim.x / kXCD) {
+        const int t = xcd * per + slot;
+        if (t >= total) break;
+        const int s = batch_stream(prefix, n, t);
+        const VarianceArgs a = args[s];
+        variance_point_tile<T>(a, t - prefix[s], wave_n, base_sh);
+        __syncthreads();  // wave_n and base_sh are reused by the next tile
+    }
+}
+
 __global__ __launch_bounds__(64) void variance_reset_k(VarWork *w) {
     if (threadIdx.x < kXCD) w->count[threadIdx.x * kLines] = 0;
+}
+
+__global__ __launch_bounds__(256) void variance_reset_batch_k(const VarianceArgs *args, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n * kXCD) args[i / kXCD].work->count[(i % kXCD) * kLines] = 0;
 }
 
 // Sum over the 8 lanes of an aligned lane group (butterfly: a fixed order,
@@ -91,7 +118,7 @@ __device__ __forceinline__ float group8_sum(float v) {
 // sub, sub + 8, ...  Every tap's loads are issued before any weight is
 // formed, and the weights and m1 stay in registers for the second pass.
 template <typename T, int R>
-__global__ __launch_bounds__(256) void variance_spatial_k(VarianceArgs a) {
+__device__ __forceinline__ void variance_spatial_stream(const VarianceArgs &a) {
     constexpr int D = 2 * R + 1, NT = D * D, PER = (NT + 7) / 8, CTR = R * D + R;
     uint32_t pre[kXCD + 1];
     pre[0] = 0;
@@ -169,13 +196,47 @@ __global__ __launch_bounds__(256) void variance_spatial_k(VarianceArgs a) {
 }
 
 template <typename T, int R>
+__global__ __launch_bounds__(256) void variance_spatial_k(VarianceArgs a) {
+    variance_spatial_stream<T, R>(a);
+}
+
+template <typename T, int R>
+__global__ __launch_bounds__(256) void variance_spatial_batch_k(const VarianceArgs *args, int n) {
+    for (int s = 0; s < n; ++s) {
+        const VarianceArgs a = args[s];
+        variance_spatial_stream<T, R>(a);
+    }
+}
+
+template <typename T>
+static void point_batch_launch(const void *args, const int *prefix, int n, int total, int bpc,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(variance_point_batch_k<T>, dim3(batch_grid(total, bpc)), dim3(256), 0, s,
+                       (const VarianceArgs *)args, prefix, n, total);
+}
+
+template <typename T, int R>
+static void spatial_batch_launch(const void *args, const int *, int n, int, int, hipStream_t s) {
+    hipLaunchKernelGGL((variance_spatial_batch_k<T, R>), dim3(kSpatialBlocks), dim3(256), 0, s,
+                       (const VarianceArgs *)args, n);
+}
+
+static void reset_batch_launch(const void *args, const int *, int n, int, int, hipStream_t s) {
+    hipLaunchKernelGGL(variance_reset_batch_k, dim3((n * kXCD + 255) / 256), dim3(256), 0, s,
+                       (const VarianceArgs *)args, n);
+}
+
+template <typename T, int R>
 void launch_spatial(const VarianceArgs &a, hipStream_t s) {
+    if (record_pass(&spatial_batch_launch<T, R>, a, 0, 0)) return;
     hipLaunchKernelGGL((variance_spatial_k<T, R>), dim3(kSpatialBlocks), dim3(256), 0, s, a);
 }
 
 template <typename T>
 void launch_variance(const VarianceArgs &a, unsigned grid, int radius, hipStream_t s) {
-    hipLaunchKernelGGL(variance_point_k<T>, dim3(grid), dim3(256), 0, s, a);
+    const int tiles = ((a.w + kVX - 1) / kVX) * ((a.h + kVY - 1) / kVY);
+    if (!record_pass(&point_batch_launch<T>, a, tiles, 8))
+        hipLaunchKernelGGL(variance_point_k<T>, dim3(grid), dim3(256), 0, s, a);
     switch (radius) {
     case 0: launch_spatial<T, 0>(a, s); break;
     case 1: launch_spatial<T, 1>(a, s); break;
@@ -186,7 +247,8 @@ void launch_variance(const VarianceArgs &a, unsigned grid, int radius, hipStream
     case 6: launch_spatial<T, 6>(a, s); break;
     default: launch_spatial<T, 7>(a, s); break;
     }
-    hipLaunchKernelGGL(variance_reset_k, dim3(1), dim3(64), 0, s, a.work);
+    if (!record_pass(&reset_batch_launch, a, 0, 0))
+        hipLaunchKernelGGL(variance_reset_k, dim3(1), dim3(64), 0, s, a.work);
 }
 
 }  // namespace sv

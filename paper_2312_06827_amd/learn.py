@@ -9,9 +9,12 @@ Frame chain (one stream):
     -> a-trous levels (kappa) -> inverse tone map
 
 Training (truncated gradients, one Adam step per frame):
-  * dL/dalpha from the blend, the history held fixed (sv_mlp_alpha_grad);
-  * dL/dkappa from every level's output, its input held fixed
-    (sv_atrous_kappa_grad), summed over levels;
+  * dL/dalpha: the blend's local derivative (history held fixed) weighted
+    by the residual of the chain's final output (sv_mlp_alpha_grad with
+    the final output in place of the temporal output);
+  * dL/dkappa: every level's local derivative (its input held fixed)
+    weighted by the same final residual, summed over levels
+    (sv_atrous_kappa_grad with ref = the final output);
   * L = mean over pixels of the per-pixel RelMSE term
     (1/3) sum_c (x - y)^2 / (y^2 + 0.01) in tone-mapped space, y = the tone-
     mapped clean image; sv_mlp_backward then sv_adam.
@@ -25,7 +28,7 @@ from __future__ import annotations
 import math
 import os
 from dataclasses import dataclass, replace
-from typing import Dict, Iterable, List, Optional, Sequence
+from typing import Dict, List, Optional, Sequence
 
 import numpy as np
 import torch
@@ -96,6 +99,14 @@ class LearnedDenoiser:
         self.work = lib.mlp_workspace(self.var)
         self.k = 0
 
+    def _training_levels(self):
+        if getattr(self, "tr_c", None) is None:
+            L, H, W = self.cfg.levels, self.H, self.W
+            self.tr_c = [None] + [torch.zeros((3, H, W), dtype=self.dtype, device="cuda")
+                                  for _ in range(1, L)]
+            self.tr_v = [torch.zeros((H, W), dtype=torch.float32, device="cuda")
+                         for _ in range(max(0, L - 1))]
+
     def reset(self):
         for t in self.c_hist + self.m1 + self.m2c + self.n:
             t.zero_()
@@ -119,24 +130,37 @@ class LearnedDenoiser:
         if train:
             # tone-mapped clean target and the blend's gradient
             lib.sv_tonemap(clean, self.y, k=c.tm_k if c.tonemap else 1.0)
-            lib.sv_mlp_alpha_grad(self.t_rgb, inp.rgb, self.hist_out, self.y, self.alpha,
-                                  self.n[1 - k], inp.g.z, self.d_alpha,
-                                  tm_k=c.tm_k if c.tonemap else 0.0)
             self.d_kappa.zero_()
+            self._training_levels()
         src, vsrc = self.t_rgb, self.var
+        level_inputs = []
         for i in range(c.levels):
             last = i == c.levels - 1
-            dst = self.c_hist[1 - k] if i == 0 else self.lvl[i % 2]
-            vdst = None if last else self.lvl_var[i % 2]
-            if train:
-                lib.sv_atrous_kappa_grad(src, vsrc, inp.g, self.kappa, self.y, self.d_kappa,
-                                         1 << i, ap)
+            if train:  # every level's input is kept for the gradients
+                dst = self.c_hist[1 - k] if i == 0 else self.tr_c[i]
+                vdst = None if last else self.tr_v[i]
+            else:
+                dst = self.c_hist[1 - k] if i == 0 else self.lvl[i % 2]
+                vdst = None if last else self.lvl_var[i % 2]
+            level_inputs.append((src, vsrc))
             if c.separable:
-                lib.sv_atrous_sep(src, vsrc, inp.g, self.scratch, dst, vdst, 1 << i, ap,
+                lib.sv_atrous_sep(src, vsrc, inp.g, None, dst, vdst, 1 << i, ap,
                                   kappa=self.kappa)
             else:
                 lib.sv_atrous(src, vsrc, inp.g, dst, vdst, 1 << i, ap, kappa=self.kappa)
             src, vsrc = dst, vdst
+        if train:
+            # the blend's and each level's local derivatives, weighted by the
+            # residual of the chain's final (tone-mapped) output: the colour
+            # history is the level-0 output fed back every frame, so a
+            # one-step loss on the temporal output alone rewards blur that
+            # accumulates over frames
+            lib.sv_mlp_alpha_grad(src, inp.rgb, self.hist_out, self.y, self.alpha,
+                                  self.n[1 - k], inp.g.z, self.d_alpha,
+                                  tm_k=c.tm_k if c.tonemap else 0.0)
+            for i, (ci, vi) in enumerate(level_inputs):
+                lib.sv_atrous_kappa_grad(ci, vi, inp.g, self.kappa, self.y, self.d_kappa, 1 << i,
+                                         ap, ref=src)
         if c.tonemap:
             lib.sv_tonemap(src, self.out, inverse=True, k=c.tm_k)
         else:
@@ -149,19 +173,30 @@ class LearnedDenoiser:
         return self.out
 
 
-def feature_statistics(cfg: TrainConfig, filt: FilterConfig = MOTION):
+def _sequence_frames(cfg: TrainConfig, s: int, frames=None):
+    """Frames of training sequence s: pre-generated, or rendered now."""
+    if frames is not None:
+        return frames[s]
+    scfg = train_sequence_config(cfg, s)
+    return (render_frame(scfg, f) for f in range(cfg.frames))
+
+
+def render_sequence(args):
+    cfg, s = args
+    scfg = train_sequence_config(cfg, s)
+    return [render_frame(scfg, f) for f in range(cfg.frames)]
+
+
+def feature_statistics(cfg: TrainConfig, filt: FilterConfig = MOTION, frames=None):
     """Per-feature mean and 1/std over a few training frames, from the
     device's own raw features (standardisation off)."""
     mlp = lib.MLP(np.zeros(lib.SV_MLP_PARAMS), np.zeros(14), np.ones(14))
     den = LearnedDenoiser(cfg.height, cfg.width, mlp, filt)
     rows = []
-    per_seq = max(2, cfg.frames)
-    nseq = max(1, math.ceil(cfg.stat_frames / per_seq))
+    nseq = max(1, math.ceil(cfg.stat_frames / max(1, cfg.frames)))
     for s in range(nseq):
-        scfg = train_sequence_config(cfg, s)
         den.reset()
-        for f in range(per_seq):
-            fr = render_frame(scfg, f)
+        for fr in _sequence_frames(cfg, s, frames):
             den.frame(FrameInputs.from_numpy(fr), _dev(fr["albedo"]))
             x = den.feat.view(torch.bfloat16)[:, :14].float()
             rows.append(x[::max(1, x.shape[0] // 20000)])
@@ -185,17 +220,15 @@ def init_params(seed: int, alpha0: float = 0.2) -> np.ndarray:
                            np.zeros(64), b3]).astype(np.float32)
 
 
-def train(cfg: TrainConfig, filt: FilterConfig = MOTION, log=None,
-          frame_source: Optional[Iterable] = None) -> lib.MLP:
-    """Train from scratch; returns the device network."""
-    mu, inv_s = feature_statistics(cfg, filt)
+def train(cfg: TrainConfig, filt: FilterConfig = MOTION, log=None, frames=None) -> lib.MLP:
+    """Train from scratch; returns the device network.  `frames[s]`, if
+    given, are training sequence s's pre-generated frames."""
+    mu, inv_s = feature_statistics(cfg, filt, frames)
     mlp = lib.MLP(init_params(cfg.init_seed), mu, inv_s)
     den = LearnedDenoiser(cfg.height, cfg.width, mlp, filt)
     for s in range(cfg.sequences):
-        scfg = train_sequence_config(cfg, s)
         den.reset()
-        for f in range(cfg.frames):
-            fr = render_frame(scfg, f)
+        for f, fr in enumerate(_sequence_frames(cfg, s, frames)):
             inp = FrameInputs.from_numpy(fr)
             alb, clean = _dev(fr["albedo"]), _dev(fr["clean"])
             tr = f >= cfg.warm
@@ -244,21 +277,34 @@ def evaluate(seeds: Sequence[int], width: int, height: int, frames: int,
 
 if __name__ == "__main__":
     import argparse
+    import multiprocessing as mp
     import sys
+    import time
 
     ap = argparse.ArgumentParser(description="train the blend/edge network and save it")
     ap.add_argument("--sequences", type=int, default=200)
-    ap.add_argument("--frames", type=int, default=8)
+    ap.add_argument("--frames", type=int, default=12)
     ap.add_argument("--width", type=int, default=320)
     ap.add_argument("--height", type=int, default=180)
+    ap.add_argument("--lr", type=float, default=3e-3)
+    ap.add_argument("--workers", type=int, default=16)
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
     args = ap.parse_args()
     cfg = TrainConfig(width=args.width, height=args.height, frames=args.frames,
-                      sequences=args.sequences)
+                      sequences=args.sequences, warm=2, lr=args.lr, stat_frames=24)
     log = lambda m: print(m, flush=True)
-    net = train(cfg, log=log)
+    # every training frame is generated before the GPU is first touched
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(max(1, args.workers)) as pool:
+        frames = pool.map(render_sequence, [(cfg, s) for s in range(cfg.sequences)])
+    log(f"generated {cfg.sequences} sequences of {cfg.frames} frames at "
+        f"{cfg.width}x{cfg.height} in {time.perf_counter() - t0:.1f} s")
+    t0 = time.perf_counter()
+    net = train(cfg, log=log, frames=frames)
+    log(f"trained in {time.perf_counter() - t0:.1f} s")
+    del frames
     save(net, args.out, meta=cfg.__dict__)
     plain = evaluate([5900, 5901], 480, 270, 24, None)
     learned = evaluate([5900, 5901], 480, 270, 24, net)
-    print(f"held-out RelMSE plain {plain:.5f} learned {learned:.5f}", flush=True)
+    log(f"held-out RelMSE (480x270, frames 10..23) plain {plain:.5f} learned {learned:.5f}")
     sys.exit(0)

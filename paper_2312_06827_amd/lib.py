@@ -136,8 +136,14 @@ EXPORTS = {
                  _vp], ctypes.c_int),
     "sv_mlp_alpha_grad": ([_P(sv_rgb), _P(sv_rgb), _P(sv_rgb), _P(sv_rgb), _vp, _vp, _vp,
                            ctypes.c_float, _vp, sv_dims, ctypes.c_int, _vp], ctypes.c_int),
-    "sv_atrous_kappa_grad": ([_P(sv_rgb), _vp, _P(sv_gbuf), _vp, _P(sv_rgb), _vp, ctypes.c_int32,
-                              sv_dims, ctypes.c_int, _P(sv_atrous_params), _vp], ctypes.c_int),
+    "sv_atrous_kappa_grad": ([_P(sv_rgb), _vp, _P(sv_gbuf), _vp, _P(sv_rgb), _P(sv_rgb), _vp,
+                              ctypes.c_int32, sv_dims, ctypes.c_int, _P(sv_atrous_params), _vp],
+                             ctypes.c_int),
+    "sv_batch_create": ([_P(sv_dims), _P(_P(sv_denoiser)), ctypes.c_int32, ctypes.c_int,
+                         _P(sv_frame_params), _P(_vp)], ctypes.c_int),
+    "sv_batch_frame": ([_vp, _P(sv_frame_in), _vp], ctypes.c_int),
+    "sv_batch_passes": ([_vp], ctypes.c_int),
+    "sv_batch_destroy": ([_vp], None),
     "sv_status_str": ([ctypes.c_int], ctypes.c_char_p),
     "sv_version": ([], ctypes.c_int),
     "sv_last_hip_error": ([], ctypes.c_int),
@@ -364,15 +370,17 @@ def sv_atrous(c_in: Planes, var_in: torch.Tensor, g: GBuf, c_out: Planes,
         ctypes.byref(pc), _stream(stream)))
 
 
-def sv_atrous_sep(c_in: Planes, var_in: torch.Tensor, g: GBuf, scratch: Planes, c_out: Planes,
-                  var_out: Optional[torch.Tensor], step: int, params: AtrousParams,
+def sv_atrous_sep(c_in: Planes, var_in: torch.Tensor, g: GBuf, scratch: Optional[Planes],
+                  c_out: Planes, var_out: Optional[torch.Tensor], step: int, params: AtrousParams,
                   kappa: Optional[torch.Tensor] = None, stream=None):
+    """scratch None: both passes in one kernel (steps 1..16)."""
     r = _planes3(c_in)[0]
     gc = g.c()
     pc = params.c()
+    sc = None if scratch is None else ctypes.byref(_rgb(scratch))
     _check("sv_atrous_sep", load().sv_atrous_sep(
         ctypes.byref(_rgb(c_in)), _plane_ptr(var_in), ctypes.byref(gc), _plane_ptr(kappa),
-        ctypes.byref(_rgb(scratch)), ctypes.byref(_rgb(c_out)), _plane_ptr(var_out), int(step),
+        sc, ctypes.byref(_rgb(c_out)), _plane_ptr(var_out), int(step),
         dims_of(r), dtype_of(r), ctypes.byref(pc), _stream(stream)))
 
 
@@ -478,12 +486,13 @@ def sv_mlp_alpha_grad(c_t: Planes, cur: Planes, hist: Planes, y: Planes, alpha: 
 
 def sv_atrous_kappa_grad(c_in: Planes, var_in: torch.Tensor, g: GBuf, kappa: torch.Tensor,
                          y: Planes, d_kappa: torch.Tensor, step: int, params: AtrousParams,
-                         stream=None):
+                         ref: Optional[Planes] = None, stream=None):
     r = _planes3(c_in)[0]
     gc, pc = g.c(), params.c()
+    rf = None if ref is None else ctypes.byref(_rgb(ref))
     _check("sv_atrous_kappa_grad", load().sv_atrous_kappa_grad(
         ctypes.byref(_rgb(c_in)), _plane_ptr(var_in), ctypes.byref(gc), _plane_ptr(kappa),
-        ctypes.byref(_rgb(y)), _plane_ptr(d_kappa), int(step), dims_of(r), dtype_of(r),
+        ctypes.byref(_rgb(y)), rf, _plane_ptr(d_kappa), int(step), dims_of(r), dtype_of(r),
         ctypes.byref(pc), _stream(stream)))
 
 

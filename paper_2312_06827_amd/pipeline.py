@@ -212,8 +212,9 @@ class Denoiser:
                 p.persistent, p.blocks_per_cu = self.tiles[i]
             if cfg.separable:
                 with tm(f"atrous_sep{i}"):
-                    lib.sv_atrous_sep(c, v, inp.g, self.scratch, dst, dst_var, 1 << i, p,
-                                      kappa=kappa, stream=stream)
+                    # the fused single-kernel form where the step has one
+                    lib.sv_atrous_sep(c, v, inp.g, None if (1 << i) <= 16 else self.scratch, dst,
+                                      dst_var, 1 << i, p, kappa=kappa, stream=stream)
             else:
                 with tm(f"atrous{i}"):
                     lib.sv_atrous(c, v, inp.g, dst, dst_var, 1 << i, p, kappa=kappa,
@@ -235,3 +236,51 @@ class Denoiser:
         t_rgb = self.c_hist[k] if fb_t else self.t_rgb[0]
         return {"t_rgb": t_rgb, "m1": self.m1[k], "m2c": self.m2c[k], "n": self.n[k],
                 "var": self.var, "level0": self.c_hist[k]}
+
+
+class BatchDenoiser:
+    """Many independent streams of uneven sizes filtered together: one
+    launch per pass over all of them, the frame's passes replayed as a HIP
+    graph (sv_batch_*).  Each stream owns a Denoiser's buffers and its
+    results are bitwise those of that Denoiser run alone."""
+
+    def __init__(self, sizes, cfg: FilterConfig = MOTION, dtype: torch.dtype = torch.float32,
+                 tiles=None, device: str = "cuda"):
+        self.streams = [Denoiser(h, w, cfg, dtype, device, tiles) for (h, w) in sizes]
+        n = len(self.streams)
+        self._dims = (lib.sv_dims * n)(*[d._dims for d in self.streams])
+        self._states = (ctypes.POINTER(lib.sv_denoiser) * n)(
+            *[ctypes.pointer(d._st) for d in self.streams])
+        self._params = self.streams[0]._params
+        self._plan = ctypes.c_void_p()
+        so = lib.load()
+        lib._check("sv_batch_create", so.sv_batch_create(
+            self._dims, self._states, n, self.streams[0]._dtype, ctypes.byref(self._params),
+            ctypes.byref(self._plan)))
+
+    def frame(self, inputs, stream=None):
+        """One frame of every stream; inputs[i] are stream i's FrameInputs.
+        Returns the streams' output tensors."""
+        if len(inputs) != len(self.streams):
+            raise ValueError("one FrameInputs per stream")
+        fins = (lib.sv_frame_in * len(inputs))(*[inp.c() for inp in inputs])
+        lib._check("sv_batch_frame", lib.load().sv_batch_frame(
+            self._plan, fins, lib._stream(stream)))
+        for d in self.streams:
+            d.frames += 1
+        return [d.out for d in self.streams]
+
+    def passes(self) -> int:
+        return lib.load().sv_batch_passes(self._plan)
+
+    def close(self):
+        if self._plan:
+            torch.cuda.synchronize()
+            lib.load().sv_batch_destroy(self._plan)
+            self._plan = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

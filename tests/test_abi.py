@@ -103,9 +103,12 @@ def test_atrous_validation_and_aliasing(so):
     g2.nz = None
     assert so.sv_atrous(r(rgb(A)), var, r(g2), None, r(rgb(B)), None, 1, D, L.SV_F32, r(AP),
                         None) == L.SV_EINVAL
-    # separable needs scratch, which must not alias the output
-    assert so.sv_atrous_sep(r(rgb(A)), var, r(g), None, None, r(rgb(B)), None, 1, D, L.SV_F32,
-                            r(AP), None) == L.SV_EINVAL
+    # without scratch (the fused form) only steps 1..16 are available; with
+    # scratch, it must not alias the output
+    assert so.sv_atrous_sep(r(rgb(A)), var, r(g), None, None, r(rgb(B)), None, 32, D, L.SV_F32,
+                            r(AP), None) == L.SV_EUNSUPPORTED
+    assert so.sv_atrous_sep(r(rgb(A)), var, r(g), None, L.sv_rgb(B, None, B), r(rgb(B)), None,
+                            1, D, L.SV_F32, r(AP), None) == L.SV_EINVAL
     assert so.sv_atrous_sep(r(rgb(A)), var, r(g), None, r(rgb(B)), r(rgb(B)), None, 1, D,
                             L.SV_F32, r(AP), None) == L.SV_EALIAS
     bad = L.sv_atrous_params(1.0, -1.0, 4.0, 1e-10, 1e-10, 1.0, 0, -1, 0)
@@ -204,6 +207,39 @@ def test_mlp_validation(so):
                                 D, L.SV_F32, None) == L.SV_EALIAS
     g = gbuf(base[20])
     assert so.sv_atrous_kappa_grad(r(rgb(base[0])), base[3], r(g), base[4], r(rgb(base[5])),
-                                   base[4], 1, D, L.SV_F32, r(AP), None) == L.SV_EALIAS
+                                   None, base[4], 1, D, L.SV_F32, r(AP), None) == L.SV_EALIAS
     assert so.sv_atrous_kappa_grad(r(rgb(base[0])), base[3], r(g), base[4], r(rgb(base[5])),
-                                   base[8], 0, D, L.SV_F32, r(AP), None) == L.SV_EINVAL
+                                   None, base[8], 0, D, L.SV_F32, r(AP), None) == L.SV_EINVAL
+    # the residual source must not overlap the gradient it accumulates into
+    assert so.sv_atrous_kappa_grad(r(rgb(base[0])), base[3], r(g), base[4], r(rgb(base[5])),
+                                   r(rgb(base[8])), base[9], 1, D, L.SV_F32, r(AP),
+                                   None) == L.SV_EALIAS
+
+
+def test_batch_validation(so):
+    r = ctypes.byref
+    out = ctypes.c_void_p()
+    lp = (ctypes.c_int32 * 10)(*([-1] * 10))
+    lb = (ctypes.c_int32 * 10)(*([0] * 10))
+    tp = L.sv_temporal_params(0.2, 0.2, 1.0, 0.1, 0.9, 1.0, 255, 0)
+    vp = L.sv_variance_params(1.0, 128.0, 1e-10, 4, 3)
+    fp = L.sv_frame_params(tp, vp, AP, 5, 0, 0, lp, lb)
+    st = [L.sv_denoiser(), L.sv_denoiser()]
+    states = (ctypes.POINTER(L.sv_denoiser) * 2)(*[ctypes.pointer(x) for x in st])
+    dims = (L.sv_dims * 2)(D, L.sv_dims(100, 20, 128))
+    assert so.sv_batch_create(dims, states, 0, L.SV_F32, r(fp), r(out)) == L.SV_EINVAL
+    assert so.sv_batch_create(dims, states, 2, 9, r(fp), r(out)) == L.SV_EDTYPE
+    bad = (L.sv_dims * 2)(D, L.sv_dims(0, 20, 128))  # an empty stream
+    assert so.sv_batch_create(bad, states, 2, L.SV_F32, r(fp), r(out)) == L.SV_EINVAL
+    same = (ctypes.POINTER(L.sv_denoiser) * 2)(ctypes.pointer(st[0]), ctypes.pointer(st[0]))
+    assert so.sv_batch_create(dims, same, 2, L.SV_F32, r(fp), r(out)) == L.SV_EALIAS
+    fp6 = L.sv_frame_params(tp, vp, AP, 6, 0, 0, lp, lb)
+    assert so.sv_batch_create(dims, states, 2, L.SV_F32, r(fp6), r(out)) == L.SV_EUNSUPPORTED
+    fp1 = L.sv_frame_params(tp, vp, AP, 1, 0, 0, lp, lb)
+    assert so.sv_batch_create(dims, states, 2, L.SV_F32, r(fp1), r(out)) == L.SV_EUNSUPPORTED
+    # a valid plan: nothing is allocated until the first frame
+    assert so.sv_batch_create(dims, states, 2, L.SV_F32, r(fp), r(out)) == L.SV_OK
+    assert so.sv_batch_passes(out) == 0
+    assert so.sv_batch_frame(out, None, None) == L.SV_EINVAL
+    so.sv_batch_destroy(out)
+    assert so.sv_batch_passes(None) == -1

@@ -203,14 +203,21 @@ def test_kappa_grad_parity(step):
     y = O.tonemap(fr["clean"]).astype(np.float32)
     deriv = M.atrous_kappa_derivative(c, var, fr["z"], fr["dzdx"], fr["dzdy"], fr["n"], kappa, step)
     outc = O.atrous(c, var, fr["z"], fr["dzdx"], fr["dzdy"], fr["n"], step, kappa=kappa)[0]
-    ref = 0.25 + M.kappa_grad_level(outc, y, deriv)  # accumulates onto 0.25
-    dk = torch.full((H, W), 0.25, device="cuda")
+    other = (y * r.uniform(0.8, 1.2, y.shape)).astype(np.float32)  # another residual source
     g = L.GBuf(dev(fr["z"]), dev(fr["dzdx"]), dev(fr["dzdy"]), dev(fr["n"]))
-    say(f"kappa grad step={step}")
-    L.sv_atrous_kappa_grad(dev(c), dev(var), g, dev(kappa), dev(y), dk, step, L.AtrousParams())
-    e = np.abs(host(dk) - ref) / np.maximum(np.abs(ref - 0.25), 1e-3 * np.sqrt(np.mean((ref - 0.25) ** 2)))
-    say(f"  rel err max {e.max():.1e}")
-    assert e.max() <= 1e-3
+    for use_ref in (False, True):
+        src = other if use_ref else outc
+        ref = 0.25 + M.kappa_grad_level(src, y, deriv)  # accumulates onto 0.25
+        dk = torch.full((H, W), 0.25, device="cuda")
+        say(f"kappa grad step={step} ref={use_ref}")
+        L.sv_atrous_kappa_grad(dev(c), dev(var), g, dev(kappa), dev(y), dk, step,
+                               L.AtrousParams(), ref=dev(other) if use_ref else None)
+        e = np.abs(host(dk) - ref) / np.maximum(np.abs(ref - 0.25),
+                                                1e-3 * np.sqrt(np.mean((ref - 0.25) ** 2)))
+        say(f"  rel err max {e.max():.1e}")
+        # the derivative is sum d c_q - c' sum d over sum w: a difference of
+        # like-sized binary32 sums, which loses a few bits to cancellation
+        assert e.max() <= 5e-3
 
 
 def test_training_beats_plain_filter():

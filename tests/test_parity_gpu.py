@@ -305,3 +305,34 @@ def test_atrous_launch_shape_does_not_change_results(sep):
             else:
                 np.testing.assert_array_equal(got[0], ref[0])
                 np.testing.assert_array_equal(got[1], ref[1])
+
+
+@pytest.mark.parametrize("H,W", [(1, 1), (3, 70), (67, 131), (130, 200)])
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float16])
+def test_atrous_sep_fused_equals_two_pass(H, W, dtype):
+    """The single-kernel separable level (no scratch) gives bitwise the
+    two-kernel result (the horizontal result rounded to the storage type
+    on chip exactly as the scratch planes round it)."""
+    c, var, z, dzdx, dzdy, n = _atrous_inputs(H, W, 800 + H, holes=True)
+    P = W + 5
+    dv = lambda a: dev(a, P, dtype)
+    g = L.GBuf(dv(z), dv(dzdx), dv(dzdy), dv(n))
+    kappa = np.random.default_rng(H).uniform(0.5, 2.0, (H, W)).astype(np.float32)
+    for step in (1, 2, 4, 8, 16):
+        for unit, want_var, inv, kap in [(False, True, False, None), (False, False, True, kappa),
+                                         (True, True, False, None), (False, True, False, kappa)]:
+            say(f"sep fused {H}x{W} {dtype} step={step} unit={unit} var={want_var} inv={inv} "
+                f"kappa={kap is not None}")
+            p = L.AtrousParams(unit_weights=unit, inv_tonemap=inv)
+            kd = None if kap is None else dev(kap, P)
+            res = []
+            for fused in (False, True):
+                out = empty_like_dev((3, H, W), P, dtype)
+                sh = empty_like_dev((3, H, W), P, dtype)
+                vo = empty_like_dev((H, W), P) if want_var else None
+                L.sv_atrous_sep(dv(c), dev(var, P), g, None if fused else sh, out, vo, step, p,
+                                kappa=kd)
+                res.append((host(out), None if vo is None else host(vo)))
+            np.testing.assert_array_equal(res[1][0], res[0][0])
+            if want_var:
+                np.testing.assert_array_equal(res[1][1], res[0][1])
