@@ -46,15 +46,16 @@ BYTES_PER_PX = {
     # cur rgb, z, normal, mv, prev z, prev normal, ids x2, history rgb,
     # m1, m2, n -> rgb, m1, m2, n
     "temporal": 12 + 4 + 12 + 8 + 4 + 12 + 2 + 12 + 8 + 1 + 12 + 8 + 1,
-    # m1, m2, n, z -> var
-    "variance": 4 + 4 + 1 + 4 + 4,
+    # m2c, n, z -> var (history long enough; the short-history pixels'
+    # window reads are extra)
+    "variance": 4 + 1 + 4 + 4,
     # rgb, var, z, dzdx, dzdy, normal -> rgb, var
     "atrous": 12 + 4 + 4 + 4 + 4 + 12 + 12 + 4,
     "atrous_last": 12 + 4 + 4 + 4 + 4 + 12 + 12,
-    # horizontal: rgb, var, z, dzdx, normal -> scratch rgb; vertical:
-    # scratch rgb, var, z, dzdy, normal -> rgb, var
-    "atrous_sep": (12 + 4 + 4 + 4 + 12 + 12) + (12 + 4 + 4 + 4 + 12 + 12 + 4),
-    "atrous_sep_last": (12 + 4 + 4 + 4 + 12 + 12) + (12 + 4 + 4 + 4 + 12 + 12),
+    # separable level in one kernel: the same inputs and outputs (the
+    # horizontal result never reaches memory)
+    "atrous_sep": 12 + 4 + 4 + 4 + 4 + 12 + 12 + 4,
+    "atrous_sep_last": 12 + 4 + 4 + 4 + 4 + 12 + 12,
 }
 
 
@@ -105,8 +106,8 @@ def measured_traffic():
         return None
 
 
-# Binary16 storage, 2D levels: the survey's per-pass figures at FP16
-# (temporal 56, variance 13, level 32, last level 28) plus the id planes.
+# Binary16 storage, 2D levels: temporal 56 (+ 2 for the id planes),
+# variance 13, level 32, last level 28.
 FP16_FRAME_BYTES = 56 + 2 + 13 + 4 * 32 + 28
 
 
@@ -341,6 +342,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--variants", default="separable,uhd_half,batched,learned",
+                    help="comma-separated variants to run after the headline chain")
     ap.add_argument("--tune", action="store_true",
                     help="a-trous launch shapes from the autotuner (timed before the run)"
                          " instead of the library defaults")
@@ -354,7 +357,8 @@ def main():
     n_frames = args.warmup + args.steps
     t0 = time.perf_counter()
     frames_np = generate(WORKLOAD, n_frames, args.workers)  # before any GPU call (fork)
-    vframes = None if args.no_variants else generate_variant_frames(args.workers)
+    want = set() if args.no_variants else set(v for v in args.variants.split(",") if v)
+    vframes = generate_variant_frames(args.workers) if want & {"uhd_half", "batched"} else None
     gen_s = time.perf_counter() - t0
     print(f"# generated {n_frames} frames in {gen_s:.1f} s", file=sys.stderr, flush=True)
 
@@ -409,7 +413,7 @@ def main():
     per_kernel = {k: {"us": round(v[0] * 1e3, 2), "launches": v[1]} for k, v in sorted(ktimes.items())}
 
     variants = {}
-    if not args.no_variants:
+    if "separable" in want:
         g2, w2, _ = run_chain(torch, frames_dev, MOTION_SEP, H, W, args.warmup, args.steps,
                               per_kernel=False, tiles=tiles_sep)
         _, _, kt2 = run_chain(torch, frames_dev, MOTION_SEP, H, W, args.warmup, args.steps,
@@ -417,17 +421,21 @@ def main():
         variants["separable"] = {
             "value": round(W * H * args.steps / (g2 * 1e-3) / 1e6, 1), "unit": "Mpix/s",
             "ms_per_step": round(g2 / args.steps, 4),
+            "frame_bytes_per_px": frame_bytes_per_px(5, True),
             "frame_hbm_frac": round(W * H * args.steps * frame_bytes_per_px(5, True)
                                     / (g2 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "per_kernel_us": {k: round(v[0] * 1e3, 2) for k, v in sorted(kt2.items())}}
         print(f"# separable chain: {variants['separable']['ms_per_step'] * 1e3:.1f} us/frame",
               file=sys.stderr, flush=True)
+    if "uhd_half" in want:
         variants["uhd_half"] = variant_uhd_half(torch, vframes["uhd"])
         print(f"# 4K binary16: {variants['uhd_half']['ms_per_step'] * 1e3:.1f} us/frame",
               file=sys.stderr, flush=True)
+    if "batched" in want:
         variants["batched"] = variant_batched(torch, vframes["batch_cfg"], vframes["batch"])
         print(f"# 16 streams batched: {variants['batched']['ms_per_step'] * 1e3:.1f} us/frame",
               file=sys.stderr, flush=True)
+    if "learned" in want:
         learned = variant_learned(torch, frames_np, args.warmup, args.steps)
         if learned is not None:
             variants["learned"] = learned
