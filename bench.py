@@ -276,9 +276,9 @@ def variant_batched(torch, scfg, frames_np, warmup=BATCH_WARMUP, steps=BATCH_STE
 
 
 def variant_learned(torch, frames_np, warmup, steps):
-    """The learned blend/edge network on the headline workload: throughput
-    of the learned chain (5 and 4 levels) and RelMSE-to-clean of both
-    filters over the timed frames."""
+    """The learned blend/edge network on the headline workload, run inside
+    the temporal step: throughput at 5, 4 and 3 levels, and RelMSE-to-clean
+    over the timed frames for each and for plain SVGF (5 levels)."""
     from dataclasses import replace as dc_replace
 
     from paper_2312_06827_amd import learn
@@ -287,31 +287,22 @@ def variant_learned(torch, frames_np, warmup, steps):
         return None
     net = learn.load_weights(learn.DEFAULT_WEIGHTS)
     H, W = WORKLOAD.height, WORKLOAD.width
-    frames = [FrameInputs.from_numpy(fr) for fr in frames_np[:warmup + steps]]
-    albedo = [torch.from_numpy(fr["albedo"]).cuda() for fr in frames_np[:warmup + steps]]
-    clean = [torch.from_numpy(fr["clean"]).cuda() for fr in frames_np[:warmup + steps]]
-    out = {}
-    for levels in (5, 4):
-        cfg = dc_replace(MOTION, levels=levels)
-        den = learn.LearnedDenoiser(H, W, net, cfg)
-        errs = []
-        idx = iter(range(len(frames)))
+    n = warmup + steps
+    frames = [FrameInputs.from_numpy(fr) for fr in frames_np[:n]]
+    clean = [torch.from_numpy(fr["clean"]).cuda() for fr in frames_np[:n]]
 
-        def step(fr, den=den, errs=errs):
-            i = next(idx)
-            o = den.frame(fr, albedo[i])
-            if i >= warmup:
-                errs.append(o)
-        ms = _timed_frames(torch, step, frames, warmup)
-        # quality over the same frames (recomputed untimed)
-        den = learn.LearnedDenoiser(H, W, net, cfg)
-        rel = [learn.relmse(den.frame(fr, albedo[i]), clean[i]) for i, fr in enumerate(frames)]
+    def quality(den):
+        return float(np.mean([learn.relmse(den.frame(fr), clean[i])
+                              for i, fr in enumerate(frames)][warmup:]))
+
+    out = {"weights": os.path.relpath(learn.DEFAULT_WEIGHTS, ROOT)}
+    for levels in (5, 4, 3):
+        cfg = dc_replace(MOTION, levels=levels)
+        ms = _timed_frames(torch, Denoiser(H, W, cfg, mlp=net).frame, frames, warmup)
         out[f"learned_{levels}"] = {"value": round(H * W / (ms * 1e-3) / 1e6, 1),
                                     "ms_per_step": round(ms, 4),
-                                    "relmse": round(float(np.mean(rel[warmup:])), 6)}
-    plain = Denoiser(H, W, MOTION)
-    rel = [learn.relmse(plain.frame(fr), clean[i]) for i, fr in enumerate(frames)]
-    out["plain_5_relmse"] = round(float(np.mean(rel[warmup:])), 6)
+                                    "relmse": round(quality(Denoiser(H, W, cfg, mlp=net)), 6)}
+    out["plain_5_relmse"] = round(quality(Denoiser(H, W, MOTION)), 6)
     return out
 
 

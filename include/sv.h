@@ -137,6 +137,25 @@ typedef struct {
     float *out_m1, *out_m2c; /* accumulated moments (m2c central) */
     uint8_t *out_n;          /* new history length */
     const float *alpha_map;  /* optional per-pixel colour alpha (NULL) */
+    /* Learned mode (optional): with `mlp` set, the per-pixel network of
+     * sv_mlp_forward runs inside the step on the features sv_mlp_features
+     * would write (needs g.dzdx, g.dzdy and albedo) and its alpha replaces
+     * the colour blend factor (alpha_map is ignored); its kappa is written
+     * to kappa_out and its alpha to alpha_out when given (binary32 planes).
+     * Bitwise the same as sv_mlp_features + sv_mlp_forward + sv_temporal
+     * with that alpha as alpha_map. */
+    const struct sv_mlp_s *mlp;
+    sv_rgb albedo;
+    float *kappa_out, *alpha_out;
+    /* Variance estimate, first part (optional): with `var` set, var =
+     * max(0, m2c) is written where the new history length is >= var_min_hist
+     * (0 for empty pixels), and the pixels with a shorter history are
+     * listed in `var_work` (an sv_variance workspace); sv_variance with
+     * SV_V_LISTED then does the rest.  Bitwise the same as sv_variance
+     * alone. */
+    float *var;
+    void *var_work;
+    int32_t var_min_hist;
 } sv_temporal_io;
 
 typedef struct {
@@ -184,7 +203,13 @@ typedef struct {
     float eps_z;      /* depth weight epsilon, default 1e-10 */
     int32_t min_hist; /* history length for the temporal estimate, default 4 */
     int32_t radius;   /* spatial window radius, 0..7, default 3 */
+    int32_t flags;    /* SV_V_* */
 } sv_variance_params;
+
+/* The long-history variance and the list of short-history pixels were
+ * already written into var and work by sv_temporal (its var outputs, same
+ * min_hist): only the spatial estimate of the listed pixels remains. */
+#define SV_V_LISTED 1
 
 /* Two passes: every pixel with n >= min_hist gets the temporal estimate and
  * the others are listed in `work`; a second pass spreads the listed pixels
@@ -304,7 +329,7 @@ int sv_atrous_sep(const sv_rgb *c_in, const float *var_in, const sv_gbuf *g,
 #define SV_MLP_HIDDEN 32
 #define SV_MLP_PARAMS 1602
 
-typedef struct {
+typedef struct sv_mlp_s {
     const float *params;    /* SV_MLP_PARAMS binary32 (biases read here) */
     const uint16_t *wq;     /* SV_MLP_PARAMS bfloat16 mirror (matrices read here) */
     const float *mu;        /* 14 feature means */
@@ -396,6 +421,7 @@ typedef struct {
     sv_rgb out;              /* final output of the frame */
     int32_t cur;             /* 0 or 1: which history buffers are current;
                                 each call flips it */
+    float *kappa;            /* learned mode: the network's kappa (scratch) */
 } sv_denoiser;
 
 typedef struct {
@@ -405,6 +431,11 @@ typedef struct {
     sv_gbuf prev;            /* previous frame's z, normal, id */
     const float *alpha_map;  /* optional per-pixel colour alpha (NULL) */
     const float *kappa;      /* optional per-pixel sigma_l scale (NULL) */
+    /* learned mode (optional): the network runs inside the temporal step
+     * and its alpha and kappa replace alpha_map and kappa; needs
+     * g.dzdx, g.dzdy, albedo and the state's kappa plane */
+    const sv_mlp *mlp;
+    sv_rgb albedo;
 } sv_frame_in;
 
 typedef struct {

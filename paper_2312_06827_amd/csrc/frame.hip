@@ -13,8 +13,10 @@ extern "C" int sv_denoise_frame(const sv_frame_in *in, sv_denoiser *st, sv_dims 
     const bool fb_temporal = p->feedback == 1 || p->levels == 0;
     const bool tm = (p->temporal.flags & SV_T_TONEMAP_IN) != 0;
 
+    const bool learn = in->mlp != nullptr;
+    if (learn && !st->kappa) return SV_EINVAL;
     // temporal: history k -> (temporal output | hist k1), moments k -> k1
-    sv_temporal_io io;
+    sv_temporal_io io{};
     io.cur = in->cur;
     io.g = in->g;
     io.mvx = in->mvx;
@@ -29,10 +31,22 @@ extern "C" int sv_denoise_frame(const sv_frame_in *in, sv_denoiser *st, sv_dims 
     io.out_m2c = st->m2c[k1];
     io.out_n = st->n[k1];
     io.alpha_map = in->alpha_map;
+    if (learn) {
+        io.mlp = in->mlp;
+        io.albedo = in->albedo;
+        io.kappa_out = st->kappa;
+    }
+    const float *kappa = learn ? st->kappa : in->kappa;
+    // the variance's pointwise part and its list come out of the temporal step
+    io.var = st->var;
+    io.var_work = st->var_work;
+    io.var_min_hist = p->variance.min_hist;
     int rc = sv_temporal(&io, d, t, &p->temporal, stream);
     if (rc != SV_OK) return rc;
-    rc = sv_variance(st->m1[k1], st->m2c[k1], st->n[k1], &in->g, st->var, st->var_work, d, t,
-                     &p->variance, stream);
+    sv_variance_params vp = p->variance;
+    vp.flags |= SV_V_LISTED;
+    rc = sv_variance(st->m1[k1], st->m2c[k1], st->n[k1], &in->g, st->var, st->var_work, d, t, &vp,
+                     stream);
     if (rc != SV_OK) return rc;
 
     sv_rgb c = io.out;
@@ -50,9 +64,9 @@ extern "C" int sv_denoise_frame(const sv_frame_in *in, sv_denoiser *st, sv_dims 
         float *dst_var = last ? nullptr : st->level_var[i & 1];
         // separable levels: the fused form (no scratch) where the step has one
         const bool fused = (1 << i) <= 16;
-        rc = p->separable ? sv_atrous_sep(&c, v, &in->g, in->kappa, fused ? nullptr : &st->scratch,
+        rc = p->separable ? sv_atrous_sep(&c, v, &in->g, kappa, fused ? nullptr : &st->scratch,
                                           &dst, dst_var, 1 << i, d, t, &ap, stream)
-                          : sv_atrous(&c, v, &in->g, in->kappa, &dst, dst_var, 1 << i, d, t, &ap,
+                          : sv_atrous(&c, v, &in->g, kappa, &dst, dst_var, 1 << i, d, t, &ap,
                                       stream);
         if (rc != SV_OK) return rc;
         c = dst;

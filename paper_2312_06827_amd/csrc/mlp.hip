@@ -3,42 +3,10 @@
 // its backward pass, Adam, and the two truncated loss gradients that train
 // it (through the temporal blend and through each a-trous level).
 //
-// Matrix layout.  Each layer is computed transposed, Y^T = W X^T, with
-// v_mfma_f32_32x32x8_bf16: A = the weights (32 output units x 8 inputs per
-// instruction), B = 32 pixels x 8 inputs.  Lane l supplies A[l % 32][4 (l/32)
-// + 0..3] and B[4 (l/32) + 0..3][l % 32] of each 8-wide K block and receives
-// D[8 (r/4) + 4 (l/32) + r % 4][l % 32] in accumulator r = 0..15.  So after a
-// layer, accumulators 4 kb .. 4 kb + 3 of a lane are exactly that lane's B
-// operand for K block kb of the next layer: activations never leave
-// registers in the forward pass.
-#include "sv_internal.h"
+// The forward pass and the matrix layout are in mlp_impl.h.
+#include "mlp_impl.h"
 
 namespace sv {
-
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-
-constexpr int kOffW1 = 0, kOffB1 = 448, kOffW2 = 480, kOffB2 = 1504, kOffW3 = 1536,
-              kOffB3 = 1600;
-static_assert(kOffB3 + 2 == SV_MLP_PARAMS, "parameter layout");
-constexpr float kAlphaMin = 0.05f;
-
-__device__ __forceinline__ uint16_t to_bf16(float f) {
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
-    return (uint16_t)(u >> 16);
-}
-
-__device__ __forceinline__ float from_bf16(uint16_t h) {
-    return __uint_as_float((uint32_t)h << 16);
-}
-
-__device__ __forceinline__ f32x16 mfma(bf16x4 a, bf16x4 b, f32x16 c) {
-    return __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, c, 0, 0, 0);
-}
-
-// Output unit (row of D) held in accumulator r by a lane of half `hf`.
-__device__ __forceinline__ int drow(int r, int hf) { return 8 * (r >> 2) + 4 * hf + (r & 3); }
 
 struct MlpArgs {
     const float *params;
@@ -50,73 +18,6 @@ struct MlpArgs {
     int w, h, pitch;
     int npix, nblk;  // pixels, 32-pixel blocks
 };
-
-// Weights one lane holds for the forward pass.
-struct FwdW {
-    bf16x4 w1[2], w2[4];
-    float w3a[16], w3b[16];  // W3 rows 0 and 1 at this lane's units (bf16 values)
-    float b3a, b3b;
-};
-
-__device__ __forceinline__ void load_fwd(const MlpArgs &a, int col, int hf, FwdW &f) {
-#pragma unroll
-    for (int kb = 0; kb < 2; ++kb)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int k = 8 * kb + 4 * hf + i;
-            f.w1[kb][i] = (short)(k < SV_MLP_IN ? a.wq[kOffW1 + col * SV_MLP_IN + k] : 0);
-        }
-#pragma unroll
-    for (int kb = 0; kb < 4; ++kb)
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-            f.w2[kb][i] = (short)a.wq[kOffW2 + col * SV_MLP_HIDDEN + 8 * kb + 4 * hf + i];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        f.w3a[r] = from_bf16(a.wq[kOffW3 + drow(r, hf)]);
-        f.w3b[r] = from_bf16(a.wq[kOffW3 + SV_MLP_HIDDEN + drow(r, hf)]);
-    }
-    f.b3a = a.params[kOffB3];
-    f.b3b = a.params[kOffB3 + 1];
-}
-
-// Forward pass of one 32-pixel block.  x: this lane's B operands of layer
-// 1; returns the layer-1 and layer-2 pre-activations (with biases), the
-// bfloat16 layer-2 activations as floats, and the two outputs (the same in
-// both halves of the wave).
-struct FwdOut {
-    f32x16 a1, a2;
-    bf16x4 h1[4];
-    float h2[16];
-    float o0, o1;
-};
-
-__device__ __forceinline__ void forward_block(const MlpArgs &a, const FwdW &f, const bf16x4 (&x)[2],
-                                              int hf, FwdOut &r) {
-#pragma unroll
-    for (int i = 0; i < 16; ++i) r.a1[i] = a.params[kOffB1 + drow(i, hf)];
-    r.a1 = mfma(f.w1[0], x[0], r.a1);
-    r.a1 = mfma(f.w1[1], x[1], r.a1);
-#pragma unroll
-    for (int kb = 0; kb < 4; ++kb)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) r.h1[kb][i] = (short)to_bf16(fmaxf(r.a1[4 * kb + i], 0.f));
-#pragma unroll
-    for (int i = 0; i < 16; ++i) r.a2[i] = a.params[kOffB2 + drow(i, hf)];
-#pragma unroll
-    for (int kb = 0; kb < 4; ++kb) r.a2 = mfma(f.w2[kb], r.h1[kb], r.a2);
-    float o0 = 0.f, o1 = 0.f;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        r.h2[i] = from_bf16(to_bf16(fmaxf(r.a2[i], 0.f)));
-        o0 = fmaf(f.w3a[i], r.h2[i], o0);
-        o1 = fmaf(f.w3b[i], r.h2[i], o1);
-    }
-    o0 += __shfl_xor(o0, 32, 64);
-    o1 += __shfl_xor(o1, 32, 64);
-    r.o0 = o0 + f.b3a;
-    r.o1 = o1 + f.b3b;
-}
 
 __device__ __forceinline__ void load_x(const MlpArgs &a, int p, int hf, bf16x4 (&x)[2]) {
     // features 8 kb + 4 hf .. + 3 of pixel p: 8 bytes inside its 32-byte row
@@ -140,18 +41,20 @@ __global__ __launch_bounds__(256) void mlp_forward_k(MlpArgs a) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int col = lane & 31, hf = lane >> 5;
     FwdW f;
-    load_fwd(a, col, hf, f);
+    load_fwd(a.params, a.wq, col, hf, f);
     for (int blk = blockIdx.x * 4 + wave; blk < a.nblk; blk += gridDim.x * 4) {
         const int p = blk * 32 + col;
         const bool valid = p < a.npix;
         bf16x4 x[2];
         load_x(a, valid ? p : a.npix - 1, hf, x);
         FwdOut r;
-        forward_block(a, f, x, hf, r);
+        forward_block(a.params, f, x, hf, r);
         if (valid && hf == 0) {
             const uint32_t o = plane_off(a, p);
-            if (a.alpha) a.alpha[o] = kAlphaMin + (1.0f - kAlphaMin) / (1.0f + expf(-r.o0));
-            if (a.kappa) a.kappa[o] = exp2f(2.0f * tanhf(r.o1));
+            float al, ka;
+            mlp_heads(r.o0, r.o1, al, ka);
+            if (a.alpha) a.alpha[o] = al;
+            if (a.kappa) a.kappa[o] = ka;
         }
     }
 }
@@ -193,7 +96,7 @@ __global__ __launch_bounds__(256) void mlp_backward_k(MlpArgs a) {
     // rows 16..31 of the x tile stay zero: the feature dimension is padded
     for (int i = lane; i < 32 * kTP; i += 64) t_x[i] = 0;
     FwdW f;
-    load_fwd(a, col, hf, f);
+    load_fwd(a.params, a.wq, col, hf, f);
     bf16x4 w2t[4];  // A operand of W2^T: [h1 unit = col][h2 unit]
 #pragma unroll
     for (int kb = 0; kb < 4; ++kb)
@@ -218,7 +121,7 @@ __global__ __launch_bounds__(256) void mlp_backward_k(MlpArgs a) {
         bf16x4 x[2];
         load_x(a, valid ? p : 0, hf, x);
         FwdOut r;
-        forward_block(a, f, x, hf, r);
+        forward_block(a.params, f, x, hf, r);
         // gradients of the outputs
         float da = 0.f, dk = 0.f;
         if (valid) {

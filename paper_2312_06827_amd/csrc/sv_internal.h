@@ -122,6 +122,47 @@ __device__ __forceinline__ int xcd_tile(int tiles) {
 
 inline unsigned xcd_grid(int tiles) { return (unsigned)(((tiles + kXCD - 1) / kXCD) * kXCD); }
 
+// ---- short-history list of the variance estimate ---------------------------
+//
+// Pixels whose history is too short for the temporal variance are listed
+// for a spatial estimate.  Workspace: eight counters (128 bytes apart),
+// then eight sublists; the 64x4-pixel tile t appends to sublist t % 8, so a
+// sublist holds at most ceil(tiles / 8) tiles' pixels (its capacity `cap`)
+// whichever workgroup runs the tile.  Entries are (y << 15) | x.
+constexpr int kVX = 64, kVY = 4;
+constexpr int kLines = 32;
+
+struct VarWork {
+    uint32_t count[kXCD * kLines];  // count[k * kLines]: entries in sublist k
+    uint32_t list[1];               // sublist k at list + k * cap
+};
+
+inline uint32_t point_grid(sv_dims d) {
+    return xcd_grid(((d.w + kVX - 1) / kVX) * ((d.h + kVY - 1) / kVY));
+}
+
+// Appends this thread's pixel (x, y) if `spatial`: one atomic per
+// workgroup.  Every thread of the 256-thread workgroup must call it (it
+// holds two barriers); tile is this workgroup's 64x4 tile index.
+__device__ __forceinline__ void list_short_pixel(VarWork *work, uint32_t cap, int tile,
+                                                 bool spatial, int x, int y, uint32_t *wave_n,
+                                                 uint32_t &base_sh) {
+    const uint64_t mask = __ballot(spatial);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) wave_n[wave] = (uint32_t)__popcll(mask);
+    __syncthreads();
+    const uint32_t n0 = wave_n[0], n1 = wave_n[1], n2 = wave_n[2], n3 = wave_n[3];
+    const uint32_t total = n0 + n1 + n2 + n3;
+    if (total == 0) return;  // uniform over the workgroup
+    const uint32_t k = (uint32_t)tile % kXCD;
+    if (threadIdx.x == 0) base_sh = atomicAdd(&work->count[k * kLines], total);
+    __syncthreads();
+    const uint32_t before = (wave > 0 ? n0 : 0u) + (wave > 1 ? n1 : 0u) + (wave > 2 ? n2 : 0u);
+    const uint32_t slot = base_sh + before + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+    // a workspace that was not zeroed cannot push a store past the sublist
+    if (spatial && slot < cap) work->list[k * cap + slot] = ((uint32_t)y << 15) | (uint32_t)x;
+}
+
 // ---- batched passes (many independent streams, one launch per pass) ----------
 //
 // A batched pass runs the tiles of n streams as one global list: stream s

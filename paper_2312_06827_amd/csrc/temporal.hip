@@ -3,7 +3,7 @@
 // moments (Section 2; Section 3 step 4; Section 3.1).  One fused pass:
 // every pixel reads its current colour (tone mapped on the fly), its 3x3
 // neighbourhood through an LDS tile, and four bilinear history taps.
-#include "sv_internal.h"
+#include "mlp_impl.h"
 
 namespace sv {
 
@@ -31,6 +31,15 @@ struct TemporalArgs {
     uint4 *feat;              // two 16-byte halves per pixel, row y * w + x
     float *fhr, *fhg, *fhb;   // clamped reprojected history (optional)
     const float *mu, *inv_s;  // standardisation
+    // learned mode only
+    const float *mparams;
+    const uint16_t *mwq;
+    float *kappa_out, *alpha_out;
+    // variance, first part
+    float *var_out;
+    VarWork *var_work;
+    uint32_t var_cap;
+    int min_hist;
 };
 
 // binary32 decisions, operation order fixed and never contracted.
@@ -135,186 +144,231 @@ __device__ __forceinline__ float box_luma_var(const float4 *tile, int lx, int ly
     return v / cnt;
 }
 
-__device__ __forceinline__ uint32_t bf16_bits(float f) {
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
-    return u >> 16;
-}
-
-// Standardise the 14 raw features, round to bfloat16 and store the pixel's
-// 32-byte row (two zero pads at the end).
-__device__ __forceinline__ void store_features(const TemporalArgs &a, int x, int y,
-                                               const float (&f)[SV_MLP_IN]) {
-    uint32_t pk[8];
+// Standardise the 14 raw features and pack them as 16 bfloat16 (the last
+// two zero) into eight words.
+__device__ __forceinline__ void standardise_pack(const TemporalArgs &a, const float (&f)[SV_MLP_IN],
+                                                 uint32_t (&pk)[8]) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
         const int k0 = 2 * i, k1 = 2 * i + 1;
         // features 14 and 15 are the zero pads
-        const uint32_t lo = k0 < SV_MLP_IN ? bf16_bits((f[k0] - a.mu[k0]) * a.inv_s[k0]) : 0u;
-        const uint32_t hi = k1 < SV_MLP_IN ? bf16_bits((f[k1] - a.mu[k1]) * a.inv_s[k1]) : 0u;
+        const uint32_t lo = k0 < SV_MLP_IN ? to_bf16((f[k0] - a.mu[k0]) * a.inv_s[k0]) : 0u;
+        const uint32_t hi = k1 < SV_MLP_IN ? to_bf16((f[k1] - a.mu[k1]) * a.inv_s[k1]) : 0u;
         pk[i] = lo | (hi << 16);
     }
+}
+
+// The pixel's 32-byte feature row.
+__device__ __forceinline__ void store_features(const TemporalArgs &a, int x, int y,
+                                               const float (&f)[SV_MLP_IN]) {
+    uint32_t pk[8];
+    standardise_pack(a, f, pk);
     uint4 *row = a.feat + 2 * ((size_t)y * (size_t)a.w + (size_t)x);
     row[0] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
     row[1] = make_uint4(pk[4], pk[5], pk[6], pk[7]);
 }
 
-// One 64x4 tile (bx, by).  Returns once this thread's pixel is done (the
-// caller's barrier follows).
-template <typename T, bool TM, bool CLAMP, bool USE_ID, bool FEAT>
-__device__ __forceinline__ void temporal_tile(const TemporalArgs &a, float4 *tile, int bx,
-                                              int by) {
-    stage_current<T, TM>(tile, a.cr, a.cg, a.cb, a.z, a.w, a.h, a.pitch, a.tm_k, bx, by);
-    __syncthreads();
-    const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
-    const int x = bx * kTX + lx, y = by * kTY + ly;
-    if (x >= a.w || y >= a.h) return;
-    const uint32_t o = (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x;
-    const float4 c = tile[(ly + 1) * (kTX + 2) + lx + 1];
-    const float L = luma(c.x, c.y, c.z);
-    const float zc = ldo<T>(a.z, o);
-    if (FEAT && empty_px(zc)) {
-        float f[SV_MLP_IN];
-#pragma unroll
-        for (int i = 0; i < SV_MLP_IN; ++i) f[i] = 0.f;
-        store_features(a, x, y, f);
-        if (a.fhr) {
-            stf(a.fhr, o, 0.f);
-            stf(a.fhg, o, 0.f);
-            stf(a.fhb, o, 0.f);
-        }
-        return;
-    }
-    if (empty_px(zc)) {
-        sto<T>(a.or_, o, c.x);
-        sto<T>(a.og, o, c.y);
-        sto<T>(a.ob, o, c.z);
-        stf(a.om1, o, 0.f);
-        stf(a.om2c, o, 0.f);
-        a.on[o] = 0;
-        return;
-    }
-    const float nxc = ldo<T>(a.nx, o), nyc = ldo<T>(a.ny, o),
-                nzc = ldo<T>(a.nz, o);
-    const float mvx = ldo<T>(a.mvx, o), mvy = ldo<T>(a.mvy, o);
-    const uint8_t idc = USE_ID ? a.id[o] : 0;
+// What one pixel's reprojection and clamp yield (before the blend).
+struct PxState {
+    float4 c;  // current colour (tone mapped); w: in the image and not empty
+    float L, zc, nxc, nyc, nzc, mvx, mvy;
+    uint32_t o;
+    bool inimg, empty, mv_ok, any;
+    float hr, hg, hb, hm1, hm2c;  // reprojected history, clamped (valid if any)
+    int nmax;
+};
 
-    // ---- backward reprojection: bilinear taps around p + mv ----
-    // Every load of the four taps is issued before any test, so the taps'
-    // memory latencies overlap instead of chaining through the tests.
+// Everything one pixel reads from memory (its own G-buffer and motion, and
+// the four bilinear history taps), gathered before the tile's barrier so
+// that these loads overlap the staging of the current colour.
+struct PxLoads {
+    float zc, nxc, nyc, nzc, mvx, mvy;
+    int idc;
     float bw[4], tz[4], tnx[4], tny[4], tnz[4], tr[4], tg[4], tb[4], t1[4], t2[4];
     int thn[4], tid_[4];
     bool inb[4];
+    bool mv_ok;
+};
+
+template <typename T, bool USE_ID>
+__device__ __forceinline__ void px_gather(const TemporalArgs &a, int x, int y, PxLoads &g) {
+    const bool inimg = x < a.w && y < a.h;
+    const uint32_t o = inimg ? (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x : 0u;
+    g.zc = ldo<T>(a.z, o);
+    g.nxc = ldo<T>(a.nx, o);
+    g.nyc = ldo<T>(a.ny, o);
+    g.nzc = ldo<T>(a.nz, o);
+    g.mvx = ldo<T>(a.mvx, o);
+    g.mvy = ldo<T>(a.mvy, o);
+    g.idc = USE_ID ? a.id[o] : 0;
+    // ---- backward reprojection: bilinear taps around p + mv ----
+    // Every load of the four taps is issued before any test, so the taps'
+    // memory latencies overlap instead of chaining through the tests.
+    const float mvx = g.mvx, mvy = g.mvy;
     const bool mv_ok = fabsf(mvx) < 1048576.0f && fabsf(mvy) < 1048576.0f;
+    g.mv_ok = mv_ok;
     const float fx0 = mv_ok ? floorf(mvx) : 0.f, fy0 = mv_ok ? floorf(mvy) : 0.f;
     const float fx = mvx - fx0, fy = mvy - fy0;  // exact in binary32
     const int x0 = x + (int)fx0, y0 = y + (int)fy0;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         const int tx = x0 + (t & 1), ty = y0 + (t >> 1);
-        bw[t] = ((t & 1) ? fx : 1.0f - fx) * ((t >> 1) ? fy : 1.0f - fy);
-        inb[t] = mv_ok && bw[t] > 0.f && tx >= 0 && tx < a.w && ty >= 0 && ty < a.h;
-        const uint32_t q = inb[t] ? (uint32_t)ty * (uint32_t)a.pitch + (uint32_t)tx : o;
-        thn[t] = a.hn[q];
-        tz[t] = ldo<T>(a.pz, q);
-        tnx[t] = ldo<T>(a.pnx, q);
-        tny[t] = ldo<T>(a.pny, q);
-        tnz[t] = ldo<T>(a.pnz, q);
-        tid_[t] = USE_ID ? a.pid[q] : 0;
-        tr[t] = ldo<T>(a.hr, q);
-        tg[t] = ldo<T>(a.hg, q);
-        tb[t] = ldo<T>(a.hb, q);
-        t1[t] = ldf(a.hm1, q);
-        t2[t] = ldf(a.hm2c, q);
+        g.bw[t] = ((t & 1) ? fx : 1.0f - fx) * ((t >> 1) ? fy : 1.0f - fy);
+        g.inb[t] = inimg && mv_ok && g.bw[t] > 0.f && tx >= 0 && tx < a.w && ty >= 0 && ty < a.h;
+        const uint32_t q = g.inb[t] ? (uint32_t)ty * (uint32_t)a.pitch + (uint32_t)tx : o;
+        g.thn[t] = a.hn[q];
+        g.tz[t] = ldo<T>(a.pz, q);
+        g.tnx[t] = ldo<T>(a.pnx, q);
+        g.tny[t] = ldo<T>(a.pny, q);
+        g.tnz[t] = ldo<T>(a.pnz, q);
+        g.tid_[t] = USE_ID ? a.pid[q] : 0;
+        g.tr[t] = ldo<T>(a.hr, q);
+        g.tg[t] = ldo<T>(a.hg, q);
+        g.tb[t] = ldo<T>(a.hb, q);
+        g.t1[t] = ldf(a.hm1, q);
+        g.t2[t] = ldf(a.hm2c, q);
     }
+}
+
+// The validity tests, the renormalised history, its central moment and the
+// clamp, from the gathered loads and the staged tile.
+template <bool CLAMP, bool USE_ID>
+__device__ __forceinline__ PxState px_reproject(const TemporalArgs &a, const float4 *tile, int lx,
+                                                int ly, int x, int y, const PxLoads &g) {
+    PxState s;
+    s.inimg = x < a.w && y < a.h;
+    s.o = s.inimg ? (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x : 0u;
+    s.c = tile[(ly + 1) * (kTX + 2) + lx + 1];
+    s.L = luma(s.c.x, s.c.y, s.c.z);
+    s.zc = g.zc;
+    s.empty = !s.inimg || empty_px(s.zc);
+    s.any = false;
+    s.mv_ok = false;
+    s.nxc = s.nyc = s.nzc = s.mvx = s.mvy = 0.f;
+    s.hr = s.hg = s.hb = s.hm1 = s.hm2c = 0.f;
+    s.nmax = 0;
+    if (s.empty) return s;
+    const float zc = s.zc, nxc = g.nxc, nyc = g.nyc, nzc = g.nzc;
+    s.nxc = nxc;
+    s.nyc = nyc;
+    s.nzc = nzc;
+    s.mvx = g.mvx;
+    s.mvy = g.mvy;
+    s.mv_ok = g.mv_ok;
     float sw = 0.f, ar = 0.f, ag = 0.f, ab = 0.f, a1 = 0.f;
     int nmax = 0;
     bool ok[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        ok[t] = inb[t] && thn[t] >= 1 && depth_consistent(tz[t], zc, a.tau_z) &&
-                normal_consistent(tnx[t], tny[t], tnz[t], nxc, nyc, nzc, a.tau_n) &&
-                (!USE_ID || tid_[t] == idc);
+        ok[t] = g.inb[t] && g.thn[t] >= 1 && depth_consistent(g.tz[t], zc, a.tau_z) &&
+                normal_consistent(g.tnx[t], g.tny[t], g.tnz[t], nxc, nyc, nzc, a.tau_n) &&
+                (!USE_ID || g.tid_[t] == g.idc);
         // selects, not zero weights: an unusable tap's history may hold
         // anything (even NaN) and must not reach the sums
-        sw = ok[t] ? sw + bw[t] : sw;
-        ar = ok[t] ? fmaf(bw[t], tr[t], ar) : ar;
-        ag = ok[t] ? fmaf(bw[t], tg[t], ag) : ag;
-        ab = ok[t] ? fmaf(bw[t], tb[t], ab) : ab;
-        a1 = ok[t] ? fmaf(bw[t], t1[t], a1) : a1;
-        nmax = ok[t] ? max(nmax, thn[t]) : nmax;
+        sw = ok[t] ? sw + g.bw[t] : sw;
+        ar = ok[t] ? fmaf(g.bw[t], g.tr[t], ar) : ar;
+        ag = ok[t] ? fmaf(g.bw[t], g.tg[t], ag) : ag;
+        ab = ok[t] ? fmaf(g.bw[t], g.tb[t], ab) : ab;
+        a1 = ok[t] ? fmaf(g.bw[t], g.t1[t], a1) : a1;
+        nmax = ok[t] ? max(nmax, g.thn[t]) : nmax;
     }
-    const bool any = ok[0] || ok[1] || ok[2] || ok[3];
-    float outr, outg, outb, m1, m2c;
-    int n;
-    if (FEAT && !any) {
-        float f[SV_MLP_IN] = {L, 0.f, 0.f, box_luma_var(tile, lx, ly), 1.0f / 255.0f,
-                              ldo<T>(a.dzdx, o), ldo<T>(a.dzdy, o), nxc, nyc, nzc,
-                              mv_ok ? sqrtf(fmaf(mvy, mvy, mvx * mvx)) : 0.f,
-                              ldo<T>(a.alr, o), ldo<T>(a.alg, o), ldo<T>(a.alb, o)};
-        store_features(a, x, y, f);
-        if (a.fhr) {
-            stf(a.fhr, o, 0.f);
-            stf(a.fhg, o, 0.f);
-            stf(a.fhb, o, 0.f);
-        }
+    s.any = ok[0] || ok[1] || ok[2] || ok[3];
+    s.nmax = nmax;
+    if (!s.any) return s;
+    const float inv = 1.0f / sw;
+    float hr = ar * inv, hg = ag * inv, hb = ab * inv;
+    const float hm1 = a1 * inv;
+    // second central moment of the bilinear mixture: mean of the taps'
+    // central moments plus the spread of their means (no cancellation)
+    float s2 = 0.f;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const float d = g.t1[t] - hm1;
+        s2 = ok[t] ? fmaf(g.bw[t], fmaf(d, d, g.t2[t]), s2) : s2;
+    }
+    // ---- history rectification: variance colour clamp ----
+    if (CLAMP) {
+        float3 lo, hi;
+        box_bounds(tile, lx, ly, a.gamma, lo, hi);
+        hr = fminf(fmaxf(hr, lo.x), hi.x);
+        hg = fminf(fmaxf(hg, lo.y), hi.y);
+        hb = fminf(fmaxf(hb, lo.z), hi.z);
+    }
+    s.hr = hr;
+    s.hg = hg;
+    s.hb = hb;
+    s.hm1 = hm1;
+    s.hm2c = s2 * inv;
+    return s;
+}
+
+// The 14 raw features of the learned component (all zero for an empty
+// pixel or one outside the image).
+template <typename T>
+__device__ __forceinline__ void px_features(const TemporalArgs &a, const float4 *tile, int lx,
+                                            int ly, const PxState &s, float (&f)[SV_MLP_IN]) {
+    if (s.empty) {
+#pragma unroll
+        for (int i = 0; i < SV_MLP_IN; ++i) f[i] = 0.f;
         return;
     }
-    if (!any) {
-        outr = c.x;
-        outg = c.y;
-        outb = c.z;
-        m1 = L;
+    const uint32_t o = s.o;
+    f[0] = s.L;
+    f[1] = s.any ? luma(s.hr, s.hg, s.hb) : 0.f;
+    f[2] = s.any ? fmaxf(s.hm2c, 0.f) : 0.f;
+    f[3] = box_luma_var(tile, lx, ly);
+    f[4] = s.any ? (float)min(s.nmax + 1, a.max_hist) / 255.0f : 1.0f / 255.0f;
+    f[5] = ldo<T>(a.dzdx, o);
+    f[6] = ldo<T>(a.dzdy, o);
+    f[7] = s.nxc;
+    f[8] = s.nyc;
+    f[9] = s.nzc;
+    f[10] = s.mv_ok ? sqrtf(fmaf(s.mvy, s.mvy, s.mvx * s.mvx)) : 0.f;
+    f[11] = ldo<T>(a.alr, o);
+    f[12] = ldo<T>(a.alg, o);
+    f[13] = ldo<T>(a.alb, o);
+}
+
+// Blend colour and moments (alpha: the colour blend factor before the 1/n
+// floor) and store the pixel's outputs.
+template <typename T>
+__device__ __forceinline__ void px_blend(const TemporalArgs &a, const PxState &s, float alpha,
+                                         int &n_out, float &m2c_out) {
+    const uint32_t o = s.o;
+    n_out = 0;
+    m2c_out = 0.f;
+    if (s.empty) {
+        sto<T>(a.or_, o, s.c.x);
+        sto<T>(a.og, o, s.c.y);
+        sto<T>(a.ob, o, s.c.z);
+        stf(a.om1, o, 0.f);
+        stf(a.om2c, o, 0.f);
+        a.on[o] = 0;
+        return;
+    }
+    float outr, outg, outb, m1, m2c;
+    int n;
+    if (!s.any) {
+        outr = s.c.x;
+        outg = s.c.y;
+        outb = s.c.z;
+        m1 = s.L;
         m2c = 0.f;
         n = 1;
     } else {
-        const float inv = 1.0f / sw;
-        float hr = ar * inv, hg = ag * inv, hb = ab * inv;
-        const float hm1 = a1 * inv;
-        // second central moment of the bilinear mixture: mean of the taps'
-        // central moments plus the spread of their means (no cancellation)
-        float s2 = 0.f;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const float d = t1[t] - hm1;
-            s2 = ok[t] ? fmaf(bw[t], fmaf(d, d, t2[t]), s2) : s2;
-        }
-        const float hm2c = s2 * inv;
-        // ---- history rectification: variance colour clamp ----
-        if (CLAMP) {
-            float3 lo, hi;
-            box_bounds(tile, lx, ly, a.gamma, lo, hi);
-            hr = fminf(fmaxf(hr, lo.x), hi.x);
-            hg = fminf(fmaxf(hg, lo.y), hi.y);
-            hb = fminf(fmaxf(hb, lo.z), hi.z);
-        }
-        if (FEAT) {
-            float f[SV_MLP_IN] = {L, luma(hr, hg, hb), fmaxf(hm2c, 0.f), box_luma_var(tile, lx, ly),
-                                  (float)min(nmax + 1, a.max_hist) / 255.0f,
-                                  ldo<T>(a.dzdx, o), ldo<T>(a.dzdy, o), nxc, nyc, nzc,
-                                  mv_ok ? sqrtf(fmaf(mvy, mvy, mvx * mvx)) : 0.f,
-                                  ldo<T>(a.alr, o), ldo<T>(a.alg, o), ldo<T>(a.alb, o)};
-            store_features(a, x, y, f);
-            if (a.fhr) {
-                stf(a.fhr, o, hr);
-                stf(a.fhg, o, hg);
-                stf(a.fhb, o, hb);
-            }
-            return;
-        }
         // ---- accumulation ----
-        n = min(nmax + 1, a.max_hist);
+        n = min(s.nmax + 1, a.max_hist);
         const float inv_n = 1.0f / (float)n;
-        const float ac = fmaxf(a.alpha_map ? ldf(a.alpha_map, o) : a.alpha, inv_n);
+        const float ac = fmaxf(alpha, inv_n);
         const float am = fmaxf(a.alpha_m, inv_n);
-        outr = fmaf(ac, c.x - hr, hr);
-        outg = fmaf(ac, c.y - hg, hg);
-        outb = fmaf(ac, c.z - hb, hb);
-        const float dl = L - hm1;
-        m1 = fmaf(am, dl, hm1);
+        outr = fmaf(ac, s.c.x - s.hr, s.hr);
+        outg = fmaf(ac, s.c.y - s.hg, s.hg);
+        outb = fmaf(ac, s.c.z - s.hb, s.hb);
+        const float dl = s.L - s.hm1;
+        m1 = fmaf(am, dl, s.hm1);
         // EMA of the raw moments written for the central one:
         // (1 - am) (m2c + am (L - m1)^2)
-        m2c = (1.0f - am) * fmaf(am * dl, dl, hm2c);
+        m2c = (1.0f - am) * fmaf(am * dl, dl, s.hm2c);
     }
     sto<T>(a.or_, o, outr);
     sto<T>(a.og, o, outg);
@@ -322,22 +376,120 @@ __device__ __forceinline__ void temporal_tile(const TemporalArgs &a, float4 *til
     stf(a.om1, o, m1);
     stf(a.om2c, o, m2c);
     a.on[o] = (uint8_t)n;
+    n_out = n;
+    m2c_out = m2c;
 }
 
-template <typename T, bool TM, bool CLAMP, bool USE_ID, bool FEAT>
+// The network on this workgroup's 256 pixels: every lane's standardised
+// features go through LDS into the matrix operands of its wave's two
+// 32-pixel blocks; returns this lane's alpha and kappa.  Every thread of
+// the workgroup must call it (barrier and matrix instructions).
+__device__ __forceinline__ void px_network(const TemporalArgs &a, uint4 *s_feat,
+                                           const float (&f)[SV_MLP_IN], float &alpha,
+                                           float &kappa) {
+    uint32_t pk[8];
+    standardise_pack(a, f, pk);
+    s_feat[2 * threadIdx.x] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
+    s_feat[2 * threadIdx.x + 1] = make_uint4(pk[4], pk[5], pk[6], pk[7]);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 31, hf = lane >> 5;
+    FwdW w;
+    load_fwd(a.mparams, a.mwq, col, hf, w);
+    float o0 = 0.f, o1 = 0.f;
+#pragma unroll
+    for (int blk = 0; blk < 2; ++blk) {
+        const uint2 *row = (const uint2 *)(s_feat + 2 * (wave * 64 + blk * 32 + col));
+        bf16x4 x[2];
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb) {
+            const uint2 v = row[2 * kb + hf];
+            x[kb][0] = (short)(v.x & 0xFFFFu);
+            x[kb][1] = (short)(v.x >> 16);
+            x[kb][2] = (short)(v.y & 0xFFFFu);
+            x[kb][3] = (short)(v.y >> 16);
+        }
+        FwdOut r;
+        forward_block(a.mparams, w, x, hf, r);
+        // lanes l and l + 32 both hold pixel blk * 32 + l % 32's outputs:
+        // lane l keeps the block that contains its own pixel (blk == l / 32)
+        if (blk == hf) {
+            o0 = r.o0;
+            o1 = r.o1;
+        }
+    }
+    mlp_heads(o0, o1, alpha, kappa);
+}
+
+// One 64x4 tile (bx, by).  MODE: kBlend (the temporal step), kFeat
+// (feature rows instead of the blend) or kLearn (features, the network,
+// then the blend with the network's alpha; kappa written out).  Returns
+// once this thread's pixel is done (the caller's barrier follows).
+enum { kBlend = 0, kFeat = 1, kLearn = 2 };
+
+template <typename T, bool TM, bool CLAMP, bool USE_ID, int MODE>
+__device__ __forceinline__ void temporal_tile(const TemporalArgs &a, float4 *tile, uint4 *s_feat,
+                                              uint32_t *wave_n, uint32_t &base_sh, int bx,
+                                              int by) {
+    const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
+    const int x = bx * kTX + lx, y = by * kTY + ly;
+    PxLoads g;
+    px_gather<T, USE_ID>(a, x, y, g);
+    stage_current<T, TM>(tile, a.cr, a.cg, a.cb, a.z, a.w, a.h, a.pitch, a.tm_k, bx, by);
+    __syncthreads();
+    const PxState s = px_reproject<CLAMP, USE_ID>(a, tile, lx, ly, x, y, g);
+    if (MODE == kFeat) {
+        if (!s.inimg) return;
+        float f[SV_MLP_IN];
+        px_features<T>(a, tile, lx, ly, s, f);
+        store_features(a, x, y, f);
+        if (a.fhr) {
+            stf(a.fhr, s.o, s.any ? s.hr : 0.f);
+            stf(a.fhg, s.o, s.any ? s.hg : 0.f);
+            stf(a.fhb, s.o, s.any ? s.hb : 0.f);
+        }
+        return;
+    }
+    float alpha = a.alpha;
+    if (MODE == kLearn) {
+        float f[SV_MLP_IN], kappa;
+        px_features<T>(a, tile, lx, ly, s, f);
+        px_network(a, s_feat, f, alpha, kappa);
+        if (s.inimg && a.kappa_out) stf(a.kappa_out, s.o, kappa);
+        if (s.inimg && a.alpha_out) stf(a.alpha_out, s.o, alpha);
+    } else if (a.alpha_map && s.inimg && s.any) {
+        alpha = ldf(a.alpha_map, s.o);
+    }
+    int n = 0;
+    float m2c = 0.f;
+    if (s.inimg) px_blend<T>(a, s, alpha, n, m2c);
+    if (a.var_out) {  // the variance estimate's first part (uniform branch)
+        const bool live = s.inimg && !s.empty;
+        const bool spatial = live && n < a.min_hist;
+        if (s.inimg && !spatial) stf(a.var_out, s.o, live ? fmaxf(0.f, m2c) : 0.f);
+        const int gxt = (a.w + kTX - 1) / kTX;
+        list_short_pixel(a.var_work, a.var_cap, by * gxt + bx, spatial, x, y, wave_n, base_sh);
+    }
+}
+
+template <typename T, bool TM, bool CLAMP, bool USE_ID, int MODE>
 __global__ __launch_bounds__(256) void temporal_k(TemporalArgs a) {
     __shared__ float4 tile[(kTX + 2) * (kTY + 2)];
+    __shared__ uint4 s_feat[MODE == kLearn ? 2 * 256 : 1];
+    __shared__ uint32_t wave_n[4], base_sh;
     const int gxt = (a.w + kTX - 1) / kTX;
     const int t = xcd_tile(gxt * ((a.h + kTY - 1) / kTY));
     if (t < 0) return;
     const int by = t / gxt, bx = t - by * gxt;
-    temporal_tile<T, TM, CLAMP, USE_ID, FEAT>(a, tile, bx, by);
+    temporal_tile<T, TM, CLAMP, USE_ID, MODE>(a, tile, s_feat, wave_n, base_sh, bx, by);
 }
 
-template <typename T, bool TM, bool CLAMP, bool USE_ID, bool FEAT>
+template <typename T, bool TM, bool CLAMP, bool USE_ID, int MODE>
 __global__ __launch_bounds__(256) void temporal_batch_k(const TemporalArgs *args, const int *prefix,
                                                         int n, int total) {
     __shared__ float4 tile[(kTX + 2) * (kTY + 2)];
+    __shared__ uint4 s_feat[MODE == kLearn ? 2 * 256 : 1];
+    __shared__ uint32_t wave_n[4], base_sh;
     const int per = (total + kXCD - 1) / kXCD, xcd = (int)blockIdx.x % kXCD;
     for (int slot = (int)blockIdx.x / kXCD; slot < per; slot += (int)gridDim.x / kXCD) {
         const int t = xcd * per + slot;
@@ -345,15 +497,16 @@ __global__ __launch_bounds__(256) void temporal_batch_k(const TemporalArgs *args
         const int s = batch_stream(prefix, n, t);
         const TemporalArgs a = args[s];
         const int lt = t - prefix[s], gxt = (a.w + kTX - 1) / kTX;
-        temporal_tile<T, TM, CLAMP, USE_ID, FEAT>(a, tile, lt % gxt, lt / gxt);
+        temporal_tile<T, TM, CLAMP, USE_ID, MODE>(a, tile, s_feat, wave_n, base_sh, lt % gxt,
+                                                  lt / gxt);
         __syncthreads();  // the next tile's staging reuses the LDS
     }
 }
 
-template <typename T, bool TM, bool CLAMP, bool USE_ID, bool FEAT>
+template <typename T, bool TM, bool CLAMP, bool USE_ID, int MODE>
 static void temporal_batch_launch(const void *args, const int *prefix, int n, int total, int bpc,
                                   hipStream_t s) {
-    hipLaunchKernelGGL((temporal_batch_k<T, TM, CLAMP, USE_ID, FEAT>),
+    hipLaunchKernelGGL((temporal_batch_k<T, TM, CLAMP, USE_ID, MODE>),
                        dim3(batch_grid(total, bpc)), dim3(256), 0, s, (const TemporalArgs *)args,
                        prefix, n, total);
 }
@@ -392,28 +545,28 @@ __global__ __launch_bounds__(256) void clamp_k(ClampArgs a) {
     sto<T>(a.ob, o, b);
 }
 
-template <typename T, bool TM, bool CLAMP, bool USE_ID, bool FEAT>
+template <typename T, bool TM, bool CLAMP, bool USE_ID, int MODE>
 static void launch_temporal_one(const TemporalArgs &a, dim3 grid, hipStream_t s) {
     const int tiles = ((a.w + kTX - 1) / kTX) * ((a.h + kTY - 1) / kTY);
-    if (record_pass(&temporal_batch_launch<T, TM, CLAMP, USE_ID, FEAT>, a, tiles, 8)) return;
-    hipLaunchKernelGGL((temporal_k<T, TM, CLAMP, USE_ID, FEAT>), grid, dim3(256), 0, s, a);
+    if (record_pass(&temporal_batch_launch<T, TM, CLAMP, USE_ID, MODE>, a, tiles, 8)) return;
+    hipLaunchKernelGGL((temporal_k<T, TM, CLAMP, USE_ID, MODE>), grid, dim3(256), 0, s, a);
 }
 
-template <typename T, bool TM, bool CLAMP, bool FEAT>
+template <typename T, bool TM, bool CLAMP, int MODE>
 static void launch_temporal_id(const TemporalArgs &a, bool use_id, dim3 grid, hipStream_t s) {
-    if (use_id) launch_temporal_one<T, TM, CLAMP, true, FEAT>(a, grid, s);
-    else launch_temporal_one<T, TM, CLAMP, false, FEAT>(a, grid, s);
+    if (use_id) launch_temporal_one<T, TM, CLAMP, true, MODE>(a, grid, s);
+    else launch_temporal_one<T, TM, CLAMP, false, MODE>(a, grid, s);
 }
 
-template <typename T, bool FEAT>
+template <typename T, int MODE>
 static void launch_temporal(const TemporalArgs &a, bool tm, bool clamp, bool use_id, dim3 grid,
                             hipStream_t s) {
     if (tm) {
-        if (clamp) launch_temporal_id<T, true, true, FEAT>(a, use_id, grid, s);
-        else launch_temporal_id<T, true, false, FEAT>(a, use_id, grid, s);
+        if (clamp) launch_temporal_id<T, true, true, MODE>(a, use_id, grid, s);
+        else launch_temporal_id<T, true, false, MODE>(a, use_id, grid, s);
     } else {
-        if (clamp) launch_temporal_id<T, false, true, FEAT>(a, use_id, grid, s);
-        else launch_temporal_id<T, false, false, FEAT>(a, use_id, grid, s);
+        if (clamp) launch_temporal_id<T, false, true, MODE>(a, use_id, grid, s);
+        else launch_temporal_id<T, false, false, MODE>(a, use_id, grid, s);
     }
 }
 
@@ -461,16 +614,73 @@ extern "C" int sv_temporal(const sv_temporal_io *io, sv_dims d, sv_dtype t,
     for (int i = 0; i < 6; ++i)
         for (int j = i + 1; j < 6; ++j)
             if (overlaps(outs[i], outs[j])) return SV_EALIAS;
+    if (io->var) {
+        if (!io->var_work || io->var_min_hist < 0) return SV_EINVAL;
+        const span vs = plane_span(io->var, d, 4);
+        const span ws{(uintptr_t)io->var_work,
+                      (uintptr_t)io->var_work + sv_variance_work_bytes(d)};
+        for (const span &si : ins)
+            if (overlaps(vs, si) || overlaps(ws, si)) return SV_EALIAS;
+        for (const span &so : outs)
+            if (overlaps(vs, so) || overlaps(ws, so)) return SV_EALIAS;
+        if (overlaps(vs, ws)) return SV_EALIAS;
+    }
+    const bool learn = io->mlp != nullptr;
+    if (learn) {
+        const void *lreq[] = {io->g.dzdx, io->g.dzdy, io->albedo.r, io->albedo.g, io->albedo.b,
+                              io->mlp->params, io->mlp->wq, io->mlp->mu, io->mlp->inv_s};
+        for (const void *q : lreq)
+            if (!q) return SV_EINVAL;
+        const span lins[] = {plane_span(io->g.dzdx, d, es), plane_span(io->g.dzdy, d, es),
+                             plane_span(io->albedo.r, d, es), plane_span(io->albedo.g, d, es),
+                             plane_span(io->albedo.b, d, es)};
+        const span louts[] = {io->kappa_out ? plane_span(io->kappa_out, d, 4) : span{0, 0},
+                              io->alpha_out ? plane_span(io->alpha_out, d, 4) : span{0, 0}};
+        for (const span &so : louts) {
+            for (const span &si : ins)
+                if (overlaps(so, si)) return SV_EALIAS;
+            for (const span &si : lins)
+                if (overlaps(so, si)) return SV_EALIAS;
+            for (const span &si : outs)
+                if (overlaps(so, si)) return SV_EALIAS;
+        }
+        if (overlaps(louts[0], louts[1])) return SV_EALIAS;
+        for (const span &so : outs)
+            for (const span &si : lins)
+                if (overlaps(so, si)) return SV_EALIAS;
+    }
     TemporalArgs a{io->cur.r, io->cur.g, io->cur.b, io->g.z, io->g.nx, io->g.ny, io->g.nz,
                    io->g.id, io->mvx, io->mvy, io->prev.z, io->prev.nx, io->prev.ny,
                    io->prev.nz, io->prev.id, io->hist.r, io->hist.g, io->hist.b, io->hist_m1,
                    io->hist_m2c, io->hist_n, io->out.r, io->out.g, io->out.b, io->out_m1,
-                   io->out_m2c, io->out_n, io->alpha_map, d.w, d.h, d.pitch, p->alpha,
-                   p->alpha_m, p->gamma, p->tau_z, p->tau_n, p->tm_k, p->max_hist};
+                   io->out_m2c, io->out_n, learn ? nullptr : io->alpha_map, d.w, d.h, d.pitch,
+                   p->alpha, p->alpha_m, p->gamma, p->tau_z, p->tau_n, p->tm_k, p->max_hist};
     dim3 grid(xcd_grid(((d.w + kTX - 1) / kTX) * ((d.h + kTY - 1) / kTY)));
     hipStream_t s = as_stream(stream);
-    if (t == SV_F32) launch_temporal<float, false>(a, tm, clamp, use_id, grid, s);
-    else launch_temporal<half_t, false>(a, tm, clamp, use_id, grid, s);
+    if (io->var) {
+        a.var_out = io->var;
+        a.var_work = (VarWork *)io->var_work;
+        a.var_cap = (point_grid(d) / kXCD) * 256u;
+        a.min_hist = io->var_min_hist;
+    }
+    if (learn) {
+        a.dzdx = io->g.dzdx;
+        a.dzdy = io->g.dzdy;
+        a.alr = io->albedo.r;
+        a.alg = io->albedo.g;
+        a.alb = io->albedo.b;
+        a.mu = io->mlp->mu;
+        a.inv_s = io->mlp->inv_s;
+        a.mparams = io->mlp->params;
+        a.mwq = io->mlp->wq;
+        a.kappa_out = io->kappa_out;
+        a.alpha_out = io->alpha_out;
+        if (t == SV_F32) launch_temporal<float, kLearn>(a, tm, clamp, use_id, grid, s);
+        else launch_temporal<half_t, kLearn>(a, tm, clamp, use_id, grid, s);
+    } else {
+        if (t == SV_F32) launch_temporal<float, kBlend>(a, tm, clamp, use_id, grid, s);
+        else launch_temporal<half_t, kBlend>(a, tm, clamp, use_id, grid, s);
+    }
     return hip_status(hipGetLastError());
 }
 
@@ -536,8 +746,8 @@ extern "C" int sv_mlp_features(const sv_temporal_io *io, const sv_rgb *albedo, c
                    hist_out ? (float *)hist_out->b : nullptr, w->mu, w->inv_s};
     dim3 grid(xcd_grid(((d.w + kTX - 1) / kTX) * ((d.h + kTY - 1) / kTY)));
     hipStream_t s = as_stream(stream);
-    if (t == SV_F32) launch_temporal<float, true>(a, tm, clamp, use_id, grid, s);
-    else launch_temporal<half_t, true>(a, tm, clamp, use_id, grid, s);
+    if (t == SV_F32) launch_temporal<float, kFeat>(a, tm, clamp, use_id, grid, s);
+    else launch_temporal<half_t, kFeat>(a, tm, clamp, use_id, grid, s);
     return hip_status(hipGetLastError());
 }
 

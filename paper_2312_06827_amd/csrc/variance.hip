@@ -10,21 +10,7 @@
 
 namespace sv {
 
-constexpr int kVX = 64, kVY = 4;
 constexpr int kSpatialBlocks = 1024;  // pass-2 grid (grid-stride over the list)
-constexpr int kLines = 32;             // counters sit 128 bytes apart
-
-// Workspace: eight counters, then eight sublists; tile t appends to
-// sublist t % 8, so each sublist holds at most ceil(tiles / 8) tiles'
-// pixels (its capacity) whichever workgroup runs the tile.
-struct VarWork {
-    uint32_t count[kXCD * kLines];  // count[k * kLines]: entries in sublist k
-    uint32_t list[1];               // sublist k at list + k * cap: (y << 15) | x
-};
-
-inline uint32_t point_grid(sv_dims d) {
-    return xcd_grid(((d.w + kVX - 1) / kVX) * ((d.h + kVY - 1) / kVY));
-}
 
 struct VarianceArgs {
     const float *m1, *m2c;
@@ -55,23 +41,7 @@ __device__ __forceinline__ void variance_point_tile(const VarianceArgs &a, int t
     const bool live = inside && n >= 1 && !empty_px(zp);
     const bool spatial = live && n < a.min_hist;
     if (inside && !spatial) stf(a.var, o, live ? fmaxf(0.f, m2) : 0.f);
-    // list the short-history pixels: one atomic per workgroup, on this XCD's counter
-    const uint64_t mask = __ballot(spatial);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) wave_n[wave] = (uint32_t)__popcll(mask);
-    __syncthreads();
-    const uint32_t n0 = wave_n[0], n1 = wave_n[1], n2 = wave_n[2], n3 = wave_n[3];
-    const uint32_t total = n0 + n1 + n2 + n3;
-    if (total == 0) return;  // uniform over the workgroup
-    const uint32_t k = (uint32_t)tile % kXCD;
-    if (threadIdx.x == 0) base_sh = atomicAdd(&a.work->count[k * kLines], total);
-    __syncthreads();
-    const uint32_t before = (wave > 0 ? n0 : 0u) + (wave > 1 ? n1 : 0u) + (wave > 2 ? n2 : 0u);
-    const uint32_t slot =
-        base_sh + before + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
-    // a sublist holds every pixel of its workgroups; a workspace that was
-    // not zeroed cannot push a store past its end
-    if (spatial && slot < a.cap) a.work->list[k * a.cap + slot] = ((uint32_t)y << 15) | (uint32_t)x;
+    list_short_pixel(a.work, a.cap, tile, spatial, x, y, wave_n, base_sh);
 }
 
 template <typename T>
@@ -233,9 +203,10 @@ void launch_spatial(const VarianceArgs &a, hipStream_t s) {
 }
 
 template <typename T>
-void launch_variance(const VarianceArgs &a, unsigned grid, int radius, hipStream_t s) {
+void launch_variance(const VarianceArgs &a, unsigned grid, int radius, bool listed,
+                     hipStream_t s) {
     const int tiles = ((a.w + kVX - 1) / kVX) * ((a.h + kVY - 1) / kVY);
-    if (!record_pass(&point_batch_launch<T>, a, tiles, 8))
+    if (!listed && !record_pass(&point_batch_launch<T>, a, tiles, 8))
         hipLaunchKernelGGL(variance_point_k<T>, dim3(grid), dim3(256), 0, s, a);
     switch (radius) {
     case 0: launch_spatial<T, 0>(a, s); break;
@@ -286,9 +257,10 @@ extern "C" int sv_variance(const float *m1, const float *m2c, const uint8_t *n, 
                    (VarWork *)work, (grid / kXCD) * 256u, d.w, d.h, d.pitch, p->sigma_z,
                    p->eps_z, make_normal_coef(p->sigma_n), p->min_hist};
     hipStream_t s = as_stream(stream);
+    const bool listed = (p->flags & SV_V_LISTED) != 0;
     if (t == SV_F32)
-        launch_variance<float>(a, grid, p->radius, s);
+        launch_variance<float>(a, grid, p->radius, listed, s);
     else
-        launch_variance<half_t>(a, grid, p->radius, s);
+        launch_variance<half_t>(a, grid, p->radius, listed, s);
     return hip_status(hipGetLastError());
 }

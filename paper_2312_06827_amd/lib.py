@@ -28,6 +28,7 @@ SV_F32, SV_F16 = 0, 1
 SV_TM_LUMA, SV_TM_CHANNEL, SV_TM_PAPER = 0, 1, 2
 SV_T_CLAMP, SV_T_USE_ID, SV_T_TONEMAP_IN = 1, 2, 4
 SV_A_UNIT_WEIGHTS, SV_A_INV_TONEMAP = 1, 2
+SV_V_LISTED = 1
 
 _vp = ctypes.c_void_p
 
@@ -53,7 +54,8 @@ class sv_temporal_io(ctypes.Structure):
     _fields_ = [("cur", sv_rgb), ("g", sv_gbuf), ("mvx", _vp), ("mvy", _vp),
                 ("prev", sv_gbuf), ("hist", sv_rgb), ("hist_m1", _vp), ("hist_m2c", _vp),
                 ("hist_n", _vp), ("out", sv_rgb), ("out_m1", _vp), ("out_m2c", _vp),
-                ("out_n", _vp), ("alpha_map", _vp)]
+                ("out_n", _vp), ("alpha_map", _vp), ("mlp", _vp), ("albedo", sv_rgb),
+                ("kappa_out", _vp), ("alpha_out", _vp)]
 
 
 class sv_temporal_params(ctypes.Structure):
@@ -66,7 +68,7 @@ class sv_temporal_params(ctypes.Structure):
 class sv_variance_params(ctypes.Structure):
     _fields_ = [("sigma_z", ctypes.c_float), ("sigma_n", ctypes.c_float),
                 ("eps_z", ctypes.c_float), ("min_hist", ctypes.c_int32),
-                ("radius", ctypes.c_int32)]
+                ("radius", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
 
 class sv_atrous_params(ctypes.Structure):
@@ -81,12 +83,13 @@ class sv_denoiser(ctypes.Structure):
     _fields_ = [("hist", sv_rgb * 2), ("m1", _vp * 2), ("m2c", _vp * 2), ("n", _vp * 2),
                 ("temporal", sv_rgb), ("var", _vp), ("var_work", _vp), ("level", sv_rgb * 2),
                 ("level_var", _vp * 2), ("scratch", sv_rgb), ("out", sv_rgb),
-                ("cur", ctypes.c_int32)]
+                ("cur", ctypes.c_int32), ("kappa", _vp)]
 
 
 class sv_frame_in(ctypes.Structure):
     _fields_ = [("cur", sv_rgb), ("g", sv_gbuf), ("mvx", _vp), ("mvy", _vp),
-                ("prev", sv_gbuf), ("alpha_map", _vp), ("kappa", _vp)]
+                ("prev", sv_gbuf), ("alpha_map", _vp), ("kappa", _vp), ("mlp", _vp),
+                ("albedo", sv_rgb)]
 
 
 class sv_frame_params(ctypes.Structure):
@@ -276,10 +279,11 @@ class VarianceParams:
     eps_z: float = 1e-10
     min_hist: int = 4
     radius: int = 3
+    listed: bool = False  # the temporal step already wrote the pointwise part and the list
 
     def c(self) -> sv_variance_params:
         return sv_variance_params(self.sigma_z, self.sigma_n, self.eps_z, self.min_hist,
-                                  self.radius)
+                                  self.radius, SV_V_LISTED if self.listed else 0)
 
 
 @dataclass
@@ -325,13 +329,26 @@ def sv_clamp(hist: Planes, cur: Planes, out: Planes, gamma: float,
 def sv_temporal(cur: Planes, g: GBuf, mv: Planes, prev: GBuf, hist: Planes,
                 hist_m1: torch.Tensor, hist_m2c: torch.Tensor, hist_n: torch.Tensor,
                 out: Planes, out_m1: torch.Tensor, out_m2c: torch.Tensor, out_n: torch.Tensor,
-                params: TemporalParams, alpha_map: Optional[torch.Tensor] = None, stream=None):
-    """m2c planes hold the central moment E[L^2] - E[L]^2."""
+                params: TemporalParams, alpha_map: Optional[torch.Tensor] = None, stream=None,
+                mlp: Optional["MLP"] = None, albedo: Optional[Planes] = None,
+                kappa_out: Optional[torch.Tensor] = None,
+                alpha_out: Optional[torch.Tensor] = None,
+                var: Optional[torch.Tensor] = None, var_work: Optional[torch.Tensor] = None,
+                var_min_hist: int = 4):
+    """m2c planes hold the central moment E[L^2] - E[L]^2.  With `mlp` the
+    network runs inside the step (needs albedo; alpha_map is ignored).
+    With `var` (and its sv_variance workspace) the variance estimate's
+    pointwise part is written here (finish with VarianceParams(listed=True))."""
     mvx, mvy = mv[0], mv[1]
+    mc = None if mlp is None else mlp.c()
     io = sv_temporal_io(_rgb(cur), g.c(), _plane_ptr(mvx), _plane_ptr(mvy), prev.c(),
                         _rgb(hist), _plane_ptr(hist_m1), _plane_ptr(hist_m2c),
                         _plane_ptr(hist_n), _rgb(out), _plane_ptr(out_m1), _plane_ptr(out_m2c),
-                        _plane_ptr(out_n), _plane_ptr(alpha_map))
+                        _plane_ptr(out_n), _plane_ptr(alpha_map),
+                        None if mc is None else ctypes.addressof(mc),
+                        _rgb(albedo) if albedo is not None else sv_rgb(),
+                        _plane_ptr(kappa_out), _plane_ptr(alpha_out), _plane_ptr(var),
+                        None if var_work is None else var_work.data_ptr(), int(var_min_hist))
     r = _planes3(cur)[0]
     pc = params.c()
     _check("sv_temporal", load().sv_temporal(ctypes.byref(io), dims_of(r), dtype_of(r),

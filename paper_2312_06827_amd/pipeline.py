@@ -87,16 +87,24 @@ class FrameInputs:
     g: GBuf                    # current G-buffer
     mv: torch.Tensor           # (2, H, W) backward motion
     prev: GBuf                 # previous frame's z, n, id
+    albedo: Optional[torch.Tensor] = None  # (3, H, W), for the learned mode
 
     def c(self, alpha_map: Optional[torch.Tensor] = None,
-          kappa: Optional[torch.Tensor] = None) -> lib.sv_frame_in:
+          kappa: Optional[torch.Tensor] = None, mlp=None) -> lib.sv_frame_in:
+        """mlp: a lib.sv_mlp structure (kept alive by the caller) for the
+        learned mode."""
         key = (None if alpha_map is None else alpha_map.data_ptr(),
-               None if kappa is None else kappa.data_ptr())
+               None if kappa is None else kappa.data_ptr(),
+               None if mlp is None else ctypes.addressof(mlp))
         cached = self.__dict__.get("_c")
         if cached is None or cached[0] != key:
+            if mlp is not None and self.albedo is None:
+                raise ValueError("the learned mode needs the albedo planes")
             fin = lib.sv_frame_in(lib._rgb(self.rgb), self.g.c(), lib._plane_ptr(self.mv[0]),
                                   lib._plane_ptr(self.mv[1]), self.prev.c(),
-                                  lib._plane_ptr(alpha_map), lib._plane_ptr(kappa))
+                                  lib._plane_ptr(alpha_map), lib._plane_ptr(kappa),
+                                  None if mlp is None else ctypes.addressof(mlp),
+                                  lib._rgb(self.albedo) if mlp is not None else lib.sv_rgb())
             self.__dict__["_c"] = cached = (key, fin)
         return cached[1]
 
@@ -109,12 +117,16 @@ class FrameInputs:
             g=GBuf(t(fr["z"]), t(fr["dzdx"]), t(fr["dzdy"]), t(fr["n"]), t(fr["id"])),
             mv=t(fr["mv"]),
             prev=GBuf(t(fr["prev_z"]), None, None, t(fr["prev_n"]), t(fr["prev_id"])),
+            albedo=t(fr["albedo"]) if "albedo" in fr else None,
         )
 
 
 class Denoiser:
     def __init__(self, height: int, width: int, cfg: FilterConfig = PLAIN,
-                 dtype: torch.dtype = torch.float32, device: str = "cuda", tiles=None):
+                 dtype: torch.dtype = torch.float32, device: str = "cuda", tiles=None,
+                 mlp: Optional[lib.MLP] = None):
+        """mlp: run the learned network inside the temporal step (its alpha
+        and kappa replace the constants)."""
         lib.load()
         self.H, self.W, self.cfg, self.dtype = height, width, cfg, dtype
         dev = torch.device(device)
@@ -144,7 +156,12 @@ class Denoiser:
             R(self.t_rgb[0]), self.var.data_ptr(), self.var_work.data_ptr(),
             (lib.sv_rgb * 2)(R(self.lvl[0]), R(self.lvl[1])),
             (lib._vp * 2)(*[t.data_ptr() for t in self.lvl_var]),
-            scratch, R(self.out), 0)
+            scratch, R(self.out), 0, None)
+        self.mlp = mlp
+        self._mlp_c = mlp.c() if mlp is not None else None
+        self.kappa = f32() if mlp is not None else None
+        if self.kappa is not None:
+            self._st.kappa = self.kappa.data_ptr()
         self._dims = lib.dims_of(self.out)
         self._dtype = lib.dtype_of(self.out)
         self.tiles = tiles
@@ -178,10 +195,12 @@ class Denoiser:
         stream reaches it; overwritten by the next frame).  `timer(name)`,
         if given, wraps each library call (for per-kernel events)."""
         if timer is None:
-            lib.sv_denoise_frame(inp.c(alpha_map, kappa), self._st, self._dims, self._dtype,
-                                 self._params, stream=stream)
+            lib.sv_denoise_frame(inp.c(alpha_map, kappa, self._mlp_c), self._st, self._dims,
+                                 self._dtype, self._params, stream=stream)
             self.frames += 1
             return self.out
+        if self.mlp is not None:
+            alpha_map, kappa = None, self.kappa
         # the same sequence call by call, for per-kernel timing
         cfg, k, k1 = self.cfg, self.k, 1 - self.k
         tm = timer
@@ -191,10 +210,15 @@ class Denoiser:
         with tm("temporal"):
             lib.sv_temporal(inp.rgb, inp.g, inp.mv, inp.prev, hist, self.m1[k], self.m2c[k],
                             self.n[k], t_out, self.m1[k1], self.m2c[k1], self.n[k1],
-                            cfg.temporal(), alpha_map=alpha_map, stream=stream)
+                            cfg.temporal(), alpha_map=alpha_map, stream=stream,
+                            mlp=self.mlp, albedo=inp.albedo,
+                            kappa_out=self.kappa if self.mlp is not None else None,
+                            var=self.var, var_work=self.var_work, var_min_hist=cfg.min_hist)
         with tm("variance"):
-            lib.sv_variance(self.m1[k1], self.m2c[k1], self.n[k1], inp.g, self.var,
-                            cfg.variance(), self.var_work, stream=stream)
+            vp = cfg.variance()
+            vp.listed = True
+            lib.sv_variance(self.m1[k1], self.m2c[k1], self.n[k1], inp.g, self.var, vp,
+                            self.var_work, stream=stream)
         c, v = t_out, self.var
         L = cfg.levels
         for i in range(L):
@@ -245,8 +269,8 @@ class BatchDenoiser:
     results are bitwise those of that Denoiser run alone."""
 
     def __init__(self, sizes, cfg: FilterConfig = MOTION, dtype: torch.dtype = torch.float32,
-                 tiles=None, device: str = "cuda"):
-        self.streams = [Denoiser(h, w, cfg, dtype, device, tiles) for (h, w) in sizes]
+                 tiles=None, device: str = "cuda", mlp: Optional[lib.MLP] = None):
+        self.streams = [Denoiser(h, w, cfg, dtype, device, tiles, mlp) for (h, w) in sizes]
         n = len(self.streams)
         self._dims = (lib.sv_dims * n)(*[d._dims for d in self.streams])
         self._states = (ctypes.POINTER(lib.sv_denoiser) * n)(
@@ -263,7 +287,8 @@ class BatchDenoiser:
         Returns the streams' output tensors."""
         if len(inputs) != len(self.streams):
             raise ValueError("one FrameInputs per stream")
-        fins = (lib.sv_frame_in * len(inputs))(*[inp.c() for inp in inputs])
+        fins = (lib.sv_frame_in * len(inputs))(
+            *[inp.c(mlp=d._mlp_c) for inp, d in zip(inputs, self.streams)])
         lib._check("sv_batch_frame", lib.load().sv_batch_frame(
             self._plan, fins, lib._stream(stream)))
         for d in self.streams:

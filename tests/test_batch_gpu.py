@@ -73,3 +73,28 @@ def test_batch_sixteen_uneven_streams_first_frames():
             say(f"  frame {f}: 16 streams bitwise equal")
     finally:
         batch.close()
+
+
+def test_batch_learned_streams():
+    """Batched streams with the network inside the temporal step equal the
+    single streams bitwise."""
+    from oracle import mlp as M
+    from paper_2312_06827_amd import lib as L
+    w = M.init_weights(7)
+    w.w3 = np.random.default_rng(7).normal(0, 0.5, w.w3.shape)
+    mlp = L.MLP(w.flat(), np.zeros(14), np.ones(14))
+    scfg = _streams(False, 3)
+    batch = BatchDenoiser(SIZES, MOTION, torch.float32, mlp=mlp)
+    singles = [Denoiser(h, w_, MOTION, torch.float32, mlp=mlp) for (h, w_) in SIZES]
+    say("batch of learned streams")
+    try:
+        for f in range(3):
+            inputs = [FrameInputs.from_numpy(render_frame(c, f)) for c in scfg]
+            outs = batch.frame(inputs)
+            refs = [d.frame(inp) for d, inp in zip(singles, inputs)]
+            torch.cuda.synchronize()
+            for i in range(len(SIZES)):
+                assert torch.equal(outs[i], refs[i]), (f, i)
+                assert torch.equal(batch.streams[i].kappa, singles[i].kappa), (f, i)
+    finally:
+        batch.close()

@@ -235,3 +235,70 @@ def test_training_beats_plain_filter():
     say(f"held-out RelMSE: plain {plain:.5f}, learned {learned:.5f}")
     assert np.isfinite(learned)
     assert learned < plain
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float16])
+def test_learned_temporal_equals_separate_path(dtype):
+    """The network inside sv_temporal gives bitwise what sv_mlp_features +
+    sv_mlp_forward + sv_temporal(alpha_map) give, alpha and kappa included."""
+    H, W = 90, 160
+    fr, st, p = _history_state(H, W, 123)
+    w = _weights(31)
+    mlp = _device_mlp(w)
+    d = lambda a, dt=dtype: dev(a, dt)
+    g = L.GBuf(d(fr["z"]), d(fr["dzdx"]), d(fr["dzdy"]), d(fr["n"]), dev(fr["id"], torch.uint8))
+    prev = L.GBuf(d(fr["prev_z"]), None, None, d(fr["prev_n"]), dev(fr["prev_id"], torch.uint8))
+    m2c = (st["m2"] - st["m1"] ** 2).astype(np.float32)
+    hist = (d(st["rgb"]), dev(st["m1"]), dev(m2c), dev(st["n"], torch.uint8))
+    tp = L.TemporalParams(clamp=True, tonemap=True, use_id=True)
+    alb = d(fr["albedo"])
+    say(f"learned temporal, {dtype}")
+    # separate kernels
+    feat = L.feature_rows(H, W)
+    L.sv_mlp_features(d(fr["rgb"]), g, d(fr["mv"]), prev, *hist, alb, mlp, feat, tp)
+    a1 = torch.empty((H, W), device="cuda")
+    k1 = torch.empty((H, W), device="cuda")
+    L.sv_mlp_forward(mlp, feat, a1, k1, a1)
+    outs = []
+    for fused in (False, True):
+        out = torch.empty((3, H, W), dtype=dtype, device="cuda")
+        om1, om2 = torch.empty((H, W), device="cuda"), torch.empty((H, W), device="cuda")
+        on = torch.empty((H, W), dtype=torch.uint8, device="cuda")
+        a2, k2 = torch.empty((H, W), device="cuda"), torch.empty((H, W), device="cuda")
+        if fused:
+            L.sv_temporal(d(fr["rgb"]), g, d(fr["mv"]), prev, *hist, out, om1, om2, on, tp,
+                          mlp=mlp, albedo=alb, kappa_out=k2, alpha_out=a2)
+        else:
+            L.sv_temporal(d(fr["rgb"]), g, d(fr["mv"]), prev, *hist, out, om1, om2, on, tp,
+                          alpha_map=a1)
+            a2, k2 = a1, k1
+        outs.append([host(t) for t in (out, om1, om2, on, a2, k2)])
+    for name, x, y in zip(("rgb", "m1", "m2c", "n", "alpha", "kappa"), *outs):
+        np.testing.assert_array_equal(x, y, err_msg=name)
+
+
+def test_learned_driver_matches_learned_calls():
+    """Denoiser(mlp=...) through the native driver equals its call-by-call
+    path and the separate-kernel learned chain, bitwise, over a sequence."""
+    from paper_2312_06827_amd import learn
+    from paper_2312_06827_amd.pipeline import MOTION, Denoiser, FrameInputs
+    cfg = with_size(CONFIGS["hd_motion"], 200, 120, 5)
+    w = _weights(41)
+    mlp = _device_mlp(w)
+    a = Denoiser(cfg.height, cfg.width, MOTION, mlp=mlp)
+    b = Denoiser(cfg.height, cfg.width, MOTION, mlp=mlp)
+    c = learn.LearnedDenoiser(cfg.height, cfg.width, mlp, MOTION)
+
+    class _Null:
+        def __call__(self, name):
+            import contextlib
+            return contextlib.nullcontext()
+
+    say("learned native driver vs calls vs separate kernels")
+    for fr in sequence(cfg):
+        inp = FrameInputs.from_numpy(fr)
+        oa = a.frame(inp).clone()
+        ob = b.frame(inp, timer=_Null()).clone()
+        oc = c.frame(inp, inp.albedo).clone()
+        assert torch.equal(oa, ob)
+        assert torch.equal(oa, oc)

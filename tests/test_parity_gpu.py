@@ -336,3 +336,31 @@ def test_atrous_sep_fused_equals_two_pass(H, W, dtype):
             np.testing.assert_array_equal(res[1][0], res[0][0])
             if want_var:
                 np.testing.assert_array_equal(res[1][1], res[0][1])
+
+
+@pytest.mark.parametrize("H,W", [(37, 70), (130, 200)])
+def test_temporal_variance_listing_equals_variance_pass(H, W):
+    """sv_temporal writing the variance's pointwise part and its list, then
+    sv_variance(listed), gives bitwise what sv_temporal then sv_variance
+    give; twice in a row (the workspace returns to zero)."""
+    fr, st = _temporal_case(H, W, 57 + H)
+    g = gbuf_dev(fr["z"], fr["dzdx"], fr["dzdy"], fr["n"], None, fr["id"])
+    prev = L.GBuf(dev(fr["prev_z"]), None, None, dev(fr["prev_n"]), dev(fr["prev_id"], None, torch.uint8))
+    tp = L.TemporalParams(clamp=True, tonemap=True, use_id=True)
+    res = []
+    for fused in (False, True, True):
+        out = empty_like_dev((3, H, W))
+        om1, om2 = empty_like_dev((H, W)), empty_like_dev((H, W))
+        on = empty_like_dev((H, W), dtype=torch.uint8)
+        var = empty_like_dev((H, W))
+        work = L.variance_workspace(var)
+        say(f"temporal + variance listing {H}x{W} fused={fused}")
+        L.sv_temporal(dev(fr["rgb"]), g, dev(fr["mv"]), prev, dev(st["rgb"]), dev(st["m1"]),
+                      dev(st["m2c"]), dev(st["n"], None, torch.uint8), out, om1, om2, on, tp,
+                      var=var if fused else None, var_work=work if fused else None)
+        L.sv_variance(om1, om2, on, g, var, L.VarianceParams(listed=fused), work)
+        res.append((host(out), host(var)))
+        assert int(work[:256].abs().sum().item()) == 0
+    for r in res[1:]:
+        np.testing.assert_array_equal(r[0], res[0][0])
+        np.testing.assert_array_equal(r[1], res[0][1])
