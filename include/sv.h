@@ -496,6 +496,13 @@ void sv_batch_destroy(sv_batch *b);
 /* ---- misc --------------------------------------------------------------- */
 
 /* Static string for a status code (never NULL). */
+/* ABI self-check for bindings: writes sizeof of sv_dims, sv_rgb, sv_gbuf,
+ * sv_tm_params, sv_temporal_io, sv_temporal_params, sv_variance_params,
+ * sv_atrous_params, sv_denoiser, sv_frame_in, sv_frame_params, sv_mlp and
+ * sv_adam_params (in that order, at most n of them) and returns how many
+ * there are. */
+int sv_struct_sizes(size_t *sizes, int32_t n);
+
 const char *sv_status_str(int status);
 
 /* ABI version: increases when a signature or a struct changes. */

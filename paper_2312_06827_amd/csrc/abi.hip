@@ -55,3 +55,17 @@ int sv_probe_copy(void *dst, const void *src, size_t bytes, sv_stream stream) {
 }
 
 }  // extern "C"
+
+extern "C" int sv_struct_sizes(size_t *sizes, int32_t n) {
+    const size_t all[] = {sizeof(sv_dims),          sizeof(sv_rgb),
+                          sizeof(sv_gbuf),          sizeof(sv_tm_params),
+                          sizeof(sv_temporal_io),   sizeof(sv_temporal_params),
+                          sizeof(sv_variance_params), sizeof(sv_atrous_params),
+                          sizeof(sv_denoiser),      sizeof(sv_frame_in),
+                          sizeof(sv_frame_params),  sizeof(sv_mlp),
+                          sizeof(sv_adam_params)};
+    const int32_t k = (int32_t)(sizeof(all) / sizeof(all[0]));
+    if (!sizes || n < 0) return SV_EINVAL;
+    for (int32_t i = 0; i < n && i < k; ++i) sizes[i] = all[i];
+    return k;
+}

@@ -55,7 +55,8 @@ class sv_temporal_io(ctypes.Structure):
                 ("prev", sv_gbuf), ("hist", sv_rgb), ("hist_m1", _vp), ("hist_m2c", _vp),
                 ("hist_n", _vp), ("out", sv_rgb), ("out_m1", _vp), ("out_m2c", _vp),
                 ("out_n", _vp), ("alpha_map", _vp), ("mlp", _vp), ("albedo", sv_rgb),
-                ("kappa_out", _vp), ("alpha_out", _vp)]
+                ("kappa_out", _vp), ("alpha_out", _vp), ("var", _vp), ("var_work", _vp),
+                ("var_min_hist", ctypes.c_int32)]
 
 
 class sv_temporal_params(ctypes.Structure):
@@ -147,6 +148,7 @@ EXPORTS = {
     "sv_batch_frame": ([_vp, _P(sv_frame_in), _vp], ctypes.c_int),
     "sv_batch_passes": ([_vp], ctypes.c_int),
     "sv_batch_destroy": ([_vp], None),
+    "sv_struct_sizes": ([_P(ctypes.c_size_t), ctypes.c_int32], ctypes.c_int),
     "sv_status_str": ([ctypes.c_int], ctypes.c_char_p),
     "sv_version": ([], ctypes.c_int),
     "sv_last_hip_error": ([], ctypes.c_int),
