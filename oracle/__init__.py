@@ -32,7 +32,7 @@ from typing import Dict, Optional
 import numpy as np
 
 __all__ = [
-    "OracleParams", "tonemap", "reproject", "clamp", "blend", "temporal",
+    "OracleParams", "tonemap", "reproject", "clamp", "clip", "blend", "temporal",
     "variance", "atrous", "atrous_sep", "quantize_half", "new_state",
     "run_frame", "luma",
 ]
@@ -49,6 +49,7 @@ TM_MODES = {"luma": 0, "channel": 1, "paper": 2}
 T_CLAMP = 1
 T_USE_ID = 2
 T_TONEMAP_IN = 4
+T_CLIP = 8
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int32)
@@ -75,6 +76,7 @@ def _load():
             [_I, _I] + [_dp] * 4 + [_up] + [_dp] * 6 + [_up] + [_dp] * 5 + [_ip]
             + [_D, _D, _I] + [_dp] * 5 + [_ip, _ip])
         lib.svo_clamp.argtypes = [_I, _I] + [_dp] * 7 + [_D] + [_dp] * 3
+        lib.svo_clip.argtypes = [_I, _I] + [_dp] * 7 + [_D] + [_dp] * 3
         lib.svo_blend.argtypes = (
             [_L] + [_dp] * 9 + [_ip, _ip, _D, _D, _dp, _I, _I] + [_dp] * 5 + [_ip])
         lib.svo_temporal.argtypes = (
@@ -126,6 +128,7 @@ class OracleParams:
     tau_n: float = 0.9
     gamma: float = 1.0
     clamp: bool = False
+    clip: bool = False  # clip the history toward the box centre instead of clamping
     use_id: bool = False
     tonemap: bool = False
     tm_k: float = 1.0
@@ -180,6 +183,17 @@ def clamp(hist_rgb, cur_rgb, gamma, z=None):
     return out
 
 
+def clip(hist_rgb, cur_rgb, gamma, z=None):
+    hist_rgb, cur_rgb = _f64(hist_rgb), _f64(cur_rgb)
+    z = None if z is None else _f64(z)
+    H, W = hist_rgb.shape[1:]
+    out = np.empty_like(hist_rgb)
+    _load().svo_clip(W, H, _ptr(hist_rgb[0]), _ptr(hist_rgb[1]), _ptr(hist_rgb[2]),
+                     _ptr(cur_rgb[0]), _ptr(cur_rgb[1]), _ptr(cur_rgb[2]), _ptr(z),
+                     float(gamma), _ptr(out[0]), _ptr(out[1]), _ptr(out[2]))
+    return out
+
+
 def blend(cur_rgb, z, hist_rgb, hist_m1, hist_m2, hist_n, valid, alpha=0.2,
           alpha_m=0.2, alpha_map=None, max_hist=255, half_out=False):
     cur_rgb, z, hist_rgb, hist_m1, hist_m2 = map(_f64, (cur_rgb, z, hist_rgb, hist_m1, hist_m2))
@@ -212,8 +226,8 @@ def temporal(frame: Dict[str, np.ndarray], state: Dict[str, np.ndarray],
            for k in ("id", "prev_id")]
     am = None if alpha_map is None else _f64(alpha_map)
     H, W = z.shape
-    flags = (T_CLAMP if p.clamp else 0) | (T_USE_ID if p.use_id else 0) | \
-        (T_TONEMAP_IN if p.tonemap else 0)
+    flags = (T_CLAMP if p.clamp else 0) | (T_CLIP if p.clip else 0) | \
+        (T_USE_ID if p.use_id else 0) | (T_TONEMAP_IN if p.tonemap else 0)
     o = np.empty((5, H, W))
     on = np.empty((H, W), np.int32)
     rc = _load().svo_temporal(

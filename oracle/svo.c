@@ -14,6 +14,7 @@
  *   svo_tonemap      Reinhard tone map and its inverse (Section 3.4)
  *   svo_reproject    backward reprojection of the history (Section 2)
  *   svo_clamp        variance colour clamp of the history (Sections 2, 3.1)
+ *   svo_clip         variance colour clipping of the history (Section 3.1)
  *   svo_blend        temporal accumulation of colour and moments (Section 2)
  *   svo_temporal     the four steps above in order (Section 3, step 4)
  *   svo_variance     per-pixel variance from the moments (Section 2)
@@ -47,6 +48,7 @@
 #define SVO_T_CLAMP 1        /* temporal: clamp the reprojected history */
 #define SVO_T_USE_ID 2       /* temporal: object ids must match */
 #define SVO_T_TONEMAP_IN 4   /* temporal: tone map the current colour first */
+#define SVO_T_CLIP 8         /* temporal: clip the reprojected history instead */
 
 /* Luminance with Rec. 709 weights (the listing's luma() is undefined). */
 static double luma(double r, double g, double b)
@@ -297,6 +299,75 @@ void svo_clamp(int W, int H, const double *hr, const double *hg,
     }
 }
 
+/* Variance colour clipping, the alternative Section 3.1 tested beside the
+ * clamp.  The box is the same (centre mu, half-widths gamma sigma per
+ * channel, from the 3x3 neighbourhood of the current colour), but a history
+ * colour outside it is moved toward mu along the segment from mu, onto the
+ * box's surface, rather than channel by channel: with d = h - mu and
+ * t = min(1, min over channels with |d_c| > gamma sigma_c of
+ * gamma sigma_c / |d_c|), the result is mu + t d.  The hue of the history
+ * is kept.  A channel with zero spread and a nonzero deviation gives t = 0,
+ * i.e. mu.  A history inside the box is kept as it is; gamma <= 0 copies
+ * the history. */
+void svo_clip(int W, int H, const double *hr, const double *hg,
+              const double *hb, const double *cr, const double *cg,
+              const double *cb, const double *z, double gamma, double *or_,
+              double *og, double *ob)
+{
+    const double *h[3] = {hr, hg, hb};
+    const double *c[3] = {cr, cg, cb};
+    double *o[3] = {or_, og, ob};
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < H; ++y) {
+        for (int x = 0; x < W; ++x) {
+            int64_t p = (int64_t)y * W + x;
+            if (!(gamma > 0.0) || (z && empty_px(z[p]))) {
+                for (int ch = 0; ch < 3; ++ch)
+                    o[ch][p] = h[ch][p];
+                continue;
+            }
+            double mu[3], half[3];
+            for (int ch = 0; ch < 3; ++ch) {
+                double sum = 0.0;
+                int cnt = 0;
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        int qx = x + dx, qy = y + dy;
+                        if (qx < 0 || qx >= W || qy < 0 || qy >= H)
+                            continue;
+                        int64_t q = (int64_t)qy * W + qx;
+                        if (z && empty_px(z[q]))
+                            continue;
+                        sum += c[ch][q];
+                        ++cnt;
+                    }
+                mu[ch] = sum / cnt;
+                double ss = 0.0;
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        int qx = x + dx, qy = y + dy;
+                        if (qx < 0 || qx >= W || qy < 0 || qy >= H)
+                            continue;
+                        int64_t q = (int64_t)qy * W + qx;
+                        if (z && empty_px(z[q]))
+                            continue;
+                        double d = c[ch][q] - mu[ch];
+                        ss += d * d;
+                    }
+                half[ch] = gamma * sqrt(ss / cnt);
+            }
+            double t = 1.0;
+            for (int ch = 0; ch < 3; ++ch) {
+                double d = fabs(h[ch][p] - mu[ch]);
+                if (d > half[ch])
+                    t = fmin(t, half[ch] / d);
+            }
+            for (int ch = 0; ch < 3; ++ch)
+                o[ch][p] = t < 1.0 ? mu[ch] + t * (h[ch][p] - mu[ch]) : h[ch][p];
+        }
+    }
+}
+
 /* ---- Section 2: temporal accumulation ---------------------------------- */
 
 /* Exponential moving average of colour and of the first two luminance
@@ -350,7 +421,7 @@ void svo_blend(int64_t npx, const double *cr, const double *cg,
 }
 
 /* The whole temporal filter of Section 3 step 4, in order: (tone map the
- * current colour), reproject the history, (clamp it), blend.  `cur` is the
+ * current colour), reproject the history, (clamp or clip it), blend.  `cur` is the
  * raw current colour; scratch is allocated here. */
 int svo_temporal(int W, int H, const double *cr, const double *cg,
                  const double *cb, const double *z, const double *nx,
@@ -388,7 +459,9 @@ int svo_temporal(int W, int H, const double *cr, const double *cg,
     svo_reproject(W, H, z, nx, ny, nz, id, mvx, mvy, pz, pnx, pny, pnz, pid,
                   hr, hg, hb, hm1, hm2, hn, tau_z, tau_n,
                   (flags & SVO_T_USE_ID) != 0, rr, rg, rb, r1, r2, rn, rv);
-    if ((flags & SVO_T_CLAMP) && gamma > 0.0) {
+    if ((flags & SVO_T_CLIP) && gamma > 0.0) {
+        svo_clip(W, H, rr, rg, rb, tr, tg, tb, z, gamma, kr, kg, kb);
+    } else if ((flags & SVO_T_CLAMP) && gamma > 0.0) {
         svo_clamp(W, H, rr, rg, rb, tr, tg, tb, z, gamma, kr, kg, kb);
     } else {
         memcpy(kr, rr, sizeof(double) * n);

@@ -271,6 +271,114 @@ def test_clamp_idempotent_identity_and_constant():
     np.testing.assert_allclose(O.clamp(mu, cur, 1.0), mu, rtol=1e-15)
 
 
+# ---- variance colour clipping (Section 3.1) ------------------------------------
+
+def _box(cur, x, y, gamma):
+    st = [_box_stats(cur[ch], x, y) for ch in range(3)]
+    return np.array([m for m, _ in st]), gamma * np.array([sd for _, sd in st])
+
+
+def test_clip_is_the_last_point_of_the_segment_inside_the_box():
+    # Brute force: bisection over t in [0, 1] for the largest t with
+    # mu + t (h - mu) inside the box, against the oracle's closed form.
+    H, W = 6, 7
+    r = rng(40)
+    cur = r.uniform(0, 1, (3, H, W))
+    hist = r.uniform(-1, 2, (3, H, W))
+    for gamma in (0.5, 1.0, 2.0):
+        out = O.clip(hist, cur, gamma)
+        for y in range(H):
+            for x in range(W):
+                mu, half = _box(cur, x, y, gamma)
+                d = hist[:, y, x] - mu
+                inside = lambda t: np.all(np.abs(t * d) <= half * (1 + 1e-15))
+                lo, hi = 0.0, 1.0
+                if inside(1.0):
+                    lo = 1.0
+                else:
+                    for _ in range(80):
+                        m = 0.5 * (lo + hi)
+                        lo, hi = (m, hi) if inside(m) else (lo, m)
+                np.testing.assert_allclose(out[:, y, x], mu + lo * d, rtol=1e-12, atol=1e-14)
+
+
+def test_clip_keeps_the_hue_and_lands_on_the_box():
+    H, W = 8, 9
+    r = rng(41)
+    cur = r.uniform(0, 1, (3, H, W))
+    hist = r.uniform(-2, 3, (3, H, W))
+    out = O.clip(hist, cur, 1.0)
+    for y in range(H):
+        for x in range(W):
+            mu, half = _box(cur, x, y, 1.0)
+            d, o = hist[:, y, x] - mu, out[:, y, x] - mu
+            # o is a non-negative multiple of d (same direction from the centre)
+            t = np.dot(o, d) / np.dot(d, d)
+            assert 0.0 <= t <= 1.0
+            np.testing.assert_allclose(o, t * d, atol=1e-14)
+            # and sits on the box's surface when h was outside it
+            if np.any(np.abs(d) > half):
+                assert np.max(np.abs(o) / half) == pytest.approx(1.0, rel=1e-12)
+    np.testing.assert_allclose(O.clip(out, cur, 1.0), out, rtol=1e-13, atol=1e-15)
+
+
+def test_clip_special_cases():
+    H, W = 7, 6
+    r = rng(42)
+    cur = r.uniform(0, 1, (3, H, W))
+    hist = r.uniform(-1, 2, (3, H, W))
+    # gamma 0 and a huge box copy the history
+    np.testing.assert_array_equal(O.clip(hist, cur, 0.0), hist)
+    np.testing.assert_array_equal(O.clip(hist, cur, 1e12), hist)
+    # a constant current frame (zero spread) sends any other history to it
+    const = np.full((3, H, W), 0.375)
+    np.testing.assert_array_equal(O.clip(hist, const, 1.0), const)
+    # grey current and history: the box is a cube on the grey axis and the
+    # segment runs along it, so clipping equals the per-channel clamp
+    grey = np.broadcast_to(cur[:1], (3, H, W)).copy()
+    hgrey = np.broadcast_to(hist[:1], (3, H, W)).copy()
+    np.testing.assert_allclose(O.clip(hgrey, grey, 1.0), O.clamp(hgrey, grey, 1.0), rtol=1e-14)
+    # a history off the centre in one channel only: clip == clamp
+    mu = np.stack([corr(cur[c], np.ones((3, 3))) / corr(np.ones((H, W)), np.ones((3, 3)))
+                   for c in range(3)])
+    one = mu.copy()
+    one[1] = hist[1]
+    np.testing.assert_allclose(O.clip(one, cur, 1.0), O.clamp(one, cur, 1.0), rtol=1e-13)
+    # empty centre pixels pass through; empty neighbours leave the box
+    z = np.ones((H, W))
+    z[3, 2] = 0.0
+    z[0, 0] = -1.0
+    out = O.clip(hist, cur, 1.0, z=z)
+    np.testing.assert_array_equal(out[:, 3, 2], hist[:, 3, 2])
+    win = [(yy, xx) for yy in range(2, 5) for xx in range(0, 3) if (yy, xx) != (3, 2)]
+    m = np.array([np.mean([cur[c, yy, xx] for yy, xx in win]) for c in range(3)])
+    hf = np.array([np.std([cur[c, yy, xx] for yy, xx in win]) for c in range(3)])
+    d = hist[:, 3, 1] - m
+    t = min([1.0] + [hf[c] / abs(d[c]) for c in range(3) if abs(d[c]) > hf[c]])
+    np.testing.assert_allclose(out[:, 3, 1], m + t * d, rtol=1e-13)
+
+
+def test_temporal_clip_flag_is_reproject_clip_blend():
+    from paper_2312_06827_amd.scene import CONFIGS, sequence, with_size
+    cfg = with_size(CONFIGS["hd_motion"], 40, 24, 3)
+    frames = list(sequence(cfg))
+    st = O.new_state(24, 40)
+    p = O.OracleParams(clip=True, use_id=True)
+    for fr in frames[:2]:
+        t = O.temporal(fr, st, p)
+        st = {"rgb": t["rgb"], "m1": t["m1"], "m2": t["m2"], "n": t["n"]}
+    fr = frames[2]
+    t = O.temporal(fr, st, p)
+    rp = O.reproject(fr["z"], fr["n"], fr["mv"], fr["prev_z"], fr["prev_n"], st["rgb"],
+                     st["m1"], st["m2"], st["n"], id=fr["id"], prev_id=fr["prev_id"],
+                     use_id=True)
+    h = O.clip(rp["rgb"], fr["rgb"], 1.0, z=fr["z"])
+    b = O.blend(fr["rgb"], fr["z"], h, rp["m1"], rp["m2"], rp["n"], rp["valid"])
+    np.testing.assert_array_equal(t["rgb"], b["rgb"])
+    tc = O.temporal(fr, st, O.OracleParams(clamp=True, use_id=True))
+    assert np.abs(tc["rgb"] - t["rgb"]).max() > 0  # the two rectifications differ here
+
+
 # ---- temporal accumulation (Section 2) ----------------------------------------
 
 def test_blend_closed_forms():
