@@ -117,11 +117,26 @@ int sv_clamp(const sv_rgb *hist, const sv_rgb *cur, const sv_rgb *out,
              const void *z, sv_dims d, sv_dtype t, float gamma,
              sv_stream stream);
 
+/* History rectification by variance colour clipping, the alternative that
+ * Section 3.1 tested beside the clamp.  Same box as sv_clamp (centre mu,
+ * half-widths gamma sigma per channel); a history colour h outside it is
+ * moved toward mu along the segment from mu onto the box's surface:
+ * mu + t (h - mu) with t the smallest gamma sigma_c / |h_c - mu_c| over the
+ * channels outside the box (a channel with zero spread and a nonzero
+ * deviation gives mu).  A colour inside the box, an empty centre pixel and
+ * gamma <= 0 copy.  Box statistics and the segment are evaluated in
+ * binary64.  Arguments, aliasing rules and errors as sv_clamp. */
+int sv_clip(const sv_rgb *hist, const sv_rgb *cur, const sv_rgb *out,
+            const void *z, sv_dims d, sv_dtype t, float gamma,
+            sv_stream stream);
+
 /* ---- temporal filter (Section 2; Section 3 step 4; Section 3.1) -------- */
 enum {
     SV_T_CLAMP = 1,     /* clamp the reprojected history (gamma > 0) */
     SV_T_USE_ID = 2,    /* object ids of the taps must match */
-    SV_T_TONEMAP_IN = 4 /* forward tone map (LUMA, tm_k) the current colour */
+    SV_T_TONEMAP_IN = 4, /* forward tone map (LUMA, tm_k) the current colour */
+    SV_T_CLIP = 8        /* clip the reprojected history (gamma > 0) as sv_clip
+                            does; not together with SV_T_CLAMP */
 };
 
 typedef struct {
@@ -183,7 +198,8 @@ typedef struct {
  * taps' bilinear weights are renormalised and the history length is the
  * largest among usable taps of positive weight; no usable tap (or |mv| not
  * finite or >= 2^20) discards the history; (3) with SV_T_CLAMP the
- * reprojected colour is clamped to the 3x3 mean +- gamma sigma of c;
+ * reprojected colour is clamped to the 3x3 mean +- gamma sigma of c, with
+ * SV_T_CLIP clipped into that box as sv_clip does (both: SV_EINVAL);
  * (4) with n = min(n_hist + 1, max_hist), a = max(alpha, 1/n),
  * am = max(alpha_m, 1/n): out = (1-a) hist + a c, m1 = (1-am) m1_hist +
  * am L(c), m2c = (1-am) (m2c_hist + am (L(c) - m1_hist)^2), which is the

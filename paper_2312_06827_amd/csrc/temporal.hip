@@ -57,15 +57,19 @@ __device__ __forceinline__ bool normal_consistent(float ax, float ay, float az, 
     return d >= tau;
 }
 
-// 3x3 box of the tile around (lx+1, ly+1): clamp bounds mu -+ gamma sigma
-// per channel from the mean and population variance over valid entries
-// (w component 1, else 0; their colour is masked out here).  Binary64: the
-// bounds are differences of quantities of the colour's size and may be
-// close to zero.  One pass of sums of x and x^2 suffices there: products of
-// binary32 values are exact in binary64, and the cancellation in
-// E[x^2] - E[x]^2 costs at most log2(mu^2 / sigma^2) of its 53 bits.
-__device__ __forceinline__ void box_bounds(const float4 *tile, int lx, int ly, float gamma,
-                                           float3 &lo, float3 &hi) {
+// History rectification: none, the per-channel variance colour clamp, or
+// variance colour clipping toward the box centre.
+enum { kRectOff = 0, kRectClamp = 1, kRectClip = 2 };
+
+// 3x3 box of the tile around (lx+1, ly+1): centre mu and half-widths
+// gamma sigma per channel from the mean and population variance over valid
+// entries (w component 1, else 0; their colour is masked out here).
+// Binary64: the bounds are differences of quantities of the colour's size
+// and may be close to zero.  One pass of sums of x and x^2 suffices there:
+// products of binary32 values are exact in binary64, and the cancellation
+// in E[x^2] - E[x]^2 costs at most log2(mu^2 / sigma^2) of its 53 bits.
+__device__ __forceinline__ void box_stats(const float4 *tile, int lx, int ly, float gamma,
+                                          double3 &mu, double3 &half) {
     double s1r = 0.0, s1g = 0.0, s1b = 0.0, s2r = 0.0, s2g = 0.0, s2b = 0.0;
     float cnt = 0.f;
 #pragma unroll
@@ -87,9 +91,39 @@ __device__ __forceinline__ void box_bounds(const float4 *tile, int lx, int ly, f
     const double vr = fmax(0.0, fma(-mr, mr, s2r * inv));
     const double vg = fmax(0.0, fma(-mg, mg, s2g * inv));
     const double vb = fmax(0.0, fma(-mb, mb, s2b * inv));
-    const double gr = gamma * sqrt(vr), gg = gamma * sqrt(vg), gb = gamma * sqrt(vb);
-    lo = make_float3((float)(mr - gr), (float)(mg - gg), (float)(mb - gb));
-    hi = make_float3((float)(mr + gr), (float)(mg + gg), (float)(mb + gb));
+    mu = make_double3(mr, mg, mb);
+    half = make_double3(gamma * sqrt(vr), gamma * sqrt(vg), gamma * sqrt(vb));
+}
+
+// Rectifies the history colour (r, g, b) against the box of (lx+1, ly+1).
+// Clamp: each channel to [mu - gamma sigma, mu + gamma sigma].  Clip: a
+// colour outside the box moves toward mu along the segment from mu onto the
+// box's surface, mu + t (h - mu) with t the smallest ratio half / |h - mu|
+// over the channels outside (so a channel with zero spread and a nonzero
+// deviation gives mu); a colour inside is kept as it is.
+template <int RECT>
+__device__ __forceinline__ void rectify(const float4 *tile, int lx, int ly, float gamma, float &r,
+                                        float &g, float &b) {
+    if (RECT == kRectOff) return;
+    double3 mu, e;
+    box_stats(tile, lx, ly, gamma, mu, e);
+    if (RECT == kRectClamp) {
+        r = fminf(fmaxf(r, (float)(mu.x - e.x)), (float)(mu.x + e.x));
+        g = fminf(fmaxf(g, (float)(mu.y - e.y)), (float)(mu.y + e.y));
+        b = fminf(fmaxf(b, (float)(mu.z - e.z)), (float)(mu.z + e.z));
+        return;
+    }
+    const double dr = (double)r - mu.x, dg = (double)g - mu.y, db = (double)b - mu.z;
+    const double ar = fabs(dr), ag = fabs(dg), ab = fabs(db);
+    double t = 1.0;
+    if (ar > e.x) t = fmin(t, e.x / ar);
+    if (ag > e.y) t = fmin(t, e.y / ag);
+    if (ab > e.z) t = fmin(t, e.z / ab);
+    if (t < 1.0) {
+        r = (float)fma(t, dr, mu.x);
+        g = (float)fma(t, dg, mu.y);
+        b = (float)fma(t, db, mu.z);
+    }
 }
 
 // Stage the current colour (tone mapped if TM) of the tile and a one-pixel
@@ -232,7 +266,7 @@ __device__ __forceinline__ void px_gather(const TemporalArgs &a, int x, int y, P
 
 // The validity tests, the renormalised history, its central moment and the
 // clamp, from the gathered loads and the staged tile.
-template <bool CLAMP, bool USE_ID>
+template <int RECT, bool USE_ID>
 __device__ __forceinline__ PxState px_reproject(const TemporalArgs &a, const float4 *tile, int lx,
                                                 int ly, int x, int y, const PxLoads &g) {
     PxState s;
@@ -286,14 +320,8 @@ __device__ __forceinline__ PxState px_reproject(const TemporalArgs &a, const flo
         const float d = g.t1[t] - hm1;
         s2 = ok[t] ? fmaf(g.bw[t], fmaf(d, d, g.t2[t]), s2) : s2;
     }
-    // ---- history rectification: variance colour clamp ----
-    if (CLAMP) {
-        float3 lo, hi;
-        box_bounds(tile, lx, ly, a.gamma, lo, hi);
-        hr = fminf(fmaxf(hr, lo.x), hi.x);
-        hg = fminf(fmaxf(hg, lo.y), hi.y);
-        hb = fminf(fmaxf(hb, lo.z), hi.z);
-    }
+    // ---- history rectification: variance colour clamp or clip ----
+    rectify<RECT>(tile, lx, ly, a.gamma, hr, hg, hb);
     s.hr = hr;
     s.hg = hg;
     s.hb = hb;
@@ -427,7 +455,7 @@ __device__ __forceinline__ void px_network(const TemporalArgs &a, uint4 *s_feat,
 // once this thread's pixel is done (the caller's barrier follows).
 enum { kBlend = 0, kFeat = 1, kLearn = 2 };
 
-template <typename T, bool TM, bool CLAMP, bool USE_ID, int MODE>
+template <typename T, bool TM, int RECT, bool USE_ID, int MODE>
 __device__ __forceinline__ void temporal_tile(const TemporalArgs &a, float4 *tile, uint4 *s_feat,
                                               uint32_t *wave_n, uint32_t &base_sh, int bx,
                                               int by) {
@@ -437,7 +465,7 @@ __device__ __forceinline__ void temporal_tile(const TemporalArgs &a, float4 *til
     px_gather<T, USE_ID>(a, x, y, g);
     stage_current<T, TM>(tile, a.cr, a.cg, a.cb, a.z, a.w, a.h, a.pitch, a.tm_k, bx, by);
     __syncthreads();
-    const PxState s = px_reproject<CLAMP, USE_ID>(a, tile, lx, ly, x, y, g);
+    const PxState s = px_reproject<RECT, USE_ID>(a, tile, lx, ly, x, y, g);
     if (MODE == kFeat) {
         if (!s.inimg) return;
         float f[SV_MLP_IN];
@@ -472,7 +500,7 @@ __device__ __forceinline__ void temporal_tile(const TemporalArgs &a, float4 *til
     }
 }
 
-template <typename T, bool TM, bool CLAMP, bool USE_ID, int MODE>
+template <typename T, bool TM, int RECT, bool USE_ID, int MODE>
 __global__ __launch_bounds__(256) void temporal_k(TemporalArgs a) {
     __shared__ float4 tile[(kTX + 2) * (kTY + 2)];
     __shared__ uint4 s_feat[MODE == kLearn ? 2 * 256 : 1];
@@ -481,10 +509,10 @@ __global__ __launch_bounds__(256) void temporal_k(TemporalArgs a) {
     const int t = xcd_tile(gxt * ((a.h + kTY - 1) / kTY));
     if (t < 0) return;
     const int by = t / gxt, bx = t - by * gxt;
-    temporal_tile<T, TM, CLAMP, USE_ID, MODE>(a, tile, s_feat, wave_n, base_sh, bx, by);
+    temporal_tile<T, TM, RECT, USE_ID, MODE>(a, tile, s_feat, wave_n, base_sh, bx, by);
 }
 
-template <typename T, bool TM, bool CLAMP, bool USE_ID, int MODE>
+template <typename T, bool TM, int RECT, bool USE_ID, int MODE>
 __global__ __launch_bounds__(256) void temporal_batch_k(const TemporalArgs *args, const int *prefix,
                                                         int n, int total) {
     __shared__ float4 tile[(kTX + 2) * (kTY + 2)];
@@ -497,16 +525,16 @@ __global__ __launch_bounds__(256) void temporal_batch_k(const TemporalArgs *args
         const int s = batch_stream(prefix, n, t);
         const TemporalArgs a = args[s];
         const int lt = t - prefix[s], gxt = (a.w + kTX - 1) / kTX;
-        temporal_tile<T, TM, CLAMP, USE_ID, MODE>(a, tile, s_feat, wave_n, base_sh, lt % gxt,
+        temporal_tile<T, TM, RECT, USE_ID, MODE>(a, tile, s_feat, wave_n, base_sh, lt % gxt,
                                                   lt / gxt);
         __syncthreads();  // the next tile's staging reuses the LDS
     }
 }
 
-template <typename T, bool TM, bool CLAMP, bool USE_ID, int MODE>
+template <typename T, bool TM, int RECT, bool USE_ID, int MODE>
 static void temporal_batch_launch(const void *args, const int *prefix, int n, int total, int bpc,
                                   hipStream_t s) {
-    hipLaunchKernelGGL((temporal_batch_k<T, TM, CLAMP, USE_ID, MODE>),
+    hipLaunchKernelGGL((temporal_batch_k<T, TM, RECT, USE_ID, MODE>),
                        dim3(batch_grid(total, bpc)), dim3(256), 0, s, (const TemporalArgs *)args,
                        prefix, n, total);
 }
@@ -518,7 +546,7 @@ struct ClampArgs {
     float gamma;
 };
 
-template <typename T>
+template <typename T, int RECT>
 __global__ __launch_bounds__(256) void clamp_k(ClampArgs a) {
     __shared__ float4 tile[(kTX + 2) * (kTY + 2)];
     const int gxt = (a.w + kTX - 1) / kTX;
@@ -533,41 +561,46 @@ __global__ __launch_bounds__(256) void clamp_k(ClampArgs a) {
     const uint32_t o = (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x;
     float r = ldo<T>(a.hr, o), g = ldo<T>(a.hg, o), b = ldo<T>(a.hb, o);
     const bool active = a.gamma > 0.f && tile[(ly + 1) * (kTX + 2) + lx + 1].w > 0.f;
-    if (active) {
-        float3 lo, hi;
-        box_bounds(tile, lx, ly, a.gamma, lo, hi);
-        r = fminf(fmaxf(r, lo.x), hi.x);
-        g = fminf(fmaxf(g, lo.y), hi.y);
-        b = fminf(fmaxf(b, lo.z), hi.z);
-    }
+    if (active) rectify<RECT>(tile, lx, ly, a.gamma, r, g, b);
     sto<T>(a.or_, o, r);
     sto<T>(a.og, o, g);
     sto<T>(a.ob, o, b);
 }
 
-template <typename T, bool TM, bool CLAMP, bool USE_ID, int MODE>
+template <typename T, bool TM, int RECT, bool USE_ID, int MODE>
 static void launch_temporal_one(const TemporalArgs &a, dim3 grid, hipStream_t s) {
     const int tiles = ((a.w + kTX - 1) / kTX) * ((a.h + kTY - 1) / kTY);
-    if (record_pass(&temporal_batch_launch<T, TM, CLAMP, USE_ID, MODE>, a, tiles, 8)) return;
-    hipLaunchKernelGGL((temporal_k<T, TM, CLAMP, USE_ID, MODE>), grid, dim3(256), 0, s, a);
+    if (record_pass(&temporal_batch_launch<T, TM, RECT, USE_ID, MODE>, a, tiles, 8)) return;
+    hipLaunchKernelGGL((temporal_k<T, TM, RECT, USE_ID, MODE>), grid, dim3(256), 0, s, a);
 }
 
-template <typename T, bool TM, bool CLAMP, int MODE>
+template <typename T, bool TM, int RECT, int MODE>
 static void launch_temporal_id(const TemporalArgs &a, bool use_id, dim3 grid, hipStream_t s) {
-    if (use_id) launch_temporal_one<T, TM, CLAMP, true, MODE>(a, grid, s);
-    else launch_temporal_one<T, TM, CLAMP, false, MODE>(a, grid, s);
+    if (use_id) launch_temporal_one<T, TM, RECT, true, MODE>(a, grid, s);
+    else launch_temporal_one<T, TM, RECT, false, MODE>(a, grid, s);
+}
+
+template <typename T, bool TM, int MODE>
+static void launch_temporal_rect(const TemporalArgs &a, int rect, bool use_id, dim3 grid,
+                                 hipStream_t s) {
+    if (rect == kRectClip) launch_temporal_id<T, TM, kRectClip, MODE>(a, use_id, grid, s);
+    else if (rect == kRectClamp) launch_temporal_id<T, TM, kRectClamp, MODE>(a, use_id, grid, s);
+    else launch_temporal_id<T, TM, kRectOff, MODE>(a, use_id, grid, s);
 }
 
 template <typename T, int MODE>
-static void launch_temporal(const TemporalArgs &a, bool tm, bool clamp, bool use_id, dim3 grid,
+static void launch_temporal(const TemporalArgs &a, bool tm, int rect, bool use_id, dim3 grid,
                             hipStream_t s) {
-    if (tm) {
-        if (clamp) launch_temporal_id<T, true, true, MODE>(a, use_id, grid, s);
-        else launch_temporal_id<T, true, false, MODE>(a, use_id, grid, s);
-    } else {
-        if (clamp) launch_temporal_id<T, false, true, MODE>(a, use_id, grid, s);
-        else launch_temporal_id<T, false, false, MODE>(a, use_id, grid, s);
-    }
+    if (tm) launch_temporal_rect<T, true, MODE>(a, rect, use_id, grid, s);
+    else launch_temporal_rect<T, false, MODE>(a, rect, use_id, grid, s);
+}
+
+// Rectification mode of the temporal flags; -1 when both are set.
+static int rect_mode(const sv_temporal_params *p) {
+    const bool clamp = (p->flags & SV_T_CLAMP) != 0, clip = (p->flags & SV_T_CLIP) != 0;
+    if (clamp && clip) return -1;
+    if (!(p->gamma > 0.f)) return kRectOff;
+    return clip ? kRectClip : clamp ? kRectClamp : kRectOff;
 }
 
 }  // namespace sv
@@ -581,7 +614,8 @@ extern "C" int sv_temporal(const sv_temporal_io *io, sv_dims d, sv_dtype t,
     if (p->max_hist < 1 || p->max_hist > 255) return SV_EINVAL;
     if (dc == 1) return SV_OK;
     const bool use_id = (p->flags & SV_T_USE_ID) != 0;
-    const bool clamp = (p->flags & SV_T_CLAMP) != 0 && p->gamma > 0.f;
+    const int rect = rect_mode(p);
+    if (rect < 0) return SV_EINVAL;
     const bool tm = (p->flags & SV_T_TONEMAP_IN) != 0;
     const void *req[] = {io->cur.r, io->cur.g, io->cur.b, io->g.z, io->g.nx, io->g.ny, io->g.nz,
                          io->mvx, io->mvy, io->prev.z, io->prev.nx, io->prev.ny, io->prev.nz,
@@ -675,11 +709,11 @@ extern "C" int sv_temporal(const sv_temporal_io *io, sv_dims d, sv_dtype t,
         a.mwq = io->mlp->wq;
         a.kappa_out = io->kappa_out;
         a.alpha_out = io->alpha_out;
-        if (t == SV_F32) launch_temporal<float, kLearn>(a, tm, clamp, use_id, grid, s);
-        else launch_temporal<half_t, kLearn>(a, tm, clamp, use_id, grid, s);
+        if (t == SV_F32) launch_temporal<float, kLearn>(a, tm, rect, use_id, grid, s);
+        else launch_temporal<half_t, kLearn>(a, tm, rect, use_id, grid, s);
     } else {
-        if (t == SV_F32) launch_temporal<float, kBlend>(a, tm, clamp, use_id, grid, s);
-        else launch_temporal<half_t, kBlend>(a, tm, clamp, use_id, grid, s);
+        if (t == SV_F32) launch_temporal<float, kBlend>(a, tm, rect, use_id, grid, s);
+        else launch_temporal<half_t, kBlend>(a, tm, rect, use_id, grid, s);
     }
     return hip_status(hipGetLastError());
 }
@@ -694,7 +728,8 @@ extern "C" int sv_mlp_features(const sv_temporal_io *io, const sv_rgb *albedo, c
     if (p->max_hist < 1 || p->max_hist > 255) return SV_EINVAL;
     if (dc == 1) return SV_OK;
     const bool use_id = (p->flags & SV_T_USE_ID) != 0;
-    const bool clamp = (p->flags & SV_T_CLAMP) != 0 && p->gamma > 0.f;
+    const int rect = rect_mode(p);
+    if (rect < 0) return SV_EINVAL;
     const bool tm = (p->flags & SV_T_TONEMAP_IN) != 0;
     const void *req[] = {io->cur.r, io->cur.g, io->cur.b, io->g.z, io->g.dzdx, io->g.dzdy,
                          io->g.nx, io->g.ny, io->g.nz, io->mvx, io->mvy, io->prev.z,
@@ -746,13 +781,13 @@ extern "C" int sv_mlp_features(const sv_temporal_io *io, const sv_rgb *albedo, c
                    hist_out ? (float *)hist_out->b : nullptr, w->mu, w->inv_s};
     dim3 grid(xcd_grid(((d.w + kTX - 1) / kTX) * ((d.h + kTY - 1) / kTY)));
     hipStream_t s = as_stream(stream);
-    if (t == SV_F32) launch_temporal<float, kFeat>(a, tm, clamp, use_id, grid, s);
-    else launch_temporal<half_t, kFeat>(a, tm, clamp, use_id, grid, s);
+    if (t == SV_F32) launch_temporal<float, kFeat>(a, tm, rect, use_id, grid, s);
+    else launch_temporal<half_t, kFeat>(a, tm, rect, use_id, grid, s);
     return hip_status(hipGetLastError());
 }
 
-extern "C" int sv_clamp(const sv_rgb *hist, const sv_rgb *cur, const sv_rgb *out, const void *z,
-                        sv_dims d, sv_dtype t, float gamma, sv_stream stream) {
+static int clamp_or_clip(const sv_rgb *hist, const sv_rgb *cur, const sv_rgb *out, const void *z,
+                         sv_dims d, sv_dtype t, float gamma, bool clip, sv_stream stream) {
     using namespace sv;
     if (!valid_dtype(t)) return SV_EDTYPE;
     int dc = check_dims(d);
@@ -772,9 +807,23 @@ extern "C" int sv_clamp(const sv_rgb *hist, const sv_rgb *cur, const sv_rgb *out
     ClampArgs a{hist->r, hist->g, hist->b, cur->r, cur->g, cur->b, z,
                 out->r, out->g, out->b, d.w, d.h, d.pitch, gamma};
     dim3 grid(xcd_grid(((d.w + kTX - 1) / kTX) * ((d.h + kTY - 1) / kTY)));
-    if (t == SV_F32)
-        hipLaunchKernelGGL(clamp_k<float>, grid, dim3(256), 0, as_stream(stream), a);
-    else
-        hipLaunchKernelGGL(clamp_k<half_t>, grid, dim3(256), 0, as_stream(stream), a);
+    hipStream_t s = as_stream(stream);
+    if (t == SV_F32) {
+        if (clip) hipLaunchKernelGGL((clamp_k<float, kRectClip>), grid, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((clamp_k<float, kRectClamp>), grid, dim3(256), 0, s, a);
+    } else {
+        if (clip) hipLaunchKernelGGL((clamp_k<half_t, kRectClip>), grid, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((clamp_k<half_t, kRectClamp>), grid, dim3(256), 0, s, a);
+    }
     return hip_status(hipGetLastError());
+}
+
+extern "C" int sv_clamp(const sv_rgb *hist, const sv_rgb *cur, const sv_rgb *out, const void *z,
+                        sv_dims d, sv_dtype t, float gamma, sv_stream stream) {
+    return clamp_or_clip(hist, cur, out, z, d, t, gamma, false, stream);
+}
+
+extern "C" int sv_clip(const sv_rgb *hist, const sv_rgb *cur, const sv_rgb *out, const void *z,
+                       sv_dims d, sv_dtype t, float gamma, sv_stream stream) {
+    return clamp_or_clip(hist, cur, out, z, d, t, gamma, true, stream);
 }

@@ -26,7 +26,7 @@ LIB_PATH = os.path.join(_PKG, "libsv.so")
 SV_OK, SV_EINVAL, SV_EALIAS, SV_EDTYPE, SV_EHIP, SV_EUNSUPPORTED = range(6)
 SV_F32, SV_F16 = 0, 1
 SV_TM_LUMA, SV_TM_CHANNEL, SV_TM_PAPER = 0, 1, 2
-SV_T_CLAMP, SV_T_USE_ID, SV_T_TONEMAP_IN = 1, 2, 4
+SV_T_CLAMP, SV_T_USE_ID, SV_T_TONEMAP_IN, SV_T_CLIP = 1, 2, 4, 8
 SV_A_UNIT_WEIGHTS, SV_A_INV_TONEMAP = 1, 2
 SV_V_LISTED = 1
 
@@ -117,6 +117,8 @@ EXPORTS = {
     "sv_tonemap": ([_P(sv_rgb), _P(sv_rgb), sv_dims, ctypes.c_int, ctypes.c_int,
                     _P(sv_tm_params), _vp], ctypes.c_int),
     "sv_clamp": ([_P(sv_rgb), _P(sv_rgb), _P(sv_rgb), _vp, sv_dims, ctypes.c_int,
+                  ctypes.c_float, _vp], ctypes.c_int),
+    "sv_clip": ([_P(sv_rgb), _P(sv_rgb), _P(sv_rgb), _vp, sv_dims, ctypes.c_int,
                   ctypes.c_float, _vp], ctypes.c_int),
     "sv_temporal": ([_P(sv_temporal_io), sv_dims, ctypes.c_int, _P(sv_temporal_params), _vp],
                     ctypes.c_int),
@@ -266,10 +268,11 @@ class TemporalParams:
     clamp: bool = False
     use_id: bool = False
     tonemap: bool = False
+    clip: bool = False  # clip the history toward the box centre instead of clamping
 
     def c(self) -> sv_temporal_params:
         flags = ((SV_T_CLAMP if self.clamp else 0) | (SV_T_USE_ID if self.use_id else 0)
-                 | (SV_T_TONEMAP_IN if self.tonemap else 0))
+                 | (SV_T_TONEMAP_IN if self.tonemap else 0) | (SV_T_CLIP if self.clip else 0))
         return sv_temporal_params(self.alpha, self.alpha_m, self.gamma, self.tau_z, self.tau_n,
                                   self.tm_k, self.max_hist, flags)
 
@@ -324,6 +327,14 @@ def sv_clamp(hist: Planes, cur: Planes, out: Planes, gamma: float,
              z: Optional[torch.Tensor] = None, stream=None):
     r = _planes3(cur)[0]
     _check("sv_clamp", load().sv_clamp(
+        ctypes.byref(_rgb(hist)), ctypes.byref(_rgb(cur)), ctypes.byref(_rgb(out)),
+        _plane_ptr(z), dims_of(r), dtype_of(r), float(gamma), _stream(stream)))
+
+
+def sv_clip(hist: Planes, cur: Planes, out: Planes, gamma: float,
+            z: Optional[torch.Tensor] = None, stream=None):
+    r = _planes3(cur)[0]
+    _check("sv_clip", load().sv_clip(
         ctypes.byref(_rgb(hist)), ctypes.byref(_rgb(cur)), ctypes.byref(_rgb(out)),
         _plane_ptr(z), dims_of(r), dtype_of(r), float(gamma), _stream(stream)))
 

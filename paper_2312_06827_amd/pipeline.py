@@ -47,10 +47,12 @@ class FilterConfig:
     min_hist: int = 4
     var_radius: int = 3
     feedback: str = "atrous0"  # colour history: level-0 output or "temporal"
+    clip: bool = False  # clip the history toward the box centre instead of clamping
 
     def temporal(self) -> TemporalParams:
         return TemporalParams(self.alpha, self.alpha_m, self.gamma, self.tau_z, self.tau_n,
-                              self.tm_k, self.max_hist, self.clamp, self.use_id, self.tonemap)
+                              self.tm_k, self.max_hist, self.clamp, self.use_id, self.tonemap,
+                              self.clip)
 
     def variance(self) -> VarianceParams:
         return VarianceParams(self.sigma_z, self.sigma_n, self.eps_z, self.min_hist,

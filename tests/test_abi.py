@@ -81,6 +81,22 @@ def test_tonemap_validation(so):
     assert so.sv_tonemap(r(rgb(A)), r(rgb(A)), big, L.SV_F32, 0, r(TM), None) == L.SV_EINVAL
 
 
+def test_clamp_and_clip_validation(so):
+    r = ctypes.byref
+    B = A + 0x20000000
+    for fn in (so.sv_clamp, so.sv_clip):
+        assert fn(None, r(rgb(A)), r(rgb(B)), None, D, L.SV_F32, 1.0, None) == L.SV_EINVAL
+        assert fn(r(rgb(A)), r(rgb(A)), r(rgb(B)), None, D, 5, 1.0, None) == L.SV_EDTYPE
+        # the output on top of the current colour (the box's source)
+        assert fn(r(rgb(A)), r(rgb(B)), r(rgb(B + 64)), None, D, L.SV_F32, 1.0,
+                  None) == L.SV_EALIAS
+        # or of the depth plane
+        assert fn(r(rgb(A)), r(rgb(B)), r(rgb(A)), A + 4, D, L.SV_F32, 1.0,
+                  None) == L.SV_EALIAS
+        assert fn(r(rgb(A)), r(rgb(B)), r(rgb(A)), None, L.sv_dims(0, 4, 4), L.SV_F32, 1.0,
+                  None) == L.SV_OK
+
+
 def test_atrous_validation_and_aliasing(so):
     r = ctypes.byref
     B = A + 0x20000000
@@ -125,6 +141,9 @@ def test_temporal_and_variance_validation(so):
     io = L.sv_temporal_io(rgb(base[0]), gbuf(base[3]), base[9], base[10], gbuf(base[11]),
                           rgb(base[17]), base[20], base[21], base[22], rgb(base[23]),
                           base[26], base[27], base[28], None)
+    # clamp and clip together
+    both = L.sv_temporal_params(0.2, 0.2, 1.0, 0.1, 0.9, 1.0, 255, L.SV_T_CLAMP | L.SV_T_CLIP)
+    assert so.sv_temporal(r(io), D, L.SV_F32, r(both), None) == L.SV_EINVAL
     # output moments on top of the history moments
     io.out_m1 = base[20]
     assert so.sv_temporal(r(io), D, L.SV_F32, r(p), None) == L.SV_EALIAS

@@ -101,6 +101,31 @@ def test_clamp(H, W, gamma):
     assert rel_err(host(out), ref) <= TOL32
 
 
+@pytest.mark.parametrize("H,W", SIZES)
+@pytest.mark.parametrize("gamma", [0.0, 1.0, 2.5])
+def test_clip(H, W, gamma):
+    r = np.random.default_rng(300 + H + int(gamma * 10))
+    cur = r.uniform(0, 1, (3, H, W)).astype(np.float32)
+    hist = r.uniform(-0.5, 1.5, (3, H, W)).astype(np.float32)
+    # flat patches (zero spread in every channel) send the history to mu;
+    # a patch flat in one channel only collapses t to 0 wherever that
+    # channel deviates
+    if H >= 8 and W >= 8:
+        cur[:, 1:6, 1:6] = 0.25
+        cur[1, 1:6, -6:-1] = 0.5
+    z = r.uniform(1, 2, (H, W)).astype(np.float32)
+    z[r.random((H, W)) < 0.1] = 0.0  # empty pixels
+    say(f"clip {H}x{W} gamma={gamma}")
+    out = empty_like_dev((3, H, W), pitch=W + 1)
+    L.sv_clip(dev(hist, W + 1), dev(cur, W + 1), out, gamma, z=dev(z, W + 1))
+    ref = O.clip(hist, cur, gamma, z=z)
+    assert rel_err(host(out), ref) <= TOL32
+    if gamma > 0 and H >= 8 and W >= 8:
+        inner = host(out)[:, 2:5, 2:5]
+        live = z[2:5, 2:5] > 0
+        np.testing.assert_array_equal(inner[:, live], 0.25)
+
+
 # ---- temporal ---------------------------------------------------------------------
 
 def _temporal_case(H, W, seed):
@@ -147,6 +172,34 @@ def test_temporal(H, W, clamp, tonemap, use_id):
     assert rel_err(host(out), ref["rgb"]) <= TOL32
     assert rel_err(host(om1), ref["m1"]) <= TOL32
     assert rel_err(host(om2), ref["m2c"]) <= TOL32
+
+
+@pytest.mark.parametrize("H,W", [(3, 5), (67, 131)])
+@pytest.mark.parametrize("tonemap,use_id", [(False, False), (True, True)])
+def test_temporal_clip(H, W, tonemap, use_id):
+    fr, st = _temporal_case(H, W, 11 + H)
+    p = O.OracleParams(clip=True, tonemap=tonemap, use_id=use_id, gamma=1.0)
+    ref = O.temporal(fr, st, p)
+    P = W + 3
+    say(f"temporal clip {H}x{W} tm={tonemap} id={use_id}")
+    g = gbuf_dev(fr["z"], fr["dzdx"], fr["dzdy"], fr["n"], P, fr["id"])
+    prev = L.GBuf(dev(fr["prev_z"], P), None, None, dev(fr["prev_n"], P),
+                  dev(fr["prev_id"], P, torch.uint8))
+    out = empty_like_dev((3, H, W), P)
+    om1, om2 = empty_like_dev((H, W), P), empty_like_dev((H, W), P)
+    on = empty_like_dev((H, W), P, torch.uint8)
+    tp = L.TemporalParams(clip=True, tonemap=tonemap, use_id=use_id, gamma=1.0)
+    L.sv_temporal(dev(fr["rgb"], P), g, dev(fr["mv"], P), prev, dev(st["rgb"], P),
+                  dev(st["m1"], P), dev(st["m2c"], P), dev(st["n"], P, torch.uint8),
+                  out, om1, om2, on, tp)
+    np.testing.assert_array_equal(host(on), ref["n"])
+    assert rel_err(host(out), ref["rgb"]) <= TOL32
+    assert rel_err(host(om1), ref["m1"]) <= TOL32
+    # clamp and clip together are refused
+    with pytest.raises(RuntimeError):
+        L.sv_temporal(dev(fr["rgb"], P), g, dev(fr["mv"], P), prev, dev(st["rgb"], P),
+                      dev(st["m1"], P), dev(st["m2c"], P), dev(st["n"], P, torch.uint8),
+                      out, om1, om2, on, L.TemporalParams(clip=True, clamp=True, gamma=1.0))
 
 
 def test_temporal_alpha_map_and_discarded_motion():

@@ -77,6 +77,14 @@ def test_motion_full_hd_first_frames(sep):
              frames=3)
 
 
+def test_motion_clipping_reduced():
+    from paper_2312_06827_amd.pipeline import FilterConfig
+    cfg = with_size(CONFIGS["hd_motion"], 320, 180, 8)
+    say("sequence 320x180 motion, clipping instead of the clamp, 8 frames")
+    run_pair(cfg, FilterConfig(clip=True, tonemap=True, use_id=True),
+             O.OracleParams(clip=True, tonemap=True, use_id=True))
+
+
 class _NullTimer:
     def __call__(self, name):
         import contextlib
