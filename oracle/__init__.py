@@ -34,7 +34,7 @@ import numpy as np
 __all__ = [
     "OracleParams", "tonemap", "reproject", "clamp", "clip", "blend", "temporal",
     "variance", "atrous", "atrous_sep", "quantize_half", "new_state",
-    "run_frame", "luma",
+    "run_frame", "luma", "blur_control", "atrous_adaptive",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -301,6 +301,68 @@ def atrous_sep(rgb, var, z, dzdx, dzdy, n, step, kappa=None, sigma_z=1.0,
     return out, vo, sh
 
 
+# ---- blur adapted to scene features (Sections 3.2, 3.5) -----------------------
+
+CTL_LEVELS_MASK, CTL_SHIFT = 15, 16
+
+
+def blur_control(roughness=None, shadow_angle=None, rough_shift=0.2, angle_shift=6.0,
+                 rough_none=0.0, rough_one=0.05, it_none=0, it_one=1, it_rest=15,
+                 shift=True, table=True):
+    """Per-pixel control bytes of the adaptive levels.
+
+    Section 3.2: a pixel whose surface roughness exceeds 0.2, or whose
+    shadow angle exceeds 6.0, starts the a-trous cascade one level coarser
+    (its first level is the usual second one) with the same number of
+    levels.  Section 3.5: the number of levels follows the roughness,
+    none at roughness <= 0, one at <= 0.05, otherwise all of them (the
+    paper's 4 is its full count; 15 here means every level).  Bits 0-3 hold
+    the level count, bit 4 the shift.  The thresholds decide integers, so
+    the comparisons are made in binary32, the precision of the device path."""
+    ref = roughness if roughness is not None else shadow_angle
+    f32 = np.float32
+    shape = np.shape(ref)
+    sh = np.zeros(shape, bool)
+    if shift:
+        if roughness is not None:
+            sh |= np.asarray(roughness, f32) > f32(rough_shift)
+        if shadow_angle is not None:
+            sh |= np.asarray(shadow_angle, f32) > f32(angle_shift)
+    lv = np.full(shape, 15, np.int32)
+    if table:
+        r = np.asarray(roughness, f32)
+        lv = np.where(r <= f32(rough_none), it_none,
+                      np.where(r <= f32(rough_one), it_one, it_rest)).astype(np.int32)
+    return (sh.astype(np.uint8) * CTL_SHIFT) | lv.astype(np.uint8)
+
+
+def atrous_adaptive(rgb, var, z, dzdx, dzdy, n, ctl, level, separable=False, kappa=None,
+                    sigma_z=1.0, sigma_n=128.0, sigma_l=4.0, eps_z=1e-10, eps_l=1e-10,
+                    tm_k=1.0, unit_weights=False, inv_tonemap=False, half_out=False,
+                    want_var=True):
+    """Level `level` of the adaptive cascade (Sections 3.2, 3.5): pixel p is
+    the output at p of the whole level filtered at step 2^(level + shift(p))
+    while level < levels(p), else its input (colour and variance) unchanged,
+    inverse tone mapped on the last level like every other output.
+    Returns (rgb, var)."""
+    rgb, var = _f64(rgb), _f64(var)
+    ctl = np.asarray(ctl, np.uint8)
+    fn = atrous_sep if separable else atrous
+    kw = dict(kappa=kappa, sigma_z=sigma_z, sigma_n=sigma_n, sigma_l=sigma_l, eps_z=eps_z,
+              eps_l=eps_l, tm_k=tm_k, unit_weights=unit_weights, inv_tonemap=inv_tonemap,
+              half_out=half_out, want_var=want_var)
+    fine = fn(rgb, var, z, dzdx, dzdy, n, 1 << level, **kw)
+    coarse = fn(rgb, var, z, dzdx, dzdy, n, 2 << level, **kw)
+    keep = level >= (ctl & CTL_LEVELS_MASK).astype(np.int32)
+    shifted = (ctl & CTL_SHIFT) != 0
+    same = tonemap(rgb, inverse=True, k=tm_k) if inv_tonemap else rgb.copy()
+    if half_out:
+        same = quantize_half(same)
+    out = np.where(keep, same, np.where(shifted, coarse[0], fine[0]))
+    vo = np.where(keep, var, np.where(shifted, coarse[1], fine[1])) if want_var else None
+    return out, vo
+
+
 def quantize_half(x):
     """binary16 round-to-nearest-even of every element (as float64)."""
     x = np.array(x, dtype=np.float64, copy=True, order="C")
@@ -316,12 +378,13 @@ def new_state(height: int, width: int):
             "m2": np.zeros((height, width)), "n": np.zeros((height, width), np.int32)}
 
 
-def run_frame(frame, state, p: OracleParams, alpha_map=None, kappa=None):
+def run_frame(frame, state, p: OracleParams, alpha_map=None, kappa=None, ctl=None):
     """Temporal filter, variance, `p.levels` a-trous levels with steps
     1, 2, 4, ..., inverse tone map.  Returns (output rgb, new state,
     intermediates).  The colour history for the next frame is the level-0
     output (or the temporal output if p.feedback == "temporal"); the moment
-    history is the temporal output."""
+    history is the temporal output.  With control bytes `ctl` the levels are
+    the adaptive ones (Sections 3.2, 3.5)."""
     t = temporal(frame, state, p, alpha_map=alpha_map)
     z, dzdx, dzdy, n = frame["z"], frame["dzdx"], frame["dzdy"], frame["n"]
     var = variance(t["m1"], t["m2"], t["n"], z, dzdx, dzdy, n, p.sigma_z,
@@ -333,10 +396,13 @@ def run_frame(frame, state, p: OracleParams, alpha_map=None, kappa=None):
     for i in range(p.levels):
         last = i == p.levels - 1
         fuse_inv = p.tonemap and last and not (i == 0 and p.feedback == "atrous0")
-        res = step_fn(c, v, z, dzdx, dzdy, n, 1 << i, kappa=kappa, sigma_z=p.sigma_z,
-                      sigma_n=p.sigma_n, sigma_l=p.sigma_l, eps_z=p.eps_z,
-                      eps_l=p.eps_l, tm_k=p.tm_k, inv_tonemap=fuse_inv,
-                      half_out=p.half, want_var=not last)
+        kw = dict(kappa=kappa, sigma_z=p.sigma_z, sigma_n=p.sigma_n, sigma_l=p.sigma_l,
+                  eps_z=p.eps_z, eps_l=p.eps_l, tm_k=p.tm_k, inv_tonemap=fuse_inv,
+                  half_out=p.half, want_var=not last)
+        if ctl is not None:
+            res = atrous_adaptive(c, v, z, dzdx, dzdy, n, ctl, i, separable=p.separable, **kw)
+        else:
+            res = step_fn(c, v, z, dzdx, dzdy, n, 1 << i, **kw)
         c, v = res[0], res[1]
         levels.append(c)
         if i == 0 and p.feedback == "atrous0":

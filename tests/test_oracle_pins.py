@@ -808,3 +808,113 @@ def test_chain_constant_image_is_reproduced_under_motion():
         p2 = O.OracleParams(clamp=True, tonemap=True, separable=sep)
         out, _, _ = O.run_frame(fr, st, p2)
         np.testing.assert_allclose(out, fr["rgb"], rtol=1e-12)
+
+
+# ---- blur adapted to scene features (Sections 3.2, 3.5) ---------------------------
+
+def test_blur_control_follows_the_papers_thresholds():
+    with open(os.path.join(GOLDEN, "blur_rule_paper.json")) as f:
+        gold = json.load(f)
+    f32 = np.float32
+    up = lambda v: np.nextafter(f32(v), f32(np.inf))
+    rs, an = gold["rough_shift"], gold["angle_shift"]
+    t0, t1 = gold["table"][0]["rough_max"], gold["table"][1]["rough_max"]
+    rough = np.array([-1.0, t0, up(t0), t1, up(t1), rs, up(rs), 1.0, np.nan], f32)[None, :]
+    full = gold["full_cascade"]
+    ctl = O.blur_control(rough, None, rough_shift=rs, rough_none=t0, rough_one=t1,
+                         it_none=gold["table"][0]["iterations"],
+                         it_one=gold["table"][1]["iterations"], it_rest=full)
+    np.testing.assert_array_equal(ctl[0] & 15, [0, 0, 1, 1, full, full, full, full, full])
+    np.testing.assert_array_equal(ctl[0] >> 4, [0, 0, 0, 0, 0, 0, 1, 1, 0])
+    # the shadow angle alone
+    ang = np.array([0.0, an, up(an), 90.0], f32)[None, :]
+    ctl = O.blur_control(None, ang, angle_shift=an, table=False)
+    np.testing.assert_array_equal(ctl[0], [15, 15, 16 + 15, 16 + 15])
+    # either one shifts
+    ctl = O.blur_control(np.array([[0.5, 0.1, 0.1]], f32), np.array([[0.0, 7.0, 1.0]], f32),
+                         table=False)
+    np.testing.assert_array_equal(ctl[0], [31, 31, 15])
+
+
+def _adaptive_case(H=23, W=29, seed=50):
+    r = rng(seed)
+    c = r.uniform(0.1, 1.5, (3, H, W))
+    var = r.uniform(0.0, 0.3, (H, W))
+    z = 5.0 + 0.1 * r.standard_normal((H, W))
+    dzdx = 0.01 * r.standard_normal((H, W))
+    dzdy = 0.01 * r.standard_normal((H, W))
+    n = r.standard_normal((3, H, W)) * 0.1
+    n[2] += 1.0
+    n /= np.linalg.norm(n, axis=0)
+    return c, var, z, dzdx, dzdy, n
+
+
+@pytest.mark.parametrize("sep", [False, True])
+def test_adaptive_level_special_cases(sep):
+    c, var, z, dzdx, dzdy, n = _adaptive_case()
+    fn = O.atrous_sep if sep else O.atrous
+    H, W = z.shape
+    for level in (0, 1, 2):
+        plain = fn(c, var, z, dzdx, dzdy, n, 1 << level)
+        coarse = fn(c, var, z, dzdx, dzdy, n, 2 << level)
+        every = np.full((H, W), 15, np.uint8)
+        out = O.atrous_adaptive(c, var, z, dzdx, dzdy, n, every, level, separable=sep)
+        np.testing.assert_array_equal(out[0], plain[0])
+        np.testing.assert_array_equal(out[1], plain[1])
+        out = O.atrous_adaptive(c, var, z, dzdx, dzdy, n, every | 16, level, separable=sep)
+        np.testing.assert_array_equal(out[0], coarse[0])
+        np.testing.assert_array_equal(out[1], coarse[1])
+        # a spent budget keeps colour and variance
+        spent = np.full((H, W), level, np.uint8) | 16
+        out = O.atrous_adaptive(c, var, z, dzdx, dzdy, n, spent, level, separable=sep)
+        np.testing.assert_array_equal(out[0], c)
+        np.testing.assert_array_equal(out[1], var)
+        out = O.atrous_adaptive(c, var, z, dzdx, dzdy, n, spent, level, separable=sep,
+                                inv_tonemap=True, want_var=False)
+        np.testing.assert_allclose(out[0], O.tonemap(c, inverse=True), rtol=1e-15)
+    # Section 3.2: a shifted pixel's first iteration is the usual second one
+    lvl1 = fn(c, var, z, dzdx, dzdy, n, 2)
+    first = O.atrous_adaptive(c, var, z, dzdx, dzdy, n, np.full((H, W), 31, np.uint8), 0,
+                              separable=sep)
+    np.testing.assert_array_equal(first[0], lvl1[0])
+
+
+@pytest.mark.parametrize("sep", [False, True])
+def test_adaptive_level_is_local_in_the_control_bytes(sep):
+    # the output at p depends on ctl(p) alone (the level input is fixed)
+    c, var, z, dzdx, dzdy, n = _adaptive_case(seed=51)
+    H, W = z.shape
+    r = rng(52)
+    a = r.integers(0, 32, (H, W)).astype(np.uint8)
+    b = r.integers(0, 32, (H, W)).astype(np.uint8)
+    same = r.random((H, W)) < 0.5
+    b[same] = a[same]
+    oa = O.atrous_adaptive(c, var, z, dzdx, dzdy, n, a, 1, separable=sep)
+    ob = O.atrous_adaptive(c, var, z, dzdx, dzdy, n, b, 1, separable=sep)
+    np.testing.assert_array_equal(oa[0][:, same], ob[0][:, same])
+    np.testing.assert_array_equal(oa[1][same], ob[1][same])
+    # and each class of pixel matches its own whole-image filter
+    fn = O.atrous_sep if sep else O.atrous
+    fine, coarse = fn(c, var, z, dzdx, dzdy, n, 2), fn(c, var, z, dzdx, dzdy, n, 4)
+    kept = (a & 15) <= 1
+    sh = ((a & 16) != 0) & ~kept
+    fi = ~kept & ~sh
+    np.testing.assert_array_equal(oa[0][:, kept], c[:, kept])
+    np.testing.assert_array_equal(oa[0][:, sh], coarse[0][:, sh])
+    np.testing.assert_array_equal(oa[0][:, fi], fine[0][:, fi])
+
+
+def test_adaptive_cascade_with_the_papers_count_equals_every_level():
+    # a count of 4 in a 4-level cascade is the same as no limit
+    from paper_2312_06827_amd.scene import CONFIGS, sequence, with_size
+    cfg = with_size(CONFIGS["hd_motion"], 48, 32, 2)
+    fr = next(iter(sequence(cfg)))
+    p = O.OracleParams(clamp=True, tonemap=True, use_id=True, levels=4)
+    st = O.new_state(32, 48)
+    plain, _, _ = O.run_frame(fr, st, p)
+    four, _, _ = O.run_frame(fr, st, p, ctl=np.full((32, 48), 4, np.uint8))
+    every, _, _ = O.run_frame(fr, st, p, ctl=np.full((32, 48), 15, np.uint8))
+    np.testing.assert_array_equal(four, plain)
+    np.testing.assert_array_equal(every, plain)
+    one, _, ex = O.run_frame(fr, st, p, ctl=np.full((32, 48), 1, np.uint8))
+    np.testing.assert_allclose(one, O.tonemap(ex["levels"][0], inverse=True), rtol=1e-15)
