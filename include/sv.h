@@ -313,6 +313,61 @@ int sv_atrous_sep(const sv_rgb *c_in, const float *var_in, const sv_gbuf *g,
                   sv_dims d, sv_dtype t, const sv_atrous_params *p,
                   sv_stream stream);
 
+/* ---- blur adapted to scene features (Sections 3.2, 3.5) ---------------- */
+
+/* Per-pixel control byte of the adaptive levels: bits 0-3 the number of
+ * levels the pixel takes part in (15: every level), bit 4 set when it
+ * starts one level coarser, so that its level i uses step 2^(i+1) and its
+ * first level equals the usual second one while the count stays the same
+ * (Section 3.2).  Bits 5-7 must be 0. */
+#define SV_CTL_LEVELS_MASK 15
+#define SV_CTL_SHIFT 16
+
+typedef struct {
+    float rough_shift;  /* shift when roughness > this (0.2) */
+    float angle_shift;  /* ... or when the shadow angle > this (6.0) */
+    float rough_none;   /* roughness <= this: it_none levels (0.0) */
+    float rough_one;    /* otherwise roughness <= this: it_one levels (0.05) */
+    int32_t it_none, it_one, it_rest; /* 0, 1 and 15 (every level), 0..15 */
+    int32_t flags;      /* SV_BR_SHIFT | SV_BR_TABLE */
+} sv_blur_rule;
+
+enum {
+    SV_BR_SHIFT = 1, /* the coarser start of Section 3.2 */
+    SV_BR_TABLE = 2  /* the roughness -> iteration count table of Section 3.5 */
+};
+
+/* Control bytes from per-pixel roughness and shadow angle (binary32
+ * planes; either may be NULL when no rule uses it).  With SV_BR_SHIFT the
+ * shift bit is (roughness > rough_shift) or (angle > angle_shift); with
+ * SV_BR_TABLE the level count is it_none, it_one or it_rest by the
+ * comparisons roughness <= rough_none, roughness <= rough_one in that
+ * order, else 15.  Comparisons are binary32, as written (a NaN compares
+ * false).  SV_EINVAL for a count outside 0..15, SV_BR_TABLE without
+ * roughness, SV_BR_SHIFT with neither plane, or `ctl` overlapping them. */
+int sv_blur_control(const float *roughness, const float *shadow_angle,
+                    uint8_t *ctl, sv_dims d, const sv_blur_rule *r,
+                    sv_stream stream);
+
+/* One adaptive a-trous level `level` (0, 1, ...): pixel p with control
+ * byte c is filtered at step 2^(level + shift(c)) exactly as sv_atrous
+ * (separable = 0) or sv_atrous_sep (separable = 1) filters it, when
+ * level < levels(c); otherwise its colour and variance pass through
+ * unchanged (the inverse tone map of SV_A_INV_TONEMAP still applies).  A
+ * shifted separable pixel takes the vertical pass of the horizontal result
+ * at its own step.  Two launches over the image, one per step; each pixel
+ * is written by one.  `scratch`: as sv_atrous_sep, separable only (NULL
+ * selects the fused form, steps up to 16, so levels 0..3; SV_EUNSUPPORTED
+ * above).  `ctl` (one byte per pixel, pitch d.pitch) must not overlap the
+ * outputs.  Other arguments and errors as sv_atrous; level outside 0..12
+ * is SV_EINVAL. */
+int sv_atrous_adaptive(const sv_rgb *c_in, const float *var_in,
+                       const sv_gbuf *g, const float *kappa,
+                       const uint8_t *ctl, const sv_rgb *scratch,
+                       const sv_rgb *c_out, float *var_out, int32_t level,
+                       int32_t separable, sv_dims d, sv_dtype t,
+                       const sv_atrous_params *p, sv_stream stream);
+
 /* ---- learned blend factor and edge scale ------------------------------
  *
  * Not in the paper, which blends with one fixed alpha and filters with one
@@ -452,6 +507,10 @@ typedef struct {
      * g.dzdx, g.dzdy, albedo and the state's kappa plane */
     const sv_mlp *mlp;
     sv_rgb albedo;
+    /* optional control bytes (sv_blur_control): the levels run as
+     * sv_atrous_adaptive; separable levels at step 32 (level 4 shifted)
+     * need the state's scratch planes */
+    const uint8_t *blur_ctl;
 } sv_frame_in;
 
 typedef struct {
@@ -511,14 +570,15 @@ void sv_batch_destroy(sv_batch *b);
 
 /* ---- misc --------------------------------------------------------------- */
 
-/* Static string for a status code (never NULL). */
 /* ABI self-check for bindings: writes sizeof of sv_dims, sv_rgb, sv_gbuf,
  * sv_tm_params, sv_temporal_io, sv_temporal_params, sv_variance_params,
- * sv_atrous_params, sv_denoiser, sv_frame_in, sv_frame_params, sv_mlp and
- * sv_adam_params (in that order, at most n of them) and returns how many
- * there are. */
+ * sv_atrous_params, sv_denoiser, sv_frame_in, sv_frame_params, sv_mlp,
+ * sv_adam_params and sv_blur_rule (in that order, at most n of them) and
+ * returns how many
+ * there are; SV_EINVAL for sizes == NULL or n < 0. */
 int sv_struct_sizes(size_t *sizes, int32_t n);
 
+/* Static string for a status code (never NULL). */
 const char *sv_status_str(int status);
 
 /* ABI version: increases when a signature or a struct changes. */

@@ -74,7 +74,8 @@ static AtrousArgs make_args(const sv_rgb *c_in, const float *var_in, const sv_gb
     return AtrousArgs{c_in->r, c_in->g, c_in->b, var_in, g->z, g->dzdx, g->dzdy, g->nx, g->ny,
                       g->nz, kappa, c_out->r, c_out->g, c_out->b, var_out, d.w, d.h, d.pitch,
                       step, p->sigma_z, p->sigma_l, p->eps_z, p->eps_l, p->tm_k,
-                      make_normal_coef(p->sigma_n), (p->flags & SV_A_INV_TONEMAP) ? 1 : 0};
+                      make_normal_coef(p->sigma_n), (p->flags & SV_A_INV_TONEMAP) ? 1 : 0,
+                      nullptr, 0, 0, c_in->r, c_in->g, c_in->b};
 }
 
 }  // namespace sv
@@ -119,5 +120,71 @@ extern "C" int sv_atrous_sep(const sv_rgb *c_in, const float *var_in, const sv_g
     AtrousArgs v = make_args(scratch, var_in, g, kappa, c_out, var_out, step, d, p);
     run_pass(h, t, kDirH, unit, tile_cfg(p, kDirH), s);
     run_pass(v, t, kDirV, unit, tile_cfg(p, kDirV), s);
+    return hip_status(hipGetLastError());
+}
+
+extern "C" int sv_atrous_adaptive(const sv_rgb *c_in, const float *var_in, const sv_gbuf *g,
+                                  const float *kappa, const uint8_t *ctl, const sv_rgb *scratch,
+                                  const sv_rgb *c_out, float *var_out, int32_t level,
+                                  int32_t separable, sv_dims d, sv_dtype t,
+                                  const sv_atrous_params *p, sv_stream stream) {
+    using namespace sv;
+    if (level < 0 || level > 12 || (separable != 0 && separable != 1)) return SV_EINVAL;
+    if (!separable && scratch) return SV_EINVAL;
+    if (scratch && (!scratch->r || !scratch->g || !scratch->b)) return SV_EINVAL;
+    int empty = 0;
+    int rc = check_atrous(c_in, var_in, g, kappa, scratch, c_out, var_out, 1 << level, d, t, p,
+                          &empty);
+    if (rc != SV_OK || empty) return rc;
+    if (!ctl) return SV_EINVAL;
+    {
+        const span cs = plane_span(ctl, d, 1);
+        const span outs[] = {plane_span(c_out->r, d, elem_size(t)),
+                             plane_span(c_out->g, d, elem_size(t)),
+                             plane_span(c_out->b, d, elem_size(t)),
+                             var_out ? plane_span(var_out, d, 4) : span{0, 0},
+                             scratch ? plane_span(scratch->r, d, elem_size(t)) : span{0, 0},
+                             scratch ? plane_span(scratch->g, d, elem_size(t)) : span{0, 0},
+                             scratch ? plane_span(scratch->b, d, elem_size(t)) : span{0, 0}};
+        for (const span &so : outs)
+            if (overlaps(so, cs)) return SV_EALIAS;
+    }
+    // separable launches at steps above 16 need the two-pass form
+    if (separable && !scratch && level + 1 > 4) return SV_EUNSUPPORTED;
+    const bool unit = (p->flags & SV_A_UNIT_WEIGHTS) != 0;
+    hipStream_t s = as_stream(stream);
+    for (int cls = 0; cls < 2; ++cls) {
+        const int step = 1 << (level + cls);
+        if (!separable) {
+            AtrousArgs a = make_args(c_in, var_in, g, kappa, c_out, var_out, step, d, p);
+            a.ctl = ctl;
+            a.ctl_level = level;
+            a.ctl_class = cls;
+            run_pass(a, t, kDir2D, unit, tile_cfg(p, kDir2D), s);
+        } else if (!scratch) {
+            HvArgs a{make_args(c_in, var_in, g, kappa, c_out, nullptr, step, d, p),
+                     make_args(c_in, var_in, g, kappa, c_out, var_out, step, d, p)};
+            a.h.inv_tm = 0;
+            a.v.ctl = ctl;
+            a.v.ctl_level = level;
+            a.v.ctl_class = cls;
+            const bool ok = t == SV_F32 ? launch_hv_f32(a, unit, s) : launch_hv_f16(a, unit, s);
+            if (!ok) return SV_EUNSUPPORTED;
+        } else {
+            // the horizontal pass covers every pixel at this launch's step;
+            // only the vertical pass's writes are selected
+            AtrousArgs h = make_args(c_in, var_in, g, kappa, scratch, nullptr, step, d, p);
+            h.inv_tm = 0;
+            AtrousArgs v = make_args(scratch, var_in, g, kappa, c_out, var_out, step, d, p);
+            v.sr = c_in->r;
+            v.sg = c_in->g;
+            v.sb = c_in->b;
+            v.ctl = ctl;
+            v.ctl_level = level;
+            v.ctl_class = cls;
+            run_pass(h, t, kDirH, unit, tile_cfg(p, kDirH), s);
+            run_pass(v, t, kDirV, unit, tile_cfg(p, kDirV), s);
+        }
+    }
     return hip_status(hipGetLastError());
 }

@@ -26,6 +26,12 @@ struct AtrousArgs {
     float sigma_z, sigma_l, eps_z, eps_l, tm_k;
     NormalCoef nc;
     int inv_tm;
+    // adaptive levels (optional): per-pixel control bytes, this level's
+    // index and which of its two launches this is; sr/sg/sb is the level's
+    // input colour, which a pixel whose iteration budget is spent keeps
+    const uint8_t *ctl;
+    int ctl_level, ctl_class;
+    const void *sr, *sg, *sb;
 };
 
 // Weight modes: every edge weight 1 (plain B3), or the full edge weights.
@@ -115,6 +121,30 @@ __device__ __forceinline__ void pass_through(const AtrousArgs &a, uint32_t o, co
                                              const void *g, const void *b) {
     write_out<T>(a, o, ldo<T>(r, o), ldo<T>(g, o), ldo<T>(b, o));
     if (a.var_out) stf(a.var_out, o, 0.f);
+}
+
+// ---- adaptive levels ----------------------------------------------------------
+//
+// Control byte of pixel p: bits 0-3 the number of levels p takes part in
+// (15: all), bit 4 set when p starts one level coarser (its level i uses
+// step 2^(i+1)).  A level then runs as two launches over the whole image:
+// class 0 at step 2^i writes the pixels without the shift and the pixels
+// whose budget is spent (passed through), class 1 at step 2^(i+1) the
+// shifted pixels.  Each pixel's output is written by exactly one of them.
+// Returns 0 when the other launch writes o, 1 to filter it here, 2 to pass
+// it through here.
+__device__ __forceinline__ int ctl_select(const AtrousArgs &a, uint32_t o) {
+    const uint32_t c = a.ctl[o];
+    if (a.ctl_level >= (int)(c & 15u)) return a.ctl_class == 0 ? 2 : 0;
+    return (int)((c >> 4) & 1u) == a.ctl_class ? 1 : 0;
+}
+
+// A pixel outside this level: colour and variance unchanged (the inverse
+// tone map still applies on the last level).
+template <typename T>
+__device__ __forceinline__ void copy_through(const AtrousArgs &a, uint32_t o) {
+    write_out<T>(a, o, ldo<T>(a.sr, o), ldo<T>(a.sg, o), ldo<T>(a.sb, o));
+    if (a.var_out) stf(a.var_out, o, ldf(a.var, o));
 }
 
 // ---- a-trous level, LDS tile -------------------------------------------------
@@ -245,6 +275,13 @@ __device__ __forceinline__ void tile_compute(const AtrousArgs &a, TileOrigin t,
         const int y = t.ybase + j * STEP;
         if (y >= a.h) break;
         const uint32_t o = (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x;
+        if (DIR != kDirH && a.ctl) {  // uniform branch
+            const int sel = ctl_select(a, o);
+            if (sel != 1) {
+                if (sel == 2) copy_through<T>(a, o);
+                continue;
+            }
+        }
         const int ci = (j + HY) * COLS + lx + HX;
         const float4 pc = s_cl[ci];
         const float4 pg = s_gn[ci];
@@ -431,6 +468,13 @@ __global__ __launch_bounds__(256) void atrous_direct_k(AtrousArgs a) {
     const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
     if (x >= a.w || y >= a.h) return;
     const uint32_t o = (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x;
+    if (a.ctl) {
+        const int sel = ctl_select(a, o);
+        if (sel != 1) {
+            if (sel == 2) copy_through<T>(a, o);
+            return;
+        }
+    }
     float4 pc, pg;
     float pv;
     load_tap<T>(a, x, y, pc, pg, pv);
@@ -485,6 +529,13 @@ __global__ __launch_bounds__(256) void atrous_sep_k(AtrousArgs a) {
     const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
     if (x >= a.w || y >= a.h) return;
     const uint32_t o = (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x;
+    if (VERTICAL && a.ctl) {
+        const int sel = ctl_select(a, o);
+        if (sel != 1) {
+            if (sel == 2) copy_through<T>(a, o);
+            return;
+        }
+    }
     float4 pc, pg;
     float pv;
     load_tap<T>(a, x, y, pc, pg, pv);
@@ -730,6 +781,13 @@ __device__ __forceinline__ void hv_row(const AtrousArgs &ah, const AtrousArgs &a
     const int yc = ph + (j0 - 4 + r) * STEP;
     if (x >= av.w || yc >= av.h) return;
     const uint32_t o = (uint32_t)yc * (uint32_t)av.pitch + (uint32_t)x;
+    if (av.ctl) {
+        const int sel = ctl_select(av, o);
+        if (sel != 1) {
+            if (sel == 2) copy_through<T>(av, o);
+            return;
+        }
+    }
     if (cen.gn.x == 0.f) {  // empty pixel: pass through
         write_out<T>(av, o, cen.c.x, cen.c.y, cen.c.z);
         if (av.var_out) stf(av.var_out, o, 0.f);

@@ -29,6 +29,8 @@ SV_TM_LUMA, SV_TM_CHANNEL, SV_TM_PAPER = 0, 1, 2
 SV_T_CLAMP, SV_T_USE_ID, SV_T_TONEMAP_IN, SV_T_CLIP = 1, 2, 4, 8
 SV_A_UNIT_WEIGHTS, SV_A_INV_TONEMAP = 1, 2
 SV_V_LISTED = 1
+SV_CTL_LEVELS_MASK, SV_CTL_SHIFT = 15, 16
+SV_BR_SHIFT, SV_BR_TABLE = 1, 2
 
 _vp = ctypes.c_void_p
 
@@ -90,7 +92,14 @@ class sv_denoiser(ctypes.Structure):
 class sv_frame_in(ctypes.Structure):
     _fields_ = [("cur", sv_rgb), ("g", sv_gbuf), ("mvx", _vp), ("mvy", _vp),
                 ("prev", sv_gbuf), ("alpha_map", _vp), ("kappa", _vp), ("mlp", _vp),
-                ("albedo", sv_rgb)]
+                ("albedo", sv_rgb), ("blur_ctl", _vp)]
+
+
+class sv_blur_rule(ctypes.Structure):
+    _fields_ = [("rough_shift", ctypes.c_float), ("angle_shift", ctypes.c_float),
+                ("rough_none", ctypes.c_float), ("rough_one", ctypes.c_float),
+                ("it_none", ctypes.c_int32), ("it_one", ctypes.c_int32),
+                ("it_rest", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
 
 class sv_frame_params(ctypes.Structure):
@@ -130,6 +139,10 @@ EXPORTS = {
     "sv_atrous_sep": ([_P(sv_rgb), _vp, _P(sv_gbuf), _vp, _P(sv_rgb), _P(sv_rgb), _vp,
                        ctypes.c_int32, sv_dims, ctypes.c_int, _P(sv_atrous_params), _vp],
                       ctypes.c_int),
+    "sv_atrous_adaptive": ([_P(sv_rgb), _vp, _P(sv_gbuf), _vp, _vp, _P(sv_rgb), _P(sv_rgb), _vp,
+                            ctypes.c_int32, ctypes.c_int32, sv_dims, ctypes.c_int,
+                            _P(sv_atrous_params), _vp], ctypes.c_int),
+    "sv_blur_control": ([_vp, _vp, _vp, sv_dims, _P(sv_blur_rule), _vp], ctypes.c_int),
     "sv_denoise_frame": ([_P(sv_frame_in), _P(sv_denoiser), sv_dims, ctypes.c_int,
                           _P(sv_frame_params), _vp], ctypes.c_int),
     "sv_mlp_features": ([_P(sv_temporal_io), _P(sv_rgb), _P(sv_mlp), _vp, _P(sv_rgb), sv_dims,
@@ -412,6 +425,49 @@ def sv_atrous_sep(c_in: Planes, var_in: torch.Tensor, g: GBuf, scratch: Optional
         ctypes.byref(_rgb(c_in)), _plane_ptr(var_in), ctypes.byref(gc), _plane_ptr(kappa),
         sc, ctypes.byref(_rgb(c_out)), _plane_ptr(var_out), int(step),
         dims_of(r), dtype_of(r), ctypes.byref(pc), _stream(stream)))
+
+
+def sv_atrous_adaptive(c_in: Planes, var_in: torch.Tensor, g: GBuf, ctl: torch.Tensor,
+                       scratch: Optional[Planes], c_out: Planes,
+                       var_out: Optional[torch.Tensor], level: int, separable: bool,
+                       params: AtrousParams, kappa: Optional[torch.Tensor] = None, stream=None):
+    """Level `level` with per-pixel control bytes `ctl` (uint8 plane)."""
+    r = _planes3(c_in)[0]
+    gc = g.c()
+    pc = params.c()
+    sc = None if scratch is None else ctypes.byref(_rgb(scratch))
+    _check("sv_atrous_adaptive", load().sv_atrous_adaptive(
+        ctypes.byref(_rgb(c_in)), _plane_ptr(var_in), ctypes.byref(gc), _plane_ptr(kappa),
+        _plane_ptr(ctl), sc, ctypes.byref(_rgb(c_out)), _plane_ptr(var_out), int(level),
+        int(bool(separable)), dims_of(r), dtype_of(r), ctypes.byref(pc), _stream(stream)))
+
+
+@dataclass
+class BlurRule:
+    """Thresholds of the adaptive blur: the coarser start above a roughness
+    or shadow angle, and the roughness -> level count table."""
+    rough_shift: float = 0.2
+    angle_shift: float = 6.0
+    rough_none: float = 0.0
+    rough_one: float = 0.05
+    it_none: int = 0
+    it_one: int = 1
+    it_rest: int = 15
+    shift: bool = True
+    table: bool = True
+
+    def c(self) -> sv_blur_rule:
+        flags = (SV_BR_SHIFT if self.shift else 0) | (SV_BR_TABLE if self.table else 0)
+        return sv_blur_rule(self.rough_shift, self.angle_shift, self.rough_none, self.rough_one,
+                            self.it_none, self.it_one, self.it_rest, flags)
+
+
+def sv_blur_control(roughness: Optional[torch.Tensor], shadow_angle: Optional[torch.Tensor],
+                    ctl: torch.Tensor, rule: BlurRule, stream=None):
+    rc = rule.c()
+    _check("sv_blur_control", load().sv_blur_control(
+        _plane_ptr(roughness), _plane_ptr(shadow_angle), _plane_ptr(ctl), dims_of(ctl),
+        ctypes.byref(rc), _stream(stream)))
 
 
 # ---- learned blend factor and edge scale -------------------------------------

@@ -90,6 +90,7 @@ class FrameInputs:
     mv: torch.Tensor           # (2, H, W) backward motion
     prev: GBuf                 # previous frame's z, n, id
     albedo: Optional[torch.Tensor] = None  # (3, H, W), for the learned mode
+    blur_ctl: Optional[torch.Tensor] = None  # (H, W) uint8 control bytes: adaptive levels
 
     def c(self, alpha_map: Optional[torch.Tensor] = None,
           kappa: Optional[torch.Tensor] = None, mlp=None) -> lib.sv_frame_in:
@@ -97,7 +98,8 @@ class FrameInputs:
         learned mode."""
         key = (None if alpha_map is None else alpha_map.data_ptr(),
                None if kappa is None else kappa.data_ptr(),
-               None if mlp is None else ctypes.addressof(mlp))
+               None if mlp is None else ctypes.addressof(mlp),
+               None if self.blur_ctl is None else self.blur_ctl.data_ptr())
         cached = self.__dict__.get("_c")
         if cached is None or cached[0] != key:
             if mlp is not None and self.albedo is None:
@@ -106,7 +108,8 @@ class FrameInputs:
                                   lib._plane_ptr(self.mv[1]), self.prev.c(),
                                   lib._plane_ptr(alpha_map), lib._plane_ptr(kappa),
                                   None if mlp is None else ctypes.addressof(mlp),
-                                  lib._rgb(self.albedo) if mlp is not None else lib.sv_rgb())
+                                  lib._rgb(self.albedo) if mlp is not None else lib.sv_rgb(),
+                                  lib._plane_ptr(self.blur_ctl))
             self.__dict__["_c"] = cached = (key, fin)
         return cached[1]
 
@@ -236,7 +239,14 @@ class Denoiser:
             p = cfg.atrous(inv_tonemap=fuse_inv)
             if self.tiles and i < len(self.tiles):
                 p.persistent, p.blocks_per_cu = self.tiles[i]
-            if cfg.separable:
+            if inp.blur_ctl is not None:
+                with tm(f"atrous_adaptive{i}"):
+                    fused = (2 << i) <= 16
+                    lib.sv_atrous_adaptive(c, v, inp.g, inp.blur_ctl,
+                                           self.scratch if cfg.separable and not fused else None,
+                                           dst, dst_var, i, cfg.separable, p, kappa=kappa,
+                                           stream=stream)
+            elif cfg.separable:
                 with tm(f"atrous_sep{i}"):
                     # the fused single-kernel form where the step has one
                     lib.sv_atrous_sep(c, v, inp.g, None if (1 << i) <= 16 else self.scratch, dst,

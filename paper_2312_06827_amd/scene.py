@@ -101,6 +101,14 @@ class _Scene:
             _, right_k, _ = self._basis(self._yaw(k))
             pos.append(pos[-1] + step * right_k)
         self.cam_pos = pos
+        # surface roughness per object (plane, spheres), from its own stream
+        # so that the draws above stay as they are: one value from each band
+        # the adaptive blur tells apart (mirror, <= 0.05, <= 0.2, above)
+        rr = np.random.Generator(
+            np.random.Philox(np.random.SeedSequence([cfg.seed, cfg.stream, 1 << 20, 2])))
+        bands = [0.0, 0.03, 0.1, 0.35, 0.6]
+        self.roughness = np.concatenate(
+            [[0.3], rr.permutation(bands + [float(rr.choice(bands))])]).astype(np.float32)
 
     def _yaw(self, frame: int) -> float:
         return 0.0 if self.cfg.static else math.radians(self.cfg.yaw_deg_per_frame * frame)
@@ -224,6 +232,7 @@ def _assemble(cfg, scene, frame, gb, gb_prev) -> Frame:
         "prev_z": q(gb_prev["z"]),
         "prev_n": q(gb_prev["n"]),
         "prev_id": np.ascontiguousarray(gb_prev["id"]),
+        "roughness": np.ascontiguousarray(scene.roughness[gb["id"]]),
     }
 
 

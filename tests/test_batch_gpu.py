@@ -49,7 +49,7 @@ def test_batch_equals_single_streams(half, sep, levels, feedback):
                                      ("var", b.var, d.var)]:
                     assert torch.equal(tb, td), (f, i, name)
             say(f"  frame {f}: {len(SIZES)} streams bitwise equal; {batch.passes()} launches per frame")
-        assert batch.passes() == 4 + levels  # temporal, variance x3, one per level (separable fused)
+        assert batch.passes() == 3 + levels  # temporal, variance x2, one per level (separable fused)
     finally:
         batch.close()
 
