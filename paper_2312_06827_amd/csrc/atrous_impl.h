@@ -165,6 +165,17 @@ __device__ __forceinline__ void copy_through(const AtrousArgs &a, uint32_t o) {
 // latency of a tile hides behind the arithmetic of the previous one.
 enum { kDir2D = 0, kDirH = 1, kDirV = 2 };
 
+// Staged prefilter entry of a pixel outside the image or without a surface.
+constexpr float kNoVar = __builtin_nanf("");
+
+// Lattice rows per thread of a tile: two, except at the largest step, where
+// the 2 x 16-column halo on each side would otherwise hold the tile's LDS
+// footprint to two resident workgroups per CU.
+#ifndef SV_PY1_FROM_STEP
+#define SV_PY1_FROM_STEP 16
+#endif
+constexpr int tile_py(int step) { return step >= SV_PY1_FROM_STEP ? 1 : 2; }
+
 template <int STEP, int PY, int DIR, bool WANT_VAR>
 struct TileShape {
     static constexpr int TX = 64, TY = 4 * PY;
@@ -238,7 +249,7 @@ __device__ __forceinline__ void tile_issue(const AtrousArgs &a, TileOrigin t, R 
 
 template <class S, class R>
 __device__ __forceinline__ void tile_store(const R &g, float4 *s_cl, float4 *s_gn, float *s_v,
-                                           float2 *s_pf) {
+                                           float *s_pf) {
 #pragma unroll
     for (int it = 0; it < S::IT; ++it) {
         const int i = threadIdx.x + it * 256;
@@ -254,16 +265,14 @@ __device__ __forceinline__ void tile_store(const R &g, float4 *s_cl, float4 *s_g
 #pragma unroll
     for (int it = 0; it < S::ITP; ++it) {
         const int i = threadIdx.x + it * 256;
-        if (i < S::NP)
-            s_pf[i] = (g.pin[it] && !empty_px(g.pz[it])) ? make_float2(g.pv[it], 1.f)
-                                                        : make_float2(0.f, 0.f);
+        if (i < S::NP) s_pf[i] = (g.pin[it] && !empty_px(g.pz[it])) ? g.pv[it] : kNoVar;
     }
 }
 
 template <typename T, int STEP, int PY, int MODE, bool WANT_VAR, int DIR>
 __device__ __forceinline__ void tile_compute(const AtrousArgs &a, TileOrigin t,
                                              const float4 *s_cl, const float4 *s_gn,
-                                             const float *s_v, const float2 *s_pf) {
+                                             const float *s_v, const float *s_pf) {
     using S = TileShape<STEP, PY, DIR, WANT_VAR>;
     constexpr int COLS = S::COLS, HY = S::HY, HX = S::HX, PFC = S::PFC;
     const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
@@ -314,9 +323,10 @@ __device__ __forceinline__ void tile_compute(const AtrousArgs &a, TileOrigin t,
                 for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
                     for (int dx = 0; dx < 3; ++dx) {
-                        const float2 e = s_pf[(j * 3 + dy) * PFC + lx + dx];
-                        const float kk = e.y * (kG3[dx] * kG3[dy]);
-                        s = fmaf(kk, e.x, s);
+                        const float e = s_pf[(j * 3 + dy) * PFC + lx + dx];
+                        const bool ok = e == e;  // kNoVar: outside or empty
+                        const float kk = ok ? kG3[dx] * kG3[dy] : 0.f;
+                        s = fmaf(kk, ok ? e : 0.f, s);
                         sw += kk;
                     }
             }
@@ -378,7 +388,7 @@ __global__ __launch_bounds__(256) void atrous_tile_k(AtrousArgs a, int tiles, in
     __shared__ float4 s_cl[S::NS];  // r, g, b, L (L = +inf: no tap)
     __shared__ float4 s_gn[S::NS];  // z, nx, ny, nz (z = 0: no tap)
     __shared__ float s_v[S::NEED_V ? S::NS : 1];
-    __shared__ float2 s_pf[S::NP > 0 ? S::NP : 1];  // (var, 1) or (0, 0)
+    __shared__ float s_pf[S::NP > 0 ? S::NP : 1];  // var, or kNoVar
     const int gxt = (a.w + S::TX - 1) / S::TX;
     // this workgroup's run of tiles: its XCD's range, strided by the number
     // of workgroups on that XCD
@@ -409,8 +419,8 @@ __global__ __launch_bounds__(256) void atrous_tile_k(AtrousArgs a, int tiles, in
     }
 }
 
-// Batched form: the tiles of many streams (each its own AtrousArgs) as one
-// persistent sweep; every tile is staged and computed exactly as above.
+// Batched form: the tiles of many streams (each its own AtrousArgs), one
+// tile per workgroup; every tile is staged and computed exactly as above.
 template <typename T, int STEP, int PY, int MODE, bool WANT_VAR, int DIR>
 __global__ __launch_bounds__(256) void atrous_batch_k(const AtrousArgs *args, const int *prefix,
                                                       int n, int total) {
@@ -418,30 +428,24 @@ __global__ __launch_bounds__(256) void atrous_batch_k(const AtrousArgs *args, co
     __shared__ float4 s_cl[S::NS];
     __shared__ float4 s_gn[S::NS];
     __shared__ float s_v[S::NEED_V ? S::NS : 1];
-    __shared__ float2 s_pf[S::NP > 0 ? S::NP : 1];
-    const int per = (total + kXCD - 1) / kXCD, xcd = (int)blockIdx.x % kXCD;
-    for (int slot = (int)blockIdx.x / kXCD; slot < per; slot += (int)gridDim.x / kXCD) {
-        const int t = xcd * per + slot;
-        if (t >= total) break;
-        const int s = batch_stream(prefix, n, t);
-        const AtrousArgs a = args[s];
-        const int gxt = (a.w + S::TX - 1) / S::TX;
-        const TileOrigin o = tile_origin<STEP, S::TY, S::TX>(t - prefix[s], gxt);
-        TileRegs<S::IT, S::ITP> regs;
-        tile_issue<T, S>(a, o, regs);
-        tile_store<S>(regs, s_cl, s_gn, s_v, s_pf);
-        __syncthreads();
-        tile_compute<T, STEP, PY, MODE, WANT_VAR, DIR>(a, o, s_cl, s_gn, s_v, s_pf);
-        __syncthreads();  // the next tile's staging reuses the LDS
-    }
+    __shared__ float s_pf[S::NP > 0 ? S::NP : 1];
+    int s = 0;
+    const int lt = batch_tile(prefix, n, total, s);
+    if (lt < 0) return;
+    const AtrousArgs a = args[s];  // a copy: the kernel's stores cannot alias it
+    const int gxt = (a.w + S::TX - 1) / S::TX;
+    const TileOrigin o = tile_origin<STEP, S::TY, S::TX>(lt, gxt);
+    TileRegs<S::IT, S::ITP> regs;
+    tile_issue<T, S>(a, o, regs);
+    tile_store<S>(regs, s_cl, s_gn, s_v, s_pf);
+    __syncthreads();
+    tile_compute<T, STEP, PY, MODE, WANT_VAR, DIR>(a, o, s_cl, s_gn, s_v, s_pf);
 }
 
 template <typename T, int STEP, int PY, int MODE, bool WANT_VAR, int DIR>
-void atrous_batch_launch(const void *args, const int *prefix, int n, int total, int bpc,
-                         hipStream_t s) {
-    hipLaunchKernelGGL((atrous_batch_k<T, STEP, PY, MODE, WANT_VAR, DIR>),
-                       dim3(batch_grid(total, bpc)), dim3(256), 0, s, (const AtrousArgs *)args,
-                       prefix, n, total);
+void atrous_batch_launch(const void *args, const int *prefix, int n, int total, hipStream_t s) {
+    hipLaunchKernelGGL((atrous_batch_k<T, STEP, PY, MODE, WANT_VAR, DIR>), dim3(xcd_grid(total)),
+                       dim3(256), 0, s, (const AtrousArgs *)args, prefix, n, total);
 }
 
 // ---- 5x5 level, direct loads (any step) -------------------------------------
@@ -875,29 +879,23 @@ __global__ __launch_bounds__(64) void atrous_hv_batch_k(const HvArgs *args, cons
     __shared__ float4 s_cl[S::COLS];
     __shared__ float4 s_gn[S::COLS];
     __shared__ float2 s_pf[3 * S::PFC];
-    const int per = (total + kXCD - 1) / kXCD, xcd = (int)blockIdx.x % kXCD;
-    for (int slot = (int)blockIdx.x / kXCD; slot < per; slot += (int)gridDim.x / kXCD) {
-        const int t = xcd * per + slot;
-        if (t >= total) break;
-        const int s = batch_stream(prefix, n, t);
-        const HvArgs a = args[s];
-        hv_tile<T, STEP, MODE>(a, t - prefix[s], s_cl, s_gn, s_pf);
-        __syncthreads();
-    }
+    int s = 0;
+    const int lt = batch_tile(prefix, n, total, s);
+    if (lt < 0) return;
+    const HvArgs a = args[s];
+    hv_tile<T, STEP, MODE>(a, lt, s_cl, s_gn, s_pf);
 }
 
 template <typename T, int STEP, int MODE>
-void hv_batch_launch(const void *args, const int *prefix, int n, int total, int bpc,
-                     hipStream_t s) {
-    // one-wave workgroups: four per CU-slot of the four-wave kernels
-    hipLaunchKernelGGL((atrous_hv_batch_k<T, STEP, MODE>), dim3(batch_grid(total, 4 * bpc)),
-                       dim3(64), 0, s, (const HvArgs *)args, prefix, n, total);
+void hv_batch_launch(const void *args, const int *prefix, int n, int total, hipStream_t s) {
+    hipLaunchKernelGGL((atrous_hv_batch_k<T, STEP, MODE>), dim3(xcd_grid(total)), dim3(64), 0, s,
+                       (const HvArgs *)args, prefix, n, total);
 }
 
 template <typename T, int STEP, int MODE>
 void launch_hv_mode(const HvArgs &a, hipStream_t s) {
     const int tiles = hv_tiles(a.h);
-    if (record_pass(&hv_batch_launch<T, STEP, MODE>, a, tiles, 8)) return;
+    if (record_pass(&hv_batch_launch<T, STEP, MODE>, a, tiles)) return;
     hipLaunchKernelGGL((atrous_hv_k<T, STEP, MODE>), dim3(xcd_grid(tiles)), dim3(64), 0, s, a,
                        tiles);
 }
@@ -939,13 +937,11 @@ struct TileCfg {
 
 template <typename T, int STEP, int MODE, bool WANT_VAR, int DIR>
 void launch_tile(const AtrousArgs &a, TileCfg cfg, hipStream_t s) {
-    constexpr int PY = 2, TY = 4 * PY;
+    constexpr int PY = tile_py(STEP), TY = 4 * PY;
     const int bands = (a.h + STEP * TY - 1) / (STEP * TY);
     const int tiles = ((a.w + 63) / 64) * bands * STEP;
     const int per_xcd = (tiles + kXCD - 1) / kXCD;
-    if (record_pass(&atrous_batch_launch<T, STEP, PY, MODE, WANT_VAR, DIR>, a, tiles,
-                    cfg.persistent ? max(1, cfg.blocks_per_cu) : 4))
-        return;
+    if (record_pass(&atrous_batch_launch<T, STEP, PY, MODE, WANT_VAR, DIR>, a, tiles)) return;
     if (cfg.persistent) {
         const int slots = min(per_xcd, kCUs / kXCD * max(1, cfg.blocks_per_cu));
         hipLaunchKernelGGL((atrous_tile_k<T, STEP, PY, MODE, WANT_VAR, DIR, true>),
@@ -965,7 +961,7 @@ void launch_steps(const AtrousArgs &a, TileCfg cfg, hipStream_t s) {
     case 8: launch_tile<T, 8, MODE, WANT_VAR, DIR>(a, cfg, s); return;
     case 16: launch_tile<T, 16, MODE, WANT_VAR, DIR>(a, cfg, s); return;
     default: {  // other steps: direct loads (not available batched)
-        if (record_pass<AtrousArgs>(nullptr, a, 0, 0)) return;
+        if (record_pass<AtrousArgs>(nullptr, a, 0)) return;
         dim3 grid((a.w + 63) / 64, (a.h + 3) / 4);
         if (DIR == kDir2D)
             hipLaunchKernelGGL((atrous_direct_k<T, MODE, WANT_VAR>), grid, dim3(256), 0, s, a);

@@ -1,5 +1,5 @@
 // Batched frames: many independent denoiser streams of uneven sizes, one
-// persistent launch per pass over the tiles of all streams, the passes of
+// launch per pass over the tiles of all streams, the passes of
 // a frame captured once as a HIP graph and replayed every frame.
 //
 // Each frame the plan runs sv_denoise_frame for every stream with a launch
@@ -31,7 +31,6 @@ struct sv_batch {
     int npass = 0;
     sv::BatchLaunch fn[kMaxPasses];
     size_t arg_size[kMaxPasses];
-    int bpc[kMaxPasses];
     int total[kMaxPasses];
     size_t off_args[kMaxPasses], off_prefix[kMaxPasses];
     size_t bytes = 0;
@@ -118,7 +117,6 @@ static int build_plan(sv_batch *b, const int counts[]) {
         if (!r0.fn) return SV_EUNSUPPORTED;
         b->fn[k] = r0.fn;
         b->arg_size[k] = r0.arg_size;
-        b->bpc[k] = r0.blocks_per_cu;
         b->off_args[k] = off;
         off = align16(off + (size_t)b->n * r0.arg_size);
         b->off_prefix[k] = off;
@@ -165,7 +163,7 @@ static int capture(sv_batch *b) {
         return SV_EHIP;
     for (int k = 0; k < b->npass; ++k)
         b->fn[k](b->dev + b->off_args[k], (const int *)(b->dev + b->off_prefix[k]), b->n,
-                 b->total[k], b->bpc[k], b->cap);
+                 b->total[k], b->cap);
     const hipError_t e1 = hipGetLastError();
     const hipError_t e2 = hipStreamEndCapture(b->cap, &b->graph);
     if (e1 != hipSuccess || e2 != hipSuccess) return SV_EHIP;

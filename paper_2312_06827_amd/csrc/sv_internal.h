@@ -166,11 +166,13 @@ __device__ __forceinline__ void list_short_pixel(VarWork *work, uint32_t cap, in
 // ---- batched passes (many independent streams, one launch per pass) ----------
 //
 // A batched pass runs the tiles of n streams as one global list: stream s
-// owns tiles prefix[s] .. prefix[s+1]-1 and its own argument struct.  The
-// grid is persistent (a multiple of 8 workgroups); as in xcd_tile each XCD
-// sweeps one contiguous eighth of the list, so a stream's tiles stay on one
-// or two XCDs.  Every tile is computed by the same device code as the
-// single-stream kernel, so each stream's result is bitwise the same.
+// owns tiles prefix[s] .. prefix[s+1]-1 and its own argument struct.  One
+// workgroup per tile, mapped as in xcd_tile, so each XCD sweeps one
+// contiguous eighth of the list in order (a stream's tiles stay on one or
+// two XCDs and neighbouring tiles share that XCD's L2), exactly as the
+// single-stream launches do.  Every tile is computed by the same device
+// code as the single-stream kernel, so each stream's result is bitwise the
+// same.
 
 // Stream that owns global tile t (prefix has n + 1 entries; n is small and
 // the loop is uniform across the workgroup).
@@ -180,15 +182,18 @@ __device__ __forceinline__ int batch_stream(const int *prefix, int n, int t) {
     return s;
 }
 
+// This workgroup's tile within its stream s, or -1 for a padding workgroup.
+__device__ __forceinline__ int batch_tile(const int *prefix, int n, int total, int &s) {
+    const int t = xcd_tile(total);
+    if (t < 0) return -1;
+    s = batch_stream(prefix, n, t);
+    return t - prefix[s];
+}
+
 // Launcher of one batched pass: `args` holds n argument structs (device),
 // `prefix` n + 1 tile offsets (device), total = prefix[n].
 typedef void (*BatchLaunch)(const void *args, const int *prefix, int n, int total,
-                            int blocks_per_cu, hipStream_t s);
-
-inline unsigned batch_grid(int total, int blocks_per_cu) {
-    const int cap = 256 * (blocks_per_cu > 0 ? blocks_per_cu : 4);
-    return xcd_grid(total < cap ? (total > 0 ? total : 1) : cap);
-}
+                            hipStream_t s);
 
 // While a recorder is installed on the calling thread, the pass launchers
 // append (launcher, argument struct, tile count) here instead of
@@ -198,7 +203,6 @@ struct PassRecord {
     BatchLaunch fn;
     size_t arg_size;
     int tiles;
-    int blocks_per_cu;
     unsigned char args[512];
 };
 
@@ -214,7 +218,7 @@ inline Recorder *&recorder() {
 }
 
 template <class A>
-inline bool record_pass(BatchLaunch fn, const A &a, int tiles, int blocks_per_cu) {
+inline bool record_pass(BatchLaunch fn, const A &a, int tiles) {
     static_assert(sizeof(A) <= sizeof(PassRecord::args), "argument struct too large");
     Recorder *r = recorder();
     if (!r) return false;
@@ -226,7 +230,6 @@ inline bool record_pass(BatchLaunch fn, const A &a, int tiles, int blocks_per_cu
     p.fn = fn;
     p.arg_size = sizeof(A);
     p.tiles = tiles;
-    p.blocks_per_cu = blocks_per_cu;
     const unsigned char *src = (const unsigned char *)&a;
     for (size_t i = 0; i < sizeof(A); ++i) p.args[i] = src[i];
     return true;

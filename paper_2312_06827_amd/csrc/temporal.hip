@@ -518,25 +518,19 @@ __global__ __launch_bounds__(256) void temporal_batch_k(const TemporalArgs *args
     __shared__ float4 tile[(kTX + 2) * (kTY + 2)];
     __shared__ uint4 s_feat[MODE == kLearn ? 2 * 256 : 1];
     __shared__ uint32_t wave_n[4], base_sh;
-    const int per = (total + kXCD - 1) / kXCD, xcd = (int)blockIdx.x % kXCD;
-    for (int slot = (int)blockIdx.x / kXCD; slot < per; slot += (int)gridDim.x / kXCD) {
-        const int t = xcd * per + slot;
-        if (t >= total) break;
-        const int s = batch_stream(prefix, n, t);
-        const TemporalArgs a = args[s];
-        const int lt = t - prefix[s], gxt = (a.w + kTX - 1) / kTX;
-        temporal_tile<T, TM, RECT, USE_ID, MODE>(a, tile, s_feat, wave_n, base_sh, lt % gxt,
-                                                  lt / gxt);
-        __syncthreads();  // the next tile's staging reuses the LDS
-    }
+    int s = 0;
+    const int lt = batch_tile(prefix, n, total, s);
+    if (lt < 0) return;
+    const TemporalArgs a = args[s];  // a copy: the kernel's stores cannot alias it
+    const int gxt = (a.w + kTX - 1) / kTX;
+    temporal_tile<T, TM, RECT, USE_ID, MODE>(a, tile, s_feat, wave_n, base_sh, lt % gxt, lt / gxt);
 }
 
 template <typename T, bool TM, int RECT, bool USE_ID, int MODE>
-static void temporal_batch_launch(const void *args, const int *prefix, int n, int total, int bpc,
+static void temporal_batch_launch(const void *args, const int *prefix, int n, int total,
                                   hipStream_t s) {
-    hipLaunchKernelGGL((temporal_batch_k<T, TM, RECT, USE_ID, MODE>),
-                       dim3(batch_grid(total, bpc)), dim3(256), 0, s, (const TemporalArgs *)args,
-                       prefix, n, total);
+    hipLaunchKernelGGL((temporal_batch_k<T, TM, RECT, USE_ID, MODE>), dim3(xcd_grid(total)),
+                       dim3(256), 0, s, (const TemporalArgs *)args, prefix, n, total);
 }
 
 struct ClampArgs {
@@ -570,7 +564,7 @@ __global__ __launch_bounds__(256) void clamp_k(ClampArgs a) {
 template <typename T, bool TM, int RECT, bool USE_ID, int MODE>
 static void launch_temporal_one(const TemporalArgs &a, dim3 grid, hipStream_t s) {
     const int tiles = ((a.w + kTX - 1) / kTX) * ((a.h + kTY - 1) / kTY);
-    if (record_pass(&temporal_batch_launch<T, TM, RECT, USE_ID, MODE>, a, tiles, 8)) return;
+    if (record_pass(&temporal_batch_launch<T, TM, RECT, USE_ID, MODE>, a, tiles)) return;
     hipLaunchKernelGGL((temporal_k<T, TM, RECT, USE_ID, MODE>), grid, dim3(256), 0, s, a);
 }
 

@@ -55,15 +55,11 @@ template <typename T>
 __global__ __launch_bounds__(256) void variance_point_batch_k(const VarianceArgs *args,
                                                               const int *prefix, int n, int total) {
     __shared__ uint32_t wave_n[4], base_sh;
-    const int per = (total + kXCD - 1) / kXCD, xcd = (int)blockIdx.x % kXCD;
-    for (int slot = (int)blockIdx.x / kXCD; slot < per; slot += (int)gridDim.x / kXCD) {
-        const int t = xcd * per + slot;
-        if (t >= total) break;
-        const int s = batch_stream(prefix, n, t);
-        const VarianceArgs a = args[s];
-        variance_point_tile<T>(a, t - prefix[s], wave_n, base_sh);
-        __syncthreads();  // wave_n and base_sh are reused by the next tile
-    }
+    int s = 0;
+    const int lt = batch_tile(prefix, n, total, s);
+    if (lt < 0) return;
+    const VarianceArgs a = args[s];
+    variance_point_tile<T>(a, lt, wave_n, base_sh);
 }
 
 __global__ __launch_bounds__(64) void variance_reset_k(VarWork *w) {
@@ -179,26 +175,26 @@ __global__ __launch_bounds__(256) void variance_spatial_batch_k(const VarianceAr
 }
 
 template <typename T>
-static void point_batch_launch(const void *args, const int *prefix, int n, int total, int bpc,
+static void point_batch_launch(const void *args, const int *prefix, int n, int total,
                                hipStream_t s) {
-    hipLaunchKernelGGL(variance_point_batch_k<T>, dim3(batch_grid(total, bpc)), dim3(256), 0, s,
+    hipLaunchKernelGGL(variance_point_batch_k<T>, dim3(xcd_grid(total)), dim3(256), 0, s,
                        (const VarianceArgs *)args, prefix, n, total);
 }
 
 template <typename T, int R>
-static void spatial_batch_launch(const void *args, const int *, int n, int, int, hipStream_t s) {
+static void spatial_batch_launch(const void *args, const int *, int n, int, hipStream_t s) {
     hipLaunchKernelGGL((variance_spatial_batch_k<T, R>), dim3(kSpatialBlocks), dim3(256), 0, s,
                        (const VarianceArgs *)args, n);
 }
 
-static void reset_batch_launch(const void *args, const int *, int n, int, int, hipStream_t s) {
+static void reset_batch_launch(const void *args, const int *, int n, int, hipStream_t s) {
     hipLaunchKernelGGL(variance_reset_batch_k, dim3((n * kXCD + 255) / 256), dim3(256), 0, s,
                        (const VarianceArgs *)args, n);
 }
 
 template <typename T, int R>
 void launch_spatial(const VarianceArgs &a, hipStream_t s) {
-    if (record_pass(&spatial_batch_launch<T, R>, a, 0, 0)) return;
+    if (record_pass(&spatial_batch_launch<T, R>, a, 0)) return;
     hipLaunchKernelGGL((variance_spatial_k<T, R>), dim3(kSpatialBlocks), dim3(256), 0, s, a);
 }
 
@@ -206,7 +202,7 @@ template <typename T>
 void launch_variance(const VarianceArgs &a, unsigned grid, int radius, bool listed,
                      hipStream_t s) {
     const int tiles = ((a.w + kVX - 1) / kVX) * ((a.h + kVY - 1) / kVY);
-    if (!listed && !record_pass(&point_batch_launch<T>, a, tiles, 8))
+    if (!listed && !record_pass(&point_batch_launch<T>, a, tiles))
         hipLaunchKernelGGL(variance_point_k<T>, dim3(grid), dim3(256), 0, s, a);
     switch (radius) {
     case 0: launch_spatial<T, 0>(a, s); break;
@@ -218,7 +214,7 @@ void launch_variance(const VarianceArgs &a, unsigned grid, int radius, bool list
     case 6: launch_spatial<T, 6>(a, s); break;
     default: launch_spatial<T, 7>(a, s); break;
     }
-    if (!record_pass(&reset_batch_launch, a, 0, 0))
+    if (!record_pass(&reset_batch_launch, a, 0))
         hipLaunchKernelGGL(variance_reset_k, dim3(1), dim3(64), 0, s, a.work);
 }
 
