@@ -34,7 +34,7 @@ import numpy as np
 __all__ = [
     "OracleParams", "tonemap", "reproject", "clamp", "clip", "blend", "temporal",
     "variance", "atrous", "atrous_sep", "quantize_half", "new_state",
-    "run_frame", "luma", "blur_control", "atrous_adaptive",
+    "run_frame", "luma", "blur_control", "atrous_adaptive", "compose",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -361,6 +361,22 @@ def atrous_adaptive(rgb, var, z, dzdx, dzdy, n, ctl, level, separable=False, kap
     out = np.where(keep, same, np.where(shifted, coarse[0], fine[0]))
     vo = np.where(keep, var, np.where(shifted, coarse[1], fine[1])) if want_var else None
     return out, vo
+
+
+# ---- composition of the channels (Section 3, step 7) ---------------------------
+
+def compose(direct, shadow=None, spec=None, half_out=False):
+    """The denoised shadow and indirect specular channels blended with the
+    noise-free direct lighting.  The paper names the step without a formula;
+    the reading is the usual deferred one: direct light attenuated by the
+    shadow visibility, plus the indirect specular light, per colour
+    channel."""
+    out = _f64(direct).copy()
+    if shadow is not None:
+        out = out * _f64(shadow)
+    if spec is not None:
+        out = out + _f64(spec)
+    return quantize_half(out) if half_out else out
 
 
 def quantize_half(x):

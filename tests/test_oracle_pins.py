@@ -918,3 +918,42 @@ def test_adaptive_cascade_with_the_papers_count_equals_every_level():
     np.testing.assert_array_equal(every, plain)
     one, _, ex = O.run_frame(fr, st, p, ctl=np.full((32, 48), 1, np.uint8))
     np.testing.assert_allclose(one, O.tonemap(ex["levels"][0], inverse=True), rtol=1e-15)
+
+
+# ---- composition of the channels (Section 3, step 7) --------------------------------
+
+def test_compose_closed_forms():
+    r = rng(60)
+    direct = r.uniform(0, 1, (3, 4, 5))
+    vis = r.uniform(0, 1, (3, 4, 5))
+    spec = r.uniform(0, 2, (3, 4, 5))
+    np.testing.assert_array_equal(O.compose(direct), direct)
+    np.testing.assert_array_equal(O.compose(direct, np.ones_like(vis)), direct)
+    np.testing.assert_array_equal(O.compose(direct, np.zeros_like(vis), spec), spec)
+    # a hand-worked pixel: 0.5 * 0.25 + 0.125
+    d = np.full((3, 1, 1), 0.5)
+    assert O.compose(d, np.full((3, 1, 1), 0.25), np.full((3, 1, 1), 0.125))[0, 0, 0] == 0.25
+    np.testing.assert_allclose(O.compose(direct, vis, spec), direct * vis + spec, rtol=1e-15)
+
+
+def test_two_channel_chain_reproduces_constant_channels():
+    # constant visibility (no tone map) and constant specular light (tone
+    # mapped) with valid history: each channel is reproduced, so the
+    # composite is direct * v + s exactly where the chain invariant holds
+    from dataclasses import replace
+    from paper_2312_06827_amd.scene import CONFIGS, sequence, with_size
+    cfg = replace(with_size(CONFIGS["hd_motion"], 64, 40, 4), channels=True)
+    ps = O.OracleParams(clamp=True, use_id=True, levels=4)
+    pr = O.OracleParams(clamp=True, tonemap=True, use_id=True, levels=4)
+    ss, sp = O.new_state(40, 64), O.new_state(40, 64)
+    v, c = 0.625, np.array([0.3, 0.2, 0.45])
+    for fr in sequence(cfg):
+        fs, fp = dict(fr), dict(fr)
+        fs["rgb"] = np.full((3, 40, 64), v)
+        fp["rgb"] = np.broadcast_to(c[:, None, None], (3, 40, 64)).copy()
+        os_, ss, _ = O.run_frame(fs, ss, ps, ctl=O.blur_control(None, fr["shadow_angle"],
+                                                                   table=False))
+        op, sp, _ = O.run_frame(fp, sp, pr, ctl=O.blur_control(fr["roughness"]))
+        out = O.compose(fr["direct"], os_, op)
+        np.testing.assert_allclose(out, fr["direct"].astype(np.float64) * v + c[:, None, None],
+                                   rtol=1e-12)
