@@ -315,6 +315,51 @@ def variant_learned(torch, frames_np, warmup, steps):
     return out
 
 
+def variant_scene_features(torch, frames_np, warmup, steps):
+    """The paper's alternatives on the headline workload: variance colour
+    clipping instead of the clamp (Section 3.1), and the blur adapted to
+    scene features (Sections 3.2, 3.5) with the control bytes computed
+    from the scene's roughness every frame (inside the timed region).
+    Throughput and RelMSE-to-clean over the timed frames."""
+    from dataclasses import replace as dc_replace
+
+    from paper_2312_06827_amd import learn
+    from paper_2312_06827_amd import lib as L
+    from paper_2312_06827_amd.pipeline import MOTION, MOTION_SEP, Denoiser, FrameInputs
+    H, W = WORKLOAD.height, WORKLOAD.width
+    n = warmup + steps
+    frames = [FrameInputs.from_numpy(fr) for fr in frames_np[:n]]
+    clean = [torch.from_numpy(fr["clean"]).cuda() for fr in frames_np[:n]]
+    rough = [torch.from_numpy(fr["roughness"]).cuda() for fr in frames_np[:n]]
+    ctl = [torch.empty((H, W), dtype=torch.uint8, device="cuda") for _ in range(n)]
+    rule = L.BlurRule()
+
+    def run(cfg, adaptive):
+        for i, fr in enumerate(frames):
+            fr.blur_ctl = ctl[i] if adaptive else None
+        den = Denoiser(H, W, cfg)
+
+        def step(i):
+            if adaptive:
+                L.sv_blur_control(rough[i], None, ctl[i], rule)
+            return den.frame(frames[i])
+        ms = _timed_frames(torch, step, list(range(n)), warmup)
+        den = Denoiser(H, W, cfg)
+        q = float(np.mean([learn.relmse(step(i), clean[i]) for i in range(n)][warmup:]))
+        return {"value": round(H * W / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 4),
+                "relmse": round(q, 6)}
+
+    out = {"rule": "shift above roughness 0.2; levels 0 / 1 / all at roughness <= 0 / <= 0.05 / above"}
+    out["clamp_2d"] = run(MOTION, False)
+    out["clip_2d"] = run(dc_replace(MOTION, clamp=False, clip=True), False)
+    out["adaptive_2d"] = run(MOTION, True)
+    out["clamp_sep"] = run(MOTION_SEP, False)
+    out["adaptive_sep"] = run(MOTION_SEP, True)
+    for fr in frames:
+        fr.blur_ctl = None
+    return out
+
+
 def cpu_baseline(frames_np, warm, timed):
     """The oracle as it stands, on the host cores, on a bounded sample."""
     import oracle as O
@@ -342,7 +387,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
-    ap.add_argument("--variants", default="separable,uhd_half,batched,learned",
+    ap.add_argument("--variants", default="separable,uhd_half,batched,scene_features,learned",
                     help="comma-separated variants to run after the headline chain")
     ap.add_argument("--tune", action="store_true",
                     help="a-trous launch shapes from the autotuner (timed before the run)"
@@ -435,6 +480,10 @@ def main():
         variants["batched"] = variant_batched(torch, vframes["batch_cfg"], vframes["batch"])
         print(f"# 16 streams batched: {variants['batched']['ms_per_step'] * 1e3:.1f} us/frame",
               file=sys.stderr, flush=True)
+    if "scene_features" in want:
+        variants["scene_features"] = variant_scene_features(torch, frames_np, args.warmup,
+                                                            args.steps)
+        print(f"# clip / adaptive: {variants['scene_features']}", file=sys.stderr, flush=True)
     if "learned" in want:
         learned = variant_learned(torch, frames_np, args.warmup, args.steps)
         if learned is not None:

@@ -473,6 +473,19 @@ int sv_atrous_kappa_grad(const sv_rgb *c_in, const float *var_in, const sv_gbuf 
                          float *d_kappa, int32_t step, sv_dims d, sv_dtype t,
                          const sv_atrous_params *p, sv_stream stream);
 
+/* ---- composition of the channels (Section 3, step 7) ------------------ */
+
+/* The paper denoises shadows and indirect specular light as separate
+ * channels and blends them with the noise-free (rasterised) direct
+ * lighting.  Reading of that blend: out = direct * shadow + spec per colour
+ * channel (shadow: the denoised visibility, spec: the denoised indirect
+ * specular radiance), evaluated as one binary32 fma and rounded to the
+ * storage type.  shadow NULL means 1, spec NULL means 0.  Every plane has
+ * the storage type; an output plane may be the same plane as the same
+ * channel of an input, but no other overlap is allowed (SV_EALIAS). */
+int sv_compose(const sv_rgb *direct, const sv_rgb *shadow, const sv_rgb *spec,
+               const sv_rgb *out, sv_dims d, sv_dtype t, sv_stream stream);
+
 /* ---- one frame of the whole filter (Section 3, steps 4 and 5) --------- */
 
 /* Caller-owned buffers of one denoiser instance; every plane has the
@@ -545,8 +558,9 @@ int sv_denoise_frame(const sv_frame_in *in, sv_denoiser *st, sv_dims d,
  * Each sv_batch_frame does for every stream exactly what sv_denoise_frame
  * does (the same kernels' tile code, so each stream's results are bitwise
  * those of sv_denoise_frame), but every pass runs once for all streams: one
- * persistent launch over the tiles of all of them, the passes of a frame
- * captured on the first call as a HIP graph and replayed afterwards.
+ * launch over the tiles of all of them (one workgroup per tile), the passes
+ * of a frame captured on the first call as a HIP graph and replayed
+ * afterwards.
  *
  * The plan is the one object of the library that allocates (a device
  * buffer of the streams' per-pass arguments, pinned staging for it, two
@@ -557,6 +571,18 @@ typedef struct sv_batch sv_batch;
 
 int sv_batch_create(const sv_dims *dims, sv_denoiser *const *states, int32_t n,
                     sv_dtype t, const sv_frame_params *p, sv_batch **out);
+
+/* As sv_batch_create with its own sv_frame_params per stream (params[i] for
+ * stream i): e.g. the channels of one frame (Section 3: shadows, indirect
+ * specular) filtered with different settings in one launch per pass.  The
+ * streams must run the same kernels pass by pass - the same level count,
+ * form (2D / separable), rectification and id test, and the learned or
+ * adaptive inputs on all or none; the tone map, the sigmas, the blend
+ * factors and the thresholds may differ.  A mismatch is found on the first
+ * sv_batch_frame, which then returns SV_EINVAL. */
+int sv_batch_create_each(const sv_dims *dims, sv_denoiser *const *states,
+                         int32_t n, sv_dtype t, const sv_frame_params *params,
+                         sv_batch **out);
 
 /* One frame of every stream: in[i] are stream i's inputs (as for
  * sv_denoise_frame).  Flips every state's `cur`. */

@@ -601,7 +601,13 @@ __global__ __launch_bounds__(256) void atrous_sep_k(AtrousArgs a) {
 // of the two-pass form would round it, and every weight, sum and order is
 // that of the two passes, so the output is bitwise theirs.  The level
 // reads the G-buffer and colour once and writes only its outputs.
-constexpr int kHvRows = 16;
+#ifndef SV_HV_ROWS
+#define SV_HV_ROWS 16
+#endif
+#ifndef SV_HV_WAVES_PER_EU
+#define SV_HV_WAVES_PER_EU 1
+#endif
+constexpr int kHvRows = SV_HV_ROWS;
 static_assert((kHvRows + 4) % 5 == 0, "rows per tile must fill the five-slot ring");
 
 template <int STEP>
@@ -862,7 +868,7 @@ __device__ __forceinline__ void hv_tile(const HvArgs &a, int t, float4 *s_cl, fl
 }
 
 template <typename T, int STEP, int MODE>
-__global__ __launch_bounds__(64) void atrous_hv_k(HvArgs a, int tiles) {
+__global__ __launch_bounds__(64, SV_HV_WAVES_PER_EU) void atrous_hv_k(HvArgs a, int tiles) {
     using S = HvShape<STEP>;
     __shared__ float4 s_cl[S::COLS];
     __shared__ float4 s_gn[S::COLS];

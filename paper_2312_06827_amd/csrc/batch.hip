@@ -24,7 +24,7 @@ inline size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
 struct sv_batch {
     int n = 0;
     sv_dtype t = SV_F32;
-    sv_frame_params p{};
+    sv_frame_params p[kMaxStreams];  // per stream
     sv_dims dims[kMaxStreams];
     sv_denoiser *st[kMaxStreams];
     // pass structure, fixed by the first frame
@@ -57,18 +57,19 @@ static void release(sv_batch *b) {
     delete b;
 }
 
-extern "C" int sv_batch_create(const sv_dims *dims, sv_denoiser *const *states, int32_t n,
-                               sv_dtype t, const sv_frame_params *p, sv_batch **out) {
+static int create(const sv_dims *dims, sv_denoiser *const *states, int32_t n, sv_dtype t,
+                  const sv_frame_params *p, size_t p_stride, sv_batch **out) {
     using namespace sv;
     if (!out) return SV_EINVAL;
     *out = nullptr;
     if (!valid_dtype(t)) return SV_EDTYPE;
     if (!dims || !states || !p || n < 1 || n > kMaxStreams) return SV_EINVAL;
-    if (p->levels < 1 || p->levels > 5) return SV_EUNSUPPORTED;  // steps 1..16: tiled passes
-    // one level whose output is the colour history needs a separate final
-    // pass; not batched
-    if (p->levels == 1 && p->feedback != 1) return SV_EUNSUPPORTED;
     for (int i = 0; i < n; ++i) {
+        const sv_frame_params &pi = p[i * p_stride];
+        if (pi.levels < 1 || pi.levels > 5) return SV_EUNSUPPORTED;  // steps 1..16: tiled passes
+        // one level whose output is the colour history needs a separate
+        // final pass; not batched
+        if (pi.levels == 1 && pi.feedback != 1) return SV_EUNSUPPORTED;
         if (check_dims(dims[i]) != 0 || !states[i]) return SV_EINVAL;
         for (int j = 0; j < i; ++j)
             if (states[j] == states[i]) return SV_EALIAS;
@@ -77,13 +78,23 @@ extern "C" int sv_batch_create(const sv_dims *dims, sv_denoiser *const *states, 
     if (!b) return SV_EHIP;
     b->n = n;
     b->t = t;
-    b->p = *p;
     for (int i = 0; i < n; ++i) {
+        b->p[i] = p[i * p_stride];
         b->dims[i] = dims[i];
         b->st[i] = states[i];
     }
     *out = b;
     return SV_OK;
+}
+
+extern "C" int sv_batch_create(const sv_dims *dims, sv_denoiser *const *states, int32_t n,
+                               sv_dtype t, const sv_frame_params *p, sv_batch **out) {
+    return create(dims, states, n, t, p, 0, out);
+}
+
+extern "C" int sv_batch_create_each(const sv_dims *dims, sv_denoiser *const *states, int32_t n,
+                                    sv_dtype t, const sv_frame_params *params, sv_batch **out) {
+    return create(dims, states, n, t, params, 1, out);
 }
 
 extern "C" void sv_batch_destroy(sv_batch *b) {
@@ -97,7 +108,7 @@ static int record_all(sv_batch *b, const sv_frame_in *in, int counts[]) {
     for (int i = 0; i < b->n; ++i) {
         Recorder r{b->rec[i], kMaxPasses, 0, false};
         recorder() = &r;
-        const int rc = sv_denoise_frame(&in[i], b->st[i], b->dims[i], b->t, &b->p, nullptr);
+        const int rc = sv_denoise_frame(&in[i], b->st[i], b->dims[i], b->t, &b->p[i], nullptr);
         recorder() = nullptr;
         counts[i] = r.count;
         if (rc != SV_OK || r.overflow) {

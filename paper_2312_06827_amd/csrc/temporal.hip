@@ -26,6 +26,7 @@ struct TemporalArgs {
     int w, h, pitch;
     float alpha, alpha_m, gamma, tau_z, tau_n, tm_k;
     int max_hist;
+    int tm;  // forward tone map of the current colour (a uniform branch)
     // feature mode only
     const void *dzdx, *dzdy, *alr, *alg, *alb;
     uint4 *feat;              // two 16-byte halves per pixel, row y * w + x
@@ -126,12 +127,12 @@ __device__ __forceinline__ void rectify(const float4 *tile, int lx, int ly, floa
     }
 }
 
-// Stage the current colour (tone mapped if TM) of the tile and a one-pixel
+// Stage the current colour (tone mapped if tm) of the tile and a one-pixel
 // apron; w = 1 for pixels inside the image that are not empty, else 0.
-template <typename T, bool TM>
+template <typename T>
 __device__ __forceinline__ void stage_current(float4 *tile, const void *cr, const void *cg,
                                               const void *cb, const void *zp, int w, int h,
-                                              int pitch, float tm_k, int bx, int by) {
+                                              int pitch, bool tm, float tm_k, int bx, int by) {
     // unrolled, every load issued from an in-image address (masked after)
     const int x0 = (int)bx * kTX - 1, y0 = (int)by * kTY - 1;
     constexpr int NS = (kTX + 2) * (kTY + 2), IT = (NS + 255) / 256;
@@ -144,7 +145,7 @@ __device__ __forceinline__ void stage_current(float4 *tile, const void *cr, cons
         const uint32_t o = in ? (uint32_t)gy * (uint32_t)pitch + (uint32_t)gx : 0u;
         float R = ldo<T>(cr, o), G = ldo<T>(cg, o), B = ldo<T>(cb, o);
         const float zz = zp ? ldo<T>(zp, o) : 1.f;
-        if (TM) {
+        if (tm) {
             const float sc = 1.0f / (1.0f + tm_k * luma(R, G, B));
             R *= sc;
             G *= sc;
@@ -455,7 +456,7 @@ __device__ __forceinline__ void px_network(const TemporalArgs &a, uint4 *s_feat,
 // once this thread's pixel is done (the caller's barrier follows).
 enum { kBlend = 0, kFeat = 1, kLearn = 2 };
 
-template <typename T, bool TM, int RECT, bool USE_ID, int MODE>
+template <typename T, int RECT, bool USE_ID, int MODE>
 __device__ __forceinline__ void temporal_tile(const TemporalArgs &a, float4 *tile, uint4 *s_feat,
                                               uint32_t *wave_n, uint32_t &base_sh, int bx,
                                               int by) {
@@ -463,7 +464,7 @@ __device__ __forceinline__ void temporal_tile(const TemporalArgs &a, float4 *til
     const int x = bx * kTX + lx, y = by * kTY + ly;
     PxLoads g;
     px_gather<T, USE_ID>(a, x, y, g);
-    stage_current<T, TM>(tile, a.cr, a.cg, a.cb, a.z, a.w, a.h, a.pitch, a.tm_k, bx, by);
+    stage_current<T>(tile, a.cr, a.cg, a.cb, a.z, a.w, a.h, a.pitch, a.tm != 0, a.tm_k, bx, by);
     __syncthreads();
     const PxState s = px_reproject<RECT, USE_ID>(a, tile, lx, ly, x, y, g);
     if (MODE == kFeat) {
@@ -500,7 +501,7 @@ __device__ __forceinline__ void temporal_tile(const TemporalArgs &a, float4 *til
     }
 }
 
-template <typename T, bool TM, int RECT, bool USE_ID, int MODE>
+template <typename T, int RECT, bool USE_ID, int MODE>
 __global__ __launch_bounds__(256) void temporal_k(TemporalArgs a) {
     __shared__ float4 tile[(kTX + 2) * (kTY + 2)];
     __shared__ uint4 s_feat[MODE == kLearn ? 2 * 256 : 1];
@@ -509,10 +510,10 @@ __global__ __launch_bounds__(256) void temporal_k(TemporalArgs a) {
     const int t = xcd_tile(gxt * ((a.h + kTY - 1) / kTY));
     if (t < 0) return;
     const int by = t / gxt, bx = t - by * gxt;
-    temporal_tile<T, TM, RECT, USE_ID, MODE>(a, tile, s_feat, wave_n, base_sh, bx, by);
+    temporal_tile<T, RECT, USE_ID, MODE>(a, tile, s_feat, wave_n, base_sh, bx, by);
 }
 
-template <typename T, bool TM, int RECT, bool USE_ID, int MODE>
+template <typename T, int RECT, bool USE_ID, int MODE>
 __global__ __launch_bounds__(256) void temporal_batch_k(const TemporalArgs *args, const int *prefix,
                                                         int n, int total) {
     __shared__ float4 tile[(kTX + 2) * (kTY + 2)];
@@ -523,13 +524,13 @@ __global__ __launch_bounds__(256) void temporal_batch_k(const TemporalArgs *args
     if (lt < 0) return;
     const TemporalArgs a = args[s];  // a copy: the kernel's stores cannot alias it
     const int gxt = (a.w + kTX - 1) / kTX;
-    temporal_tile<T, TM, RECT, USE_ID, MODE>(a, tile, s_feat, wave_n, base_sh, lt % gxt, lt / gxt);
+    temporal_tile<T, RECT, USE_ID, MODE>(a, tile, s_feat, wave_n, base_sh, lt % gxt, lt / gxt);
 }
 
-template <typename T, bool TM, int RECT, bool USE_ID, int MODE>
+template <typename T, int RECT, bool USE_ID, int MODE>
 static void temporal_batch_launch(const void *args, const int *prefix, int n, int total,
                                   hipStream_t s) {
-    hipLaunchKernelGGL((temporal_batch_k<T, TM, RECT, USE_ID, MODE>), dim3(xcd_grid(total)),
+    hipLaunchKernelGGL((temporal_batch_k<T, RECT, USE_ID, MODE>), dim3(xcd_grid(total)),
                        dim3(256), 0, s, (const TemporalArgs *)args, prefix, n, total);
 }
 
@@ -547,7 +548,7 @@ __global__ __launch_bounds__(256) void clamp_k(ClampArgs a) {
     const int t = xcd_tile(gxt * ((a.h + kTY - 1) / kTY));
     if (t < 0) return;
     const int by = t / gxt, bx = t - by * gxt;
-    stage_current<T, false>(tile, a.cr, a.cg, a.cb, a.z, a.w, a.h, a.pitch, 0.f, bx, by);
+    stage_current<T>(tile, a.cr, a.cg, a.cb, a.z, a.w, a.h, a.pitch, false, 0.f, bx, by);
     __syncthreads();
     const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
     const int x = bx * kTX + lx, y = by * kTY + ly;
@@ -561,32 +562,25 @@ __global__ __launch_bounds__(256) void clamp_k(ClampArgs a) {
     sto<T>(a.ob, o, b);
 }
 
-template <typename T, bool TM, int RECT, bool USE_ID, int MODE>
+template <typename T, int RECT, bool USE_ID, int MODE>
 static void launch_temporal_one(const TemporalArgs &a, dim3 grid, hipStream_t s) {
     const int tiles = ((a.w + kTX - 1) / kTX) * ((a.h + kTY - 1) / kTY);
-    if (record_pass(&temporal_batch_launch<T, TM, RECT, USE_ID, MODE>, a, tiles)) return;
-    hipLaunchKernelGGL((temporal_k<T, TM, RECT, USE_ID, MODE>), grid, dim3(256), 0, s, a);
+    if (record_pass(&temporal_batch_launch<T, RECT, USE_ID, MODE>, a, tiles)) return;
+    hipLaunchKernelGGL((temporal_k<T, RECT, USE_ID, MODE>), grid, dim3(256), 0, s, a);
 }
 
-template <typename T, bool TM, int RECT, int MODE>
+template <typename T, int RECT, int MODE>
 static void launch_temporal_id(const TemporalArgs &a, bool use_id, dim3 grid, hipStream_t s) {
-    if (use_id) launch_temporal_one<T, TM, RECT, true, MODE>(a, grid, s);
-    else launch_temporal_one<T, TM, RECT, false, MODE>(a, grid, s);
-}
-
-template <typename T, bool TM, int MODE>
-static void launch_temporal_rect(const TemporalArgs &a, int rect, bool use_id, dim3 grid,
-                                 hipStream_t s) {
-    if (rect == kRectClip) launch_temporal_id<T, TM, kRectClip, MODE>(a, use_id, grid, s);
-    else if (rect == kRectClamp) launch_temporal_id<T, TM, kRectClamp, MODE>(a, use_id, grid, s);
-    else launch_temporal_id<T, TM, kRectOff, MODE>(a, use_id, grid, s);
+    if (use_id) launch_temporal_one<T, RECT, true, MODE>(a, grid, s);
+    else launch_temporal_one<T, RECT, false, MODE>(a, grid, s);
 }
 
 template <typename T, int MODE>
-static void launch_temporal(const TemporalArgs &a, bool tm, int rect, bool use_id, dim3 grid,
+static void launch_temporal(const TemporalArgs &a, int rect, bool use_id, dim3 grid,
                             hipStream_t s) {
-    if (tm) launch_temporal_rect<T, true, MODE>(a, rect, use_id, grid, s);
-    else launch_temporal_rect<T, false, MODE>(a, rect, use_id, grid, s);
+    if (rect == kRectClip) launch_temporal_id<T, kRectClip, MODE>(a, use_id, grid, s);
+    else if (rect == kRectClamp) launch_temporal_id<T, kRectClamp, MODE>(a, use_id, grid, s);
+    else launch_temporal_id<T, kRectOff, MODE>(a, use_id, grid, s);
 }
 
 // Rectification mode of the temporal flags; -1 when both are set.
@@ -682,7 +676,8 @@ extern "C" int sv_temporal(const sv_temporal_io *io, sv_dims d, sv_dtype t,
                    io->prev.nz, io->prev.id, io->hist.r, io->hist.g, io->hist.b, io->hist_m1,
                    io->hist_m2c, io->hist_n, io->out.r, io->out.g, io->out.b, io->out_m1,
                    io->out_m2c, io->out_n, learn ? nullptr : io->alpha_map, d.w, d.h, d.pitch,
-                   p->alpha, p->alpha_m, p->gamma, p->tau_z, p->tau_n, p->tm_k, p->max_hist};
+                   p->alpha, p->alpha_m, p->gamma, p->tau_z, p->tau_n, p->tm_k, p->max_hist,
+                   tm ? 1 : 0};
     dim3 grid(xcd_grid(((d.w + kTX - 1) / kTX) * ((d.h + kTY - 1) / kTY)));
     hipStream_t s = as_stream(stream);
     if (io->var) {
@@ -703,11 +698,11 @@ extern "C" int sv_temporal(const sv_temporal_io *io, sv_dims d, sv_dtype t,
         a.mwq = io->mlp->wq;
         a.kappa_out = io->kappa_out;
         a.alpha_out = io->alpha_out;
-        if (t == SV_F32) launch_temporal<float, kLearn>(a, tm, rect, use_id, grid, s);
-        else launch_temporal<half_t, kLearn>(a, tm, rect, use_id, grid, s);
+        if (t == SV_F32) launch_temporal<float, kLearn>(a, rect, use_id, grid, s);
+        else launch_temporal<half_t, kLearn>(a, rect, use_id, grid, s);
     } else {
-        if (t == SV_F32) launch_temporal<float, kBlend>(a, tm, rect, use_id, grid, s);
-        else launch_temporal<half_t, kBlend>(a, tm, rect, use_id, grid, s);
+        if (t == SV_F32) launch_temporal<float, kBlend>(a, rect, use_id, grid, s);
+        else launch_temporal<half_t, kBlend>(a, rect, use_id, grid, s);
     }
     return hip_status(hipGetLastError());
 }
@@ -768,15 +763,15 @@ extern "C" int sv_mlp_features(const sv_temporal_io *io, const sv_rgb *albedo, c
                    io->prev.nz, io->prev.id, io->hist.r, io->hist.g, io->hist.b, io->hist_m1,
                    io->hist_m2c, io->hist_n, nullptr, nullptr, nullptr, nullptr,
                    nullptr, nullptr, nullptr, d.w, d.h, d.pitch, p->alpha,
-                   p->alpha_m, p->gamma, p->tau_z, p->tau_n, p->tm_k, p->max_hist,
+                   p->alpha_m, p->gamma, p->tau_z, p->tau_n, p->tm_k, p->max_hist, tm ? 1 : 0,
                    io->g.dzdx, io->g.dzdy, albedo->r, albedo->g, albedo->b, (uint4 *)feat,
                    hist_out ? (float *)hist_out->r : nullptr,
                    hist_out ? (float *)hist_out->g : nullptr,
                    hist_out ? (float *)hist_out->b : nullptr, w->mu, w->inv_s};
     dim3 grid(xcd_grid(((d.w + kTX - 1) / kTX) * ((d.h + kTY - 1) / kTY)));
     hipStream_t s = as_stream(stream);
-    if (t == SV_F32) launch_temporal<float, kFeat>(a, tm, rect, use_id, grid, s);
-    else launch_temporal<half_t, kFeat>(a, tm, rect, use_id, grid, s);
+    if (t == SV_F32) launch_temporal<float, kFeat>(a, rect, use_id, grid, s);
+    else launch_temporal<half_t, kFeat>(a, rect, use_id, grid, s);
     return hip_status(hipGetLastError());
 }
 

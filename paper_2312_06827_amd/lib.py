@@ -142,6 +142,8 @@ EXPORTS = {
     "sv_atrous_adaptive": ([_P(sv_rgb), _vp, _P(sv_gbuf), _vp, _vp, _P(sv_rgb), _P(sv_rgb), _vp,
                             ctypes.c_int32, ctypes.c_int32, sv_dims, ctypes.c_int,
                             _P(sv_atrous_params), _vp], ctypes.c_int),
+    "sv_compose": ([_P(sv_rgb), _P(sv_rgb), _P(sv_rgb), _P(sv_rgb), sv_dims, ctypes.c_int, _vp],
+                   ctypes.c_int),
     "sv_blur_control": ([_vp, _vp, _vp, sv_dims, _P(sv_blur_rule), _vp], ctypes.c_int),
     "sv_denoise_frame": ([_P(sv_frame_in), _P(sv_denoiser), sv_dims, ctypes.c_int,
                           _P(sv_frame_params), _vp], ctypes.c_int),
@@ -160,6 +162,8 @@ EXPORTS = {
                              ctypes.c_int),
     "sv_batch_create": ([_P(sv_dims), _P(_P(sv_denoiser)), ctypes.c_int32, ctypes.c_int,
                          _P(sv_frame_params), _P(_vp)], ctypes.c_int),
+    "sv_batch_create_each": ([_P(sv_dims), _P(_P(sv_denoiser)), ctypes.c_int32, ctypes.c_int,
+                              _P(sv_frame_params), _P(_vp)], ctypes.c_int),
     "sv_batch_frame": ([_vp, _P(sv_frame_in), _vp], ctypes.c_int),
     "sv_batch_passes": ([_vp], ctypes.c_int),
     "sv_batch_destroy": ([_vp], None),
@@ -468,6 +472,16 @@ def sv_blur_control(roughness: Optional[torch.Tensor], shadow_angle: Optional[to
     _check("sv_blur_control", load().sv_blur_control(
         _plane_ptr(roughness), _plane_ptr(shadow_angle), _plane_ptr(ctl), dims_of(ctl),
         ctypes.byref(rc), _stream(stream)))
+
+
+def sv_compose(direct: Planes, shadow: Optional[Planes], spec: Optional[Planes], out: Planes,
+               stream=None):
+    """out = direct * shadow + spec per colour channel."""
+    r = _planes3(direct)[0]
+    opt = lambda p: None if p is None else ctypes.byref(_rgb(p))
+    _check("sv_compose", load().sv_compose(
+        ctypes.byref(_rgb(direct)), opt(shadow), opt(spec), ctypes.byref(_rgb(out)),
+        dims_of(r), dtype_of(r), _stream(stream)))
 
 
 # ---- learned blend factor and edge scale -------------------------------------

@@ -15,6 +15,7 @@ from __future__ import annotations
 
 import contextlib
 import ctypes
+import dataclasses
 from dataclasses import dataclass
 from typing import Callable, Dict, Optional
 
@@ -80,6 +81,11 @@ class FilterConfig:
 PLAIN = FilterConfig()
 MOTION = FilterConfig(clamp=True, tonemap=True, use_id=True)
 MOTION_SEP = FilterConfig(clamp=True, tonemap=True, use_id=True, separable=True)
+# The two channels of Section 3: shadows without the tone map (Section 3.4
+# applies it to the indirect specular channel only), four levels each (the
+# paper's cascade).
+SHADOW = FilterConfig(clamp=True, use_id=True, levels=4)
+SPECULAR = FilterConfig(clamp=True, tonemap=True, use_id=True, levels=4)
 
 
 @dataclass
@@ -280,18 +286,24 @@ class BatchDenoiser:
     graph (sv_batch_*).  Each stream owns a Denoiser's buffers and its
     results are bitwise those of that Denoiser run alone."""
 
-    def __init__(self, sizes, cfg: FilterConfig = MOTION, dtype: torch.dtype = torch.float32,
+    def __init__(self, sizes, cfg=MOTION, dtype: torch.dtype = torch.float32,
                  tiles=None, device: str = "cuda", mlp: Optional[lib.MLP] = None):
-        self.streams = [Denoiser(h, w, cfg, dtype, device, tiles, mlp) for (h, w) in sizes]
+        """cfg: one FilterConfig for every stream, or a list with one per
+        stream (the streams must then run the same kernels pass by pass)."""
+        cfgs = list(cfg) if isinstance(cfg, (list, tuple)) else [cfg] * len(sizes)
+        if len(cfgs) != len(sizes):
+            raise ValueError("one FilterConfig per stream")
+        self.streams = [Denoiser(h, w, c, dtype, device, tiles, mlp)
+                        for (h, w), c in zip(sizes, cfgs)]
         n = len(self.streams)
         self._dims = (lib.sv_dims * n)(*[d._dims for d in self.streams])
         self._states = (ctypes.POINTER(lib.sv_denoiser) * n)(
             *[ctypes.pointer(d._st) for d in self.streams])
-        self._params = self.streams[0]._params
+        self._params = (lib.sv_frame_params * n)(*[d._params for d in self.streams])
         self._plan = ctypes.c_void_p()
         so = lib.load()
-        lib._check("sv_batch_create", so.sv_batch_create(
-            self._dims, self._states, n, self.streams[0]._dtype, ctypes.byref(self._params),
+        lib._check("sv_batch_create_each", so.sv_batch_create_each(
+            self._dims, self._states, n, self.streams[0]._dtype, self._params,
             ctypes.byref(self._plan)))
 
     def frame(self, inputs, stream=None):
@@ -321,3 +333,43 @@ class BatchDenoiser:
             self.close()
         except Exception:
             pass
+
+
+class ChannelDenoiser:
+    """The paper's pipeline shape (Section 3): a shadow channel and an
+    indirect specular channel denoised separately, each with its own
+    settings and its own adaptive-blur rule (shadow angle for shadows,
+    roughness for reflections), in one batch plan (one launch per pass over
+    both channels), then blended with the noise-free direct light by
+    sv_compose."""
+
+    def __init__(self, height: int, width: int, shadow: FilterConfig = SHADOW,
+                 specular: FilterConfig = SPECULAR, dtype: torch.dtype = torch.float32,
+                 adaptive: bool = True, device: str = "cuda"):
+        self.H, self.W, self.adaptive = height, width, adaptive
+        self.batch = BatchDenoiser([(height, width)] * 2, [shadow, specular], dtype,
+                                   device=device)
+        dev = torch.device(device)
+        self.out = torch.zeros((3, height, width), dtype=dtype, device=dev)
+        self.ctl = [torch.zeros((height, width), dtype=torch.uint8, device=dev) for _ in range(2)]
+        self.shadow_rule = lib.BlurRule(table=False)  # shift above the shadow angle
+        self.spec_rule = lib.BlurRule()               # shift and level table by roughness
+
+    def frame(self, geo: FrameInputs, shadow_rgb: torch.Tensor, spec_rgb: torch.Tensor,
+              direct: torch.Tensor, roughness: Optional[torch.Tensor] = None,
+              shadow_angle: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """geo: the frame's G-buffer and motion (its rgb is not used);
+        shadow_rgb: the one-sample visibility (3, H, W); spec_rgb: the
+        one-sample indirect specular light; direct: the direct light."""
+        ins = [dataclasses.replace(geo, rgb=shadow_rgb, blur_ctl=None),
+               dataclasses.replace(geo, rgb=spec_rgb, blur_ctl=None)]
+        if self.adaptive:
+            lib.sv_blur_control(None, shadow_angle, self.ctl[0], self.shadow_rule, stream=stream)
+            lib.sv_blur_control(roughness, None, self.ctl[1], self.spec_rule, stream=stream)
+            ins[0].blur_ctl, ins[1].blur_ctl = self.ctl
+        shadow_out, spec_out = self.batch.frame(ins, stream=stream)
+        lib.sv_compose(direct, shadow_out, spec_out, self.out, stream=stream)
+        return self.out
+
+    def close(self):
+        self.batch.close()

@@ -56,6 +56,11 @@ class SceneConfig:
     cam_px_per_frame: float = 2.0  # camera translation along its right axis
     yaw_deg_per_frame: float = 0.1  # camera rotation about the world up axis
     n_moving: int = 3  # spheres 0..n_moving-1 move in the image plane
+    # the two channels the paper denoises separately (Section 3): a shadow
+    # channel (one-sample visibility of a light of this angular diameter,
+    # in degrees) and an indirect specular channel
+    channels: bool = False
+    shadow_angle_deg: float = 8.0
     sphere_px_per_frame: float = 5.0
     half: bool = False  # store every input plane as binary16
 
@@ -208,6 +213,61 @@ def _noise(cfg: SceneConfig, frame: int, clean: np.ndarray) -> np.ndarray:
     return clean * e * gain[None]
 
 
+def _disc_overlap(d, r1, r2):
+    """Area of the intersection of two discs of radii r1, r2 whose centres
+    are d apart (all arrays, planar)."""
+    d = np.maximum(d, 1e-12)
+    a1 = np.clip((d * d + r1 * r1 - r2 * r2) / (2.0 * d * r1), -1.0, 1.0)
+    a2 = np.clip((d * d + r2 * r2 - r1 * r1) / (2.0 * d * r2), -1.0, 1.0)
+    k = (-d + r1 + r2) * (d + r1 - r2) * (d - r1 + r2) * (d + r1 + r2)
+    lens = r1 * r1 * np.arccos(a1) + r2 * r2 * np.arccos(a2) - 0.5 * np.sqrt(np.maximum(k, 0.0))
+    inner = np.pi * np.minimum(r1, r2) ** 2
+    return np.where(d >= r1 + r2, 0.0, np.where(d <= np.abs(r1 - r2), inner, lens))
+
+
+def _visibility(cfg, scene, frame, gb) -> np.ndarray:
+    """Fraction of the light's disc (angular diameter shadow_angle_deg
+    around the light direction) seen from each surface point: every sphere
+    other than the point's own covers a disc of angular radius
+    asin(R / distance); the covered fractions combine as independent
+    occluders.  Small-angle (planar) disc geometry."""
+    theta = math.radians(cfg.shadow_angle_deg) / 2.0
+    X, obj = gb["X"], gb["id"]
+    vis = np.ones(obj.shape)
+    for i, S in enumerate(scene.centers(frame)):
+        D = S[:, None, None] - X
+        dist = np.sqrt(np.einsum("ihw,ihw->hw", D, D))
+        beta = np.arcsin(np.clip(scene.radius[i] / np.maximum(dist, 1e-9), 0.0, 1.0))
+        cosd = np.einsum("i,ihw->hw", _LIGHT, D) / np.maximum(dist, 1e-9)
+        delta = np.arccos(np.clip(cosd, -1.0, 1.0))
+        covered = _disc_overlap(delta, np.full_like(delta, theta), beta) / (np.pi * theta * theta)
+        covered = np.where((obj == i + 1) | (dist <= scene.radius[i]), 0.0, covered)
+        vis *= 1.0 - np.clip(covered, 0.0, 1.0)
+    return vis
+
+
+def _specular(cfg, scene, frame, gb) -> np.ndarray:
+    """Indirect specular radiance: a sky gradient seen along the mirror
+    direction, scaled by 0.25 (1 - roughness)."""
+    C, _, _, _ = scene.camera(frame)
+    V = gb["X"] - C[:, None, None]
+    V /= np.sqrt(np.einsum("ihw,ihw->hw", V, V))[None]
+    n = gb["n"]
+    R = V - 2.0 * np.einsum("ihw,ihw->hw", V, n)[None] * n
+    up = np.clip(R[1], 0.0, 1.0)[None]
+    horizon = np.array([0.85, 0.8, 0.75])[:, None, None]
+    zenith = np.array([0.25, 0.45, 0.95])[:, None, None]
+    sky = horizon * (1.0 - up) + zenith * up
+    ks = 0.25 * (1.0 - scene.roughness[gb["id"]].astype(np.float64))
+    return 2.0 * sky * ks[None]
+
+
+def _channel_noise(cfg, frame: int, key: int, shape):
+    """Uniforms of one channel's frame, from their own stream."""
+    return np.random.Generator(
+        np.random.Philox(np.random.SeedSequence([cfg.seed, cfg.stream, frame, 1 << 21, key])))
+
+
 def _assemble(cfg, scene, frame, gb, gb_prev) -> Frame:
     n_dot_l = np.maximum(0.0, np.einsum("i,ihw->hw", _LIGHT, gb["n"]))
     alb = scene.albedo[gb["id"]].transpose(2, 0, 1)  # (3, H, W)
@@ -219,7 +279,7 @@ def _assemble(cfg, scene, frame, gb, gb_prev) -> Frame:
     def q(a):
         return np.ascontiguousarray(a.astype(np.float32).astype(ft))
 
-    return {
+    out = {
         "rgb": q(noisy),
         "clean": np.ascontiguousarray(clean.astype(np.float32)),
         "albedo": q(alb),
@@ -234,6 +294,28 @@ def _assemble(cfg, scene, frame, gb, gb_prev) -> Frame:
         "prev_id": np.ascontiguousarray(gb_prev["id"]),
         "roughness": np.ascontiguousarray(scene.roughness[gb["id"]]),
     }
+    if cfg.channels:
+        H, W = gb["z"].shape
+        vis = _visibility(cfg, scene, frame, gb)
+        # one shadow ray per pixel: a Bernoulli sample of the visibility
+        hit = _channel_noise(cfg, frame, 1, (H, W)).random(size=(H, W)) < vis
+        shadow = np.broadcast_to(hit.astype(np.float64)[None], (3, H, W))
+        spec_clean = _specular(cfg, scene, frame, gb)
+        rs = _channel_noise(cfg, frame, 2, (H, W))
+        e = rs.standard_exponential(size=(3, H, W))
+        fire = rs.random(size=(H, W)) < FIREFLY_P
+        spec = spec_clean * e * (np.where(fire, FIREFLY_GAIN, 1.0) / _NOISE_NORM)[None]
+        out.update({
+            "direct": q(clean),
+            "shadow": q(shadow),
+            "shadow_clean": np.ascontiguousarray(vis.astype(np.float32)),
+            "spec": q(spec),
+            "spec_clean": np.ascontiguousarray(spec_clean.astype(np.float32)),
+            "shadow_angle": np.full((H, W), cfg.shadow_angle_deg, np.float32),
+            "composite_clean": np.ascontiguousarray(
+                (clean * vis[None] + spec_clean).astype(np.float32)),
+        })
+    return out
 
 
 def render_frame(cfg: SceneConfig, frame: int) -> Frame:

@@ -1,0 +1,108 @@
+"""The paper's two-channel pipeline (Section 3): shadow and indirect
+specular channels denoised with their own settings in one batch plan, then
+composed with the direct light.  Against the FP64 oracle (each channel's
+chain with its own parameters and control bytes, then the composition)
+within 1e-5, and bitwise against the channels run one by one."""
+
+from dataclasses import replace
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2312_06827_amd import lib as L
+from paper_2312_06827_amd.pipeline import (SHADOW, SPECULAR, ChannelDenoiser, Denoiser,
+                                           FrameInputs)
+from paper_2312_06827_amd.scene import CONFIGS, sequence, with_size
+from tests._util import rel_err, say
+from tests.test_parity_gpu import dev, empty_like_dev, host
+
+pytestmark = pytest.mark.gpu
+TOL32 = 1e-5
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float16])
+def test_compose(dtype):
+    H, W = 37, 70
+    r = np.random.default_rng(1200)
+    d, s, p = (r.uniform(0, 1, (3, H, W)), r.uniform(0, 1, (3, H, W)), r.uniform(0, 2, (3, H, W)))
+    if dtype == torch.float16:
+        d, s, p = (O.quantize_half(a) for a in (d, s, p))
+    P = W + 6
+    dd, sd, pd = dev(d, P, dtype), dev(s, P, dtype), dev(p, P, dtype)
+    for shadow, spec in [(True, True), (True, False), (False, True), (False, False)]:
+        say(f"compose {dtype} shadow={shadow} spec={spec}")
+        out = empty_like_dev((3, H, W), P, dtype)
+        L.sv_compose(dd, sd if shadow else None, pd if spec else None, out)
+        ref = O.compose(d, s if shadow else None, p if spec else None,
+                        half_out=dtype == torch.float16)
+        tol = TOL32 if dtype == torch.float32 else 2e-3
+        assert rel_err(host(out), ref) <= tol
+    # in place: the output is the direct light's planes
+    L.sv_compose(dd, sd, pd, dd)
+    assert rel_err(host(dd), O.compose(d, s, p, half_out=dtype == torch.float16)) <= (
+        TOL32 if dtype == torch.float32 else 2e-3)
+
+
+def _channel_frames(W=320, H=180, frames=6):
+    cfg = replace(with_size(CONFIGS["hd_motion"], W, H, frames), channels=True)
+    return list(sequence(cfg))
+
+
+@pytest.mark.parametrize("adaptive", [True, False])
+def test_channel_pipeline_matches_oracle(adaptive):
+    frames = _channel_frames()
+    H, W = frames[0]["z"].shape
+    den = ChannelDenoiser(H, W, adaptive=adaptive)
+    ps = O.OracleParams(clamp=True, use_id=True, levels=4)
+    pr = O.OracleParams(clamp=True, tonemap=True, use_id=True, levels=4)
+    ss, sp = O.new_state(H, W), O.new_state(H, W)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    try:
+        for f, fr in enumerate(frames):
+            say(f"channels adaptive={adaptive} frame {f}")
+            out = den.frame(FrameInputs.from_numpy(fr), t(fr["shadow"]), t(fr["spec"]),
+                            t(fr["direct"]), roughness=t(fr["roughness"]),
+                            shadow_angle=t(fr["shadow_angle"]))
+            fs, fp = dict(fr), dict(fr)
+            fs["rgb"], fp["rgb"] = fr["shadow"], fr["spec"]
+            cs = O.blur_control(None, fr["shadow_angle"], table=False) if adaptive else None
+            cp = O.blur_control(fr["roughness"]) if adaptive else None
+            os_, ss, _ = O.run_frame(fs, ss, ps, ctl=cs)
+            op, sp, _ = O.run_frame(fp, sp, pr, ctl=cp)
+            ref = O.compose(fr["direct"], os_, op)
+            e = (rel_err(host(den.batch.streams[0].out), os_),
+                 rel_err(host(den.batch.streams[1].out), op), rel_err(host(out), ref))
+            say(f"  shadow {e[0]:.2e} specular {e[1]:.2e} composite {e[2]:.2e}")
+            assert max(e) <= TOL32, (f, e)
+    finally:
+        den.close()
+
+
+def test_channel_batch_equals_channels_alone():
+    frames = _channel_frames(W=200, H=120, frames=4)
+    H, W = frames[0]["z"].shape
+    den = ChannelDenoiser(H, W)
+    alone = [Denoiser(H, W, SHADOW), Denoiser(H, W, SPECULAR)]
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    try:
+        for f, fr in enumerate(frames):
+            say(f"channel batch vs alone frame {f}")
+            geo = FrameInputs.from_numpy(fr)
+            out = den.frame(geo, t(fr["shadow"]), t(fr["spec"]), t(fr["direct"]),
+                            roughness=t(fr["roughness"]), shadow_angle=t(fr["shadow_angle"]))
+            outs = []
+            for k, (d, key) in enumerate(zip(alone, ("shadow", "spec"))):
+                inp = replace(geo, rgb=t(fr[key]), blur_ctl=den.ctl[k])
+                outs.append(d.frame(inp))
+            direct = t(fr["direct"])
+            ref = torch.empty_like(direct)
+            L.sv_compose(direct, outs[0], outs[1], ref)
+            torch.cuda.synchronize()
+            assert torch.equal(den.batch.streams[0].out, outs[0])
+            assert torch.equal(den.batch.streams[1].out, outs[1])
+            assert torch.equal(out, ref)
+        assert den.batch.passes() == 3 + 2 * 4  # temporal, variance x2, two launches per level
+    finally:
+        den.close()
