@@ -916,10 +916,310 @@ void launch_hv_step(const HvArgs &a, int mode, hipStream_t s) {
     }
 }
 
+// ---- separable level, both passes in one workgroup tile ----------------------
+//
+// The 2D level's tile (64 columns x TY lattice rows of one step phase, the
+// taps' lattice rows and columns staged in LDS) carries both passes: the
+// horizontal pass runs for the TY rows and for the two lattice rows above
+// and below them (the vertical taps); its results, rounded to the storage
+// type exactly as the two-pass form's scratch planes round them, then take
+// the place of the staged colour in LDS, and the vertical pass reads them
+// there.  Every weight, sum and summation order is that of the two passes,
+// so the output is bitwise theirs.  256 threads per tile, so many tiles
+// are resident per CU.
+template <int STEP, int PY, bool WANT_VAR>
+struct SepShape {
+    static constexpr int TX = 64, TY = 4 * PY, HX = 2 * STEP, ROWS = TY + 4;
+    static constexpr int COLS = TX + 2 * HX, PFC = TX + 2;
+    static constexpr int NS = ROWS * COLS, IT = (NS + 255) / 256;
+    static constexpr int NV = WANT_VAR ? ROWS * TX : 0, ITV = (NV + 255) / 256;
+    static constexpr int NP = ROWS * 3 * PFC, ITP = (NP + 255) / 256;
+    static constexpr int NH = ROWS * TX, ITH = (NH + 255) / 256;
+    static_assert(NP >= NH, "the prefilter staging holds the horizontal pass's g afterwards");
+};
+
+// Lattice rows per thread of the separable tile: the largest step keeps
+// four rows so that three tiles fit in a CU's LDS.
+constexpr int sep_py(int step) { return step >= 16 ? 1 : 2; }
+
+template <typename T, int STEP, int PY, int MODE, bool WANT_VAR>
+__device__ __forceinline__ void sep_tile(const AtrousArgs &ah, const AtrousArgs &av, int tile,
+                                         float4 *s_cl, float4 *s_gn, float *s_v, float *s_pf) {
+    using S = SepShape<STEP, PY, WANT_VAR>;
+    constexpr int WM = MODE;  // kUnit or kWeighted
+    const int gxt = (ah.w + S::TX - 1) / S::TX;
+    const TileOrigin t = tile_origin<STEP, S::TY, S::TX>(tile, gxt);
+    // ---- stage: colour, depth and normal of the taps' rows and columns;
+    // the input variance at the tile's own columns; three image rows per
+    // lattice row for the 3x3 variance prefilter
+    {
+        float z[S::IT], r[S::IT], g[S::IT], b[S::IT], nx[S::IT], ny[S::IT], nz[S::IT];
+        bool in[S::IT];
+#pragma unroll
+        for (int it = 0; it < S::IT; ++it) {
+            const int i = threadIdx.x + it * 256;
+            const int row = i / S::COLS, c = i - row * S::COLS;
+            const int gx = t.x0 - S::HX + c, gy = t.ybase + (row - 2) * STEP;
+            in[it] = i < S::NS && gx >= 0 && gx < ah.w && gy >= 0 && gy < ah.h;
+            const uint32_t o = in[it] ? (uint32_t)gy * (uint32_t)ah.pitch + (uint32_t)gx : 0u;
+            z[it] = ldo<T>(ah.z, o);
+            r[it] = ldo<T>(ah.cr, o);
+            g[it] = ldo<T>(ah.cg, o);
+            b[it] = ldo<T>(ah.cb, o);
+            nx[it] = ldo<T>(ah.nx, o);
+            ny[it] = ldo<T>(ah.ny, o);
+            nz[it] = ldo<T>(ah.nz, o);
+        }
+        float v[S::ITV > 0 ? S::ITV : 1];
+        bool vin[S::ITV > 0 ? S::ITV : 1];
+#pragma unroll
+        for (int it = 0; it < S::ITV; ++it) {
+            const int i = threadIdx.x + it * 256;
+            const int row = i / S::TX, c = i - row * S::TX;
+            const int gx = t.x0 + c, gy = t.ybase + (row - 2) * STEP;
+            vin[it] = i < S::NV && gx < ah.w && gy >= 0 && gy < ah.h;
+            v[it] = ldf(ah.var, vin[it] ? (uint32_t)gy * (uint32_t)ah.pitch + (uint32_t)gx : 0u);
+        }
+        float pz[S::ITP], pv[S::ITP];
+        bool pin[S::ITP];
+#pragma unroll
+        for (int it = 0; it < S::ITP; ++it) {
+            const int i = threadIdx.x + it * 256;
+            const int j = i / (3 * S::PFC), rem = i - j * (3 * S::PFC);
+            const int r3 = rem / S::PFC, c = rem - r3 * S::PFC;
+            const int gx = t.x0 - 1 + c, gy = t.ybase + (j - 2) * STEP + r3 - 1;
+            pin[it] = i < S::NP && gx >= 0 && gx < ah.w && gy >= 0 && gy < ah.h;
+            const uint32_t o = pin[it] ? (uint32_t)gy * (uint32_t)ah.pitch + (uint32_t)gx : 0u;
+            pz[it] = ldo<T>(ah.z, o);
+            pv[it] = ldf(ah.var, o);
+        }
+#pragma unroll
+        for (int it = 0; it < S::IT; ++it) {
+            const int i = threadIdx.x + it * 256;
+            if (i < S::NS) {
+                const bool ok = in[it] && !empty_px(z[it]);
+                s_cl[i] = ok ? make_float4(r[it], g[it], b[it], luma(r[it], g[it], b[it]))
+                             : make_float4(0.f, 0.f, 0.f, INFINITY);
+                s_gn[i] = ok ? make_float4(z[it], nx[it], ny[it], nz[it])
+                             : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+        }
+#pragma unroll
+        for (int it = 0; it < S::ITV; ++it) {
+            const int i = threadIdx.x + it * 256;
+            if (i < S::NV) s_v[i] = vin[it] ? v[it] : 0.f;  // masked by emptiness when read
+        }
+#pragma unroll
+        for (int it = 0; it < S::ITP; ++it) {
+            const int i = threadIdx.x + it * 256;
+            if (i < S::NP) s_pf[i] = (pin[it] && !empty_px(pz[it])) ? pv[it] : kNoVar;
+        }
+    }
+    __syncthreads();
+    // ---- horizontal pass for every row of the tile, results in registers
+    float4 hres[S::ITH];
+    float hg[S::ITH];
+#pragma unroll
+    for (int it = 0; it < S::ITH; ++it) {
+        const int k = threadIdx.x + it * 256;
+        hres[it] = make_float4(0.f, 0.f, 0.f, INFINITY);
+        hg[it] = 0.f;
+        if (k >= S::NH) continue;
+        const int row = k / S::TX, lx = k - row * S::TX;
+        const int x = t.x0 + lx, y = t.ybase + (row - 2) * STEP;
+        const int ci = row * S::COLS + lx + S::HX;
+        const float4 pc = s_cl[ci], pg = s_gn[ci];
+        if (x >= ah.w || y < 0 || y >= ah.h || pg.x == 0.f) continue;  // not a tap
+        const uint32_t o = (uint32_t)y * (uint32_t)ah.pitch + (uint32_t)x;
+        float gsum = 0.f, wsum = 0.f;
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+                const float e = s_pf[(row * 3 + dy) * S::PFC + lx + dx];
+                const bool ok = e == e;  // kNoVar: outside or empty
+                const float kk = ok ? kG3[dx] * kG3[dy] : 0.f;
+                gsum = fmaf(kk, ok ? e : 0.f, gsum);
+                wsum += kk;
+            }
+        const float gv = gsum / wsum;
+        hg[it] = gv;
+        float kz[2] = {0.f, 0.f};
+        float kl = 0.f;
+        if (WM != kUnit) {
+            kl = luma_scale(ah, gv, o);
+            const float gx = ldo<T>(ah.dzdx, o) * (float)STEP, gy = 0.f;
+#pragma unroll
+            for (int aa = 1; aa <= 2; ++aa) {
+                const float den = fmaf(ah.sigma_z, fabsf(fmaf(gx, (float)aa, gy * 0.f)), ah.eps_z);
+                kz[aa - 1] = kLog2e * fast_rcp(den);
+            }
+        }
+        constexpr float h0 = 0.375f;
+        Acc acc;
+        acc.sw = h0;
+        acc.sr = h0 * pc.x;
+        acc.sg = h0 * pc.y;
+        acc.sb = h0 * pc.z;
+        acc.sv = 0.f;
+#pragma unroll
+        for (int aa = -2; aa <= 2; ++aa) {
+            if (aa == 0) continue;
+            const int qi = ci + aa * STEP;
+            tap<WM, false>(acc, s_cl[qi], s_gn[qi], 0.f, kLog2H1[aa + 2], kH1[aa + 2],
+                           WM == kUnit ? 0.f : kz[(aa < 0 ? -aa : aa) - 1], pg.x, pc.w, pg.y,
+                           pg.z, pg.w, kl, ah.nc);
+        }
+        const float inv = 1.0f / acc.sw;
+        const float hr = round_to<T>(acc.sr * inv), hgr = round_to<T>(acc.sg * inv),
+                    hb = round_to<T>(acc.sb * inv);
+        hres[it] = make_float4(hr, hgr, hb, luma(hr, hgr, hb));
+    }
+    __syncthreads();
+    // the horizontal results replace the staged colour; g takes the place
+    // of the prefilter rows
+#pragma unroll
+    for (int it = 0; it < S::ITH; ++it) {
+        const int k = threadIdx.x + it * 256;
+        if (k < S::NH) {
+            const int row = k / S::TX, lx = k - row * S::TX;
+            s_cl[row * S::COLS + lx + S::HX] = hres[it];
+            s_pf[k] = hg[it];
+        }
+    }
+    __syncthreads();
+    // ---- vertical pass for the tile's own rows
+    const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
+    const int x = t.x0 + lx;
+    if (x >= av.w) return;
+#pragma unroll 1
+    for (int kk = 0; kk < PY; ++kk) {
+        const int j = ly + 4 * kk, row = j + 2;
+        const int y = t.ybase + j * STEP;
+        if (y >= av.h) break;
+        const uint32_t o = (uint32_t)y * (uint32_t)av.pitch + (uint32_t)x;
+        if (av.ctl) {  // uniform branch
+            const int sel = ctl_select(av, o);
+            if (sel != 1) {
+                if (sel == 2) copy_through<T>(av, o);
+                continue;
+            }
+        }
+        const int ci = row * S::COLS + lx + S::HX;
+        const float4 cen = s_cl[ci], cg = s_gn[ci];
+        if (cg.x == 0.f) {  // empty pixel: its input colour passes through
+            write_out<T>(av, o, ldo<T>(ah.cr, o), ldo<T>(ah.cg, o), ldo<T>(ah.cb, o));
+            if (av.var_out) stf(av.var_out, o, 0.f);
+            continue;
+        }
+        const float gv = s_pf[row * S::TX + lx];
+        float kz[2] = {0.f, 0.f};
+        float kl = 0.f;
+        if (WM != kUnit) {
+            kl = luma_scale(av, gv, o);
+            const float gx = 0.f, gy = ldo<T>(av.dzdy, o) * (float)STEP;
+#pragma unroll
+            for (int b = 1; b <= 2; ++b) {
+                const float den = fmaf(av.sigma_z, fabsf(fmaf(gx, 0.f, gy * (float)b)), av.eps_z);
+                kz[b - 1] = kLog2e * fast_rcp(den);
+            }
+        }
+        constexpr float h0 = 0.375f;
+        Acc acc;
+        acc.sw = h0;
+        acc.sr = h0 * cen.x;
+        acc.sg = h0 * cen.y;
+        acc.sb = h0 * cen.z;
+        acc.sv = WANT_VAR ? h0 * h0 * s_v[row * S::TX + lx] : 0.f;
+#pragma unroll
+        for (int b = -2; b <= 2; ++b) {
+            if (b == 0) continue;
+            const int q = ci + b * S::COLS;
+            const float4 qg = s_gn[q];
+            const float qv = WANT_VAR ? (qg.x == 0.f ? 0.f : s_v[(row + b) * S::TX + lx]) : 0.f;
+            tap<WM, WANT_VAR>(acc, s_cl[q], qg, qv, kLog2H1[b + 2], kH1[b + 2],
+                              WM == kUnit ? 0.f : kz[(b < 0 ? -b : b) - 1], cg.x, cen.w, cg.y,
+                              cg.z, cg.w, kl, av.nc);
+        }
+        const float inv = 1.0f / acc.sw;
+        write_out<T>(av, o, acc.sr * inv, acc.sg * inv, acc.sb * inv);
+        if (WANT_VAR) stf(av.var_out, o, acc.sv * inv * inv);
+    }
+}
+
+template <typename T, int STEP, int PY, int MODE, bool WANT_VAR>
+__global__ __launch_bounds__(256) void atrous_sept_k(HvArgs a, int tiles) {
+    using S = SepShape<STEP, PY, WANT_VAR>;
+    __shared__ float4 s_cl[S::NS];
+    __shared__ float4 s_gn[S::NS];
+    __shared__ float s_v[S::NV > 0 ? S::NV : 1];
+    __shared__ float s_pf[S::NP];
+    const int t = xcd_tile(tiles);
+    if (t < 0) return;
+    sep_tile<T, STEP, PY, MODE, WANT_VAR>(a.h, a.v, t, s_cl, s_gn, s_v, s_pf);
+}
+
+template <typename T, int STEP, int PY, int MODE, bool WANT_VAR>
+__global__ __launch_bounds__(256) void atrous_sept_batch_k(const HvArgs *args, const int *prefix,
+                                                           int n, int total) {
+    using S = SepShape<STEP, PY, WANT_VAR>;
+    __shared__ float4 s_cl[S::NS];
+    __shared__ float4 s_gn[S::NS];
+    __shared__ float s_v[S::NV > 0 ? S::NV : 1];
+    __shared__ float s_pf[S::NP];
+    int s = 0;
+    const int lt = batch_tile(prefix, n, total, s);
+    if (lt < 0) return;
+    const HvArgs a = args[s];  // a copy: the kernel's stores cannot alias it
+    sep_tile<T, STEP, PY, MODE, WANT_VAR>(a.h, a.v, lt, s_cl, s_gn, s_v, s_pf);
+}
+
+template <typename T, int STEP, int PY, int MODE, bool WANT_VAR>
+void sept_batch_launch(const void *args, const int *prefix, int n, int total, hipStream_t s) {
+    hipLaunchKernelGGL((atrous_sept_batch_k<T, STEP, PY, MODE, WANT_VAR>), dim3(xcd_grid(total)),
+                       dim3(256), 0, s, (const HvArgs *)args, prefix, n, total);
+}
+
+template <typename T, int STEP, int MODE, bool WANT_VAR>
+void launch_sept_mode(const HvArgs &a, hipStream_t s) {
+    constexpr int PY = sep_py(STEP), TY = 4 * PY;
+    const int bands = (a.h.h + STEP * TY - 1) / (STEP * TY);
+    const int tiles = ((a.h.w + 63) / 64) * bands * STEP;
+    if (record_pass(&sept_batch_launch<T, STEP, PY, MODE, WANT_VAR>, a, tiles)) return;
+    hipLaunchKernelGGL((atrous_sept_k<T, STEP, PY, MODE, WANT_VAR>), dim3(xcd_grid(tiles)),
+                       dim3(256), 0, s, a, tiles);
+}
+
+template <typename T, int STEP>
+void launch_sept_step(const HvArgs &a, bool unit, hipStream_t s) {
+    const bool wv = a.v.var_out != nullptr;
+    if (unit) {
+        if (wv) launch_sept_mode<T, STEP, kUnit, true>(a, s);
+        else launch_sept_mode<T, STEP, kUnit, false>(a, s);
+    } else {
+        if (wv) launch_sept_mode<T, STEP, kWeighted, true>(a, s);
+        else launch_sept_mode<T, STEP, kWeighted, false>(a, s);
+    }
+}
+
+#ifndef SV_SEP_RING
+#define SV_SEP_RING 0
+#endif
+
 // Fused separable level; false when the step has no fused form (then the
 // two passes run through a scratch buffer).
 template <typename T>
 bool launch_hv(const HvArgs &a, bool unit, hipStream_t s) {
+    if (!SV_SEP_RING) {
+        switch (a.h.step) {
+        case 1: launch_sept_step<T, 1>(a, unit, s); return true;
+        case 2: launch_sept_step<T, 2>(a, unit, s); return true;
+        case 4: launch_sept_step<T, 4>(a, unit, s); return true;
+        case 8: launch_sept_step<T, 8>(a, unit, s); return true;
+        case 16: launch_sept_step<T, 16>(a, unit, s); return true;
+        default: return false;
+        }
+    }
     const int mode = (unit ? 0 : 1) | (a.v.var_out ? 2 : 0);
     switch (a.h.step) {
     case 1: launch_hv_step<T, 1>(a, mode, s); return true;
