@@ -219,25 +219,40 @@ def _timed_frames(torch, fn, frames, warmup):
 
 UHD_WARMUP, UHD_STEPS = 4, 10
 BATCH_WARMUP, BATCH_STEPS = 3, 5
+CH_WARMUP, CH_STEPS = 5, 15
 
 
-def generate_variant_frames(workers):
-    """Host frames of the 4K and sixteen-stream variants (generated before
-    the GPU is touched, like the headline frames)."""
+def generate_variant_frames(workers, want):
+    """Host frames of the 4K, sixteen-stream and two-channel variants
+    (generated before the GPU is touched, like the headline frames)."""
     from paper_2312_06827_amd.scene import batched_configs
     uhd = CONFIGS["uhd_half"]
     uhd = type(uhd)(**{**uhd.__dict__, "frames": UHD_WARMUP + UHD_STEPS})
     n = BATCH_WARMUP + BATCH_STEPS
     scfg = batched_configs(16, n, half=True)
-    jobs = [(uhd, f) for f in range(uhd.frames)] + [(c, f) for f in range(n) for c in scfg]
+    ch = type(WORKLOAD)(**{**WORKLOAD.__dict__, "frames": CH_WARMUP + CH_STEPS, "channels": True})
+    jobs = []
+    if "uhd_half" in want:
+        jobs += [(uhd, f) for f in range(uhd.frames)]
+    if "batched" in want:
+        jobs += [(c, f) for f in range(n) for c in scfg]
+    if "channels" in want:
+        jobs += [(ch, f) for f in range(ch.frames)]
     if workers <= 1:
         out = [_render(j) for j in jobs]
     else:
         with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork")) as ex:
             out = list(ex.map(_render, jobs))
-    k = uhd.frames
-    return {"uhd": out[:k], "batch_cfg": scfg,
-            "batch": [out[k + f * 16:k + (f + 1) * 16] for f in range(n)]}
+    res, k = {}, 0
+    if "uhd_half" in want:
+        res["uhd"], k = out[:uhd.frames], uhd.frames
+    if "batched" in want:
+        res["batch_cfg"] = scfg
+        res["batch"] = [out[k + f * 16:k + (f + 1) * 16] for f in range(n)]
+        k += 16 * n
+    if "channels" in want:
+        res["channels"] = out[k:k + ch.frames]
+    return res
 
 
 def variant_uhd_half(torch, frames_np, warmup=UHD_WARMUP, steps=UHD_STEPS):
@@ -360,6 +375,45 @@ def variant_scene_features(torch, frames_np, warmup, steps):
     return out
 
 
+def variant_channels(torch, frames_np, warmup=CH_WARMUP, steps=CH_STEPS):
+    """The paper's pipeline shape (Section 3): a shadow channel and an
+    indirect specular channel, each filtered with its own settings and
+    adaptive-blur rule in one batch plan, then composed with the direct
+    light.  Throughput (pixels of the composed frame per second) and
+    RelMSE of the composite against the clean one, with and without the
+    adaptive blur; the plain single-channel filter of the composite's
+    noisy estimate is reported beside it."""
+    from paper_2312_06827_amd import learn
+    from paper_2312_06827_amd.pipeline import ChannelDenoiser, Denoiser, FrameInputs, MOTION
+    H, W = WORKLOAD.height, WORKLOAD.width
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    geo = [FrameInputs.from_numpy(fr) for fr in frames_np]
+    planes = [{k: t(fr[k]) for k in ("shadow", "spec", "direct", "roughness", "shadow_angle")}
+              for fr in frames_np]
+    clean = [t(fr["composite_clean"]) for fr in frames_np]
+    out = {"config": f"{W}x{H}, two channels, {steps} frames timed after {warmup}"}
+    for adaptive in (True, False):
+        den = ChannelDenoiser(H, W, adaptive=adaptive)
+        step = lambda i: den.frame(geo[i], planes[i]["shadow"], planes[i]["spec"],
+                                   planes[i]["direct"], roughness=planes[i]["roughness"],
+                                   shadow_angle=planes[i]["shadow_angle"])
+        ms = _timed_frames(torch, step, list(range(len(geo))), warmup)
+        den.close()
+        den = ChannelDenoiser(H, W, adaptive=adaptive)
+        q = float(np.mean([learn.relmse(step(i), clean[i]) for i in range(len(geo))][warmup:]))
+        den.close()
+        out["adaptive" if adaptive else "fixed"] = {
+            "value": round(H * W / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 4),
+            "relmse": round(q, 6)}
+    # one filter over the noisy composite (direct * shadow sample + specular sample)
+    comp = [FrameInputs.from_numpy({**fr, "rgb": fr["direct"] * fr["shadow"] + fr["spec"]})
+            for fr in frames_np]
+    den = Denoiser(H, W, MOTION)
+    q = float(np.mean([learn.relmse(den.frame(c), clean[i]) for i, c in enumerate(comp)][warmup:]))
+    out["one_filter_relmse"] = round(q, 6)
+    return out
+
+
 def cpu_baseline(frames_np, warm, timed):
     """The oracle as it stands, on the host cores, on a bounded sample."""
     import oracle as O
@@ -387,7 +441,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
-    ap.add_argument("--variants", default="separable,uhd_half,batched,scene_features,learned",
+    ap.add_argument("--variants",
+                    default="separable,uhd_half,batched,scene_features,channels,learned",
                     help="comma-separated variants to run after the headline chain")
     ap.add_argument("--tune", action="store_true",
                     help="a-trous launch shapes from the autotuner (timed before the run)"
@@ -403,7 +458,8 @@ def main():
     t0 = time.perf_counter()
     frames_np = generate(WORKLOAD, n_frames, args.workers)  # before any GPU call (fork)
     want = set() if args.no_variants else set(v for v in args.variants.split(",") if v)
-    vframes = generate_variant_frames(args.workers) if want & {"uhd_half", "batched"} else None
+    vframes = (generate_variant_frames(args.workers, want)
+               if want & {"uhd_half", "batched", "channels"} else None)
     gen_s = time.perf_counter() - t0
     print(f"# generated {n_frames} frames in {gen_s:.1f} s", file=sys.stderr, flush=True)
 
@@ -480,6 +536,9 @@ def main():
         variants["batched"] = variant_batched(torch, vframes["batch_cfg"], vframes["batch"])
         print(f"# 16 streams batched: {variants['batched']['ms_per_step'] * 1e3:.1f} us/frame",
               file=sys.stderr, flush=True)
+    if "channels" in want:
+        variants["channels"] = variant_channels(torch, vframes["channels"])
+        print(f"# channels: {variants['channels']}", file=sys.stderr, flush=True)
     if "scene_features" in want:
         variants["scene_features"] = variant_scene_features(torch, frames_np, args.warmup,
                                                             args.steps)

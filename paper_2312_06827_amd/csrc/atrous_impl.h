@@ -37,6 +37,8 @@ struct AtrousArgs {
 // Weight modes: every edge weight 1 (plain B3), or the full edge weights.
 enum { kUnit = 0, kWeighted = 1 };
 
+constexpr int kCUs = 256;
+
 // log2 of the B3-spline taps (1, 4, 6, 4, 1) / 16
 __device__ constexpr float kLog2H1[5] = {-4.0f, -2.0f, -1.4150374992788438f, -2.0f, -4.0f};
 __device__ constexpr float kH1[5] = {0.0625f, 0.25f, 0.375f, 0.25f, 0.0625f};
@@ -940,82 +942,100 @@ struct SepShape {
 
 // Lattice rows per thread of the separable tile: the largest step keeps
 // four rows so that three tiles fit in a CU's LDS.
-constexpr int sep_py(int step) { return step >= 16 ? 1 : 2; }
+#ifndef SV_SEP_PY16
+#define SV_SEP_PY16 1
+#endif
+#ifndef SV_SEP_PY
+#define SV_SEP_PY 2
+#endif
+constexpr int sep_py(int step) { return step >= 16 ? SV_SEP_PY16 : SV_SEP_PY; }
 
-template <typename T, int STEP, int PY, int MODE, bool WANT_VAR>
-__device__ __forceinline__ void sep_tile(const AtrousArgs &ah, const AtrousArgs &av, int tile,
-                                         float4 *s_cl, float4 *s_gn, float *s_v, float *s_pf) {
-    using S = SepShape<STEP, PY, WANT_VAR>;
-    constexpr int WM = MODE;  // kUnit or kWeighted
-    const int gxt = (ah.w + S::TX - 1) / S::TX;
-    const TileOrigin t = tile_origin<STEP, S::TY, S::TX>(tile, gxt);
-    // ---- stage: colour, depth and normal of the taps' rows and columns;
-    // the input variance at the tile's own columns; three image rows per
-    // lattice row for the 3x3 variance prefilter
-    {
-        float z[S::IT], r[S::IT], g[S::IT], b[S::IT], nx[S::IT], ny[S::IT], nz[S::IT];
-        bool in[S::IT];
+// Raw loads of one separable tile, held between issue and LDS store.
+template <class S>
+struct SepRegs {
+    float z[S::IT], r[S::IT], g[S::IT], b[S::IT], nx[S::IT], ny[S::IT], nz[S::IT];
+    bool in[S::IT];
+    float v[S::ITV > 0 ? S::ITV : 1];
+    bool vin[S::ITV > 0 ? S::ITV : 1];
+    float pz[S::ITP], pv[S::ITP];
+    bool pin[S::ITP];
+};
+
+// Issue the tile's loads: colour, depth and normal of the taps' rows and
+// columns; the input variance at the tile's own columns; three image rows
+// per lattice row for the 3x3 variance prefilter.
+template <typename T, int STEP, class S>
+__device__ __forceinline__ void sep_issue(const AtrousArgs &ah, TileOrigin t, SepRegs<S> &q) {
 #pragma unroll
-        for (int it = 0; it < S::IT; ++it) {
-            const int i = threadIdx.x + it * 256;
-            const int row = i / S::COLS, c = i - row * S::COLS;
-            const int gx = t.x0 - S::HX + c, gy = t.ybase + (row - 2) * STEP;
-            in[it] = i < S::NS && gx >= 0 && gx < ah.w && gy >= 0 && gy < ah.h;
-            const uint32_t o = in[it] ? (uint32_t)gy * (uint32_t)ah.pitch + (uint32_t)gx : 0u;
-            z[it] = ldo<T>(ah.z, o);
-            r[it] = ldo<T>(ah.cr, o);
-            g[it] = ldo<T>(ah.cg, o);
-            b[it] = ldo<T>(ah.cb, o);
-            nx[it] = ldo<T>(ah.nx, o);
-            ny[it] = ldo<T>(ah.ny, o);
-            nz[it] = ldo<T>(ah.nz, o);
-        }
-        float v[S::ITV > 0 ? S::ITV : 1];
-        bool vin[S::ITV > 0 ? S::ITV : 1];
+    for (int it = 0; it < S::IT; ++it) {
+        const int i = threadIdx.x + it * 256;
+        const int row = i / S::COLS, c = i - row * S::COLS;
+        const int gx = t.x0 - S::HX + c, gy = t.ybase + (row - 2) * STEP;
+        q.in[it] = i < S::NS && gx >= 0 && gx < ah.w && gy >= 0 && gy < ah.h;
+        const uint32_t o = q.in[it] ? (uint32_t)gy * (uint32_t)ah.pitch + (uint32_t)gx : 0u;
+        q.z[it] = ldo<T>(ah.z, o);
+        q.r[it] = ldo<T>(ah.cr, o);
+        q.g[it] = ldo<T>(ah.cg, o);
+        q.b[it] = ldo<T>(ah.cb, o);
+        q.nx[it] = ldo<T>(ah.nx, o);
+        q.ny[it] = ldo<T>(ah.ny, o);
+        q.nz[it] = ldo<T>(ah.nz, o);
+    }
 #pragma unroll
-        for (int it = 0; it < S::ITV; ++it) {
-            const int i = threadIdx.x + it * 256;
-            const int row = i / S::TX, c = i - row * S::TX;
-            const int gx = t.x0 + c, gy = t.ybase + (row - 2) * STEP;
-            vin[it] = i < S::NV && gx < ah.w && gy >= 0 && gy < ah.h;
-            v[it] = ldf(ah.var, vin[it] ? (uint32_t)gy * (uint32_t)ah.pitch + (uint32_t)gx : 0u);
-        }
-        float pz[S::ITP], pv[S::ITP];
-        bool pin[S::ITP];
+    for (int it = 0; it < S::ITV; ++it) {
+        const int i = threadIdx.x + it * 256;
+        const int row = i / S::TX, c = i - row * S::TX;
+        const int gx = t.x0 + c, gy = t.ybase + (row - 2) * STEP;
+        q.vin[it] = i < S::NV && gx < ah.w && gy >= 0 && gy < ah.h;
+        q.v[it] = ldf(ah.var, q.vin[it] ? (uint32_t)gy * (uint32_t)ah.pitch + (uint32_t)gx : 0u);
+    }
 #pragma unroll
-        for (int it = 0; it < S::ITP; ++it) {
-            const int i = threadIdx.x + it * 256;
-            const int j = i / (3 * S::PFC), rem = i - j * (3 * S::PFC);
-            const int r3 = rem / S::PFC, c = rem - r3 * S::PFC;
-            const int gx = t.x0 - 1 + c, gy = t.ybase + (j - 2) * STEP + r3 - 1;
-            pin[it] = i < S::NP && gx >= 0 && gx < ah.w && gy >= 0 && gy < ah.h;
-            const uint32_t o = pin[it] ? (uint32_t)gy * (uint32_t)ah.pitch + (uint32_t)gx : 0u;
-            pz[it] = ldo<T>(ah.z, o);
-            pv[it] = ldf(ah.var, o);
-        }
+    for (int it = 0; it < S::ITP; ++it) {
+        const int i = threadIdx.x + it * 256;
+        const int j = i / (3 * S::PFC), rem = i - j * (3 * S::PFC);
+        const int r3 = rem / S::PFC, c = rem - r3 * S::PFC;
+        const int gx = t.x0 - 1 + c, gy = t.ybase + (j - 2) * STEP + r3 - 1;
+        q.pin[it] = i < S::NP && gx >= 0 && gx < ah.w && gy >= 0 && gy < ah.h;
+        const uint32_t o = q.pin[it] ? (uint32_t)gy * (uint32_t)ah.pitch + (uint32_t)gx : 0u;
+        q.pz[it] = ldo<T>(ah.z, o);
+        q.pv[it] = ldf(ah.var, o);
+    }
+}
+
+template <class S>
+__device__ __forceinline__ void sep_store(const SepRegs<S> &q, float4 *s_cl, float4 *s_gn,
+                                          float *s_v, float *s_pf) {
 #pragma unroll
-        for (int it = 0; it < S::IT; ++it) {
-            const int i = threadIdx.x + it * 256;
-            if (i < S::NS) {
-                const bool ok = in[it] && !empty_px(z[it]);
-                s_cl[i] = ok ? make_float4(r[it], g[it], b[it], luma(r[it], g[it], b[it]))
-                             : make_float4(0.f, 0.f, 0.f, INFINITY);
-                s_gn[i] = ok ? make_float4(z[it], nx[it], ny[it], nz[it])
-                             : make_float4(0.f, 0.f, 0.f, 0.f);
-            }
-        }
-#pragma unroll
-        for (int it = 0; it < S::ITV; ++it) {
-            const int i = threadIdx.x + it * 256;
-            if (i < S::NV) s_v[i] = vin[it] ? v[it] : 0.f;  // masked by emptiness when read
-        }
-#pragma unroll
-        for (int it = 0; it < S::ITP; ++it) {
-            const int i = threadIdx.x + it * 256;
-            if (i < S::NP) s_pf[i] = (pin[it] && !empty_px(pz[it])) ? pv[it] : kNoVar;
+    for (int it = 0; it < S::IT; ++it) {
+        const int i = threadIdx.x + it * 256;
+        if (i < S::NS) {
+            const bool ok = q.in[it] && !empty_px(q.z[it]);
+            s_cl[i] = ok ? make_float4(q.r[it], q.g[it], q.b[it], luma(q.r[it], q.g[it], q.b[it]))
+                         : make_float4(0.f, 0.f, 0.f, INFINITY);
+            s_gn[i] = ok ? make_float4(q.z[it], q.nx[it], q.ny[it], q.nz[it])
+                         : make_float4(0.f, 0.f, 0.f, 0.f);
         }
     }
-    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < S::ITV; ++it) {
+        const int i = threadIdx.x + it * 256;
+        if (i < S::NV) s_v[i] = q.vin[it] ? q.v[it] : 0.f;  // masked by emptiness when read
+    }
+#pragma unroll
+    for (int it = 0; it < S::ITP; ++it) {
+        const int i = threadIdx.x + it * 256;
+        if (i < S::NP) s_pf[i] = (q.pin[it] && !empty_px(q.pz[it])) ? q.pv[it] : kNoVar;
+    }
+}
+
+// Both passes of a staged tile (the caller's barrier after sep_store has
+// been passed); returns with the LDS still in use by other threads.
+template <typename T, int STEP, int PY, int MODE, bool WANT_VAR>
+__device__ __forceinline__ void sep_compute(const AtrousArgs &ah, const AtrousArgs &av,
+                                            TileOrigin t, float4 *s_cl, const float4 *s_gn,
+                                            const float *s_v, float *s_pf) {
+    using S = SepShape<STEP, PY, WANT_VAR>;
+    constexpr int WM = MODE;  // kUnit or kWeighted
     // ---- horizontal pass for every row of the tile, results in registers
     float4 hres[S::ITH];
     float hg[S::ITH];
@@ -1147,16 +1167,42 @@ __device__ __forceinline__ void sep_tile(const AtrousArgs &ah, const AtrousArgs 
     }
 }
 
-template <typename T, int STEP, int PY, int MODE, bool WANT_VAR>
-__global__ __launch_bounds__(256) void atrous_sept_k(HvArgs a, int tiles) {
+// One tile per workgroup, or (PERSIST) a strided run of tiles of this
+// workgroup's XCD range with the next tile's loads in flight while the
+// current one is computed.
+template <typename T, int STEP, int PY, int MODE, bool WANT_VAR, bool PERSIST>
+__global__ __launch_bounds__(256) void atrous_sept_k(HvArgs a, int tiles, int per_xcd) {
     using S = SepShape<STEP, PY, WANT_VAR>;
     __shared__ float4 s_cl[S::NS];
     __shared__ float4 s_gn[S::NS];
     __shared__ float s_v[S::NV > 0 ? S::NV : 1];
     __shared__ float s_pf[S::NP];
-    const int t = xcd_tile(tiles);
-    if (t < 0) return;
-    sep_tile<T, STEP, PY, MODE, WANT_VAR>(a.h, a.v, t, s_cl, s_gn, s_v, s_pf);
+    const int gxt = (a.h.w + S::TX - 1) / S::TX;
+    const int xcd = (int)blockIdx.x % kXCD, slot = (int)blockIdx.x / kXCD;
+    const int nslot = (int)gridDim.x / kXCD;
+    const int first = xcd * per_xcd, last = min(tiles, first + per_xcd);
+    int t = first + slot;
+    if (t >= last) return;
+    SepRegs<S> q;
+    sep_issue<T, STEP, S>(a.h, tile_origin<STEP, S::TY, S::TX>(t, gxt), q);
+    sep_store<S>(q, s_cl, s_gn, s_v, s_pf);
+    __syncthreads();
+    if (!PERSIST) {
+        sep_compute<T, STEP, PY, MODE, WANT_VAR>(a.h, a.v, tile_origin<STEP, S::TY, S::TX>(t, gxt),
+                                                 s_cl, s_gn, s_v, s_pf);
+        return;
+    }
+    for (;;) {
+        const int tn = t + nslot;
+        if (tn < last) sep_issue<T, STEP, S>(a.h, tile_origin<STEP, S::TY, S::TX>(tn, gxt), q);
+        sep_compute<T, STEP, PY, MODE, WANT_VAR>(a.h, a.v, tile_origin<STEP, S::TY, S::TX>(t, gxt),
+                                                 s_cl, s_gn, s_v, s_pf);
+        if (tn >= last) break;
+        __syncthreads();
+        sep_store<S>(q, s_cl, s_gn, s_v, s_pf);
+        __syncthreads();
+        t = tn;
+    }
 }
 
 template <typename T, int STEP, int PY, int MODE, bool WANT_VAR>
@@ -1171,7 +1217,12 @@ __global__ __launch_bounds__(256) void atrous_sept_batch_k(const HvArgs *args, c
     const int lt = batch_tile(prefix, n, total, s);
     if (lt < 0) return;
     const HvArgs a = args[s];  // a copy: the kernel's stores cannot alias it
-    sep_tile<T, STEP, PY, MODE, WANT_VAR>(a.h, a.v, lt, s_cl, s_gn, s_v, s_pf);
+    const TileOrigin o = tile_origin<STEP, S::TY, S::TX>(lt, (a.h.w + S::TX - 1) / S::TX);
+    SepRegs<S> q;
+    sep_issue<T, STEP, S>(a.h, o, q);
+    sep_store<S>(q, s_cl, s_gn, s_v, s_pf);
+    __syncthreads();
+    sep_compute<T, STEP, PY, MODE, WANT_VAR>(a.h, a.v, o, s_cl, s_gn, s_v, s_pf);
 }
 
 template <typename T, int STEP, int PY, int MODE, bool WANT_VAR>
@@ -1180,14 +1231,25 @@ void sept_batch_launch(const void *args, const int *prefix, int n, int total, hi
                        dim3(256), 0, s, (const HvArgs *)args, prefix, n, total);
 }
 
+#ifndef SV_SEP_PERSIST_BPC
+#define SV_SEP_PERSIST_BPC 0
+#endif
+
 template <typename T, int STEP, int MODE, bool WANT_VAR>
 void launch_sept_mode(const HvArgs &a, hipStream_t s) {
     constexpr int PY = sep_py(STEP), TY = 4 * PY;
     const int bands = (a.h.h + STEP * TY - 1) / (STEP * TY);
     const int tiles = ((a.h.w + 63) / 64) * bands * STEP;
+    const int per_xcd = (tiles + kXCD - 1) / kXCD;
     if (record_pass(&sept_batch_launch<T, STEP, PY, MODE, WANT_VAR>, a, tiles)) return;
-    hipLaunchKernelGGL((atrous_sept_k<T, STEP, PY, MODE, WANT_VAR>), dim3(xcd_grid(tiles)),
-                       dim3(256), 0, s, a, tiles);
+    if (SV_SEP_PERSIST_BPC > 0) {
+        const int slots = min(per_xcd, kCUs / kXCD * SV_SEP_PERSIST_BPC);
+        hipLaunchKernelGGL((atrous_sept_k<T, STEP, PY, MODE, WANT_VAR, true>), dim3(slots * kXCD),
+                           dim3(256), 0, s, a, tiles, per_xcd);
+    } else {
+        hipLaunchKernelGGL((atrous_sept_k<T, STEP, PY, MODE, WANT_VAR, false>),
+                           dim3(per_xcd * kXCD), dim3(256), 0, s, a, tiles, per_xcd);
+    }
 }
 
 template <typename T, int STEP>
@@ -1232,8 +1294,6 @@ bool launch_hv(const HvArgs &a, bool unit, hipStream_t s) {
 }
 
 // ---- launch ---------------------------------------------------------------------
-
-constexpr int kCUs = 256;
 
 // Launch-time tile configuration (autotuned by the caller, or the defaults).
 struct TileCfg {
