@@ -172,11 +172,9 @@ constexpr float kNoVar = __builtin_nanf("");
 
 // Lattice rows per thread of a tile: two, except at the largest step, where
 // the 2 x 16-column halo on each side would otherwise hold the tile's LDS
-// footprint to two resident workgroups per CU.
-#ifndef SV_PY1_FROM_STEP
-#define SV_PY1_FROM_STEP 16
-#endif
-constexpr int tile_py(int step) { return step >= SV_PY1_FROM_STEP ? 1 : 2; }
+// footprint to two resident workgroups per CU (measured: 53 instead of 74
+// us per 1080p level; one row per thread at step 8 gained nothing).
+constexpr int tile_py(int step) { return step >= 16 ? 1 : 2; }
 
 template <int STEP, int PY, int DIR, bool WANT_VAR>
 struct TileShape {
@@ -596,21 +594,19 @@ __global__ __launch_bounds__(256) void atrous_sep_k(AtrousArgs a) {
 //
 // One wave owns 64 columns and walks kHvRows + 4 lattice rows of one step
 // phase (image rows ph + j * STEP).  Each row is staged once in LDS for the
-// horizontal pass; the horizontal results of the last five rows live in a
-// register ring (slot = row mod 5, static after unrolling by five), which
-// is exactly the vertical pass's 5-tap window for the row two behind.  The
+// horizontal pass, its loads issued two rows ahead; the horizontal results
+// of the last five rows live in a register ring (slot = row mod 5, static
+// after unrolling by ten), which is exactly the vertical pass's 5-tap
+// window for the row two behind.  (A 256-thread tile form with both passes
+// in LDS, one or two lattice rows per thread and a persistent prefetching
+// variant all measured 5-30 % slower than this walker.)  The
 // horizontal result is rounded to the storage type as the scratch planes
 // of the two-pass form would round it, and every weight, sum and order is
 // that of the two passes, so the output is bitwise theirs.  The level
 // reads the G-buffer and colour once and writes only its outputs.
-#ifndef SV_HV_ROWS
-#define SV_HV_ROWS 16
-#endif
-#ifndef SV_HV_WAVES_PER_EU
-#define SV_HV_WAVES_PER_EU 1
-#endif
-constexpr int kHvRows = SV_HV_ROWS;
-static_assert((kHvRows + 4) % 5 == 0, "rows per tile must fill the five-slot ring");
+constexpr int kHvRows = 16;
+static_assert((kHvRows + 4) % 10 == 0,
+              "rows per tile must fill the five-slot ring and the two load buffers");
 
 template <int STEP>
 struct HvShape {
@@ -718,14 +714,15 @@ __device__ __forceinline__ void hv_row(const AtrousArgs &ah, const AtrousArgs &a
     const int lx = threadIdx.x, x = x0 + lx;
     const int r = ro + SLOT;  // row index within the tile
     const int y = ph + (j0 - 2 + r) * STEP;
-    // stage this row, then start loading the next
+    // stage this row (its loads were issued two rows ago), then start
+    // loading the row after next into the same registers
     __syncthreads();
     hv_store<STEP>(q, s_cl, s_gn, s_pf);
     __syncthreads();
     const float dzdx = q.dzdx, dzdy = q.dzdy, kap = q.kap;
-    if (r + 1 < S::ROWS) hv_issue<T, STEP>(ah, x0, ph + (j0 - 1 + r) * STEP, q);
+    if (r + 2 < S::ROWS) hv_issue<T, STEP>(ah, x0, ph + (j0 + r) * STEP, q);
     // ---- horizontal pass at (x, y) ----
-    HvSlot &cur = ring[SLOT];
+    HvSlot &cur = ring[SLOT % 5];
     const int ci = lx + S::HX;
     const float4 pc = s_cl[ci], pg = s_gn[ci];
     cur.gn = pg;
@@ -788,7 +785,7 @@ __device__ __forceinline__ void hv_row(const AtrousArgs &ah, const AtrousArgs &a
     }
     // ---- vertical pass for the row two behind ----
     if (r < 4) return;
-    constexpr int CS = (SLOT + 3) % 5;  // centre: row r - 2
+    constexpr int CS = (SLOT + 3) % 5;  // centre: row r - 2 (slot (r - 2) mod 5)
     const HvSlot &cen = ring[CS];
     const int yc = ph + (j0 - 4 + r) * STEP;
     if (x >= av.w || yc >= av.h) return;
@@ -857,20 +854,28 @@ __device__ __forceinline__ void hv_tile(const HvArgs &a, int t, float4 *s_cl, fl
     const int ph = rest % STEP, band = rest / STEP;
     const int x0 = cx * 64, j0 = band * kHvRows;
     HvSlot ring[5];
-    HvRow<STEP> q;
-    hv_issue<T, STEP>(a.h, x0, ph + (j0 - 2) * STEP, q);
+    HvRow<STEP> q0, q1;  // even and odd rows' loads, two rows in flight
+    hv_issue<T, STEP>(a.h, x0, ph + (j0 - 2) * STEP, q0);
+    hv_issue<T, STEP>(a.h, x0, ph + (j0 - 1) * STEP, q1);
+    // ten rows per iteration: each ring slot and each load buffer a fixed
+    // register set
 #pragma unroll 1
-    for (int ro = 0; ro < S::ROWS; ro += 5) {  // five rows: each ring slot a fixed register set
-        hv_row<T, STEP, MODE, 0>(a.h, a.v, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q);
-        hv_row<T, STEP, MODE, 1>(a.h, a.v, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q);
-        hv_row<T, STEP, MODE, 2>(a.h, a.v, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q);
-        hv_row<T, STEP, MODE, 3>(a.h, a.v, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q);
-        hv_row<T, STEP, MODE, 4>(a.h, a.v, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q);
+    for (int ro = 0; ro < S::ROWS; ro += 10) {
+        hv_row<T, STEP, MODE, 0>(a.h, a.v, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q0);
+        hv_row<T, STEP, MODE, 1>(a.h, a.v, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q1);
+        hv_row<T, STEP, MODE, 2>(a.h, a.v, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q0);
+        hv_row<T, STEP, MODE, 3>(a.h, a.v, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q1);
+        hv_row<T, STEP, MODE, 4>(a.h, a.v, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q0);
+        hv_row<T, STEP, MODE, 5>(a.h, a.v, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q1);
+        hv_row<T, STEP, MODE, 6>(a.h, a.v, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q0);
+        hv_row<T, STEP, MODE, 7>(a.h, a.v, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q1);
+        hv_row<T, STEP, MODE, 8>(a.h, a.v, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q0);
+        hv_row<T, STEP, MODE, 9>(a.h, a.v, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q1);
     }
 }
 
 template <typename T, int STEP, int MODE>
-__global__ __launch_bounds__(64, SV_HV_WAVES_PER_EU) void atrous_hv_k(HvArgs a, int tiles) {
+__global__ __launch_bounds__(64) void atrous_hv_k(HvArgs a, int tiles) {
     using S = HvShape<STEP>;
     __shared__ float4 s_cl[S::COLS];
     __shared__ float4 s_gn[S::COLS];
@@ -918,370 +923,10 @@ void launch_hv_step(const HvArgs &a, int mode, hipStream_t s) {
     }
 }
 
-// ---- separable level, both passes in one workgroup tile ----------------------
-//
-// The 2D level's tile (64 columns x TY lattice rows of one step phase, the
-// taps' lattice rows and columns staged in LDS) carries both passes: the
-// horizontal pass runs for the TY rows and for the two lattice rows above
-// and below them (the vertical taps); its results, rounded to the storage
-// type exactly as the two-pass form's scratch planes round them, then take
-// the place of the staged colour in LDS, and the vertical pass reads them
-// there.  Every weight, sum and summation order is that of the two passes,
-// so the output is bitwise theirs.  256 threads per tile, so many tiles
-// are resident per CU.
-template <int STEP, int PY, bool WANT_VAR>
-struct SepShape {
-    static constexpr int TX = 64, TY = 4 * PY, HX = 2 * STEP, ROWS = TY + 4;
-    static constexpr int COLS = TX + 2 * HX, PFC = TX + 2;
-    static constexpr int NS = ROWS * COLS, IT = (NS + 255) / 256;
-    static constexpr int NV = WANT_VAR ? ROWS * TX : 0, ITV = (NV + 255) / 256;
-    static constexpr int NP = ROWS * 3 * PFC, ITP = (NP + 255) / 256;
-    static constexpr int NH = ROWS * TX, ITH = (NH + 255) / 256;
-    static_assert(NP >= NH, "the prefilter staging holds the horizontal pass's g afterwards");
-};
-
-// Lattice rows per thread of the separable tile: the largest step keeps
-// four rows so that three tiles fit in a CU's LDS.
-#ifndef SV_SEP_PY16
-#define SV_SEP_PY16 1
-#endif
-#ifndef SV_SEP_PY
-#define SV_SEP_PY 2
-#endif
-constexpr int sep_py(int step) { return step >= 16 ? SV_SEP_PY16 : SV_SEP_PY; }
-
-// Raw loads of one separable tile, held between issue and LDS store.
-template <class S>
-struct SepRegs {
-    float z[S::IT], r[S::IT], g[S::IT], b[S::IT], nx[S::IT], ny[S::IT], nz[S::IT];
-    bool in[S::IT];
-    float v[S::ITV > 0 ? S::ITV : 1];
-    bool vin[S::ITV > 0 ? S::ITV : 1];
-    float pz[S::ITP], pv[S::ITP];
-    bool pin[S::ITP];
-};
-
-// Issue the tile's loads: colour, depth and normal of the taps' rows and
-// columns; the input variance at the tile's own columns; three image rows
-// per lattice row for the 3x3 variance prefilter.
-template <typename T, int STEP, class S>
-__device__ __forceinline__ void sep_issue(const AtrousArgs &ah, TileOrigin t, SepRegs<S> &q) {
-#pragma unroll
-    for (int it = 0; it < S::IT; ++it) {
-        const int i = threadIdx.x + it * 256;
-        const int row = i / S::COLS, c = i - row * S::COLS;
-        const int gx = t.x0 - S::HX + c, gy = t.ybase + (row - 2) * STEP;
-        q.in[it] = i < S::NS && gx >= 0 && gx < ah.w && gy >= 0 && gy < ah.h;
-        const uint32_t o = q.in[it] ? (uint32_t)gy * (uint32_t)ah.pitch + (uint32_t)gx : 0u;
-        q.z[it] = ldo<T>(ah.z, o);
-        q.r[it] = ldo<T>(ah.cr, o);
-        q.g[it] = ldo<T>(ah.cg, o);
-        q.b[it] = ldo<T>(ah.cb, o);
-        q.nx[it] = ldo<T>(ah.nx, o);
-        q.ny[it] = ldo<T>(ah.ny, o);
-        q.nz[it] = ldo<T>(ah.nz, o);
-    }
-#pragma unroll
-    for (int it = 0; it < S::ITV; ++it) {
-        const int i = threadIdx.x + it * 256;
-        const int row = i / S::TX, c = i - row * S::TX;
-        const int gx = t.x0 + c, gy = t.ybase + (row - 2) * STEP;
-        q.vin[it] = i < S::NV && gx < ah.w && gy >= 0 && gy < ah.h;
-        q.v[it] = ldf(ah.var, q.vin[it] ? (uint32_t)gy * (uint32_t)ah.pitch + (uint32_t)gx : 0u);
-    }
-#pragma unroll
-    for (int it = 0; it < S::ITP; ++it) {
-        const int i = threadIdx.x + it * 256;
-        const int j = i / (3 * S::PFC), rem = i - j * (3 * S::PFC);
-        const int r3 = rem / S::PFC, c = rem - r3 * S::PFC;
-        const int gx = t.x0 - 1 + c, gy = t.ybase + (j - 2) * STEP + r3 - 1;
-        q.pin[it] = i < S::NP && gx >= 0 && gx < ah.w && gy >= 0 && gy < ah.h;
-        const uint32_t o = q.pin[it] ? (uint32_t)gy * (uint32_t)ah.pitch + (uint32_t)gx : 0u;
-        q.pz[it] = ldo<T>(ah.z, o);
-        q.pv[it] = ldf(ah.var, o);
-    }
-}
-
-template <class S>
-__device__ __forceinline__ void sep_store(const SepRegs<S> &q, float4 *s_cl, float4 *s_gn,
-                                          float *s_v, float *s_pf) {
-#pragma unroll
-    for (int it = 0; it < S::IT; ++it) {
-        const int i = threadIdx.x + it * 256;
-        if (i < S::NS) {
-            const bool ok = q.in[it] && !empty_px(q.z[it]);
-            s_cl[i] = ok ? make_float4(q.r[it], q.g[it], q.b[it], luma(q.r[it], q.g[it], q.b[it]))
-                         : make_float4(0.f, 0.f, 0.f, INFINITY);
-            s_gn[i] = ok ? make_float4(q.z[it], q.nx[it], q.ny[it], q.nz[it])
-                         : make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-    }
-#pragma unroll
-    for (int it = 0; it < S::ITV; ++it) {
-        const int i = threadIdx.x + it * 256;
-        if (i < S::NV) s_v[i] = q.vin[it] ? q.v[it] : 0.f;  // masked by emptiness when read
-    }
-#pragma unroll
-    for (int it = 0; it < S::ITP; ++it) {
-        const int i = threadIdx.x + it * 256;
-        if (i < S::NP) s_pf[i] = (q.pin[it] && !empty_px(q.pz[it])) ? q.pv[it] : kNoVar;
-    }
-}
-
-// Both passes of a staged tile (the caller's barrier after sep_store has
-// been passed); returns with the LDS still in use by other threads.
-template <typename T, int STEP, int PY, int MODE, bool WANT_VAR>
-__device__ __forceinline__ void sep_compute(const AtrousArgs &ah, const AtrousArgs &av,
-                                            TileOrigin t, float4 *s_cl, const float4 *s_gn,
-                                            const float *s_v, float *s_pf) {
-    using S = SepShape<STEP, PY, WANT_VAR>;
-    constexpr int WM = MODE;  // kUnit or kWeighted
-    // ---- horizontal pass for every row of the tile, results in registers
-    float4 hres[S::ITH];
-    float hg[S::ITH];
-#pragma unroll
-    for (int it = 0; it < S::ITH; ++it) {
-        const int k = threadIdx.x + it * 256;
-        hres[it] = make_float4(0.f, 0.f, 0.f, INFINITY);
-        hg[it] = 0.f;
-        if (k >= S::NH) continue;
-        const int row = k / S::TX, lx = k - row * S::TX;
-        const int x = t.x0 + lx, y = t.ybase + (row - 2) * STEP;
-        const int ci = row * S::COLS + lx + S::HX;
-        const float4 pc = s_cl[ci], pg = s_gn[ci];
-        if (x >= ah.w || y < 0 || y >= ah.h || pg.x == 0.f) continue;  // not a tap
-        const uint32_t o = (uint32_t)y * (uint32_t)ah.pitch + (uint32_t)x;
-        float gsum = 0.f, wsum = 0.f;
-#pragma unroll
-        for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-            for (int dx = 0; dx < 3; ++dx) {
-                const float e = s_pf[(row * 3 + dy) * S::PFC + lx + dx];
-                const bool ok = e == e;  // kNoVar: outside or empty
-                const float kk = ok ? kG3[dx] * kG3[dy] : 0.f;
-                gsum = fmaf(kk, ok ? e : 0.f, gsum);
-                wsum += kk;
-            }
-        const float gv = gsum / wsum;
-        hg[it] = gv;
-        float kz[2] = {0.f, 0.f};
-        float kl = 0.f;
-        if (WM != kUnit) {
-            kl = luma_scale(ah, gv, o);
-            const float gx = ldo<T>(ah.dzdx, o) * (float)STEP, gy = 0.f;
-#pragma unroll
-            for (int aa = 1; aa <= 2; ++aa) {
-                const float den = fmaf(ah.sigma_z, fabsf(fmaf(gx, (float)aa, gy * 0.f)), ah.eps_z);
-                kz[aa - 1] = kLog2e * fast_rcp(den);
-            }
-        }
-        constexpr float h0 = 0.375f;
-        Acc acc;
-        acc.sw = h0;
-        acc.sr = h0 * pc.x;
-        acc.sg = h0 * pc.y;
-        acc.sb = h0 * pc.z;
-        acc.sv = 0.f;
-#pragma unroll
-        for (int aa = -2; aa <= 2; ++aa) {
-            if (aa == 0) continue;
-            const int qi = ci + aa * STEP;
-            tap<WM, false>(acc, s_cl[qi], s_gn[qi], 0.f, kLog2H1[aa + 2], kH1[aa + 2],
-                           WM == kUnit ? 0.f : kz[(aa < 0 ? -aa : aa) - 1], pg.x, pc.w, pg.y,
-                           pg.z, pg.w, kl, ah.nc);
-        }
-        const float inv = 1.0f / acc.sw;
-        const float hr = round_to<T>(acc.sr * inv), hgr = round_to<T>(acc.sg * inv),
-                    hb = round_to<T>(acc.sb * inv);
-        hres[it] = make_float4(hr, hgr, hb, luma(hr, hgr, hb));
-    }
-    __syncthreads();
-    // the horizontal results replace the staged colour; g takes the place
-    // of the prefilter rows
-#pragma unroll
-    for (int it = 0; it < S::ITH; ++it) {
-        const int k = threadIdx.x + it * 256;
-        if (k < S::NH) {
-            const int row = k / S::TX, lx = k - row * S::TX;
-            s_cl[row * S::COLS + lx + S::HX] = hres[it];
-            s_pf[k] = hg[it];
-        }
-    }
-    __syncthreads();
-    // ---- vertical pass for the tile's own rows
-    const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
-    const int x = t.x0 + lx;
-    if (x >= av.w) return;
-#pragma unroll 1
-    for (int kk = 0; kk < PY; ++kk) {
-        const int j = ly + 4 * kk, row = j + 2;
-        const int y = t.ybase + j * STEP;
-        if (y >= av.h) break;
-        const uint32_t o = (uint32_t)y * (uint32_t)av.pitch + (uint32_t)x;
-        if (av.ctl) {  // uniform branch
-            const int sel = ctl_select(av, o);
-            if (sel != 1) {
-                if (sel == 2) copy_through<T>(av, o);
-                continue;
-            }
-        }
-        const int ci = row * S::COLS + lx + S::HX;
-        const float4 cen = s_cl[ci], cg = s_gn[ci];
-        if (cg.x == 0.f) {  // empty pixel: its input colour passes through
-            write_out<T>(av, o, ldo<T>(ah.cr, o), ldo<T>(ah.cg, o), ldo<T>(ah.cb, o));
-            if (av.var_out) stf(av.var_out, o, 0.f);
-            continue;
-        }
-        const float gv = s_pf[row * S::TX + lx];
-        float kz[2] = {0.f, 0.f};
-        float kl = 0.f;
-        if (WM != kUnit) {
-            kl = luma_scale(av, gv, o);
-            const float gx = 0.f, gy = ldo<T>(av.dzdy, o) * (float)STEP;
-#pragma unroll
-            for (int b = 1; b <= 2; ++b) {
-                const float den = fmaf(av.sigma_z, fabsf(fmaf(gx, 0.f, gy * (float)b)), av.eps_z);
-                kz[b - 1] = kLog2e * fast_rcp(den);
-            }
-        }
-        constexpr float h0 = 0.375f;
-        Acc acc;
-        acc.sw = h0;
-        acc.sr = h0 * cen.x;
-        acc.sg = h0 * cen.y;
-        acc.sb = h0 * cen.z;
-        acc.sv = WANT_VAR ? h0 * h0 * s_v[row * S::TX + lx] : 0.f;
-#pragma unroll
-        for (int b = -2; b <= 2; ++b) {
-            if (b == 0) continue;
-            const int q = ci + b * S::COLS;
-            const float4 qg = s_gn[q];
-            const float qv = WANT_VAR ? (qg.x == 0.f ? 0.f : s_v[(row + b) * S::TX + lx]) : 0.f;
-            tap<WM, WANT_VAR>(acc, s_cl[q], qg, qv, kLog2H1[b + 2], kH1[b + 2],
-                              WM == kUnit ? 0.f : kz[(b < 0 ? -b : b) - 1], cg.x, cen.w, cg.y,
-                              cg.z, cg.w, kl, av.nc);
-        }
-        const float inv = 1.0f / acc.sw;
-        write_out<T>(av, o, acc.sr * inv, acc.sg * inv, acc.sb * inv);
-        if (WANT_VAR) stf(av.var_out, o, acc.sv * inv * inv);
-    }
-}
-
-// One tile per workgroup, or (PERSIST) a strided run of tiles of this
-// workgroup's XCD range with the next tile's loads in flight while the
-// current one is computed.
-template <typename T, int STEP, int PY, int MODE, bool WANT_VAR, bool PERSIST>
-__global__ __launch_bounds__(256) void atrous_sept_k(HvArgs a, int tiles, int per_xcd) {
-    using S = SepShape<STEP, PY, WANT_VAR>;
-    __shared__ float4 s_cl[S::NS];
-    __shared__ float4 s_gn[S::NS];
-    __shared__ float s_v[S::NV > 0 ? S::NV : 1];
-    __shared__ float s_pf[S::NP];
-    const int gxt = (a.h.w + S::TX - 1) / S::TX;
-    const int xcd = (int)blockIdx.x % kXCD, slot = (int)blockIdx.x / kXCD;
-    const int nslot = (int)gridDim.x / kXCD;
-    const int first = xcd * per_xcd, last = min(tiles, first + per_xcd);
-    int t = first + slot;
-    if (t >= last) return;
-    SepRegs<S> q;
-    sep_issue<T, STEP, S>(a.h, tile_origin<STEP, S::TY, S::TX>(t, gxt), q);
-    sep_store<S>(q, s_cl, s_gn, s_v, s_pf);
-    __syncthreads();
-    if (!PERSIST) {
-        sep_compute<T, STEP, PY, MODE, WANT_VAR>(a.h, a.v, tile_origin<STEP, S::TY, S::TX>(t, gxt),
-                                                 s_cl, s_gn, s_v, s_pf);
-        return;
-    }
-    for (;;) {
-        const int tn = t + nslot;
-        if (tn < last) sep_issue<T, STEP, S>(a.h, tile_origin<STEP, S::TY, S::TX>(tn, gxt), q);
-        sep_compute<T, STEP, PY, MODE, WANT_VAR>(a.h, a.v, tile_origin<STEP, S::TY, S::TX>(t, gxt),
-                                                 s_cl, s_gn, s_v, s_pf);
-        if (tn >= last) break;
-        __syncthreads();
-        sep_store<S>(q, s_cl, s_gn, s_v, s_pf);
-        __syncthreads();
-        t = tn;
-    }
-}
-
-template <typename T, int STEP, int PY, int MODE, bool WANT_VAR>
-__global__ __launch_bounds__(256) void atrous_sept_batch_k(const HvArgs *args, const int *prefix,
-                                                           int n, int total) {
-    using S = SepShape<STEP, PY, WANT_VAR>;
-    __shared__ float4 s_cl[S::NS];
-    __shared__ float4 s_gn[S::NS];
-    __shared__ float s_v[S::NV > 0 ? S::NV : 1];
-    __shared__ float s_pf[S::NP];
-    int s = 0;
-    const int lt = batch_tile(prefix, n, total, s);
-    if (lt < 0) return;
-    const HvArgs a = args[s];  // a copy: the kernel's stores cannot alias it
-    const TileOrigin o = tile_origin<STEP, S::TY, S::TX>(lt, (a.h.w + S::TX - 1) / S::TX);
-    SepRegs<S> q;
-    sep_issue<T, STEP, S>(a.h, o, q);
-    sep_store<S>(q, s_cl, s_gn, s_v, s_pf);
-    __syncthreads();
-    sep_compute<T, STEP, PY, MODE, WANT_VAR>(a.h, a.v, o, s_cl, s_gn, s_v, s_pf);
-}
-
-template <typename T, int STEP, int PY, int MODE, bool WANT_VAR>
-void sept_batch_launch(const void *args, const int *prefix, int n, int total, hipStream_t s) {
-    hipLaunchKernelGGL((atrous_sept_batch_k<T, STEP, PY, MODE, WANT_VAR>), dim3(xcd_grid(total)),
-                       dim3(256), 0, s, (const HvArgs *)args, prefix, n, total);
-}
-
-#ifndef SV_SEP_PERSIST_BPC
-#define SV_SEP_PERSIST_BPC 0
-#endif
-
-template <typename T, int STEP, int MODE, bool WANT_VAR>
-void launch_sept_mode(const HvArgs &a, hipStream_t s) {
-    constexpr int PY = sep_py(STEP), TY = 4 * PY;
-    const int bands = (a.h.h + STEP * TY - 1) / (STEP * TY);
-    const int tiles = ((a.h.w + 63) / 64) * bands * STEP;
-    const int per_xcd = (tiles + kXCD - 1) / kXCD;
-    if (record_pass(&sept_batch_launch<T, STEP, PY, MODE, WANT_VAR>, a, tiles)) return;
-    if (SV_SEP_PERSIST_BPC > 0) {
-        const int slots = min(per_xcd, kCUs / kXCD * SV_SEP_PERSIST_BPC);
-        hipLaunchKernelGGL((atrous_sept_k<T, STEP, PY, MODE, WANT_VAR, true>), dim3(slots * kXCD),
-                           dim3(256), 0, s, a, tiles, per_xcd);
-    } else {
-        hipLaunchKernelGGL((atrous_sept_k<T, STEP, PY, MODE, WANT_VAR, false>),
-                           dim3(per_xcd * kXCD), dim3(256), 0, s, a, tiles, per_xcd);
-    }
-}
-
-template <typename T, int STEP>
-void launch_sept_step(const HvArgs &a, bool unit, hipStream_t s) {
-    const bool wv = a.v.var_out != nullptr;
-    if (unit) {
-        if (wv) launch_sept_mode<T, STEP, kUnit, true>(a, s);
-        else launch_sept_mode<T, STEP, kUnit, false>(a, s);
-    } else {
-        if (wv) launch_sept_mode<T, STEP, kWeighted, true>(a, s);
-        else launch_sept_mode<T, STEP, kWeighted, false>(a, s);
-    }
-}
-
-#ifndef SV_SEP_RING
-#define SV_SEP_RING 0
-#endif
-
 // Fused separable level; false when the step has no fused form (then the
 // two passes run through a scratch buffer).
 template <typename T>
 bool launch_hv(const HvArgs &a, bool unit, hipStream_t s) {
-    if (!SV_SEP_RING) {
-        switch (a.h.step) {
-        case 1: launch_sept_step<T, 1>(a, unit, s); return true;
-        case 2: launch_sept_step<T, 2>(a, unit, s); return true;
-        case 4: launch_sept_step<T, 4>(a, unit, s); return true;
-        case 8: launch_sept_step<T, 8>(a, unit, s); return true;
-        case 16: launch_sept_step<T, 16>(a, unit, s); return true;
-        default: return false;
-        }
-    }
     const int mode = (unit ? 0 : 1) | (a.v.var_out ? 2 : 0);
     switch (a.h.step) {
     case 1: launch_hv_step<T, 1>(a, mode, s); return true;

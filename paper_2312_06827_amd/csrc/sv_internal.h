@@ -45,9 +45,16 @@ __device__ __forceinline__ void stf(float *base, uint32_t idx, float v) {
 
 // ---- shared arithmetic ----------------------------------------------------
 
-// Rec. 709 luminance, fixed evaluation order.
+// Rec. 709 luminance, fixed evaluation order, written as
+// g + 0.2126 (r - g) + 0.0722 (b - g) (the weights sum to one): exact for
+// grey colours, so the luminance difference of two grey pixels is their
+// exact difference.  The luminance edge weight divides that difference by
+// sigma_l sqrt(g) + eps_l, which is tiny where the variance vanishes (e.g.
+// a binary visibility signal away from its edges); with the plain form the
+// rounding of each pixel's luminance (an ulp of L) then moves weights by
+// percents.
 __device__ __forceinline__ float luma(float r, float g, float b) {
-    return fmaf(0.0722f, b, fmaf(0.7152f, g, 0.2126f * r));
+    return fmaf(0.0722f, b - g, fmaf(0.2126f, r - g, g));
 }
 
 // No surface: depth not > 0 or not finite.

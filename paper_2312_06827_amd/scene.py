@@ -231,8 +231,11 @@ def _visibility(cfg, scene, frame, gb) -> np.ndarray:
     other than the point's own covers a disc of angular radius
     asin(R / distance); the covered fractions combine as independent
     occluders.  Small-angle (planar) disc geometry."""
+    return _visibility_at(cfg, scene, frame, gb["X"], gb["id"])
+
+
+def _visibility_at(cfg, scene, frame, X, obj) -> np.ndarray:
     theta = math.radians(cfg.shadow_angle_deg) / 2.0
-    X, obj = gb["X"], gb["id"]
     vis = np.ones(obj.shape)
     for i, S in enumerate(scene.centers(frame)):
         D = S[:, None, None] - X
@@ -260,6 +263,27 @@ def _specular(cfg, scene, frame, gb) -> np.ndarray:
     sky = horizon * (1.0 - up) + zenith * up
     ks = 0.25 * (1.0 - scene.roughness[gb["id"]].astype(np.float64))
     return 2.0 * sky * ks[None]
+
+
+def _forward(cfg, scene, frame, gb_prev):
+    """Where each pixel of frame - 1 lands in frame `frame`: its surface
+    point moved with its object, projected with the current camera.
+    Returns the moved points, the forward motion in pixels (2, H, W) and
+    the moved points' view depth."""
+    W, H, f = cfg.width, cfg.height, scene.f
+    X = gb_prev["X"].copy()
+    for i in range(6):
+        if np.any(scene.vel[i] != 0.0):
+            m = gb_prev["id"] == i + 1
+            X[:, m] += scene.vel[i][:, None]
+    C, fwd, right, up = scene.camera(frame)
+    rel = X - C[:, None, None]
+    zc = np.einsum("i,ihw->hw", fwd, rel)
+    xp = np.einsum("i,ihw->hw", right, rel) / zc * f + W / 2.0 - 0.5
+    yp = -np.einsum("i,ihw->hw", up, rel) / zc * f + H / 2.0 - 0.5
+    xs = np.arange(W, dtype=np.float64)[None, :]
+    ys = np.arange(H, dtype=np.float64)[:, None]
+    return X, np.stack([xp - xs, yp - ys]), zc
 
 
 def _channel_noise(cfg, frame: int, key: int, shape):
@@ -314,6 +338,27 @@ def _assemble(cfg, scene, frame, gb, gb_prev) -> Frame:
             "shadow_angle": np.full((H, W), cfg.shadow_angle_deg, np.float32),
             "composite_clean": np.ascontiguousarray(
                 (clean * vis[None] + spec_clean).astype(np.float32)),
+        })
+        # the temporal gradient's inputs (A-SVGF): every pixel of the
+        # previous frame carried forward, its shadow ray traced again in
+        # this frame with the previous frame's random number, and one
+        # sample per 3x3 stratum of the previous frame chosen for it
+        if frame > 0 and not cfg.static:
+            Xf, fmv, fz = _forward(cfg, scene, frame, gb_prev)
+            u_prev = _channel_noise(cfg, frame - 1, 1, (H, W)).random(size=(H, W))
+            vis_f = _visibility_at(cfg, scene, frame, Xf, gb_prev["id"])
+            reshade = (u_prev < vis_f).astype(np.float32)
+        else:
+            fmv = np.zeros((2, H, W))
+            fz = gb_prev["z"]
+            reshade = hit.astype(np.float32)
+        pick = _channel_noise(cfg, frame, 3, (H, W)).integers(
+            0, 9, size=((H + 2) // 3, (W + 2) // 3)).astype(np.uint8)
+        out.update({
+            "fmv": q(fmv),
+            "fz": q(fz),
+            "shadow_reshade": np.ascontiguousarray(reshade),
+            "grad_pick": np.ascontiguousarray(pick),
         })
     return out
 

@@ -106,3 +106,33 @@ def test_channel_batch_equals_channels_alone():
         assert den.batch.passes() == 3 + 2 * 4  # temporal, variance x2, two launches per level
     finally:
         den.close()
+
+
+@pytest.mark.parametrize("sep", [False, True])
+def test_levels_on_binary_visibility(sep):
+    """Grey 0/1 visibility with zero variance almost everywhere: the
+    luminance edge weight divides by a nearly vanishing scale there, so the
+    luminance differences must be exact for grey colours (the level is
+    still within 1e-5 of the oracle, colour and variance)."""
+    fr = _channel_frames(W=200, H=120, frames=1)[0]
+    z, dzdx, dzdy, n = fr["z"], fr["dzdx"], fr["dzdy"], fr["n"]
+    vis = fr["shadow"].astype(np.float32)
+    # the variance a first frame gives such a signal: the spatial estimate
+    var = O.variance(vis[0], vis[0] ** 2, np.ones(z.shape, np.int32), z, dzdx, dzdy, n)
+    var = var.astype(np.float32)
+    c, v = vis, var
+    g = L.GBuf(dev(z), dev(dzdx), dev(dzdy), dev(n))
+    for i in range(4):
+        step = 1 << i
+        say(f"binary visibility sep={sep} step={step} zero-var {(v == 0).mean():.2f}")
+        out, vo = empty_like_dev((3,) + z.shape), empty_like_dev(z.shape)
+        if sep:
+            L.sv_atrous_sep(dev(c), dev(v), g, None, out, vo, step, L.AtrousParams())
+            rc, rv, _ = O.atrous_sep(c, v, z, dzdx, dzdy, n, step)
+        else:
+            L.sv_atrous(dev(c), dev(v), g, out, vo, step, L.AtrousParams())
+            rc, rv = O.atrous(c, v, z, dzdx, dzdy, n, step)
+        assert rel_err(host(out), rc) <= TOL32
+        assert rel_err(host(vo), rv) <= TOL32
+        # the next level's input: this level's device output
+        c, v = host(out).astype(np.float32), host(vo).astype(np.float32)
