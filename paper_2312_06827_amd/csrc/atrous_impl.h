@@ -372,11 +372,12 @@ __device__ __forceinline__ void tile_compute(const AtrousArgs &a, TileOrigin t,
             }
         const float inv = 1.0f / acc.sw;
         if (DIR == kDirH) {
-            sto<T>(a.or_, o, acc.sr * inv);
-            sto<T>(a.og, o, acc.sg * inv);
-            sto<T>(a.ob, o, acc.sb * inv);
+            sto<T>(a.or_, o, quot(acc.sr, acc.sw, inv));
+            sto<T>(a.og, o, quot(acc.sg, acc.sw, inv));
+            sto<T>(a.ob, o, quot(acc.sb, acc.sw, inv));
         } else {
-            write_out<T>(a, o, acc.sr * inv, acc.sg * inv, acc.sb * inv);
+            write_out<T>(a, o, quot(acc.sr, acc.sw, inv), quot(acc.sg, acc.sw, inv),
+                     quot(acc.sb, acc.sw, inv));
             if (WANT_VAR) stf(a.var_out, o, acc.sv * inv * inv);
         }
     }
@@ -517,7 +518,8 @@ __global__ __launch_bounds__(256) void atrous_direct_k(AtrousArgs a) {
                                 pc.w, pg.y, pg.z, pg.w, kl, a.nc);
         }
     const float inv = 1.0f / acc.sw;
-    write_out<T>(a, o, acc.sr * inv, acc.sg * inv, acc.sb * inv);
+    write_out<T>(a, o, quot(acc.sr, acc.sw, inv), quot(acc.sg, acc.sw, inv),
+                     quot(acc.sb, acc.sw, inv));
     if (WANT_VAR) stf(a.var_out, o, acc.sv * inv * inv);
 }
 
@@ -581,12 +583,13 @@ __global__ __launch_bounds__(256) void atrous_sep_k(AtrousArgs a) {
     }
     const float inv = 1.0f / acc.sw;
     if (VERTICAL) {
-        write_out<T>(a, o, acc.sr * inv, acc.sg * inv, acc.sb * inv);
+        write_out<T>(a, o, quot(acc.sr, acc.sw, inv), quot(acc.sg, acc.sw, inv),
+                     quot(acc.sb, acc.sw, inv));
         if (WANT_VAR) stf(a.var_out, o, acc.sv * inv * inv);
     } else {
-        sto<T>(a.or_, o, acc.sr * inv);
-        sto<T>(a.og, o, acc.sg * inv);
-        sto<T>(a.ob, o, acc.sb * inv);
+        sto<T>(a.or_, o, quot(acc.sr, acc.sw, inv));
+        sto<T>(a.og, o, quot(acc.sg, acc.sw, inv));
+        sto<T>(a.ob, o, quot(acc.sb, acc.sw, inv));
     }
 }
 
@@ -779,8 +782,9 @@ __device__ __forceinline__ void hv_row(const AtrousArgs &ah, const AtrousArgs &a
                            pg.w, kl, ah.nc);
         }
         const float inv = 1.0f / acc.sw;
-        const float hr = round_to<T>(acc.sr * inv), hg = round_to<T>(acc.sg * inv),
-                    hb = round_to<T>(acc.sb * inv);
+        const float hr = round_to<T>(quot(acc.sr, acc.sw, inv)),
+                    hg = round_to<T>(quot(acc.sg, acc.sw, inv)),
+                    hb = round_to<T>(quot(acc.sb, acc.sw, inv));
         cur.c = make_float4(hr, hg, hb, luma(hr, hg, hb));
     }
     // ---- vertical pass for the row two behind ----
@@ -829,7 +833,8 @@ __device__ __forceinline__ void hv_row(const AtrousArgs &ah, const AtrousArgs &a
                           cen.gn.y, cen.gn.z, cen.gn.w, kl, av.nc);
     }
     const float inv = 1.0f / acc.sw;
-    write_out<T>(av, o, acc.sr * inv, acc.sg * inv, acc.sb * inv);
+    write_out<T>(av, o, quot(acc.sr, acc.sw, inv), quot(acc.sg, acc.sw, inv),
+                 quot(acc.sb, acc.sw, inv));
     if (WANT_VAR) stf(av.var_out, o, acc.sv * inv * inv);
 }
 

@@ -54,7 +54,21 @@ __device__ __forceinline__ void stf(float *base, uint32_t idx, float v) {
 // rounding of each pixel's luminance (an ulp of L) then moves weights by
 // percents.
 __device__ __forceinline__ float luma(float r, float g, float b) {
-    return fmaf(0.0722f, b - g, fmaf(0.2126f, r - g, g));
+    // no contraction of the differences into a producer's product: every
+    // caller gets the same bits for the same colour
+    return fmaf(0.0722f, __fsub_rn(b, g), fmaf(0.2126f, __fsub_rn(r, g), g));
+}
+
+// n / d from inv = 1 / d with one correction step: the residual n - q d is
+// exact in an fma, so the quotient is correctly rounded but in rare hard
+// cases, and n == d gives exactly 1, n == 0 gives 0.  Weighted means thus
+// keep a flat region exactly flat, which the luminance edge weight needs:
+// where the variance vanishes it is a near step function of the luminance
+// difference (scale eps_l), and a flat value off by an ulp would cut its
+// neighbours off.
+__device__ __forceinline__ float quot(float n, float d, float inv) {
+    const float q = n * inv;
+    return fmaf(fmaf(-q, d, n), inv, q);
 }
 
 // No surface: depth not > 0 or not finite.

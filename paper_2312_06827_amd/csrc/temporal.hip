@@ -315,8 +315,8 @@ __device__ __forceinline__ PxState px_reproject(const TemporalArgs &a, const flo
     s.nmax = nmax;
     if (!s.any) return s;
     const float inv = 1.0f / sw;
-    float hr = ar * inv, hg = ag * inv, hb = ab * inv;
-    const float hm1 = a1 * inv;
+    float hr = quot(ar, sw, inv), hg = quot(ag, sw, inv), hb = quot(ab, sw, inv);
+    const float hm1 = quot(a1, sw, inv);
     // second central moment of the bilinear mixture: mean of the taps'
     // central moments plus the spread of their means (no cancellation)
     float s2 = 0.f;
