@@ -13,9 +13,10 @@ luminance, correctly rounded weighted means), which holds every single 2D
 level to 1e-5; but beside the penumbrae, single roundings of the weighted
 means (and of the separable level's horizontal result) still move
 weights of nearly equal neighbours by percents, and over a chain the
-output moves by up to 3e-5 (measured).  The shadow channel's chain and the
-separable level's variance on such input are therefore held to 1e-4; the
-specular channel, whose variance does not vanish, to 1e-5."""
+output moves by up to 3e-5 (measured).  The shadow channel's chain is
+therefore held to 1e-4, and the separable level's variance on such input,
+which differs by up to 4x where it is 1e-6 of its plane's RMS, to 1e-5 of
+that RMS; the specular channel, whose variance does not vanish, to 1e-5."""
 
 from dataclasses import replace
 
@@ -147,8 +148,11 @@ def test_levels_on_binary_visibility(sep):
         else:
             L.sv_atrous(dev(c), dev(v), g, out, vo, step, L.AtrousParams())
             rc, rv = O.atrous(c, v, z, dzdx, dzdy, n, step)
-        ec, ev = rel_err(host(out), rc), rel_err(host(vo), rv)
+        ec = rel_err(host(out), rc)
+        # the separable level's variance where it nearly vanishes is judged
+        # against the plane's own scale (see above)
+        ev = rel_err(host(vo), rv, floor=1.0 if sep else 1e-3)
         say(f"  colour {ec:.2e} {worst(host(out), rc)}  var {ev:.2e} {worst(host(vo), rv)}")
-        assert ec <= TOL32 and ev <= (TOL_BINARY if sep else TOL32)
+        assert ec <= TOL32 and ev <= TOL32
         # the next level's input: this level's device output
         c, v = host(out).astype(np.float32), host(vo).astype(np.float32)
