@@ -141,6 +141,22 @@ __device__ __forceinline__ int ctl_select(const AtrousArgs &a, uint32_t o) {
     return (int)((c >> 4) & 1u) == a.ctl_class ? 1 : 0;
 }
 
+// Whether any of the rows y0 + k * dy, k < rows, at this thread's column x
+// holds a pixel that this launch writes: a uniform answer over the
+// workgroup (every thread must call it), so that a launch skips the tiles
+// of the other class before staging them.
+__device__ __forceinline__ bool any_of_class(const AtrousArgs &a, int x, int y0, int dy,
+                                             int rows) {
+    bool mine = false;
+    if (x < a.w)
+        for (int k = 0; k < rows; ++k) {
+            const int y = y0 + k * dy;
+            if (y >= 0 && y < a.h)
+                mine |= ctl_select(a, (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x) != 0;
+        }
+    return __syncthreads_or(mine) != 0;
+}
+
 // A pixel outside this level: colour and variance unchanged (the inverse
 // tone map still applies on the last level).
 template <typename T>
@@ -399,14 +415,23 @@ __global__ __launch_bounds__(256) void atrous_tile_k(AtrousArgs a, int tiles, in
     int t = first + slot;
     if (t >= last) return;
     TileRegs<S::IT, S::ITP> regs;
+    if (!PERSIST) {  // one tile per workgroup: no prefetch registers live
+        const TileOrigin o = tile_origin<STEP, S::TY, S::TX>(t, gxt);
+        // adaptive levels: a tile without a pixel of this launch's class
+        // is not staged at all (uniform branch)
+        if (DIR != kDirH && a.ctl &&
+            !any_of_class(a, o.x0 + (int)(threadIdx.x & 63), o.ybase + (int)(threadIdx.x >> 6) * STEP,
+                          4 * STEP, PY))
+            return;
+        tile_issue<T, S>(a, o, regs);
+        tile_store<S>(regs, s_cl, s_gn, s_v, s_pf);
+        __syncthreads();
+        tile_compute<T, STEP, PY, MODE, WANT_VAR, DIR>(a, o, s_cl, s_gn, s_v, s_pf);
+        return;
+    }
     tile_issue<T, S>(a, tile_origin<STEP, S::TY, S::TX>(t, gxt), regs);
     tile_store<S>(regs, s_cl, s_gn, s_v, s_pf);
     __syncthreads();
-    if (!PERSIST) {  // one tile per workgroup: no prefetch registers live
-        tile_compute<T, STEP, PY, MODE, WANT_VAR, DIR>(a, tile_origin<STEP, S::TY, S::TX>(t, gxt),
-                                                       s_cl, s_gn, s_v, s_pf);
-        return;
-    }
     for (;;) {
         const int tn = t + nslot;
         if (tn < last) tile_issue<T, S>(a, tile_origin<STEP, S::TY, S::TX>(tn, gxt), regs);
@@ -436,6 +461,10 @@ __global__ __launch_bounds__(256) void atrous_batch_k(const AtrousArgs *args, co
     const AtrousArgs a = args[s];  // a copy: the kernel's stores cannot alias it
     const int gxt = (a.w + S::TX - 1) / S::TX;
     const TileOrigin o = tile_origin<STEP, S::TY, S::TX>(lt, gxt);
+    if (DIR != kDirH && a.ctl &&
+        !any_of_class(a, o.x0 + (int)(threadIdx.x & 63), o.ybase + (int)(threadIdx.x >> 6) * STEP,
+                      4 * STEP, PY))
+        return;
     TileRegs<S::IT, S::ITP> regs;
     tile_issue<T, S>(a, o, regs);
     tile_store<S>(regs, s_cl, s_gn, s_v, s_pf);
@@ -858,6 +887,10 @@ __device__ __forceinline__ void hv_tile(const HvArgs &a, int t, float4 *s_cl, fl
     const int cx = t % gxt, rest = t / gxt;
     const int ph = rest % STEP, band = rest / STEP;
     const int x0 = cx * 64, j0 = band * kHvRows;
+    // adaptive levels: a tile without a pixel of this launch's class is
+    // skipped (uniform branch)
+    if (a.v.ctl && !any_of_class(a.v, x0 + (int)threadIdx.x, ph + j0 * STEP, STEP, kHvRows))
+        return;
     HvSlot ring[5];
     HvRow<STEP> q0, q1;  // even and odd rows' loads, two rows in flight
     hv_issue<T, STEP>(a.h, x0, ph + (j0 - 2) * STEP, q0);
