@@ -305,7 +305,7 @@ int sv_atrous(const sv_rgb *c_in, const float *var_in, const sv_gbuf *g,
  * not overlap inputs or outputs) the horizontal result is written there
  * and read back by a second kernel.  With scratch NULL both passes run in
  * one kernel and the horizontal result never leaves the chip (steps 1, 2,
- * 4, 8, 16; other steps return SV_EUNSUPPORTED); the outputs are bitwise
+ * 4, 8, 16, 32; other steps return SV_EUNSUPPORTED); the outputs are bitwise
  * those of the two-kernel form. */
 int sv_atrous_sep(const sv_rgb *c_in, const float *var_in, const sv_gbuf *g,
                   const float *kappa, const sv_rgb *scratch,
@@ -357,7 +357,7 @@ int sv_blur_control(const float *roughness, const float *shadow_angle,
  * shifted separable pixel takes the vertical pass of the horizontal result
  * at its own step.  Two launches over the image, one per step; each pixel
  * is written by one.  `scratch`: as sv_atrous_sep, separable only (NULL
- * selects the fused form, steps up to 16, so levels 0..3; SV_EUNSUPPORTED
+ * selects the fused form, steps up to 32, so levels 0..4; SV_EUNSUPPORTED
  * above).  `ctl` (one byte per pixel, pitch d.pitch) must not overlap the
  * outputs.  Other arguments and errors as sv_atrous; level outside 0..12
  * is SV_EINVAL. */

@@ -149,8 +149,8 @@ extern "C" int sv_atrous_adaptive(const sv_rgb *c_in, const float *var_in, const
         for (const span &so : outs)
             if (overlaps(so, cs)) return SV_EALIAS;
     }
-    // separable launches at steps above 16 need the two-pass form
-    if (separable && !scratch && level + 1 > 4) return SV_EUNSUPPORTED;
+    // separable launches at steps above 32 need the two-pass form
+    if (separable && !scratch && level + 1 > 5) return SV_EUNSUPPORTED;
     const bool unit = (p->flags & SV_A_UNIT_WEIGHTS) != 0;
     hipStream_t s = as_stream(stream);
     for (int cls = 0; cls < 2; ++cls) {

@@ -186,10 +186,11 @@ enum { kDir2D = 0, kDirH = 1, kDirV = 2 };
 // Staged prefilter entry of a pixel outside the image or without a surface.
 constexpr float kNoVar = __builtin_nanf("");
 
-// Lattice rows per thread of a tile: two, except at the largest step, where
-// the 2 x 16-column halo on each side would otherwise hold the tile's LDS
-// footprint to two resident workgroups per CU (measured: 53 instead of 74
-// us per 1080p level; one row per thread at step 8 gained nothing).
+// Lattice rows per thread of a tile: two, except at the largest steps,
+// where the 2 x step-column halo on each side would otherwise hold the
+// tile's LDS footprint to two resident workgroups per CU (measured at step
+// 16: 53 instead of 74 us per 1080p level; one row per thread at step 8
+// gained nothing).  Step 32 is the coarser start of the fifth level.
 constexpr int tile_py(int step) { return step >= 16 ? 1 : 2; }
 
 template <int STEP, int PY, int DIR, bool WANT_VAR>
@@ -972,6 +973,7 @@ bool launch_hv(const HvArgs &a, bool unit, hipStream_t s) {
     case 4: launch_hv_step<T, 4>(a, mode, s); return true;
     case 8: launch_hv_step<T, 8>(a, mode, s); return true;
     case 16: launch_hv_step<T, 16>(a, mode, s); return true;
+    case 32: launch_hv_step<T, 32>(a, mode, s); return true;
     default: return false;
     }
 }
@@ -1009,6 +1011,7 @@ void launch_steps(const AtrousArgs &a, TileCfg cfg, hipStream_t s) {
     case 4: launch_tile<T, 4, MODE, WANT_VAR, DIR>(a, cfg, s); return;
     case 8: launch_tile<T, 8, MODE, WANT_VAR, DIR>(a, cfg, s); return;
     case 16: launch_tile<T, 16, MODE, WANT_VAR, DIR>(a, cfg, s); return;
+    case 32: launch_tile<T, 32, MODE, WANT_VAR, DIR>(a, cfg, s); return;
     default: {  // other steps: direct loads (not available batched)
         if (record_pass<AtrousArgs>(nullptr, a, 0)) return;
         dim3 grid((a.w + 63) / 64, (a.h + 3) / 4);

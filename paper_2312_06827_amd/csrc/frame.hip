@@ -65,13 +65,13 @@ extern "C" int sv_denoise_frame(const sv_frame_in *in, sv_denoiser *st, sv_dims 
         if (in->blur_ctl) {
             // adaptive levels: launches at steps 2^i and 2^(i+1); separable
             // ones fused while both steps have the fused form
-            const bool fused = (2 << i) <= 16;
+            const bool fused = (2 << i) <= 32;
             const sv_rgb *scr = p->separable && !fused ? &st->scratch : nullptr;
             rc = sv_atrous_adaptive(&c, v, &in->g, kappa, in->blur_ctl, scr, &dst, dst_var, i,
                                     p->separable, d, t, &ap, stream);
         } else {
             // separable levels: the fused form (no scratch) where the step has one
-            const bool fused = (1 << i) <= 16;
+            const bool fused = (1 << i) <= 32;
             rc = p->separable
                      ? sv_atrous_sep(&c, v, &in->g, kappa, fused ? nullptr : &st->scratch, &dst,
                                      dst_var, 1 << i, d, t, &ap, stream)

@@ -247,7 +247,7 @@ class Denoiser:
                 p.persistent, p.blocks_per_cu = self.tiles[i]
             if inp.blur_ctl is not None:
                 with tm(f"atrous_adaptive{i}"):
-                    fused = (2 << i) <= 16
+                    fused = (2 << i) <= 32
                     lib.sv_atrous_adaptive(c, v, inp.g, inp.blur_ctl,
                                            self.scratch if cfg.separable and not fused else None,
                                            dst, dst_var, i, cfg.separable, p, kappa=kappa,
@@ -255,7 +255,7 @@ class Denoiser:
             elif cfg.separable:
                 with tm(f"atrous_sep{i}"):
                     # the fused single-kernel form where the step has one
-                    lib.sv_atrous_sep(c, v, inp.g, None if (1 << i) <= 16 else self.scratch, dst,
+                    lib.sv_atrous_sep(c, v, inp.g, None if (1 << i) <= 32 else self.scratch, dst,
                                       dst_var, 1 << i, p, kappa=kappa, stream=stream)
             else:
                 with tm(f"atrous{i}"):

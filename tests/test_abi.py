@@ -119,9 +119,9 @@ def test_atrous_validation_and_aliasing(so):
     g2.nz = None
     assert so.sv_atrous(r(rgb(A)), var, r(g2), None, r(rgb(B)), None, 1, D, L.SV_F32, r(AP),
                         None) == L.SV_EINVAL
-    # without scratch (the fused form) only steps 1..16 are available; with
+    # without scratch (the fused form) only steps 1..32 are available; with
     # scratch, it must not alias the output
-    assert so.sv_atrous_sep(r(rgb(A)), var, r(g), None, None, r(rgb(B)), None, 32, D, L.SV_F32,
+    assert so.sv_atrous_sep(r(rgb(A)), var, r(g), None, None, r(rgb(B)), None, 64, D, L.SV_F32,
                             r(AP), None) == L.SV_EUNSUPPORTED
     assert so.sv_atrous_sep(r(rgb(A)), var, r(g), None, L.sv_rgb(B, None, B), r(rgb(B)), None,
                             1, D, L.SV_F32, r(AP), None) == L.SV_EINVAL

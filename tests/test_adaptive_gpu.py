@@ -85,10 +85,6 @@ def test_adaptive_level_separable(H, W, level):
         scratch = None if fused else empty_like_dev((3, H, W), P)
         args = (dev(c, P), dev(var, P), g, dev(ctl, P, torch.uint8), scratch, out, vo, level,
                 True, L.AtrousParams())
-        if fused and level >= 4:  # a step-32 launch has no fused form
-            with pytest.raises(L.SVError):
-                L.sv_atrous_adaptive(*args)
-            continue
         L.sv_atrous_adaptive(*args)
         assert rel_err(host(out), rc) <= TOL32
         assert rel_err(host(vo), rv) <= TOL32
@@ -144,3 +140,19 @@ def test_driver_with_adaptive_levels(sep):
     say(f"  worst {worst_all:.2e}")
     # every band of the roughness table is present in the scene
     assert set(np.unique(ctl & 15)) >= {0, 1, 15} and (ctl >> 4).any()
+
+
+def test_adaptive_separable_beyond_the_fused_steps():
+    """Level 5 shifted is step 64: only the two-pass form has it."""
+    H, W = 40, 70
+    c, var, z, dzdx, dzdy, n = _atrous_inputs(H, W, 990)
+    g = gbuf_dev(z, dzdx, dzdy, n)
+    ctl = dev(np.full((H, W), 31, np.uint8), None, torch.uint8)
+    out, vo = empty_like_dev((3, H, W)), empty_like_dev((H, W))
+    with pytest.raises(L.SVError):
+        L.sv_atrous_adaptive(dev(c), dev(var), g, ctl, None, out, vo, 5, True, L.AtrousParams())
+    L.sv_atrous_adaptive(dev(c), dev(var), g, ctl, empty_like_dev((3, H, W)), out, vo, 5, True,
+                         L.AtrousParams())
+    rc, rv = O.atrous_adaptive(c, var, z, dzdx, dzdy, n, np.full((H, W), 31, np.uint8), 5,
+                               separable=True)
+    assert rel_err(host(out), rc) <= TOL32

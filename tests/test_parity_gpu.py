@@ -371,7 +371,7 @@ def test_atrous_sep_fused_equals_two_pass(H, W, dtype):
     dv = lambda a: dev(a, P, dtype)
     g = L.GBuf(dv(z), dv(dzdx), dv(dzdy), dv(n))
     kappa = np.random.default_rng(H).uniform(0.5, 2.0, (H, W)).astype(np.float32)
-    for step in (1, 2, 4, 8, 16):
+    for step in (1, 2, 4, 8, 16, 32):
         for unit, want_var, inv, kap in [(False, True, False, None), (False, False, True, kappa),
                                          (True, True, False, None), (False, True, False, kappa)]:
             say(f"sep fused {H}x{W} {dtype} step={step} unit={unit} var={want_var} inv={inv} "
