@@ -1,0 +1,150 @@
+"""FP64 oracle of the temporal gradient (A-SVGF), the answer to temporal lag
+that the paper's related work names (Section 2): surface samples of the
+previous frame are carried forward into the current one, shaded again, and
+the difference between the two shadings drives the temporal blend.
+
+TEST INFRASTRUCTURE ONLY: loaded by the test suite, the smoke check and the
+CPU-baseline leg of the benchmark, never by the product path; it shares no
+code with the HIP library.
+
+The paper describes the method in one paragraph without formulas; the
+steps below are the readings used (each is stated where it is made):
+
+1. One sample per 3x3 stratum of the previous frame: pixel q = (3 sx + k %
+   3, 3 sy + k // 3) with k the stratum's pick (0..8, drawn by the
+   renderer, an input); a pick outside the image gives no sample.
+2. Forward projection: q lands on pixel p = floor(q + fmv(q) + 1/2) of the
+   current frame (fmv: forward motion in pixels).  The sample is kept if p
+   is inside the image, the current pixel has a surface, and the depth of
+   the moved point fz(q) agrees with the current depth z(p) as in the
+   reprojection test, |z(p) - fz(q)| <= tau_z z(p) (binary32, as there).
+3. The sample goes to the current 3x3 cell of p; when several samples land
+   in one cell, the one of the lowest stratum index (row-major) is kept.
+4. Gradient sample: delta = L(reshade(q)) - L(prev(q)) and
+   norm = max(L(reshade(q)), L(prev(q))), L the Rec. 709 luminance, reshade
+   the sample traced again in the current frame with its old random
+   numbers.
+5. Dense gradient: a normalized convolution over the cells, cascading
+   `levels` 5x5 a-trous B3 kernels at cell steps 1, 2, 4, ... with a depth
+   edge weight exp(-|z_c - z_d| / (sigma_z |dz . o| + eps)) between the
+   cells' centre pixels (o the offset in pixels); delta, norm and the
+   sample indicator are filtered alike and divided at the end.
+6. lambda = min(1, |delta_hat| / norm_hat) (0 where norm_hat is 0 or no
+   sample reached the cell), and the blend factor of every pixel of the
+   cell is alpha' = (1 - lambda) alpha + lambda: the history is dropped
+   where the shading changed.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = ["cells_of", "gradient_samples", "reconstruct", "temporal_gradient"]
+
+_W = (0.2126, 0.7152, 0.0722)
+_H1 = np.array([1.0, 4.0, 6.0, 4.0, 1.0]) / 16.0
+
+
+def _luma(rgb):
+    rgb = np.asarray(rgb, np.float64)
+    return _W[0] * rgb[0] + _W[1] * rgb[1] + _W[2] * rgb[2]
+
+
+def cells_of(H, W):
+    """Cell (and stratum) grid size: ceil(H / 3) x ceil(W / 3)."""
+    return (H + 2) // 3, (W + 2) // 3
+
+
+def _empty(z):
+    return not (z > 0.0) or not np.isfinite(z)
+
+
+def gradient_samples(prev_rgb, reshade_rgb, fmv, fz, pick, z, tau_z=0.1):
+    """Steps 1-4.  Returns (delta, norm, present, src): per current cell the
+    gradient sample, whether one landed, and the stratum index it came from
+    (-1 for none)."""
+    H, W = z.shape
+    CH, CW = cells_of(H, W)
+    Lp, Lr = _luma(prev_rgb), _luma(reshade_rgb)
+    f32 = np.float32
+    src = -np.ones((CH, CW), np.int64)
+    for sy in range(CH):
+        for sx in range(CW):
+            k = int(pick[sy, sx])
+            qx, qy = 3 * sx + k % 3, 3 * sy + k // 3
+            if qx >= W or qy >= H:
+                continue
+            px = int(np.floor(float(qx) + float(fmv[0][qy, qx]) + 0.5))
+            py = int(np.floor(float(qy) + float(fmv[1][qy, qx]) + 0.5))
+            if not (0 <= px < W and 0 <= py < H):
+                continue
+            zc = f32(z[py, px])
+            if _empty(zc):
+                continue
+            # the reprojection's depth test, in binary32 with its order
+            if not (abs(f32(f32(fz[qy, qx]) - zc)) <= f32(f32(tau_z) * zc)):
+                continue
+            cy, cx = py // 3, px // 3
+            s = sy * CW + sx
+            if src[cy, cx] < 0 or s < src[cy, cx]:
+                src[cy, cx] = s
+    delta = np.zeros((CH, CW))
+    norm = np.zeros((CH, CW))
+    for cy in range(CH):
+        for cx in range(CW):
+            s = src[cy, cx]
+            if s < 0:
+                continue
+            sy, sx = divmod(int(s), CW)
+            k = int(pick[sy, sx])
+            qx, qy = 3 * sx + k % 3, 3 * sy + k // 3
+            delta[cy, cx] = Lr[qy, qx] - Lp[qy, qx]
+            norm[cy, cx] = max(Lr[qy, qx], Lp[qy, qx])
+    return delta, norm, (src >= 0).astype(np.float64), src
+
+
+def reconstruct(delta, norm, present, z, dzdx, dzdy, levels=3, sigma_z=1.0, eps_z=1e-10):
+    """Step 5 and the ratio of step 6: lambda per cell."""
+    H, W = z.shape
+    CH, CW = delta.shape
+    cyy = np.minimum(3 * np.arange(CH) + 1, H - 1)
+    cxx = np.minimum(3 * np.arange(CW) + 1, W - 1)
+    zc = np.asarray(z, np.float64)[np.ix_(cyy, cxx)]
+    gx = np.asarray(dzdx, np.float64)[np.ix_(cyy, cxx)]
+    gy = np.asarray(dzdy, np.float64)[np.ix_(cyy, cxx)]
+    a = [delta * present, norm * present, present.copy()]
+    for lvl in range(levels):
+        s = 1 << lvl
+        out = [np.zeros_like(x) for x in a]
+        for cy in range(CH):
+            for cx in range(CW):
+                acc = [0.0, 0.0, 0.0]
+                for b in range(-2, 3):
+                    for c in range(-2, 3):
+                        ny, nx = cy + b * s, cx + c * s
+                        if not (0 <= ny < CH and 0 <= nx < CW):
+                            continue
+                        # offset between the centre pixels, in pixels
+                        ox, oy = 3.0 * c * s, 3.0 * b * s
+                        den = sigma_z * abs(gx[cy, cx] * ox + gy[cy, cx] * oy) + eps_z
+                        w = _H1[b + 2] * _H1[c + 2] * np.exp(-abs(zc[cy, cx] - zc[ny, nx]) / den)
+                        for i in range(3):
+                            acc[i] += w * a[i][ny, nx]
+                for i in range(3):
+                    out[i][cy, cx] = acc[i]
+        a = out
+    with np.errstate(divide="ignore", invalid="ignore"):
+        d_hat = np.where(a[2] > 0, a[0] / a[2], 0.0)
+        n_hat = np.where(a[2] > 0, a[1] / a[2], 0.0)
+        lam = np.where(n_hat > 0, np.minimum(1.0, np.abs(d_hat) / n_hat), 0.0)
+    return lam
+
+
+def temporal_gradient(prev_rgb, reshade_rgb, fmv, fz, pick, z, dzdx, dzdy, alpha=0.2,
+                      tau_z=0.1, sigma_z=1.0, levels=3):
+    """The whole gradient: returns (alpha_map (H, W), lambda (cells))."""
+    delta, norm, present, _ = gradient_samples(prev_rgb, reshade_rgb, fmv, fz, pick, z, tau_z)
+    lam = reconstruct(delta, norm, present, z, dzdx, dzdy, levels, sigma_z)
+    H, W = z.shape
+    per_px = lam[np.arange(H)[:, None] // 3, np.arange(W)[None, :] // 3]
+    return (1.0 - per_px) * alpha + per_px, lam

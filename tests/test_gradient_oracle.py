@@ -1,0 +1,134 @@
+"""Pins of the temporal-gradient oracle (oracle/gradient.py) against closed
+forms, brute force and a library routine (CPU only)."""
+
+import numpy as np
+import pytest
+from scipy.ndimage import correlate
+
+from oracle import gradient as G
+
+
+def _frame(H, W, seed=0):
+    r = np.random.default_rng(seed)
+    prev = r.uniform(0.1, 1.0, (3, H, W))
+    z = np.full((H, W), 5.0)
+    dz = np.zeros((H, W))
+    pick = r.integers(0, 9, G.cells_of(H, W)).astype(np.uint8)
+    return prev, z, dz, pick
+
+
+def test_no_change_gives_no_gradient():
+    H, W = 20, 26
+    prev, z, dz, pick = _frame(H, W)
+    fmv = np.zeros((2, H, W))
+    am, lam = G.temporal_gradient(prev, prev, fmv, z, pick, z, dz, dz, alpha=0.2)
+    assert np.all(lam == 0.0)
+    np.testing.assert_array_equal(am, 0.2)
+
+
+@pytest.mark.parametrize("scale,expect", [(2.0, 0.5), (0.0, 1.0), (0.5, 0.5)])
+def test_uniform_relative_change_gives_its_ratio(scale, expect):
+    # every sample changes by the same factor, so |delta| / norm is the
+    # same ratio everywhere and the normalized convolution keeps it
+    H, W = 21, 24
+    prev, z, dz, pick = _frame(H, W, 1)
+    fmv = np.zeros((2, H, W))
+    am, lam = G.temporal_gradient(prev, scale * prev, fmv, z, pick, z, dz, dz, alpha=0.2)
+    np.testing.assert_allclose(lam, expect, rtol=1e-13)
+    np.testing.assert_allclose(am, (1 - expect) * 0.2 + expect, rtol=1e-13)
+
+
+def test_projection_shift_conflict_and_depth_test():
+    H, W = 9, 12  # 3 x 4 cells
+    prev, z, dz, pick = _frame(H, W, 2)
+    pick[:] = 4  # the centre pixel of each stratum
+    fmv = np.zeros((2, H, W))
+    fmv[0] += 3.0  # one cell to the right
+    d, n, present, src = G.gradient_samples(prev, prev, fmv, z, pick, z)
+    CW = 4
+    exp = -np.ones((3, 4), np.int64)
+    for sy in range(3):
+        for sx in range(3):  # the last column's samples leave the image
+            exp[sy, sx + 1] = sy * CW + sx
+    np.testing.assert_array_equal(src, exp)
+    # two strata onto one cell: the lower index wins
+    fmv2 = np.zeros((2, H, W))
+    fmv2[0, 1, 4] = -3.0  # stratum (0, 1) moves onto cell (0, 0)
+    _, _, _, src2 = G.gradient_samples(prev, prev, fmv2, z, pick, z)
+    assert src2[0, 0] == 0 and src2[0, 1] == -1
+    fmv3 = np.zeros((2, H, W))
+    fmv3[0, 1, 1] = 3.0  # stratum (0, 0) moves onto cell (0, 1): index 0 beats 1
+    _, _, _, src3 = G.gradient_samples(prev, prev, fmv3, z, pick, z)
+    assert src3[0, 1] == 0 and src3[0, 0] == -1
+    # rounding to the nearest pixel: +1.49 stays in the cell, +1.5 crosses
+    fmv4 = np.zeros((2, H, W))
+    fmv4[0, 1, 1] = 1.49
+    _, _, _, s4 = G.gradient_samples(prev, prev, fmv4, z, pick, z)
+    assert s4[0, 0] == 0
+    fmv4[0, 1, 1] = 1.5
+    _, _, _, s4 = G.gradient_samples(prev, prev, fmv4, z, pick, z)
+    # cell (0, 0) is left empty; cell (0, 1) keeps stratum 0 over its own stratum 1
+    assert s4[0, 0] == -1 and s4[0, 1] == 0
+    # a moved depth that disagrees with the current one drops the sample
+    fz = z.copy()
+    fz[1, 1] = 10.0
+    _, _, pr, _ = G.gradient_samples(prev, prev, np.zeros((2, H, W)), fz, pick, z)
+    assert pr[0, 0] == 0 and pr.sum() == 11
+    # a pick outside the image gives no sample (W = 11: the last stratum is two wide)
+    H2, W2 = 9, 11
+    prev2, z2, _, pick2 = _frame(H2, W2, 3)
+    pick2[:] = 2  # third column of each stratum
+    _, _, pr2, _ = G.gradient_samples(prev2, prev2, np.zeros((2, H2, W2)), z2, pick2, z2)
+    assert pr2[:, 3].sum() == 0 and pr2[:, :3].sum() == 9
+
+
+def test_samples_are_the_luminance_difference_and_maximum():
+    H, W = 6, 6
+    prev, z, dz, pick = _frame(H, W, 4)
+    re = np.random.default_rng(5).uniform(0.1, 1.0, (3, H, W))
+    pick[:] = np.array([[0, 8], [4, 2]], np.uint8)
+    d, n, present, src = G.gradient_samples(prev, re, np.zeros((2, H, W)), z, pick, z)
+    L = lambda c: 0.2126 * c[0] + 0.7152 * c[1] + 0.0722 * c[2]
+    for (cy, cx), k in np.ndenumerate(pick):
+        qy, qx = 3 * cy + k // 3, 3 * cx + k % 3
+        assert d[cy, cx] == pytest.approx(L(re[:, qy, qx]) - L(prev[:, qy, qx]), rel=1e-14)
+        assert n[cy, cx] == pytest.approx(max(L(re[:, qy, qx]), L(prev[:, qy, qx])), rel=1e-14)
+
+
+def test_reconstruction_on_flat_depth_is_the_normalized_b3_cascade():
+    # constant depth makes every edge weight 1: the cascade is the
+    # correlation with the dilated B3 kernels (scipy), divided at the end
+    r = np.random.default_rng(6)
+    CH, CW = 11, 14
+    H, W = 3 * CH, 3 * CW
+    z = np.full((H, W), 4.0)
+    dz = np.zeros((H, W))
+    present = (r.random((CH, CW)) < 0.6).astype(np.float64)
+    delta = r.uniform(-1, 1, (CH, CW)) * present
+    norm = r.uniform(0.5, 2, (CH, CW)) * present
+    lam = G.reconstruct(delta, norm, present, z, dz, dz, levels=3)
+    h = np.array([1, 4, 6, 4, 1]) / 16.0
+    a = [delta, norm, present]
+    for lvl in range(3):
+        s = 1 << lvl
+        k1 = np.zeros(4 * s + 1)
+        k1[::s] = h
+        a = [correlate(x, np.outer(k1, k1), mode="constant") for x in a]
+    ref = np.where(a[2] > 0, np.minimum(1, np.abs(a[0] / a[2]) / (a[1] / a[2])), 0)
+    np.testing.assert_allclose(lam, ref, rtol=1e-12, atol=1e-15)
+
+
+def test_depth_edges_keep_gradients_apart():
+    # two depth planes far apart: a gradient on one side does not leak
+    CH, CW = 6, 10
+    H, W = 3 * CH, 3 * CW
+    z = np.full((H, W), 4.0)
+    z[:, W // 2:] = 40.0
+    dz = np.zeros((H, W))
+    present = np.ones((CH, CW))
+    delta = np.zeros((CH, CW))
+    delta[:, :CW // 2] = 1.0
+    norm = np.ones((CH, CW))
+    lam = G.reconstruct(delta, norm, present, z, dz, dz, levels=3)
+    np.testing.assert_allclose(lam[:, :CW // 2], 1.0, rtol=1e-12)
+    np.testing.assert_allclose(lam[:, CW // 2:], 0.0, atol=1e-12)
