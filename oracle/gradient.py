@@ -14,10 +14,12 @@ steps below are the readings used (each is stated where it is made):
    3, 3 sy + k // 3) with k the stratum's pick (0..8, drawn by the
    renderer, an input); a pick outside the image gives no sample.
 2. Forward projection: q lands on pixel p = floor(q + fmv(q) + 1/2) of the
-   current frame (fmv: forward motion in pixels).  The sample is kept if p
-   is inside the image, the current pixel has a surface, and the depth of
-   the moved point fz(q) agrees with the current depth z(p) as in the
-   reprojection test, |z(p) - fz(q)| <= tau_z z(p) (binary32, as there).
+   current frame (fmv: forward motion in pixels; the two additions are
+   binary32 roundings, the device's precision, since they decide an
+   integer).  The sample is kept if p is inside the image, the current
+   pixel has a surface, and the depth of the moved point fz(q) agrees with
+   the current depth z(p) as in the reprojection test,
+   |z(p) - fz(q)| <= tau_z z(p) (binary32, as there).
 3. The sample goes to the current 3x3 cell of p; when several samples land
    in one cell, the one of the lowest stratum index (row-major) is kept.
 4. Gradient sample: delta = L(reshade(q)) - L(prev(q)) and
@@ -74,10 +76,11 @@ def gradient_samples(prev_rgb, reshade_rgb, fmv, fz, pick, z, tau_z=0.1):
             qx, qy = 3 * sx + k % 3, 3 * sy + k // 3
             if qx >= W or qy >= H:
                 continue
-            px = int(np.floor(float(qx) + float(fmv[0][qy, qx]) + 0.5))
-            py = int(np.floor(float(qy) + float(fmv[1][qy, qx]) + 0.5))
-            if not (0 <= px < W and 0 <= py < H):
+            tx = f32(f32(qx) + f32(fmv[0][qy, qx])) + f32(0.5)
+            ty = f32(f32(qy) + f32(fmv[1][qy, qx])) + f32(0.5)
+            if not (0.0 <= tx < W and 0.0 <= ty < H):  # NaN fails too
                 continue
+            px, py = int(np.floor(tx)), int(np.floor(ty))
             zc = f32(z[py, px])
             if _empty(zc):
                 continue
