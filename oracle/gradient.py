@@ -12,7 +12,8 @@ steps below are the readings used (each is stated where it is made):
 
 1. One sample per 3x3 stratum of the previous frame: pixel q = (3 sx + k %
    3, 3 sy + k // 3) with k the stratum's pick (0..8, drawn by the
-   renderer, an input); a pick outside the image gives no sample.
+   renderer, an input); a pick outside the image, or above 8, gives no
+   sample.
 2. Forward projection: q lands on pixel p = floor(q + fmv(q) + 1/2) of the
    current frame (fmv: forward motion in pixels; the two additions are
    binary32 roundings, the device's precision, since they decide an
@@ -74,7 +75,7 @@ def gradient_samples(prev_rgb, reshade_rgb, fmv, fz, pick, z, tau_z=0.1):
         for sx in range(CW):
             k = int(pick[sy, sx])
             qx, qy = 3 * sx + k % 3, 3 * sy + k // 3
-            if qx >= W or qy >= H:
+            if k > 8 or qx >= W or qy >= H:
                 continue
             tx = f32(f32(qx) + f32(fmv[0][qy, qx])) + f32(0.5)
             ty = f32(f32(qy) + f32(fmv[1][qy, qx])) + f32(0.5)
