@@ -473,6 +473,50 @@ int sv_atrous_kappa_grad(const sv_rgb *c_in, const float *var_in, const sv_gbuf 
                          float *d_kappa, int32_t step, sv_dims d, sv_dtype t,
                          const sv_atrous_params *p, sv_stream stream);
 
+/* ---- temporal gradient (A-SVGF, related work of Section 2) ------------- */
+
+/* The answer to temporal lag that the paper names: surface samples of the
+ * previous frame are carried forward and traced again in the current frame
+ * with their old random numbers, and the change of their shading raises
+ * the temporal blend factor.  Readings (the paper gives no formulas):
+ *  1. one sample per 3x3 stratum of the previous frame, pixel
+ *     q = (3 sx + k % 3, 3 sy + k / 3), k = pick[sy * CW + sx] (0..8; a k
+ *     above 8 or a q outside the image gives none); CW = ceil(w / 3),
+ *     CH = ceil(h / 3);
+ *  2. it lands on p = floor(q + fmv(q) + 1/2) (binary32 additions) if p is
+ *     inside the image, has a surface, and |z(p) - fz(q)| <= tau_z z(p);
+ *  3. in the 3x3 cell of p the lowest stratum index wins;
+ *  4. sample: delta = L(reshade(q)) - L(prev(q)), norm = the larger of the
+ *     two luminances;
+ *  5. (delta, norm, present) are filtered alike by `levels` 5x5 B3 a-trous
+ *     passes over the cells (cell steps 1, 2, 4, ...) with the depth weight
+ *     exp(-|z_c - z_d| / (sigma_z |grad z . o| + 1e-10)) between the cells'
+ *     centre pixels (3 c + 1, clamped; o the offset in pixels);
+ *  6. lambda = min(1, |delta| / norm) of the filtered sums (0 where nothing
+ *     reached the cell), and every pixel of the cell gets
+ *     alpha_map = alpha + lambda (1 - alpha) - for sv_temporal's alpha_map.
+ * prev, reshade, fmvx/fmvy (forward motion of the previous frame's pixels),
+ * fz (view depth of the moved point) and g->z, g->dzdx, g->dzdy have the
+ * storage type and dims d; pick is CH x CW bytes, contiguous; alpha_map is
+ * a binary32 plane of dims d; lambda (optional) CH x CW binary32,
+ * contiguous; work: sv_grad_work_bytes(d) bytes of device memory, any
+ * contents.  Outputs and work must not overlap inputs (SV_EALIAS). */
+typedef struct {
+    float alpha;    /* blend factor where nothing changed (0.2) */
+    float tau_z;    /* depth test of the landing pixel (0.1) */
+    float sigma_z;  /* depth edge weight of the reconstruction (1) */
+    int32_t levels; /* reconstruction levels, 0..8 (3) */
+} sv_grad_params;
+
+size_t sv_grad_work_bytes(sv_dims d);
+
+int sv_temporal_gradient(const sv_rgb *prev, const sv_rgb *reshade,
+                         const void *fmvx, const void *fmvy, const void *fz,
+                         const uint8_t *pick, const sv_gbuf *g,
+                         float *alpha_map, float *lambda, void *work,
+                         sv_dims d, sv_dtype t, const sv_grad_params *p,
+                         sv_stream stream);
+
 /* ---- composition of the channels (Section 3, step 7) ------------------ */
 
 /* The paper denoises shadows and indirect specular light as separate
@@ -599,8 +643,8 @@ void sv_batch_destroy(sv_batch *b);
 /* ABI self-check for bindings: writes sizeof of sv_dims, sv_rgb, sv_gbuf,
  * sv_tm_params, sv_temporal_io, sv_temporal_params, sv_variance_params,
  * sv_atrous_params, sv_denoiser, sv_frame_in, sv_frame_params, sv_mlp,
- * sv_adam_params and sv_blur_rule (in that order, at most n of them) and
- * returns how many
+ * sv_adam_params, sv_blur_rule and sv_grad_params (in that order, at most n
+ * of them) and returns how many
  * there are; SV_EINVAL for sizes == NULL or n < 0. */
 int sv_struct_sizes(size_t *sizes, int32_t n);
 

@@ -63,7 +63,8 @@ extern "C" int sv_struct_sizes(size_t *sizes, int32_t n) {
                           sizeof(sv_variance_params), sizeof(sv_atrous_params),
                           sizeof(sv_denoiser),      sizeof(sv_frame_in),
                           sizeof(sv_frame_params),  sizeof(sv_mlp),
-                          sizeof(sv_adam_params),   sizeof(sv_blur_rule)};
+                          sizeof(sv_adam_params),   sizeof(sv_blur_rule),
+                          sizeof(sv_grad_params)};
     const int32_t k = (int32_t)(sizeof(all) / sizeof(all[0]));
     if (!sizes || n < 0) return SV_EINVAL;
     for (int32_t i = 0; i < n && i < k; ++i) sizes[i] = all[i];

@@ -1,0 +1,226 @@
+// Temporal gradient (A-SVGF), the answer to temporal lag that the paper's
+// related work names (Section 2): one surface sample per 3x3 stratum of the
+// previous frame is carried forward into the current frame and traced
+// again there with its old random numbers; the change of its shading,
+// reconstructed densely over 3x3 cells, raises the temporal blend factor
+// where the lighting changed.
+//
+// Passes (one stream, graph-capturable: the key clear is a kernel):
+//   grad_clear_k    cell keys := none
+//   grad_project_k  per stratum: land the sample, atomicMin of its index
+//                   on the cell's key (the lowest stratum index wins)
+//   grad_gather_k   per cell: the winning sample's luminance difference and
+//                   maximum, and a presence flag
+//   grad_atrous_k   `levels` 5x5 B3 a-trous passes over the cells with a
+//                   depth edge weight, on (delta, norm, present) alike
+//   grad_alpha_k    per pixel: lambda = min(1, |delta| / norm) of its cell,
+//                   alpha' = alpha + lambda (1 - alpha)
+#include "sv_internal.h"
+
+namespace sv {
+
+namespace {
+
+struct GradArgs {
+    const void *pr, *pg, *pb, *rr, *rg, *rb;  // previous samples, traced again
+    const void *fmvx, *fmvy, *fz;
+    const uint8_t *pick;                      // cells: CH x CW, contiguous
+    const void *z, *dzdx, *dzdy;              // current G-buffer
+    float *alpha_map, *lambda;
+    uint32_t *key;
+    float4 *ca, *cb;                          // cell ping-pong
+    int w, h, pitch, cw, ch;
+    float alpha, tau_z, sigma_z;
+};
+
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+
+__device__ __forceinline__ int cells_x(int w) { return (w + 2) / 3; }
+
+__global__ __launch_bounds__(256) void grad_clear_k(uint32_t *key, int n) {
+    const int i = (int)blockIdx.x * 256 + (int)threadIdx.x;
+    if (i < n) key[i] = kNone;
+}
+
+// The stratum's sample pixel q and where it lands; false if it does not.
+template <typename T>
+__device__ __forceinline__ bool land(const GradArgs &a, int s, int &qx, int &qy, int &cell) {
+    const int sy = s / a.cw, sx = s - sy * a.cw;
+    const int k = a.pick[s];
+    qx = 3 * sx + k % 3;
+    qy = 3 * sy + k / 3;
+    if (k > 8 || qx >= a.w || qy >= a.h) return false;
+    const uint32_t q = (uint32_t)qy * (uint32_t)a.pitch + (uint32_t)qx;
+    // binary32 decisions with a fixed order, as the reprojection takes them
+    const float tx = __fadd_rn(__fadd_rn((float)qx, ldo<T>(a.fmvx, q)), 0.5f);
+    const float ty = __fadd_rn(__fadd_rn((float)qy, ldo<T>(a.fmvy, q)), 0.5f);
+    if (!(tx >= 0.f && tx < (float)a.w && ty >= 0.f && ty < (float)a.h)) return false;
+    const int px = (int)floorf(tx), py = (int)floorf(ty);
+    const uint32_t p = (uint32_t)py * (uint32_t)a.pitch + (uint32_t)px;
+    const float zc = ldo<T>(a.z, p);
+    if (empty_px(zc)) return false;
+    if (!(fabsf(__fsub_rn(ldo<T>(a.fz, q), zc)) <= __fmul_rn(a.tau_z, zc))) return false;
+    cell = (py / 3) * a.cw + px / 3;
+    return true;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void grad_project_k(GradArgs a) {
+    const int s = (int)blockIdx.x * 256 + (int)threadIdx.x;
+    if (s >= a.cw * a.ch) return;
+    int qx, qy, cell;
+    if (land<T>(a, s, qx, qy, cell)) atomicMin(&a.key[cell], (uint32_t)s);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void grad_gather_k(GradArgs a) {
+    const int c = (int)blockIdx.x * 256 + (int)threadIdx.x;
+    if (c >= a.cw * a.ch) return;
+    const uint32_t s = a.key[c];
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (s != kNone) {
+        const int sy = (int)s / a.cw, sx = (int)s - sy * a.cw;
+        const int k = a.pick[s];
+        const uint32_t q = (uint32_t)(3 * sy + k / 3) * (uint32_t)a.pitch + (uint32_t)(3 * sx + k % 3);
+        const float lp = luma(ldo<T>(a.pr, q), ldo<T>(a.pg, q), ldo<T>(a.pb, q));
+        const float lr = luma(ldo<T>(a.rr, q), ldo<T>(a.rg, q), ldo<T>(a.rb, q));
+        v = make_float4(lr - lp, fmaxf(lr, lp), 1.f, 0.f);
+    }
+    a.ca[c] = v;
+}
+
+__constant__ float kB3[5] = {0.0625f, 0.25f, 0.375f, 0.25f, 0.0625f};
+
+// One cascade level at cell step `step`: from `src` into `dst`.
+template <typename T>
+__global__ __launch_bounds__(256) void grad_atrous_k(GradArgs a, const float4 *src, float4 *dst,
+                                                    int step) {
+    const int c = (int)blockIdx.x * 256 + (int)threadIdx.x;
+    if (c >= a.cw * a.ch) return;
+    const int cy = c / a.cw, cx = c - cy * a.cw;
+    // the cells' centre pixels carry the depth
+    const auto centre = [&](int yy, int xx) {
+        return (uint32_t)min(3 * yy + 1, a.h - 1) * (uint32_t)a.pitch + (uint32_t)min(3 * xx + 1, a.w - 1);
+    };
+    const uint32_t o = centre(cy, cx);
+    const float zc = ldo<T>(a.z, o), gx = ldo<T>(a.dzdx, o), gy = ldo<T>(a.dzdy, o);
+    float sd = 0.f, sn = 0.f, sp = 0.f;
+#pragma unroll
+    for (int b = -2; b <= 2; ++b) {
+#pragma unroll
+        for (int e = -2; e <= 2; ++e) {
+            const int ny = cy + b * step, nx = cx + e * step;
+            if (ny < 0 || ny >= a.ch || nx < 0 || nx >= a.cw) continue;
+            const float ox = 3.f * (float)(e * step), oy = 3.f * (float)(b * step);
+            const float den = fmaf(a.sigma_z, fabsf(fmaf(gx, ox, gy * oy)), 1e-10f);
+            const float zd = ldo<T>(a.z, centre(ny, nx));
+            const float w = kB3[b + 2] * kB3[e + 2] * exp2f(-fabsf(zc - zd) * (kLog2e / den));
+            const float4 v = src[ny * a.cw + nx];
+            sd = fmaf(w, v.x, sd);
+            sn = fmaf(w, v.y, sn);
+            sp = fmaf(w, v.z, sp);
+        }
+    }
+    dst[c] = make_float4(sd, sn, sp, 0.f);
+}
+
+__global__ __launch_bounds__(256) void grad_alpha_k(GradArgs a, const float4 *cells) {
+    const int x = (int)blockIdx.x * 64 + (int)(threadIdx.x & 63);
+    const int y = (int)blockIdx.y * 4 + (int)(threadIdx.x >> 6);
+    if (x >= a.w || y >= a.h) return;
+    const int c = (y / 3) * a.cw + x / 3;
+    const float4 v = cells[c];
+    // |delta_hat| / norm_hat: the common normaliser cancels
+    const float lam = (v.z > 0.f && v.y > 0.f) ? fminf(1.f, fabsf(v.x) / v.y) : 0.f;
+    stf(a.alpha_map, (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x, fmaf(lam, 1.f - a.alpha, a.alpha));
+    if (a.lambda && x % 3 == 0 && y % 3 == 0) a.lambda[c] = lam;
+}
+
+struct GradWork {
+    size_t key, ca, cb, total;
+};
+
+GradWork work_layout(sv_dims d) {
+    const size_t n = (size_t)((d.w + 2) / 3) * (size_t)((d.h + 2) / 3);
+    GradWork g;
+    g.key = 0;
+    g.ca = (n * sizeof(uint32_t) + 255) & ~(size_t)255;
+    g.cb = g.ca + ((n * sizeof(float4) + 255) & ~(size_t)255);
+    g.total = g.cb + n * sizeof(float4);
+    return g;
+}
+
+template <typename T>
+void launch_gradient(GradArgs a, int levels, hipStream_t s) {
+    const int n = a.cw * a.ch;
+    const dim3 g1((unsigned)((n + 255) / 256));
+    hipLaunchKernelGGL(grad_clear_k, g1, dim3(256), 0, s, a.key, n);
+    hipLaunchKernelGGL(grad_project_k<T>, g1, dim3(256), 0, s, a);
+    hipLaunchKernelGGL(grad_gather_k<T>, g1, dim3(256), 0, s, a);
+    float4 *src = a.ca, *dst = a.cb;
+    for (int l = 0; l < levels; ++l) {
+        hipLaunchKernelGGL(grad_atrous_k<T>, g1, dim3(256), 0, s, a, (const float4 *)src, dst,
+                           1 << l);
+        float4 *tmp = src;
+        src = dst;
+        dst = tmp;
+    }
+    hipLaunchKernelGGL(grad_alpha_k, dim3((unsigned)((a.w + 63) / 64), (unsigned)((a.h + 3) / 4)),
+                       dim3(256), 0, s, a, (const float4 *)src);
+}
+
+}  // namespace
+
+}  // namespace sv
+
+extern "C" size_t sv_grad_work_bytes(sv_dims d) {
+    if (sv::check_dims(d) < 0) return 0;
+    return sv::work_layout(d).total;
+}
+
+extern "C" int sv_temporal_gradient(const sv_rgb *prev, const sv_rgb *reshade, const void *fmvx,
+                                    const void *fmvy, const void *fz, const uint8_t *pick,
+                                    const sv_gbuf *g, float *alpha_map, float *lambda, void *work,
+                                    sv_dims d, sv_dtype t, const sv_grad_params *p,
+                                    sv_stream stream) {
+    using namespace sv;
+    if (!valid_dtype(t)) return SV_EDTYPE;
+    const int dc = check_dims(d);
+    if (dc < 0 || !prev || !reshade || !g || !p) return SV_EINVAL;
+    if (p->levels < 0 || p->levels > 8 || !(p->tau_z >= 0.f) || !(p->sigma_z >= 0.f))
+        return SV_EINVAL;
+    if (dc == 1) return SV_OK;
+    const void *req[] = {prev->r, prev->g, prev->b, reshade->r, reshade->g, reshade->b, fmvx,
+                         fmvy, fz, pick, g->z, g->dzdx, g->dzdy, alpha_map, work};
+    for (const void *q : req)
+        if (!q) return SV_EINVAL;
+    const int cw = (d.w + 2) / 3, ch = (d.h + 2) / 3;
+    const size_t es = elem_size(t);
+    const GradWork wl = work_layout(d);
+    const span outs[] = {plane_span(alpha_map, d, 4),
+                         span{(uintptr_t)work, (uintptr_t)work + wl.total},
+                         lambda ? span{(uintptr_t)lambda, (uintptr_t)(lambda + (size_t)cw * ch)}
+                                : span{0, 0}};
+    const span ins[] = {plane_span(prev->r, d, es),    plane_span(prev->g, d, es),
+                        plane_span(prev->b, d, es),    plane_span(reshade->r, d, es),
+                        plane_span(reshade->g, d, es), plane_span(reshade->b, d, es),
+                        plane_span(fmvx, d, es),       plane_span(fmvy, d, es),
+                        plane_span(fz, d, es),         plane_span(g->z, d, es),
+                        plane_span(g->dzdx, d, es),    plane_span(g->dzdy, d, es),
+                        span{(uintptr_t)pick, (uintptr_t)(pick + (size_t)cw * ch)}};
+    for (int i = 0; i < 3; ++i) {
+        for (const span &si : ins)
+            if (overlaps(outs[i], si)) return SV_EALIAS;
+        for (int j = i + 1; j < 3; ++j)
+            if (overlaps(outs[i], outs[j])) return SV_EALIAS;
+    }
+    unsigned char *wb = (unsigned char *)work;
+    GradArgs a{prev->r,  prev->g, prev->b, reshade->r, reshade->g, reshade->b, fmvx, fmvy, fz, pick,
+               g->z,     g->dzdx, g->dzdy, alpha_map,  lambda,     (uint32_t *)(wb + wl.key),
+               (float4 *)(wb + wl.ca), (float4 *)(wb + wl.cb), d.w, d.h, d.pitch, cw, ch,
+               p->alpha, p->tau_z, p->sigma_z};
+    hipStream_t s = as_stream(stream);
+    if (t == SV_F32) launch_gradient<float>(a, p->levels, s);
+    else launch_gradient<half_t>(a, p->levels, s);
+    return hip_status(hipGetLastError());
+}

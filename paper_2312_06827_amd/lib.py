@@ -95,6 +95,11 @@ class sv_frame_in(ctypes.Structure):
                 ("albedo", sv_rgb), ("blur_ctl", _vp)]
 
 
+class sv_grad_params(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_float), ("tau_z", ctypes.c_float),
+                ("sigma_z", ctypes.c_float), ("levels", ctypes.c_int32)]
+
+
 class sv_blur_rule(ctypes.Structure):
     _fields_ = [("rough_shift", ctypes.c_float), ("angle_shift", ctypes.c_float),
                 ("rough_none", ctypes.c_float), ("rough_one", ctypes.c_float),
@@ -142,6 +147,9 @@ EXPORTS = {
     "sv_atrous_adaptive": ([_P(sv_rgb), _vp, _P(sv_gbuf), _vp, _vp, _P(sv_rgb), _P(sv_rgb), _vp,
                             ctypes.c_int32, ctypes.c_int32, sv_dims, ctypes.c_int,
                             _P(sv_atrous_params), _vp], ctypes.c_int),
+    "sv_grad_work_bytes": ([sv_dims], ctypes.c_size_t),
+    "sv_temporal_gradient": ([_P(sv_rgb), _P(sv_rgb), _vp, _vp, _vp, _vp, _P(sv_gbuf), _vp, _vp,
+                              _vp, sv_dims, ctypes.c_int, _P(sv_grad_params), _vp], ctypes.c_int),
     "sv_compose": ([_P(sv_rgb), _P(sv_rgb), _P(sv_rgb), _P(sv_rgb), sv_dims, ctypes.c_int, _vp],
                    ctypes.c_int),
     "sv_blur_control": ([_vp, _vp, _vp, sv_dims, _P(sv_blur_rule), _vp], ctypes.c_int),
@@ -472,6 +480,30 @@ def sv_blur_control(roughness: Optional[torch.Tensor], shadow_angle: Optional[to
     _check("sv_blur_control", load().sv_blur_control(
         _plane_ptr(roughness), _plane_ptr(shadow_angle), _plane_ptr(ctl), dims_of(ctl),
         ctypes.byref(rc), _stream(stream)))
+
+
+def gradient_workspace(like: torch.Tensor) -> torch.Tensor:
+    """Device workspace of sv_temporal_gradient for planes shaped like `like`."""
+    n = load().sv_grad_work_bytes(dims_of(like))
+    return torch.empty(max(n, 1), dtype=torch.uint8, device=like.device)
+
+
+def sv_temporal_gradient(prev: Planes, reshade: Planes, fmv: torch.Tensor, fz: torch.Tensor,
+                         pick: torch.Tensor, g: GBuf, alpha_map: torch.Tensor,
+                         work: torch.Tensor, alpha: float = 0.2, tau_z: float = 0.1,
+                         sigma_z: float = 1.0, levels: int = 3,
+                         lam: Optional[torch.Tensor] = None, stream=None):
+    """alpha_map <- the blend factor raised where the previous frame's
+    samples, traced again, changed.  pick and lam are (ceil(H/3), ceil(W/3))
+    contiguous."""
+    r = _planes3(prev)[0]
+    gc = g.c()
+    p = sv_grad_params(alpha, tau_z, sigma_z, levels)
+    _check("sv_temporal_gradient", load().sv_temporal_gradient(
+        ctypes.byref(_rgb(prev)), ctypes.byref(_rgb(reshade)), _plane_ptr(fmv[0]),
+        _plane_ptr(fmv[1]), _plane_ptr(fz), _plane_ptr(pick), ctypes.byref(gc),
+        _plane_ptr(alpha_map), _plane_ptr(lam), _plane_ptr(work), dims_of(r), dtype_of(r),
+        ctypes.byref(p), _stream(stream)))
 
 
 def sv_compose(direct: Planes, shadow: Optional[Planes], spec: Optional[Planes], out: Planes,

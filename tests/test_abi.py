@@ -270,7 +270,8 @@ def test_binding_structures_match_the_header(so):
     k = so.sv_struct_sizes(sizes, 32)
     mine = [L.sv_dims, L.sv_rgb, L.sv_gbuf, L.sv_tm_params, L.sv_temporal_io,
             L.sv_temporal_params, L.sv_variance_params, L.sv_atrous_params, L.sv_denoiser,
-            L.sv_frame_in, L.sv_frame_params, L.sv_mlp, L.sv_adam_params, L.sv_blur_rule]
+            L.sv_frame_in, L.sv_frame_params, L.sv_mlp, L.sv_adam_params, L.sv_blur_rule,
+            L.sv_grad_params]
     assert k == len(mine)
     for i, t in enumerate(mine):
         assert ctypes.sizeof(t) == sizes[i], (t.__name__, ctypes.sizeof(t), sizes[i])
