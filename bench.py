@@ -236,7 +236,7 @@ def generate_variant_frames(workers, want):
         jobs += [(uhd, f) for f in range(uhd.frames)]
     if "batched" in want:
         jobs += [(c, f) for f in range(n) for c in scfg]
-    if "channels" in want:
+    if want & {"channels", "gradient"}:
         jobs += [(ch, f) for f in range(ch.frames)]
     if workers <= 1:
         out = [_render(j) for j in jobs]
@@ -250,7 +250,7 @@ def generate_variant_frames(workers, want):
         res["batch_cfg"] = scfg
         res["batch"] = [out[k + f * 16:k + (f + 1) * 16] for f in range(n)]
         k += 16 * n
-    if "channels" in want:
+    if want & {"channels", "gradient"}:
         res["channels"] = out[k:k + ch.frames]
     return res
 
@@ -414,6 +414,50 @@ def variant_channels(torch, frames_np, warmup=CH_WARMUP, steps=CH_STEPS):
     return out
 
 
+def variant_gradient(torch, frames_np, warmup=CH_WARMUP, steps=CH_STEPS):
+    """The temporal gradient (A-SVGF) on the shadow channel, whose moving
+    shadows lag behind under a constant blend factor: throughput of the
+    shadow channel's frame with the gradient passes included, and RelMSE of
+    its output against the clean visibility, with and without the gradient."""
+    from paper_2312_06827_amd import learn
+    from paper_2312_06827_amd import lib as L
+    from paper_2312_06827_amd.pipeline import SHADOW, Denoiser, FrameInputs
+    H, W = WORKLOAD.height, WORKLOAD.width
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    ins, grads = [], []
+    for f, fr in enumerate(frames_np):
+        ins.append(FrameInputs.from_numpy({**fr, "rgb": fr["shadow"]}))
+        if f == 0:
+            grads.append(None)
+            continue
+        re = np.broadcast_to(fr["shadow_reshade"][None], (3, H, W))
+        grads.append({"prev": t(frames_np[f - 1]["shadow"]), "reshade": t(re),
+                      "fmv": t(fr["fmv"]), "fz": t(fr["fz"]), "pick": t(fr["grad_pick"])})
+    clean = [t(np.broadcast_to(fr["shadow_clean"][None], (3, H, W))) for fr in frames_np]
+    am = torch.full((H, W), SHADOW.alpha, dtype=torch.float32, device="cuda")
+    work = L.gradient_workspace(am)
+    out = {"config": f"{W}x{H} shadow channel, {steps} frames timed after {warmup}"}
+    for use in (False, True):
+        def run():
+            den = Denoiser(H, W, SHADOW)
+
+            def step(i):
+                g = grads[i]
+                if use and g is not None:
+                    L.sv_temporal_gradient(g["prev"], g["reshade"], g["fmv"], g["fz"], g["pick"],
+                                           ins[i].g, am, work, alpha=SHADOW.alpha)
+                    return den.frame(ins[i], alpha_map=am)
+                return den.frame(ins[i])
+            return step
+        ms = _timed_frames(torch, run(), list(range(len(ins))), warmup)
+        step = run()
+        q = float(np.mean([learn.relmse(step(i), clean[i]) for i in range(len(ins))][warmup:]))
+        out["gradient" if use else "constant_alpha"] = {
+            "value": round(H * W / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 4),
+            "relmse": round(q, 6)}
+    return out
+
+
 def cpu_baseline(frames_np, warm, timed):
     """The oracle as it stands, on the host cores, on a bounded sample."""
     import oracle as O
@@ -442,7 +486,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--variants",
-                    default="separable,uhd_half,batched,scene_features,channels,learned",
+                    default="separable,uhd_half,batched,scene_features,channels,gradient,learned",
                     help="comma-separated variants to run after the headline chain")
     ap.add_argument("--tune", action="store_true",
                     help="a-trous launch shapes from the autotuner (timed before the run)"
@@ -459,7 +503,7 @@ def main():
     frames_np = generate(WORKLOAD, n_frames, args.workers)  # before any GPU call (fork)
     want = set() if args.no_variants else set(v for v in args.variants.split(",") if v)
     vframes = (generate_variant_frames(args.workers, want)
-               if want & {"uhd_half", "batched", "channels"} else None)
+               if want & {"uhd_half", "batched", "channels", "gradient"} else None)
     gen_s = time.perf_counter() - t0
     print(f"# generated {n_frames} frames in {gen_s:.1f} s", file=sys.stderr, flush=True)
 
@@ -539,6 +583,9 @@ def main():
     if "channels" in want:
         variants["channels"] = variant_channels(torch, vframes["channels"])
         print(f"# channels: {variants['channels']}", file=sys.stderr, flush=True)
+    if "gradient" in want:
+        variants["gradient"] = variant_gradient(torch, vframes["channels"])
+        print(f"# gradient: {variants['gradient']}", file=sys.stderr, flush=True)
     if "scene_features" in want:
         variants["scene_features"] = variant_scene_features(torch, frames_np, args.warmup,
                                                             args.steps)

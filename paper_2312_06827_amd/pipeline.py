@@ -97,11 +97,14 @@ class FrameInputs:
     prev: GBuf                 # previous frame's z, n, id
     albedo: Optional[torch.Tensor] = None  # (3, H, W), for the learned mode
     blur_ctl: Optional[torch.Tensor] = None  # (H, W) uint8 control bytes: adaptive levels
+    alpha_map: Optional[torch.Tensor] = None  # (H, W) binary32 blend factor (e.g. the gradient's)
 
     def c(self, alpha_map: Optional[torch.Tensor] = None,
           kappa: Optional[torch.Tensor] = None, mlp=None) -> lib.sv_frame_in:
         """mlp: a lib.sv_mlp structure (kept alive by the caller) for the
         learned mode."""
+        if alpha_map is None:
+            alpha_map = self.alpha_map
         key = (None if alpha_map is None else alpha_map.data_ptr(),
                None if kappa is None else kappa.data_ptr(),
                None if mlp is None else ctypes.addressof(mlp),
@@ -205,6 +208,8 @@ class Denoiser:
         """Enqueue one frame; returns the output tensor (valid once the
         stream reaches it; overwritten by the next frame).  `timer(name)`,
         if given, wraps each library call (for per-kernel events)."""
+        if alpha_map is None:
+            alpha_map = inp.alpha_map
         if timer is None:
             lib.sv_denoise_frame(inp.c(alpha_map, kappa, self._mlp_c), self._st, self._dims,
                                  self._dtype, self._params, stream=stream)
@@ -354,15 +359,31 @@ class ChannelDenoiser:
         self.ctl = [torch.zeros((height, width), dtype=torch.uint8, device=dev) for _ in range(2)]
         self.shadow_rule = lib.BlurRule(table=False)  # shift above the shadow angle
         self.spec_rule = lib.BlurRule()               # shift and level table by roughness
+        # the temporal gradient's blend factor for the shadow channel
+        self.grad_alpha = torch.full((height, width), shadow.alpha, dtype=torch.float32,
+                                     device=dev)
+        self.grad_work = lib.gradient_workspace(self.grad_alpha)
+        self.shadow_cfg = shadow
 
     def frame(self, geo: FrameInputs, shadow_rgb: torch.Tensor, spec_rgb: torch.Tensor,
               direct: torch.Tensor, roughness: Optional[torch.Tensor] = None,
-              shadow_angle: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+              shadow_angle: Optional[torch.Tensor] = None, gradient: Optional[dict] = None,
+              stream=None) -> torch.Tensor:
         """geo: the frame's G-buffer and motion (its rgb is not used);
         shadow_rgb: the one-sample visibility (3, H, W); spec_rgb: the
-        one-sample indirect specular light; direct: the direct light."""
-        ins = [dataclasses.replace(geo, rgb=shadow_rgb, blur_ctl=None),
-               dataclasses.replace(geo, rgb=spec_rgb, blur_ctl=None)]
+        one-sample indirect specular light; direct: the direct light.
+        gradient (optional): the temporal gradient's inputs for the shadow
+        channel - prev (the previous frame's visibility samples), reshade
+        (them traced again), fmv, fz, pick - whose blend factor then replaces
+        the shadow channel's constant one."""
+        am = None
+        if gradient is not None:
+            lib.sv_temporal_gradient(gradient["prev"], gradient["reshade"], gradient["fmv"],
+                                     gradient["fz"], gradient["pick"], geo.g, self.grad_alpha,
+                                     self.grad_work, alpha=self.shadow_cfg.alpha, stream=stream)
+            am = self.grad_alpha
+        ins = [dataclasses.replace(geo, rgb=shadow_rgb, blur_ctl=None, alpha_map=am),
+               dataclasses.replace(geo, rgb=spec_rgb, blur_ctl=None, alpha_map=None)]
         if self.adaptive:
             lib.sv_blur_control(None, shadow_angle, self.ctl[0], self.shadow_rule, stream=stream)
             lib.sv_blur_control(roughness, None, self.ctl[1], self.spec_rule, stream=stream)

@@ -156,3 +156,41 @@ def test_levels_on_binary_visibility(sep):
         assert ec <= TOL32 and ev <= TOL32
         # the next level's input: this level's device output
         c, v = host(out).astype(np.float32), host(vo).astype(np.float32)
+
+
+def test_channel_pipeline_with_temporal_gradient():
+    """The shadow channel's blend factor from the temporal gradient: the
+    batched channels against the oracle chain fed the oracle's gradient."""
+    from oracle import gradient as OG
+    frames = _channel_frames(W=200, H=120, frames=5)
+    H, W = frames[0]["z"].shape
+    den = ChannelDenoiser(H, W, adaptive=False)
+    ps = O.OracleParams(clamp=True, use_id=True, levels=4)
+    pr = O.OracleParams(clamp=True, tonemap=True, use_id=True, levels=4)
+    ss, sp = O.new_state(H, W), O.new_state(H, W)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    try:
+        for f, fr in enumerate(frames):
+            grad, am = None, None
+            if f > 0:
+                pv = frames[f - 1]
+                re = np.broadcast_to(fr["shadow_reshade"][None], (3, H, W)).copy()
+                grad = {"prev": t(pv["shadow"]), "reshade": t(re), "fmv": t(fr["fmv"]),
+                        "fz": t(fr["fz"]), "pick": t(fr["grad_pick"])}
+                am, _ = OG.temporal_gradient(pv["shadow"], re, fr["fmv"], fr["fz"],
+                                             fr["grad_pick"], fr["z"], fr["dzdx"], fr["dzdy"])
+            say(f"channels with gradient frame {f}")
+            out = den.frame(FrameInputs.from_numpy(fr), t(fr["shadow"]), t(fr["spec"]),
+                            t(fr["direct"]), gradient=grad)
+            fs, fp = dict(fr), dict(fr)
+            fs["rgb"], fp["rgb"] = fr["shadow"], fr["spec"]
+            os_, ss, _ = O.run_frame(fs, ss, ps, alpha_map=am)
+            op, sp, _ = O.run_frame(fp, sp, pr)
+            if am is not None:
+                np.testing.assert_allclose(host(den.grad_alpha), am, atol=1e-5, rtol=0)
+            e = (rel_err(host(den.batch.streams[0].out), os_),
+                 rel_err(host(den.batch.streams[1].out), op))
+            say(f"  shadow {e[0]:.2e} specular {e[1]:.2e}")
+            assert e[0] <= TOL_BINARY and e[1] <= TOL32, (f, e)
+    finally:
+        den.close()
