@@ -502,7 +502,7 @@ def sv_temporal_gradient(prev: Planes, reshade: Planes, fmv: torch.Tensor, fz: t
     _check("sv_temporal_gradient", load().sv_temporal_gradient(
         ctypes.byref(_rgb(prev)), ctypes.byref(_rgb(reshade)), _plane_ptr(fmv[0]),
         _plane_ptr(fmv[1]), _plane_ptr(fz), _plane_ptr(pick), ctypes.byref(gc),
-        _plane_ptr(alpha_map), _plane_ptr(lam), _plane_ptr(work), dims_of(r), dtype_of(r),
+        _plane_ptr(alpha_map), _plane_ptr(lam), work.data_ptr(), dims_of(r), dtype_of(r),
         ctypes.byref(p), _stream(stream)))
 
 
