@@ -29,6 +29,7 @@ struct GradArgs {
     float *alpha_map, *lambda;
     uint32_t *key;
     float4 *ca, *cb;                          // cell ping-pong
+    float4 *cz;                               // cells' centre pixel: z, dz/dx, dz/dy
     int w, h, pitch, cw, ch;
     float alpha, tau_z, sigma_z;
 };
@@ -76,6 +77,12 @@ template <typename T>
 __global__ __launch_bounds__(256) void grad_gather_k(GradArgs a) {
     const int c = (int)blockIdx.x * 256 + (int)threadIdx.x;
     if (c >= a.cw * a.ch) return;
+    {  // the cell's centre pixel, which carries its depth in the reconstruction
+        const int cy = c / a.cw, cx = c - cy * a.cw;
+        const uint32_t o = (uint32_t)min(3 * cy + 1, a.h - 1) * (uint32_t)a.pitch +
+                           (uint32_t)min(3 * cx + 1, a.w - 1);
+        a.cz[c] = make_float4(ldo<T>(a.z, o), ldo<T>(a.dzdx, o), ldo<T>(a.dzdy, o), 0.f);
+    }
     const uint32_t s = a.key[c];
     float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
     if (s != kNone) {
@@ -92,18 +99,13 @@ __global__ __launch_bounds__(256) void grad_gather_k(GradArgs a) {
 __constant__ float kB3[5] = {0.0625f, 0.25f, 0.375f, 0.25f, 0.0625f};
 
 // One cascade level at cell step `step`: from `src` into `dst`.
-template <typename T>
 __global__ __launch_bounds__(256) void grad_atrous_k(GradArgs a, const float4 *src, float4 *dst,
                                                     int step) {
     const int c = (int)blockIdx.x * 256 + (int)threadIdx.x;
     if (c >= a.cw * a.ch) return;
     const int cy = c / a.cw, cx = c - cy * a.cw;
-    // the cells' centre pixels carry the depth
-    const auto centre = [&](int yy, int xx) {
-        return (uint32_t)min(3 * yy + 1, a.h - 1) * (uint32_t)a.pitch + (uint32_t)min(3 * xx + 1, a.w - 1);
-    };
-    const uint32_t o = centre(cy, cx);
-    const float zc = ldo<T>(a.z, o), gx = ldo<T>(a.dzdx, o), gy = ldo<T>(a.dzdy, o);
+    const float4 cc = a.cz[c];
+    const float zc = cc.x, gx = cc.y, gy = cc.z;
     float sd = 0.f, sn = 0.f, sp = 0.f;
 #pragma unroll
     for (int b = -2; b <= 2; ++b) {
@@ -113,7 +115,7 @@ __global__ __launch_bounds__(256) void grad_atrous_k(GradArgs a, const float4 *s
             if (ny < 0 || ny >= a.ch || nx < 0 || nx >= a.cw) continue;
             const float ox = 3.f * (float)(e * step), oy = 3.f * (float)(b * step);
             const float den = fmaf(a.sigma_z, fabsf(fmaf(gx, ox, gy * oy)), 1e-10f);
-            const float zd = ldo<T>(a.z, centre(ny, nx));
+            const float zd = a.cz[ny * a.cw + nx].x;
             const float w = kB3[b + 2] * kB3[e + 2] * exp2f(-fabsf(zc - zd) * (kLog2e / den));
             const float4 v = src[ny * a.cw + nx];
             sd = fmaf(w, v.x, sd);
@@ -137,16 +139,18 @@ __global__ __launch_bounds__(256) void grad_alpha_k(GradArgs a, const float4 *ce
 }
 
 struct GradWork {
-    size_t key, ca, cb, total;
+    size_t key, ca, cb, cz, total;
 };
 
 GradWork work_layout(sv_dims d) {
     const size_t n = (size_t)((d.w + 2) / 3) * (size_t)((d.h + 2) / 3);
+    const size_t f4 = (n * sizeof(float4) + 255) & ~(size_t)255;
     GradWork g;
     g.key = 0;
     g.ca = (n * sizeof(uint32_t) + 255) & ~(size_t)255;
-    g.cb = g.ca + ((n * sizeof(float4) + 255) & ~(size_t)255);
-    g.total = g.cb + n * sizeof(float4);
+    g.cb = g.ca + f4;
+    g.cz = g.cb + f4;
+    g.total = g.cz + n * sizeof(float4);
     return g;
 }
 
@@ -159,7 +163,7 @@ void launch_gradient(GradArgs a, int levels, hipStream_t s) {
     hipLaunchKernelGGL(grad_gather_k<T>, g1, dim3(256), 0, s, a);
     float4 *src = a.ca, *dst = a.cb;
     for (int l = 0; l < levels; ++l) {
-        hipLaunchKernelGGL(grad_atrous_k<T>, g1, dim3(256), 0, s, a, (const float4 *)src, dst,
+        hipLaunchKernelGGL(grad_atrous_k, g1, dim3(256), 0, s, a, (const float4 *)src, dst,
                            1 << l);
         float4 *tmp = src;
         src = dst;
@@ -217,7 +221,8 @@ extern "C" int sv_temporal_gradient(const sv_rgb *prev, const sv_rgb *reshade, c
     unsigned char *wb = (unsigned char *)work;
     GradArgs a{prev->r,  prev->g, prev->b, reshade->r, reshade->g, reshade->b, fmvx, fmvy, fz, pick,
                g->z,     g->dzdx, g->dzdy, alpha_map,  lambda,     (uint32_t *)(wb + wl.key),
-               (float4 *)(wb + wl.ca), (float4 *)(wb + wl.cb), d.w, d.h, d.pitch, cw, ch,
+               (float4 *)(wb + wl.ca), (float4 *)(wb + wl.cb), (float4 *)(wb + wl.cz), d.w, d.h,
+               d.pitch, cw, ch,
                p->alpha, p->tau_z, p->sigma_z};
     hipStream_t s = as_stream(stream);
     if (t == SV_F32) launch_gradient<float>(a, p->levels, s);
