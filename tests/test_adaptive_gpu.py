@@ -156,3 +156,25 @@ def test_adaptive_separable_beyond_the_fused_steps():
     rc, rv = O.atrous_adaptive(c, var, z, dzdx, dzdy, n, np.full((H, W), 31, np.uint8), 5,
                                separable=True)
     assert rel_err(host(out), rc) <= TOL32
+
+
+@pytest.mark.parametrize("sep", [False, True])
+def test_adaptive_level_binary16(sep):
+    """Binary16 storage: against the oracle rounding its stored colours to
+    binary16 (within 2e-3)."""
+    H, W = 67, 131
+    c, var, z, dzdx, dzdy, n = _atrous_inputs(H, W, 970 + int(sep))
+    q = lambda a: O.quantize_half(a)
+    c, z, dzdx, dzdy, n = q(c), q(z), q(dzdx), q(dzdy), q(n)
+    ctl = _ctl(np.random.default_rng(971), H, W)
+    h16 = lambda a: dev(a, None, torch.float16)
+    g = L.GBuf(h16(z), h16(dzdx), h16(dzdy), h16(n))
+    for level in (0, 2):
+        say(f"adaptive binary16 sep={sep} level={level}")
+        out, vo = empty_like_dev((3, H, W), None, torch.float16), empty_like_dev((H, W))
+        L.sv_atrous_adaptive(h16(c), dev(var), g, dev(ctl, None, torch.uint8), None, out, vo,
+                             level, sep, L.AtrousParams())
+        rc, rv = O.atrous_adaptive(c, var, z, dzdx, dzdy, n, ctl, level, separable=sep,
+                                   half_out=True)
+        assert rel_err(host(out), rc) <= 2e-3
+        assert rel_err(host(vo), rv) <= 2e-3

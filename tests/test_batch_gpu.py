@@ -98,3 +98,37 @@ def test_batch_learned_streams():
                 assert torch.equal(batch.streams[i].kappa, singles[i].kappa), (f, i)
     finally:
         batch.close()
+
+
+@pytest.mark.parametrize("sep", [False, True])
+def test_batch_with_adaptive_levels_and_per_stream_settings(sep):
+    """Adaptive levels (control bytes from each stream's roughness) and
+    per-stream settings (tone map on some streams, clipping on none): the
+    plan still equals the streams run alone, bitwise."""
+    from paper_2312_06827_amd import lib as L
+    cfgs = [replace(MOTION_SEP if sep else MOTION, tonemap=(i % 2 == 0)) for i in range(len(SIZES))]
+    frames = 3
+    scfg = _streams(False, frames)
+    rule = L.BlurRule()
+    say(f"batch adaptive sep={sep}")
+    batch = BatchDenoiser(SIZES, cfgs)
+    singles = [Denoiser(h, w, c) for (h, w), c in zip(SIZES, cfgs)]
+    ctl = [torch.empty((h, w), dtype=torch.uint8, device="cuda") for (h, w) in SIZES]
+    try:
+        for f in range(frames):
+            frs = [render_frame(c, f) for c in scfg]
+            inputs = []
+            for i, fr in enumerate(frs):
+                inp = FrameInputs.from_numpy(fr)
+                L.sv_blur_control(torch.from_numpy(fr["roughness"]).cuda(), None, ctl[i], rule)
+                inp.blur_ctl = ctl[i]
+                inputs.append(inp)
+            outs = batch.frame(inputs)
+            refs = [d.frame(inp) for d, inp in zip(singles, inputs)]
+            torch.cuda.synchronize()
+            for i in range(len(SIZES)):
+                assert torch.equal(outs[i], refs[i]), (f, i)
+            say(f"  frame {f}: bitwise equal; {batch.passes()} launches per frame")
+        assert batch.passes() == 3 + 2 * 5  # two launches per adaptive level
+    finally:
+        batch.close()
