@@ -625,7 +625,7 @@ __global__ __launch_bounds__(256) void atrous_sep_k(AtrousArgs a) {
 
 // ---- separable level, both passes fused -------------------------------------
 //
-// One wave owns 64 columns and walks kHvRows + 4 lattice rows of one step
+// One wave owns 64 columns and walks hv_rows(STEP) + 4 lattice rows of one step
 // phase (image rows ph + j * STEP).  Each row is staged once in LDS for the
 // horizontal pass, its loads issued two rows ahead; the horizontal results
 // of the last five rows live in a register ring (slot = row mod 5, static
@@ -637,15 +637,18 @@ __global__ __launch_bounds__(256) void atrous_sep_k(AtrousArgs a) {
 // of the two-pass form would round it, and every weight, sum and order is
 // that of the two passes, so the output is bitwise theirs.  The level
 // reads the G-buffer and colour once and writes only its outputs.
-constexpr int kHvRows = 16;
-static_assert((kHvRows + 4) % 10 == 0,
-              "rows per tile must fill the five-slot ring and the two load buffers");
+// Output rows per wave: 16 at the small steps; 6 from step 8, whose wider
+// halo makes a wave's rows costlier, so that more, shorter waves hide their
+// latency better (measured at 1080p: 53 instead of 58 us per level at steps
+// 8 and 16, but 55-58 instead of 48-50 us at steps 1-4).
+constexpr int hv_rows(int step) { return step >= 8 ? 6 : 16; }
 
 template <int STEP>
 struct HvShape {
     static constexpr int TX = 64, HX = 2 * STEP, COLS = TX + 2 * HX, PFC = TX + 2;
     static constexpr int IT = (COLS + 63) / 64, ITP = (3 * PFC + 63) / 64;
-    static constexpr int ROWS = kHvRows + 4;
+    static constexpr int OUT = hv_rows(STEP), ROWS = OUT + 4;
+    static_assert(ROWS % 10 == 0, "rows per tile must fill the five-slot ring and the two load buffers");
 };
 
 template <int STEP>
@@ -874,10 +877,11 @@ struct HvArgs {
 };
 
 inline int hv_tiles(const AtrousArgs &a) {
-    return ((a.w + 63) / 64) * a.step * ((((a.h + a.step - 1) / a.step) + kHvRows - 1) / kHvRows);
+    const int rows = hv_rows(a.step);
+    return ((a.w + 63) / 64) * a.step * ((((a.h + a.step - 1) / a.step) + rows - 1) / rows);
 }
 
-// Tile t: 64 columns x kHvRows lattice rows of one phase (columns fastest,
+// Tile t: 64 columns x hv_rows(STEP) lattice rows of one phase (columns fastest,
 // then phases, then bands of rows).  MODE: bit 0 = edge weights on,
 // bit 1 = variance output.
 template <typename T, int STEP, int MODE>
@@ -887,10 +891,10 @@ __device__ __forceinline__ void hv_tile(const HvArgs &a, int t, float4 *s_cl, fl
     const int gxt = (a.h.w + 63) / 64;
     const int cx = t % gxt, rest = t / gxt;
     const int ph = rest % STEP, band = rest / STEP;
-    const int x0 = cx * 64, j0 = band * kHvRows;
+    const int x0 = cx * 64, j0 = band * S::OUT;
     // adaptive levels: a tile without a pixel of this launch's class is
     // skipped (uniform branch)
-    if (a.v.ctl && !any_of_class(a.v, x0 + (int)threadIdx.x, ph + j0 * STEP, STEP, kHvRows))
+    if (a.v.ctl && !any_of_class(a.v, x0 + (int)threadIdx.x, ph + j0 * STEP, STEP, S::OUT))
         return;
     HvSlot ring[5];
     HvRow<STEP> q0, q1;  // even and odd rows' loads, two rows in flight
