@@ -56,6 +56,17 @@ static_assert(kz_index(1, 0) == 0 && kz_index(-2, 0) == 1 && kz_index(-2, 1) == 
                   kz_index(2, -2) == 7 && kz_index(2, 2) == 11,
               "depth denominator indexing");
 
+// Mean s / sw of the 3x3 variance prefilter (sw > 0: the centre counts).
+__device__ __forceinline__ float pf_mean(float s, float sw) { return quot(s, sw, fast_rcp(sw)); }
+
+// Luminance scale log2(e) / (sigma_l kappa sqrt(g) + eps_l) from the
+// prefiltered variance g >= 0, with the hardware square root and reciprocal
+// (about an ulp each; a full-precision divide and square root cost some 25
+// instructions per pixel, and g only sets the width of the weight).
+__device__ __forceinline__ float lum_scale(float sl_kappa, float g, float eps_l) {
+    return kLog2e * fast_rcp(fmaf(sl_kappa, __builtin_amdgcn_sqrtf(g), eps_l));
+}
+
 // 3x3 Gaussian of the variance around (x, y) over in-image, non-empty
 // pixels, renormalised.  All nine loads are issued before any test.
 template <typename T>
@@ -65,7 +76,8 @@ __device__ __forceinline__ float prefilter_global(const AtrousArgs &a, int x, in
     for (int i = 0; i < 9; ++i) {
         const int qx = x + i % 3 - 1, qy = y + i / 3 - 1;
         const bool in = qx >= 0 && qx < a.w && qy >= 0 && qy < a.h;
-        const uint32_t q = in ? (uint32_t)qy * (uint32_t)a.pitch + (uint32_t)qx : (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x;
+        const uint32_t q = vofs(in ? (uint32_t)qy * (uint32_t)a.pitch + (uint32_t)qx
+                                   : (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x);
         zq[i] = in ? ldo<T>(a.z, q) : 0.f;
         vq[i] = ldf(a.var, q);
     }
@@ -76,12 +88,12 @@ __device__ __forceinline__ float prefilter_global(const AtrousArgs &a, int x, in
         s = fmaf(k, vq[i], s);
         sw += k;
     }
-    return s / sw;
+    return pf_mean(s, sw);
 }
 
 __device__ __forceinline__ float luma_scale(const AtrousArgs &a, float g, uint32_t o) {
     const float kap = a.kappa ? ldf(a.kappa, o) : 1.0f;
-    return kLog2e / fmaf(a.sigma_l * kap, sqrtf(g), a.eps_l);
+    return lum_scale(a.sigma_l * kap, g, a.eps_l);
 }
 
 struct Acc {
@@ -238,7 +250,7 @@ __device__ __forceinline__ void tile_issue(const AtrousArgs &a, TileOrigin t, R 
         const int gx = t.x0 - S::HX + c;
         const int gy = t.ybase + (r - S::HY) * a.step;
         const bool in = i < S::NS && gx >= 0 && gx < a.w && gy >= 0 && gy < a.h;
-        const uint32_t o = in ? (uint32_t)gy * (uint32_t)a.pitch + (uint32_t)gx : 0u;
+        const uint32_t o = vofs(in ? (uint32_t)gy * (uint32_t)a.pitch + (uint32_t)gx : 0u);
         g.in[it] = in;
         g.z[it] = ldo<T>(a.z, o);
         g.r[it] = ldo<T>(a.cr, o);
@@ -257,7 +269,7 @@ __device__ __forceinline__ void tile_issue(const AtrousArgs &a, TileOrigin t, R 
         const int r3 = rem / S::PFC, c = rem - r3 * S::PFC;
         const int gx = t.x0 - 1 + c, gy = t.ybase + j * a.step + r3 - 1;
         const bool in = i < S::NP && gx >= 0 && gx < a.w && gy >= 0 && gy < a.h;
-        const uint32_t o = in ? (uint32_t)gy * (uint32_t)a.pitch + (uint32_t)gx : 0u;
+        const uint32_t o = vofs(in ? (uint32_t)gy * (uint32_t)a.pitch + (uint32_t)gx : 0u);
         g.pin[it] = in;
         g.pz[it] = ldo<T>(a.z, o);
         g.pv[it] = ldf(a.var, o);
@@ -300,7 +312,7 @@ __device__ __forceinline__ void tile_compute(const AtrousArgs &a, TileOrigin t,
         const int j = ly + 4 * k;
         const int y = t.ybase + j * STEP;
         if (y >= a.h) break;
-        const uint32_t o = (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x;
+        const uint32_t o = vofs((uint32_t)y * (uint32_t)a.pitch + (uint32_t)x);
         if (DIR != kDirH && a.ctl) {  // uniform branch
             const int sel = ctl_select(a, o);
             if (sel != 1) {
@@ -347,7 +359,7 @@ __device__ __forceinline__ void tile_compute(const AtrousArgs &a, TileOrigin t,
                         sw += kk;
                     }
             }
-            g = s / sw;
+            g = pf_mean(s, sw);
         }
         float kz[12];
         float kl = 0.f;
@@ -387,7 +399,7 @@ __device__ __forceinline__ void tile_compute(const AtrousArgs &a, TileOrigin t,
                                     MODE == kUnit ? 0.f : kz[kz_index(aa, b)], pg.x, pc.w, pg.y,
                                     pg.z, pg.w, kl, a.nc);
             }
-        const float inv = 1.0f / acc.sw;
+        const float inv = fast_rcp(acc.sw);
         if (DIR == kDirH) {
             sto<T>(a.or_, o, quot(acc.sr, acc.sw, inv));
             sto<T>(a.og, o, quot(acc.sg, acc.sw, inv));
@@ -488,7 +500,7 @@ __device__ __forceinline__ void load_tap(const AtrousArgs &a, int qx, int qy, fl
     qg = make_float4(0.f, 0.f, 0.f, 0.f);
     qv = 0.f;
     if (qx < 0 || qx >= a.w || qy < 0 || qy >= a.h) return;
-    const uint32_t q = (uint32_t)qy * (uint32_t)a.pitch + (uint32_t)qx;
+    const uint32_t q = vofs((uint32_t)qy * (uint32_t)a.pitch + (uint32_t)qx);
     const float zz = ldo<T>(a.z, q);
     if (empty_px(zz)) return;
     const float R = ldo<T>(a.cr, q), G = ldo<T>(a.cg, q), B = ldo<T>(a.cb, q);
@@ -502,7 +514,7 @@ __global__ __launch_bounds__(256) void atrous_direct_k(AtrousArgs a) {
     const int x = blockIdx.x * 64 + (threadIdx.x & 63);
     const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
     if (x >= a.w || y >= a.h) return;
-    const uint32_t o = (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x;
+    const uint32_t o = vofs((uint32_t)y * (uint32_t)a.pitch + (uint32_t)x);
     if (a.ctl) {
         const int sel = ctl_select(a, o);
         if (sel != 1) {
@@ -547,7 +559,7 @@ __global__ __launch_bounds__(256) void atrous_direct_k(AtrousArgs a) {
                                 kH1[aa + 2] * kH1[b + 2], MODE == kUnit ? 0.f : kz[kz_index(aa, b)], pg.x,
                                 pc.w, pg.y, pg.z, pg.w, kl, a.nc);
         }
-    const float inv = 1.0f / acc.sw;
+    const float inv = fast_rcp(acc.sw);
     write_out<T>(a, o, quot(acc.sr, acc.sw, inv), quot(acc.sg, acc.sw, inv),
                      quot(acc.sb, acc.sw, inv));
     if (WANT_VAR) stf(a.var_out, o, acc.sv * inv * inv);
@@ -564,7 +576,7 @@ __global__ __launch_bounds__(256) void atrous_sep_k(AtrousArgs a) {
     const int x = blockIdx.x * 64 + (threadIdx.x & 63);
     const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
     if (x >= a.w || y >= a.h) return;
-    const uint32_t o = (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x;
+    const uint32_t o = vofs((uint32_t)y * (uint32_t)a.pitch + (uint32_t)x);
     if (VERTICAL && a.ctl) {
         const int sel = ctl_select(a, o);
         if (sel != 1) {
@@ -611,7 +623,7 @@ __global__ __launch_bounds__(256) void atrous_sep_k(AtrousArgs a) {
                             MODE == kUnit ? 0.f : kz[(t < 0 ? -t : t) - 1], pg.x, pc.w, pg.y, pg.z, pg.w,
                             kl, a.nc);
     }
-    const float inv = 1.0f / acc.sw;
+    const float inv = fast_rcp(acc.sw);
     if (VERTICAL) {
         write_out<T>(a, o, quot(acc.sr, acc.sw, inv), quot(acc.sg, acc.sw, inv),
                      quot(acc.sb, acc.sw, inv));
@@ -677,7 +689,7 @@ __device__ __forceinline__ void hv_issue(const AtrousArgs &a, int x0, int y, HvR
         const int i = lx + it * 64;
         const int gx = x0 - S::HX + i;
         const bool in = i < S::COLS && yin && gx >= 0 && gx < a.w;
-        const uint32_t o = in ? (uint32_t)y * (uint32_t)a.pitch + (uint32_t)gx : 0u;
+        const uint32_t o = vofs(in ? (uint32_t)y * (uint32_t)a.pitch + (uint32_t)gx : 0u);
         q.in[it] = in;
         q.z[it] = ldo<T>(a.z, o);
         q.r[it] = ldo<T>(a.cr, o);
@@ -693,13 +705,13 @@ __device__ __forceinline__ void hv_issue(const AtrousArgs &a, int x0, int y, HvR
         const int rr = i / S::PFC, c = i - rr * S::PFC;
         const int gx = x0 - 1 + c, gy = y + rr - 1;
         const bool in = i < 3 * S::PFC && gx >= 0 && gx < a.w && gy >= 0 && gy < a.h;
-        const uint32_t o = in ? (uint32_t)gy * (uint32_t)a.pitch + (uint32_t)gx : 0u;
+        const uint32_t o = vofs(in ? (uint32_t)gy * (uint32_t)a.pitch + (uint32_t)gx : 0u);
         q.pin[it] = in;
         q.pz[it] = ldo<T>(a.z, o);
         q.pv[it] = ldf(a.var, o);
     }
     const int x = x0 + lx;
-    const uint32_t o = (yin && x < a.w) ? (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x : 0u;
+    const uint32_t o = vofs((yin && x < a.w) ? (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x : 0u);
     q.dzdx = ldo<T>(a.dzdx, o);
     q.dzdy = ldo<T>(a.dzdy, o);
     q.kap = a.kappa ? ldf(a.kappa, o) : 1.0f;
@@ -776,13 +788,13 @@ __device__ __forceinline__ void hv_row(const AtrousArgs &ah, const AtrousArgs &a
                 s = fmaf(kk, e.x, s);
                 sw += kk;
             }
-        cur.g = s / sw;
+        cur.g = pf_mean(s, sw);
     }
     if (pg.x == 0.f) {
         // not a tap; an empty pixel inside the image passes its colour on
         cur.c = make_float4(pc.x, pc.y, pc.z, INFINITY);
         if (y >= 0 && y < ah.h && x < ah.w) {
-            const uint32_t o = (uint32_t)y * (uint32_t)ah.pitch + (uint32_t)x;
+            const uint32_t o = vofs((uint32_t)y * (uint32_t)ah.pitch + (uint32_t)x);
             cur.c.x = ldo<T>(ah.cr, o);
             cur.c.y = ldo<T>(ah.cg, o);
             cur.c.z = ldo<T>(ah.cb, o);
@@ -791,7 +803,7 @@ __device__ __forceinline__ void hv_row(const AtrousArgs &ah, const AtrousArgs &a
         float kz[2] = {0.f, 0.f};
         float kl = 0.f;
         if (WM != kUnit) {
-            kl = kLog2e / fmaf(ah.sigma_l * kap, sqrtf(cur.g), ah.eps_l);
+            kl = lum_scale(ah.sigma_l * kap, cur.g, ah.eps_l);
             const float gx = dzdx * (float)STEP, gy = 0.f;
 #pragma unroll
             for (int aa = 1; aa <= 2; ++aa) {
@@ -814,7 +826,7 @@ __device__ __forceinline__ void hv_row(const AtrousArgs &ah, const AtrousArgs &a
                            WM == kUnit ? 0.f : kz[(aa < 0 ? -aa : aa) - 1], pg.x, pc.w, pg.y, pg.z,
                            pg.w, kl, ah.nc);
         }
-        const float inv = 1.0f / acc.sw;
+        const float inv = fast_rcp(acc.sw);
         const float hr = round_to<T>(quot(acc.sr, acc.sw, inv)),
                     hg = round_to<T>(quot(acc.sg, acc.sw, inv)),
                     hb = round_to<T>(quot(acc.sb, acc.sw, inv));
@@ -826,7 +838,7 @@ __device__ __forceinline__ void hv_row(const AtrousArgs &ah, const AtrousArgs &a
     const HvSlot &cen = ring[CS];
     const int yc = ph + (j0 - 4 + r) * STEP;
     if (x >= av.w || yc >= av.h) return;
-    const uint32_t o = (uint32_t)yc * (uint32_t)av.pitch + (uint32_t)x;
+    const uint32_t o = vofs((uint32_t)yc * (uint32_t)av.pitch + (uint32_t)x);
     if (av.ctl) {
         const int sel = ctl_select(av, o);
         if (sel != 1) {
@@ -842,7 +854,7 @@ __device__ __forceinline__ void hv_row(const AtrousArgs &ah, const AtrousArgs &a
     float kz[2] = {0.f, 0.f};
     float kl = 0.f;
     if (WM != kUnit) {
-        kl = kLog2e / fmaf(av.sigma_l * cen.kap, sqrtf(cen.g), av.eps_l);
+        kl = lum_scale(av.sigma_l * cen.kap, cen.g, av.eps_l);
         const float gx = 0.f, gy = cen.dzdy * (float)STEP;
 #pragma unroll
         for (int b = 1; b <= 2; ++b) {
@@ -865,7 +877,7 @@ __device__ __forceinline__ void hv_row(const AtrousArgs &ah, const AtrousArgs &a
                           WM == kUnit ? 0.f : kz[(b < 0 ? -b : b) - 1], cen.gn.x, cen.c.w,
                           cen.gn.y, cen.gn.z, cen.gn.w, kl, av.nc);
     }
-    const float inv = 1.0f / acc.sw;
+    const float inv = fast_rcp(acc.sw);
     write_out<T>(av, o, quot(acc.sr, acc.sw, inv), quot(acc.sg, acc.sw, inv),
                  quot(acc.sb, acc.sw, inv));
     if (WANT_VAR) stf(av.var_out, o, acc.sv * inv * inv);

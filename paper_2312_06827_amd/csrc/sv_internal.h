@@ -43,6 +43,17 @@ __device__ __forceinline__ void stf(float *base, uint32_t idx, float v) {
     *(float *)((char *)base + idx * 4u) = v;
 }
 
+// An element offset shared by loads or stores of several planes, made
+// opaque to the optimiser: an empty asm statement (no instruction) that
+// pins it as a 32-bit value in a VGPR.  Each access is then addressed as
+// plane base (SGPRs) + this offset, which the memory instruction adds by
+// itself; left visible, the compiler tends to widen the offset once and
+// form a 64-bit address per plane with a VALU add.
+__device__ __forceinline__ uint32_t vofs(uint32_t o) {
+    asm volatile("" : "+v"(o));
+    return o;
+}
+
 // ---- shared arithmetic ----------------------------------------------------
 
 // Rec. 709 luminance, fixed evaluation order, written as
@@ -59,9 +70,10 @@ __device__ __forceinline__ float luma(float r, float g, float b) {
     return fmaf(0.0722f, __fsub_rn(b, g), fmaf(0.2126f, __fsub_rn(r, g), g));
 }
 
-// n / d from inv = 1 / d with one correction step: the residual n - q d is
-// exact in an fma, so the quotient is correctly rounded but in rare hard
-// cases, and n == d gives exactly 1, n == 0 gives 0.  Weighted means thus
+// n / d from inv ~ 1 / d (rounded, or the hardware reciprocal within an
+// ulp) with one correction step: the residual n - q d is exact in an fma,
+// so the quotient is correctly rounded but in rare hard cases, and n == d
+// gives exactly 1, n == 0 gives 0.  Weighted means thus
 // keep a flat region exactly flat, which the luminance edge weight needs:
 // where the variance vanishes it is a near step function of the luminance
 // difference (scale eps_l), and a flat value off by an ulp would cut its

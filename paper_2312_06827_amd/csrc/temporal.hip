@@ -146,7 +146,7 @@ __device__ __forceinline__ void stage_current(float4 *tile, const void *cr, cons
         const int r = i / (kTX + 2), c = i - r * (kTX + 2);
         const int gx = x0 + c, gy = y0 + r;
         const bool in = i < NS && gx >= 0 && gx < w && gy >= 0 && gy < h;
-        const uint32_t o = in ? (uint32_t)gy * (uint32_t)pitch + (uint32_t)gx : 0u;
+        const uint32_t o = vofs(in ? (uint32_t)gy * (uint32_t)pitch + (uint32_t)gx : 0u);
         float R = ldo<T>(cr, o), G = ldo<T>(cg, o), B = ldo<T>(cb, o);
         const float zz = zp ? ldo<T>(zp, o) : 1.f;
         if (tm) {
@@ -232,7 +232,7 @@ struct PxLoads {
 template <typename T, bool USE_ID>
 __device__ __forceinline__ void px_gather(const TemporalArgs &a, int x, int y, PxLoads &g) {
     const bool inimg = x < a.w && y < a.h;
-    const uint32_t o = inimg ? (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x : 0u;
+    const uint32_t o = vofs(inimg ? (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x : 0u);
     g.zc = ldo<T>(a.z, o);
     g.nxc = ldo<T>(a.nx, o);
     g.nyc = ldo<T>(a.ny, o);
@@ -254,7 +254,7 @@ __device__ __forceinline__ void px_gather(const TemporalArgs &a, int x, int y, P
         const int tx = x0 + (t & 1), ty = y0 + (t >> 1);
         g.bw[t] = ((t & 1) ? fx : 1.0f - fx) * ((t >> 1) ? fy : 1.0f - fy);
         g.inb[t] = inimg && mv_ok && g.bw[t] > 0.f && tx >= 0 && tx < a.w && ty >= 0 && ty < a.h;
-        const uint32_t q = g.inb[t] ? (uint32_t)ty * (uint32_t)a.pitch + (uint32_t)tx : o;
+        const uint32_t q = vofs(g.inb[t] ? (uint32_t)ty * (uint32_t)a.pitch + (uint32_t)tx : o);
         g.thn[t] = a.hn[q];
         g.tz[t] = ldo<T>(a.pz, q);
         g.tnx[t] = ldo<T>(a.pnx, q);
@@ -276,7 +276,7 @@ __device__ __forceinline__ PxState px_reproject(const TemporalArgs &a, const flo
                                                 int ly, int x, int y, const PxLoads &g) {
     PxState s;
     s.inimg = x < a.w && y < a.h;
-    s.o = s.inimg ? (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x : 0u;
+    s.o = vofs(s.inimg ? (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x : 0u);
     s.c = tile[(ly + 1) * (kTX + 2) + lx + 1];
     s.L = luma(s.c.x, s.c.y, s.c.z);
     s.zc = g.zc;

@@ -33,7 +33,7 @@ __device__ __forceinline__ void variance_point_tile(const VarianceArgs &a, int t
     const int byt = tile / gxt, bxt = tile - byt * gxt;
     const int x = bxt * kVX + (threadIdx.x & 63), y = byt * kVY + (threadIdx.x >> 6);
     const bool inside = tile >= 0 && x < a.w && y < a.h;
-    const uint32_t o = inside ? (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x : 0u;
+    const uint32_t o = vofs(inside ? (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x : 0u);
     // all three loads issued together (the address is in the image)
     const int nn = a.n[o];
     const float zp = ldo<T>(a.z, o), m2 = ldf(a.m2c, o);
@@ -111,7 +111,7 @@ __device__ __forceinline__ void variance_spatial_stream(const VarianceArgs &a) {
             const int dx = t % D - R, dy = t / D - R;
             const int qx = x + dx, qy = y + dy;
             ok[j] = t < NT && qx >= 0 && qx < a.w && qy >= 0 && qy < a.h;
-            const uint32_t q = ok[j] ? (uint32_t)qy * (uint32_t)a.pitch + (uint32_t)qx : po;
+            const uint32_t q = vofs(ok[j] ? (uint32_t)qy * (uint32_t)a.pitch + (uint32_t)qx : po);
             zq[j] = ldo<T>(a.z, q);
             qx_[j] = ldo<T>(a.nx, q);
             qy_[j] = ldo<T>(a.ny, q);
