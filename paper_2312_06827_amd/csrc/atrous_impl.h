@@ -5,7 +5,8 @@
 // exponential: log2 H - |dz| kz(a,b) - |dL| kl + sigma_n log2 max(0, cos)
 // (the normal term as in sv_internal.h),
 // with kz(a,b) = log2(e) / (sigma_z |grad z . step (a,b)| + eps_z) (12
-// distinct values per pixel, the offsets pairing up as +-(a,b)) and
+// distinct values per pixel, the offsets pairing up as +-(a,b); each one
+// reciprocal, see depth_scale) and
 // kl = log2(e) / (sigma_l kappa sqrt(g) + eps_l).  A tap outside the image
 // or on an empty pixel is staged with luminance +inf and zero colour,
 // variance, depth and normal, which drives its exponent to -inf (weight 0)
@@ -55,6 +56,23 @@ __host__ __device__ __forceinline__ constexpr int kz_index(int a, int b) {
 static_assert(kz_index(1, 0) == 0 && kz_index(-2, 0) == 1 && kz_index(-2, 1) == 2 &&
                   kz_index(2, -2) == 7 && kz_index(2, 2) == 11,
               "depth denominator indexing");
+
+// Depth scale log2(e) / (sigma_z |d| + eps_z) of an offset whose depth
+// difference p's gradient predicts as d, from szl, ezl = sigma_z ln 2,
+// eps_z ln 2 (see depth_coefs): one fma and one reciprocal.
+__device__ __forceinline__ float depth_scale(float d, float szl, float ezl) {
+    return fast_rcp(fmaf(szl, fabsf(d), ezl));
+}
+__device__ __forceinline__ void depth_coefs(const AtrousArgs &a, float &szl, float &ezl) {
+    szl = a.sigma_z * kLn2;
+    ezl = a.eps_z * kLn2;
+}
+
+// grad z . (a, b) for an offset (a, b): a term whose offset component is
+// zero is left out rather than multiplied by zero.
+__device__ __forceinline__ float grad_dot(float gx, float gy, int a, int b) {
+    return b == 0 ? gx * (float)a : a == 0 ? gy * (float)b : fmaf(gx, (float)a, gy * (float)b);
+}
 
 // Mean s / sw of the 3x3 variance prefilter (sw > 0: the centre counts).
 __device__ __forceinline__ float pf_mean(float s, float sw) { return quot(s, sw, fast_rcp(sw)); }
@@ -367,14 +385,15 @@ __device__ __forceinline__ void tile_compute(const AtrousArgs &a, TileOrigin t,
             kl = luma_scale(a, g, o);
             const float gx = DIR == kDirV ? 0.f : ldo<T>(a.dzdx, o) * (float)STEP;
             const float gy = DIR == kDirH ? 0.f : ldo<T>(a.dzdy, o) * (float)STEP;
+            float szl, ezl;
+            depth_coefs(a, szl, ezl);
 #pragma unroll
             for (int b = 0; b <= 2; ++b)
 #pragma unroll
                 for (int aa = -2; aa <= 2; ++aa) {
                     if (b == 0 && aa <= 0) continue;
-                    const float den =
-                        fmaf(a.sigma_z, fabsf(fmaf(gx, (float)aa, gy * (float)b)), a.eps_z);
-                    kz[kz_index(aa, b)] = kLog2e * fast_rcp(den);
+                    if ((DIR == kDirH && b != 0) || (DIR == kDirV && aa != 0)) continue;
+                    kz[kz_index(aa, b)] = depth_scale(grad_dot(gx, gy, aa, b), szl, ezl);
                 }
         }
         constexpr float h0 = DIR == kDir2D ? 0.375f * 0.375f : 0.375f;
@@ -536,13 +555,14 @@ __global__ __launch_bounds__(256) void atrous_direct_k(AtrousArgs a) {
     if (MODE != kUnit) {
         kl = luma_scale(a, g, o);
         const float gx = ldo<T>(a.dzdx, o) * s, gy = ldo<T>(a.dzdy, o) * s;
+        float szl, ezl;
+        depth_coefs(a, szl, ezl);
 #pragma unroll
         for (int b = 0; b <= 2; ++b)
 #pragma unroll
             for (int aa = -2; aa <= 2; ++aa) {
                 if (b == 0 && aa <= 0) continue;
-                const float den = fmaf(a.sigma_z, fabsf(fmaf(gx, (float)aa, gy * (float)b)), a.eps_z);
-                kz[kz_index(aa, b)] = kLog2e * fast_rcp(den);
+                kz[kz_index(aa, b)] = depth_scale(grad_dot(gx, gy, aa, b), szl, ezl);
             }
     }
     constexpr float h00 = 0.375f * 0.375f;
@@ -604,11 +624,12 @@ __global__ __launch_bounds__(256) void atrous_sep_k(AtrousArgs a) {
     if (MODE != kUnit) {
         kl = luma_scale(a, g, o);
         const float grad = ld((const T *)(VERTICAL ? a.dzdy : a.dzdx) + o) * s;
+        float szl, ezl;
+        depth_coefs(a, szl, ezl);
 #pragma unroll
-        for (int i = 1; i <= 2; ++i) {
-            const float den = fmaf(a.sigma_z, fabsf(grad * (float)i), a.eps_z);
-            kz[i - 1] = kLog2e * fast_rcp(den);
-        }
+        for (int i = 1; i <= 2; ++i)
+            kz[i - 1] = depth_scale(VERTICAL ? grad_dot(0.f, grad, 0, i) : grad_dot(grad, 0.f, i, 0),
+                                    szl, ezl);
     }
     constexpr float h0 = 0.375f;
     Acc acc{h0, h0 * pc.x, h0 * pc.y, h0 * pc.z, WANT_VAR ? h0 * h0 * pv : 0.f};
@@ -804,12 +825,12 @@ __device__ __forceinline__ void hv_row(const AtrousArgs &ah, const AtrousArgs &a
         float kl = 0.f;
         if (WM != kUnit) {
             kl = lum_scale(ah.sigma_l * kap, cur.g, ah.eps_l);
-            const float gx = dzdx * (float)STEP, gy = 0.f;
+            const float gx = dzdx * (float)STEP;
+            float szl, ezl;
+            depth_coefs(ah, szl, ezl);
 #pragma unroll
-            for (int aa = 1; aa <= 2; ++aa) {
-                const float den = fmaf(ah.sigma_z, fabsf(fmaf(gx, (float)aa, gy * 0.f)), ah.eps_z);
-                kz[aa - 1] = kLog2e * fast_rcp(den);
-            }
+            for (int aa = 1; aa <= 2; ++aa)
+                kz[aa - 1] = depth_scale(grad_dot(gx, 0.f, aa, 0), szl, ezl);
         }
         constexpr float h0 = 0.375f;
         Acc acc;
@@ -855,12 +876,11 @@ __device__ __forceinline__ void hv_row(const AtrousArgs &ah, const AtrousArgs &a
     float kl = 0.f;
     if (WM != kUnit) {
         kl = lum_scale(av.sigma_l * cen.kap, cen.g, av.eps_l);
-        const float gx = 0.f, gy = cen.dzdy * (float)STEP;
+        const float gy = cen.dzdy * (float)STEP;
+        float szl, ezl;
+        depth_coefs(av, szl, ezl);
 #pragma unroll
-        for (int b = 1; b <= 2; ++b) {
-            const float den = fmaf(av.sigma_z, fabsf(fmaf(gx, 0.f, gy * (float)b)), av.eps_z);
-            kz[b - 1] = kLog2e * fast_rcp(den);
-        }
+        for (int b = 1; b <= 2; ++b) kz[b - 1] = depth_scale(grad_dot(0.f, gy, 0, b), szl, ezl);
     }
     constexpr float h0 = 0.375f;
     Acc acc;
