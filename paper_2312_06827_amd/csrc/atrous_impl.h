@@ -204,8 +204,9 @@ __device__ __forceinline__ void copy_through(const AtrousArgs &a, uint32_t o) {
 // pixels lie in the tile's own lattice rows (HY = 2 above and below, none
 // for the horizontal pass) and columns (HX = 2 STEP left and right, none for
 // the vertical pass), so the LDS footprint is (TY + 2 HY) x (TX + 2 HX)
-// pixels whatever the step, plus three image rows per lattice row for the
-// 3x3 variance prefilter unless they are already in the tile.
+// pixels whatever the step, plus the image rows above and below each
+// lattice row (and the row itself where the tile holds no variance) for the
+// 3x3 variance prefilter, unless the tile holds them all (step 1).
 //
 // The kernel is persistent: each workgroup walks a strided run of tiles of
 // its XCD's contiguous range, and issues the global loads of its next tile
@@ -233,7 +234,17 @@ struct TileShape {
     static constexpr bool NEED_V = WANT_VAR || PF_TILE;
     static constexpr int PFC = TX + 2;
     static constexpr int NS = ROWS * COLS, IT = (NS + 255) / 256;
-    static constexpr int NP = PF_TILE ? 0 : TY * 3 * PFC, ITP = (NP + 255) / 256;
+    // prefilter rows staged per lattice row: the image rows above and below
+    // it, and the row itself unless the tile already holds its variance
+    // (with a column of halo on each side)
+    static constexpr bool MID_TILE = !PF_TILE && NEED_V && HX >= 1;
+    static constexpr int PFR = PF_TILE ? 0 : MID_TILE ? 2 : 3;
+    static constexpr int NP = TY * PFR * PFC, ITP = (NP + 255) / 256;
+    // LDS bytes of one workgroup, and the workgroups (one wave per SIMD
+    // each) that fit a CU's 160 KiB: the register budget is set to match,
+    // so registers never hold occupancy below what LDS allows
+    static constexpr int LDS = NS * 32 + (NEED_V ? NS * 4 : 4) + (NP > 0 ? NP * 4 : 4);
+    static constexpr int WAVES = 163840 / LDS < 8 ? 163840 / LDS : 8;
 };
 
 // Raw values of one tile held in registers between issue and LDS store.
@@ -283,9 +294,11 @@ __device__ __forceinline__ void tile_issue(const AtrousArgs &a, TileOrigin t, R 
 #pragma unroll
     for (int it = 0; it < S::ITP; ++it) {
         const int i = threadIdx.x + it * 256;
-        const int j = i / (3 * S::PFC), rem = i - j * (3 * S::PFC);
-        const int r3 = rem / S::PFC, c = rem - r3 * S::PFC;
-        const int gx = t.x0 - 1 + c, gy = t.ybase + j * a.step + r3 - 1;
+        constexpr int PR = S::PFR > 0 ? S::PFR * S::PFC : 1;  // (no rows: no iteration)
+        const int j = i / PR, rem = i - j * PR;
+        const int rr = rem / S::PFC, c = rem - rr * S::PFC;
+        const int dy = S::PFR == 3 ? rr - 1 : 2 * rr - 1;  // image rows -1, (0,) +1
+        const int gx = t.x0 - 1 + c, gy = t.ybase + j * a.step + dy;
         const bool in = i < S::NP && gx >= 0 && gx < a.w && gy >= 0 && gy < a.h;
         const uint32_t o = vofs(in ? (uint32_t)gy * (uint32_t)a.pitch + (uint32_t)gx : 0u);
         g.pin[it] = in;
@@ -370,7 +383,13 @@ __device__ __forceinline__ void tile_compute(const AtrousArgs &a, TileOrigin t,
                 for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
                     for (int dx = 0; dx < 3; ++dx) {
-                        const float e = s_pf[(j * 3 + dy) * PFC + lx + dx];
+                        // the lattice row's own entries come from the tile
+                        // (z = 0 there: outside or empty)
+                        const int qi = ci + dx - 1;
+                        const int pr = S::MID_TILE ? (dy == 0 ? 0 : 1) : dy;
+                        const float e = S::MID_TILE && dy == 1
+                                            ? (s_gn[qi].x > 0.f ? s_v[qi] : kNoVar)
+                                            : s_pf[(j * S::PFR + pr) * PFC + lx + dx];
                         const bool ok = e == e;  // kNoVar: outside or empty
                         const float kk = ok ? kG3[dx] * kG3[dy] : 0.f;
                         s = fmaf(kk, ok ? e : 0.f, s);
@@ -432,7 +451,8 @@ __device__ __forceinline__ void tile_compute(const AtrousArgs &a, TileOrigin t,
 }
 
 template <typename T, int STEP, int PY, int MODE, bool WANT_VAR, int DIR, bool PERSIST>
-__global__ __launch_bounds__(256) void atrous_tile_k(AtrousArgs a, int tiles, int per_xcd) {
+__global__ __launch_bounds__(256) __attribute__((
+    amdgpu_waves_per_eu(TileShape<STEP, PY, DIR, WANT_VAR>::WAVES))) void atrous_tile_k(AtrousArgs a, int tiles, int per_xcd) {
     using S = TileShape<STEP, PY, DIR, WANT_VAR>;
     __shared__ float4 s_cl[S::NS];  // r, g, b, L (L = +inf: no tap)
     __shared__ float4 s_gn[S::NS];  // z, nx, ny, nz (z = 0: no tap)
@@ -480,7 +500,8 @@ __global__ __launch_bounds__(256) void atrous_tile_k(AtrousArgs a, int tiles, in
 // Batched form: the tiles of many streams (each its own AtrousArgs), one
 // tile per workgroup; every tile is staged and computed exactly as above.
 template <typename T, int STEP, int PY, int MODE, bool WANT_VAR, int DIR>
-__global__ __launch_bounds__(256) void atrous_batch_k(const AtrousArgs *args, const int *prefix,
+__global__ __launch_bounds__(256) __attribute__((
+    amdgpu_waves_per_eu(TileShape<STEP, PY, DIR, WANT_VAR>::WAVES))) void atrous_batch_k(const AtrousArgs *args, const int *prefix,
                                                       int n, int total) {
     using S = TileShape<STEP, PY, DIR, WANT_VAR>;
     __shared__ float4 s_cl[S::NS];
