@@ -106,9 +106,7 @@ extern "C" int sv_atrous_sep(const sv_rgb *c_in, const float *var_in, const sv_g
     const bool unit = (p->flags & SV_A_UNIT_WEIGHTS) != 0;
     hipStream_t s = as_stream(stream);
     if (!scratch) {  // both passes in one kernel, the horizontal result kept on chip
-        HvArgs a{make_args(c_in, var_in, g, kappa, c_out, nullptr, step, d, p),
-                 make_args(c_in, var_in, g, kappa, c_out, var_out, step, d, p)};
-        a.h.inv_tm = 0;
+        const HvArgs a = make_args(c_in, var_in, g, kappa, c_out, var_out, step, d, p);
         const bool ok = t == SV_F32 ? launch_hv_f32(a, unit, s) : launch_hv_f16(a, unit, s);
         if (!ok) return SV_EUNSUPPORTED;
         return hip_status(hipGetLastError());
@@ -162,12 +160,10 @@ extern "C" int sv_atrous_adaptive(const sv_rgb *c_in, const float *var_in, const
             a.ctl_class = cls;
             run_pass(a, t, kDir2D, unit, tile_cfg(p, kDir2D), s);
         } else if (!scratch) {
-            HvArgs a{make_args(c_in, var_in, g, kappa, c_out, nullptr, step, d, p),
-                     make_args(c_in, var_in, g, kappa, c_out, var_out, step, d, p)};
-            a.h.inv_tm = 0;
-            a.v.ctl = ctl;
-            a.v.ctl_level = level;
-            a.v.ctl_class = cls;
+            HvArgs a = make_args(c_in, var_in, g, kappa, c_out, var_out, step, d, p);
+            a.ctl = ctl;
+            a.ctl_level = level;
+            a.ctl_class = cls;
             const bool ok = t == SV_F32 ? launch_hv_f32(a, unit, s) : launch_hv_f16(a, unit, s);
             if (!ok) return SV_EUNSUPPORTED;
         } else {

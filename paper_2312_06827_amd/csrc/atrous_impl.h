@@ -924,10 +924,13 @@ __device__ __forceinline__ void hv_row(const AtrousArgs &ah, const AtrousArgs &a
     if (WANT_VAR) stf(av.var_out, o, acc.sv * inv * inv);
 }
 
-struct HvArgs {
-    AtrousArgs h;  // horizontal pass: input colour, variance, G-buffer
-    AtrousArgs v;  // vertical pass: outputs (colour, variance, inverse tone map)
-};
+// Arguments of the fused level: those of its vertical pass (outputs,
+// variance output, inverse tone map, adaptive control).  The horizontal
+// pass reads the same input colour, variance and G-buffer from them and
+// no output field, so one struct serves both passes (two copies overflow
+// the kernel's scalar registers, and the spilled arguments cost VALU
+// reloads in every row).
+typedef AtrousArgs HvArgs;
 
 inline int hv_tiles(const AtrousArgs &a) {
     const int rows = hv_rows(a.step);
@@ -941,32 +944,32 @@ template <typename T, int STEP, int MODE>
 __device__ __forceinline__ void hv_tile(const HvArgs &a, int t, float4 *s_cl, float4 *s_gn,
                                         float2 *s_pf) {
     using S = HvShape<STEP>;
-    const int gxt = (a.h.w + 63) / 64;
+    const int gxt = (a.w + 63) / 64;
     const int cx = t % gxt, rest = t / gxt;
     const int ph = rest % STEP, band = rest / STEP;
     const int x0 = cx * 64, j0 = band * S::OUT;
     // adaptive levels: a tile without a pixel of this launch's class is
     // skipped (uniform branch)
-    if (a.v.ctl && !any_of_class(a.v, x0 + (int)threadIdx.x, ph + j0 * STEP, STEP, S::OUT))
+    if (a.ctl && !any_of_class(a, x0 + (int)threadIdx.x, ph + j0 * STEP, STEP, S::OUT))
         return;
     HvSlot ring[5];
     HvRow<STEP> q0, q1;  // even and odd rows' loads, two rows in flight
-    hv_issue<T, STEP>(a.h, x0, ph + (j0 - 2) * STEP, q0);
-    hv_issue<T, STEP>(a.h, x0, ph + (j0 - 1) * STEP, q1);
+    hv_issue<T, STEP>(a, x0, ph + (j0 - 2) * STEP, q0);
+    hv_issue<T, STEP>(a, x0, ph + (j0 - 1) * STEP, q1);
     // ten rows per iteration: each ring slot and each load buffer a fixed
     // register set
 #pragma unroll 1
     for (int ro = 0; ro < S::ROWS; ro += 10) {
-        hv_row<T, STEP, MODE, 0>(a.h, a.v, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q0);
-        hv_row<T, STEP, MODE, 1>(a.h, a.v, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q1);
-        hv_row<T, STEP, MODE, 2>(a.h, a.v, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q0);
-        hv_row<T, STEP, MODE, 3>(a.h, a.v, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q1);
-        hv_row<T, STEP, MODE, 4>(a.h, a.v, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q0);
-        hv_row<T, STEP, MODE, 5>(a.h, a.v, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q1);
-        hv_row<T, STEP, MODE, 6>(a.h, a.v, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q0);
-        hv_row<T, STEP, MODE, 7>(a.h, a.v, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q1);
-        hv_row<T, STEP, MODE, 8>(a.h, a.v, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q0);
-        hv_row<T, STEP, MODE, 9>(a.h, a.v, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q1);
+        hv_row<T, STEP, MODE, 0>(a, a, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q0);
+        hv_row<T, STEP, MODE, 1>(a, a, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q1);
+        hv_row<T, STEP, MODE, 2>(a, a, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q0);
+        hv_row<T, STEP, MODE, 3>(a, a, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q1);
+        hv_row<T, STEP, MODE, 4>(a, a, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q0);
+        hv_row<T, STEP, MODE, 5>(a, a, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q1);
+        hv_row<T, STEP, MODE, 6>(a, a, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q0);
+        hv_row<T, STEP, MODE, 7>(a, a, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q1);
+        hv_row<T, STEP, MODE, 8>(a, a, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q0);
+        hv_row<T, STEP, MODE, 9>(a, a, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q1);
     }
 }
 
@@ -1003,7 +1006,7 @@ void hv_batch_launch(const void *args, const int *prefix, int n, int total, hipS
 
 template <typename T, int STEP, int MODE>
 void launch_hv_mode(const HvArgs &a, hipStream_t s) {
-    const int tiles = hv_tiles(a.h);
+    const int tiles = hv_tiles(a);
     if (record_pass(&hv_batch_launch<T, STEP, MODE>, a, tiles)) return;
     hipLaunchKernelGGL((atrous_hv_k<T, STEP, MODE>), dim3(xcd_grid(tiles)), dim3(64), 0, s, a,
                        tiles);
@@ -1023,8 +1026,8 @@ void launch_hv_step(const HvArgs &a, int mode, hipStream_t s) {
 // two passes run through a scratch buffer).
 template <typename T>
 bool launch_hv(const HvArgs &a, bool unit, hipStream_t s) {
-    const int mode = (unit ? 0 : 1) | (a.v.var_out ? 2 : 0);
-    switch (a.h.step) {
+    const int mode = (unit ? 0 : 1) | (a.var_out ? 2 : 0);
+    switch (a.step) {
     case 1: launch_hv_step<T, 1>(a, mode, s); return true;
     case 2: launch_hv_step<T, 2>(a, mode, s); return true;
     case 4: launch_hv_step<T, 4>(a, mode, s); return true;
