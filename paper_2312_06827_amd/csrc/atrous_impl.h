@@ -710,9 +710,11 @@ struct HvRow {  // one lattice row's loads, held between issue and LDS store
     float r[HvShape<STEP>::IT], g[HvShape<STEP>::IT], b[HvShape<STEP>::IT];
     float z[HvShape<STEP>::IT], nx[HvShape<STEP>::IT], ny[HvShape<STEP>::IT],
         nz[HvShape<STEP>::IT];
-    bool in[HvShape<STEP>::IT];
+    // in-image flags as 0/1 in VGPRs: held over two rows, lane masks would
+    // take two scalar registers each and spill
+    uint32_t in[HvShape<STEP>::IT];
     float pz[HvShape<STEP>::ITP], pv[HvShape<STEP>::ITP];
-    bool pin[HvShape<STEP>::ITP];
+    uint32_t pin[HvShape<STEP>::ITP];
     float dzdx, dzdy, kap;  // this lane's pixel
 };
 
@@ -732,7 +734,7 @@ __device__ __forceinline__ void hv_issue(const AtrousArgs &a, int x0, int y, HvR
         const int gx = x0 - S::HX + i;
         const bool in = i < S::COLS && yin && gx >= 0 && gx < a.w;
         const uint32_t o = vofs(in ? (uint32_t)y * (uint32_t)a.pitch + (uint32_t)gx : 0u);
-        q.in[it] = in;
+        q.in[it] = vofs(in ? 1u : 0u);
         q.z[it] = ldo<T>(a.z, o);
         q.r[it] = ldo<T>(a.cr, o);
         q.g[it] = ldo<T>(a.cg, o);
@@ -748,7 +750,7 @@ __device__ __forceinline__ void hv_issue(const AtrousArgs &a, int x0, int y, HvR
         const int gx = x0 - 1 + c, gy = y + rr - 1;
         const bool in = i < 3 * S::PFC && gx >= 0 && gx < a.w && gy >= 0 && gy < a.h;
         const uint32_t o = vofs(in ? (uint32_t)gy * (uint32_t)a.pitch + (uint32_t)gx : 0u);
-        q.pin[it] = in;
+        q.pin[it] = vofs(in ? 1u : 0u);
         q.pz[it] = ldo<T>(a.z, o);
         q.pv[it] = ldf(a.var, o);
     }
@@ -768,7 +770,7 @@ __device__ __forceinline__ void hv_store(const HvRow<STEP> &q, float4 *s_cl, flo
     for (int it = 0; it < S::IT; ++it) {
         const int i = lx + it * 64;
         if (i < S::COLS) {
-            const bool ok = q.in[it] && !empty_px(q.z[it]);
+            const bool ok = q.in[it] != 0u && !empty_px(q.z[it]);
             s_cl[i] = ok ? make_float4(q.r[it], q.g[it], q.b[it], luma(q.r[it], q.g[it], q.b[it]))
                          : make_float4(0.f, 0.f, 0.f, INFINITY);
             s_gn[i] = ok ? make_float4(q.z[it], q.nx[it], q.ny[it], q.nz[it])
@@ -779,7 +781,7 @@ __device__ __forceinline__ void hv_store(const HvRow<STEP> &q, float4 *s_cl, flo
     for (int it = 0; it < S::ITP; ++it) {
         const int i = lx + it * 64;
         if (i < 3 * S::PFC)
-            s_pf[i] = (q.pin[it] && !empty_px(q.pz[it])) ? make_float2(q.pv[it], 1.f)
+            s_pf[i] = (q.pin[it] != 0u && !empty_px(q.pz[it])) ? make_float2(q.pv[it], 1.f)
                                                          : make_float2(0.f, 0.f);
     }
 }
