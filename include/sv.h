@@ -29,14 +29,19 @@
  *  - Arguments are checked on the host before any HIP call; on failure
  *    nothing is enqueued and a status below is returned.  w == 0 or h == 0
  *    is a valid empty call that enqueues nothing.  Limits: w, h <= 32768,
- *    pitch * h < 2^31.
+ *    pitch * h <= 2^29 (every byte offset into a plane then fits in 32
+ *    bits); larger sizes return SV_EINVAL.
  *  - A pixel is EMPTY (no surface) when its depth z is not > 0 or not
  *    finite.  Empty pixels pass their colour through, get zero moments,
  *    variance and history length, and are never used as neighbours.
  *  - Stencil calls (clamp, temporal, variance, a-trous) read neighbours:
  *    their outputs must not overlap any input plane (SV_EALIAS).
- *  - Results are deterministic: no atomics, a fixed summation order per
- *    pixel.
+ *  - Results are deterministic: a fixed summation order per pixel.  The
+ *    atomics the library uses decide no value: the variance pass appends
+ *    short-history pixels to its list with one atomic add per workgroup
+ *    (the list's order changes, each pixel's estimate does not), and the
+ *    temporal gradient takes the lowest colliding stratum with an atomic
+ *    minimum.
  *  - Luminance is L(c) = 0.2126 r + 0.7152 g + 0.0722 b (Rec. 709).
  */
 #ifndef SV_H

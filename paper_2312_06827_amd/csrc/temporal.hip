@@ -247,13 +247,24 @@ __device__ __forceinline__ void px_gather(const TemporalArgs &a, int x, int y, P
     const bool mv_ok = fabsf(mvx) < 1048576.0f && fabsf(mvy) < 1048576.0f;
     g.mv_ok = mv_ok;
     const float fx0 = mv_ok ? floorf(mvx) : 0.f, fy0 = mv_ok ? floorf(mvy) : 0.f;
-    const float fx = mvx - fx0, fy = mvy - fy0;  // exact in binary32
+    // The bilinear factors of the far and near taps, each formed from mv:
+    // f = mv - floor(mv) and e = (floor(mv) + 1) - mv.  Whichever of the two
+    // is below 1/2 is exact in binary32 (Sterbenz), the other within an ulp.
+    // e = 1 - f would not do: for -1/2 < mv < 0, f = 1 + mv rounds, and a
+    // tiny 1 - f then carries a large relative error, which matters where
+    // the near taps are the only usable ones.
+    const float fx = mvx - fx0, fy = mvy - fy0;
+    const float ex = (fx0 + 1.0f) - mvx, ey = (fy0 + 1.0f) - mvy;
     const int x0 = x + (int)fx0, y0 = y + (int)fy0;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         const int tx = x0 + (t & 1), ty = y0 + (t >> 1);
-        g.bw[t] = ((t & 1) ? fx : 1.0f - fx) * ((t >> 1) ? fy : 1.0f - fy);
-        g.inb[t] = inimg && mv_ok && g.bw[t] > 0.f && tx >= 0 && tx < a.w && ty >= 0 && ty < a.h;
+        const float wx = (t & 1) ? fx : ex, wy = (t >> 1) ? fy : ey;
+        g.bw[t] = wx * wy;
+        // a nonzero weight, decided on the factors (their product could
+        // underflow where the exact one does not)
+        g.inb[t] = inimg && mv_ok && wx > 0.f && wy > 0.f && tx >= 0 && tx < a.w && ty >= 0 &&
+                   ty < a.h;
         const uint32_t q = vofs(g.inb[t] ? (uint32_t)ty * (uint32_t)a.pitch + (uint32_t)tx : o);
         g.thn[t] = a.hn[q];
         g.tz[t] = ldo<T>(a.pz, q);

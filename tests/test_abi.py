@@ -79,6 +79,11 @@ def test_tonemap_validation(so):
                          None) == L.SV_OK
     big = L.sv_dims(32768, 32768, 65536)
     assert so.sv_tonemap(r(rgb(A)), r(rgb(A)), big, L.SV_F32, 0, r(TM), None) == L.SV_EINVAL
+    # the limits: pitch * h <= 2^29 elements, w and h <= 32768
+    over = L.sv_dims(64, 32768, 16385)  # one row's pitch over 2^29
+    assert so.sv_tonemap(r(rgb(A)), r(rgb(A)), over, L.SV_F32, 0, r(TM), None) == L.SV_EINVAL
+    for dims in (L.sv_dims(32769, 1, 32769), L.sv_dims(1, 32769, 1)):
+        assert so.sv_tonemap(r(rgb(A)), r(rgb(A)), dims, L.SV_F32, 0, r(TM), None) == L.SV_EINVAL
 
 
 def test_clamp_and_clip_validation(so):

@@ -225,6 +225,46 @@ def test_temporal_alpha_map_and_discarded_motion():
     assert rel_err(host(out), ref["rgb"]) <= TOL32
 
 
+@pytest.mark.parametrize("mvx,mvy", [(42.999966, -1.551829e-05), (-3.0e-07, 5.999998),
+                                     (-0.4999999, -0.25)])
+def test_temporal_small_negative_motion(mvx, mvy):
+    """Motion just below an integer, or just above one from below zero: one
+    bilinear factor is tiny.  Histories are withheld (n = 0) so that only
+    the taps with tiny factors remain usable, and their weights alone form
+    the history: each tiny factor must be exact (for -1/2 < mv < 0, 1 - f
+    with f = 1 + mv rounded in binary32 is not)."""
+    H, W = 16, 96
+    r = np.random.default_rng(77)
+    cur = r.uniform(0.05, 1.0, (3, H, W)).astype(np.float32)
+    z = np.full((H, W), 5.0, np.float32)
+    n = np.zeros((3, H, W), np.float32)
+    n[1] = 1.0
+    mv = np.empty((2, H, W), np.float32)
+    mv[0], mv[1] = np.float32(mvx), np.float32(mvy)
+    fr = {"rgb": cur, "z": z, "n": n, "id": None, "mv": mv, "prev_z": z.copy(),
+          "prev_n": n.copy(), "prev_id": None}
+    hist = r.uniform(0.05, 1.0, (3, H, W)).astype(np.float32)
+    m1 = hist.mean(0).astype(np.float32)
+    m2c = (0.1 * m1 * m1).astype(np.float32)
+    cols, rows = np.meshgrid(np.arange(W), np.arange(H))
+    hn = np.where((cols % 2 == 1) & (rows % 2 == 0), 0, 3).astype(np.uint8)
+    st = {"rgb": hist, "m1": m1, "m2c": m2c,
+          "m2": m2c.astype(np.float64) + m1.astype(np.float64) ** 2, "n": hn}
+    ref = O.temporal(fr, st, O.OracleParams())
+    say(f"temporal tiny bilinear factor mv=({mvx}, {mvy})")
+    g = L.GBuf(dev(z), None, None, dev(n))
+    prev = L.GBuf(dev(z), None, None, dev(n))
+    out, om1, om2 = empty_like_dev((3, H, W)), empty_like_dev((H, W)), empty_like_dev((H, W))
+    on = empty_like_dev((H, W), dtype=torch.uint8)
+    L.sv_temporal(dev(cur), g, dev(mv), prev, dev(hist), dev(m1), dev(m2c),
+                  dev(hn, dtype=torch.uint8), out, om1, om2, on, L.TemporalParams())
+    np.testing.assert_array_equal(host(on), ref["n"])
+    assert (ref["n"] > 1).sum() > H * W // 4  # histories were used
+    assert rel_err(host(out), ref["rgb"]) <= TOL32
+    assert rel_err(host(om1), ref["m1"]) <= TOL32
+    assert rel_err(host(om2), ref["m2c"]) <= TOL32
+
+
 # ---- variance ------------------------------------------------------------------------
 
 @pytest.mark.parametrize("H,W", SIZES)
