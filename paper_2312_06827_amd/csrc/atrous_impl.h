@@ -68,8 +68,10 @@ __device__ __forceinline__ void depth_coefs(const AtrousArgs &a, float &szl, flo
     ezl = a.eps_z * kLn2;
 }
 
-// grad z . (a, b) for an offset (a, b): a term whose offset component is
-// zero is left out rather than multiplied by zero.
+// grad z . (a, b) for the tile kernels' offsets: gx, gy are the gradient
+// times the (power-of-two) step and a, b in {-2..2}, so both products are
+// exact and the fma rounds once.  A term whose offset component is zero is
+// left out rather than multiplied by zero.
 __device__ __forceinline__ float grad_dot(float gx, float gy, int a, int b) {
     return b == 0 ? gx * (float)a : a == 0 ? gy * (float)b : fmaf(gx, (float)a, gy * (float)b);
 }
@@ -575,7 +577,9 @@ __global__ __launch_bounds__(256) void atrous_direct_k(AtrousArgs a) {
     float kl = 0.f;
     if (MODE != kUnit) {
         kl = luma_scale(a, g, o);
-        const float gx = ldo<T>(a.dzdx, o) * s, gy = ldo<T>(a.dzdy, o) * s;
+        // any step here: the offsets step (a, b) are integers, but their
+        // products with the gradient need not be exact (see grad_offset)
+        const float gx = ldo<T>(a.dzdx, o), gy = ldo<T>(a.dzdy, o);
         float szl, ezl;
         depth_coefs(a, szl, ezl);
 #pragma unroll
@@ -583,7 +587,8 @@ __global__ __launch_bounds__(256) void atrous_direct_k(AtrousArgs a) {
 #pragma unroll
             for (int aa = -2; aa <= 2; ++aa) {
                 if (b == 0 && aa <= 0) continue;
-                kz[kz_index(aa, b)] = depth_scale(grad_dot(gx, gy, aa, b), szl, ezl);
+                kz[kz_index(aa, b)] =
+                    depth_scale(grad_offset(gx, gy, s * (float)aa, s * (float)b), szl, ezl);
             }
     }
     constexpr float h00 = 0.375f * 0.375f;
@@ -644,13 +649,11 @@ __global__ __launch_bounds__(256) void atrous_sep_k(AtrousArgs a) {
     float kl = 0.f;
     if (MODE != kUnit) {
         kl = luma_scale(a, g, o);
-        const float grad = ld((const T *)(VERTICAL ? a.dzdy : a.dzdx) + o) * s;
+        const float grad = ld((const T *)(VERTICAL ? a.dzdy : a.dzdx) + o);
         float szl, ezl;
         depth_coefs(a, szl, ezl);
 #pragma unroll
-        for (int i = 1; i <= 2; ++i)
-            kz[i - 1] = depth_scale(VERTICAL ? grad_dot(0.f, grad, 0, i) : grad_dot(grad, 0.f, i, 0),
-                                    szl, ezl);
+        for (int i = 1; i <= 2; ++i) kz[i - 1] = depth_scale(grad * (s * (float)i), szl, ezl);
     }
     constexpr float h0 = 0.375f;
     Acc acc{h0, h0 * pc.x, h0 * pc.y, h0 * pc.z, WANT_VAR ? h0 * h0 * pv : 0.f};

@@ -121,6 +121,18 @@ __device__ __forceinline__ float add_normal_term(float e, float s2, const Normal
     return fmaf(k.snl, r, e);
 }
 
+// The depth difference p's gradient (gx, gy) predicts over an offset
+// (a, b) of integers (held as floats): gx a + gy b, rounded about once.
+// The rounding error of gy b is recovered with an fma and added back, so
+// an offset nearly orthogonal to the gradient, where the two terms almost
+// cancel, keeps its significant bits (the depth weight divides by this
+// difference).  Where both products are exact (offsets of 1 or 2 times a
+// power of two) it is the single rounding of one fma.
+__device__ __forceinline__ float grad_offset(float gx, float gy, float a, float b) {
+    const float p = gy * b;
+    return fmaf(gx, a, p) + fmaf(gy, b, -p);
+}
+
 __device__ __forceinline__ float chord2(float ax, float ay, float az, float bx, float by,
                                         float bz) {
     const float dx = ax - bx, dy = ay - by, dz = az - bz;

@@ -131,8 +131,8 @@ __device__ __forceinline__ void variance_spatial_stream(const VarianceArgs &a) {
                 w = 1.f;
             } else {
                 const float s2 = chord2(nxp, nyp, nzp, qx_[j], qy_[j], qz_[j]);
-                const float den =
-                    fmaf(a.sigma_z, fabsf(fmaf(gx, (float)dx, gy * (float)dy)), a.eps_z);
+                const float den = fmaf(
+                    a.sigma_z, fabsf(grad_offset(gx, gy, (float)dx, (float)dy)), a.eps_z);
                 float ex = -fabsf(zc - zq[j]) * (kLog2e / den);
                 ex = add_normal_term(ex, s2, a.nc);
                 w = empty_px(zq[j]) ? 0.f : __builtin_amdgcn_exp2f(ex);
