@@ -9,14 +9,20 @@ its variance vanishes away from the penumbrae, and the luminance edge
 weight exp(-|dL| / (sigma_l sqrt(g) + eps_l)) becomes a near step function
 of the luminance difference at scales far below what binary32 resolves
 (eps_l = 1e-10).  The kernels keep flat regions exactly flat (grey-exact
-luminance, correctly rounded weighted means), which holds every single 2D
-level to 1e-5; but beside the penumbrae, single roundings of the weighted
-means (and of the separable level's horizontal result) still move
-weights of nearly equal neighbours by percents, and over a chain the
-output moves by up to 3e-5 (measured).  The shadow channel's chain is
-therefore held to 1e-4, and the separable level's variance on such input,
-which differs by up to 4x where it is 1e-6 of its plane's RMS, to 1e-5 of
-that RMS; the specular channel, whose variance does not vanish, to 1e-5."""
+luminance, correctly rounded weighted means), which holds every stage to
+1e-5 from the same inputs (test_shadow_channel_stages_from_the_oracle_state,
+measured 2e-6).  A chain that feeds each side its own output back as the
+next frame's history is another matter: beside the penumbrae an ulp of
+difference in the history can switch a neighbour's weight on or off, and
+through four levels and over frames, lit pixels move by up to 3e-5 of
+their value and near-black ones (visibility ~1e-5) by a few percent of
+theirs, at most 1e-5 of the plane's scale (measured).  The chained shadow
+output (and the composite it enters) is therefore held to 1e-4 of
+max(|value|, plane RMS); the separable level's variance on such input,
+which differs by up to 4x where it is 1e-6 of its plane's RMS, is judged
+against that RMS at 1e-5.  The
+specular channel, whose variance does not vanish, is held to 1e-5 of
+every value in its chain."""
 
 from dataclasses import replace
 
@@ -34,7 +40,8 @@ from tests.test_parity_gpu import dev, empty_like_dev, host
 
 pytestmark = pytest.mark.gpu
 TOL32 = 1e-5
-TOL_BINARY = 1e-4  # zero-variance binary visibility (see above)
+FLOOR_BINARY = 1.0  # chained zero-variance visibility: errors judged against the plane RMS
+TOL_CHAIN = 1e-4  # ... and held to 1e-4 of max(|value|, RMS) (see above)
 
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float16])
@@ -87,13 +94,65 @@ def test_channel_pipeline_matches_oracle(adaptive):
             os_, ss, _ = O.run_frame(fs, ss, ps, ctl=cs)
             op, sp, _ = O.run_frame(fp, sp, pr, ctl=cp)
             ref = O.compose(fr["direct"], os_, op)
-            e = (rel_err(host(den.batch.streams[0].out), os_),
-                 rel_err(host(den.batch.streams[1].out), op), rel_err(host(out), ref))
+            e = (rel_err(host(den.batch.streams[0].out), os_, floor=FLOOR_BINARY),
+                 rel_err(host(den.batch.streams[1].out), op),
+                 rel_err(host(out), ref, floor=FLOOR_BINARY))
             say(f"  shadow {e[0]:.2e} specular {e[1]:.2e} composite {e[2]:.2e}; worst shadow "
-                f"{worst(host(den.batch.streams[0].out), os_)}")
-            assert e[0] <= TOL_BINARY and e[1] <= TOL32 and e[2] <= TOL_BINARY, (f, e)
+                f"{worst(host(den.batch.streams[0].out), os_, floor=FLOOR_BINARY)}")
+            assert e[0] <= TOL_CHAIN and e[1] <= TOL32 and e[2] <= TOL_CHAIN, (f, e)
     finally:
         den.close()
+
+
+def test_shadow_channel_stages_from_the_oracle_state():
+    """Every stage of the shadow channel, frame after frame, from the same
+    inputs as the oracle's (its history, temporal output, variance and level
+    inputs, rounded to binary32): the temporal step, the variance estimate
+    and the four levels, each within 1e-5 of the oracle, with identical
+    history lengths."""
+    frames = _channel_frames()
+    H, W = frames[0]["z"].shape
+    ps = O.OracleParams(clamp=True, use_id=True, levels=4)
+    st = O.new_state(H, W)
+    f32 = lambda a: np.asarray(a, np.float32)
+    for f, fr in enumerate(frames):
+        fs = dict(fr)
+        fs["rgb"] = fr["shadow"]
+        _, st_next, inter = O.run_frame(fs, st, ps)
+        g = L.GBuf(dev(fr["z"]), dev(fr["dzdx"]), dev(fr["dzdy"]), dev(fr["n"]),
+                   dev(fr["id"], dtype=torch.uint8))
+        prev = L.GBuf(dev(fr["prev_z"]), None, None, dev(fr["prev_n"]),
+                      dev(fr["prev_id"], dtype=torch.uint8))
+        out, om1, om2 = empty_like_dev((3, H, W)), empty_like_dev((H, W)), empty_like_dev((H, W))
+        on = empty_like_dev((H, W), dtype=torch.uint8)
+        L.sv_temporal(dev(fs["rgb"]), g, dev(fr["mv"]), prev, dev(f32(st["rgb"])),
+                      dev(f32(st["m1"])), dev(f32(st["m2"] - st["m1"] ** 2)),
+                      dev(st["n"], dtype=torch.uint8), out, om1, om2, on, SHADOW.temporal())
+        t = inter["temporal"]
+        e = {"temporal": rel_err(host(out), t["rgb"]), "m1": rel_err(host(om1), t["m1"])}
+        np.testing.assert_array_equal(host(on), t["n"])
+        m1, m2c = f32(t["m1"]), f32(np.maximum(t["m2c"], 0.0))
+        var = empty_like_dev((H, W))
+        L.sv_variance(dev(m1), dev(m2c), dev(t["n"], dtype=torch.uint8), g, var,
+                      SHADOW.variance(), L.variance_workspace(var))
+        e["variance"] = rel_err(host(var), O.variance(
+            m1, m2c.astype(np.float64) + m1.astype(np.float64) ** 2, t["n"], fr["z"],
+            fr["dzdx"], fr["dzdy"], fr["n"]))
+        c, v = f32(t["rgb"]), f32(inter["var"])
+        for i in range(4):
+            last = i == 3
+            rc, rv = O.atrous(c, v, fr["z"], fr["dzdx"], fr["dzdy"], fr["n"], 1 << i,
+                              want_var=not last)
+            co = empty_like_dev((3, H, W))
+            vo = None if last else empty_like_dev((H, W))
+            L.sv_atrous(dev(c), dev(v), g, co, vo, 1 << i, SHADOW.atrous())
+            e[f"level{i}"] = rel_err(host(co), rc)
+            if not last:
+                e[f"var{i}"] = rel_err(host(vo), rv)
+                c, v = f32(rc), f32(rv)
+        say(f"shadow stages frame {f}: " + " ".join(f"{k} {x:.1e}" for k, x in e.items()))
+        assert max(e.values()) <= TOL32, (f, e)
+        st = st_next
 
 
 def test_channel_batch_equals_channels_alone():
@@ -188,9 +247,9 @@ def test_channel_pipeline_with_temporal_gradient():
             op, sp, _ = O.run_frame(fp, sp, pr)
             if am is not None:
                 np.testing.assert_allclose(host(den.grad_alpha), am, atol=1e-5, rtol=0)
-            e = (rel_err(host(den.batch.streams[0].out), os_),
+            e = (rel_err(host(den.batch.streams[0].out), os_, floor=FLOOR_BINARY),
                  rel_err(host(den.batch.streams[1].out), op))
             say(f"  shadow {e[0]:.2e} specular {e[1]:.2e}")
-            assert e[0] <= TOL_BINARY and e[1] <= TOL32, (f, e)
+            assert e[0] <= TOL_CHAIN and e[1] <= TOL32, (f, e)
     finally:
         den.close()
