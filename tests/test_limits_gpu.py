@@ -130,3 +130,49 @@ def test_temporal_and_variance_at_the_limits(H, W, P):
     rv = O.variance(m1v, m2raw, nv, fr["z"], fr["dzdx"], fr["dzdy"], fr["n"])
     assert (nv[fr["z"] > 0] < 4).sum() > 1000  # the spatial estimate is exercised
     assert rel_err(host(var), rv) <= TOL32
+
+
+@pytest.mark.parametrize("H,W,P", [TALL, WIDE])
+def test_atrous_half_at_the_limits(H, W, P):
+    """Binary16 storage (byte offsets up to 2^30) against the oracle with
+    binary16 rounding at the same storage points, bar 2e-3."""
+    r = np.random.default_rng(3000 + W)
+    z, dzdx, dzdy, n = (a.astype(np.float16) for a in random_gbuf(r, H, W))
+    c = r.exponential(0.5, (3, H, W)).astype(np.float16)
+    var = r.uniform(0.001, 0.05, (H, W)).astype(np.float32)
+    h = torch.float16
+    g = L.GBuf(padded(z, P, h), padded(dzdx, P, h), padded(dzdy, P, h), padded(n, P, h))
+    ci, vi = padded(c, P, h), padded(var, P)
+    for step, sep in ((1, False), (16, False), (16, True)):
+        say(f"atrous f16 {H}x{W} pitch {P} step {step} sep={sep}")
+        out, vo = out_plane((3, H, W), P, h), out_plane((H, W), P)
+        if sep:
+            L.sv_atrous_sep(ci, vi, g, None, out, vo, step, L.AtrousParams())
+            rc, rv, _ = O.atrous_sep(c, var, z, dzdx, dzdy, n, step, half_out=True)
+        else:
+            L.sv_atrous(ci, vi, g, out, vo, step, L.AtrousParams())
+            rc, rv = O.atrous(c, var, z, dzdx, dzdy, n, step, half_out=True)
+        assert rel_err(host(out), rc) <= 2e-3
+        assert rel_err(host(vo), rv) <= 2e-3
+
+
+def test_batch_of_the_tallest_and_widest_streams():
+    """A batch plan whose streams are the tallest and the widest image: each
+    stream equals, bitwise, the same stream run alone (the batched passes
+    index tiles through prefix sums over the streams)."""
+    from paper_2312_06827_amd.pipeline import MOTION, BatchDenoiser, Denoiser, FrameInputs
+    sizes = [(TALL[0], TALL[1]), (WIDE[0], WIDE[1])]
+    cfgs = [with_size(CONFIGS["hd_motion"], w, h, 2) for (h, w) in sizes]
+    batch = BatchDenoiser(sizes, MOTION)
+    singles = [Denoiser(h, w, MOTION) for (h, w) in sizes]
+    try:
+        for f in range(2):
+            say(f"batch of the limit shapes, frame {f}")
+            inputs = [FrameInputs.from_numpy(render_frame(c, f)) for c in cfgs]
+            outs = batch.frame(inputs)
+            refs = [d.frame(inp) for d, inp in zip(singles, inputs)]
+            torch.cuda.synchronize()
+            for i in range(len(sizes)):
+                assert torch.equal(outs[i], refs[i]), (f, i)
+    finally:
+        batch.close()
