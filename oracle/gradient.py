@@ -31,7 +31,13 @@ steps below are the readings used (each is stated where it is made):
    `levels` 5x5 a-trous B3 kernels at cell steps 1, 2, 4, ... with a depth
    edge weight exp(-|z_c - z_d| / (sigma_z |dz . o| + eps)) between the
    cells' centre pixels (o the offset in pixels); delta, norm and the
-   sample indicator are filtered alike and divided at the end.
+   sample indicator are filtered alike and divided at the end.  The sums
+   are carried as the ratios (weighted means of delta and norm) and the
+   logarithm of the filtered indicator, each level's terms combined with
+   their largest exponent factored out: the same quotients, with no
+   underflow where every weight reaching a cell is tiny (a cell far across
+   depth edges from every sample), where plain binary64 sums would fall
+   into subnormal numbers and lose the ratio's digits.
 6. lambda = min(1, |delta_hat| / norm_hat) (0 where norm_hat is 0 or no
    sample reached the cell), and the blend factor of every pixel of the
    cell is alpha' = (1 - lambda) alpha + lambda: the history is dropped
@@ -108,7 +114,14 @@ def gradient_samples(prev_rgb, reshade_rgb, fmv, fz, pick, z, tau_z=0.1):
 
 
 def reconstruct(delta, norm, present, z, dzdx, dzdy, levels=3, sigma_z=1.0, eps_z=1e-10):
-    """Step 5 and the ratio of step 6: lambda per cell."""
+    """Step 5 and the ratio of step 6: lambda per cell.
+
+    The normalized convolution sum_j w_j x_j / sum_j w_j p_j, cascaded over
+    the levels, is carried per cell as (mean of delta, mean of norm, natural
+    logarithm of the filtered indicator): a level's sum over taps j of
+    w_ij * (indicator sum of j) * (means of j) is formed as
+    exp(t_ij - t_max) terms with t_ij = log w_ij + log(indicator sum of j),
+    which is the plain sum divided by exp(t_max)."""
     H, W = z.shape
     CH, CW = delta.shape
     cyy = np.minimum(3 * np.arange(CH) + 1, H - 1)
@@ -116,31 +129,40 @@ def reconstruct(delta, norm, present, z, dzdx, dzdy, levels=3, sigma_z=1.0, eps_
     zc = np.asarray(z, np.float64)[np.ix_(cyy, cxx)]
     gx = np.asarray(dzdx, np.float64)[np.ix_(cyy, cxx)]
     gy = np.asarray(dzdy, np.float64)[np.ix_(cyy, cxx)]
-    a = [delta * present, norm * present, present.copy()]
+    have = present > 0
+    d = np.where(have, delta, 0.0)          # weighted mean of delta
+    m = np.where(have, norm, 0.0)           # weighted mean of norm
+    lg = np.where(have, 0.0, -np.inf)       # log of the indicator's sum
     for lvl in range(levels):
         s = 1 << lvl
-        out = [np.zeros_like(x) for x in a]
+        nd, nm, nlg = np.zeros_like(d), np.zeros_like(m), np.full_like(lg, -np.inf)
         for cy in range(CH):
             for cx in range(CW):
-                acc = [0.0, 0.0, 0.0]
+                ts, ds, ms = [], [], []
                 for b in range(-2, 3):
                     for c in range(-2, 3):
                         ny, nx = cy + b * s, cx + c * s
-                        if not (0 <= ny < CH and 0 <= nx < CW):
+                        if not (0 <= ny < CH and 0 <= nx < CW) or lg[ny, nx] == -np.inf:
                             continue
                         # offset between the centre pixels, in pixels
                         ox, oy = 3.0 * c * s, 3.0 * b * s
                         den = sigma_z * abs(gx[cy, cx] * ox + gy[cy, cx] * oy) + eps_z
-                        w = _H1[b + 2] * _H1[c + 2] * np.exp(-abs(zc[cy, cx] - zc[ny, nx]) / den)
-                        for i in range(3):
-                            acc[i] += w * a[i][ny, nx]
-                for i in range(3):
-                    out[i][cy, cx] = acc[i]
-        a = out
+                        ts.append(np.log(_H1[b + 2] * _H1[c + 2])
+                                  - abs(zc[cy, cx] - zc[ny, nx]) / den + lg[ny, nx])
+                        ds.append(d[ny, nx])
+                        ms.append(m[ny, nx])
+                if not ts:
+                    continue
+                t = np.array(ts)
+                top = t.max()
+                w = np.exp(t - top)
+                nd[cy, cx] = np.dot(w, ds) / w.sum()
+                nm[cy, cx] = np.dot(w, ms) / w.sum()
+                nlg[cy, cx] = top + np.log(w.sum())
+        d, m, lg = nd, nm, nlg
+    reached = lg > -np.inf
     with np.errstate(divide="ignore", invalid="ignore"):
-        d_hat = np.where(a[2] > 0, a[0] / a[2], 0.0)
-        n_hat = np.where(a[2] > 0, a[1] / a[2], 0.0)
-        lam = np.where(n_hat > 0, np.minimum(1.0, np.abs(d_hat) / n_hat), 0.0)
+        lam = np.where(reached & (m > 0), np.minimum(1.0, np.abs(d) / m), 0.0)
     return lam
 
 

@@ -132,3 +132,27 @@ def test_depth_edges_keep_gradients_apart():
     lam = G.reconstruct(delta, norm, present, z, dz, dz, levels=3)
     np.testing.assert_allclose(lam[:, :CW // 2], 1.0, rtol=1e-12)
     np.testing.assert_allclose(lam[:, CW // 2:], 0.0, atol=1e-12)
+
+
+def test_reconstruction_keeps_the_ratio_of_tiny_weights():
+    """A cell without a sample between two cells far across depth edges:
+    their weights are about e^-733 (1e-318, subnormal in binary64) and in the
+    ratio 3:1 by construction, so the cell's means are the 3:1 averages of
+    theirs and lambda has a closed form, which summing the tiny weights in
+    plain binary64 would lose."""
+    H, W = 3, 9  # one row of three cells, centre pixels x = 1, 4, 7
+    g = 1e-3
+    den = 1.0 * abs(g * 3.0) + 1e-10
+    z = np.full((H, W), 5.0)
+    z[1, 1] = 5.0 + 733.0 * den
+    z[1, 7] = 5.0 + 733.0 * den + np.log(3.0) * den
+    dzdx = np.zeros((H, W))
+    dzdx[1, 4] = g
+    dzdy = np.zeros((H, W))
+    delta = np.array([[0.3, 0.0, -0.5]])
+    norm = np.array([[1.0, 0.0, 2.0]])
+    present = np.array([[1.0, 0.0, 1.0]])
+    lam = G.reconstruct(delta, norm, present, z, dzdx, dzdy, levels=1)
+    d_hat = (3 * 0.3 + 1 * -0.5) / 4
+    n_hat = (3 * 1.0 + 1 * 2.0) / 4
+    assert abs(lam[0, 1] - abs(d_hat) / n_hat) < 1e-12
