@@ -15,6 +15,17 @@
 //                   depth edge weight, on (delta, norm, present) alike
 //   grad_alpha_k    per pixel: lambda = min(1, |delta| / norm) of its cell,
 //                   alpha' = alpha + lambda (1 - alpha)
+//
+// The normalized convolution is carried in a form with no underflow.  A
+// cell holds (d, m, l): the weighted means of delta and norm over the
+// samples that reached it and l = log2 of their total weight (-inf: none).
+// A level combines its 25 taps in the log domain, each tap's exponent
+// (kernel coefficient, depth weight, l of the tap) shifted by the largest,
+// and yields the new means and l = that maximum + log2 of the shifted sum.
+// In exact arithmetic this is the plain convolution of (delta p, norm p, p)
+// with the means taken at the end; binary32 weights of a cell whose every
+// neighbour lies far across depth edges (2^-150 and below) would underflow
+// to zero there, and the cell would lose the ratio the plain sums define.
 #include "sv_internal.h"
 
 namespace sv {
@@ -84,21 +95,23 @@ __global__ __launch_bounds__(256) void grad_gather_k(GradArgs a) {
         a.cz[c] = make_float4(ldo<T>(a.z, o), ldo<T>(a.dzdx, o), ldo<T>(a.dzdy, o), 0.f);
     }
     const uint32_t s = a.key[c];
-    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 v = make_float4(0.f, 0.f, -INFINITY, 0.f);  // (d, m, l): no sample
     if (s != kNone) {
         const int sy = (int)s / a.cw, sx = (int)s - sy * a.cw;
         const int k = a.pick[s];
         const uint32_t q = (uint32_t)(3 * sy + k / 3) * (uint32_t)a.pitch + (uint32_t)(3 * sx + k % 3);
         const float lp = luma(ldo<T>(a.pr, q), ldo<T>(a.pg, q), ldo<T>(a.pb, q));
         const float lr = luma(ldo<T>(a.rr, q), ldo<T>(a.rg, q), ldo<T>(a.rb, q));
-        v = make_float4(lr - lp, fmaxf(lr, lp), 1.f, 0.f);
+        v = make_float4(lr - lp, fmaxf(lr, lp), 0.f, 0.f);  // one sample of weight 1
     }
     a.ca[c] = v;
 }
 
-__constant__ float kB3[5] = {0.0625f, 0.25f, 0.375f, 0.25f, 0.0625f};
+// log2 of the B3-spline taps (1, 4, 6, 4, 1) / 16
+__constant__ float kLog2B3[5] = {-4.0f, -2.0f, -1.4150374992788438f, -2.0f, -4.0f};
 
-// One cascade level at cell step `step`: from `src` into `dst`.
+// One cascade level at cell step `step`: from `src` into `dst`, cells as
+// (d, m, l) (see above).
 __global__ __launch_bounds__(256) void grad_atrous_k(GradArgs a, const float4 *src, float4 *dst,
                                                     int step) {
     const int c = (int)blockIdx.x * 256 + (int)threadIdx.x;
@@ -106,24 +119,42 @@ __global__ __launch_bounds__(256) void grad_atrous_k(GradArgs a, const float4 *s
     const int cy = c / a.cw, cx = c - cy * a.cw;
     const float4 cc = a.cz[c];
     const float zc = cc.x, gx = cc.y, gy = cc.z;
-    float sd = 0.f, sn = 0.f, sp = 0.f;
+    float e[25], d[25], m[25];
+    float top = -INFINITY;
 #pragma unroll
     for (int b = -2; b <= 2; ++b) {
 #pragma unroll
-        for (int e = -2; e <= 2; ++e) {
-            const int ny = cy + b * step, nx = cx + e * step;
+        for (int k = -2; k <= 2; ++k) {
+            const int t = (b + 2) * 5 + (k + 2);
+            const int ny = cy + b * step, nx = cx + k * step;
+            e[t] = -INFINITY;
+            d[t] = m[t] = 0.f;
             if (ny < 0 || ny >= a.ch || nx < 0 || nx >= a.cw) continue;
-            const float ox = 3.f * (float)(e * step), oy = 3.f * (float)(b * step);
-            const float den = fmaf(a.sigma_z, fabsf(fmaf(gx, ox, gy * oy)), 1e-10f);
-            const float zd = a.cz[ny * a.cw + nx].x;
-            const float w = kB3[b + 2] * kB3[e + 2] * exp2f(-fabsf(zc - zd) * (kLog2e / den));
-            const float4 v = src[ny * a.cw + nx];
-            sd = fmaf(w, v.x, sd);
-            sn = fmaf(w, v.y, sn);
-            sp = fmaf(w, v.z, sp);
+            const int q = ny * a.cw + nx;
+            const float4 v = src[q];
+            if (!(v.z > -INFINITY)) continue;  // no sample reached that cell
+            // offset between the centre pixels, in pixels
+            const float ox = 3.f * (float)(k * step), oy = 3.f * (float)(b * step);
+            const float den = fmaf(a.sigma_z, fabsf(grad_offset(gx, gy, ox, oy)), 1e-10f);
+            e[t] = kLog2B3[b + 2] + kLog2B3[k + 2] - fabsf(zc - a.cz[q].x) * (kLog2e / den) + v.z;
+            d[t] = v.x;
+            m[t] = v.y;
+            top = fmaxf(top, e[t]);
         }
     }
-    dst[c] = make_float4(sd, sn, sp, 0.f);
+    float4 out = make_float4(0.f, 0.f, -INFINITY, 0.f);
+    if (top > -INFINITY) {
+        float sw = 0.f, sd = 0.f, sm = 0.f;
+#pragma unroll
+        for (int t = 0; t < 25; ++t) {
+            const float w = exp2f(e[t] - top);  // 0 for a tap without samples
+            sw += w;
+            sd = fmaf(w, d[t], sd);
+            sm = fmaf(w, m[t], sm);
+        }
+        out = make_float4(sd / sw, sm / sw, top + log2f(sw), 0.f);
+    }
+    dst[c] = out;
 }
 
 __global__ __launch_bounds__(256) void grad_alpha_k(GradArgs a, const float4 *cells) {
@@ -131,9 +162,8 @@ __global__ __launch_bounds__(256) void grad_alpha_k(GradArgs a, const float4 *ce
     const int y = (int)blockIdx.y * 4 + (int)(threadIdx.x >> 6);
     if (x >= a.w || y >= a.h) return;
     const int c = (y / 3) * a.cw + x / 3;
-    const float4 v = cells[c];
-    // |delta_hat| / norm_hat: the common normaliser cancels
-    const float lam = (v.z > 0.f && v.y > 0.f) ? fminf(1.f, fabsf(v.x) / v.y) : 0.f;
+    const float4 v = cells[c];  // (d, m, l): weighted means of delta and norm
+    const float lam = (v.z > -INFINITY && v.y > 0.f) ? fminf(1.f, fabsf(v.x) / v.y) : 0.f;
     stf(a.alpha_map, (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x, fmaf(lam, 1.f - a.alpha, a.alpha));
     if (a.lambda && x % 3 == 0 && y % 3 == 0) a.lambda[c] = lam;
 }

@@ -86,3 +86,34 @@ def test_gradient_without_change_keeps_alpha():
     am, lam = _run(prev, prev, np.zeros((2, H, W)), z, pick, z, zero, zero, alpha=0.3)
     assert np.all(lam == 0.0)
     np.testing.assert_array_equal(am, np.float32(0.3))
+
+
+def test_gradient_with_tiny_weights():
+    """A cell without a sample between two that lie far across depth edges
+    (weights about e^-733, far below binary32's range, in the ratio 3:1):
+    its lambda is the ratio of their weighted means, as the oracle forms
+    it, not 0 from weights that underflowed."""
+    H, W = 3, 9
+    g = 1e-3
+    den = abs(np.float32(g) * 3.0) + 1e-10
+    z = np.full((H, W), 5.0)
+    z[1, 1] = 5.0 + 733.0 * den
+    z[1, 7] = 5.0 + 733.0 * den + np.log(3.0) * den
+    z = z.astype(np.float32).astype(np.float64)
+    dzdx = np.zeros((H, W))
+    dzdx[1, 4] = g
+    dzdx = dzdx.astype(np.float32).astype(np.float64)
+    dzdy = np.zeros((H, W))
+    prev = np.full((3, H, W), 0.5)
+    re = np.full((3, H, W), 0.5)
+    prev[:, 1, 1], re[:, 1, 1] = 0.7, 1.0   # delta 0.3, norm 1
+    prev[:, 1, 7], re[:, 1, 7] = 2.0, 1.5   # delta -0.5, norm 2
+    pick = np.array([[4, 9, 4]], np.uint8)  # the middle stratum has no sample
+    fmv = np.zeros((2, H, W))
+    for levels in (1, 3):
+        am, lam = _run(prev, re, fmv, z, pick, z, dzdx, dzdy, levels=levels)
+        ram, rlam = OG.temporal_gradient(prev, re, fmv, z, pick, z, dzdx, dzdy, levels=levels)
+        say(f"tiny weights, levels {levels}: lambda {lam.ravel()} oracle {rlam.ravel()}")
+        assert rlam[0, 1] > 0.05
+        np.testing.assert_allclose(lam, rlam, atol=TOL, rtol=0)
+        np.testing.assert_allclose(am, ram, atol=TOL, rtol=0)

@@ -176,3 +176,55 @@ def test_batch_of_the_tallest_and_widest_streams():
                 assert torch.equal(outs[i], refs[i]), (f, i)
     finally:
         batch.close()
+
+
+@pytest.mark.parametrize("H,W,P", [(32768, 8, LIMIT // 32768), WIDE])
+def test_temporal_gradient_at_the_limits(H, W, P):
+    """The gradient's strata, cells and normalized convolution at the
+    limits (the tall case keeps to 8 columns: the oracle is Python)."""
+    from oracle import gradient as OG
+    r = np.random.default_rng(4000 + W)
+    q = lambda a: a.astype(np.float32).astype(np.float64)
+    prev = q(r.uniform(0, 2, (3, H, W)))
+    re = q(np.where(r.random((3, H, W)) < 0.7, prev, r.uniform(0, 2, (3, H, W))))
+    fmv = q(r.normal(0, 2.5, (2, H, W)))
+    z = q(r.uniform(4, 6, (H, W)))
+    z[r.random((H, W)) < 0.03] = 0.0
+    fz = q(z * np.where(r.random((H, W)) < 0.1, 1.5, 1.0))
+    dzdx, dzdy = q(r.normal(0, 0.05, (H, W))), q(r.normal(0, 0.05, (H, W)))
+    pick = r.integers(0, 10, OG.cells_of(H, W)).astype(np.uint8)
+    say(f"temporal gradient {H}x{W} pitch {P}")
+    g = L.GBuf(padded(z, P), padded(dzdx, P), padded(dzdy, P), padded(np.zeros((3, H, W)), P))
+    am = out_plane((H, W), P)
+    lam = torch.full(OG.cells_of(H, W), float("nan"), device="cuda")
+    L.sv_temporal_gradient(padded(prev, P), padded(re, P), padded(fmv, P), padded(fz, P),
+                           torch.from_numpy(pick).cuda(), g, am, L.gradient_workspace(am),
+                           alpha=0.2, levels=3, lam=lam)
+    ram, rlam = OG.temporal_gradient(prev, re, fmv, fz, pick, z, dzdx, dzdy)
+    np.testing.assert_allclose(host(lam), rlam, atol=1e-5, rtol=0)
+    np.testing.assert_allclose(host(am), ram, atol=1e-5, rtol=0)
+
+
+@pytest.mark.parametrize("H,W,P", [TALL, WIDE])
+def test_adaptive_levels_at_the_limits(H, W, P):
+    """Control bytes from roughness (bitwise) and the first two adaptive
+    levels, 2D and fused separable, at the limits."""
+    c, var, z, dzdx, dzdy, n = _atrous_inputs(H, W, 5000 + W)
+    rough = np.random.default_rng(5000).uniform(0.0, 0.4, (H, W)).astype(np.float32)
+    rough[:, ::7] = 0.0  # some pixels with no blur at all
+    ctl = out_plane((H, W), P, torch.uint8)
+    L.sv_blur_control(padded(rough, P), None, ctl, L.BlurRule())
+    rctl = O.blur_control(rough)
+    np.testing.assert_array_equal(host(ctl), rctl)
+    g = gbuf(z, dzdx, dzdy, n, P)
+    for sep in (False, True):
+        ci, vi = c, var
+        for level in (0, 1):
+            say(f"adaptive {H}x{W} pitch {P} level {level} sep={sep}")
+            out, vo = out_plane((3, H, W), P), out_plane((H, W), P)
+            L.sv_atrous_adaptive(padded(ci, P), padded(vi, P), g, ctl, None, out, vo, level, sep,
+                                 L.AtrousParams())
+            rc, rv = O.atrous_adaptive(ci, vi, z, dzdx, dzdy, n, rctl, level, separable=sep)[:2]
+            assert rel_err(host(out), rc) <= TOL32
+            assert rel_err(host(vo), rv) <= TOL32
+            ci, vi = rc.astype(np.float32), rv.astype(np.float32)
