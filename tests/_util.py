@@ -11,9 +11,11 @@ def say(msg):
     sys.stdout.flush()
 
 
-def rel_err(gpu, ora, floor=1e-3):
-    """Largest relative error |g - o| / max(|o|, floor * RMS(o)), taken per
-    plane (leading axes are planes) and maximised."""
+def rel_err(gpu, ora, floor=1e-3, abs_floor=0.0):
+    """Largest relative error |g - o| / max(|o|, floor * RMS(o), abs_floor),
+    taken per plane (leading axes are planes) and maximised.  abs_floor
+    states the plane's scale where the oracle's plane alone cannot (a
+    variance that is zero but for rounding residues)."""
     g = np.asarray(gpu, dtype=np.float64)
     o = np.asarray(ora, dtype=np.float64)
     assert g.shape == o.shape, (g.shape, o.shape)
@@ -24,7 +26,7 @@ def rel_err(gpu, ora, floor=1e-3):
     worst = 0.0
     for gp, op in zip(g, o):
         rms = np.sqrt(np.mean(op * op))
-        den = np.maximum(np.abs(op), floor * rms)
+        den = np.maximum(np.maximum(np.abs(op), floor * rms), abs_floor)
         den = np.where(den > 0, den, 1.0)
         e = np.abs(gp - op) / den
         if not np.all(np.isfinite(e)):
@@ -56,7 +58,7 @@ def worst(gpu, ora, floor=1e-3):
     best = (0.0, None)
     for k, (gp, op) in enumerate(zip(g, o)):
         rms = np.sqrt(np.mean(op * op))
-        den = np.maximum(np.abs(op), floor * rms)
+        den = np.maximum(np.maximum(np.abs(op), floor * rms), abs_floor)
         den = np.where(den > 0, den, 1.0)
         e = np.abs(gp - op) / den
         i = np.unravel_index(int(np.argmax(e)), e.shape)
