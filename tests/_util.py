@@ -49,7 +49,7 @@ def random_gbuf(r, H, W, z_range=(4.0, 6.0)):
     return f(z), f(dzdx), f(dzdy), f(n)
 
 
-def worst(gpu, ora, floor=1e-3):
+def worst(gpu, ora, floor=1e-3, abs_floor=0.0):
     """Where the relative error of rel_err() peaks: (plane, y, x, gpu, oracle)."""
     g = np.asarray(gpu, dtype=np.float64)
     o = np.asarray(ora, dtype=np.float64)
