@@ -494,7 +494,7 @@ def main():
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this library runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
 
     H, W = WORKLOAD.height, WORKLOAD.width

@@ -19,7 +19,7 @@ their value and near-black ones (visibility ~1e-5) by a few percent of
 theirs, at most 1e-5 of the plane's scale (measured).  The chained shadow
 output (and the composite it enters) is therefore held to 1e-4 of
 max(|value|, plane RMS); the separable level's variance on such input,
-which differs by up to 4x where it is 1e-6 of its plane's RMS, is judged
+which differs by up to 4x where it is 1e-6 of its plane's RMS, is measured
 against that RMS at 1e-5.  The
 specular channel, whose variance does not vanish, is held to 1e-5 of
 every value in its chain."""
@@ -40,7 +40,7 @@ from tests.test_parity_gpu import dev, empty_like_dev, host
 
 pytestmark = pytest.mark.gpu
 TOL32 = 1e-5
-FLOOR_BINARY = 1.0  # chained zero-variance visibility: errors judged against the plane RMS
+FLOOR_BINARY = 1.0  # chained zero-variance visibility: errors measured against the plane RMS
 TOL_CHAIN = 1e-4  # ... and held to 1e-4 of max(|value|, RMS) (see above)
 
 
@@ -208,7 +208,7 @@ def test_levels_on_binary_visibility(sep):
             L.sv_atrous(dev(c), dev(v), g, out, vo, step, L.AtrousParams())
             rc, rv = O.atrous(c, v, z, dzdx, dzdy, n, step)
         ec = rel_err(host(out), rc)
-        # the separable level's variance where it nearly vanishes is judged
+        # the separable level's variance where it nearly vanishes is measured
         # against the plane's own scale (see above)
         ev = rel_err(host(vo), rv, floor=1.0 if sep else 1e-3)
         say(f"  colour {ec:.2e} {worst(host(out), rc)}  var {ev:.2e} {worst(host(vo), rv)}")

@@ -3,7 +3,7 @@ frame after frame: no surface anywhere (depth 0, or not finite), motion
 that is unusable everywhere, a constant image, and images of one or two
 pixels.  Outputs, temporal intermediates and variance within 1e-5 (the
 variance, which is zero but for rounding residues in some of these cases,
-judged in its own units: the mean squared luminance), history lengths
+measured in its own units: the mean squared luminance), history lengths
 exact; the closed forms each case has are checked as well."""
 
 from dataclasses import replace
@@ -49,7 +49,7 @@ def _run(frames, filt, ofilt):
         inter = den.intermediates()
         np.testing.assert_array_equal(host(inter["n"]), ex["temporal"]["n"])
         # a variance plane that is zero but for rounding residues (a constant
-        # image, one pixel) is judged in its own units: differences below
+        # image, one pixel) is measured in its own units: differences below
         # 1e-12 of the mean squared luminance (binary32's resolution of a
         # square) are zero
         lsq = float(np.mean(ex["temporal"]["m1"] ** 2))
