@@ -32,11 +32,12 @@ if ROOT not in sys.path:
 from paper_2312_06827_amd.scene import CONFIGS, render_frame  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-# VALU issue rate with packed FP32 off: 256 CUs x 4 SIMDs x 16 lanes x
-# 2.4 GHz = 39.3 T lane-operations per second (a transcendental takes four
-# issue slots).  The published 157.3 TFLOP/s counts an FMA as two flops and
-# packed (two-wide) FP32 issue, which this library does not generate.
-VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# VALU issue rate: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz = 78.6 T
+# lane-operations per second, the published 157.3 TFLOP/s FP32 vector peak
+# with an FMA counted as one operation.  Non-packed FP32 instructions reach
+# it on this chip (the issue-rate probe's FMA links issue a wave64
+# instruction in about two cycles), so it is the a-trous level's ALU peak.
+VALU_PEAK_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12
 WORKLOAD = CONFIGS["hd_motion"]
 PROFILES = os.path.join(ROOT, "profiles")
 
@@ -59,15 +60,44 @@ BYTES_PER_PX = {
 }
 
 
-# Algorithmic VALU slots per output pixel of one a-trous level (FP32 ops
-# of the level's definition, one slot each, a transcendental four).  Per
-# non-centre tap: depth term 2, luminance term 2, normal term 12 (chord 6,
-# max + log2 + scale 6), exp2 4, accumulation 6 (Σw, three colour FMAs,
-# w² var).  Per pixel: 3x3 variance prefilter 23, luminance scale 11, the
-# 12 distinct depth scales 84, own luminance 3, centre tap 5, normalisation
-# 9.  The separable level: 4 horizontal taps without the variance term
-# (24 each) plus 62 per pixel, and 4 vertical taps (26 each) plus 65.
-ALU_OPS_PER_PX = {"atrous": 24 * 26 + 135, "atrous_sep": 4 * 24 + 62 + 4 * 26 + 65}
+# Algorithmic VALU slots per output pixel of the 5x5 a-trous level: the
+# FP32 operations of the level's definition, one full-rate issue slot each
+# but for the transcendentals, which are priced at their issue cost measured
+# on the GPU the benchmark runs on (issue_costs).  Per non-centre tap: depth term 2,
+# luminance term 2, normal term 8 + log2 (chord 6, u, scale), exp2, and the
+# accumulation 6 (sum of weights, three colour FMAs, w^2 var).  Per pixel:
+# 71 plain operations (3x3 variance prefilter 19, luminance scale 3, the 12
+# distinct depth scales 36, own luminance 3, centre tap 5, normalisation 5)
+# plus 15 reciprocals (prefilter, luminance scale, 12 depth scales,
+# normalisation) and one square root.
+def atrous_ops_per_px(cost):
+    return 24 * (18 + cost["log2"] + cost["exp2"]) + 71 + 15 * cost["rcp"] + cost["sqrt"]
+
+
+def issue_costs(torch, blocks=8192, iters=2048, reps=3):
+    """Issue cost of exp2, log2, rcp and sqrt in full-rate VALU slots (the
+    issue time of the probe's FMA link, which runs at the full rate), from
+    the library's issue-rate probe: each chain link is the operation beside
+    one or two full-rate ones, timed against FMA links."""
+    from paper_2312_06827_amd import lib
+
+    out = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t = {}
+    for kind in range(5):
+        lib.sv_probe_issue(out, kind, iters)  # warm
+        best = float("inf")
+        for _ in range(reps):
+            a.record()
+            lib.sv_probe_issue(out, kind, iters)
+            b.record()
+            torch.cuda.synchronize()
+            best = min(best, a.elapsed_time(b))
+        t[kind] = best
+    unit = t[0]  # one FMA per link
+    return {"exp2": round(t[1] / unit - 1, 2), "log2": round(t[2] / unit - 2, 2),
+            "rcp": round(t[3] / unit - 2, 2), "sqrt": round(t[4] / unit - 2, 2)}
+
 
 # Source files that make up the 2D a-trous kernel; PMC traffic measured on
 # them is reported only while they are unchanged.
@@ -544,13 +574,16 @@ def main():
     mean_us = tot_ms / launches * 1e3
     tot_bytes = sum(ktimes[k][1] * npx * BYTES_PER_PX["atrous_last" if k.endswith("4") else "atrous"]
                     for k in lv)
-    achieved = npx * ALU_OPS_PER_PX["atrous"] / (mean_us * 1e-6) / 1e12
+    costs = issue_costs(torch)
+    ops_px = atrous_ops_per_px(costs)
+    achieved = npx * ops_px / (mean_us * 1e-6) / 1e12
     hbm_gbs = tot_bytes / (tot_ms * 1e-3) / 1e9
     roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": round(VALU_PEAK_TOPS, 2),
                 "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
                 "traffic": measured_traffic(),
                 "kernel": "atrous 5x5 level (mean over the five levels)",
-                "ops_per_px": ALU_OPS_PER_PX["atrous"], "px_per_launch": npx,
+                "ops_per_px": round(ops_px, 1), "transcendental_slots": costs,
+                "px_per_launch": npx,
                 "launch_us": round(mean_us, 2),
                 "algorithmic_bytes_per_launch": round(tot_bytes / launches),
                 "hbm_achieved_gbs": round(hbm_gbs, 1),

@@ -667,6 +667,19 @@ int sv_last_hip_error(void);
  * roofline figures are compared with. */
 int sv_probe_copy(void *dst, const void *src, size_t bytes, sv_stream stream);
 
+/* Issue-rate probe: `blocks` workgroups of 256 lanes, each lane running
+ * eight independent chains of `iters` links, a link being one fma
+ * (kind 0), or exp2 and a multiply (1), or an add, log2 and a multiply
+ * (2), or the same with rcp (3) or sqrt (4).  Kind 0's fma is a form
+ * that issues at the full rate (a wave64 instruction in about two cycles on
+ * MI355X); timed against it, the other kinds give the issue cost of those
+ * instructions in full-rate slots, which prices the a-trous level's
+ * arithmetic in the roofline.  `out`: device buffer of
+ * blocks * 256 floats (one result per lane, written).  SV_EINVAL for a
+ * kind outside 0..4, iters outside 1..2^20, blocks outside 1..65536 or a
+ * null `out`. */
+int sv_probe_issue(int32_t kind, int32_t iters, float *out, int32_t blocks, sv_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,4 +1,5 @@
-// Status strings, version, error capture and the copy bandwidth probe.
+// Status strings, version, error capture, the copy bandwidth probe and the
+// issue-rate probe.
 #include "sv_internal.h"
 
 namespace sv {
@@ -17,6 +18,33 @@ __global__ __launch_bounds__(256) void probe_copy_k(uint4 *__restrict__ dst,
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (; i < n; i += stride) dst[i] = src[i];
+}
+
+// Issue-rate probe: eight independent chains per lane, each link one
+// operation under test beside full-rate ones (KIND 0: fma with literal
+// operands, which issues at the full rate; 1: exp2, mul;
+// 2: add, log2, mul; 3: add, rcp, mul; 4: add, sqrt, mul).  The values
+// stay bounded (exp2 of [0, 1/2], log2 / rcp / sqrt of [1.5, 2.5]), and
+// each lane writes its one sum, so nothing is optimised away.
+template <int KIND>
+__global__ __launch_bounds__(256) void probe_issue_k(float *out, int iters) {
+    float x[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) x[j] = 0.0625f * (float)((threadIdx.x + j) & 7);
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            if (KIND == 0) x[j] = fmaf(x[j], 0.5f, 0.25f);
+            if (KIND == 1) x[j] = __builtin_amdgcn_exp2f(x[j]) * 0.25f;
+            if (KIND == 2) x[j] = __builtin_amdgcn_logf(x[j] + 1.5f) * 0.5f;
+            if (KIND == 3) x[j] = __builtin_amdgcn_rcpf(x[j] + 1.5f) * 0.5f;
+            if (KIND == 4) x[j] = __builtin_amdgcn_sqrtf(x[j] + 1.5f) * 0.5f;
+        }
+    }
+    float acc = 0.f;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc += x[j];
+    out[(size_t)blockIdx.x * 256 + threadIdx.x] = acc;
 }
 
 }  // namespace sv
@@ -51,6 +79,22 @@ int sv_probe_copy(void *dst, const void *src, size_t bytes, sv_stream stream) {
     if (blocks > 256 * 64) blocks = 256 * 64;  // 64 workgroups per CU, grid-stride beyond
     hipLaunchKernelGGL(sv::probe_copy_k, dim3((unsigned)blocks), dim3(256), 0,
                        sv::as_stream(stream), (uint4 *)dst, (const uint4 *)src, n);
+    return sv::hip_status(hipGetLastError());
+}
+
+int sv_probe_issue(int32_t kind, int32_t iters, float *out, int32_t blocks, sv_stream stream) {
+    if (!out || kind < 0 || kind > 4 || iters < 1 || iters > (1 << 20) || blocks < 1 ||
+        blocks > 65536)
+        return SV_EINVAL;
+    hipStream_t s = sv::as_stream(stream);
+    const dim3 g((unsigned)blocks), b(256);
+    switch (kind) {
+    case 0: hipLaunchKernelGGL(sv::probe_issue_k<0>, g, b, 0, s, out, (int)iters); break;
+    case 1: hipLaunchKernelGGL(sv::probe_issue_k<1>, g, b, 0, s, out, (int)iters); break;
+    case 2: hipLaunchKernelGGL(sv::probe_issue_k<2>, g, b, 0, s, out, (int)iters); break;
+    case 3: hipLaunchKernelGGL(sv::probe_issue_k<3>, g, b, 0, s, out, (int)iters); break;
+    default: hipLaunchKernelGGL(sv::probe_issue_k<4>, g, b, 0, s, out, (int)iters); break;
+    }
     return sv::hip_status(hipGetLastError());
 }
 

@@ -180,6 +180,7 @@ EXPORTS = {
     "sv_version": ([], ctypes.c_int),
     "sv_last_hip_error": ([], ctypes.c_int),
     "sv_probe_copy": ([_vp, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
+    "sv_probe_issue": ([ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_int32, _vp], ctypes.c_int),
 }
 
 _lib = None
@@ -634,6 +635,14 @@ def sv_probe_copy(dst: torch.Tensor, src: torch.Tensor, stream=None):
         raise ValueError("dst is smaller than src")
     _check("sv_probe_copy", load().sv_probe_copy(dst.data_ptr(), src.data_ptr(), nbytes,
                                                  _stream(stream)))
+
+
+def sv_probe_issue(out: torch.Tensor, kind: int, iters: int, stream=None):
+    """`out`: float32 device tensor of blocks * 256 elements."""
+    if out.dtype != torch.float32 or out.numel() % 256 or not out.is_cuda:
+        raise ValueError("out must be a float32 device tensor of blocks * 256 elements")
+    _check("sv_probe_issue", load().sv_probe_issue(int(kind), int(iters), out.data_ptr(),
+                                                   out.numel() // 256, _stream(stream)))
 
 
 def sv_denoise_frame(fin: sv_frame_in, st: sv_denoiser, dims: sv_dims, dtype: int,

@@ -180,6 +180,14 @@ def test_probe_copy_validation(so):
     assert so.sv_probe_copy(A, A + 0x100000, 0, None) == L.SV_OK
 
 
+def test_issue_probe_validation(so):
+    out = A
+    assert so.sv_probe_issue(0, 16, None, 4, None) == L.SV_EINVAL
+    for kind, iters, blocks in ((-1, 16, 4), (5, 16, 4), (0, 0, 4), (0, 1 << 21, 4), (0, 16, 0),
+                                (0, 16, 65537)):
+        assert so.sv_probe_issue(kind, iters, out, blocks, None) == L.SV_EINVAL
+
+
 def test_binding_rejects_host_tensors():
     import torch
     t = torch.zeros((3, 4, 4))
