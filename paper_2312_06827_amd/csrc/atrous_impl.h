@@ -219,6 +219,16 @@ enum { kDir2D = 0, kDirH = 1, kDirV = 2 };
 // Staged prefilter entry of a pixel outside the image or without a surface.
 constexpr float kNoVar = __builtin_nanf("");
 
+// The tile's variance entry of a pixel outside the image or without a
+// surface is -0, which no other entry is: a pixel's own variance is staged
+// plus +0, turning -0 into +0 and leaving every other value as it is.  The
+// prefilter tells the two kinds apart from this 4-byte entry alone; reading
+// the depth out of the 16-byte G-buffer entries instead strides the LDS
+// banks four entries at a time and conflicts.  The taps need no test: an
+// empty pixel's weight is exactly 0, and 0 * -0 adds nothing.
+constexpr uint32_t kNoVarBits = 0x80000000u;
+__device__ __forceinline__ bool tile_no_var(float e) { return __float_as_uint(e) == kNoVarBits; }
+
 // Lattice rows per thread of a tile: two, except at the largest steps,
 // where the 2 x step-column halo on each side would otherwise hold the
 // tile's LDS footprint to two resident workgroups per CU (measured at step
@@ -321,7 +331,7 @@ __device__ __forceinline__ void tile_store(const R &g, float4 *s_cl, float4 *s_g
                          : make_float4(0.f, 0.f, 0.f, INFINITY);
             s_gn[i] = ok ? make_float4(g.z[it], g.nx[it], g.ny[it], g.nz[it])
                          : make_float4(0.f, 0.f, 0.f, 0.f);
-            if (S::NEED_V) s_v[i] = ok ? g.v[it] : 0.f;
+            if (S::NEED_V) s_v[i] = ok ? g.v[it] + 0.0f : __uint_as_float(kNoVarBits);
         }
     }
 #pragma unroll
@@ -375,9 +385,9 @@ __device__ __forceinline__ void tile_compute(const AtrousArgs &a, TileOrigin t,
                 for (int dy = -1; dy <= 1; ++dy)
 #pragma unroll
                     for (int dx = -1; dx <= 1; ++dx) {
-                        const int qi = ci + dy * COLS + dx;
-                        const float kk = s_gn[qi].x > 0.f ? kG3[dx + 1] * kG3[dy + 1] : 0.f;
-                        s = fmaf(kk, s_v[qi], s);
+                        const float e = s_v[ci + dy * COLS + dx];
+                        const float kk = tile_no_var(e) ? 0.f : kG3[dx + 1] * kG3[dy + 1];
+                        s = fmaf(kk, e, s);  // 0 * -0 adds nothing
                         sw += kk;
                     }
             } else {
@@ -386,11 +396,11 @@ __device__ __forceinline__ void tile_compute(const AtrousArgs &a, TileOrigin t,
 #pragma unroll
                     for (int dx = 0; dx < 3; ++dx) {
                         // the lattice row's own entries come from the tile
-                        // (z = 0 there: outside or empty)
+                        // (-0 there: outside or empty)
                         const int qi = ci + dx - 1;
                         const int pr = S::MID_TILE ? (dy == 0 ? 0 : 1) : dy;
                         const float e = S::MID_TILE && dy == 1
-                                            ? (s_gn[qi].x > 0.f ? s_v[qi] : kNoVar)
+                                            ? (tile_no_var(s_v[qi]) ? kNoVar : s_v[qi])
                                             : s_pf[(j * S::PFR + pr) * PFC + lx + dx];
                         const bool ok = e == e;  // kNoVar: outside or empty
                         const float kk = ok ? kG3[dx] * kG3[dy] : 0.f;
