@@ -329,6 +329,28 @@ def test_atrous(H, W, step):
             assert rel_err(host(vo), rv) <= TOL32
 
 
+@pytest.mark.parametrize("step", [1, 2])
+def test_atrous_signed_zero_variance(step):
+    """Live pixels of variance -0 and +0 beside empty ones.  The tile marks
+    an empty neighbour's variance entry as -0 and stages a live pixel's
+    plus +0, so a live pixel of variance -0 still counts in the 3x3
+    prefilter (at steps 1 and 2 the prefilter's middle row comes from the
+    tile) and the output matches the oracle's, which takes -0 as 0."""
+    H, W = 70, 130
+    c, var, z, dzdx, dzdy, n = _atrous_inputs(H, W, 470 + step, holes=True)
+    u = np.random.default_rng(471 + step).random((H, W))
+    var[u < 0.2] = -0.0
+    var[(u >= 0.2) & (u < 0.3)] = 0.0
+    assert np.signbit(var).sum() > 0.1 * H * W and np.sum(z == 0) > 0
+    g = gbuf_dev(z, dzdx, dzdy, n)
+    out, vo = empty_like_dev((3, H, W)), empty_like_dev((H, W))
+    say(f"atrous signed-zero variance {H}x{W} step={step}")
+    L.sv_atrous(dev(c), dev(var), g, out, vo, step, L.AtrousParams())
+    rc, rv = O.atrous(c, var, z, dzdx, dzdy, n, step)
+    assert rel_err(host(out), rc) <= TOL32
+    assert rel_err(host(vo), rv) <= TOL32
+
+
 @pytest.mark.parametrize("step", [1, 4, 16])
 def test_atrous_kappa_and_params(step):
     H, W = 90, 150
