@@ -231,10 +231,11 @@ __device__ __forceinline__ bool tile_no_var(float e) { return __float_as_uint(e)
 
 // Lattice rows per thread of a tile: two, except at the largest steps,
 // where the 2 x step-column halo on each side would otherwise hold the
-// tile's LDS footprint to two resident workgroups per CU (measured at step
-// 16: 53 instead of 74 us per 1080p level; one row per thread at step 8
-// gained nothing).  Step 32 is the coarser start of the fifth level.
-constexpr int tile_py(int step) { return step >= 16 ? 1 : 2; }
+// tile's LDS footprint to two or three resident workgroups per CU (per
+// 1080p level, step 16: 53 instead of 74 us; step 8: five workgroups
+// instead of three, 53 instead of 55 us).  Step 32 is the coarser start of
+// the fifth level.
+constexpr int tile_py(int step) { return step >= 8 ? 1 : 2; }
 
 template <int STEP, int PY, int DIR, bool WANT_VAR>
 struct TileShape {
