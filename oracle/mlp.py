@@ -297,14 +297,17 @@ def atrous_kappa_derivative(c, var, z, dzdx, dzdy, n, kappa, step, sigma_z=1.0,
     h1 = np.array([1, 4, 6, 4, 1]) / 16.0
     k3 = np.array([0.25, 0.5, 0.25])
     ok = ~_empty(z)
-    # 3x3 Gaussian of var over in-image taps, renormalised
+    # 3x3 Gaussian of var over the in-image, non-empty taps, renormalised
+    # (the level's own prefilter: an empty pixel is no neighbour)
+    okf = ok.astype(np.float64)
     num, den = np.zeros((H, W)), np.zeros((H, W))
     for dy in (-1, 0, 1):
         for dx in (-1, 0, 1):
-            vv, mm = _shift(var, dx, dy), _shift(np.ones((H, W)), dx, dy)
+            vv, mm = _shift(np.where(ok, var, 0.0), dx, dy), _shift(okf, dx, dy)
             num += k3[dy + 1] * k3[dx + 1] * vv
             den += k3[dy + 1] * k3[dx + 1] * mm
-    g = num / den
+    with np.errstate(invalid="ignore", divide="ignore"):
+        g = np.where(ok, num / den, 0.0)
     L = luma(c)
     dl = sigma_l * kappa * np.sqrt(g) + eps_l
     sw, sc = np.zeros((H, W)), np.zeros((3, H, W))

@@ -118,6 +118,55 @@ def test_reconstruction_on_flat_depth_is_the_normalized_b3_cascade():
     np.testing.assert_allclose(lam, ref, rtol=1e-12, atol=1e-15)
 
 
+@pytest.mark.parametrize("seed,H,W", [(11, 31, 40), (12, 27, 35)])
+def test_reconstruction_equals_plain_sums_at_ordinary_weights(seed, H, W):
+    """Random depth with a non-trivial gradient field and ragged cells: the
+    log-domain form of the oracle gives the quotients of the plain binary64
+    normalized convolution, sum_j w_j x_j / sum_j w_j p_j cascaded over the
+    levels, with the depth weight of each cell's centre pixel and its own
+    gradient.  Written out here tap by tap."""
+    r = np.random.default_rng(seed)
+    ys, xs = np.mgrid[0:H, 0:W].astype(np.float64)
+    z = 5.0 + 0.04 * xs - 0.03 * ys + 0.3 * np.sin(0.2 * xs) * np.cos(0.15 * ys) \
+        + r.normal(0, 0.02, (H, W))
+    dzdx = 0.04 + 0.06 * np.cos(0.2 * xs) * np.cos(0.15 * ys)
+    dzdy = -0.03 - 0.045 * np.sin(0.2 * xs) * np.sin(0.15 * ys)
+    CH, CW = G.cells_of(H, W)
+    present = (r.random((CH, CW)) < 0.5).astype(np.float64)
+    delta = r.uniform(-1, 1, (CH, CW)) * present
+    norm = r.uniform(0.5, 2, (CH, CW)) * present
+    levels = 3
+    lam = G.reconstruct(delta, norm, present, z, dzdx, dzdy, levels=levels)
+    h = np.array([1, 4, 6, 4, 1]) / 16.0
+    cy = np.minimum(3 * np.arange(CH) + 1, H - 1)
+    cx = np.minimum(3 * np.arange(CW) + 1, W - 1)
+    X = [delta * present, norm * present, present.copy()]
+    for lvl in range(levels):
+        s = 1 << lvl
+        Y = [np.zeros((CH, CW)) for _ in X]
+        for i in range(CH):
+            for j in range(CW):
+                zc, gx, gy = z[cy[i], cx[j]], dzdx[cy[i], cx[j]], dzdy[cy[i], cx[j]]
+                for b in range(-2, 3):
+                    for a in range(-2, 3):
+                        ii, jj = i + b * s, j + a * s
+                        if not (0 <= ii < CH and 0 <= jj < CW):
+                            continue
+                        den = abs(gx * 3.0 * a * s + gy * 3.0 * b * s) + 1e-10
+                        w = h[a + 2] * h[b + 2] * np.exp(-abs(zc - z[cy[ii], cx[jj]]) / den)
+                        for k in range(3):
+                            Y[k][i, j] += w * X[k][ii, jj]
+        X = Y
+    ok = (X[2] > 0) & (X[1] > 0)
+    ref = np.where(ok, np.minimum(1.0, np.abs(X[0] / np.where(ok, X[2], 1))
+                                  / np.where(ok, X[1] / np.where(ok, X[2], 1), 1)), 0.0)
+    np.testing.assert_allclose(lam, ref, rtol=1e-12, atol=1e-15)
+    # every reached cell's filtered indicator is an ordinary number (not the
+    # underflow case of the test below), and most lambdas are fractions
+    assert X[2][X[2] > 0].min() > 1e-100
+    assert np.count_nonzero((ref > 0) & (ref < 1)) > CH * CW // 2
+
+
 def test_depth_edges_keep_gradients_apart():
     # two depth planes far apart: a gradient on one side does not leak
     CH, CW = 6, 10

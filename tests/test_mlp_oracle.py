@@ -181,3 +181,145 @@ def test_features_of_a_static_sequence():
             assert ft["valid"].all()
             np.testing.assert_allclose(x[1], O.luma(ft["hist"]), rtol=1e-15)
         _, st, _ = O.run_frame(fr, st, p)
+
+
+def _gbuf_with_holes(r, H, W, holes):
+    """random_gbuf with some pixels without a surface (sky: z = inf, and
+    z = 0), as the level treats them (R15)."""
+    z, dzdx, dzdy, n = random_gbuf(r, H, W)
+    z = z.astype(np.float64)
+    for k, (y, x) in enumerate(holes):
+        z[y, x] = np.inf if k % 2 == 0 else 0.0
+    return z, dzdx, dzdy, n
+
+
+@pytest.mark.parametrize("step", [1, 2])
+def test_kappa_derivative_next_to_empty_pixels(step):
+    """The level's variance prefilter skips empty neighbours (their
+    variance is no sample of p's surface); the derivative must be that of
+    the level as the C oracle runs it, so finite differences through it
+    pin the prefilter beside sky pixels too."""
+    r = np.random.default_rng(40 + step)
+    H, W = 11, 13
+    holes = [(4, 5), (4, 6), (0, 12), (9, 2)]
+    z, dzdx, dzdy, n = _gbuf_with_holes(r, H, W, holes)
+    c = r.uniform(0.05, 1.0, (3, H, W))
+    # the empty pixels' variance is large, so a prefilter that averaged it
+    # in would move the derivative well past the tolerance
+    var = np.where(np.isfinite(z) & (z > 0), r.uniform(0.001, 0.05, (H, W)), 3.0)
+    kappa = r.uniform(0.5, 2.0, (H, W))
+    d = M.atrous_kappa_derivative(c, var, z, dzdx, dzdy, n, kappa, step)
+    h = 1e-6
+    for (y, x) in [(3, 5), (5, 6), (4, 7), (1, 11), (8, 2), (4, 5), (0, 12)]:
+        kp, km = kappa.copy(), kappa.copy()
+        kp[y, x] += h
+        km[y, x] -= h
+        op = O.atrous(c, var, z, dzdx, dzdy, n, step, kappa=kp)[0]
+        om = O.atrous(c, var, z, dzdx, dzdy, n, step, kappa=km)[0]
+        fd = (op[:, y, x] - om[:, y, x]) / (2 * h)
+        np.testing.assert_allclose(d[:, y, x], fd, rtol=1e-5, atol=1e-10)
+    # an empty pixel passes its input through: no dependence on kappa
+    for (y, x) in holes:
+        assert np.all(d[:, y, x] == 0.0)
+
+
+@pytest.mark.parametrize("step", [1, 4])
+def test_kappa_grad_level_matches_finite_differences_of_level_relmse(step):
+    """dL/dkappa(p) of one level, L the level output's RelMSE summed over
+    pixels (mean over channels), against central differences of L through
+    the C oracle's level with kappa moved at p alone.  kappa(p) scales p's
+    own luminance width only, so the other pixels must not move at all."""
+    r = np.random.default_rng(60 + step)
+    H, W = 12, 15
+    z, dzdx, dzdy, n = _gbuf_with_holes(r, H, W, [(6, 7), (2, 2)])
+    c = r.uniform(0.05, 1.0, (3, H, W))
+    var = r.uniform(0.001, 0.05, (H, W))
+    kappa = r.uniform(0.5, 2.0, (H, W))
+    y_ref = r.uniform(0.05, 1.0, (3, H, W))
+    out = O.atrous(c, var, z, dzdx, dzdy, n, step, kappa=kappa)[0]
+    d = M.atrous_kappa_derivative(c, var, z, dzdx, dzdy, n, kappa, step)
+    g = M.kappa_grad_level(out, y_ref, d)
+
+    def loss(o):
+        return float((((o - y_ref) ** 2) * M.relmse_weight(y_ref)).mean(0).sum())
+
+    h = 1e-6
+    for (py, px) in [(0, 0), (5, 7), (6, 8), (11, 14), (3, 10), (6, 7)]:
+        kp, km = kappa.copy(), kappa.copy()
+        kp[py, px] += h
+        km[py, px] -= h
+        op = O.atrous(c, var, z, dzdx, dzdy, n, step, kappa=kp)[0]
+        om = O.atrous(c, var, z, dzdx, dzdy, n, step, kappa=km)[0]
+        mask = np.ones((H, W), bool)
+        mask[py, px] = False
+        np.testing.assert_array_equal(op[:, mask], out[:, mask])
+        np.testing.assert_array_equal(om[:, mask], out[:, mask])
+        fd = (loss(op) - loss(om)) / (2 * h)
+        assert abs(g[py, px] - fd) <= 1e-5 * max(abs(fd), 1e-6), (py, px, g[py, px], fd)
+
+
+def test_features_of_a_moving_sequence():
+    """Rows 2 (reprojected central moment) and 10 (motion length) where the
+    camera and three spheres move, with motion planted that the temporal
+    step discards (not finite, or 2^20 pixels and more): row 2 equals
+    m2 - m1^2 of the bilinear mixture worked out here pixel by pixel from
+    the history, row 10 the length of the kept motion and 0 elsewhere."""
+    import math
+    from paper_2312_06827_amd.scene import CONFIGS, sequence, with_size
+    cfg = with_size(CONFIGS["hd_motion"], 48, 30, 4)
+    p = O.OracleParams(clamp=True, tonemap=True, use_id=True)
+    H, W = 30, 48
+    st = O.new_state(H, W)
+    planted = {(3, 4): (np.nan, 0.5), (5, 6): (0.25, 2.0 ** 20), (7, 8): (-2.0 ** 21, 0.0),
+               (9, 10): (0.0, np.inf), (11, 12): (2.0 ** 20 - 1, -3.0)}
+    f32 = np.float32
+    nonzero_moment = moving = 0
+    for f, fr in enumerate(sequence(cfg)):
+        fr = dict(fr)
+        mv = fr["mv"].astype(np.float64)
+        for (y, x), v in planted.items():
+            mv[:, y, x] = v
+        fr["mv"] = mv
+        x_ft = M.features(fr, st, p)["x"]
+        for yy in range(H):
+            for xx in range(W):
+                mx, my = mv[0, yy, xx], mv[1, yy, xx]
+                kept = math.isfinite(mx) and math.isfinite(my) and abs(mx) < 2 ** 20 and abs(my) < 2 ** 20
+                want = math.hypot(mx, my) if kept else 0.0
+                assert abs(x_ft[10, yy, xx] - want) <= 1e-15 * max(1.0, want), (f, yy, xx)
+                if want > 0.5:
+                    moving += 1
+                # bilinear mixture of the history's raw moments over the usable taps
+                if not kept:
+                    assert x_ft[2, yy, xx] == 0.0
+                    continue
+                x0, y0 = xx + math.floor(mx), yy + math.floor(my)
+                fx, fy = mx - math.floor(mx), my - math.floor(my)
+                sw = s1 = s2 = 0.0
+                for t in range(4):
+                    tx, ty = x0 + (t & 1), y0 + (t >> 1)
+                    bw = (fx if t & 1 else 1 - fx) * (fy if t >> 1 else 1 - fy)
+                    if bw <= 0 or not (0 <= tx < W and 0 <= ty < H) or st["n"][ty, tx] < 1:
+                        continue
+                    zc = f32(fr["z"][yy, xx])
+                    if not abs(f32(f32(fr["prev_z"][ty, tx]) - zc)) <= f32(f32(p.tau_z) * zc):
+                        continue
+                    a, b = fr["prev_n"][:, ty, tx].astype(f32), fr["n"][:, yy, xx].astype(f32)
+                    # binary32 dot in the decision's order, each fma as an
+                    # exact binary64 product and sum rounded to binary32
+                    dn = f32(a[0] * b[0])
+                    dn = f32(float(a[1]) * float(b[1]) + float(dn))
+                    dn = f32(float(a[2]) * float(b[2]) + float(dn))
+                    if not dn >= f32(p.tau_n):
+                        continue
+                    if fr["id"][yy, xx] != fr["prev_id"][ty, tx]:
+                        continue
+                    sw += bw
+                    s1 += bw * st["m1"][ty, tx]
+                    s2 += bw * st["m2"][ty, tx]
+                want2 = max(s2 / sw - (s1 / sw) ** 2, 0.0) if sw > 0 else 0.0
+                assert abs(x_ft[2, yy, xx] - want2) <= 1e-12 * max(1e-3, want2), (f, yy, xx)
+                if want2 > 1e-4:
+                    nonzero_moment += 1
+        _, st, _ = O.run_frame(fr, st, p)
+    assert moving > 1000 and nonzero_moment > 1000, (moving, nonzero_moment)

@@ -658,6 +658,52 @@ def test_atrous_normal_weight_power_and_clamp():
             np.testing.assert_allclose(out[ch][~odd], (num / den)[~odd], rtol=1e-12)
 
 
+@pytest.mark.parametrize("theta,eps_a,eps_b", [(0.05, 1e-3, -2e-3), (0.12, -1e-3, -1e-3),
+                                             (0.02, 3e-3, 1e-3)])
+def test_atrous_normal_weight_of_non_unit_normals_follows_the_angle(theta, eps_a, eps_b):
+    """Reading R13: the cosine in (n_p . n_q)^sigma_n is taken as
+    1 - |n_p - n_q|^2 / 2.  For normals of lengths 1 + ea, 1 + eb at angle
+    theta that is, exactly,
+        cos t + (ea + eb)(cos t - 1) + ea eb cos t - (ea^2 + eb^2) / 2,
+    so the weight is cos(theta)^sigma_n up to a relative
+    sigma_n (|ea| + |eb|)(1 - cos t) / cos t plus second order: a function
+    of the angle alone where the weights matter, while the plain dot
+    product (|n_p||n_q| cos t) is off by sigma_n (ea + eb) at every angle.
+    Lengths off by 1e-3 make the two readings far apart in FP64."""
+    H, W = 9, 10
+    sigma_n = 128.0
+    r = rng(23)
+    c = equal_luma_rgb(r, H, W)
+    z, dzdx, dzdy, n = flat_gbuf(H, W)
+    odd = (np.arange(W) % 2 == 1)[None, :] * np.ones((H, 1), bool)
+    ua = np.array([0.3, 0.9, 0.1])
+    ua /= np.linalg.norm(ua)
+    perp = np.cross(ua, [0.0, 0.0, 1.0])
+    perp /= np.linalg.norm(perp)
+    ub = math.cos(theta) * ua + math.sin(theta) * perp
+    a, b = (1 + eps_a) * ua, (1 + eps_b) * ub
+    nn = n.copy()
+    nn[:, ~odd] = a[:, None]
+    nn[:, odd] = b[:, None]
+    ct = math.cos(theta)
+    chord = ct + (eps_a + eps_b) * (ct - 1) + eps_a * eps_b * ct - (eps_a ** 2 + eps_b ** 2) / 2
+    w_other = chord ** sigma_n
+    out, _ = O.atrous(c, np.ones((H, W)), z, dzdx, dzdy, nn, 1, sigma_n=sigma_n)
+    K = kernel2d(1)
+    same, other = (~odd).astype(float), odd.astype(float)
+    for ch in range(3):
+        num = corr(c[ch] * same, K) + w_other * corr(c[ch] * other, K)
+        den = corr(same, K) + w_other * corr(other, K)
+        np.testing.assert_allclose(out[ch][~odd], (num / den)[~odd], rtol=1e-11)
+    # the weight follows the angle to first order in the length error ...
+    first = sigma_n * (abs(eps_a) + abs(eps_b)) * (1 - ct) / ct
+    second = sigma_n * 2 * max(abs(eps_a), abs(eps_b)) ** 2
+    assert abs(w_other / ct ** sigma_n - 1) <= 1.05 * first + second
+    # ... where the plain dot product does not
+    dot = float(a @ b) ** sigma_n
+    assert abs(dot / ct ** sigma_n - 1) > 10 * (first + second)
+
+
 def test_atrous_luminance_weight_worked_example():
     with open(os.path.join(GOLDEN, "atrous_luma_example.json")) as f:
         gold = json.load(f)
