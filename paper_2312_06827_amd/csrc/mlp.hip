@@ -248,30 +248,38 @@ struct AlphaGradArgs {
     float tm_k;
 };
 
+// The two loss gradients are training-only passes, off the measured path.
+// Their results are sums over channels (and, for kappa, over taps) of terms
+// of either sign, so binary32 would lose digits to cancellation wherever the
+// terms nearly balance; they are evaluated in binary64 from the stored
+// (binary32 or binary16) inputs, like the definition they implement.
+__device__ __forceinline__ double luma_d(double r, double g, double b) {
+    return 0.2126 * r + 0.7152 * g + 0.0722 * b;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void alpha_grad_k(AlphaGradArgs a) {
     const int x = blockIdx.x * 64 + (threadIdx.x & 63), y = blockIdx.y * 4 + (threadIdx.x >> 6);
     if (x >= a.w || y >= a.h) return;
     const uint32_t o = (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x;
     const int n = a.n[o];
-    float g = 0.f;
+    double g = 0.0;
     if (!empty_px(ldo<T>(a.z, o)) && n >= 1 && a.alpha[o] >= 1.0f / (float)n) {
-        float c[3] = {ldo<T>(a.cr, o), ldo<T>(a.cg, o), ldo<T>(a.cb, o)};
+        double c[3] = {ldo<T>(a.cr, o), ldo<T>(a.cg, o), ldo<T>(a.cb, o)};
         if (a.tm_k > 0.f) {
-            const float sc = 1.0f / (1.0f + a.tm_k * luma(c[0], c[1], c[2]));
+            const double sc = 1.0 / (1.0 + (double)a.tm_k * luma_d(c[0], c[1], c[2]));
             c[0] *= sc;
             c[1] *= sc;
             c[2] *= sc;
         }
-        const float ct[3] = {ldo<T>(a.ctr, o), ldo<T>(a.ctg, o), ldo<T>(a.ctb, o)};
-        const float hh[3] = {ldf(a.hr, o), ldf(a.hg, o), ldf(a.hb, o)};
-        const float yy[3] = {ldf(a.yr, o), ldf(a.yg, o), ldf(a.yb, o)};
+        const double ct[3] = {ldo<T>(a.ctr, o), ldo<T>(a.ctg, o), ldo<T>(a.ctb, o)};
+        const double hh[3] = {ldf(a.hr, o), ldf(a.hg, o), ldf(a.hb, o)};
+        const double yy[3] = {ldf(a.yr, o), ldf(a.yg, o), ldf(a.yb, o)};
 #pragma unroll
-        for (int k = 0; k < 3; ++k)
-            g = fmaf((ct[k] - yy[k]) / fmaf(yy[k], yy[k], 0.01f), c[k] - hh[k], g);
-        g *= 2.0f / 3.0f;
+        for (int k = 0; k < 3; ++k) g += (ct[k] - yy[k]) / (yy[k] * yy[k] + 0.01) * (c[k] - hh[k]);
+        g *= 2.0 / 3.0;
     }
-    a.d_alpha[o] = g;
+    a.d_alpha[o] = (float)g;
 }
 
 struct KappaGradArgs {
@@ -286,76 +294,80 @@ struct KappaGradArgs {
     float sigma_z, sigma_n, sigma_l, eps_z, eps_l;
 };
 
-// One pixel per thread, taps read directly (the training pass, not the
-// measured path).
+// One pixel per thread, taps read directly, in binary64 (see alpha_grad_k).
+// The 3x3 variance prefilter runs over the in-image, non-empty taps, as in
+// the level itself.
 template <typename T>
 __global__ __launch_bounds__(256) void kappa_grad_k(KappaGradArgs a) {
     const int x = blockIdx.x * 64 + (threadIdx.x & 63), y = blockIdx.y * 4 + (threadIdx.x >> 6);
     if (x >= a.w || y >= a.h) return;
     const uint32_t o = (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x;
-    const float zp = ldo<T>(a.z, o);
-    if (empty_px(zp)) return;
-    // 3x3 Gaussian of the variance, in-image taps renormalised
-    float gs = 0.f, gw = 0.f;
-#pragma unroll
+    const double zp = ldo<T>(a.z, o);
+    if (empty_px((float)zp)) return;
+    double gs = 0.0, gw = 0.0;
     for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
         for (int dx = -1; dx <= 1; ++dx) {
             const int qx = x + dx, qy = y + dy;
             if (qx < 0 || qx >= a.w || qy < 0 || qy >= a.h) continue;
-            const float k = (dx == 0 ? 0.5f : 0.25f) * (dy == 0 ? 0.5f : 0.25f);
-            gs = fmaf(k, ldf(a.var, (uint32_t)qy * (uint32_t)a.pitch + (uint32_t)qx), gs);
+            const uint32_t q = (uint32_t)qy * (uint32_t)a.pitch + (uint32_t)qx;
+            if (empty_px(ldo<T>(a.z, q))) continue;
+            const double k = (dx == 0 ? 0.5 : 0.25) * (dy == 0 ? 0.5 : 0.25);
+            gs += k * (double)ldf(a.var, q);
             gw += k;
         }
-    const float sg = sqrtf(gs / gw);
-    const float dl = fmaf(a.sigma_l * ldf(a.kappa, o), sg, a.eps_l);
-    const float cp[3] = {ldo<T>(a.cr, o), ldo<T>(a.cg, o), ldo<T>(a.cb, o)};
-    const float lp = luma(cp[0], cp[1], cp[2]);
-    const float gx = ldo<T>(a.dzdx, o), gy = ldo<T>(a.dzdy, o);
-    const float nxp = ldo<T>(a.nx, o), nyp = ldo<T>(a.ny, o), nzp = ldo<T>(a.nz, o);
-    const float h1[5] = {1.f / 16, 4.f / 16, 6.f / 16, 4.f / 16, 1.f / 16};
-    float sw = 0.f, sd = 0.f, sc[3] = {0.f, 0.f, 0.f}, sdc[3] = {0.f, 0.f, 0.f};
+    const double sg = sqrt(gs / gw);
+    const double sl = a.sigma_l;
+    const double dl = sl * (double)ldf(a.kappa, o) * sg + (double)a.eps_l;
+    const double cp[3] = {ldo<T>(a.cr, o), ldo<T>(a.cg, o), ldo<T>(a.cb, o)};
+    const double lp = luma_d(cp[0], cp[1], cp[2]);
+    const double gx = ldo<T>(a.dzdx, o), gy = ldo<T>(a.dzdy, o);
+    const double np_[3] = {ldo<T>(a.nx, o), ldo<T>(a.ny, o), ldo<T>(a.nz, o)};
+    const double h1[5] = {1.0 / 16, 4.0 / 16, 6.0 / 16, 4.0 / 16, 1.0 / 16};
+    double sw = 0.0, sd = 0.0, sc[3] = {0.0, 0.0, 0.0}, sdc[3] = {0.0, 0.0, 0.0};
     for (int b = -2; b <= 2; ++b)
         for (int aa = -2; aa <= 2; ++aa) {
             const int qx = x + aa * a.step, qy = y + b * a.step;
             if (qx < 0 || qx >= a.w || qy < 0 || qy >= a.h) continue;
             const uint32_t q = (uint32_t)qy * (uint32_t)a.pitch + (uint32_t)qx;
-            const float hh = h1[aa + 2] * h1[b + 2];
-            const float cq[3] = {ldo<T>(a.cr, q), ldo<T>(a.cg, q), ldo<T>(a.cb, q)};
-            float w = 1.f, d = 0.f;
+            const double hh = h1[aa + 2] * h1[b + 2];
+            const double cq[3] = {ldo<T>(a.cr, q), ldo<T>(a.cg, q), ldo<T>(a.cb, q)};
+            double w = 1.0, d = 0.0;
             if (aa != 0 || b != 0) {
-                const float zq = ldo<T>(a.z, q);
-                if (empty_px(zq)) continue;
-                const float den = fmaf(a.sigma_z,
-                                       fabsf(fmaf(gx, (float)(a.step * aa), gy * (float)(a.step * b))),
-                                       a.eps_z);
-                const float wz = expf(-fabsf(zp - zq) / den);
-                const float ch = chord2(nxp, nyp, nzp, ldo<T>(a.nx, q), ldo<T>(a.ny, q),
-                                        ldo<T>(a.nz, q));
-                const float wn = a.sigma_n == 0.f ? 1.f : powf(fmaxf(0.f, fmaf(-0.5f, ch, 1.f)), a.sigma_n);
-                const float adl = fabsf(lp - luma(cq[0], cq[1], cq[2]));
-                w = wz * wn * expf(-adl / dl);
-                d = w * adl * a.sigma_l * sg / (dl * dl);
+                const float zq32 = ldo<T>(a.z, q);
+                if (empty_px(zq32)) continue;
+                const double zq = zq32;
+                const double den = (double)a.sigma_z *
+                                       fabs(gx * (double)(a.step * aa) + gy * (double)(a.step * b)) +
+                                   (double)a.eps_z;
+                const double wz = exp(-fabs(zp - zq) / den);
+                const double ex = np_[0] - (double)ldo<T>(a.nx, q);
+                const double ey = np_[1] - (double)ldo<T>(a.ny, q);
+                const double ez = np_[2] - (double)ldo<T>(a.nz, q);
+                const double cs = 1.0 - 0.5 * (ex * ex + ey * ey + ez * ez);
+                const double wn = pow(cs > 0.0 ? cs : 0.0, (double)a.sigma_n);
+                const double adl = fabs(lp - luma_d(cq[0], cq[1], cq[2]));
+                w = wz * wn * exp(-adl / dl);
+                d = w * adl * sl * sg / (dl * dl);
             }
-            sw = fmaf(hh, w, sw);
-            sd = fmaf(hh, d, sd);
+            sw += hh * w;
+            sd += hh * d;
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                sc[k] = fmaf(hh * w, cq[k], sc[k]);
-                sdc[k] = fmaf(hh * d, cq[k], sdc[k]);
+                sc[k] += hh * w * cq[k];
+                sdc[k] += hh * d * cq[k];
             }
         }
-    const float yy[3] = {ldf(a.yr, o), ldf(a.yg, o), ldf(a.yb, o)};
+    const double yy[3] = {ldf(a.yr, o), ldf(a.yg, o), ldf(a.yb, o)};
     const float *rp[3] = {a.rr, a.rg, a.rb};
-    float g = 0.f;
+    double g = 0.0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const float out = sc[k] / sw;
-        const float der = (sdc[k] - out * sd) / sw;
-        const float res = (a.rr ? ldf(rp[k], o) : out) - yy[k];
-        g = fmaf(res / fmaf(yy[k], yy[k], 0.01f), der, g);
+        const double out = sc[k] / sw;
+        const double der = (sdc[k] - out * sd) / sw;
+        const double res = (a.rr ? (double)ldf(rp[k], o) : out) - yy[k];
+        g += res / (yy[k] * yy[k] + 0.01) * der;
     }
-    a.d_kappa[o] += g * (2.0f / 3.0f);
+    a.d_kappa[o] += (float)(g * (2.0 / 3.0));
 }
 
 inline unsigned mlp_grid(int nblk) {

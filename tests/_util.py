@@ -65,3 +65,38 @@ def worst(gpu, ora, floor=1e-3, abs_floor=0.0):
         if e[i] > best[0]:
             best = (float(e[i]), (k,) + tuple(int(v) for v in i) + (float(gp[i]), float(op[i])))
     return best[1]
+
+
+# ---- guard bands of pitched output planes --------------------------------------
+#
+# Output planes with a row pitch larger than the width are registered here
+# with their padding filled (NaN, or 0xA5 in byte planes); after every test
+# the padding must be unchanged: a kernel that writes past a row's end fails
+# the test that ran it.
+
+GUARDED = []
+
+
+def guard_value(dtype):
+    return float("nan") if dtype.is_floating_point else 0xA5
+
+
+def guard(full, width):
+    """Register the full pitched tensor whose columns >= width are padding."""
+    GUARDED.append((full, width))
+
+
+def check_guards():
+    if not GUARDED:
+        return
+    import torch
+    torch.cuda.synchronize()
+    bad = []
+    for full, width in GUARDED:
+        pad = full[..., width:]
+        ok = bool(torch.isnan(pad).all()) if pad.dtype.is_floating_point \
+            else bool((pad == 0xA5).all())
+        if not ok:
+            bad.append((tuple(full.shape), width, str(full.dtype)))
+    GUARDED.clear()
+    assert not bad, f"writes into the row padding of pitched outputs: {bad}"

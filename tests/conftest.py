@@ -11,3 +11,12 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) and the built HIP library")
     config.addinivalue_line("markers", "slow: long-running CPU test")
+
+
+@pytest.fixture(autouse=True)
+def _pitched_output_guards():
+    """Pitched output planes registered by a test keep their padding."""
+    from tests import _util
+    _util.GUARDED.clear()
+    yield
+    _util.check_guards()

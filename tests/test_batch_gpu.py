@@ -54,6 +54,40 @@ def test_batch_equals_single_streams(half, sep, levels, feedback):
         batch.close()
 
 
+@pytest.mark.parametrize("half,sep", [(False, False), (True, False), (False, True), (True, True)])
+def test_batch_streams_match_the_oracle(half, sep):
+    """Every stream of a batch plan against the FP64 oracle run on that
+    stream alone, frame after frame: 1e-5 with binary32 storage, 2e-3 with
+    binary16 storage (against the oracle that rounds to binary16 at the
+    same storage points); history lengths exactly."""
+    import oracle as O
+    from tests._util import rel_err
+    dt = torch.float16 if half else torch.float32
+    tol = 2e-3 if half else 1e-5
+    cfg = MOTION_SEP if sep else MOTION
+    ofilt = O.OracleParams(clamp=True, tonemap=True, use_id=True, separable=sep, half=half)
+    frames = 5
+    scfg = _streams(half, frames)
+    say(f"batch vs oracle: {len(SIZES)} streams half={half} sep={sep}")
+    batch = BatchDenoiser(SIZES, cfg, dt)
+    states = [O.new_state(h, w) for (h, w) in SIZES]
+    try:
+        for f in range(frames):
+            frs = [render_frame(c, f) for c in scfg]
+            outs = batch.frame([FrameInputs.from_numpy(fr) for fr in frs])
+            torch.cuda.synchronize()
+            errs = []
+            for i, (fr, b) in enumerate(zip(frs, batch.streams)):
+                ref, states[i], ex = O.run_frame(fr, states[i], ofilt)
+                np.testing.assert_array_equal(b.n[b.k].cpu().numpy(), ex["temporal"]["n"])
+                e = rel_err(outs[i].double().cpu().numpy(), ref)
+                errs.append(e)
+                assert e <= tol, (f, i, SIZES[i], e)
+            say(f"  frame {f}: max rel err per stream " + " ".join(f"{e:.1e}" for e in errs))
+    finally:
+        batch.close()
+
+
 def test_batch_sixteen_uneven_streams_first_frames():
     """The sixteen-stream workload (640x360 .. 2560x1440, binary16), two
     frames, against single-stream runs."""

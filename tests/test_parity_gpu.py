@@ -14,7 +14,7 @@ import torch
 import oracle as O
 from paper_2312_06827_amd import lib as L
 from paper_2312_06827_amd.scene import CONFIGS, render_frame, with_size
-from tests._util import rel_err, random_gbuf, say, worst
+from tests._util import guard, guard_value, rel_err, random_gbuf, say, worst
 
 pytestmark = pytest.mark.gpu
 
@@ -23,21 +23,27 @@ SIZES = [(1, 1), (3, 5), (37, 70), (67, 131)]  # (H, W)
 
 
 def dev(a, pitch=None, dtype=torch.float32):
-    """numpy (.., H, W) -> device tensor view with row pitch `pitch`."""
+    """numpy (.., H, W) -> device tensor view with row pitch `pitch`.  The
+    padding past the width holds NaN (0xA5 in byte planes): a read past a
+    row's end would carry it into the result."""
     a = np.ascontiguousarray(a)
     t = torch.from_numpy(a).to(dtype)
     if pitch is None or pitch == a.shape[-1]:
         return t.cuda()
-    full = torch.zeros(a.shape[:-1] + (pitch,), dtype=dtype)
+    full = torch.full(a.shape[:-1] + (pitch,), guard_value(dtype), dtype=dtype)
     full[..., : a.shape[-1]] = t
     return full.cuda()[..., : a.shape[-1]]
 
 
 def empty_like_dev(shape, pitch=None, dtype=torch.float32):
+    """Output planes, NaN-filled (0xA5 in byte planes).  With a pitch past
+    the width the padding is a guard band: the test's end checks that no
+    call wrote into it."""
     W = shape[-1]
     p = W if pitch is None else pitch
-    t = torch.full(shape[:-1] + (p,), float("nan") if dtype.is_floating_point else 0,
-                   dtype=dtype, device="cuda")
+    t = torch.full(shape[:-1] + (p,), guard_value(dtype), dtype=dtype, device="cuda")
+    if p > W:
+        guard(t, W)
     return t[..., :W]
 
 

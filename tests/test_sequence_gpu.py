@@ -69,12 +69,15 @@ def test_motion_reduced(sep):
     run_pair(cfg, MOTION_SEP if sep else MOTION, ORACLE_MOTION_SEP if sep else ORACLE_MOTION)
 
 
+@pytest.mark.timeout(600)
 @pytest.mark.parametrize("sep", [False, True])
-def test_motion_full_hd_first_frames(sep):
+def test_motion_full_hd_frames(sep):
+    """The 1920x1080 workload for 8 frames: history lengths reach 8, so the
+    temporal variance (n >= 4) and the fed-back history run at full size."""
     cfg = CONFIGS["hd_motion"]
-    say(f"sequence 1920x1080 motion, separable={sep}, 3 frames")
+    say(f"sequence 1920x1080 motion, separable={sep}, 8 frames")
     run_pair(cfg, MOTION_SEP if sep else MOTION, ORACLE_MOTION_SEP if sep else ORACLE_MOTION,
-             frames=3)
+             frames=8)
 
 
 def test_motion_clipping_reduced():
