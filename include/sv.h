@@ -61,7 +61,8 @@ enum {
     SV_EALIAS = 2,      /* an output overlaps an input of a stencil call */
     SV_EDTYPE = 3,      /* unknown storage type */
     SV_EHIP = 4,        /* the HIP runtime reported an error on launch */
-    SV_EUNSUPPORTED = 5 /* valid but not implemented combination */
+    SV_EUNSUPPORTED = 5, /* valid but not implemented combination */
+    SV_ETOOBIG = 6       /* larger than the fixed workspace of sv_variance_noalloc */
 };
 
 typedef void *sv_stream; /* a hipStream_t */
@@ -257,6 +258,24 @@ int sv_variance(const float *m1, const float *m2c, const uint8_t *n,
  * number of calls in order on one stream (calls that may run concurrently
  * need one buffer each).  It must not overlap any input or `var`. */
 size_t sv_variance_work_bytes(sv_dims d);
+
+/* sv_variance without the `work` argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation).  Same arguments, rules and
+ * results (bitwise) as sv_variance, minus `work`.  The workspace is a
+ * fixed 32 MiB array in the library's device memory, one per GPU, held
+ * until the process ends: calls whose sv_variance_work_bytes(d) exceeds
+ * 32 MiB (33,554,432 bytes; 3840x2160 needs 33,178,624) return SV_ETOOBIG
+ * without touching the GPU.  The first call on a device looks up that
+ * device's copy of the array (with the device current).  Each call clears
+ * the array's counters on `stream` before use; it calls no allocator.
+ * Every call on one GPU uses the same array, so calls that may overlap on
+ * one GPU (other streams, other threads) race: order them on one stream.
+ * SV_V_LISTED is rejected (SV_EINVAL): a list sv_temporal wrote lives in
+ * the caller's workspace.  SV_EHIP if the array's address cannot be had. */
+int sv_variance_noalloc(const float *m1, const float *m2c, const uint8_t *n,
+                        const sv_gbuf *g, float *var, sv_dims d, sv_dtype t,
+                        const sv_variance_params *p, sv_stream stream);
 
 /* ---- edge-avoiding a-trous level (Section 2, Fig. 1; Section 3.3) ------ */
 enum {

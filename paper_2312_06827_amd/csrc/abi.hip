@@ -59,6 +59,7 @@ const char *sv_status_str(int status) {
     case SV_EDTYPE: return "unknown storage type";
     case SV_EHIP: return "HIP launch error";
     case SV_EUNSUPPORTED: return "unsupported combination";
+    case SV_ETOOBIG: return "larger than the fixed workspace of the allocation-free call";
     default: return "unknown status";
     }
 }

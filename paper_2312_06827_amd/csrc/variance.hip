@@ -6,6 +6,8 @@
 // Pass 1 (pointwise) writes the temporal estimate and lists the pixels
 // whose history is short; pass 2 computes the spatial estimate of the
 // listed pixels, eight lanes per pixel, spread over every CU.
+#include <mutex>
+
 #include "sv_internal.h"
 
 namespace sv {
@@ -219,6 +221,65 @@ void launch_variance(const VarianceArgs &a, unsigned grid, int radius, bool list
 }
 
 }  // namespace sv
+
+// ---- the variance estimate without a caller workspace -------------------------
+//
+// For callers that cannot allocate (code under graph capture, tight serving
+// loops): the workspace is one file-scope device array, kNoAllocBytes
+// long, which each GPU holds for the life of the process.  Host code never
+// passes the array's name to a kernel (in host code it is a stand-in, not a
+// device address): the device address comes from hipGetSymbolAddress, taken
+// once per device with that device current, and only that address is used.
+
+namespace sv {
+
+// 32 MiB: the eight counters and the pixel list of a 3840x2160 frame
+// (sv_variance_work_bytes gives 33,178,624 bytes there).
+constexpr size_t kNoAllocBytes = size_t(32) << 20;
+constexpr int kMaxDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+static std::mutex g_scratch_lock;
+static void *g_scratch_ptr[kMaxDevices];
+
+// This device's address of the array, looked up on the first call on the
+// device (with the device current); nullptr on failure.
+static void *scratch_ptr(int dev) {
+    std::lock_guard<std::mutex> lk(g_scratch_lock);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace sv
+
+extern "C" int sv_variance_noalloc(const float *m1, const float *m2c, const uint8_t *n,
+                                   const sv_gbuf *g, float *var, sv_dims d, sv_dtype t,
+                                   const sv_variance_params *p, sv_stream stream) {
+    using namespace sv;
+    if (!valid_dtype(t)) return SV_EDTYPE;
+    const int dc = check_dims(d);
+    if (dc < 0 || !p) return SV_EINVAL;
+    if (p->flags & SV_V_LISTED) return SV_EINVAL;  // a list lives in the caller's workspace
+    if (dc == 1) return SV_OK;
+    if (sv_variance_work_bytes(d) > kNoAllocBytes) return SV_ETOOBIG;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return SV_EHIP;
+    void *work = scratch_ptr(dev);
+    if (!work) return SV_EHIP;
+    // every call shares this device's array and finds what the last call
+    // left there: its counters are cleared first (a kernel, not a memset,
+    // so that a captured graph holds kernel nodes only)
+    hipLaunchKernelGGL(variance_reset_k, dim3(1), dim3(64), 0, as_stream(stream),
+                       (VarWork *)work);
+    const int rc = hip_status(hipGetLastError());
+    if (rc != SV_OK) return rc;
+    return sv_variance(m1, m2c, n, g, var, work, d, t, p, stream);
+}
 
 extern "C" size_t sv_variance_work_bytes(sv_dims d) {
     if (sv::check_dims(d) < 0) return 0;

@@ -23,7 +23,7 @@ import torch
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libsv.so")
 
-SV_OK, SV_EINVAL, SV_EALIAS, SV_EDTYPE, SV_EHIP, SV_EUNSUPPORTED = range(6)
+SV_OK, SV_EINVAL, SV_EALIAS, SV_EDTYPE, SV_EHIP, SV_EUNSUPPORTED, SV_ETOOBIG = range(7)
 SV_F32, SV_F16 = 0, 1
 SV_TM_LUMA, SV_TM_CHANNEL, SV_TM_PAPER = 0, 1, 2
 SV_T_CLAMP, SV_T_USE_ID, SV_T_TONEMAP_IN, SV_T_CLIP = 1, 2, 4, 8
@@ -139,6 +139,8 @@ EXPORTS = {
     "sv_variance": ([_vp, _vp, _vp, _P(sv_gbuf), _vp, _vp, sv_dims, ctypes.c_int,
                      _P(sv_variance_params), _vp], ctypes.c_int),
     "sv_variance_work_bytes": ([sv_dims], ctypes.c_size_t),
+    "sv_variance_noalloc": ([_vp, _vp, _vp, _P(sv_gbuf), _vp, sv_dims, ctypes.c_int,
+                             _P(sv_variance_params), _vp], ctypes.c_int),
     "sv_atrous": ([_P(sv_rgb), _vp, _P(sv_gbuf), _vp, _P(sv_rgb), _vp, ctypes.c_int32,
                    sv_dims, ctypes.c_int, _P(sv_atrous_params), _vp], ctypes.c_int),
     "sv_atrous_sep": ([_P(sv_rgb), _vp, _P(sv_gbuf), _vp, _P(sv_rgb), _P(sv_rgb), _vp,
@@ -412,6 +414,16 @@ def sv_variance(m1: torch.Tensor, m2c: torch.Tensor, n: torch.Tensor, g: GBuf,
     _check("sv_variance", load().sv_variance(
         _plane_ptr(m1), _plane_ptr(m2c), _plane_ptr(n), ctypes.byref(gc), _plane_ptr(var),
         work.data_ptr(), dims_of(m1), dtype_of(g.z), ctypes.byref(pc), _stream(stream)))
+
+
+def sv_variance_noalloc(m1: torch.Tensor, m2c: torch.Tensor, n: torch.Tensor, g: GBuf,
+                        var: torch.Tensor, params: VarianceParams, stream=None):
+    """sv_variance with the library's fixed workspace (no allocation)."""
+    gc = g.c()
+    pc = params.c()
+    _check("sv_variance_noalloc", load().sv_variance_noalloc(
+        _plane_ptr(m1), _plane_ptr(m2c), _plane_ptr(n), ctypes.byref(gc), _plane_ptr(var),
+        dims_of(m1), dtype_of(g.z), ctypes.byref(pc), _stream(stream)))
 
 
 def sv_atrous(c_in: Planes, var_in: torch.Tensor, g: GBuf, c_out: Planes,

@@ -38,7 +38,7 @@ def test_every_declared_symbol_is_exported(so):
 
 def test_status_strings_and_version(so):
     assert so.sv_version() == 1
-    for code in range(6):
+    for code in range(7):
         assert so.sv_status_str(code)
     assert so.sv_status_str(99) == b"unknown status"
     assert so.sv_last_hip_error() == 0
@@ -288,3 +288,23 @@ def test_binding_structures_match_the_header(so):
     assert k == len(mine)
     for i, t in enumerate(mine):
         assert ctypes.sizeof(t) == sizes[i], (t.__name__, ctypes.sizeof(t), sizes[i])
+
+
+def test_variance_noalloc_rejects_on_the_host(so):
+    """Sizes past the fixed 32 MiB workspace fail with SV_ETOOBIG, and the
+    listed mode with SV_EINVAL, before any HIP call."""
+    vp = L.sv_variance_params(1.0, 128.0, 1e-10, 4, 3, 0)
+    r = ctypes.byref
+    g = gbuf(A)
+    big = L.sv_dims(4096, 2304, 4096)  # needs 37.7 MB of workspace
+    assert so.sv_variance_work_bytes(big) > 32 << 20
+    assert so.sv_variance_noalloc(A, A + STRIDE, A + 2 * STRIDE, r(g), A + 3 * STRIDE, big,
+                                  L.SV_F32, r(vp), None) == L.SV_ETOOBIG
+    uhd = L.sv_dims(3840, 2160, 3840)
+    assert so.sv_variance_work_bytes(uhd) <= 32 << 20
+    listed = L.sv_variance_params(1.0, 128.0, 1e-10, 4, 3, L.SV_V_LISTED)
+    assert so.sv_variance_noalloc(A, A + STRIDE, A + 2 * STRIDE, r(g), A + 3 * STRIDE, uhd,
+                                  L.SV_F32, r(listed), None) == L.SV_EINVAL
+    empty = L.sv_dims(0, 10, 0)
+    assert so.sv_variance_noalloc(None, None, None, r(g), None, empty, L.SV_F32, r(vp),
+                                  None) == L.SV_OK
