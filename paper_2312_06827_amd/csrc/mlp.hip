@@ -129,11 +129,15 @@ __global__ __launch_bounds__(256) void mlp_backward_k(MlpArgs a) {
             da = a.d_alpha ? a.d_alpha[o] : 0.f;
             dk = a.d_kappa ? a.d_kappa[o] : 0.f;
         }
-        const float sg = 1.0f / (1.0f + expf(-r.o0));
-        const float th = tanhf(r.o1);
-        const float kap = exp2f(2.0f * th);
-        const float g0 = da * (1.0f - kAlphaMin) * sg * (1.0f - sg);
-        const float g1 = dk * kap * 0.69314718055994531f * 2.0f * (1.0f - th * th);
+        // the heads' slopes without cancellation: sigmoid' = e / (1 + e)^2
+        // with e = exp(-|o|), and 1 - tanh^2 = 4 e / (1 + e)^2 with
+        // e = exp(-2|o|) (1 - sg and 1 - th^2 would lose every digit once
+        // the heads saturate)
+        const float e0 = expf(-fabsf(r.o0)), d0 = 1.0f / (1.0f + e0);
+        const float e1 = expf(-2.0f * fabsf(r.o1)), d1 = 1.0f / (1.0f + e1);
+        const float kap = exp2f(2.0f * tanhf(r.o1));
+        const float g0 = da * (1.0f - kAlphaMin) * (e0 * d0 * d0);
+        const float g1 = dk * kap * 0.69314718055994531f * 2.0f * (4.0f * e1 * d1 * d1);
         const float g0q = from_bf16(to_bf16(g0)), g1q = from_bf16(to_bf16(g1));
         if (hf == 0) {
             db3a += g0;

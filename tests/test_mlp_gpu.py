@@ -3,10 +3,13 @@
 
 Tolerances.  The device rounds matrix operands to bfloat16 exactly as the
 oracle's precision model does, but its binary32 sums run in another order;
-a pre-activation within a few binary32 ulps of a bfloat16 rounding
-boundary can therefore round the other way (one bfloat16 ulp, 2^-8
-relative, of one activation).  Such flips are rare; the tests bound the
-median error tightly and the maximum by the effect of a few flips.
+a value within a few binary32 ulps of a bfloat16 rounding midpoint can
+therefore round the other way (one bfloat16 ulp of one activation or
+gradient).  The forward and backward tests hold the median error at the
+binary32 level and every element within the summed effect of the flips
+that could reach it (tests/_mlp_bounds.py: each candidate value rounded
+the other way, the pixel run again) plus binary32 rounding slack; the
+flips are counted.
 """
 
 import numpy as np
@@ -17,6 +20,7 @@ import oracle as O
 from oracle import mlp as M
 from paper_2312_06827_amd import lib as L
 from paper_2312_06827_amd.scene import CONFIGS, render_frame, sequence, with_size
+from tests import _mlp_bounds as B
 from tests._util import rel_err, say
 
 pytestmark = pytest.mark.gpu
@@ -74,10 +78,15 @@ def test_forward_parity(H, W):
     fw = M.forward(w, xs, bf16_ops=True)
     ea = np.abs(host(a).ravel() - fw["alpha"])
     ek = np.abs(host(k).ravel() - fw["kappa"]) / fw["kappa"]
+    zero = np.zeros(H * W)
+    ba, bk, _, _, _, nflip = B.flip_bounds(w, xs, zero, zero, forward_only=True)
     say(f"  alpha err median {np.median(ea):.1e} max {ea.max():.1e}; "
-        f"kappa rel err median {np.median(ek):.1e} max {ek.max():.1e}")
+        f"kappa rel err median {np.median(ek):.1e} max {ek.max():.1e}; "
+        f"{nflip} flip candidates, {int((ea > 1e-6).sum())} alphas off by more than 1e-6")
     assert np.median(ea) <= 1e-6 and np.median(ek) <= 1e-6
-    assert ea.max() <= 2e-3 and ek.max() <= 4e-3
+    # binary32 heads: 1e-6 beside the flips
+    assert np.all(ea <= ba + 1e-6), np.argmax(ea - ba)
+    assert np.all(ek <= bk + 1e-6), np.argmax(ek - bk)
 
 
 @pytest.mark.parametrize("N", [40, 1000, 4096 + 17])
@@ -98,13 +107,21 @@ def test_backward_parity(N):
     g_o = M.head_grads(fw, M.f32(da), M.f32(dk))
     ref = 0.5 * M.backward(w, fw, g_o, bf16_ops=True)
     got = host(grad)
+    _, _, bg, asum, _, nflip = B.flip_bounds(w, xs, M.f32(da), M.f32(dk))
+    # binary32 sums over the pixels in the device's order: 2^-16 of the sum
+    # of the magnitudes summed (far above the about 200 additions on the
+    # longest path times 2^-24)
+    allow = 0.5 * (bg + 2.0 ** -16 * asum)
+    err = np.abs(got - ref)
     off = 0
     for name, n in [("W1", 448), ("b1", 32), ("W2", 1024), ("b2", 32), ("W3", 64), ("b3", 2)]:
         g, o = got[off:off + n], ref[off:off + n]
         e = np.abs(g - o).max() / max(np.abs(o).max(), 1e-30)
-        say(f"  {name}: max err / max |grad| = {e:.1e}")
-        assert e <= 5e-3, name
+        say(f"  {name}: max err / max |grad| = {e:.1e}; max err / allowed = "
+            f"{(err[off:off + n] / np.maximum(allow[off:off + n], 1e-30)).max():.2f}")
         off += n
+    say(f"  {nflip} flip candidates over {N} pixels")
+    assert np.all(err <= allow), (int(np.argmax(err - allow)), float((err - allow).max()))
     # a second call with the same inputs is bitwise identical (fixed order)
     g2 = torch.empty_like(grad)
     L.sv_mlp_backward(mlp, _rows(xs), dev(da[None]), dev(dk[None]), g2, work, like, scale=0.5)

@@ -323,3 +323,30 @@ def test_features_of_a_moving_sequence():
                     nonzero_moment += 1
         _, st, _ = O.run_frame(fr, st, p)
     assert moving > 1000 and nonzero_moment > 1000, (moving, nonzero_moment)
+
+
+def test_per_pixel_pass_of_the_flip_bounds_equals_the_oracle():
+    """tests/_mlp_bounds.pixel_pass (the per-pixel model the GPU tests use
+    to bound bfloat16 rounding flips) reproduces the oracle's batched
+    forward and backward exactly when nothing is overridden, and a flip
+    moves one value by one bfloat16 ulp."""
+    from tests import _mlp_bounds as B
+    w = _weights(31)
+    r = np.random.default_rng(32)
+    xs = M.bf16(r.normal(0, 1.2, (M.N_IN, 25)))
+    da, dk = M.f32(r.normal(0, 1, 25)), M.f32(r.normal(0, 1, 25))
+    fw = M.forward(w, xs, bf16_ops=True)
+    ref = M.backward(w, fw, M.head_grads(fw, da, dk), bf16_ops=True)
+    tot = np.zeros(M.N_PARAMS)
+    for p in range(25):
+        al, ka, c, _ = B.pixel_pass(w, xs[:, p], da[p], dk[p])
+        assert al == fw["alpha"][p] and ka == fw["kappa"][p]
+        tot += c
+    np.testing.assert_allclose(tot, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+    v = np.array([1.0 + 2 ** -8, 3.0 * (1 + 2 ** -9 + 2 ** -20)])
+    alt = B.other_rounding(v)
+    assert np.all(alt != M.bf16(v)) and np.all(np.abs(alt - v) < 2 * np.abs(M.bf16(v) - v) + 2 ** -6 * np.abs(v))
+    assert B.near_midpoint(np.array([1.0 + 2 ** -8]))[0] and not B.near_midpoint(np.array([1.0]))[0]
+    # a sum whose terms are 2^12 times larger may be off by far more of its ulps
+    v = np.array([1.0 + 2 ** -8 + 2 ** -16])
+    assert not B.near_midpoint(v)[0] and B.near_midpoint(v, 4096.0)[0]
