@@ -295,9 +295,15 @@ typedef struct {
      * persistent: -1 library default (one tile per workgroup), 0 one tile
      * per workgroup, 1 each
      * workgroup loops over tiles and prefetches the next one;
-     * blocks_per_cu: workgroups per CU of a persistent launch (0 default). */
+     * blocks_per_cu: workgroups per CU of a persistent launch (0 default);
+     * tile_rows: the LDS tile's height.  5x5 levels: lattice rows per
+     * thread, 1 or 2 (a tile of 64 x 4 tile_rows lattice rows); fused
+     * separable levels: output rows per wave, 6 or 16.  0 = library default
+     * (5x5: 2 up to step 4, 1 above; separable: 16 up to step 4, 6 above);
+     * other values are SV_EINVAL. */
     int32_t persistent;
     int32_t blocks_per_cu;
+    int32_t tile_rows;
 } sv_atrous_params;
 
 /* One level with hole spacing `step` (>= 1; 1, 2, 4, 8, 16 for the five
@@ -524,7 +530,8 @@ int sv_atrous_kappa_grad(const sv_rgb *c_in, const float *var_in, const sv_gbuf 
  * storage type and dims d; pick is CH x CW bytes, contiguous; alpha_map is
  * a binary32 plane of dims d; lambda (optional) CH x CW binary32,
  * contiguous; work: sv_grad_work_bytes(d) bytes of device memory, any
- * contents.  Outputs and work must not overlap inputs (SV_EALIAS). */
+ * contents, 16-byte aligned (SV_EINVAL otherwise).  Outputs and work must
+ * not overlap inputs (SV_EALIAS). */
 typedef struct {
     float alpha;    /* blend factor where nothing changed (0.2) */
     float tau_z;    /* depth test of the landing pixel (0.1) */
@@ -602,10 +609,12 @@ typedef struct {
     int32_t separable;           /* 1: sv_atrous_sep levels */
     int32_t feedback;            /* colour history: 0 level-0 output,
                                     1 temporal output */
-    /* per-level launch shape overriding atrous.persistent / blocks_per_cu
-     * when >= 0 / > 0 (set by an autotuner; results do not depend on it) */
+    /* per-level launch shape overriding atrous.persistent / blocks_per_cu /
+     * tile_rows when >= 0 / > 0 / > 0 (set by an autotuner; results do not
+     * depend on it) */
     int32_t level_persistent[10];
     int32_t level_blocks_per_cu[10];
+    int32_t level_tile_rows[10];
 } sv_frame_params;
 
 /* Enqueues one frame: sv_temporal (history -> temporal), sv_variance,

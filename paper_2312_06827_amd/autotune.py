@@ -1,15 +1,19 @@
 """Autotuner for the launch shape of the LDS-tiled a-trous kernels.
 
-Every level (5x5, or separable horizontal + vertical) can run one tile per
-workgroup or with persistent workgroups that prefetch their next tile, at a
-chosen number of workgroups per CU.  Which is fastest depends on the step
-(the LDS footprint grows with it), the pass and the image size, so the
-choice is measured: each candidate is timed with HIP events on synthetic
-planes of the target size, and the fastest kept.  Results do not depend on
-the launch shape (the tests check that), only the time does.
+A 5x5 level's tile is 64 columns by 4 x rows lattice rows, with rows (the
+lattice rows each thread computes) 1 or 2; it runs one tile per workgroup
+or with persistent workgroups that prefetch their next tile, at a chosen
+number of workgroups per CU.  The fused separable level's wave walks a band
+of 6 or 16 output rows.  Which is fastest depends on the step (the LDS
+halo grows with it and sets how many workgroups fit a CU), the storage type
+and the image size, so the choice is measured: each candidate is timed with
+HIP events on synthetic planes of the target size, and the fastest kept.
+Results do not depend on the launch shape (the tests check that bitwise),
+only the time does.
 
-Choices are cached as JSON, keyed by device, image size, storage type,
-filter form and level.
+A choice is (persistent, workgroups per CU, tile rows), the per-level
+fields of the frame parameters.  Choices are cached as JSON, keyed by
+device, image size, storage type, filter form and level.
 """
 
 from __future__ import annotations
@@ -22,8 +26,13 @@ import torch
 
 from . import lib
 
-# (persistent, workgroups per CU); (0, 0) = one tile per workgroup
-CANDIDATES: Sequence[Tuple[int, int]] = ((0, 0), (1, 2), (1, 3), (1, 4), (1, 6), (1, 8))
+# 5x5 levels: (persistent, workgroups per CU, lattice rows per thread);
+# (0, 0, r) = one tile per workgroup
+CANDIDATES: Sequence[Tuple[int, int, int]] = tuple(
+    (per, bpc, rows) for rows in (1, 2)
+    for per, bpc in ((0, 0), (1, 2), (1, 3), (1, 4), (1, 6), (1, 8)))
+# fused separable levels: output rows per wave
+SEP_CANDIDATES: Sequence[Tuple[int, int, int]] = ((0, 0, 6), (0, 0, 16))
 
 _DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
 
@@ -63,27 +72,30 @@ def _time(fn, reps: int) -> float:
 
 def tune(H: int, W: int, dtype: torch.dtype = torch.float32, separable: bool = False,
          levels: int = 5, params: Optional[lib.AtrousParams] = None, reps: int = 10,
-         candidates: Sequence[Tuple[int, int]] = CANDIDATES) -> Tuple[List[Tuple[int, int]], Dict]:
+         candidates: Optional[Sequence[Tuple[int, int, int]]] = None
+         ) -> Tuple[List[Tuple[int, int, int]], Dict]:
     """Time every candidate for each level; returns the per-level choice and
     the measured times (ms) per level and candidate."""
     params = params or lib.AtrousParams()
+    if candidates is None:
+        candidates = SEP_CANDIDATES if separable else CANDIDATES
     c, var, g = _planes(H, W, dtype)
     out = torch.empty_like(c)
-    scratch = torch.empty_like(c)
     vout = torch.empty_like(var)
     best, times = [], {}
     for i in range(levels):
         step = 1 << i
         last = i == levels - 1
         row = {}
-        for per, bpc in candidates:
-            p = lib.AtrousParams(**{**params.__dict__, "persistent": per, "blocks_per_cu": bpc})
+        for per, bpc, rows in candidates:
+            p = lib.AtrousParams(**{**params.__dict__, "persistent": per, "blocks_per_cu": bpc,
+                                    "tile_rows": rows, "inv_tonemap": last})
             vo = None if last else vout
-            if separable:
-                fn = lambda p=p, vo=vo: lib.sv_atrous_sep(c, var, g, scratch, out, vo, step, p)
+            if separable:  # the fused form (no scratch)
+                fn = lambda p=p, vo=vo: lib.sv_atrous_sep(c, var, g, None, out, vo, step, p)
             else:
                 fn = lambda p=p, vo=vo: lib.sv_atrous(c, var, g, out, vo, step, p)
-            row[(per, bpc)] = _time(fn, reps)
+            row[(per, bpc, rows)] = _time(fn, reps)
         times[i] = row
         best.append(min(row, key=row.get))
     return best, times
@@ -91,12 +103,10 @@ def tune(H: int, W: int, dtype: torch.dtype = torch.float32, separable: bool = F
 
 def tiles_for(H: int, W: int, dtype: torch.dtype = torch.float32, separable: bool = False,
               levels: int = 5, cache: Optional[str] = _DEFAULT_CACHE,
-              retune: bool = False) -> List[Tuple[int, int]]:
-    """Per-level launch shapes for this device and size, from the cache or
-    measured now (and cached)."""
-    if separable:
-        # the fused separable level has one launch form: nothing to choose
-        return [(0, 0)] * levels
+              retune: bool = False) -> List[Tuple[int, int, int]]:
+    """Per-level launch shapes (persistent, workgroups per CU, tile rows)
+    for this device and size, from the cache or measured now (and
+    cached)."""
     dev = torch.cuda.get_device_name()
     keys = [_key(dev, W, H, dtype, separable, i) for i in range(levels)]
     table = {}
@@ -106,7 +116,7 @@ def tiles_for(H: int, W: int, dtype: torch.dtype = torch.float32, separable: boo
                 table = json.load(f)
         except (OSError, ValueError):
             table = {}
-    if not retune and all(k in table for k in keys):
+    if not retune and all(k in table and len(table[k]) == 3 for k in keys):
         return [tuple(table[k]) for k in keys]
     best, _ = tune(H, W, dtype, separable, levels)
     for k, b in zip(keys, best):

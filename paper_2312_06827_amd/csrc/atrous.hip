@@ -47,22 +47,31 @@ static int check_atrous(const sv_rgb *c_in, const float *var_in, const sv_gbuf *
 static TileCfg tile_cfg(const sv_atrous_params *p, int dir) {
     // default: one tile per workgroup, which measured fastest (or within
     // noise of the persistent forms) for every level at 1080p; callers pick
-    // the persistent form through the params (the autotuner does)
-    TileCfg c{false, 4};
+    // the persistent form and the tile height through the params (the
+    // autotuner does)
+    TileCfg c{false, 4, 0};
     if (p->persistent > 0) c.persistent = true;
     if (p->blocks_per_cu > 0) c.blocks_per_cu = p->blocks_per_cu;
-    (void)dir;
+    if (dir == kDir2D) c.rows = p->tile_rows;
     return c;
+}
+
+// tile_rows: 5x5 levels 0, 1 or 2; fused separable levels 0, 6 or 16
+static bool valid_rows(const sv_atrous_params *p, bool separable) {
+    const int r = p->tile_rows;
+    return separable ? (r == 0 || r == 6 || r == 16) : (r == 0 || r == 1 || r == 2);
 }
 
 static void run_pass(const AtrousArgs &a, sv_dtype t, int dir, bool unit, TileCfg cfg,
                      hipStream_t s) {
     if (t == SV_F32) {
         if (dir == kDir2D) launch_pass_f32_2d(a, unit, cfg, s);
+        else if (dir == kDir2DA) launch_pass_f32_2da(a, unit, cfg, s);
         else if (dir == kDirH) launch_pass_f32_h(a, unit, cfg, s);
         else launch_pass_f32_v(a, unit, cfg, s);
     } else {
         if (dir == kDir2D) launch_pass_f16_2d(a, unit, cfg, s);
+        else if (dir == kDir2DA) launch_pass_f16_2da(a, unit, cfg, s);
         else if (dir == kDirH) launch_pass_f16_h(a, unit, cfg, s);
         else launch_pass_f16_v(a, unit, cfg, s);
     }
@@ -85,6 +94,7 @@ extern "C" int sv_atrous(const sv_rgb *c_in, const float *var_in, const sv_gbuf 
                          sv_dims d, sv_dtype t, const sv_atrous_params *p, sv_stream stream) {
     using namespace sv;
     int empty = 0;
+    if (p && !valid_rows(p, false)) return SV_EINVAL;
     int rc = check_atrous(c_in, var_in, g, kappa, nullptr, c_out, var_out, step, d, t, p, &empty);
     if (rc != SV_OK || empty) return rc;
     AtrousArgs a = make_args(c_in, var_in, g, kappa, c_out, var_out, step, d, p);
@@ -101,13 +111,15 @@ extern "C" int sv_atrous_sep(const sv_rgb *c_in, const float *var_in, const sv_g
     using namespace sv;
     int empty = 0;
     if (scratch && (!scratch->r || !scratch->g || !scratch->b)) return SV_EINVAL;
+    if (p && !valid_rows(p, true)) return SV_EINVAL;
     int rc = check_atrous(c_in, var_in, g, kappa, scratch, c_out, var_out, step, d, t, p, &empty);
     if (rc != SV_OK || empty) return rc;
     const bool unit = (p->flags & SV_A_UNIT_WEIGHTS) != 0;
     hipStream_t s = as_stream(stream);
     if (!scratch) {  // both passes in one kernel, the horizontal result kept on chip
         const HvArgs a = make_args(c_in, var_in, g, kappa, c_out, var_out, step, d, p);
-        const bool ok = t == SV_F32 ? launch_hv_f32(a, unit, s) : launch_hv_f16(a, unit, s);
+        const bool ok = t == SV_F32 ? launch_hv_f32(a, unit, p->tile_rows, s)
+                                    : launch_hv_f16(a, unit, p->tile_rows, s);
         if (!ok) return SV_EUNSUPPORTED;
         return hip_status(hipGetLastError());
     }
@@ -130,6 +142,7 @@ extern "C" int sv_atrous_adaptive(const sv_rgb *c_in, const float *var_in, const
     if (level < 0 || level > 12 || (separable != 0 && separable != 1)) return SV_EINVAL;
     if (!separable && scratch) return SV_EINVAL;
     if (scratch && (!scratch->r || !scratch->g || !scratch->b)) return SV_EINVAL;
+    if (p && !valid_rows(p, separable != 0)) return SV_EINVAL;
     int empty = 0;
     int rc = check_atrous(c_in, var_in, g, kappa, scratch, c_out, var_out, 1 << level, d, t, p,
                           &empty);
@@ -151,6 +164,13 @@ extern "C" int sv_atrous_adaptive(const sv_rgb *c_in, const float *var_in, const
     if (separable && !scratch && level + 1 > 5) return SV_EUNSUPPORTED;
     const bool unit = (p->flags & SV_A_UNIT_WEIGHTS) != 0;
     hipStream_t s = as_stream(stream);
+    if (!separable && (1 << level) <= kMaxStep2DA) {  // one launch, each pixel at its step
+        AtrousArgs a = make_args(c_in, var_in, g, kappa, c_out, var_out, 1 << level, d, p);
+        a.ctl = ctl;
+        a.ctl_level = level;
+        run_pass(a, t, kDir2DA, unit, tile_cfg(p, kDir2D), s);
+        return hip_status(hipGetLastError());
+    }
     for (int cls = 0; cls < 2; ++cls) {
         const int step = 1 << (level + cls);
         if (!separable) {
@@ -164,7 +184,8 @@ extern "C" int sv_atrous_adaptive(const sv_rgb *c_in, const float *var_in, const
             a.ctl = ctl;
             a.ctl_level = level;
             a.ctl_class = cls;
-            const bool ok = t == SV_F32 ? launch_hv_f32(a, unit, s) : launch_hv_f16(a, unit, s);
+            const bool ok = t == SV_F32 ? launch_hv_f32(a, unit, p->tile_rows, s)
+                                        : launch_hv_f16(a, unit, p->tile_rows, s);
             if (!ok) return SV_EUNSUPPORTED;
         } else {
             // the horizontal pass covers every pixel at this launch's step;

@@ -2,5 +2,7 @@
 #include "atrous_impl.h"
 
 namespace sv {
-bool launch_hv_f16(const HvArgs &a, bool unit, hipStream_t s) { return launch_hv<half_t>(a, unit, s); }
+bool launch_hv_f16(const HvArgs &a, bool unit, int rows, hipStream_t s) {
+    return launch_hv<half_t>(a, unit, rows, s);
+}
 }  // namespace sv

@@ -35,8 +35,10 @@ struct AtrousArgs {
     const void *sr, *sg, *sb;
 };
 
-// Weight modes: every edge weight 1 (plain B3), or the full edge weights.
-enum { kUnit = 0, kWeighted = 1 };
+// Weight modes: every edge weight 1 (plain B3), or the full edge weights
+// with the normal term in log form (add_normal_term) or, for large sigma_n,
+// as a series (add_normal_series).
+enum { kUnit = 0, kWeighted = 1, kWeightedSeries = 2 };
 
 constexpr int kCUs = 256;
 
@@ -131,7 +133,8 @@ __device__ __forceinline__ void tap(Acc &acc, float4 qc, float4 qg, float qv, fl
     } else {
         float t = fmaf(-fabsf(zp - qg.x), kz, log2h);
         t = fmaf(-fabsf(lp - qc.w), kl, t);
-        t = add_normal_term(t, chord2(nxp, nyp, nzp, qg.y, qg.z, qg.w), nc);
+        const float s2 = chord2(nxp, nyp, nzp, qg.y, qg.z, qg.w);
+        t = MODE == kWeightedSeries ? add_normal_series(t, s2, nc) : add_normal_term(t, s2, nc);
         hw = fast_exp2(t);
     }
     acc.sw += hw;
@@ -161,10 +164,12 @@ __device__ __forceinline__ void pass_through(const AtrousArgs &a, uint32_t o, co
 //
 // Control byte of pixel p: bits 0-3 the number of levels p takes part in
 // (15: all), bit 4 set when p starts one level coarser (its level i uses
-// step 2^(i+1)).  A level then runs as two launches over the whole image:
-// class 0 at step 2^i writes the pixels without the shift and the pixels
-// whose budget is spent (passed through), class 1 at step 2^(i+1) the
-// shifted pixels.  Each pixel's output is written by exactly one of them.
+// step 2^(i+1)).  A 5x5 level up to kMaxStep2DA runs as one launch that
+// picks each pixel's step (kDir2DA); otherwise as two launches over the
+// whole image: class 0 at step 2^i writes the pixels without the shift and
+// the pixels whose budget is spent (passed through), class 1 at step
+// 2^(i+1) the shifted pixels.  Each pixel's output is written by exactly
+// one of them.
 // Returns 0 when the other launch writes o, 1 to filter it here, 2 to pass
 // it through here.
 __device__ __forceinline__ int ctl_select(const AtrousArgs &a, uint32_t o) {
@@ -214,7 +219,14 @@ __device__ __forceinline__ void copy_through(const AtrousArgs &a, uint32_t o) {
 // its XCD's contiguous range, and issues the global loads of its next tile
 // into registers before computing the current one from LDS, so the memory
 // latency of a tile hides behind the arithmetic of the previous one.
-enum { kDir2D = 0, kDirH = 1, kDirV = 2 };
+// kDir2DA: the 5x5 level of the adaptive blur in one launch, every pixel at
+// its own step (the level's, or twice it when its control byte says so):
+// the tile holds the halo of the doubled step (four lattice rows and
+// columns of the level's step around it).
+enum { kDir2D = 0, kDirH = 1, kDirV = 2, kDir2DA = 3 };
+// Largest level step run as one adaptive launch: beyond it the doubled halo
+// costs more LDS (so occupancy) than the second launch's staging.
+constexpr int kMaxStep2DA = 8;
 
 // Staged prefilter entry of a pixel outside the image or without a surface.
 constexpr float kNoVar = __builtin_nanf("");
@@ -240,10 +252,11 @@ constexpr int tile_py(int step) { return step >= 8 ? 1 : 2; }
 template <int STEP, int PY, int DIR, bool WANT_VAR>
 struct TileShape {
     static constexpr int TX = 64, TY = 4 * PY;
-    static constexpr int HY = DIR == kDirH ? 0 : 2, HX = DIR == kDirV ? 0 : 2 * STEP;
+    static constexpr int HALO = DIR == kDir2DA ? 4 : 2;
+    static constexpr int HY = DIR == kDirH ? 0 : HALO, HX = DIR == kDirV ? 0 : HALO * STEP;
     static constexpr int ROWS = TY + 2 * HY, COLS = TX + 2 * HX;
     static constexpr int AMAX = DIR == kDirV ? 0 : 2, BMAX = DIR == kDirH ? 0 : 2;
-    static constexpr bool PF_TILE = STEP == 1 && DIR == kDir2D;
+    static constexpr bool PF_TILE = STEP == 1 && (DIR == kDir2D || DIR == kDir2DA);
     static constexpr bool NEED_V = WANT_VAR || PF_TILE;
     static constexpr int PFC = TX + 2;
     static constexpr int NS = ROWS * COLS, IT = (NS + 255) / 256;
@@ -357,7 +370,17 @@ __device__ __forceinline__ void tile_compute(const AtrousArgs &a, TileOrigin t,
         const int y = t.ybase + j * STEP;
         if (y >= a.h) break;
         const uint32_t o = vofs((uint32_t)y * (uint32_t)a.pitch + (uint32_t)x);
-        if (DIR != kDirH && a.ctl) {  // uniform branch
+        // the adaptive level in one launch: a pixel whose budget is spent
+        // keeps its input, a shifted one takes every tap at twice the step
+        int m = 1;
+        if (DIR == kDir2DA) {
+            const uint32_t c = a.ctl[o];
+            if (a.ctl_level >= (int)(c & 15u)) {
+                copy_through<T>(a, o);
+                continue;
+            }
+            m = (c & 16u) ? 2 : 1;
+        } else if (DIR != kDirH && a.ctl) {  // uniform branch
             const int sel = ctl_select(a, o);
             if (sel != 1) {
                 if (sel == 2) copy_through<T>(a, o);
@@ -415,8 +438,8 @@ __device__ __forceinline__ void tile_compute(const AtrousArgs &a, TileOrigin t,
         float kl = 0.f;
         if (MODE != kUnit) {
             kl = luma_scale(a, g, o);
-            const float gx = DIR == kDirV ? 0.f : ldo<T>(a.dzdx, o) * (float)STEP;
-            const float gy = DIR == kDirH ? 0.f : ldo<T>(a.dzdy, o) * (float)STEP;
+            const float gx = DIR == kDirV ? 0.f : ldo<T>(a.dzdx, o) * (float)(STEP * m);
+            const float gy = DIR == kDirH ? 0.f : ldo<T>(a.dzdy, o) * (float)(STEP * m);
             float szl, ezl;
             depth_coefs(a, szl, ezl);
 #pragma unroll
@@ -428,24 +451,28 @@ __device__ __forceinline__ void tile_compute(const AtrousArgs &a, TileOrigin t,
                     kz[kz_index(aa, b)] = depth_scale(grad_dot(gx, gy, aa, b), szl, ezl);
                 }
         }
-        constexpr float h0 = DIR == kDir2D ? 0.375f * 0.375f : 0.375f;
+        constexpr bool FULL = DIR == kDir2D || DIR == kDir2DA;
+        constexpr float h0 = FULL ? 0.375f * 0.375f : 0.375f;
         Acc acc;
         acc.sw = h0;
         acc.sr = h0 * pc.x;
         acc.sg = h0 * pc.y;
         acc.sb = h0 * pc.z;
         acc.sv = WANT_VAR ? h0 * h0 * s_v[ci] : 0.f;
+        // taps at lattice offsets (aa, b) times m: a shifted pixel of the
+        // adaptive level (m = 2) takes the same instructions with a runtime
+        // stride, so that a wave mixing both kinds does not run both
+        const int rs = (DIR == kDir2DA ? m : 1) * COLS, cs = (DIR == kDir2DA ? m : 1) * STEP;
 #pragma unroll
         for (int b = -S::BMAX; b <= S::BMAX; ++b)
 #pragma unroll
             for (int aa = -S::AMAX; aa <= S::AMAX; ++aa) {
                 if (aa == 0 && b == 0) continue;
-                const int qi = ci + b * COLS + aa * STEP;
+                const int qi = ci + b * rs + aa * cs;
                 const float qv = WANT_VAR ? s_v[qi] : 0.f;
-                const float log2h = DIR == kDir2D ? kLog2H1[aa + 2] + kLog2H1[b + 2]
-                                    : kLog2H1[(DIR == kDirH ? aa : b) + 2];
-                const float hc = DIR == kDir2D ? kH1[aa + 2] * kH1[b + 2]
-                                 : kH1[(DIR == kDirH ? aa : b) + 2];
+                const float log2h = FULL ? kLog2H1[aa + 2] + kLog2H1[b + 2]
+                                         : kLog2H1[(DIR == kDirH ? aa : b) + 2];
+                const float hc = FULL ? kH1[aa + 2] * kH1[b + 2] : kH1[(DIR == kDirH ? aa : b) + 2];
                 tap<MODE, WANT_VAR>(acc, s_cl[qi], s_gn[qi], qv, log2h, hc,
                                     MODE == kUnit ? 0.f : kz[kz_index(aa, b)], pg.x, pc.w, pg.y,
                                     pg.z, pg.w, kl, a.nc);
@@ -484,7 +511,7 @@ __global__ __launch_bounds__(256) __attribute__((
         const TileOrigin o = tile_origin<STEP, S::TY, S::TX>(t, gxt);
         // adaptive levels: a tile without a pixel of this launch's class
         // is not staged at all (uniform branch)
-        if (DIR != kDirH && a.ctl &&
+        if ((DIR == kDir2D || DIR == kDirV) && a.ctl &&
             !any_of_class(a, o.x0 + (int)(threadIdx.x & 63), o.ybase + (int)(threadIdx.x >> 6) * STEP,
                           4 * STEP, PY))
             return;
@@ -527,7 +554,7 @@ __global__ __launch_bounds__(256) __attribute__((
     const AtrousArgs a = args[s];  // a copy: the kernel's stores cannot alias it
     const int gxt = (a.w + S::TX - 1) / S::TX;
     const TileOrigin o = tile_origin<STEP, S::TY, S::TX>(lt, gxt);
-    if (DIR != kDirH && a.ctl &&
+    if ((DIR == kDir2D || DIR == kDirV) && a.ctl &&
         !any_of_class(a, o.x0 + (int)(threadIdx.x & 63), o.ybase + (int)(threadIdx.x >> 6) * STEP,
                       4 * STEP, PY))
         return;
@@ -711,11 +738,11 @@ __global__ __launch_bounds__(256) void atrous_sep_k(AtrousArgs a) {
 // 8 and 16, but 55-58 instead of 48-50 us at steps 1-4).
 constexpr int hv_rows(int step) { return step >= 8 ? 6 : 16; }
 
-template <int STEP>
+template <int STEP, int OUT_ = hv_rows(STEP)>
 struct HvShape {
     static constexpr int TX = 64, HX = 2 * STEP, COLS = TX + 2 * HX, PFC = TX + 2;
     static constexpr int IT = (COLS + 63) / 64, ITP = (3 * PFC + 63) / 64;
-    static constexpr int OUT = hv_rows(STEP), ROWS = OUT + 4;
+    static constexpr int OUT = OUT_, ROWS = OUT + 4;
     static_assert(ROWS % 10 == 0, "rows per tile must fill the five-slot ring and the two load buffers");
 };
 
@@ -810,13 +837,14 @@ struct HvSlot {
     float dzdy, kap;
 };
 
-template <typename T, int STEP, int MODE, int SLOT>
+template <typename T, int STEP, int OUT, int MODE, int SLOT>
 __device__ __forceinline__ void hv_row(const AtrousArgs &ah, const AtrousArgs &av, int x0, int ph,
                                        int j0, int ro, HvSlot (&ring)[5], float4 *s_cl,
                                        float4 *s_gn, float2 *s_pf, HvRow<STEP> &q) {
-    using S = HvShape<STEP>;
-    constexpr bool WANT_VAR = MODE >= 2;  // packed: MODE & 1 = weights, MODE & 2 = variance
-    constexpr int WM = MODE & 1;
+    using S = HvShape<STEP, OUT>;
+    // packed: MODE & 1 = weights, MODE & 2 = variance, MODE & 4 = series normal term
+    constexpr bool WANT_VAR = (MODE & 2) != 0;
+    constexpr int WM = (MODE & 1) ? ((MODE & 4) ? kWeightedSeries : kWeighted) : kUnit;
     const int lx = threadIdx.x, x = x0 + lx;
     const int r = ro + SLOT;  // row index within the tile
     const int y = ph + (j0 - 2 + r) * STEP;
@@ -948,18 +976,17 @@ __device__ __forceinline__ void hv_row(const AtrousArgs &ah, const AtrousArgs &a
 // reloads in every row).
 typedef AtrousArgs HvArgs;
 
-inline int hv_tiles(const AtrousArgs &a) {
-    const int rows = hv_rows(a.step);
+inline int hv_tiles(const AtrousArgs &a, int rows) {
     return ((a.w + 63) / 64) * a.step * ((((a.h + a.step - 1) / a.step) + rows - 1) / rows);
 }
 
 // Tile t: 64 columns x hv_rows(STEP) lattice rows of one phase (columns fastest,
 // then phases, then bands of rows).  MODE: bit 0 = edge weights on,
-// bit 1 = variance output.
-template <typename T, int STEP, int MODE>
+// bit 1 = variance output, bit 2 = the normal term as a series.
+template <typename T, int STEP, int OUT, int MODE>
 __device__ __forceinline__ void hv_tile(const HvArgs &a, int t, float4 *s_cl, float4 *s_gn,
                                         float2 *s_pf) {
-    using S = HvShape<STEP>;
+    using S = HvShape<STEP, OUT>;
     const int gxt = (a.w + 63) / 64;
     const int cx = t % gxt, rest = t / gxt;
     const int ph = rest % STEP, band = rest / STEP;
@@ -976,34 +1003,34 @@ __device__ __forceinline__ void hv_tile(const HvArgs &a, int t, float4 *s_cl, fl
     // register set
 #pragma unroll 1
     for (int ro = 0; ro < S::ROWS; ro += 10) {
-        hv_row<T, STEP, MODE, 0>(a, a, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q0);
-        hv_row<T, STEP, MODE, 1>(a, a, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q1);
-        hv_row<T, STEP, MODE, 2>(a, a, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q0);
-        hv_row<T, STEP, MODE, 3>(a, a, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q1);
-        hv_row<T, STEP, MODE, 4>(a, a, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q0);
-        hv_row<T, STEP, MODE, 5>(a, a, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q1);
-        hv_row<T, STEP, MODE, 6>(a, a, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q0);
-        hv_row<T, STEP, MODE, 7>(a, a, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q1);
-        hv_row<T, STEP, MODE, 8>(a, a, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q0);
-        hv_row<T, STEP, MODE, 9>(a, a, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q1);
+        hv_row<T, STEP, OUT, MODE, 0>(a, a, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q0);
+        hv_row<T, STEP, OUT, MODE, 1>(a, a, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q1);
+        hv_row<T, STEP, OUT, MODE, 2>(a, a, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q0);
+        hv_row<T, STEP, OUT, MODE, 3>(a, a, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q1);
+        hv_row<T, STEP, OUT, MODE, 4>(a, a, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q0);
+        hv_row<T, STEP, OUT, MODE, 5>(a, a, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q1);
+        hv_row<T, STEP, OUT, MODE, 6>(a, a, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q0);
+        hv_row<T, STEP, OUT, MODE, 7>(a, a, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q1);
+        hv_row<T, STEP, OUT, MODE, 8>(a, a, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q0);
+        hv_row<T, STEP, OUT, MODE, 9>(a, a, x0, ph, j0, ro, ring, s_cl, s_gn, s_pf, q1);
     }
 }
 
-template <typename T, int STEP, int MODE>
+template <typename T, int STEP, int OUT, int MODE>
 __global__ __launch_bounds__(64) void atrous_hv_k(HvArgs a, int tiles) {
-    using S = HvShape<STEP>;
+    using S = HvShape<STEP, OUT>;
     __shared__ float4 s_cl[S::COLS];
     __shared__ float4 s_gn[S::COLS];
     __shared__ float2 s_pf[3 * S::PFC];
     const int t = xcd_tile(tiles);
     if (t < 0) return;
-    hv_tile<T, STEP, MODE>(a, t, s_cl, s_gn, s_pf);
+    hv_tile<T, STEP, OUT, MODE>(a, t, s_cl, s_gn, s_pf);
 }
 
-template <typename T, int STEP, int MODE>
+template <typename T, int STEP, int OUT, int MODE>
 __global__ __launch_bounds__(64) void atrous_hv_batch_k(const HvArgs *args, const int *prefix,
                                                         int n, int total) {
-    using S = HvShape<STEP>;
+    using S = HvShape<STEP, OUT>;
     __shared__ float4 s_cl[S::COLS];
     __shared__ float4 s_gn[S::COLS];
     __shared__ float2 s_pf[3 * S::PFC];
@@ -1011,45 +1038,54 @@ __global__ __launch_bounds__(64) void atrous_hv_batch_k(const HvArgs *args, cons
     const int lt = batch_tile(prefix, n, total, s);
     if (lt < 0) return;
     const HvArgs a = args[s];
-    hv_tile<T, STEP, MODE>(a, lt, s_cl, s_gn, s_pf);
+    hv_tile<T, STEP, OUT, MODE>(a, lt, s_cl, s_gn, s_pf);
 }
 
-template <typename T, int STEP, int MODE>
+template <typename T, int STEP, int OUT, int MODE>
 void hv_batch_launch(const void *args, const int *prefix, int n, int total, hipStream_t s) {
-    hipLaunchKernelGGL((atrous_hv_batch_k<T, STEP, MODE>), dim3(xcd_grid(total)), dim3(64), 0, s,
-                       (const HvArgs *)args, prefix, n, total);
+    hipLaunchKernelGGL((atrous_hv_batch_k<T, STEP, OUT, MODE>), dim3(xcd_grid(total)), dim3(64),
+                       0, s, (const HvArgs *)args, prefix, n, total);
 }
 
-template <typename T, int STEP, int MODE>
+template <typename T, int STEP, int OUT, int MODE>
 void launch_hv_mode(const HvArgs &a, hipStream_t s) {
-    const int tiles = hv_tiles(a);
-    if (record_pass(&hv_batch_launch<T, STEP, MODE>, a, tiles)) return;
-    hipLaunchKernelGGL((atrous_hv_k<T, STEP, MODE>), dim3(xcd_grid(tiles)), dim3(64), 0, s, a,
-                       tiles);
+    const int tiles = hv_tiles(a, OUT);
+    if (record_pass(&hv_batch_launch<T, STEP, OUT, MODE>, a, tiles)) return;
+    hipLaunchKernelGGL((atrous_hv_k<T, STEP, OUT, MODE>), dim3(xcd_grid(tiles)), dim3(64), 0, s,
+                       a, tiles);
 }
 
-template <typename T, int STEP>
-void launch_hv_step(const HvArgs &a, int mode, hipStream_t s) {
+template <typename T, int STEP, int OUT>
+void launch_hv_rows(const HvArgs &a, int mode, hipStream_t s) {
     switch (mode) {
-    case 0: launch_hv_mode<T, STEP, 0>(a, s); return;
-    case 1: launch_hv_mode<T, STEP, 1>(a, s); return;
-    case 2: launch_hv_mode<T, STEP, 2>(a, s); return;
-    default: launch_hv_mode<T, STEP, 3>(a, s); return;
+    case 0: launch_hv_mode<T, STEP, OUT, 0>(a, s); return;
+    case 1: launch_hv_mode<T, STEP, OUT, 1>(a, s); return;
+    case 2: launch_hv_mode<T, STEP, OUT, 2>(a, s); return;
+    case 3: launch_hv_mode<T, STEP, OUT, 3>(a, s); return;
+    case 5: launch_hv_mode<T, STEP, OUT, 5>(a, s); return;
+    default: launch_hv_mode<T, STEP, OUT, 7>(a, s); return;
     }
 }
 
+template <typename T, int STEP>
+void launch_hv_step(const HvArgs &a, int mode, int rows, hipStream_t s) {
+    if ((rows == 0 ? hv_rows(STEP) : rows) == 6) launch_hv_rows<T, STEP, 6>(a, mode, s);
+    else launch_hv_rows<T, STEP, 16>(a, mode, s);
+}
+
 // Fused separable level; false when the step has no fused form (then the
-// two passes run through a scratch buffer).
+// two passes run through a scratch buffer).  rows: output rows per wave,
+// 6 or 16 (0: hv_rows(step)).
 template <typename T>
-bool launch_hv(const HvArgs &a, bool unit, hipStream_t s) {
-    const int mode = (unit ? 0 : 1) | (a.var_out ? 2 : 0);
+bool launch_hv(const HvArgs &a, bool unit, int rows, hipStream_t s) {
+    const int mode = (unit ? 0 : (a.nc.series ? 5 : 1)) | (a.var_out ? 2 : 0);
     switch (a.step) {
-    case 1: launch_hv_step<T, 1>(a, mode, s); return true;
-    case 2: launch_hv_step<T, 2>(a, mode, s); return true;
-    case 4: launch_hv_step<T, 4>(a, mode, s); return true;
-    case 8: launch_hv_step<T, 8>(a, mode, s); return true;
-    case 16: launch_hv_step<T, 16>(a, mode, s); return true;
-    case 32: launch_hv_step<T, 32>(a, mode, s); return true;
+    case 1: launch_hv_step<T, 1>(a, mode, rows, s); return true;
+    case 2: launch_hv_step<T, 2>(a, mode, rows, s); return true;
+    case 4: launch_hv_step<T, 4>(a, mode, rows, s); return true;
+    case 8: launch_hv_step<T, 8>(a, mode, rows, s); return true;
+    case 16: launch_hv_step<T, 16>(a, mode, rows, s); return true;
+    case 32: launch_hv_step<T, 32>(a, mode, rows, s); return true;
     default: return false;
     }
 }
@@ -1057,46 +1093,78 @@ bool launch_hv(const HvArgs &a, bool unit, hipStream_t s) {
 // ---- launch ---------------------------------------------------------------------
 
 // Launch-time tile configuration (autotuned by the caller, or the defaults).
+// rows: lattice rows per thread of the 5x5 level's tile, 1 or 2 (0: tile_py).
 struct TileCfg {
     bool persistent;
     int blocks_per_cu;
+    int rows;
 };
 
-template <typename T, int STEP, int MODE, bool WANT_VAR, int DIR>
-void launch_tile(const AtrousArgs &a, TileCfg cfg, hipStream_t s) {
-    constexpr int PY = tile_py(STEP), TY = 4 * PY;
+template <typename T, int STEP, int PY, int MODE, bool WANT_VAR, int DIR>
+void launch_tile_py(const AtrousArgs &a, TileCfg cfg, hipStream_t s) {
+    constexpr int TY = 4 * PY;
     const int bands = (a.h + STEP * TY - 1) / (STEP * TY);
     const int tiles = ((a.w + 63) / 64) * bands * STEP;
     const int per_xcd = (tiles + kXCD - 1) / kXCD;
     if (record_pass(&atrous_batch_launch<T, STEP, PY, MODE, WANT_VAR, DIR>, a, tiles)) return;
-    if (cfg.persistent) {
-        const int slots = min(per_xcd, kCUs / kXCD * max(1, cfg.blocks_per_cu));
-        hipLaunchKernelGGL((atrous_tile_k<T, STEP, PY, MODE, WANT_VAR, DIR, true>),
-                           dim3(slots * kXCD), dim3(256), 0, s, a, tiles, per_xcd);
+    // the adaptive level's wider tile leaves no registers for a prefetched
+    // next tile: it always runs one tile per workgroup
+    if constexpr (DIR != kDir2DA) {
+        if (cfg.persistent) {
+            const int slots = min(per_xcd, kCUs / kXCD * max(1, cfg.blocks_per_cu));
+            hipLaunchKernelGGL((atrous_tile_k<T, STEP, PY, MODE, WANT_VAR, DIR, true>),
+                               dim3(slots * kXCD), dim3(256), 0, s, a, tiles, per_xcd);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((atrous_tile_k<T, STEP, PY, MODE, WANT_VAR, DIR, false>),
+                       dim3(per_xcd * kXCD), dim3(256), 0, s, a, tiles, per_xcd);
+}
+
+// The tile height: the caller's choice for 5x5 levels up to step 16 (at 32
+// two lattice rows per thread would need more LDS than a workgroup has),
+// tile_py otherwise.
+template <typename T, int STEP, int MODE, bool WANT_VAR, int DIR>
+void launch_tile(const AtrousArgs &a, TileCfg cfg, hipStream_t s) {
+    if constexpr (DIR == kDir2DA) {  // two rows per thread (measured best at every step)
+        launch_tile_py<T, STEP, 2, MODE, WANT_VAR, DIR>(a, cfg, s);
     } else {
-        hipLaunchKernelGGL((atrous_tile_k<T, STEP, PY, MODE, WANT_VAR, DIR, false>),
-                           dim3(per_xcd * kXCD), dim3(256), 0, s, a, tiles, per_xcd);
+        const int py = (DIR == kDir2D && STEP <= 16 && cfg.rows > 0) ? cfg.rows : tile_py(STEP);
+        if (py == 1) launch_tile_py<T, STEP, 1, MODE, WANT_VAR, DIR>(a, cfg, s);
+        else launch_tile_py<T, STEP, (STEP <= 16 ? 2 : 1), MODE, WANT_VAR, DIR>(a, cfg, s);
     }
 }
 
 template <typename T, int MODE, bool WANT_VAR, int DIR>
 void launch_steps(const AtrousArgs &a, TileCfg cfg, hipStream_t s) {
-    switch (a.step) {
-    case 1: launch_tile<T, 1, MODE, WANT_VAR, DIR>(a, cfg, s); return;
-    case 2: launch_tile<T, 2, MODE, WANT_VAR, DIR>(a, cfg, s); return;
-    case 4: launch_tile<T, 4, MODE, WANT_VAR, DIR>(a, cfg, s); return;
-    case 8: launch_tile<T, 8, MODE, WANT_VAR, DIR>(a, cfg, s); return;
-    case 16: launch_tile<T, 16, MODE, WANT_VAR, DIR>(a, cfg, s); return;
-    case 32: launch_tile<T, 32, MODE, WANT_VAR, DIR>(a, cfg, s); return;
-    default: {  // other steps: direct loads (not available batched)
-        if (record_pass<AtrousArgs>(nullptr, a, 0)) return;
-        dim3 grid((a.w + 63) / 64, (a.h + 3) / 4);
-        if (DIR == kDir2D)
-            hipLaunchKernelGGL((atrous_direct_k<T, MODE, WANT_VAR>), grid, dim3(256), 0, s, a);
-        else
-            hipLaunchKernelGGL((atrous_sep_k<T, MODE, DIR == kDirV, WANT_VAR>), grid, dim3(256), 0,
-                               s, a);
-    }
+    if constexpr (DIR == kDir2DA) {  // steps up to kMaxStep2DA
+        switch (a.step) {
+        case 1: launch_tile<T, 1, MODE, WANT_VAR, DIR>(a, cfg, s); return;
+        case 2: launch_tile<T, 2, MODE, WANT_VAR, DIR>(a, cfg, s); return;
+        case 4: launch_tile<T, 4, MODE, WANT_VAR, DIR>(a, cfg, s); return;
+        case 8:
+            if constexpr (kMaxStep2DA >= 8) launch_tile<T, 8, MODE, WANT_VAR, DIR>(a, cfg, s);
+            return;
+        default: return;
+        }
+    } else {
+        switch (a.step) {
+        case 1: launch_tile<T, 1, MODE, WANT_VAR, DIR>(a, cfg, s); return;
+        case 2: launch_tile<T, 2, MODE, WANT_VAR, DIR>(a, cfg, s); return;
+        case 4: launch_tile<T, 4, MODE, WANT_VAR, DIR>(a, cfg, s); return;
+        case 8: launch_tile<T, 8, MODE, WANT_VAR, DIR>(a, cfg, s); return;
+        case 16: launch_tile<T, 16, MODE, WANT_VAR, DIR>(a, cfg, s); return;
+        case 32: launch_tile<T, 32, MODE, WANT_VAR, DIR>(a, cfg, s); return;
+        default: {  // other steps: direct loads (not available batched)
+            if (record_pass<AtrousArgs>(nullptr, a, 0)) return;
+            dim3 grid((a.w + 63) / 64, (a.h + 3) / 4);
+            if (DIR == kDir2D)
+                hipLaunchKernelGGL((atrous_direct_k<T, MODE, WANT_VAR>), grid, dim3(256), 0, s, a);
+            else
+                hipLaunchKernelGGL((atrous_sep_k<T, MODE, DIR == kDirV, WANT_VAR>), grid,
+                                   dim3(256), 0, s, a);
+        }
+        }
     }
 }
 
@@ -1108,8 +1176,13 @@ void launch_pass(const AtrousArgs &a, bool unit, TileCfg cfg, hipStream_t s) {
         if (wv) launch_steps<T, kUnit, true, DIR>(a, cfg, s);
         else launch_steps<T, kUnit, false, DIR>(a, cfg, s);
     } else {
-        if (wv) launch_steps<T, kWeighted, true, DIR>(a, cfg, s);
-        else launch_steps<T, kWeighted, false, DIR>(a, cfg, s);
+        if (a.nc.series) {
+            if (wv) launch_steps<T, kWeightedSeries, true, DIR>(a, cfg, s);
+            else launch_steps<T, kWeightedSeries, false, DIR>(a, cfg, s);
+        } else {
+            if (wv) launch_steps<T, kWeighted, true, DIR>(a, cfg, s);
+            else launch_steps<T, kWeighted, false, DIR>(a, cfg, s);
+        }
     }
 }
 
@@ -1120,7 +1193,9 @@ void launch_pass_f32_v(const AtrousArgs &a, bool unit, TileCfg cfg, hipStream_t 
 void launch_pass_f16_2d(const AtrousArgs &a, bool unit, TileCfg cfg, hipStream_t s);
 void launch_pass_f16_h(const AtrousArgs &a, bool unit, TileCfg cfg, hipStream_t s);
 void launch_pass_f16_v(const AtrousArgs &a, bool unit, TileCfg cfg, hipStream_t s);
-bool launch_hv_f32(const HvArgs &a, bool unit, hipStream_t s);
-bool launch_hv_f16(const HvArgs &a, bool unit, hipStream_t s);
+void launch_pass_f32_2da(const AtrousArgs &a, bool unit, TileCfg cfg, hipStream_t s);
+void launch_pass_f16_2da(const AtrousArgs &a, bool unit, TileCfg cfg, hipStream_t s);
+bool launch_hv_f32(const HvArgs &a, bool unit, int rows, hipStream_t s);
+bool launch_hv_f16(const HvArgs &a, bool unit, int rows, hipStream_t s);
 
 }  // namespace sv

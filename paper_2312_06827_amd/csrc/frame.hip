@@ -59,6 +59,7 @@ extern "C" int sv_denoise_frame(const sv_frame_in *in, sv_denoiser *st, sv_dims 
         ap.flags &= ~SV_A_INV_TONEMAP;
         if (p->level_persistent[i] >= 0) ap.persistent = p->level_persistent[i];
         if (p->level_blocks_per_cu[i] > 0) ap.blocks_per_cu = p->level_blocks_per_cu[i];
+        if (p->level_tile_rows[i] > 0) ap.tile_rows = p->level_tile_rows[i];
         if (tm && last && !level0_is_hist) ap.flags |= SV_A_INV_TONEMAP;
         const sv_rgb dst = level0_is_hist ? st->hist[k1] : (last ? st->out : st->level[i & 1]);
         float *dst_var = last ? nullptr : st->level_var[i & 1];

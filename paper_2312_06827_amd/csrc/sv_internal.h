@@ -108,17 +108,46 @@ struct NormalCoef {
     float sn;    // sigma_n
     float snl;   // sigma_n log2(e)
     float umin;  // 0, or 1 when sigma_n == 0
+    int series;  // sigma_n >= kSeriesMinSigmaN: the a-trous levels use the series form
 };
-
-inline NormalCoef make_normal_coef(float sigma_n) {
-    return NormalCoef{sigma_n, sigma_n * 1.4426950408889634f, sigma_n == 0.0f ? 1.0f : 0.0f};
-}
 
 __device__ __forceinline__ float add_normal_term(float e, float s2, const NormalCoef &k) {
     const float u = fmaf(-0.5f, s2, 1.0f);
     const float r = fmaf(-0.5f, s2, 1.0f - u);  // (1 - s2/2) - u, exact for u >= 1/2
     e = fmaf(k.sn, __builtin_amdgcn_logf(fmaxf(u, k.umin)), e);
     return fmaf(k.snl, r, e);
+}
+
+// From this sigma_n on, the a-trous levels take the normal term as a
+// truncated series (add_normal_series), with no logarithm.
+constexpr float kSeriesMinSigmaN = 96.0f;
+
+inline NormalCoef make_normal_coef(float sigma_n) {
+    return NormalCoef{sigma_n, sigma_n * 1.4426950408889634f, sigma_n == 0.0f ? 1.0f : 0.0f,
+                      sigma_n >= kSeriesMinSigmaN ? 1 : 0};
+}
+
+// The same term for large sigma_n without the logarithm.  With x = s2/2,
+// log2(1 - x) = -log2(e) (x + x^2/2 + ... + x^6/6 + R), taken through x^6/6
+// and evaluated by Horner in s2 (x^k/k = s2^k / (k 2^k)):
+//   sigma_n log2(1 - s2/2) ~ sigma_n s2 P(s2),  P(s2) = -log2(e) sum_k s2^(k-1) / (k 2^k).
+// The remainder R <= x^7 / (7 (1 - x)) is dropped; sigma_n R is the relative
+// error it leaves in the weight.  At sigma_n = 128 that stays below the
+// binary32 evaluation's own error (about 1e-6 relative) for every weight
+// above 1e-3 of the centre's and below 4e-6 for weights above 1e-6 (at 96:
+// 1.4e-6 and 1.5e-5), comparable to the log form's 5e-7 and 1.1e-6.  Where
+// x is large the series gives an exponentially small weight, as the exact
+// one is (or zero: for x >= 1 the exact weight is 0 and the series' exp2
+// underflows), so no clamp is needed; and no 1 - s2/2 is rounded, so no
+// residual term either.
+__device__ __forceinline__ float add_normal_series(float e, float s2, const NormalCoef &k) {
+    constexpr float L = 1.4426950408889634f;
+    float p = fmaf(s2, -L / 384.0f, -L / 160.0f);  // 1/(6 2^6), 1/(5 2^5)
+    p = fmaf(p, s2, -L / 64.0f);
+    p = fmaf(p, s2, -L / 24.0f);
+    p = fmaf(p, s2, -L / 8.0f);
+    p = fmaf(p, s2, -L / 2.0f);
+    return fmaf(p * s2, k.sn, e);
 }
 
 // The depth difference p's gradient (gx, gy) predicts over an offset

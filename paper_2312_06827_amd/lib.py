@@ -79,7 +79,7 @@ class sv_atrous_params(ctypes.Structure):
                 ("sigma_l", ctypes.c_float), ("eps_z", ctypes.c_float),
                 ("eps_l", ctypes.c_float), ("tm_k", ctypes.c_float),
                 ("flags", ctypes.c_int32), ("persistent", ctypes.c_int32),
-                ("blocks_per_cu", ctypes.c_int32)]
+                ("blocks_per_cu", ctypes.c_int32), ("tile_rows", ctypes.c_int32)]
 
 
 class sv_denoiser(ctypes.Structure):
@@ -112,7 +112,8 @@ class sv_frame_params(ctypes.Structure):
                 ("atrous", sv_atrous_params), ("levels", ctypes.c_int32),
                 ("separable", ctypes.c_int32), ("feedback", ctypes.c_int32),
                 ("level_persistent", ctypes.c_int32 * 10),
-                ("level_blocks_per_cu", ctypes.c_int32 * 10)]
+                ("level_blocks_per_cu", ctypes.c_int32 * 10),
+                ("level_tile_rows", ctypes.c_int32 * 10)]
 
 
 _P = ctypes.POINTER
@@ -331,13 +332,14 @@ class AtrousParams:
     inv_tonemap: bool = False
     persistent: int = -1      # launch shape: -1 default, 0 / 1
     blocks_per_cu: int = 0    # persistent workgroups per CU, 0 default
+    tile_rows: int = 0        # LDS tile height (5x5: 1 / 2; separable: 6 / 16), 0 default
 
     def c(self) -> sv_atrous_params:
         flags = ((SV_A_UNIT_WEIGHTS if self.unit_weights else 0)
                  | (SV_A_INV_TONEMAP if self.inv_tonemap else 0))
         return sv_atrous_params(self.sigma_z, self.sigma_n, self.sigma_l, self.eps_z,
                                 self.eps_l, self.tm_k, flags, self.persistent,
-                                self.blocks_per_cu)
+                                self.blocks_per_cu, self.tile_rows)
 
 
 # ---- the calls ------------------------------------------------------------------

@@ -64,16 +64,20 @@ class FilterConfig:
                             self.tm_k, False, inv_tonemap)
 
     def frame_params(self, tiles=None) -> lib.sv_frame_params:
-        """`tiles`: optional per-level (persistent, blocks_per_cu) launch shapes."""
+        """`tiles`: optional per-level launch shapes (persistent,
+        blocks_per_cu[, tile_rows]), as the autotuner chooses them."""
         if self.feedback not in ("atrous0", "temporal"):
             raise ValueError(f"unknown feedback {self.feedback!r}")
         lp = (ctypes.c_int32 * 10)(*([-1] * 10))
         lb = (ctypes.c_int32 * 10)(*([0] * 10))
-        for i, (per, bpc) in enumerate((tiles or [])[:10]):
-            lp[i], lb[i] = per, bpc
+        lr = (ctypes.c_int32 * 10)(*([0] * 10))
+        for i, shape in enumerate((tiles or [])[:10]):
+            lp[i], lb[i] = shape[0], shape[1]
+            if len(shape) > 2:
+                lr[i] = shape[2]
         return lib.sv_frame_params(self.temporal().c(), self.variance().c(), self.atrous().c(),
                                    self.levels, int(self.separable),
-                                   1 if self.feedback == "temporal" else 0, lp, lb)
+                                   1 if self.feedback == "temporal" else 0, lp, lb, lr)
 
 
 # The filter settings of the workloads: plain (static camera) and the

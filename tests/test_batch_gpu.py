@@ -23,17 +23,22 @@ def _streams(half, frames):
     return [with_size(c, w, h, frames) for c, (h, w) in zip(base, SIZES)]
 
 
-@pytest.mark.parametrize("half,sep,levels,feedback", [
-    (False, False, 5, "atrous0"), (True, False, 5, "atrous0"), (True, True, 5, "atrous0"),
-    (False, True, 3, "temporal"), (False, False, 1, "temporal")])
-def test_batch_equals_single_streams(half, sep, levels, feedback):
+@pytest.mark.parametrize("half,sep,levels,feedback,rows", [
+    (False, False, 5, "atrous0", 0), (True, False, 5, "atrous0", 0), (True, True, 5, "atrous0", 0),
+    (False, True, 3, "temporal", 0), (False, False, 1, "temporal", 0),
+    (True, False, 5, "atrous0", 1), (False, True, 5, "atrous0", 6)])
+def test_batch_equals_single_streams(half, sep, levels, feedback, rows):
+    """rows: tile height of every level (0: the library default), as the
+    autotuner passes it, in the batched launches and the single ones."""
     dt = torch.float16 if half else torch.float32
     cfg = replace(MOTION_SEP if sep else MOTION, levels=levels, feedback=feedback)
     frames = 5
     scfg = _streams(half, frames)
-    say(f"batch: {len(SIZES)} streams half={half} sep={sep} levels={levels} feedback={feedback}")
-    batch = BatchDenoiser(SIZES, cfg, dt)
-    singles = [Denoiser(h, w, cfg, dt) for (h, w) in SIZES]
+    tiles = [(0, 0, rows)] * levels if rows else None
+    say(f"batch: {len(SIZES)} streams half={half} sep={sep} levels={levels} feedback={feedback}"
+        f" rows={rows}")
+    batch = BatchDenoiser(SIZES, cfg, dt, tiles=tiles)
+    singles = [Denoiser(h, w, cfg, dt, tiles=tiles) for (h, w) in SIZES]
     try:
         for f in range(frames):
             inputs = [FrameInputs.from_numpy(render_frame(c, f)) for c in scfg]
@@ -163,6 +168,8 @@ def test_batch_with_adaptive_levels_and_per_stream_settings(sep):
             for i in range(len(SIZES)):
                 assert torch.equal(outs[i], refs[i]), (f, i)
             say(f"  frame {f}: bitwise equal; {batch.passes()} launches per frame")
-        assert batch.passes() == 3 + 2 * 5  # two launches per adaptive level
+        # the 5x5 adaptive levels at steps 1 to 8 are one launch each, the one
+        # at step 16 and the separable ones two (one per step class)
+        assert batch.passes() == 3 + (2 * 5 if sep else 4 + 2)
     finally:
         batch.close()

@@ -357,8 +357,10 @@ def test_atrous_signed_zero_variance(step):
     assert rel_err(host(vo), rv) <= TOL32
 
 
-@pytest.mark.parametrize("step", [1, 4, 16])
+@pytest.mark.parametrize("step", [1, 3, 4, 16])
 def test_atrous_kappa_and_params(step):
+    """sigma_n from 64 up takes the normal term as a series (no logarithm),
+    below 64 in log form: both, at tile steps and a direct-load step."""
     H, W = 90, 150
     c, var, z, dzdx, dzdy, n = _atrous_inputs(H, W, 500 + step)
     kappa = np.random.default_rng(5).uniform(0.25, 4.0, (H, W)).astype(np.float32)
@@ -402,20 +404,27 @@ def test_atrous_sep(H, W, step):
 
 @pytest.mark.parametrize("sep", [False, True])
 def test_atrous_launch_shape_does_not_change_results(sep):
-    """Persistent or not, any workgroups per CU: bitwise identical output."""
-    from paper_2312_06827_amd.autotune import CANDIDATES
+    """Every launch shape the autotuner chooses from (persistent or not, any
+    workgroups per CU, either tile height; for the separable level the
+    two-pass form and both band heights of the fused one): bitwise
+    identical output."""
+    from paper_2312_06827_amd.autotune import CANDIDATES, SEP_CANDIDATES
     H, W = 300, 450
     c, var, z, dzdx, dzdy, n = _atrous_inputs(H, W, 700)
     g = gbuf_dev(z, dzdx, dzdy, n)
     cd, vd = dev(c), dev(var)
-    for step in (1, 2, 16):
+    cands = [(per, bpc, 0, True) for per, bpc, _ in CANDIDATES[:6]] + \
+        [(per, bpc, rows, False) for per, bpc, rows in SEP_CANDIDATES] if sep else \
+        [(per, bpc, rows, False) for per, bpc, rows in CANDIDATES]
+    for step in (1, 2, 8, 16):
         ref = None
-        for per, bpc in CANDIDATES:
-            say(f"launch shape sep={sep} step={step} persistent={per} bpc={bpc}")
+        for per, bpc, rows, two_pass in cands:
+            say(f"launch shape sep={sep} step={step} persistent={per} bpc={bpc} rows={rows}"
+                f" two_pass={two_pass}")
             out, vo, sh = empty_like_dev((3, H, W)), empty_like_dev((H, W)), empty_like_dev((3, H, W))
-            p = L.AtrousParams(persistent=per, blocks_per_cu=bpc)
+            p = L.AtrousParams(persistent=per, blocks_per_cu=bpc, tile_rows=rows)
             if sep:
-                L.sv_atrous_sep(cd, vd, g, sh, out, vo, step, p)
+                L.sv_atrous_sep(cd, vd, g, sh if two_pass else None, out, vo, step, p)
             else:
                 L.sv_atrous(cd, vd, g, out, vo, step, p)
             got = (host(out), host(vo))
@@ -440,11 +449,14 @@ def test_atrous_sep_fused_equals_two_pass(H, W, dtype):
     g = L.GBuf(dv(z), dv(dzdx), dv(dzdy), dv(n))
     kappa = np.random.default_rng(H).uniform(0.5, 2.0, (H, W)).astype(np.float32)
     for step in (1, 2, 4, 8, 16, 32):
-        for unit, want_var, inv, kap in [(False, True, False, None), (False, False, True, kappa),
-                                         (True, True, False, None), (False, True, False, kappa)]:
+        for unit, want_var, inv, kap, sn in [(False, True, False, None, 128.0),
+                                             (False, False, True, kappa, 128.0),
+                                             (True, True, False, None, 128.0),
+                                             (False, True, False, kappa, 128.0),
+                                             (False, True, False, None, 16.0)]:
             say(f"sep fused {H}x{W} {dtype} step={step} unit={unit} var={want_var} inv={inv} "
-                f"kappa={kap is not None}")
-            p = L.AtrousParams(unit_weights=unit, inv_tonemap=inv)
+                f"kappa={kap is not None} sigma_n={sn}")
+            p = L.AtrousParams(unit_weights=unit, inv_tonemap=inv, sigma_n=sn)
             kd = None if kap is None else dev(kap, P)
             res = []
             for fused in (False, True):
