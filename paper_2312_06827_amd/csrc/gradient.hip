@@ -8,7 +8,8 @@
 // Passes (one stream, graph-capturable: the key clear is a kernel):
 //   grad_clear_k    cell keys := none
 //   grad_project_k  per stratum: land the sample, atomicMin of its index
-//                   on the cell's key (the lowest stratum index wins)
+//                   (high word) and its pixel (low word) on the cell's
+//                   64-bit key: the lowest stratum index wins
 //   grad_gather_k   per cell: the winning sample's luminance difference and
 //                   maximum, and a presence flag
 //   grad_atrous_k   `levels` 5x5 B3 a-trous passes over the cells with a
@@ -38,18 +39,18 @@ struct GradArgs {
     const uint8_t *pick;                      // cells: CH x CW, contiguous
     const void *z, *dzdx, *dzdy;              // current G-buffer
     float *alpha_map, *lambda;
-    uint32_t *key;
+    unsigned long long *key;                  // (stratum << 32) | sample pixel
     float4 *ca, *cb;                          // cell ping-pong
     float4 *cz;                               // cells' centre pixel: z, dz/dx, dz/dy
     int w, h, pitch, cw, ch;
     float alpha, tau_z, sigma_z;
 };
 
-constexpr uint32_t kNone = 0xFFFFFFFFu;
+constexpr unsigned long long kNone = ~0ull;
 
 __device__ __forceinline__ int cells_x(int w) { return (w + 2) / 3; }
 
-__global__ __launch_bounds__(256) void grad_clear_k(uint32_t *key, int n) {
+__global__ __launch_bounds__(256) void grad_clear_k(unsigned long long *key, int n) {
     const int i = (int)blockIdx.x * 256 + (int)threadIdx.x;
     if (i < n) key[i] = kNone;
 }
@@ -81,7 +82,10 @@ __global__ __launch_bounds__(256) void grad_project_k(GradArgs a) {
     const int s = (int)blockIdx.x * 256 + (int)threadIdx.x;
     if (s >= a.cw * a.ch) return;
     int qx, qy, cell;
-    if (land<T>(a, s, qx, qy, cell)) atomicMin(&a.key[cell], (uint32_t)s);
+    if (land<T>(a, s, qx, qy, cell)) {
+        const uint32_t q = (uint32_t)qy * (uint32_t)a.pitch + (uint32_t)qx;
+        atomicMin(&a.key[cell], ((unsigned long long)(uint32_t)s << 32) | q);
+    }
 }
 
 template <typename T>
@@ -94,12 +98,10 @@ __global__ __launch_bounds__(256) void grad_gather_k(GradArgs a) {
                            (uint32_t)min(3 * cx + 1, a.w - 1);
         a.cz[c] = make_float4(ldo<T>(a.z, o), ldo<T>(a.dzdx, o), ldo<T>(a.dzdy, o), 0.f);
     }
-    const uint32_t s = a.key[c];
+    const unsigned long long key = a.key[c];
     float4 v = make_float4(0.f, 0.f, -INFINITY, 0.f);  // (d, m, l): no sample
-    if (s != kNone) {
-        const int sy = (int)s / a.cw, sx = (int)s - sy * a.cw;
-        const int k = a.pick[s];
-        const uint32_t q = (uint32_t)(3 * sy + k / 3) * (uint32_t)a.pitch + (uint32_t)(3 * sx + k % 3);
+    if (key != kNone) {
+        const uint32_t q = (uint32_t)key;  // the winner's pixel
         const float lp = luma(ldo<T>(a.pr, q), ldo<T>(a.pg, q), ldo<T>(a.pb, q));
         const float lr = luma(ldo<T>(a.rr, q), ldo<T>(a.rg, q), ldo<T>(a.rb, q));
         v = make_float4(lr - lp, fmaxf(lr, lp), 0.f, 0.f);  // one sample of weight 1
@@ -157,6 +159,135 @@ __global__ __launch_bounds__(256) void grad_atrous_k(GradArgs a, const float4 *s
     dst[c] = out;
 }
 
+// ---- the cascade in LDS tiles ------------------------------------------------
+//
+// A level at cell step STEP as tiles of 64 consecutive cell columns by 4
+// lattice rows of one phase (cell rows cy0 + j STEP), one cell per thread.
+// The taps of those cells lie in the tile's own lattice rows (two above and
+// below) and columns (2 STEP left and right), staged once in LDS: the cell
+// (d, m, l) and the depth of its centre pixel.  The first level computes
+// its cells from the projected samples while staging (the gather), the
+// last writes the blend factor of each cell's 3 x 3 pixels (and lambda).
+// Every tap is the same arithmetic as grad_atrous_k's, with the hardware
+// exp2, log2 and reciprocal (each within an ulp; the weights are relative to
+// the largest, whose exp2 is exactly 1).
+constexpr int kGTX = 64, kGTY = 4;
+
+// The cell (d, m, l) of cell c from its winning sample: one sample of
+// weight 1 (l = 0), or none (l = -inf).
+template <typename T>
+__device__ __forceinline__ float4 cell_sample(const GradArgs &a, int c) {
+    const unsigned long long key = a.key[c];
+    if (key == kNone) return make_float4(0.f, 0.f, -INFINITY, 0.f);
+    const uint32_t q = (uint32_t)key;  // the winner's pixel
+    const float lp = luma(ldo<T>(a.pr, q), ldo<T>(a.pg, q), ldo<T>(a.pb, q));
+    const float lr = luma(ldo<T>(a.rr, q), ldo<T>(a.rg, q), ldo<T>(a.rb, q));
+    return make_float4(lr - lp, fmaxf(lr, lp), 0.f, 0.f);
+}
+
+// Offset of the centre pixel of cell (cx, cy).
+__device__ __forceinline__ uint32_t cell_centre(const GradArgs &a, int cx, int cy) {
+    return (uint32_t)min(3 * cy + 1, a.h - 1) * (uint32_t)a.pitch + (uint32_t)min(3 * cx + 1, a.w - 1);
+}
+
+template <typename T, int STEP>
+__global__ __launch_bounds__(256) void grad_level_k(GradArgs a, const float4 *src, float4 *dst,
+                                                    int first, int last) {
+    constexpr int HX = 2 * STEP, COLS = kGTX + 2 * HX, ROWS = kGTY + 4, NS = ROWS * COLS;
+    __shared__ float4 s_c[NS];  // (d, m, l)
+    __shared__ float s_z[NS];   // depth of the cell's centre pixel
+    const int gxt = (a.cw + kGTX - 1) / kGTX;
+    const int t = xcd_tile(gxt * STEP * ((a.ch + STEP * kGTY - 1) / (STEP * kGTY)));
+    if (t < 0) return;
+    const int tyt = t / gxt, band = tyt / STEP, phase = tyt - band * STEP;
+    const int cx0 = (t - tyt * gxt) * kGTX, cy0 = band * STEP * kGTY + phase;
+    for (int i = (int)threadIdx.x; i < NS; i += 256) {
+        const int r = i / COLS, col = i - r * COLS;
+        const int cx = cx0 - HX + col, cy = cy0 + (r - 2) * STEP;
+        float4 v = make_float4(0.f, 0.f, -INFINITY, 0.f);
+        float zq = 0.f;
+        if (cx >= 0 && cx < a.cw && cy >= 0 && cy < a.ch) {
+            const int c = cy * a.cw + cx;
+            v = first ? cell_sample<T>(a, c) : src[c];
+            zq = ldo<T>(a.z, cell_centre(a, cx, cy));
+        }
+        s_c[i] = v;
+        s_z[i] = zq;
+    }
+    __syncthreads();
+    const int lx = (int)(threadIdx.x & 63), ly = (int)(threadIdx.x >> 6);
+    const int cx = cx0 + lx, cy = cy0 + ly * STEP;
+    if (cx >= a.cw || cy >= a.ch) return;
+    const int ci = (ly + 2) * COLS + HX + lx;
+    const uint32_t o = cell_centre(a, cx, cy);
+    const float zc = s_z[ci], gx = ldo<T>(a.dzdx, o), gy = ldo<T>(a.dzdy, o);
+    float e[25];
+    float top = -INFINITY;
+#pragma unroll
+    for (int b = -2; b <= 2; ++b)
+#pragma unroll
+        for (int k = -2; k <= 2; ++k) {
+            const int q = ci + b * COLS + k * STEP;
+            const float ox = 3.f * (float)(k * STEP), oy = 3.f * (float)(b * STEP);
+            const float den = fmaf(a.sigma_z, fabsf(grad_offset(gx, gy, ox, oy)), 1e-10f);
+            const float et = kLog2B3[b + 2] + kLog2B3[k + 2] -
+                             fabsf(zc - s_z[q]) * (kLog2e * fast_rcp(den)) + s_c[q].z;
+            e[(b + 2) * 5 + k + 2] = et;
+            top = fmaxf(top, et);
+        }
+    float4 out = make_float4(0.f, 0.f, -INFINITY, 0.f);
+    if (top > -INFINITY) {
+        float sw = 0.f, sd = 0.f, sm = 0.f;
+#pragma unroll
+        for (int b = -2; b <= 2; ++b)
+#pragma unroll
+            for (int k = -2; k <= 2; ++k) {
+                const float4 v = s_c[ci + b * COLS + k * STEP];
+                const float w = fast_exp2(e[(b + 2) * 5 + k + 2] - top);  // 0 without samples
+                sw += w;
+                sd = fmaf(w, v.x, sd);
+                sm = fmaf(w, v.y, sm);
+            }
+        const float inv = fast_rcp(sw);
+        out = make_float4(quot(sd, sw, inv), quot(sm, sw, inv), top + fast_log2(sw), 0.f);
+    }
+    const int c = cy * a.cw + cx;
+    if (!last) {
+        dst[c] = out;
+        return;
+    }
+    // the blend factor of the cell's pixels
+    const float lam = (out.z > -INFINITY && out.y > 0.f) ? fminf(1.f, fabsf(out.x) / out.y) : 0.f;
+    const float am = fmaf(lam, 1.f - a.alpha, a.alpha);
+    for (int dy = 0; dy < 3; ++dy) {
+        const int y = 3 * cy + dy;
+        if (y >= a.h) break;
+        for (int dx = 0; dx < 3; ++dx) {
+            const int x = 3 * cx + dx;
+            if (x < a.w) stf(a.alpha_map, (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x, am);
+        }
+    }
+    if (a.lambda) a.lambda[c] = lam;
+}
+
+template <typename T>
+bool launch_level(const GradArgs &a, const float4 *src, float4 *dst, int step, bool first,
+                  bool last, hipStream_t s) {
+    const int gxt = (a.cw + kGTX - 1) / kGTX;
+    const int tiles = gxt * step * ((a.ch + step * kGTY - 1) / (step * kGTY));
+    const dim3 g(xcd_grid(tiles)), b(256);
+    const int f = first ? 1 : 0, l = last ? 1 : 0;
+    switch (step) {
+    case 1: hipLaunchKernelGGL((grad_level_k<T, 1>), g, b, 0, s, a, src, dst, f, l); return true;
+    case 2: hipLaunchKernelGGL((grad_level_k<T, 2>), g, b, 0, s, a, src, dst, f, l); return true;
+    case 4: hipLaunchKernelGGL((grad_level_k<T, 4>), g, b, 0, s, a, src, dst, f, l); return true;
+    case 8: hipLaunchKernelGGL((grad_level_k<T, 8>), g, b, 0, s, a, src, dst, f, l); return true;
+    case 16: hipLaunchKernelGGL((grad_level_k<T, 16>), g, b, 0, s, a, src, dst, f, l); return true;
+    case 32: hipLaunchKernelGGL((grad_level_k<T, 32>), g, b, 0, s, a, src, dst, f, l); return true;
+    default: return false;
+    }
+}
+
 __global__ __launch_bounds__(256) void grad_alpha_k(GradArgs a, const float4 *cells) {
     const int x = (int)blockIdx.x * 64 + (int)(threadIdx.x & 63);
     const int y = (int)blockIdx.y * 4 + (int)(threadIdx.x >> 6);
@@ -177,30 +308,39 @@ GradWork work_layout(sv_dims d) {
     const size_t f4 = (n * sizeof(float4) + 255) & ~(size_t)255;
     GradWork g;
     g.key = 0;
-    g.ca = (n * sizeof(uint32_t) + 255) & ~(size_t)255;
+    g.ca = (n * sizeof(unsigned long long) + 255) & ~(size_t)255;
     g.cb = g.ca + f4;
     g.cz = g.cb + f4;
     g.total = g.cz + n * sizeof(float4);
     return g;
 }
 
+// Levels at cell steps up to 32 run as LDS tiles, the first gathering the
+// samples itself and the last writing the blend factors; with no level, or
+// past step 32, the per-cell passes do those steps.
 template <typename T>
 void launch_gradient(GradArgs a, int levels, hipStream_t s) {
     const int n = a.cw * a.ch;
     const dim3 g1((unsigned)((n + 255) / 256));
     hipLaunchKernelGGL(grad_clear_k, g1, dim3(256), 0, s, a.key, n);
     hipLaunchKernelGGL(grad_project_k<T>, g1, dim3(256), 0, s, a);
-    hipLaunchKernelGGL(grad_gather_k<T>, g1, dim3(256), 0, s, a);
+    const bool tiled = levels >= 1 && levels <= 6;
+    if (!tiled) hipLaunchKernelGGL(grad_gather_k<T>, g1, dim3(256), 0, s, a);
     float4 *src = a.ca, *dst = a.cb;
     for (int l = 0; l < levels; ++l) {
-        hipLaunchKernelGGL(grad_atrous_k, g1, dim3(256), 0, s, a, (const float4 *)src, dst,
-                           1 << l);
+        if (tiled)
+            launch_level<T>(a, src, dst, 1 << l, l == 0, l == levels - 1, s);
+        else
+            hipLaunchKernelGGL(grad_atrous_k, g1, dim3(256), 0, s, a, (const float4 *)src, dst,
+                               1 << l);
         float4 *tmp = src;
         src = dst;
         dst = tmp;
     }
-    hipLaunchKernelGGL(grad_alpha_k, dim3((unsigned)((a.w + 63) / 64), (unsigned)((a.h + 3) / 4)),
-                       dim3(256), 0, s, a, (const float4 *)src);
+    if (!tiled)
+        hipLaunchKernelGGL(grad_alpha_k,
+                           dim3((unsigned)((a.w + 63) / 64), (unsigned)((a.h + 3) / 4)),
+                           dim3(256), 0, s, a, (const float4 *)src);
 }
 
 }  // namespace
@@ -228,6 +368,7 @@ extern "C" int sv_temporal_gradient(const sv_rgb *prev, const sv_rgb *reshade, c
                          fmvy, fz, pick, g->z, g->dzdx, g->dzdy, alpha_map, work};
     for (const void *q : req)
         if (!q) return SV_EINVAL;
+    if ((uintptr_t)work % 16) return SV_EINVAL;  // 64-bit keys and float4 cells
     const int cw = (d.w + 2) / 3, ch = (d.h + 2) / 3;
     const size_t es = elem_size(t);
     const GradWork wl = work_layout(d);
@@ -250,7 +391,7 @@ extern "C" int sv_temporal_gradient(const sv_rgb *prev, const sv_rgb *reshade, c
     }
     unsigned char *wb = (unsigned char *)work;
     GradArgs a{prev->r,  prev->g, prev->b, reshade->r, reshade->g, reshade->b, fmvx, fmvy, fz, pick,
-               g->z,     g->dzdx, g->dzdy, alpha_map,  lambda,     (uint32_t *)(wb + wl.key),
+               g->z,     g->dzdx, g->dzdy, alpha_map,  lambda,     (unsigned long long *)(wb + wl.key),
                (float4 *)(wb + wl.ca), (float4 *)(wb + wl.cb), (float4 *)(wb + wl.cz), d.w, d.h,
                d.pitch, cw, ch,
                p->alpha, p->tau_z, p->sigma_z};

@@ -308,3 +308,19 @@ def test_variance_noalloc_rejects_on_the_host(so):
     empty = L.sv_dims(0, 10, 0)
     assert so.sv_variance_noalloc(None, None, None, r(g), None, empty, L.SV_F32, r(vp),
                                   None) == L.SV_OK
+
+
+def test_gradient_validation(so):
+    """The temporal gradient's workspace must be 16-byte aligned (its cell
+    keys are 64-bit atomics, its cells float4); bad parameters and
+    aliasing are refused before any HIP call."""
+    r = ctypes.byref
+    gp = L.sv_grad_params(0.2, 0.1, 1.0, 3)
+    work = A + 20 * STRIDE
+    args = lambda wk, p=gp: (r(rgb(A)), r(rgb(A + 3 * STRIDE)), A + 6 * STRIDE, A + 7 * STRIDE,
+                             A + 8 * STRIDE, A + 9 * STRIDE, r(gbuf(A + 10 * STRIDE)),
+                             A + 18 * STRIDE, None, wk, D, L.SV_F32, r(p), None)
+    assert so.sv_grad_work_bytes(D) >= 22 * 11 * 8
+    assert so.sv_temporal_gradient(*args(work + 8)) == L.SV_EINVAL
+    assert so.sv_temporal_gradient(*args(work, L.sv_grad_params(0.2, 0.1, 1.0, 9))) == L.SV_EINVAL
+    assert so.sv_temporal_gradient(*args(A + 8 * STRIDE)) == L.SV_EALIAS

@@ -76,6 +76,29 @@ def test_gradient_random_inputs(H, W, dtype):
         np.testing.assert_allclose(am, ram, atol=TOL, rtol=0)
 
 
+@pytest.mark.parametrize("levels", [1, 2, 4, 5, 6])
+def test_gradient_levels_across_tiles(levels):
+    """Every cascade depth on a grid of cells several tiles wide and high
+    (134 x 67 cells, ragged at both edges), the steps reaching past a
+    tile's width at depth 6."""
+    H, W = 200, 401
+    r = np.random.default_rng(4000 + levels)
+    q = lambda a: a.astype(np.float32).astype(np.float64)
+    prev = q(r.uniform(0, 2, (3, H, W)))
+    re = q(np.where(r.random((3, H, W)) < 0.6, prev, r.uniform(0, 2, (3, H, W))))
+    fmv = q(r.normal(0, 2.0, (2, H, W)))
+    z = q(r.uniform(4, 6, (H, W)))
+    z[r.random((H, W)) < 0.02] = 0.0
+    fz = q(z * np.where(r.random((H, W)) < 0.05, 1.5, 1.0))
+    dzdx, dzdy = q(r.normal(0, 0.05, (H, W))), q(r.normal(0, 0.05, (H, W)))
+    pick = r.integers(0, 10, OG.cells_of(H, W)).astype(np.uint8)
+    say(f"gradient {H}x{W} levels={levels}")
+    am, lam = _run(prev, re, fmv, fz, pick, z, dzdx, dzdy, levels=levels, pitch=W + 7)
+    ram, rlam = OG.temporal_gradient(prev, re, fmv, fz, pick, z, dzdx, dzdy, levels=levels)
+    np.testing.assert_allclose(lam, rlam, atol=TOL, rtol=0)
+    np.testing.assert_allclose(am, ram, atol=TOL, rtol=0)
+
+
 def test_gradient_without_change_keeps_alpha():
     H, W = 33, 50
     r = np.random.default_rng(9)
