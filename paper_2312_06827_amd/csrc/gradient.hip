@@ -8,10 +8,11 @@
 // Passes (one stream, graph-capturable: the key clear is a kernel):
 //   grad_clear_k    cell keys := none
 //   grad_project_k  per stratum: land the sample, atomicMin of its index
-//                   (high word) and its pixel (low word) on the cell's
-//                   64-bit key: the lowest stratum index wins
-//   grad_gather_k   per cell: the winning sample's luminance difference and
-//                   maximum, and a presence flag
+//                   on the cell's key (the lowest stratum index wins), and
+//                   the sample's luminance difference and maximum, stored
+//                   by stratum
+//   grad_gather_k   per cell: the winning stratum's difference and maximum,
+//                   and a presence flag
 //   grad_atrous_k   `levels` 5x5 B3 a-trous passes over the cells with a
 //                   depth edge weight, on (delta, norm, present) alike
 //   grad_alpha_k    per pixel: lambda = min(1, |delta| / norm) of its cell,
@@ -39,18 +40,19 @@ struct GradArgs {
     const uint8_t *pick;                      // cells: CH x CW, contiguous
     const void *z, *dzdx, *dzdy;              // current G-buffer
     float *alpha_map, *lambda;
-    unsigned long long *key;                  // (stratum << 32) | sample pixel
+    uint32_t *key;                            // cells: winning stratum
+    float2 *samp;                             // strata: (lr - lp, max(lr, lp))
     float4 *ca, *cb;                          // cell ping-pong
     float4 *cz;                               // cells' centre pixel: z, dz/dx, dz/dy
     int w, h, pitch, cw, ch;
     float alpha, tau_z, sigma_z;
 };
 
-constexpr unsigned long long kNone = ~0ull;
+constexpr uint32_t kNone = 0xFFFFFFFFu;
 
 __device__ __forceinline__ int cells_x(int w) { return (w + 2) / 3; }
 
-__global__ __launch_bounds__(256) void grad_clear_k(unsigned long long *key, int n) {
+__global__ __launch_bounds__(256) void grad_clear_k(uint32_t *key, int n) {
     const int i = (int)blockIdx.x * 256 + (int)threadIdx.x;
     if (i < n) key[i] = kNone;
 }
@@ -83,8 +85,13 @@ __global__ __launch_bounds__(256) void grad_project_k(GradArgs a) {
     if (s >= a.cw * a.ch) return;
     int qx, qy, cell;
     if (land<T>(a, s, qx, qy, cell)) {
+        // the sample's luminances here, where its pixel is known: the
+        // gather then reads one value per cell
         const uint32_t q = (uint32_t)qy * (uint32_t)a.pitch + (uint32_t)qx;
-        atomicMin(&a.key[cell], ((unsigned long long)(uint32_t)s << 32) | q);
+        const float lp = luma(ldo<T>(a.pr, q), ldo<T>(a.pg, q), ldo<T>(a.pb, q));
+        const float lr = luma(ldo<T>(a.rr, q), ldo<T>(a.rg, q), ldo<T>(a.rb, q));
+        a.samp[s] = make_float2(lr - lp, fmaxf(lr, lp));
+        atomicMin(&a.key[cell], (uint32_t)s);
     }
 }
 
@@ -98,13 +105,11 @@ __global__ __launch_bounds__(256) void grad_gather_k(GradArgs a) {
                            (uint32_t)min(3 * cx + 1, a.w - 1);
         a.cz[c] = make_float4(ldo<T>(a.z, o), ldo<T>(a.dzdx, o), ldo<T>(a.dzdy, o), 0.f);
     }
-    const unsigned long long key = a.key[c];
+    const uint32_t key = a.key[c];
     float4 v = make_float4(0.f, 0.f, -INFINITY, 0.f);  // (d, m, l): no sample
     if (key != kNone) {
-        const uint32_t q = (uint32_t)key;  // the winner's pixel
-        const float lp = luma(ldo<T>(a.pr, q), ldo<T>(a.pg, q), ldo<T>(a.pb, q));
-        const float lr = luma(ldo<T>(a.rr, q), ldo<T>(a.rg, q), ldo<T>(a.rb, q));
-        v = make_float4(lr - lp, fmaxf(lr, lp), 0.f, 0.f);  // one sample of weight 1
+        const float2 dm = a.samp[key];
+        v = make_float4(dm.x, dm.y, 0.f, 0.f);  // one sample of weight 1
     }
     a.ca[c] = v;
 }
@@ -177,12 +182,12 @@ constexpr int kGTX = 64, kGTY = 4;
 // weight 1 (l = 0), or none (l = -inf).
 template <typename T>
 __device__ __forceinline__ float4 cell_sample(const GradArgs &a, int c) {
-    const unsigned long long key = a.key[c];
-    if (key == kNone) return make_float4(0.f, 0.f, -INFINITY, 0.f);
-    const uint32_t q = (uint32_t)key;  // the winner's pixel
-    const float lp = luma(ldo<T>(a.pr, q), ldo<T>(a.pg, q), ldo<T>(a.pb, q));
-    const float lr = luma(ldo<T>(a.rr, q), ldo<T>(a.rg, q), ldo<T>(a.rb, q));
-    return make_float4(lr - lp, fmaxf(lr, lp), 0.f, 0.f);
+    const uint32_t key = a.key[c];
+    // no branch before the load (a cell without a sample reads stratum 0
+    // and drops it), so that a thread's cells all have their loads in flight
+    const bool none = key == kNone;
+    const float2 dm = a.samp[none ? 0u : key];
+    return none ? make_float4(0.f, 0.f, -INFINITY, 0.f) : make_float4(dm.x, dm.y, 0.f, 0.f);
 }
 
 // Offset of the centre pixel of cell (cx, cy).
@@ -201,18 +206,31 @@ __global__ __launch_bounds__(256) void grad_level_k(GradArgs a, const float4 *sr
     if (t < 0) return;
     const int tyt = t / gxt, band = tyt / STEP, phase = tyt - band * STEP;
     const int cx0 = (t - tyt * gxt) * kGTX, cy0 = band * STEP * kGTY + phase;
-    for (int i = (int)threadIdx.x; i < NS; i += 256) {
+    // staging: every load of a thread's cells issued before the first store
+    constexpr int IT = (NS + 255) / 256;
+    float4 v[IT];
+    float zq[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int i = (int)threadIdx.x + it * 256;
         const int r = i / COLS, col = i - r * COLS;
         const int cx = cx0 - HX + col, cy = cy0 + (r - 2) * STEP;
-        float4 v = make_float4(0.f, 0.f, -INFINITY, 0.f);
-        float zq = 0.f;
-        if (cx >= 0 && cx < a.cw && cy >= 0 && cy < a.ch) {
-            const int c = cy * a.cw + cx;
-            v = first ? cell_sample<T>(a, c) : src[c];
-            zq = ldo<T>(a.z, cell_centre(a, cx, cy));
+        const bool in = i < NS && cx >= 0 && cx < a.cw && cy >= 0 && cy < a.ch;
+        const int c = in ? cy * a.cw + cx : 0;
+        v[it] = first ? cell_sample<T>(a, c) : src[c];
+        zq[it] = ldo<T>(a.z, cell_centre(a, in ? cx : 0, in ? cy : 0));
+        if (!in) {
+            v[it] = make_float4(0.f, 0.f, -INFINITY, 0.f);
+            zq[it] = 0.f;
         }
-        s_c[i] = v;
-        s_z[i] = zq;
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int i = (int)threadIdx.x + it * 256;
+        if (i < NS) {
+            s_c[i] = v[it];
+            s_z[i] = zq[it];
+        }
     }
     __syncthreads();
     const int lx = (int)(threadIdx.x & 63), ly = (int)(threadIdx.x >> 6);
@@ -300,15 +318,17 @@ __global__ __launch_bounds__(256) void grad_alpha_k(GradArgs a, const float4 *ce
 }
 
 struct GradWork {
-    size_t key, ca, cb, cz, total;
+    size_t key, samp, ca, cb, cz, total;
 };
 
 GradWork work_layout(sv_dims d) {
     const size_t n = (size_t)((d.w + 2) / 3) * (size_t)((d.h + 2) / 3);
-    const size_t f4 = (n * sizeof(float4) + 255) & ~(size_t)255;
+    const auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t f4 = up(n * sizeof(float4));
     GradWork g;
     g.key = 0;
-    g.ca = (n * sizeof(unsigned long long) + 255) & ~(size_t)255;
+    g.samp = up(n * sizeof(uint32_t));
+    g.ca = g.samp + up(n * sizeof(float2));
     g.cb = g.ca + f4;
     g.cz = g.cb + f4;
     g.total = g.cz + n * sizeof(float4);
@@ -368,7 +388,7 @@ extern "C" int sv_temporal_gradient(const sv_rgb *prev, const sv_rgb *reshade, c
                          fmvy, fz, pick, g->z, g->dzdx, g->dzdy, alpha_map, work};
     for (const void *q : req)
         if (!q) return SV_EINVAL;
-    if ((uintptr_t)work % 16) return SV_EINVAL;  // 64-bit keys and float4 cells
+    if ((uintptr_t)work % 16) return SV_EINVAL;  // float4 cells
     const int cw = (d.w + 2) / 3, ch = (d.h + 2) / 3;
     const size_t es = elem_size(t);
     const GradWork wl = work_layout(d);
@@ -390,11 +410,12 @@ extern "C" int sv_temporal_gradient(const sv_rgb *prev, const sv_rgb *reshade, c
             if (overlaps(outs[i], outs[j])) return SV_EALIAS;
     }
     unsigned char *wb = (unsigned char *)work;
-    GradArgs a{prev->r,  prev->g, prev->b, reshade->r, reshade->g, reshade->b, fmvx, fmvy, fz, pick,
-               g->z,     g->dzdx, g->dzdy, alpha_map,  lambda,     (unsigned long long *)(wb + wl.key),
-               (float4 *)(wb + wl.ca), (float4 *)(wb + wl.cb), (float4 *)(wb + wl.cz), d.w, d.h,
-               d.pitch, cw, ch,
-               p->alpha, p->tau_z, p->sigma_z};
+    GradArgs a{prev->r,    prev->g,    prev->b,   reshade->r,
+               reshade->g, reshade->b, fmvx,      fmvy,
+               fz,         pick,       g->z,      g->dzdx,
+               g->dzdy,    alpha_map,  lambda,    (uint32_t *)(wb + wl.key),
+               (float2 *)(wb + wl.samp), (float4 *)(wb + wl.ca), (float4 *)(wb + wl.cb),
+               (float4 *)(wb + wl.cz), d.w, d.h, d.pitch, cw, ch, p->alpha, p->tau_z, p->sigma_z};
     hipStream_t s = as_stream(stream);
     if (t == SV_F32) launch_gradient<float>(a, p->levels, s);
     else launch_gradient<half_t>(a, p->levels, s);

@@ -253,7 +253,10 @@ class Denoiser:
             dst_var = None if last else self.lvl_var[i % 2]
             p = cfg.atrous(inv_tonemap=fuse_inv)
             if self.tiles and i < len(self.tiles):
-                p.persistent, p.blocks_per_cu = self.tiles[i]
+                shape = self.tiles[i]  # (persistent, blocks per CU[, tile rows])
+                p.persistent, p.blocks_per_cu = shape[0], shape[1]
+                if len(shape) > 2:
+                    p.tile_rows = shape[2]
             if inp.blur_ctl is not None:
                 with tm(f"atrous_adaptive{i}"):
                     fused = (2 << i) <= 32

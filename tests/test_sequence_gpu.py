@@ -94,17 +94,25 @@ class _NullTimer:
         return contextlib.nullcontext()
 
 
-@pytest.mark.parametrize("levels,sep,feedback", [(5, False, "atrous0"), (5, True, "atrous0"),
-                                                 (1, False, "atrous0"), (0, False, "atrous0"),
-                                                 (3, True, "temporal")])
-def test_native_driver_equals_call_by_call(levels, sep, feedback):
-    """sv_denoise_frame enqueues exactly the individual calls: bitwise equal."""
+# per-level launch shapes (persistent, workgroups per CU, tile rows) as the
+# autotuner hands them over
+_SHAPES_2D = [(1, 4, 1), (0, 0, 2), (1, 2, 1), (0, 0, 1), (1, 3, 0)]
+_SHAPES_SEP = [(0, 0, 16), (0, 0, 6), (0, 0, 16), (0, 0, 6), (0, 0, 0)]
+
+
+@pytest.mark.parametrize("levels,sep,feedback,tiles", [
+    (5, False, "atrous0", None), (5, True, "atrous0", None), (1, False, "atrous0", None),
+    (0, False, "atrous0", None), (3, True, "temporal", None), (5, False, "atrous0", _SHAPES_2D),
+    (5, True, "atrous0", _SHAPES_SEP)])
+def test_native_driver_equals_call_by_call(levels, sep, feedback, tiles):
+    """sv_denoise_frame enqueues exactly the individual calls: bitwise equal,
+    also with per-level launch shapes."""
     from dataclasses import replace
     cfg = with_size(CONFIGS["hd_motion"], 200, 120, 6)
     filt = replace(MOTION_SEP if sep else MOTION, levels=levels, feedback=feedback)
-    say(f"native driver vs calls: levels={levels} sep={sep} feedback={feedback}")
-    a = Denoiser(cfg.height, cfg.width, filt)
-    b = Denoiser(cfg.height, cfg.width, filt)
+    say(f"native driver vs calls: levels={levels} sep={sep} feedback={feedback} tiles={tiles}")
+    a = Denoiser(cfg.height, cfg.width, filt, tiles=tiles)
+    b = Denoiser(cfg.height, cfg.width, filt, tiles=tiles)
     ofilt = O.OracleParams(clamp=True, tonemap=True, use_id=True, separable=sep,
                            levels=levels, feedback=feedback)
     st = O.new_state(cfg.height, cfg.width)
