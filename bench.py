@@ -250,6 +250,22 @@ def _timed_frames(torch, fn, frames, warmup):
 UHD_WARMUP, UHD_STEPS = 4, 10
 BATCH_WARMUP, BATCH_STEPS = 3, 5
 CH_WARMUP, CH_STEPS = 5, 15
+# the learned component's quality judge: the held-out sequences (never
+# trained on), 1920x1080, RelMSE-to-clean over frames 10..13 of each
+LEARN_SEEDS = tuple(range(5900, 5908))
+LEARN_FRAMES, LEARN_FIRST = 14, 10
+# the plain filter at its best constant blend factor and luminance-edge
+# width, the grid the learned per-pixel values are judged against (wider
+# than the network's own ranges: alpha in [0.05, 1], kappa in [1/4, 4])
+PLAIN_GRID_ALPHA = (0.05, 0.1, 0.2, 0.4, 0.6, 0.8, 1.0)
+PLAIN_GRID_KAPPA = (0.5, 1.0, 2.0, 4.0, 8.0, 16.0)
+_LEARN_KEYS = ("rgb", "clean", "albedo", "z", "dzdx", "dzdy", "n", "id", "mv", "prev_z",
+               "prev_n", "prev_id")
+
+
+def _render_learn(args):
+    fr = render_frame(*args)
+    return {k: fr[k] for k in _LEARN_KEYS}
 
 
 def generate_variant_frames(workers, want):
@@ -268,11 +284,16 @@ def generate_variant_frames(workers, want):
         jobs += [(c, f) for f in range(n) for c in scfg]
     if want & {"channels", "gradient"}:
         jobs += [(ch, f) for f in range(ch.frames)]
+    held = [type(WORKLOAD)(**{**WORKLOAD.__dict__, "frames": LEARN_FRAMES, "seed": sd})
+            for sd in LEARN_SEEDS]
+    ljobs = [(c, f) for c in held for f in range(LEARN_FRAMES)] if "learned" in want else []
     if workers <= 1:
         out = [_render(j) for j in jobs]
+        lout = [_render_learn(j) for j in ljobs]
     else:
         with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork")) as ex:
             out = list(ex.map(_render, jobs))
+            lout = list(ex.map(_render_learn, ljobs))
     res, k = {}, 0
     if "uhd_half" in want:
         res["uhd"], k = out[:uhd.frames], uhd.frames
@@ -282,50 +303,68 @@ def generate_variant_frames(workers, want):
         k += 16 * n
     if want & {"channels", "gradient"}:
         res["channels"] = out[k:k + ch.frames]
+    if "learned" in want:
+        res["held_out"] = [lout[i * LEARN_FRAMES:(i + 1) * LEARN_FRAMES]
+                           for i in range(len(LEARN_SEEDS))]
     return res
 
 
-def variant_uhd_half(torch, frames_np, warmup=UHD_WARMUP, steps=UHD_STEPS):
-    """Binary16 storage at 3840x2160 (2D levels)."""
+def variant_uhd_half(torch, frames_np, warmup=UHD_WARMUP, steps=UHD_STEPS, tune=True):
+    """Binary16 storage at 3840x2160 (2D levels), launch shapes from the
+    autotuner at that size and storage type."""
+    from paper_2312_06827_amd.autotune import tiles_for
     from paper_2312_06827_amd.pipeline import MOTION, Denoiser, FrameInputs
     cfg = CONFIGS["uhd_half"]
     frames = [FrameInputs.from_numpy(fr) for fr in frames_np]
-    den = Denoiser(cfg.height, cfg.width, MOTION, dtype=torch.float16)
+    tiles = tiles_for(cfg.height, cfg.width, torch.float16, cache=None) if tune else None
+    den = Denoiser(cfg.height, cfg.width, MOTION, dtype=torch.float16, tiles=tiles)
     ms = _timed_frames(torch, den.frame, frames, warmup)
     px = cfg.width * cfg.height
     return {"value": round(px / (ms * 1e-3) / 1e6, 1), "unit": "Mpix/s", "ms_per_step": round(ms, 4),
             "dtype": "f16 storage / f32 math", "frame_bytes_per_px": FP16_FRAME_BYTES,
+            "launch_shapes": tiles and [list(t) for t in tiles],
             "frame_hbm_frac": round(px * FP16_FRAME_BYTES / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "config": f"{cfg.width}x{cfg.height}, {steps} frames timed after {warmup}"}
 
 
-def variant_batched(torch, scfg, frames_np, warmup=BATCH_WARMUP, steps=BATCH_STEPS):
+def variant_batched(torch, scfg, frames_np, warmup=BATCH_WARMUP, steps=BATCH_STEPS, tune=True):
     """Sixteen streams of uneven size, binary16: one launch per pass under a
-    HIP graph, against the same streams run one by one."""
+    HIP graph, against the same streams run one by one.  One set of launch
+    shapes for every stream (a pass is one launch over all of them), from
+    the autotuner at the median stream size."""
+    from paper_2312_06827_amd.autotune import tiles_for
     from paper_2312_06827_amd.pipeline import MOTION, BatchDenoiser, Denoiser, FrameInputs
     frames = [[FrameInputs.from_numpy(fr) for fr in per] for per in frames_np]
     sizes = [(c.height, c.width) for c in scfg]
     px = sum(h * w for h, w in sizes)
-    batch = BatchDenoiser(sizes, MOTION, torch.float16)
+    mh, mw = sorted(sizes, key=lambda s: s[0] * s[1])[len(sizes) // 2]
+    tiles = tiles_for(mh, mw, torch.float16, cache=None) if tune else None
+    batch = BatchDenoiser(sizes, MOTION, torch.float16, tiles=tiles)
     ms_b = _timed_frames(torch, batch.frame, frames, warmup)
     passes = batch.passes()
     batch.close()
-    singles = [Denoiser(h, w, MOTION, torch.float16) for h, w in sizes]
+    singles = [Denoiser(h, w, MOTION, torch.float16, tiles=tiles) for h, w in sizes]
     ms_s = _timed_frames(torch, lambda fr: [d.frame(x) for d, x in zip(singles, fr)], frames, warmup)
     return {"value": round(px / (ms_b * 1e-3) / 1e6, 1), "unit": "Mpix/s",
             "ms_per_step": round(ms_b, 4), "launches_per_frame": passes,
+            "launch_shapes": tiles and [list(t) for t in tiles],
+            "tuned_at": f"{mw}x{mh}",
             "one_by_one": {"value": round(px / (ms_s * 1e-3) / 1e6, 1), "ms_per_step": round(ms_s, 4),
                            "launches_per_frame": 16 * passes},
             "config": f"16 streams {min(sizes)}..{max(sizes)} (HxW), {px / 1e6:.1f} Mpix per frame, "
                       f"{steps} frames timed after {warmup}"}
 
 
-def variant_learned(torch, frames_np, warmup, steps):
-    """The learned blend/edge network on the headline workload, run inside
-    the temporal step, against plain SVGF: throughput and RelMSE-to-clean
-    over the timed frames for {plain, learned} x {2D, separable} x {5, 4, 3}
-    levels.  The claim holds if a learned point has RelMSE no higher and
-    throughput no lower than plain 5-level 2D."""
+def variant_learned(torch, frames_np, held_np, warmup, steps):
+    """The learned blend/edge network inside the temporal step, against
+    plain SVGF.  Throughput: the headline frames, for {plain, learned} x
+    {2D, separable} x {5, 4, 3} levels.  Quality: RelMSE-to-clean over
+    frames 10..13 of the eight held-out 1080p sequences (seeds 5900-5907).
+    Two plain references: the paper's constants (alpha 0.2, sigma_l 4) and
+    the best constant (alpha, sigma_l scale) of a 7 x 6 grid chosen on those
+    same held-out frames (the strongest constant the network could be
+    replaced by).  The claim holds against a reference if some learned point
+    has RelMSE no higher and throughput no lower than plain 5-level 2D."""
     from dataclasses import replace as dc_replace
 
     from paper_2312_06827_amd import learn
@@ -336,13 +375,23 @@ def variant_learned(torch, frames_np, warmup, steps):
     H, W = WORKLOAD.height, WORKLOAD.width
     n = warmup + steps
     frames = [FrameInputs.from_numpy(fr) for fr in frames_np[:n]]
-    clean = [torch.from_numpy(fr["clean"]).cuda() for fr in frames_np[:n]]
+    held = [[(FrameInputs.from_numpy(fr), torch.from_numpy(fr["clean"]).cuda()) for fr in seq]
+            for seq in held_np]
 
-    def quality(den):
-        return float(np.mean([learn.relmse(den.frame(fr), clean[i])
-                              for i, fr in enumerate(frames)][warmup:]))
+    def quality(cfg, mlp):
+        errs = []
+        for seq in held:
+            den = Denoiser(H, W, cfg, mlp=mlp)
+            for f, (fr, clean) in enumerate(seq):
+                out = den.frame(fr)
+                if f >= LEARN_FIRST:
+                    errs.append(learn.relmse(out, clean))
+        return float(np.mean(errs))
 
-    out = {"weights": os.path.relpath(learn.DEFAULT_WEIGHTS, ROOT), "points": {}}
+    out = {"weights": os.path.relpath(learn.DEFAULT_WEIGHTS, ROOT),
+           "judge": f"RelMSE over frames {LEARN_FIRST}..{LEARN_FRAMES - 1} of held-out 1080p "
+                    f"sequences, seeds {LEARN_SEEDS[0]}-{LEARN_SEEDS[-1]}",
+           "points": {}}
     for mode in ("plain", "learned"):
         mlp = net if mode == "learned" else None
         for form, base in (("2d", MOTION), ("sep", MOTION_SEP)):
@@ -351,12 +400,26 @@ def variant_learned(torch, frames_np, warmup, steps):
                 ms = _timed_frames(torch, Denoiser(H, W, cfg, mlp=mlp).frame, frames, warmup)
                 out["points"][f"{mode}_{form}_{levels}"] = {
                     "value": round(H * W / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 4),
-                    "relmse": round(quality(Denoiser(H, W, cfg, mlp=mlp)), 6)}
+                    "relmse": round(quality(cfg, mlp), 6)}
+    grid = {}
+    for a in PLAIN_GRID_ALPHA:
+        for k in PLAIN_GRID_KAPPA:
+            grid[(a, k)] = quality(dc_replace(MOTION, alpha=a,
+                                              sigma_l=MOTION.sigma_l * k), None)
+    (ba, bk), best = min(grid.items(), key=lambda kv: kv[1])
+    out["plain_best_constant"] = {
+        "alpha": ba, "sigma_l_scale": bk, "relmse": round(best, 6),
+        "grid": {f"a{a}_k{k}": round(v, 6) for (a, k), v in grid.items()}}
     ref = out["points"]["plain_2d_5"]
-    wins = [k for k, v in out["points"].items() if k.startswith("learned")
-            and v["relmse"] <= ref["relmse"] and v["value"] >= ref["value"]]
-    out["claim_holds"] = bool(wins)
-    out["winning_points"] = wins
+
+    def winners(rel):
+        return [k for k, v in out["points"].items() if k.startswith("learned")
+                and v["relmse"] <= rel and v["value"] >= ref["value"]]
+
+    out["winning_points"] = winners(ref["relmse"])
+    out["claim_holds"] = bool(out["winning_points"])
+    out["winning_points_vs_best_constant"] = winners(best)
+    out["claim_holds_vs_best_constant"] = bool(out["winning_points_vs_best_constant"])
     return out
 
 
@@ -488,24 +551,57 @@ def variant_gradient(torch, frames_np, warmup=CH_WARMUP, steps=CH_STEPS):
     return out
 
 
-def cpu_baseline(frames_np, warm, timed):
-    """The oracle as it stands, on the host cores, on a bounded sample."""
+def host_cpu():
+    """CPU model and the logical CPUs this process may run on."""
+    model = platform.processor() or platform.machine()
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return {"model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
+
+
+def cpu_baseline(frames_np, warm, timed, timed_one=1):
+    """The oracle as it stands, on the host cores, on a bounded sample: the
+    chain over `timed` frames with every usable core, then over `timed_one`
+    further frames on one thread (the same frames the GPU filters)."""
     import oracle as O
 
     p = O.OracleParams(clamp=True, tonemap=True, use_id=True)
     H, W = frames_np[0]["z"].shape
     st = O.new_state(H, W)
+    cpu = host_cpu()
+    threads = int(os.environ.get("OMP_NUM_THREADS", cpu["usable_cpus"]))
+    O.set_threads(threads)
     for f in range(warm):
         _, st, _ = O.run_frame(frames_np[f], st, p)
     t0 = time.perf_counter()
     for f in range(warm, warm + timed):
         _, st, _ = O.run_frame(frames_np[f], st, p)
     dt = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": W * H * timed / dt / 1e6, "unit": "Mpix/s", "cores": threads,
+    O.set_threads(1)
+    t1 = time.perf_counter()
+    for f in range(warm + timed, warm + timed + timed_one):
+        _, st, _ = O.run_frame(frames_np[f], st, p)
+    dt1 = time.perf_counter() - t1
+    O.set_threads(threads)
+    return {"value": W * H * timed / dt / 1e6, "unit": "Mpix/s", "cores": O.threads(),
             "kind": "oracle",
             "sample": f"{W}x{H} frames {warm}..{warm + timed - 1} of the same sequence after "
-                      f"{warm} untimed frames, FP64 C oracle with OpenMP ({dt:.1f} s)"}
+                      f"{warm} untimed frames, FP64 C oracle with OpenMP ({dt:.1f} s)",
+            "single_thread": {"value": W * H * timed_one / dt1 / 1e6, "unit": "Mpix/s", "cores": 1,
+                              "sample": f"frame{'s' if timed_one > 1 else ''} {warm + timed}"
+                                        f"{'..' + str(warm + timed + timed_one - 1) if timed_one > 1 else ''}"
+                                        f" on one thread ({dt1:.1f} s)"},
+            "cpu": cpu}
 
 
 def main():
@@ -518,9 +614,9 @@ def main():
     ap.add_argument("--variants",
                     default="separable,uhd_half,batched,scene_features,channels,gradient,learned",
                     help="comma-separated variants to run after the headline chain")
-    ap.add_argument("--tune", action="store_true",
-                    help="a-trous launch shapes from the autotuner (timed before the run)"
-                         " instead of the library defaults")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="the library's default a-trous launch shapes instead of the"
+                         " autotuner's (which are timed on this GPU before the run)")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     args = ap.parse_args()
     if args.gpus != 1:
@@ -533,7 +629,7 @@ def main():
     frames_np = generate(WORKLOAD, n_frames, args.workers)  # before any GPU call (fork)
     want = set() if args.no_variants else set(v for v in args.variants.split(",") if v)
     vframes = (generate_variant_frames(args.workers, want)
-               if want & {"uhd_half", "batched", "channels", "gradient"} else None)
+               if want & {"uhd_half", "batched", "channels", "gradient", "learned"} else None)
     gen_s = time.perf_counter() - t0
     print(f"# generated {n_frames} frames in {gen_s:.1f} s", file=sys.stderr, flush=True)
 
@@ -546,14 +642,15 @@ def main():
 
     # launch shapes of the a-trous levels, measured on this device and size
     from paper_2312_06827_amd.autotune import tiles_for
-    if not args.tune:
+    if args.no_tune:
         tiles_2d = tiles_sep = None
     else:
         tiles_2d = tiles_for(H, W, separable=False, cache=None)
         tiles_sep = tiles_for(H, W, separable=True, cache=None)
     print(f"# tuned launch shapes 2d {tiles_2d} sep {tiles_sep}", file=sys.stderr, flush=True)
     # a throwaway pass warms clocks, code objects and allocator
-    run_chain(torch, frames_dev, MOTION, H, W, 2, min(8, args.steps), per_kernel=False,
+    tw = min(2, args.warmup)
+    run_chain(torch, frames_dev, MOTION, H, W, tw, min(8, n_frames - tw), per_kernel=False,
               tiles=tiles_2d)
     gpu_ms, wall, _ = run_chain(torch, frames_dev, MOTION, H, W, args.warmup, args.steps,
                                 per_kernel=False, tiles=tiles_2d)
@@ -606,11 +703,12 @@ def main():
         print(f"# separable chain: {variants['separable']['ms_per_step'] * 1e3:.1f} us/frame",
               file=sys.stderr, flush=True)
     if "uhd_half" in want:
-        variants["uhd_half"] = variant_uhd_half(torch, vframes["uhd"])
+        variants["uhd_half"] = variant_uhd_half(torch, vframes["uhd"], tune=not args.no_tune)
         print(f"# 4K binary16: {variants['uhd_half']['ms_per_step'] * 1e3:.1f} us/frame",
               file=sys.stderr, flush=True)
     if "batched" in want:
-        variants["batched"] = variant_batched(torch, vframes["batch_cfg"], vframes["batch"])
+        variants["batched"] = variant_batched(torch, vframes["batch_cfg"], vframes["batch"],
+                                              tune=not args.no_tune)
         print(f"# 16 streams batched: {variants['batched']['ms_per_step'] * 1e3:.1f} us/frame",
               file=sys.stderr, flush=True)
     if "channels" in want:
@@ -624,7 +722,7 @@ def main():
                                                             args.steps)
         print(f"# clip / adaptive: {variants['scene_features']}", file=sys.stderr, flush=True)
     if "learned" in want:
-        learned = variant_learned(torch, frames_np, args.warmup, args.steps)
+        learned = variant_learned(torch, frames_np, vframes["held_out"], args.warmup, args.steps)
         if learned is not None:
             variants["learned"] = learned
     copy_gbs = copy_probe(torch)
@@ -652,13 +750,22 @@ def main():
                    "width": W, "height": H, "frames_timed": args.steps, "levels": 5,
                    "alpha": 0.2, "sigma_z": 1, "sigma_n": 128, "sigma_l": 4},
         "roofline": roofline,
+        # a-trous launch shapes per level (persistent, workgroups per CU,
+        # tile rows), from the autotuner on this GPU; null: library defaults
+        "launch_shapes": {"2d": tiles_2d and [list(t) for t in tiles_2d],
+                          "separable": tiles_sep and [list(t) for t in tiles_sep]},
         "frame_hbm_frac": round(mpix * 1e6 * fb / 1e9 / HBM_PEAK_GBS, 4),
+        # the whole frame against the HBM roofline at its algorithmic bytes:
+        # the target is 0.60 of 8 TB/s
+        "hbm_target": {"frame_hbm_frac": round(mpix * 1e6 * fb / 1e9 / HBM_PEAK_GBS, 4),
+                       "target": 0.60,
+                       "met": bool(mpix * 1e6 * fb / 1e9 / HBM_PEAK_GBS >= 0.60)},
         "frame_bytes_per_px": fb,
         "copy_probe_gbs": round(copy_gbs, 1),
         "per_kernel_us": per_kernel,
         "variants": variants,
         "cpu_baseline": cpu,
-        "host": {"cpu": platform.processor() or platform.machine(), "gen_s": round(gen_s, 1)},
+        "host": {**host_cpu(), "gen_s": round(gen_s, 1)},
     }
     print(json.dumps(line), flush=True)
 

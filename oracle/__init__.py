@@ -91,6 +91,8 @@ def _load():
             [_I, _I] + [_dp] * 11 + [_I] + [_D] * 6 + [_I] + [_dp] * 7)
         lib.svo_quantize_half.argtypes = [_L, _dp]
         lib.svo_version.restype = _I
+        lib.svo_set_threads.argtypes = [_I]
+        lib.svo_threads.restype = _I
         _lib = lib
         return lib
 
@@ -435,3 +437,13 @@ def run_frame(frame, state, p: OracleParams, alpha_map=None, kappa=None, ctl=Non
         hist_rgb = t["rgb"]
     new = {"rgb": hist_rgb, "m1": t["m1"], "m2": t["m2"], "n": t["n"]}
     return c, new, {"temporal": t, "var": var, "levels": levels}
+
+
+def set_threads(n: int) -> None:
+    """Host threads of the oracle's parallel loops (results do not depend
+    on it)."""
+    _load().svo_set_threads(int(n))
+
+
+def threads() -> int:
+    return int(_load().svo_threads())

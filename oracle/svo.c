@@ -33,6 +33,7 @@
  * is FP64.  Build with -ffp-contract=off so that the compiler fuses nothing.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -798,4 +799,16 @@ void svo_atrous_sep(int W, int H, const double *cr, const double *cg,
 int svo_version(void)
 {
     return 1;
+}
+
+/* Host threads of the parallel loops (timing only: every result is the
+ * same at any count, each pixel being computed by one thread alone). */
+void svo_set_threads(int n)
+{
+    omp_set_num_threads(n > 0 ? n : 1);
+}
+
+int svo_threads(void)
+{
+    return omp_get_max_threads();
 }

@@ -49,6 +49,23 @@ def random_gbuf(r, H, W, z_range=(4.0, 6.0)):
     return f(z), f(dzdx), f(dzdy), f(n)
 
 
+def frac_over(gpu, ora, tol, floor=1e-3, abs_floor=0.0):
+    """Fraction of the elements whose relative error (as rel_err() takes
+    it) exceeds tol."""
+    g = np.asarray(gpu, dtype=np.float64)
+    o = np.asarray(ora, dtype=np.float64)
+    if o.ndim == 2:
+        g, o = g[None], o[None]
+    over = total = 0
+    for gp, op in zip(g.reshape(-1, *o.shape[-2:]), o.reshape(-1, *o.shape[-2:])):
+        rms = np.sqrt(np.mean(op * op))
+        den = np.maximum(np.maximum(np.abs(op), floor * rms), abs_floor)
+        den = np.where(den > 0, den, 1.0)
+        over += int(np.count_nonzero(np.abs(gp - op) / den > tol))
+        total += gp.size
+    return over / max(total, 1)
+
+
 def worst(gpu, ora, floor=1e-3, abs_floor=0.0):
     """Where the relative error of rel_err() peaks: (plane, y, x, gpu, oracle)."""
     g = np.asarray(gpu, dtype=np.float64)

@@ -35,13 +35,14 @@ from paper_2312_06827_amd import lib as L
 from paper_2312_06827_amd.pipeline import (SHADOW, SPECULAR, ChannelDenoiser, Denoiser,
                                            FrameInputs)
 from paper_2312_06827_amd.scene import CONFIGS, sequence, with_size
-from tests._util import rel_err, say, worst
+from tests._util import frac_over, rel_err, say, worst
 from tests.test_parity_gpu import dev, empty_like_dev, host
 
 pytestmark = pytest.mark.gpu
 TOL32 = 1e-5
 FLOOR_BINARY = 1.0  # chained zero-variance visibility: errors measured against the plane RMS
 TOL_CHAIN = 1e-4  # ... and held to 1e-4 of max(|value|, RMS) (see above)
+OVER_CHAIN = 2e-3  # the fraction of chained shadow values past 1e-5 of that (measured 6.3e-4)
 
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float16])
@@ -97,9 +98,13 @@ def test_channel_pipeline_matches_oracle(adaptive):
             e = (rel_err(host(den.batch.streams[0].out), os_, floor=FLOOR_BINARY),
                  rel_err(host(den.batch.streams[1].out), op),
                  rel_err(host(out), ref, floor=FLOOR_BINARY))
-            say(f"  shadow {e[0]:.2e} specular {e[1]:.2e} composite {e[2]:.2e}; worst shadow "
+            # the strict bar's misses are counted, as decision flips are
+            over = frac_over(host(den.batch.streams[0].out), os_, TOL32, floor=FLOOR_BINARY)
+            say(f"  shadow {e[0]:.2e} specular {e[1]:.2e} composite {e[2]:.2e}; shadow values"
+                f" beyond 1e-5: {over:.2e} of them; worst shadow "
                 f"{worst(host(den.batch.streams[0].out), os_, floor=FLOOR_BINARY)}")
             assert e[0] <= TOL_CHAIN and e[1] <= TOL32 and e[2] <= TOL_CHAIN, (f, e)
+            assert over <= OVER_CHAIN, (f, over)
     finally:
         den.close()
 
