@@ -385,10 +385,13 @@ int sv_blur_control(const float *roughness, const float *shadow_angle,
  * level < levels(c); otherwise its colour and variance pass through
  * unchanged (the inverse tone map of SV_A_INV_TONEMAP still applies).  A
  * shifted separable pixel takes the vertical pass of the horizontal result
- * at its own step.  Two launches over the image, one per step; each pixel
- * is written by one.  `scratch`: as sv_atrous_sep, separable only (NULL
- * selects the fused form, steps up to 32, so levels 0..4; SV_EUNSUPPORTED
- * above).  `ctl` (one byte per pixel, pitch d.pitch) must not overlap the
+ * at its own step.  A 5x5 level at step 2^level <= 8 is one launch, each
+ * pixel taking its taps at its own step (p->persistent and tile_rows do
+ * not apply there: tiles of 64 x 8 lattice rows, one per workgroup);
+ * otherwise, and for separable levels, two launches over the image, one
+ * per step, each pixel written by one.  `scratch`: as sv_atrous_sep,
+ * separable only (NULL selects the fused form, steps up to 32, so levels
+ * 0..4; SV_EUNSUPPORTED above).  `ctl` (one byte per pixel, pitch d.pitch) must not overlap the
  * outputs.  Other arguments and errors as sv_atrous; level outside 0..12
  * is SV_EINVAL. */
 int sv_atrous_adaptive(const sv_rgb *c_in, const float *var_in,
