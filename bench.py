@@ -216,6 +216,41 @@ def run_chain(torch, frames_dev, cfg, H, W, warmup, steps, per_kernel, tiles=Non
     return gpu_ms, wall, (timer.summary() if timer else None)
 
 
+def frame_times(torch, frames_dev, cfg, H, W, warmup, steps, tiles=None):
+    """Per-frame GPU times (us) of the chain: an event between consecutive
+    native frame calls on the launch stream, nothing else added."""
+    from paper_2312_06827_amd.pipeline import Denoiser
+
+    den = Denoiser(H, W, cfg, tiles=tiles)
+    for f in range(warmup):
+        den.frame(frames_dev[f])
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    for i, f in enumerate(range(warmup, warmup + steps)):
+        den.frame(frames_dev[f])
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    t = np.array([ev[i].elapsed_time(ev[i + 1]) * 1e3 for i in range(steps)])
+    return {"median": round(float(np.median(t)), 2), "p90": round(float(np.percentile(t, 90)), 2),
+            "min": round(float(t.min()), 2), "max": round(float(t.max()), 2)}
+
+
+def graph_replay(torch, frames_dev, cfg, H, W, warmup, tiles=None):
+    """The headline chain as a one-stream batch plan: the frame's passes
+    captured once as a HIP graph and replayed with refreshed arguments."""
+    from paper_2312_06827_amd.pipeline import BatchDenoiser
+
+    plan = BatchDenoiser([(H, W)], cfg, torch.float32, tiles=tiles)
+    try:
+        ms = _timed_frames(torch, plan.frame, [[fd] for fd in frames_dev], warmup)
+        passes = plan.passes()
+    finally:
+        plan.close()
+    return {"value": round(H * W / (ms * 1e-3) / 1e6, 1), "unit": "Mpix/s",
+            "ms_per_step": round(ms, 4), "launches_per_frame": passes}
+
+
 def copy_probe(torch, nbytes=1 << 30, reps=10):
     from paper_2312_06827_amd import lib
 
@@ -585,11 +620,15 @@ def host_cpu():
     return {"model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
 
 
-def cpu_baseline(frames_np, warm, timed, timed_one=1):
+def cpu_baseline(frames_np, warm, timed, timed_one=1, timed_eight=2, uhd_np=None):
     """The oracle as it stands, on the host cores, on a bounded sample: the
-    chain over `timed` frames with every usable core, then over `timed_one`
-    further frames on one thread (the same frames the GPU filters)."""
+    chain over `timed` frames with every usable core, then `timed_one`
+    further frames on one thread and `timed_eight` on eight (the same frames
+    the GPU filters); beside it the small static workload in full and, when
+    its frames are at hand, the first two 3840x2160 binary16 frames (every
+    pixel short of history there, so the spatial variance runs everywhere)."""
     import oracle as O
+    from paper_2312_06827_amd.scene import sequence
 
     p = O.OracleParams(clamp=True, tonemap=True, use_id=True)
     H, W = frames_np[0]["z"].shape
@@ -599,25 +638,55 @@ def cpu_baseline(frames_np, warm, timed, timed_one=1):
     O.set_threads(threads)
     for f in range(warm):
         _, st, _ = O.run_frame(frames_np[f], st, p)
-    t0 = time.perf_counter()
-    for f in range(warm, warm + timed):
-        _, st, _ = O.run_frame(frames_np[f], st, p)
-    dt = time.perf_counter() - t0
-    O.set_threads(1)
-    t1 = time.perf_counter()
-    for f in range(warm + timed, warm + timed + timed_one):
-        _, st, _ = O.run_frame(frames_np[f], st, p)
-    dt1 = time.perf_counter() - t1
+
+    def run(first, count, n_threads):
+        nonlocal st
+        O.set_threads(n_threads)
+        t0 = time.perf_counter()
+        for f in range(first, first + count):
+            _, st, _ = O.run_frame(frames_np[f], st, p)
+        return time.perf_counter() - t0
+
+    dt = run(warm, timed, threads)
+    f1 = warm + timed
+    dt1 = run(f1, timed_one, 1)
+    f8 = f1 + timed_one
+    dt8 = run(f8, timed_eight, 8) if timed_eight and f8 + timed_eight <= len(frames_np) else None
     O.set_threads(threads)
-    return {"value": W * H * timed / dt / 1e6, "unit": "Mpix/s", "cores": O.threads(),
-            "kind": "oracle",
-            "sample": f"{W}x{H} frames {warm}..{warm + timed - 1} of the same sequence after "
-                      f"{warm} untimed frames, FP64 C oracle with OpenMP ({dt:.1f} s)",
-            "single_thread": {"value": W * H * timed_one / dt1 / 1e6, "unit": "Mpix/s", "cores": 1,
-                              "sample": f"frame{'s' if timed_one > 1 else ''} {warm + timed}"
-                                        f"{'..' + str(warm + timed + timed_one - 1) if timed_one > 1 else ''}"
-                                        f" on one thread ({dt1:.1f} s)"},
-            "cpu": cpu}
+    frames = lambda a, n: f"frame{'s' if n > 1 else ''} {a}{'..' + str(a + n - 1) if n > 1 else ''}"
+    out = {"value": W * H * timed / dt / 1e6, "unit": "Mpix/s", "cores": O.threads(),
+           "kind": "oracle",
+           "sample": f"{W}x{H} {frames(warm, timed)} of the same sequence after {warm} untimed "
+                     f"frames, FP64 C oracle with OpenMP ({dt:.1f} s)",
+           "single_thread": {"value": W * H * timed_one / dt1 / 1e6, "unit": "Mpix/s", "cores": 1,
+                             "sample": f"{frames(f1, timed_one)} on one thread ({dt1:.1f} s)"},
+           "cpu": cpu}
+    if dt8 is not None:
+        out["eight_threads"] = {"value": W * H * timed_eight / dt8 / 1e6, "unit": "Mpix/s",
+                                "cores": 8, "sample": f"{frames(f8, timed_eight)} ({dt8:.1f} s)"}
+    # the small static workload, all eight frames
+    small = list(sequence(CONFIGS["small_static"]))
+    sh, sw = small[0]["z"].shape
+    s_st = O.new_state(sh, sw)
+    t0 = time.perf_counter()
+    for fr in small:
+        _, s_st, _ = O.run_frame(fr, s_st, O.OracleParams())
+    dts = time.perf_counter() - t0
+    out["small_static"] = {"value": sw * sh * len(small) / dts / 1e6, "unit": "Mpix/s",
+                           "cores": O.threads(),
+                           "sample": f"{sw}x{sh}, all {len(small)} frames ({dts:.2f} s)"}
+    if uhd_np:
+        hp = O.OracleParams(clamp=True, tonemap=True, use_id=True, half=True)
+        uh, uw = uhd_np[0]["z"].shape
+        u_st = O.new_state(uh, uw)
+        n = min(2, len(uhd_np))
+        t0 = time.perf_counter()
+        for fr in uhd_np[:n]:
+            _, u_st, _ = O.run_frame(fr, u_st, hp)
+        dtu = time.perf_counter() - t0
+        out["uhd_half"] = {"value": uw * uh * n / dtu / 1e6, "unit": "Mpix/s", "cores": O.threads(),
+                           "sample": f"{uw}x{uh} binary16, frames 0..{n - 1} ({dtu:.1f} s)"}
+    return out
 
 
 def main():
@@ -702,6 +771,11 @@ def main():
                 "hbm_achieved_gbs": round(hbm_gbs, 1),
                 "hbm_frac": round(hbm_gbs / HBM_PEAK_GBS, 4)}
     per_kernel = {k: {"us": round(v[0] * 1e3, 2), "launches": v[1]} for k, v in sorted(ktimes.items())}
+    # the spread of single frames, and the same chain replayed as a HIP graph
+    frame_us = frame_times(torch, frames_dev, MOTION, H, W, args.warmup, args.steps, tiles=tiles_2d)
+    graph = graph_replay(torch, frames_dev, MOTION, H, W, args.warmup, tiles=tiles_2d)
+    print(f"# per frame: {frame_us}; as a graph: {graph['ms_per_step'] * 1e3:.1f} us/frame",
+          file=sys.stderr, flush=True)
 
     variants = {}
     if "separable" in want:
@@ -750,7 +824,8 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(frames_np, warm=4, timed=6)
+        cpu = cpu_baseline(frames_np, warm=4, timed=4,
+                           uhd_np=vframes.get("uhd") if vframes else None)
 
     fb = frame_bytes_per_px(5, False)
     line = {
@@ -779,8 +854,11 @@ def main():
         # the whole frame against the HBM roofline at its algorithmic bytes:
         # the target is 0.60 of 8 TB/s
         "hbm_target": {"frame_hbm_frac": round(mpix * 1e6 * fb / 1e9 / HBM_PEAK_GBS, 4),
+                       "frame_copy_frac": round(mpix * 1e6 * fb / 1e9 / copy_gbs, 4),
                        "target": 0.60,
                        "met": bool(mpix * 1e6 * fb / 1e9 / HBM_PEAK_GBS >= 0.60)},
+        "frame_us": frame_us,
+        "graph_replay": graph,
         "frame_bytes_per_px": fb,
         "copy_probe_gbs": round(copy_gbs, 1),
         "per_kernel_us": per_kernel,
