@@ -11,12 +11,15 @@
 //                   on the cell's key (the lowest stratum index wins), and
 //                   the sample's luminance difference and maximum, stored
 //                   by stratum
-//   grad_gather_k   per cell: the winning stratum's difference and maximum,
-//                   and a presence flag
-//   grad_atrous_k   `levels` 5x5 B3 a-trous passes over the cells with a
-//                   depth edge weight, on (delta, norm, present) alike
-//   grad_alpha_k    per pixel: lambda = min(1, |delta| / norm) of its cell,
+//   grad_level_k    `levels` 5x5 B3 a-trous passes over the cells with a
+//                   depth edge weight, on (delta, norm, present) alike, in
+//                   LDS tiles (see below): the first gathers each cell's
+//                   winning stratum (difference, maximum, presence), the
+//                   last sets every pixel's blend factor from its cell,
+//                   lambda = min(1, |delta| / norm) and
 //                   alpha' = alpha + lambda (1 - alpha)
+// With no level, or past step 32, the same steps run as per-cell passes
+// (grad_gather_k, grad_atrous_k per level, grad_alpha_k per pixel).
 //
 // The normalized convolution is carried in a form with no underflow.  A
 // cell holds (d, m, l): the weighted means of delta and norm over the
