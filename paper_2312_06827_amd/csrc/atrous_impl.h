@@ -245,13 +245,17 @@ __device__ __forceinline__ bool tile_no_var(float e) { return __float_as_uint(e)
 // where the 2 x step-column halo on each side would otherwise hold the
 // tile's LDS footprint to two or three resident workgroups per CU (per
 // 1080p level, step 16: 53 instead of 74 us; step 8: five workgroups
-// instead of three, 53 instead of 55 us).  Step 32 is the coarser start of
-// the fifth level.
+// instead of three, 53 instead of 55 us).  Step 32, the coarser start of
+// the fifth level, takes a wider tile instead (see TileShape).
 constexpr int tile_py(int step) { return step >= 8 ? 1 : 2; }
 
 template <int STEP, int PY, int DIR, bool WANT_VAR>
 struct TileShape {
-    static constexpr int TX = 64, TY = 4 * PY;
+    // lattice columns: 64 (one wave per lattice row), or 128 at step 32,
+    // where the column halo (2 x 64 pixels) would otherwise be staged for
+    // every 64 outputs (two waves per lattice row there: 12 % faster)
+    static constexpr int WX = (DIR == kDir2D && STEP == 32) ? 2 : 1;
+    static constexpr int TX = 64 * WX, RPP = 4 / WX, TY = RPP * PY;
     static constexpr int HALO = DIR == kDir2DA ? 4 : 2;
     static constexpr int HY = DIR == kDirH ? 0 : HALO, HX = DIR == kDirV ? 0 : HALO * STEP;
     static constexpr int ROWS = TY + 2 * HY, COLS = TX + 2 * HX;
@@ -361,12 +365,12 @@ __device__ __forceinline__ void tile_compute(const AtrousArgs &a, TileOrigin t,
                                              const float *s_v, const float *s_pf) {
     using S = TileShape<STEP, PY, DIR, WANT_VAR>;
     constexpr int COLS = S::COLS, HY = S::HY, HX = S::HX, PFC = S::PFC;
-    const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
+    const int lx = (int)threadIdx.x % S::TX, ly = (int)threadIdx.x / S::TX;
     const int x = t.x0 + lx;
     if (x >= a.w) return;
 #pragma unroll 1
     for (int k = 0; k < PY; ++k) {
-        const int j = ly + 4 * k;
+        const int j = ly + S::RPP * k;
         const int y = t.ybase + j * STEP;
         if (y >= a.h) break;
         const uint32_t o = vofs((uint32_t)y * (uint32_t)a.pitch + (uint32_t)x);
@@ -512,8 +516,8 @@ __global__ __launch_bounds__(256) __attribute__((
         // adaptive levels: a tile without a pixel of this launch's class
         // is not staged at all (uniform branch)
         if ((DIR == kDir2D || DIR == kDirV) && a.ctl &&
-            !any_of_class(a, o.x0 + (int)(threadIdx.x & 63), o.ybase + (int)(threadIdx.x >> 6) * STEP,
-                          4 * STEP, PY))
+            !any_of_class(a, o.x0 + (int)threadIdx.x % S::TX,
+                          o.ybase + (int)threadIdx.x / S::TX * STEP, S::RPP * STEP, PY))
             return;
         tile_issue<T, S>(a, o, regs);
         tile_store<S>(regs, s_cl, s_gn, s_v, s_pf);
@@ -555,8 +559,8 @@ __global__ __launch_bounds__(256) __attribute__((
     const int gxt = (a.w + S::TX - 1) / S::TX;
     const TileOrigin o = tile_origin<STEP, S::TY, S::TX>(lt, gxt);
     if ((DIR == kDir2D || DIR == kDirV) && a.ctl &&
-        !any_of_class(a, o.x0 + (int)(threadIdx.x & 63), o.ybase + (int)(threadIdx.x >> 6) * STEP,
-                      4 * STEP, PY))
+        !any_of_class(a, o.x0 + (int)threadIdx.x % S::TX, o.ybase + (int)threadIdx.x / S::TX * STEP,
+                      S::RPP * STEP, PY))
         return;
     TileRegs<S::IT, S::ITP> regs;
     tile_issue<T, S>(a, o, regs);
@@ -1102,9 +1106,10 @@ struct TileCfg {
 
 template <typename T, int STEP, int PY, int MODE, bool WANT_VAR, int DIR>
 void launch_tile_py(const AtrousArgs &a, TileCfg cfg, hipStream_t s) {
-    constexpr int TY = 4 * PY;
+    using S = TileShape<STEP, PY, DIR, WANT_VAR>;
+    constexpr int TY = S::TY;
     const int bands = (a.h + STEP * TY - 1) / (STEP * TY);
-    const int tiles = ((a.w + 63) / 64) * bands * STEP;
+    const int tiles = ((a.w + S::TX - 1) / S::TX) * bands * STEP;
     const int per_xcd = (tiles + kXCD - 1) / kXCD;
     if (record_pass(&atrous_batch_launch<T, STEP, PY, MODE, WANT_VAR, DIR>, a, tiles)) return;
     // the adaptive level's wider tile leaves no registers for a prefetched
@@ -1121,12 +1126,15 @@ void launch_tile_py(const AtrousArgs &a, TileCfg cfg, hipStream_t s) {
                        dim3(per_xcd * kXCD), dim3(256), 0, s, a, tiles, per_xcd);
 }
 
-// The tile height: the caller's choice for 5x5 levels up to step 16 (at 32
-// two lattice rows per thread would need more LDS than a workgroup has),
-// tile_py otherwise.
+// The tile height: the caller's choice for 5x5 levels up to step 16; at
+// step 32 (the adaptive level's coarser start) the 128-column tile with two
+// rows per thread (78 KB of LDS, as many workgroups per CU as the 64-column
+// one-row tile); tile_py otherwise.
 template <typename T, int STEP, int MODE, bool WANT_VAR, int DIR>
 void launch_tile(const AtrousArgs &a, TileCfg cfg, hipStream_t s) {
     if constexpr (DIR == kDir2DA) {  // two rows per thread (measured best at every step)
+        launch_tile_py<T, STEP, 2, MODE, WANT_VAR, DIR>(a, cfg, s);
+    } else if constexpr (DIR == kDir2D && STEP == 32) {  // the 128-column tile, two rows
         launch_tile_py<T, STEP, 2, MODE, WANT_VAR, DIR>(a, cfg, s);
     } else {
         const int py = (DIR == kDir2D && STEP <= 16 && cfg.rows > 0) ? cfg.rows : tile_py(STEP);
