@@ -383,12 +383,18 @@ def _batch_vs_singles(torch, scfg, frames_np, warmup, tune):
     ms_b = _timed_frames(torch, batch.frame, frames, warmup)
     passes = batch.passes()
     batch.close()
+    # the same plan with its passes launched one by one instead of a graph
+    direct = BatchDenoiser(sizes, MOTION, torch.float16, tiles=tiles, graph=False)
+    ms_d = _timed_frames(torch, direct.frame, frames, warmup)
+    direct.close()
     singles = [Denoiser(h, w, MOTION, torch.float16, tiles=tiles) for h, w in sizes]
     ms_s = _timed_frames(torch, lambda fr: [d.frame(x) for d, x in zip(singles, fr)], frames, warmup)
     return {"value": round(px / (ms_b * 1e-3) / 1e6, 1), "unit": "Mpix/s",
             "ms_per_step": round(ms_b, 4), "launches_per_frame": passes,
             "launch_shapes": tiles and [list(t) for t in tiles],
             "tuned_at": f"{mw}x{mh}",
+            "direct_launches": {"value": round(px / (ms_d * 1e-3) / 1e6, 1),
+                                "ms_per_step": round(ms_d, 4)},
             "one_by_one": {"value": round(px / (ms_s * 1e-3) / 1e6, 1), "ms_per_step": round(ms_s, 4),
                            "launches_per_frame": len(sizes) * passes},
             "config": f"{len(sizes)} streams {min(sizes)}..{max(sizes)} (HxW), {px / 1e6:.1f} Mpix "
@@ -801,11 +807,13 @@ def main():
                                               vframes["small_cfg"], vframes["small"],
                                               tune=not args.no_tune)
         bv = variants["batched"]
-        print(f"# 16 streams batched: {bv['ms_per_step'] * 1e3:.1f} us/frame (one by one"
+        sm = bv['small_streams']
+        print(f"# 16 streams batched: {bv['ms_per_step'] * 1e3:.1f} us/frame (direct "
+              f"{bv['direct_launches']['ms_per_step'] * 1e3:.1f}, one by one"
               f" {bv['one_by_one']['ms_per_step'] * 1e3:.1f}); 64 small streams: "
-              f"{bv['small_streams']['ms_per_step'] * 1e3:.1f} us/frame (one by one "
-              f"{bv['small_streams']['one_by_one']['ms_per_step'] * 1e3:.1f})",
-              file=sys.stderr, flush=True)
+              f"{sm['ms_per_step'] * 1e3:.1f} us/frame (direct "
+              f"{sm['direct_launches']['ms_per_step'] * 1e3:.1f}, one by one "
+              f"{sm['one_by_one']['ms_per_step'] * 1e3:.1f})", file=sys.stderr, flush=True)
     if "channels" in want:
         variants["channels"] = variant_channels(torch, vframes["channels"])
         print(f"# channels: {variants['channels']}", file=sys.stderr, flush=True)

@@ -672,6 +672,14 @@ int sv_batch_frame(sv_batch *b, const sv_frame_in *in, sv_stream stream);
  * a NULL plan. */
 int sv_batch_passes(const sv_batch *b);
 
+/* How later sv_batch_frame calls launch the passes: 0 (default) replays
+ * the frame's HIP graph, 1 launches the same batched passes one by one on
+ * the caller's stream (no graph; with large streams each launch already
+ * fills the GPU, and the graph's kernel nodes measured slower there).
+ * Results are bitwise the same either way.  SV_EINVAL for a NULL plan or a
+ * value other than 0 or 1. */
+int sv_batch_set_direct(sv_batch *b, int32_t direct);
+
 void sv_batch_destroy(sv_batch *b);
 
 /* ---- misc --------------------------------------------------------------- */

@@ -38,6 +38,7 @@ struct sv_batch {
     unsigned char *host[2] = {nullptr, nullptr};
     hipEvent_t ev[2] = {nullptr, nullptr};
     int parity = 0;
+    bool direct = false;  // launch the passes each frame instead of replaying the graph
     bool broken = false;  // a failed allocation or capture: the plan is unusable
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
@@ -209,6 +210,12 @@ extern "C" int sv_batch_frame(sv_batch *b, const sv_frame_in *in, sv_stream stre
     if (hipMemcpyAsync(b->dev, h, b->bytes, hipMemcpyHostToDevice, s) != hipSuccess) return SV_EHIP;
     if (hipEventRecord(b->ev[b->parity], s) != hipSuccess) return SV_EHIP;
     b->parity ^= 1;
+    if (b->direct) {  // the same passes, launched on the caller's stream
+        for (int k = 0; k < b->npass; ++k)
+            b->fn[k](b->dev + b->off_args[k], (const int *)(b->dev + b->off_prefix[k]), b->n,
+                     b->total[k], s);
+        return hip_status(hipGetLastError());
+    }
     if (first) {
         rc = capture(b);
         if (rc != SV_OK) {
@@ -217,6 +224,12 @@ extern "C" int sv_batch_frame(sv_batch *b, const sv_frame_in *in, sv_stream stre
         }
     }
     return hip_status(hipGraphLaunch(b->exec, s));
+}
+
+extern "C" int sv_batch_set_direct(sv_batch *b, int32_t direct) {
+    if (!b || (direct != 0 && direct != 1)) return SV_EINVAL;
+    b->direct = direct != 0;
+    return SV_OK;
 }
 
 extern "C" int sv_batch_passes(const sv_batch *b) { return b ? b->npass : -1; }

@@ -177,6 +177,7 @@ EXPORTS = {
                               _P(sv_frame_params), _P(_vp)], ctypes.c_int),
     "sv_batch_frame": ([_vp, _P(sv_frame_in), _vp], ctypes.c_int),
     "sv_batch_passes": ([_vp], ctypes.c_int),
+    "sv_batch_set_direct": ([_vp, ctypes.c_int32], ctypes.c_int),
     "sv_batch_destroy": ([_vp], None),
     "sv_struct_sizes": ([_P(ctypes.c_size_t), ctypes.c_int32], ctypes.c_int),
     "sv_status_str": ([ctypes.c_int], ctypes.c_char_p),

@@ -299,9 +299,12 @@ class BatchDenoiser:
     results are bitwise those of that Denoiser run alone."""
 
     def __init__(self, sizes, cfg=MOTION, dtype: torch.dtype = torch.float32,
-                 tiles=None, device: str = "cuda", mlp: Optional[lib.MLP] = None):
+                 tiles=None, device: str = "cuda", mlp: Optional[lib.MLP] = None,
+                 graph: bool = True):
         """cfg: one FilterConfig for every stream, or a list with one per
-        stream (the streams must then run the same kernels pass by pass)."""
+        stream (the streams must then run the same kernels pass by pass).
+        graph: replay the frame's passes as a HIP graph (else launch them
+        one by one; the same results)."""
         cfgs = list(cfg) if isinstance(cfg, (list, tuple)) else [cfg] * len(sizes)
         if len(cfgs) != len(sizes):
             raise ValueError("one FilterConfig per stream")
@@ -317,6 +320,7 @@ class BatchDenoiser:
         lib._check("sv_batch_create_each", so.sv_batch_create_each(
             self._dims, self._states, n, self.streams[0]._dtype, self._params,
             ctypes.byref(self._plan)))
+        lib._check("sv_batch_set_direct", so.sv_batch_set_direct(self._plan, 0 if graph else 1))
 
     def frame(self, inputs, stream=None):
         """One frame of every stream; inputs[i] are stream i's FrameInputs.

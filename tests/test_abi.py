@@ -324,3 +324,8 @@ def test_gradient_validation(so):
     assert so.sv_temporal_gradient(*args(work + 8)) == L.SV_EINVAL
     assert so.sv_temporal_gradient(*args(work, L.sv_grad_params(0.2, 0.1, 1.0, 9))) == L.SV_EINVAL
     assert so.sv_temporal_gradient(*args(A + 8 * STRIDE)) == L.SV_EALIAS
+
+
+def test_batch_set_direct_validation(so):
+    assert so.sv_batch_set_direct(None, 0) == L.SV_EINVAL
+    assert so.sv_batch_set_direct(None, 1) == L.SV_EINVAL

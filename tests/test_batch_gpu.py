@@ -23,21 +23,25 @@ def _streams(half, frames):
     return [with_size(c, w, h, frames) for c, (h, w) in zip(base, SIZES)]
 
 
-@pytest.mark.parametrize("half,sep,levels,feedback,rows", [
-    (False, False, 5, "atrous0", 0), (True, False, 5, "atrous0", 0), (True, True, 5, "atrous0", 0),
-    (False, True, 3, "temporal", 0), (False, False, 1, "temporal", 0),
-    (True, False, 5, "atrous0", 1), (False, True, 5, "atrous0", 6)])
-def test_batch_equals_single_streams(half, sep, levels, feedback, rows):
+@pytest.mark.parametrize("half,sep,levels,feedback,rows,graph", [
+    (False, False, 5, "atrous0", 0, True), (True, False, 5, "atrous0", 0, True),
+    (True, True, 5, "atrous0", 0, True), (False, True, 3, "temporal", 0, True),
+    (False, False, 1, "temporal", 0, True), (True, False, 5, "atrous0", 1, True),
+    (False, True, 5, "atrous0", 6, True), (False, False, 5, "atrous0", 0, False),
+    (True, True, 5, "atrous0", 0, False)])
+def test_batch_equals_single_streams(half, sep, levels, feedback, rows, graph):
     """rows: tile height of every level (0: the library default), as the
-    autotuner passes it, in the batched launches and the single ones."""
+    autotuner passes it, in the batched launches and the single ones.
+    graph: the plan's passes replayed as a HIP graph, or launched one by
+    one."""
     dt = torch.float16 if half else torch.float32
     cfg = replace(MOTION_SEP if sep else MOTION, levels=levels, feedback=feedback)
     frames = 5
     scfg = _streams(half, frames)
     tiles = [(0, 0, rows)] * levels if rows else None
     say(f"batch: {len(SIZES)} streams half={half} sep={sep} levels={levels} feedback={feedback}"
-        f" rows={rows}")
-    batch = BatchDenoiser(SIZES, cfg, dt, tiles=tiles)
+        f" rows={rows} graph={graph}")
+    batch = BatchDenoiser(SIZES, cfg, dt, tiles=tiles, graph=graph)
     singles = [Denoiser(h, w, cfg, dt, tiles=tiles) for (h, w) in SIZES]
     try:
         for f in range(frames):
