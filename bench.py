@@ -543,18 +543,26 @@ def variant_channels(torch, frames_np, warmup=CH_WARMUP, steps=CH_STEPS):
     clean = [t(fr["composite_clean"]) for fr in frames_np]
     out = {"config": f"{W}x{H}, two channels, {steps} frames timed after {warmup}"}
     for adaptive in (True, False):
+        timed = {}
+        for graph in (True, False):  # the batch plan as a graph, or launched directly
+            den = ChannelDenoiser(H, W, adaptive=adaptive, graph=graph)
+            step = lambda i: den.frame(geo[i], planes[i]["shadow"], planes[i]["spec"],
+                                       planes[i]["direct"], roughness=planes[i]["roughness"],
+                                       shadow_angle=planes[i]["shadow_angle"])
+            timed[graph] = _timed_frames(torch, step, list(range(len(geo))), warmup)
+            den.close()
+        ms = timed[True]
         den = ChannelDenoiser(H, W, adaptive=adaptive)
         step = lambda i: den.frame(geo[i], planes[i]["shadow"], planes[i]["spec"],
                                    planes[i]["direct"], roughness=planes[i]["roughness"],
                                    shadow_angle=planes[i]["shadow_angle"])
-        ms = _timed_frames(torch, step, list(range(len(geo))), warmup)
-        den.close()
-        den = ChannelDenoiser(H, W, adaptive=adaptive)
         q = float(np.mean([learn.relmse(step(i), clean[i]) for i in range(len(geo))][warmup:]))
         den.close()
         out["adaptive" if adaptive else "fixed"] = {
             "value": round(H * W / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 4),
-            "relmse": round(q, 6)}
+            "relmse": round(q, 6),
+            "direct_launches": {"value": round(H * W / (timed[False] * 1e-3) / 1e6, 1),
+                                "ms_per_step": round(timed[False], 4)}}
     # one filter over the noisy composite (direct * shadow sample + specular sample)
     comp = [FrameInputs.from_numpy({**fr, "rgb": fr["direct"] * fr["shadow"] + fr["spec"]})
             for fr in frames_np]

@@ -361,10 +361,12 @@ class ChannelDenoiser:
 
     def __init__(self, height: int, width: int, shadow: FilterConfig = SHADOW,
                  specular: FilterConfig = SPECULAR, dtype: torch.dtype = torch.float32,
-                 adaptive: bool = True, device: str = "cuda"):
+                 adaptive: bool = True, device: str = "cuda", graph: bool = True):
+        """graph: the batch plan replays its passes as a HIP graph (else it
+        launches them one by one; the same results)."""
         self.H, self.W, self.adaptive = height, width, adaptive
         self.batch = BatchDenoiser([(height, width)] * 2, [shadow, specular], dtype,
-                                   device=device)
+                                   device=device, graph=graph)
         dev = torch.device(device)
         self.out = torch.zeros((3, height, width), dtype=dtype, device=dev)
         self.ctl = [torch.zeros((height, width), dtype=torch.uint8, device=dev) for _ in range(2)]
