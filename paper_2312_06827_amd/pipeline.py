@@ -200,6 +200,46 @@ class Denoiser:
         self.k = 0
         self.frames = 0
 
+    # ---- checkpoint / resume ------------------------------------------
+    # Between frames the stream's state is its history buffers (both
+    # halves of each ping-pong pair, and the temporal output that the
+    # "temporal" feedback reads back), the index of the current half and
+    # the frame count; everything else a frame writes before reading.
+
+    def _state_tensors(self) -> Dict[str, torch.Tensor]:
+        out = {}
+        for name in ("c_hist", "m1", "m2c", "n"):
+            for i, t in enumerate(getattr(self, name)):
+                out[f"{name}{i}"] = t
+        out["t_rgb"] = self.t_rgb[0]
+        return out
+
+    def save_state(self, path: str):
+        """Write the stream's state to `path` (.npz; waits for the device)."""
+        torch.cuda.synchronize()
+        arrays = {k: t.cpu().numpy() for k, t in self._state_tensors().items()}
+        np.savez(path, k=np.int32(self.k), frames=np.int64(self.frames),
+                 dims=np.array([self.H, self.W], np.int64), **arrays)
+
+    def load_state(self, path: str):
+        """Resume from a state written by save_state for the same size and
+        storage type: the next frame continues bitwise as the saved stream
+        would have."""
+        with np.load(path, allow_pickle=False) as f:
+            if tuple(int(v) for v in f["dims"]) != (self.H, self.W):
+                raise ValueError(f"state of a {tuple(f['dims'])} stream, this one is "
+                                 f"{(self.H, self.W)}")
+            for name, t in self._state_tensors().items():
+                a = f[name]
+                want = torch.empty(0, dtype=t.dtype).numpy().dtype
+                if a.shape != tuple(t.shape) or a.dtype != want:
+                    raise ValueError(f"{name}: {a.dtype}{a.shape} does not fit "
+                                     f"{t.dtype}{tuple(t.shape)}")
+                t.copy_(torch.from_numpy(a))
+            self.k = int(f["k"])
+            self.frames = int(f["frames"])
+        torch.cuda.synchronize()
+
     def state(self) -> Dict[str, torch.Tensor]:
         """The history the next frame will read."""
         k = self.k
