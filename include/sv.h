@@ -252,11 +252,16 @@ int sv_variance(const float *m1, const float *m2c, const uint8_t *n,
                 const sv_variance_params *p, sv_stream stream);
 
 /* Size in bytes of the `work` buffer sv_variance needs for dims d (0 for
- * invalid dims): eight counters and a list of the short-history pixels.
- * The caller allocates it on the device and ZEROES it before its first
- * use; every call returns the counters to zero, so one buffer serves any
- * number of calls in order on one stream (calls that may run concurrently
- * need one buffer each).  It must not overlap any input or `var`. */
+ * invalid dims): eight lines of counters and a list of the short-history
+ * pixels.  The caller allocates it on the device and ZEROES it before its
+ * first use.  The counters are never reset: each listing pass (sv_variance,
+ * or sv_temporal with var_work) appends after what the last sv_variance
+ * read, and each sv_variance leaves them consistent for the next call, so
+ * one buffer sized for the largest dims serves any number of calls of any
+ * size, in order on one stream (calls that may run concurrently need one
+ * buffer each).  A list sv_temporal wrote must be read by sv_variance with
+ * SV_V_LISTED before the next listing pass.  It must not overlap any input
+ * or `var`. */
 size_t sv_variance_work_bytes(sv_dims d);
 
 /* sv_variance without the `work` argument, for callers that cannot

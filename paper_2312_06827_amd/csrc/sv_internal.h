@@ -200,15 +200,27 @@ inline unsigned xcd_grid(int tiles) { return (unsigned)(((tiles + kXCD - 1) / kX
 // ---- short-history list of the variance estimate ---------------------------
 //
 // Pixels whose history is too short for the temporal variance are listed
-// for a spatial estimate.  Workspace: eight counters (128 bytes apart),
+// for a spatial estimate.  Workspace: eight 128-byte lines of counters,
 // then eight sublists; the 64x4-pixel tile t appends to sublist t % 8, so a
 // sublist holds at most ceil(tiles / 8) tiles' pixels (its capacity `cap`)
 // whichever workgroup runs the tile.  Entries are (y << 15) | x.
+//
+// The counters are never reset.  Line k holds three words of sublist k:
+//   kCount  the number of appends so far (atomic, wraps modulo 2^32);
+//   kNext   its value when the last reading pass ran: an appending pass
+//           stores entry i of its own appends at slot i = count - next;
+//   kBase   the same value, copied by the appending pass's tile 0 for the
+//           reading pass, which lists the count - base entries and then
+//           sets next = count.
+// Each word is written by one kind of pass and read only by the other, and
+// passes are ordered on one stream, so no pass reads a word that another
+// workgroup of the same launch writes.  A zeroed workspace is consistent.
 constexpr int kVX = 64, kVY = 4;
 constexpr int kLines = 32;
+constexpr int kCount = 0, kBase = 1, kNext = 2;
 
 struct VarWork {
-    uint32_t count[kXCD * kLines];  // count[k * kLines]: entries in sublist k
+    uint32_t count[kXCD * kLines];  // count[k * kLines + kCount | kBase | kNext]
     uint32_t list[1];               // sublist k at list + k * cap
 };
 
@@ -225,12 +237,18 @@ __device__ __forceinline__ void list_short_pixel(VarWork *work, uint32_t cap, in
     const uint64_t mask = __ballot(spatial);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0) wave_n[wave] = (uint32_t)__popcll(mask);
+    // tile 0 (every launch has it) hands each sublist's start to the
+    // reading pass, also for sublists that no tile of this launch reaches
+    if (tile == 0 && threadIdx.x < kXCD)
+        work->count[threadIdx.x * kLines + kBase] = work->count[threadIdx.x * kLines + kNext];
     __syncthreads();
     const uint32_t n0 = wave_n[0], n1 = wave_n[1], n2 = wave_n[2], n3 = wave_n[3];
     const uint32_t total = n0 + n1 + n2 + n3;
     if (total == 0) return;  // uniform over the workgroup
     const uint32_t k = (uint32_t)tile % kXCD;
-    if (threadIdx.x == 0) base_sh = atomicAdd(&work->count[k * kLines], total);
+    if (threadIdx.x == 0)
+        base_sh = atomicAdd(&work->count[k * kLines + kCount], total) -
+                  work->count[k * kLines + kNext];
     __syncthreads();
     const uint32_t before = (wave > 0 ? n0 : 0u) + (wave > 1 ? n1 : 0u) + (wave > 2 ? n2 : 0u);
     const uint32_t slot = base_sh + before + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));

@@ -64,13 +64,14 @@ __global__ __launch_bounds__(256) void variance_point_batch_k(const VarianceArgs
     variance_point_tile<T>(a, lt, wave_n, base_sh);
 }
 
+// Zero state of a workspace's counters (the allocation-free entry point's
+// shared array, which another call may have left in any state).
 __global__ __launch_bounds__(64) void variance_reset_k(VarWork *w) {
-    if (threadIdx.x < kXCD) w->count[threadIdx.x * kLines] = 0;
-}
-
-__global__ __launch_bounds__(256) void variance_reset_batch_k(const VarianceArgs *args, int n) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n * kXCD) args[i / kXCD].work->count[(i % kXCD) * kLines] = 0;
+    if (threadIdx.x < kXCD) {
+        w->count[threadIdx.x * kLines + kCount] = 0;
+        w->count[threadIdx.x * kLines + kBase] = 0;
+        w->count[threadIdx.x * kLines + kNext] = 0;
+    }
 }
 
 // Sum over the 8 lanes of an aligned lane group (butterfly: a fixed order,
@@ -91,8 +92,15 @@ __device__ __forceinline__ void variance_spatial_stream(const VarianceArgs &a) {
     uint32_t pre[kXCD + 1];
     pre[0] = 0;
 #pragma unroll
-    for (int k = 0; k < kXCD; ++k) pre[k + 1] = pre[k] + min(a.work->count[k * kLines], a.cap);
+    for (int k = 0; k < kXCD; ++k)
+        pre[k + 1] = pre[k] + min(a.work->count[k * kLines + kCount] -
+                                      a.work->count[k * kLines + kBase],
+                                  a.cap);
     const uint32_t count = pre[kXCD];
+    // the list is consumed: the next appending pass starts after it (no
+    // workgroup of this pass reads kNext)
+    if (blockIdx.x == 0 && threadIdx.x < kXCD)
+        a.work->count[threadIdx.x * kLines + kNext] = a.work->count[threadIdx.x * kLines + kCount];
     const int sub = threadIdx.x & 7;
     const uint32_t groups = gridDim.x * (blockDim.x / 8);
     for (uint32_t e = blockIdx.x * (blockDim.x / 8) + (threadIdx.x >> 3); e < count; e += groups) {
@@ -189,11 +197,6 @@ static void spatial_batch_launch(const void *args, const int *, int n, int, hipS
                        (const VarianceArgs *)args, n);
 }
 
-static void reset_batch_launch(const void *args, const int *, int n, int, hipStream_t s) {
-    hipLaunchKernelGGL(variance_reset_batch_k, dim3((n * kXCD + 255) / 256), dim3(256), 0, s,
-                       (const VarianceArgs *)args, n);
-}
-
 template <typename T, int R>
 void launch_spatial(const VarianceArgs &a, hipStream_t s) {
     if (record_pass(&spatial_batch_launch<T, R>, a, 0)) return;
@@ -216,8 +219,6 @@ void launch_variance(const VarianceArgs &a, unsigned grid, int radius, bool list
     case 6: launch_spatial<T, 6>(a, s); break;
     default: launch_spatial<T, 7>(a, s); break;
     }
-    if (!record_pass(&reset_batch_launch, a, 0))
-        hipLaunchKernelGGL(variance_reset_k, dim3(1), dim3(64), 0, s, a.work);
 }
 
 }  // namespace sv

@@ -117,3 +117,11 @@ def check_guards():
             bad.append((tuple(full.shape), width, str(full.dtype)))
     GUARDED.clear()
     assert not bad, f"writes into the row padding of pitched outputs: {bad}"
+
+
+def list_consumed(work):
+    """Whether the variance workspace's short-history list has been read:
+    each of the eight counter lines (32 words) holds its append count in
+    word 0 and, once the reading pass has run, the same value in word 2."""
+    c = work[:256].view(8, 32).cpu()
+    return bool((c[:, 0] == c[:, 2]).all())

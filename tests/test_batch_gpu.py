@@ -58,7 +58,7 @@ def test_batch_equals_single_streams(half, sep, levels, feedback, rows, graph):
                                      ("var", b.var, d.var)]:
                     assert torch.equal(tb, td), (f, i, name)
             say(f"  frame {f}: {len(SIZES)} streams bitwise equal; {batch.passes()} launches per frame")
-        assert batch.passes() == 3 + levels  # temporal, variance x2, one per level (separable fused)
+        assert batch.passes() == 2 + levels  # temporal, variance, one per level (separable fused)
     finally:
         batch.close()
 
@@ -174,6 +174,6 @@ def test_batch_with_adaptive_levels_and_per_stream_settings(sep):
             say(f"  frame {f}: bitwise equal; {batch.passes()} launches per frame")
         # the 5x5 adaptive levels at steps 1 to 8 are one launch each, the one
         # at step 16 and the separable ones two (one per step class)
-        assert batch.passes() == 3 + (2 * 5 if sep else 4 + 2)
+        assert batch.passes() == 2 + (2 * 5 if sep else 4 + 2)
     finally:
         batch.close()

@@ -184,7 +184,7 @@ def test_channel_batch_equals_channels_alone():
             assert torch.equal(den.batch.streams[1].out, outs[1])
             assert torch.equal(out, ref)
         # temporal, variance x2, one launch per adaptive level (steps 1 to 8)
-        assert den.batch.passes() == 3 + 4
+        assert den.batch.passes() == 2 + 4
     finally:
         den.close()
 

@@ -14,7 +14,7 @@ import torch
 import oracle as O
 from paper_2312_06827_amd import lib as L
 from paper_2312_06827_amd.scene import CONFIGS, render_frame, with_size
-from tests._util import guard, guard_value, rel_err, random_gbuf, say, worst
+from tests._util import guard, guard_value, list_consumed, rel_err, random_gbuf, say, worst
 
 pytestmark = pytest.mark.gpu
 
@@ -292,9 +292,36 @@ def test_variance(H, W):
                       work)
         L.sv_variance(dev(m1, W + 2), dev(m2c, W + 2), dev(hn, W + 2, torch.uint8),
                       gbuf_dev(z, dzdx, dzdy, n, W + 2), out, L.VarianceParams(sigma_n=sigma_n),
-                      work)  # a second call: the workspace is back to zero
-        assert int(work[:256].abs().sum().item()) == 0  # the eight counters
+                      work)  # a second call continues from the first one's counters
+        assert list_consumed(work)
         ref = O.variance(m1, m2, hn, z, dzdx, dzdy, n, sigma_n=sigma_n)
+        assert rel_err(host(out), ref) <= TOL32
+
+
+def test_variance_workspace_across_sizes():
+    """One workspace, sized for the largest frame, serves calls of any
+    smaller size in any order: the list of one call never leaks into the
+    next, also when the smaller image has fewer than eight tiles (sublists
+    that no tile of the call reaches)."""
+    big, small = (37, 300), (4, 64)
+    r = np.random.default_rng(311)
+    cases = {}
+    for H, W in (big, small):
+        z, dzdx, dzdy, n = random_gbuf(r, H, W)
+        m1 = r.uniform(0.1, 1.0, (H, W)).astype(np.float32)
+        m2c = (m1 * m1 * r.uniform(0.0, 1.0, (H, W))).astype(np.float32)
+        hn = r.integers(0, 7, (H, W)).astype(np.uint8)
+        ref = O.variance(m1, m2c.astype(np.float64) + m1.astype(np.float64) ** 2, hn, z, dzdx,
+                         dzdy, n)
+        cases[(H, W)] = (m1, m2c, hn, gbuf_dev(z, dzdx, dzdy, n), ref)
+    work = L.variance_workspace(empty_like_dev(big))
+    for H, W in (big, small, small, big, small):
+        m1, m2c, hn, g, ref = cases[(H, W)]
+        say(f"variance {H}x{W} on a workspace for {big}")
+        out = empty_like_dev((H, W))
+        L.sv_variance(dev(m1), dev(m2c), dev(hn, None, torch.uint8), g, out, L.VarianceParams(),
+                      work)
+        assert list_consumed(work)
         assert rel_err(host(out), ref) <= TOL32
 
 
@@ -493,7 +520,7 @@ def test_temporal_variance_listing_equals_variance_pass(H, W):
                       var=var if fused else None, var_work=work if fused else None)
         L.sv_variance(om1, om2, on, g, var, L.VarianceParams(listed=fused), work)
         res.append((host(out), host(var)))
-        assert int(work[:256].abs().sum().item()) == 0
+        assert list_consumed(work)
     for r in res[1:]:
         np.testing.assert_array_equal(r[0], res[0][0])
         np.testing.assert_array_equal(r[1], res[0][1])
