@@ -502,18 +502,20 @@ def test_atrous_sep_fused_equals_two_pass(H, W, dtype):
 def test_temporal_variance_listing_equals_variance_pass(H, W):
     """sv_temporal writing the variance's pointwise part and its list, then
     sv_variance(listed), gives bitwise what sv_temporal then sv_variance
-    give; twice in a row (the workspace returns to zero)."""
+    give; twice in a row on one workspace (the second listing starts after
+    what the first reading pass consumed)."""
     fr, st = _temporal_case(H, W, 57 + H)
     g = gbuf_dev(fr["z"], fr["dzdx"], fr["dzdy"], fr["n"], None, fr["id"])
     prev = L.GBuf(dev(fr["prev_z"]), None, None, dev(fr["prev_n"]), dev(fr["prev_id"], None, torch.uint8))
     tp = L.TemporalParams(clamp=True, tonemap=True, use_id=True)
     res = []
+    shared = L.variance_workspace(empty_like_dev((H, W)))
     for fused in (False, True, True):
         out = empty_like_dev((3, H, W))
         om1, om2 = empty_like_dev((H, W)), empty_like_dev((H, W))
         on = empty_like_dev((H, W), dtype=torch.uint8)
         var = empty_like_dev((H, W))
-        work = L.variance_workspace(var)
+        work = shared if fused else L.variance_workspace(var)
         say(f"temporal + variance listing {H}x{W} fused={fused}")
         L.sv_temporal(dev(fr["rgb"]), g, dev(fr["mv"]), prev, dev(st["rgb"]), dev(st["m1"]),
                       dev(st["m2c"]), dev(st["n"], None, torch.uint8), out, om1, om2, on, tp,
@@ -524,3 +526,40 @@ def test_temporal_variance_listing_equals_variance_pass(H, W):
     for r in res[1:]:
         np.testing.assert_array_equal(r[0], res[0][0])
         np.testing.assert_array_equal(r[1], res[0][1])
+
+
+def test_temporal_variance_listing_across_sizes():
+    """The listing path (sv_temporal's list read by sv_variance with
+    SV_V_LISTED) on one workspace sized for the largest frame, with frames
+    of two sizes in turn, the smaller one under eight tiles: each frame's
+    variance equals, bitwise, the two-pass variance on a fresh workspace."""
+    big, small = (130, 200), (4, 64)
+    tp = L.TemporalParams(clamp=True, tonemap=True, use_id=True)
+    cases = {}
+    for H, W in (big, small):
+        fr, st = _temporal_case(H, W, 91 + H)
+        g = gbuf_dev(fr["z"], fr["dzdx"], fr["dzdy"], fr["n"], None, fr["id"])
+        prev = L.GBuf(dev(fr["prev_z"]), None, None, dev(fr["prev_n"]),
+                      dev(fr["prev_id"], None, torch.uint8))
+        cases[(H, W)] = (fr, st, g, prev)
+
+    def run(H, W, work, fused):
+        fr, st, g, prev = cases[(H, W)]
+        out = empty_like_dev((3, H, W))
+        om1, om2 = empty_like_dev((H, W)), empty_like_dev((H, W))
+        on = empty_like_dev((H, W), dtype=torch.uint8)
+        var = empty_like_dev((H, W))
+        if work is None:
+            work = L.variance_workspace(var)
+        L.sv_temporal(dev(fr["rgb"]), g, dev(fr["mv"]), prev, dev(st["rgb"]), dev(st["m1"]),
+                      dev(st["m2c"]), dev(st["n"], None, torch.uint8), out, om1, om2, on, tp,
+                      var=var if fused else None, var_work=work if fused else None)
+        L.sv_variance(om1, om2, on, g, var, L.VarianceParams(listed=fused), work)
+        assert list_consumed(work)
+        return host(var)
+
+    ref = {hw: run(*hw, None, False) for hw in (big, small)}
+    shared = L.variance_workspace(empty_like_dev(big))
+    for hw in (big, small, small, big, small):
+        say(f"temporal listing {hw} on a workspace for {big}")
+        np.testing.assert_array_equal(run(*hw, shared, True), ref[hw])
