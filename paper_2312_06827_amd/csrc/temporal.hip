@@ -428,18 +428,21 @@ __device__ __forceinline__ void px_blend(const TemporalArgs &a, const PxState &s
 // features go through LDS into the matrix operands of its wave's two
 // 32-pixel blocks; returns this lane's alpha and kappa.  Every thread of
 // the workgroup must call it (barrier and matrix instructions).
-__device__ __forceinline__ void px_network(const TemporalArgs &a, uint4 *s_feat,
+// The network's parameters come from the workgroup's LDS copy (`ns`: this
+// thread's share of it, loaded earlier): the pass is bound by its load path,
+// which per-lane weight loads would add to.
+__device__ __forceinline__ void px_network(const TemporalArgs &a, uint4 *s_feat, uint16_t *s_w,
+                                           float *s_b, const NetStage &ns,
                                            const float (&f)[SV_MLP_IN], float &alpha,
                                            float &kappa) {
     uint32_t pk[8];
     standardise_pack(a, f, pk);
     s_feat[2 * threadIdx.x] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
     s_feat[2 * threadIdx.x + 1] = make_uint4(pk[4], pk[5], pk[6], pk[7]);
+    net_store(ns, s_w, s_b);
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int col = lane & 31, hf = lane >> 5;
-    FwdW w;
-    load_fwd(a.mparams, a.mwq, col, hf, w);
     float o0 = 0.f, o1 = 0.f;
 #pragma unroll
     for (int blk = 0; blk < 2; ++blk) {
@@ -454,7 +457,7 @@ __device__ __forceinline__ void px_network(const TemporalArgs &a, uint4 *s_feat,
             x[kb][3] = (short)(v.y >> 16);
         }
         FwdOut r;
-        forward_block(a.mparams, w, x, hf, r);
+        forward_block_lds(s_w, s_b, col, hf, x, r);
         // lanes l and l + 32 both hold pixel blk * 32 + l % 32's outputs:
         // lane l keeps the block that contains its own pixel (blk == l / 32)
         if (blk == hf) {
@@ -473,8 +476,8 @@ enum { kBlend = 0, kFeat = 1, kLearn = 2 };
 
 template <typename T, int RECT, bool USE_ID, int MODE>
 __device__ __forceinline__ void temporal_tile(const TemporalArgs &a, float4 *tile, uint4 *s_feat,
-                                              uint32_t *wave_n, uint32_t &base_sh, int bx,
-                                              int by) {
+                                              uint16_t *s_w, float *s_b, uint32_t *wave_n,
+                                              uint32_t &base_sh, int bx, int by) {
     const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
     const int x = bx * kTX + lx, y = by * kTY + ly;
     PxLoads g;
@@ -496,9 +499,11 @@ __device__ __forceinline__ void temporal_tile(const TemporalArgs &a, float4 *til
     }
     float alpha = a.alpha;
     if (MODE == kLearn) {
+        NetStage ns;
+        net_issue(a.mparams, a.mwq, ns);  // in flight while the features are formed
         float f[SV_MLP_IN], kappa;
         px_features<T>(a, tile, lx, ly, s, f);
-        px_network(a, s_feat, f, alpha, kappa);
+        px_network(a, s_feat, s_w, s_b, ns, f, alpha, kappa);
         if (s.inimg && a.kappa_out) stf(a.kappa_out, s.o, kappa);
         if (s.inimg && a.alpha_out) stf(a.alpha_out, s.o, alpha);
     } else if (a.alpha_map && s.inimg && s.any) {
@@ -516,30 +521,41 @@ __device__ __forceinline__ void temporal_tile(const TemporalArgs &a, float4 *til
     }
 }
 
+// The learned mode holds the network's matrix accumulators beside the pass's
+// own state: it is asked for four waves per SIMD, which it reaches without
+// spilling (left alone, its accumulation registers cost it a wave).
+#define SV_TEMPORAL_WAVES(MODE) amdgpu_waves_per_eu((MODE) == kLearn ? 4 : 1)
+
 template <typename T, int RECT, bool USE_ID, int MODE>
-__global__ __launch_bounds__(256) void temporal_k(TemporalArgs a) {
+__global__ __launch_bounds__(256) __attribute__((SV_TEMPORAL_WAVES(MODE))) void temporal_k(
+    TemporalArgs a) {
     __shared__ float4 tile[(kTX + 2) * (kTY + 2)];
     __shared__ uint4 s_feat[MODE == kLearn ? 2 * 256 : 1];
+    __shared__ uint16_t s_w[MODE == kLearn ? SV_MLP_PARAMS : 1];
+    __shared__ float s_b[MODE == kLearn ? kNetBiases : 1];
     __shared__ uint32_t wave_n[4], base_sh;
     const int gxt = (a.w + kTX - 1) / kTX;
     const int t = xcd_tile(gxt * ((a.h + kTY - 1) / kTY));
     if (t < 0) return;
     const int by = t / gxt, bx = t - by * gxt;
-    temporal_tile<T, RECT, USE_ID, MODE>(a, tile, s_feat, wave_n, base_sh, bx, by);
+    temporal_tile<T, RECT, USE_ID, MODE>(a, tile, s_feat, s_w, s_b, wave_n, base_sh, bx, by);
 }
 
 template <typename T, int RECT, bool USE_ID, int MODE>
-__global__ __launch_bounds__(256) void temporal_batch_k(const TemporalArgs *args, const int *prefix,
-                                                        int n, int total) {
+__global__ __launch_bounds__(256) __attribute__((SV_TEMPORAL_WAVES(MODE))) void temporal_batch_k(
+    const TemporalArgs *args, const int *prefix, int n, int total) {
     __shared__ float4 tile[(kTX + 2) * (kTY + 2)];
     __shared__ uint4 s_feat[MODE == kLearn ? 2 * 256 : 1];
+    __shared__ uint16_t s_w[MODE == kLearn ? SV_MLP_PARAMS : 1];
+    __shared__ float s_b[MODE == kLearn ? kNetBiases : 1];
     __shared__ uint32_t wave_n[4], base_sh;
     int s = 0;
     const int lt = batch_tile(prefix, n, total, s);
     if (lt < 0) return;
     const TemporalArgs a = args[s];  // a copy: the kernel's stores cannot alias it
     const int gxt = (a.w + kTX - 1) / kTX;
-    temporal_tile<T, RECT, USE_ID, MODE>(a, tile, s_feat, wave_n, base_sh, lt % gxt, lt / gxt);
+    temporal_tile<T, RECT, USE_ID, MODE>(a, tile, s_feat, s_w, s_b, wave_n, base_sh, lt % gxt,
+                                         lt / gxt);
 }
 
 template <typename T, int RECT, bool USE_ID, int MODE>
