@@ -51,8 +51,12 @@ def test_blur_control_bit_exact():
             np.testing.assert_array_equal(host(ctl), ref)
 
 
-@pytest.mark.parametrize("H,W", [(5, 7), (67, 131), (130, 200)])
-@pytest.mark.parametrize("level", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("H,W,level", [(5, 7, l) for l in range(5)] +
+                         [(67, 131, l) for l in range(5)] +
+                         [(130, 200, l) for l in range(5)] +
+                         # several column tiles of the step-32 class (16 lattice
+                         # columns of 8-column groups each), ragged at both ends
+                         [(70, 1100, 3), (70, 1100, 4)])
 def test_adaptive_level_2d(H, W, level):
     c, var, z, dzdx, dzdy, n = _atrous_inputs(H, W, 900 + level + H, holes=(level == 1))
     ctl = _ctl(np.random.default_rng(901 + level), H, W)

@@ -343,8 +343,11 @@ def _atrous_inputs(H, W, seed, holes=False, scene=True):
     return c, var, z, dzdx, dzdy, n
 
 
-@pytest.mark.parametrize("H,W", SIZES + [(130, 200)])
-@pytest.mark.parametrize("step", [1, 2, 3, 4, 8, 16, 32])
+@pytest.mark.parametrize("H,W,step", [(h, w, s) for (h, w) in SIZES + [(130, 200)]
+                                      for s in (1, 2, 3, 4, 8, 16, 32)] +
+                         # several column tiles at the large steps (at step 32 the
+                         # tile is 16 lattice columns of 8-column groups), ragged
+                         [(70, 1100, 16), (70, 1100, 32), (37, 4100, 32)])
 def test_atrous(H, W, step):
     c, var, z, dzdx, dzdy, n = _atrous_inputs(H, W, 400 + step + H, holes=(step == 2))
     P = W + 7
