@@ -109,6 +109,43 @@ def test_constant_image(name):
         assert (np.abs(out - k) / k).max() <= 5e-6
 
 
+@pytest.mark.parametrize("name", list(FILTERS))
+@pytest.mark.parametrize("H,W", [(37, 70), (67, 131)])
+def test_hostile_mixed_inputs(name, H, W):
+    """Every kind of unusable input scattered over the frame, so that live
+    and unusable pixels meet inside tiles and at their edges: empty pixels
+    of every kind in the current and the previous depth (0, -0, negative,
+    NaN, infinite), motion that is not finite or beyond 2^20 pixels, motion
+    that leaves the image, and taps straddling its border.  Each frame
+    through the frame driver against the oracle chain, to the same bars."""
+    r = np.random.default_rng(4242 + H + len(name))
+    frames = _frames(H, W, 3)
+    bad_z = np.array([0.0, -0.0, -1.0, np.nan, np.inf], np.float32)
+    bad_mv = np.array([1e7, -1e7, np.nan, np.inf, 1048575.5, -1048576.0, 3.0 * 1048576.0],
+                      np.float32)
+    ys, xs = np.mgrid[0:H, 0:W]
+    for fr in frames:
+        for key in ("z", "prev_z"):
+            z = fr[key].copy()
+            pick = r.random((H, W)) < 0.12
+            z[pick] = bad_z[r.integers(0, len(bad_z), pick.sum())]
+            fr[key] = z
+        mv = fr["mv"].copy()
+        u = r.random((H, W))
+        hard = u < 0.08
+        mv[0][hard] = bad_mv[r.integers(0, len(bad_mv), hard.sum())]
+        mv[1][hard] = bad_mv[r.integers(0, len(bad_mv), hard.sum())]
+        off = (u >= 0.08) & (u < 0.16)  # well off the image
+        mv[0][off] = ((r.random(off.sum()) - 0.5) * 4.0 * (W + 2)).astype(np.float32)
+        mv[1][off] = ((r.random(off.sum()) - 0.5) * 4.0 * (H + 2)).astype(np.float32)
+        edge = (u >= 0.16) & (u < 0.2)  # taps straddling x = -1 and y = H - 1
+        mv[0][edge] = (-xs[edge] - 0.5).astype(np.float32)
+        mv[1][edge] = (H - 1 - ys[edge] + 0.25).astype(np.float32)
+        fr["mv"] = mv
+    say(f"hostile mixed inputs {H}x{W}, {name}")
+    _run(frames, *FILTERS[name])
+
+
 @pytest.mark.parametrize("H,W", [(1, 1), (1, 2), (2, 1), (1, 70), (37, 1)])
 def test_tiny_images(H, W):
     """Images of a single row, column or pixel (every stencil clipped to
