@@ -125,3 +125,34 @@ def list_consumed(work):
     word 0 and, once the reading pass has run, the same value in word 2."""
     c = work[:256].view(8, 32).cpu()
     return bool((c[:, 0] == c[:, 2]).all())
+
+
+def make_hostile(fr, r):
+    """Scatter every kind of unusable input over one frame (in place, in the
+    frame's own dtype; binary16 overflows to infinity): empty pixels of
+    every kind in the current and previous depth (0, -0, negative, NaN,
+    infinite), motion that is not finite or beyond 2^20 pixels, motion that
+    leaves the image, and taps straddling its border."""
+    H, W = fr["z"].shape
+    bad_z = np.array([0.0, -0.0, -1.0, np.nan, np.inf])
+    bad_mv = np.array([1e7, -1e7, np.nan, np.inf, 1048575.5, -1048576.0, 3.0 * 1048576.0])
+    ys, xs = np.mgrid[0:H, 0:W]
+    with np.errstate(over="ignore", invalid="ignore"):
+        for key in ("z", "prev_z"):
+            z = fr[key].copy()
+            pick = r.random((H, W)) < 0.12
+            z[pick] = bad_z[r.integers(0, len(bad_z), pick.sum())]
+            fr[key] = z
+        mv = fr["mv"].copy()
+        u = r.random((H, W))
+        hard = u < 0.08
+        mv[0][hard] = bad_mv[r.integers(0, len(bad_mv), hard.sum())]
+        mv[1][hard] = bad_mv[r.integers(0, len(bad_mv), hard.sum())]
+        off = (u >= 0.08) & (u < 0.16)  # well off the image
+        mv[0][off] = (r.random(off.sum()) - 0.5) * 4.0 * (W + 2)
+        mv[1][off] = (r.random(off.sum()) - 0.5) * 4.0 * (H + 2)
+        edge = (u >= 0.16) & (u < 0.2)  # taps straddling x = -1 and y = H - 1
+        mv[0][edge] = -xs[edge] - 0.5
+        mv[1][edge] = H - 1 - ys[edge] + 0.25
+        fr["mv"] = mv
+    return fr

@@ -11,7 +11,7 @@ import torch
 
 from paper_2312_06827_amd.pipeline import MOTION, MOTION_SEP, BatchDenoiser, Denoiser, FrameInputs
 from paper_2312_06827_amd.scene import batched_configs, render_frame, with_size
-from tests._util import say
+from tests._util import make_hostile, say
 
 pytestmark = pytest.mark.gpu
 
@@ -59,6 +59,35 @@ def test_batch_equals_single_streams(half, sep, levels, feedback, rows, graph):
                     assert torch.equal(tb, td), (f, i, name)
             say(f"  frame {f}: {len(SIZES)} streams bitwise equal; {batch.passes()} launches per frame")
         assert batch.passes() == 2 + levels  # temporal, variance, one per level (separable fused)
+    finally:
+        batch.close()
+
+
+@pytest.mark.parametrize("half,sep", [(False, False), (True, True)])
+def test_batch_hostile_inputs_equal_single_streams(half, sep):
+    """Every kind of unusable depth and motion scattered over every stream
+    (the single-stream path is held to the oracle on such frames by the
+    degenerate-frame tests): each batched stream still equals, bitwise, the
+    stream run alone."""
+    dt = torch.float16 if half else torch.float32
+    cfg = MOTION_SEP if sep else MOTION
+    frames = 3
+    scfg = _streams(half, frames)
+    r = np.random.default_rng(77 + int(half) + 2 * int(sep))
+    say(f"batch hostile inputs: {len(SIZES)} streams half={half} sep={sep}")
+    batch = BatchDenoiser(SIZES, cfg, dt)
+    singles = [Denoiser(h, w, cfg, dt) for (h, w) in SIZES]
+    try:
+        for f in range(frames):
+            inputs = [FrameInputs.from_numpy(make_hostile(render_frame(c, f), r)) for c in scfg]
+            outs = batch.frame(inputs)
+            refs = [d.frame(inp) for d, inp in zip(singles, inputs)]
+            torch.cuda.synchronize()
+            for i, (b, d) in enumerate(zip(batch.streams, singles)):
+                assert torch.equal(outs[i], refs[i]), (f, i)
+                assert torch.equal(b.n[b.k], d.n[d.k]), (f, i)
+                assert torch.equal(b.var, d.var), (f, i)
+            say(f"  frame {f}: bitwise equal")
     finally:
         batch.close()
 

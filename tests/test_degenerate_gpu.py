@@ -15,7 +15,7 @@ import torch
 import oracle as O
 from paper_2312_06827_amd.pipeline import MOTION, MOTION_SEP, PLAIN, Denoiser, FrameInputs
 from paper_2312_06827_amd.scene import CONFIGS, sequence, with_size
-from tests._util import rel_err, say
+from tests._util import make_hostile, rel_err, say
 
 pytestmark = pytest.mark.gpu
 TOL32 = 1e-5
@@ -119,29 +119,7 @@ def test_hostile_mixed_inputs(name, H, W):
     that leaves the image, and taps straddling its border.  Each frame
     through the frame driver against the oracle chain, to the same bars."""
     r = np.random.default_rng(4242 + H + len(name))
-    frames = _frames(H, W, 3)
-    bad_z = np.array([0.0, -0.0, -1.0, np.nan, np.inf], np.float32)
-    bad_mv = np.array([1e7, -1e7, np.nan, np.inf, 1048575.5, -1048576.0, 3.0 * 1048576.0],
-                      np.float32)
-    ys, xs = np.mgrid[0:H, 0:W]
-    for fr in frames:
-        for key in ("z", "prev_z"):
-            z = fr[key].copy()
-            pick = r.random((H, W)) < 0.12
-            z[pick] = bad_z[r.integers(0, len(bad_z), pick.sum())]
-            fr[key] = z
-        mv = fr["mv"].copy()
-        u = r.random((H, W))
-        hard = u < 0.08
-        mv[0][hard] = bad_mv[r.integers(0, len(bad_mv), hard.sum())]
-        mv[1][hard] = bad_mv[r.integers(0, len(bad_mv), hard.sum())]
-        off = (u >= 0.08) & (u < 0.16)  # well off the image
-        mv[0][off] = ((r.random(off.sum()) - 0.5) * 4.0 * (W + 2)).astype(np.float32)
-        mv[1][off] = ((r.random(off.sum()) - 0.5) * 4.0 * (H + 2)).astype(np.float32)
-        edge = (u >= 0.16) & (u < 0.2)  # taps straddling x = -1 and y = H - 1
-        mv[0][edge] = (-xs[edge] - 0.5).astype(np.float32)
-        mv[1][edge] = (H - 1 - ys[edge] + 0.25).astype(np.float32)
-        fr["mv"] = mv
+    frames = [make_hostile(fr, r) for fr in _frames(H, W, 3)]
     say(f"hostile mixed inputs {H}x{W}, {name}")
     _run(frames, *FILTERS[name])
 
